@@ -1,0 +1,700 @@
+/*
+ * hgp_oracle.c -- plain sequential CPU oracle of the multilevel hot path of
+ * "Scalable High-Quality Hypergraph Partitioning" (Gottesbüren, Heuer, Maas,
+ * Sanders, Schlag; arXiv 2303.17679).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference that the GPU library is compared against.  Only the test suite,
+ * the smoke check and the CPU baseline of the benchmark may load it; the
+ * product path never does.  It shares no code, header or table with the GPU
+ * library.
+ *
+ * Everything is integer arithmetic.  Each function names the part of the
+ * paper it follows; where the paper is silent or ambiguous, the reading
+ * taken is named R1..R14 (listed in the design notes of the repository).
+ *
+ * Pinning: every exported function is checked by the CPU test suite against
+ * brute force from the definitions (objective, gains, ratings, contraction by
+ * sets, pair selection by enumeration of the merge walk), closed-form special
+ * cases and hand-derived golden fixtures.  The SplitMix64 finalizer used as
+ * the seeded tie-break hash is pinned by published SplitMix64 output values.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    uint32_t n, m, p;
+    const uint32_t *pin_off, *pins;   /* nets -> pins, pins ascending per net   */
+    const uint32_t *inc_off, *inc;    /* vertices -> nets, nets ascending        */
+    const int32_t *vwgt, *nwgt;       /* c(v) >= 1, omega(e) >= 1                */
+} or_hg;
+
+typedef struct {
+    uint32_t k;
+    uint32_t eps_num, eps_den;        /* epsilon = eps_num / eps_den (R13)      */
+    uint64_t seed;
+    uint32_t limit_factor;            /* contraction limit 160 k (Sec. 4.1)    */
+    uint32_t coarsen_subrounds;       /* S_c                                   */
+    uint32_t lp_subrounds;            /* S_lp                                  */
+    uint32_t lp_rounds;               /* R_lp                                  */
+} or_params;
+
+#define OR_NONE 0xFFFFFFFFu
+
+enum { OR_OK = 0, OR_E_INVALID = -1, OR_E_NOMEM = -3 };
+
+/* ------------------------------------------------------------------------ */
+/* Seeded hash (R5): the SplitMix64 finalizer applied to a tagged counter.   */
+/* ------------------------------------------------------------------------ */
+uint64_t or_mix64(uint64_t z)
+{
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ULL;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return z;
+}
+
+/* purpose: 1 coarsening sub-round, 2 rating tie, 3 LP sub-round. */
+uint64_t or_hash(uint64_t seed, uint32_t purpose, uint32_t level, uint32_t it, uint32_t x)
+{
+    uint64_t tag = (uint64_t)((purpose & 0xFFu) | ((level & 0xFFu) << 8) | ((it & 0xFFFFu) << 16));
+    return or_mix64(or_mix64(seed) ^ ((tag << 32) | (uint64_t)x));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Totals and the balance bound (Sec. 2, balanced partitioning problem).     */
+/* ------------------------------------------------------------------------ */
+int64_t or_total_weight(const or_hg *h)
+{
+    int64_t w = 0;
+    for (uint32_t v = 0; v < h->n; ++v) w += h->vwgt[v];
+    return w;
+}
+
+/* L_max = (1 + eps) * ceil(c(V) / k); an integer block weight c satisfies
+ * c <= (1+eps)*ceil(W/k) exactly when c <= floor((den+num)*ceil(W/k)/den). */
+int64_t or_lmax(int64_t W, uint32_t k, uint32_t eps_num, uint32_t eps_den)
+{
+    int64_t per = (W + (int64_t)k - 1) / (int64_t)k;
+    return ((int64_t)(eps_den + eps_num) * per) / (int64_t)eps_den;
+}
+
+static int64_t floor_div(int64_t a, int64_t b) /* b > 0 */
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) q -= 1;
+    return q;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Connectivity objective (Sec. 2): f = sum over cut nets of (lambda-1)*w.   */
+/* ------------------------------------------------------------------------ */
+int64_t or_objective(const or_hg *h, uint32_t k, const uint32_t *part, int64_t *block_w)
+{
+    uint32_t *mark = (uint32_t *)malloc(sizeof(uint32_t) * (k ? k : 1));
+    for (uint32_t b = 0; b < k; ++b) mark[b] = OR_NONE;
+    int64_t f = 0;
+    for (uint32_t e = 0; e < h->m; ++e) {
+        uint32_t lambda = 0;
+        for (uint32_t j = h->pin_off[e]; j < h->pin_off[e + 1]; ++j) {
+            uint32_t b = part[h->pins[j]];
+            if (mark[b] != e) { mark[b] = e; ++lambda; }
+        }
+        if (lambda > 1) f += (int64_t)(lambda - 1) * h->nwgt[e];
+    }
+    if (block_w) {
+        for (uint32_t b = 0; b < k; ++b) block_w[b] = 0;
+        for (uint32_t v = 0; v < h->n; ++v) block_w[part[v]] += h->vwgt[v];
+    }
+    free(mark);
+    return f;
+}
+
+/* Pin count Phi(e, b) = |e intersect V_b| (Sec. 2). */
+static uint32_t phi(const or_hg *h, const uint32_t *part, uint32_t e, uint32_t b)
+{
+    uint32_t c = 0;
+    for (uint32_t j = h->pin_off[e]; j < h->pin_off[e + 1]; ++j)
+        if (part[h->pins[j]] == b) ++c;
+    return c;
+}
+
+/* Connectivity gain of moving u to block t (Sec. 6):
+ * g = w({e in I(u): Phi(e, Pi[u]) = 1}) - w({e in I(u): Phi(e, t) = 0}). */
+int64_t or_gain(const or_hg *h, const uint32_t *part, uint32_t u, uint32_t t)
+{
+    int64_t g = 0;
+    uint32_t s = part[u];
+    for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+        uint32_t e = h->inc[j];
+        if (phi(h, part, e, s) == 1) g += h->nwgt[e];
+        if (phi(h, part, e, t) == 0) g -= h->nwgt[e];
+    }
+    return g;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coarsening: one clustering pass (Sec. 4.1 rating function and contraction */
+/* limits; Sec. 11 deterministic clustering for coarsening).                 */
+/* ------------------------------------------------------------------------ */
+
+/* Heavy-edge rating score of one net, fixed point: floor(w(e) * 2^32 / (|e|-1)) (R14). */
+static uint64_t net_score(int32_t w, uint32_t size)
+{
+    return (((uint64_t)(uint32_t)w) << 32) / (uint64_t)(size - 1);
+}
+
+/* Best target cluster of every candidate of sub-round r.  Candidates are the
+ * unclustered singletons u with H(seed,1,level,0,u) mod S_c = r (Sec. 11).
+ * rep/cw/csize are the snapshot at the start of the sub-round.  target[u] is
+ * set for candidates (OR_NONE when no valid cluster exists) and left OR_NONE
+ * for non-candidates.  Returns the number of candidates. */
+uint32_t or_rate_subround(const or_hg *h, const or_params *P, uint32_t level, uint32_t r,
+                          const uint32_t *rep, const int64_t *cw, const uint32_t *csize,
+                          uint32_t *target)
+{
+    const uint32_t n = h->n;
+    const int64_t W = or_total_weight(h);
+    const int64_t cap_mult = (int64_t)P->limit_factor * (int64_t)P->k; /* 160 k */
+    uint8_t *cand = (uint8_t *)calloc(n ? n : 1, 1);
+    uint64_t *R = (uint64_t *)calloc(n ? n : 1, sizeof(uint64_t));
+    uint64_t *seen = (uint64_t *)calloc(n ? n : 1, sizeof(uint64_t));
+    uint32_t *touched = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint64_t stamp = 0;
+    uint32_t ncand = 0;
+
+    for (uint32_t u = 0; u < n; ++u) {
+        target[u] = OR_NONE;
+        cand[u] = (rep[u] == u && csize[u] == 1 &&
+                   or_hash(P->seed, 1, level, 0, u) % P->coarsen_subrounds == r);
+    }
+    for (uint32_t u = 0; u < n; ++u) {
+        if (!cand[u]) continue;
+        ++ncand;
+        uint32_t nt = 0;
+        /* r(u, C) = sum over nets e in I(u) that also touch C of w(e)/(|e|-1);
+         * each net counts once per cluster (R1). */
+        for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+            uint32_t e = h->inc[j];
+            uint32_t size = h->pin_off[e + 1] - h->pin_off[e];
+            if (size < 2) continue;
+            uint64_t s = net_score(h->nwgt[e], size);
+            ++stamp; /* one stamp per (candidate, net): de-duplicates clusters inside e */
+            for (uint32_t q = h->pin_off[e]; q < h->pin_off[e + 1]; ++q) {
+                uint32_t v = h->pins[q];
+                if (v == u) continue;
+                uint32_t C = rep[v];
+                if (seen[C] == stamp) continue;
+                seen[C] = stamp;
+                if (R[C] == 0) touched[nt++] = C; /* every score is >= 1 */
+                R[C] += s;
+            }
+        }
+        /* argmax over valid clusters; ties -> smaller H(seed,2,level,0,C) -> smaller C (R5). */
+        uint32_t best = OR_NONE;
+        uint64_t bestR = 0, bestH = 0;
+        for (uint32_t q = 0; q < nt; ++q) {
+            uint32_t C = touched[q];
+            uint64_t rc = R[C];
+            int valid = (C != rep[u]) &&
+                        (cap_mult * ((int64_t)h->vwgt[u] + cw[C]) <= W) && /* R4 */
+                        !cand[C];                                          /* R3 */
+            if (valid) {
+                uint64_t hc = or_hash(P->seed, 2, level, 0, C);
+                if (best == OR_NONE || rc > bestR ||
+                    (rc == bestR && (hc < bestH || (hc == bestH && C < best)))) {
+                    best = C; bestR = rc; bestH = hc;
+                }
+            }
+        }
+        for (uint32_t q = 0; q < nt; ++q) { R[touched[q]] = 0; }
+        target[u] = best;
+    }
+    free(cand); free(R); free(seen); free(touched);
+    return ncand;
+}
+
+typedef struct { uint32_t C; int32_t c; uint32_t u; } or_join;
+
+static int cmp_join(const void *a, const void *b)
+{
+    const or_join *x = (const or_join *)a, *y = (const or_join *)b;
+    if (x->C != y->C) return x->C < y->C ? -1 : 1;
+    if (x->c != y->c) return x->c < y->c ? -1 : 1;
+    if (x->u != y->u) return x->u < y->u ? -1 : 1;
+    return 0;
+}
+
+/* Approval (Sec. 11): group the moves by target cluster, order each group by
+ * ascending node weight with the node ID as tie breaker, and apply the longest
+ * prefix whose weight keeps the cluster within c_max (Sec. 4.1:
+ * c_max = c(V)/(160k), tested exactly as 160k * c(C) <= c(V)).
+ * Updates rep, cw, csize in place; returns the number of approved joins. */
+uint32_t or_approve_apply(const or_hg *h, const or_params *P, const uint32_t *target,
+                          uint32_t *rep, int64_t *cw, uint32_t *csize)
+{
+    const uint32_t n = h->n;
+    const int64_t W = or_total_weight(h);
+    const int64_t cap_mult = (int64_t)P->limit_factor * (int64_t)P->k;
+    uint32_t nj = 0;
+    for (uint32_t u = 0; u < n; ++u) if (target[u] != OR_NONE) ++nj;
+    or_join *J = (or_join *)malloc(sizeof(or_join) * (nj ? nj : 1));
+    nj = 0;
+    for (uint32_t u = 0; u < n; ++u)
+        if (target[u] != OR_NONE) { J[nj].C = target[u]; J[nj].c = h->vwgt[u]; J[nj].u = u; ++nj; }
+    qsort(J, nj, sizeof(or_join), cmp_join);
+    /* decide on the snapshot cw, then apply */
+    uint8_t *ok = (uint8_t *)calloc(nj ? nj : 1, 1);
+    uint32_t i = 0, approved = 0;
+    while (i < nj) {
+        uint32_t C = J[i].C, g = i;
+        int64_t prefix = 0;
+        int open = 1;
+        for (; g < nj && J[g].C == C; ++g) {
+            prefix += J[g].c;
+            if (open && cap_mult * (cw[C] + prefix) <= W) ok[g] = 1;
+            else open = 0;
+        }
+        i = g;
+    }
+    for (uint32_t q = 0; q < nj; ++q) {
+        if (!ok[q]) continue;
+        rep[J[q].u] = J[q].C;
+        cw[J[q].C] += J[q].c;
+        csize[J[q].C] += 1;
+        ++approved;
+    }
+    free(J); free(ok);
+    return approved;
+}
+
+/* One clustering pass of level `level` (Sec. 4.1, Sec. 11).  rep is output.
+ * The pass ends early after a sub-round in which the number of clusters drops
+ * below n/2.5 of the current level (R2). */
+int or_cluster_pass(const or_hg *h, const or_params *P, uint32_t level,
+                    uint32_t *rep, uint32_t *n_clusters, uint32_t *subrounds_run)
+{
+    const uint32_t n = h->n;
+    int64_t *cw = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    uint32_t *csize = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t *target = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!cw || !csize || !target) return OR_E_NOMEM;
+    for (uint32_t u = 0; u < n; ++u) { rep[u] = u; cw[u] = h->vwgt[u]; csize[u] = 1; }
+    uint32_t cnt = n, run = 0;
+    for (uint32_t r = 0; r < P->coarsen_subrounds; ++r) {
+        or_rate_subround(h, P, level, r, rep, cw, csize, target);
+        cnt -= or_approve_apply(h, P, target, rep, cw, csize);
+        ++run;
+        if ((uint64_t)5 * cnt < (uint64_t)2 * n) break;
+    }
+    *n_clusters = cnt;
+    if (subrounds_run) *subrounds_run = run;
+    free(cw); free(csize); free(target);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Contraction (Sec. 4.2).                                                   */
+/* ------------------------------------------------------------------------ */
+static int cmp_u32(const void *a, const void *b)
+{
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+typedef struct { uint64_t f; uint32_t size; uint32_t e; } or_fp;
+
+static int cmp_fp(const void *a, const void *b)
+{
+    const or_fp *x = (const or_fp *)a, *y = (const or_fp *)b;
+    if (x->f != y->f) return x->f < y->f ? -1 : 1;
+    if (x->size != y->size) return x->size < y->size ? -1 : 1;
+    if (x->e != y->e) return x->e < y->e ? -1 : 1;
+    return 0;
+}
+
+/* Contract the clustering rep.  Output buffers are sized by the fine level:
+ * c_pin_off[m+1], c_pins[p], c_inc_off[n+1], c_inc[p], c_vwgt[n], c_nwgt[m].
+ * dims[0..2] <- n', m', p'.  cid[n] <- coarse vertex of every fine vertex. */
+int or_contract(const or_hg *h, const uint32_t *rep, uint32_t *cid, uint32_t *dims,
+                uint32_t *c_pin_off, uint32_t *c_pins, uint32_t *c_inc_off, uint32_t *c_inc,
+                int32_t *c_vwgt, int32_t *c_nwgt)
+{
+    const uint32_t n = h->n, m = h->m;
+    /* Remap node IDs to a consecutive range: representatives in ascending ID. */
+    uint32_t *rank = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t nc = 0;
+    for (uint32_t v = 0; v < n; ++v) { rank[v] = nc; if (rep[v] == v) ++nc; }
+    for (uint32_t v = 0; v < n; ++v) cid[v] = rank[rep[v]];
+    /* Supernode weight = sum of the weights of its cluster. */
+    for (uint32_t c = 0; c < nc; ++c) c_vwgt[c] = 0;
+    for (uint32_t v = 0; v < n; ++v) c_vwgt[cid[v]] += h->vwgt[v];
+
+    /* Replace pins by their supernodes and discard repeated supernodes. */
+    uint32_t *t_off = (uint32_t *)malloc(sizeof(uint32_t) * (m + 1));
+    uint32_t *t_pins = (uint32_t *)malloc(sizeof(uint32_t) * (h->p ? h->p : 1));
+    t_off[0] = 0;
+    uint32_t w = 0;
+    for (uint32_t e = 0; e < m; ++e) {
+        uint32_t b = w;
+        for (uint32_t j = h->pin_off[e]; j < h->pin_off[e + 1]; ++j) t_pins[w++] = cid[h->pins[j]];
+        qsort(t_pins + b, w - b, sizeof(uint32_t), cmp_u32);
+        uint32_t u = b;
+        for (uint32_t j = b; j < w; ++j)
+            if (j == b || t_pins[j] != t_pins[u - 1]) t_pins[u++] = t_pins[j];
+        w = u;
+        t_off[e + 1] = w;
+    }
+
+    /* Identical nets: fingerprints f(e) = sum of v^2 (mod 2^64), sort by
+     * (fingerprint, size), compare pairwise inside runs; single-pin nets are
+     * removed (they never contribute to the objective). */
+    or_fp *F = (or_fp *)malloc(sizeof(or_fp) * (m ? m : 1));
+    uint32_t nf = 0;
+    for (uint32_t e = 0; e < m; ++e) {
+        uint32_t size = t_off[e + 1] - t_off[e];
+        if (size < 2) continue;
+        uint64_t f = 0;
+        for (uint32_t j = t_off[e]; j < t_off[e + 1]; ++j) f += (uint64_t)t_pins[j] * (uint64_t)t_pins[j];
+        F[nf].f = f; F[nf].size = size; F[nf].e = e; ++nf;
+    }
+    qsort(F, nf, sizeof(or_fp), cmp_fp);
+    uint32_t *rep_net = (uint32_t *)malloc(sizeof(uint32_t) * (m ? m : 1));
+    for (uint32_t e = 0; e < m; ++e) rep_net[e] = OR_NONE;
+    uint32_t i = 0;
+    while (i < nf) {
+        uint32_t g = i;
+        while (g < nf && F[g].f == F[i].f && F[g].size == F[i].size) ++g;
+        for (uint32_t a = i; a < g; ++a) {
+            uint32_t ea = F[a].e;
+            rep_net[ea] = ea;
+            for (uint32_t b = i; b < a; ++b) {
+                uint32_t eb = F[b].e;
+                if (rep_net[eb] != eb) continue;
+                if (memcmp(t_pins + t_off[ea], t_pins + t_off[eb], sizeof(uint32_t) * F[a].size) == 0) {
+                    rep_net[ea] = eb; /* run is in ascending net ID: eb is the smallest */
+                    break;
+                }
+            }
+        }
+        i = g;
+    }
+    /* The kept net of each identical group carries the group's total weight. */
+    int64_t *wsum = (int64_t *)calloc(m ? m : 1, sizeof(int64_t));
+    for (uint32_t e = 0; e < m; ++e) if (rep_net[e] != OR_NONE) wsum[rep_net[e]] += h->nwgt[e];
+
+    /* Kept nets are renumbered in ascending fine ID (prefix sum over the
+     * validity bitset). */
+    uint32_t mc = 0, pc = 0;
+    c_pin_off[0] = 0;
+    for (uint32_t e = 0; e < m; ++e) {
+        if (rep_net[e] != e) continue;
+        for (uint32_t j = t_off[e]; j < t_off[e + 1]; ++j) c_pins[pc++] = t_pins[j];
+        c_nwgt[mc] = (int32_t)wsum[e];
+        ++mc;
+        c_pin_off[mc] = pc;
+    }
+    /* Incident nets: transpose of the pin lists, ascending net ID. */
+    for (uint32_t v = 0; v <= nc; ++v) c_inc_off[v] = 0;
+    for (uint32_t j = 0; j < pc; ++j) c_inc_off[c_pins[j] + 1]++;
+    for (uint32_t v = 0; v < nc; ++v) c_inc_off[v + 1] += c_inc_off[v];
+    uint32_t *cur = (uint32_t *)malloc(sizeof(uint32_t) * (nc ? nc : 1));
+    for (uint32_t v = 0; v < nc; ++v) cur[v] = c_inc_off[v];
+    for (uint32_t e = 0; e < mc; ++e)
+        for (uint32_t j = c_pin_off[e]; j < c_pin_off[e + 1]; ++j) c_inc[cur[c_pins[j]]++] = e;
+
+    dims[0] = nc; dims[1] = mc; dims[2] = pc;
+    free(rank); free(t_off); free(t_pins); free(F); free(rep_net); free(wsum); free(cur);
+    return OR_OK;
+}
+
+/* Projection of a coarse partition onto the finer level (Sec. 3). */
+void or_project(uint32_t n, const uint32_t *cid, const uint32_t *coarse_part, uint32_t *part)
+{
+    for (uint32_t v = 0; v < n; ++v) part[v] = coarse_part[cid[v]];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Greedy initial partition (a simple deterministic method, as permitted for */
+/* the coarsest level): BFS order, blocks filled to ceil(c(V)/k) in turn.     */
+/* ------------------------------------------------------------------------ */
+int or_greedy_ip(const or_hg *h, uint32_t k, uint32_t *part)
+{
+    const uint32_t n = h->n;
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint8_t *vis = (uint8_t *)calloc(n ? n : 1, 1);
+    uint32_t head = 0, tail = 0, next_start = 0;
+    while (tail < n) {
+        while (vis[next_start]) ++next_start;
+        vis[next_start] = 1;
+        order[tail++] = next_start;
+        while (head < tail) {
+            uint32_t v = order[head++];
+            for (uint32_t j = h->inc_off[v]; j < h->inc_off[v + 1]; ++j) {
+                uint32_t e = h->inc[j];
+                for (uint32_t q = h->pin_off[e]; q < h->pin_off[e + 1]; ++q) {
+                    uint32_t w = h->pins[q];
+                    if (!vis[w]) { vis[w] = 1; order[tail++] = w; }
+                }
+            }
+        }
+    }
+    const int64_t W = or_total_weight(h);
+    const int64_t T = (W + (int64_t)k - 1) / (int64_t)k;
+    uint32_t b = 0;
+    int64_t cb = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t v = order[i];
+        part[v] = b;
+        cb += h->vwgt[v];
+        if (cb >= T && b + 1 < k) { ++b; cb = 0; }
+    }
+    free(order); free(vis);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Deterministic synchronous label propagation (Sec. 11).                    */
+/* ------------------------------------------------------------------------ */
+
+/* Longest feasible prefixes of one block pair by the two-pointer walk
+ * (Sec. 11, reading R8): A = moves s->t, B = moves t->s, each already in
+ * priority order; x = weight(A[0:i]) - weight(B[0:j]).  Feasible iff
+ * -beta_s <= x <= beta_t.  The walk advances i while x <= 0 (i.e. while the
+ * source block s receives at least as much as it gives) and j while x > 0,
+ * taking the only remaining side once one sequence is exhausted.  Returns 1
+ * and the last feasible visited state, or 0 (approve nothing). */
+int or_select_pair(const int32_t *ca, uint32_t la, const int32_t *cb, uint32_t lb,
+                   int64_t beta_s, int64_t beta_t, uint32_t *i_out, uint32_t *j_out)
+{
+    uint32_t i = 0, j = 0;
+    int64_t sa = 0, sb = 0;
+    int found = 0;
+    *i_out = 0; *j_out = 0;
+    for (;;) {
+        int64_t x = sa - sb;
+        if (-beta_s <= x && x <= beta_t) { found = 1; *i_out = i; *j_out = j; }
+        if (i == la && j == lb) break;
+        if (i == la) { sb += cb[j]; ++j; }
+        else if (j == lb) { sa += ca[i]; ++i; }
+        else if (x <= 0) { sa += ca[i]; ++i; }
+        else { sb += cb[j]; ++j; }
+    }
+    if (!found) { *i_out = 0; *j_out = 0; }
+    return found;
+}
+
+typedef struct { uint32_t s, t; int64_t g; uint32_t u; } or_move;
+
+static int cmp_move(const void *a, const void *b)
+{
+    const or_move *x = (const or_move *)a, *y = (const or_move *)b;
+    if (x->s != y->s) return x->s < y->s ? -1 : 1;
+    if (x->t != y->t) return x->t < y->t ? -1 : 1;
+    if (x->g != y->g) return x->g > y->g ? -1 : 1; /* gain descending */
+    if (x->u != y->u) return x->u < y->u ? -1 : 1; /* node ID tie breaker */
+    return 0;
+}
+
+/* Highest-gain move of u on the snapshot (part, bw): the block t != Pi[u]
+ * with the largest positive gain among those that can take u without
+ * exceeding L_max; ties to the smaller block (R10).  Returns OR_NONE if none. */
+static uint32_t best_move(const or_hg *h, const uint32_t *part, const int64_t *bw,
+                          int64_t lmax, uint32_t u, int64_t *aff, uint32_t *cnt,
+                          uint32_t *blist, uint32_t *alist, int64_t *g_out)
+{
+    const uint32_t s = part[u];
+    int64_t b_u = 0, w_inc = 0;
+    uint32_t na = 0;
+    for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+        uint32_t e = h->inc[j];
+        uint32_t nb = 0;
+        /* Phi(e, .) on the snapshot */
+        for (uint32_t q = h->pin_off[e]; q < h->pin_off[e + 1]; ++q) {
+            uint32_t b = part[h->pins[q]];
+            if (cnt[b]++ == 0) blist[nb++] = b;
+        }
+        w_inc += h->nwgt[e];
+        if (cnt[s] == 1) b_u += h->nwgt[e];
+        for (uint32_t q = 0; q < nb; ++q) {
+            uint32_t t = blist[q];
+            if (aff[t] == 0) alist[na++] = t;
+            aff[t] += h->nwgt[e]; /* w({e in I(u): Phi(e,t) > 0}) */
+            cnt[t] = 0;
+        }
+    }
+    /* g(t) = b(u) - w({e in I(u): Phi(e,t) = 0}); only blocks with aff > 0 can be positive */
+    uint32_t best = OR_NONE;
+    int64_t bestg = 0;
+    for (uint32_t q = 0; q < na; ++q) {
+        uint32_t t = alist[q];
+        int64_t g = b_u - (w_inc - aff[t]);
+        aff[t] = 0;
+        if (t == s || g <= 0) continue;
+        if (bw[t] + h->vwgt[u] > lmax) continue;
+        if (g > bestg || (g == bestg && t < best)) { bestg = g; best = t; }
+    }
+    *g_out = bestg;
+    return best;
+}
+
+/* LP refinement of one level.  part is refined in place; returns the
+ * objective and block weights of the result. */
+int or_refine_lp(const or_hg *h, const or_params *P, uint32_t level, uint32_t *part,
+                 int64_t *f_out, int64_t *block_w, uint32_t *rounds_out, uint64_t *moves_out)
+{
+    const uint32_t n = h->n, k = P->k;
+    const int64_t W = or_total_weight(h);
+    const int64_t lmax = or_lmax(W, k, P->eps_num, P->eps_den);
+    int64_t *bw = (int64_t *)malloc(sizeof(int64_t) * k);
+    int64_t *aff = (int64_t *)calloc(k, sizeof(int64_t));
+    uint32_t *cnt = (uint32_t *)calloc(k, sizeof(uint32_t));
+    uint32_t *blist = (uint32_t *)malloc(sizeof(uint32_t) * k);
+    uint32_t *alist = (uint32_t *)malloc(sizeof(uint32_t) * k);
+    uint32_t *snap = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    or_move *M = (or_move *)malloc(sizeof(or_move) * (n ? n : 1));
+    int32_t *ca = (int32_t *)malloc(sizeof(int32_t) * (n ? n : 1));
+    int32_t *cb = (int32_t *)malloc(sizeof(int32_t) * (n ? n : 1));
+    uint32_t *pos_ab = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)k * k);
+    uint32_t *len_ab = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)k * k);
+    uint64_t total_moves = 0;
+    uint32_t rounds = 0;
+    or_objective(h, k, part, bw);
+
+    for (uint32_t r = 0; r < P->lp_rounds; ++r) {
+        uint64_t round_moves = 0;
+        ++rounds;
+        for (uint32_t sub = 0; sub < P->lp_subrounds; ++sub) {
+            /* 1. highest-gain move of every node of this sub-round, on the snapshot */
+            memcpy(snap, part, sizeof(uint32_t) * n);
+            uint32_t nm = 0;
+            for (uint32_t u = 0; u < n; ++u) {
+                if (or_hash(P->seed, 3, level, r, u) % P->lp_subrounds != sub) continue;
+                int64_t g;
+                uint32_t t = best_move(h, snap, bw, lmax, u, aff, cnt, blist, alist, &g);
+                if (t == OR_NONE) continue;
+                M[nm].s = snap[u]; M[nm].t = t; M[nm].g = g; M[nm].u = u; ++nm;
+            }
+            /* 2. per block pair, sort by gain (node ID tie breaker) */
+            qsort(M, nm, sizeof(or_move), cmp_move);
+            for (size_t q = 0; q < (size_t)k * k; ++q) { len_ab[q] = 0; pos_ab[q] = 0; }
+            for (uint32_t q = 0; q < nm; ++q) {
+                size_t key = (size_t)M[q].s * k + M[q].t;
+                if (len_ab[key] == 0) pos_ab[key] = q;
+                len_ab[key]++;
+            }
+            /* 3. longest feasible prefixes, per-pair budget beta_b (R9) */
+            uint64_t sub_moves = 0;
+            for (uint32_t s = 0; s < k; ++s) {
+                for (uint32_t t = s + 1; t < k; ++t) {
+                    uint32_t la = len_ab[(size_t)s * k + t], lb = len_ab[(size_t)t * k + s];
+                    if (la == 0 && lb == 0) continue;
+                    uint32_t pa = pos_ab[(size_t)s * k + t], pb = pos_ab[(size_t)t * k + s];
+                    for (uint32_t q = 0; q < la; ++q) ca[q] = h->vwgt[M[pa + q].u];
+                    for (uint32_t q = 0; q < lb; ++q) cb[q] = h->vwgt[M[pb + q].u];
+                    int64_t beta_s = floor_div(lmax - bw[s], (int64_t)k - 1);
+                    int64_t beta_t = floor_div(lmax - bw[t], (int64_t)k - 1);
+                    uint32_t ii, jj;
+                    or_select_pair(ca, la, cb, lb, beta_s, beta_t, &ii, &jj);
+                    for (uint32_t q = 0; q < ii; ++q) { part[M[pa + q].u] = t; }
+                    for (uint32_t q = 0; q < jj; ++q) { part[M[pb + q].u] = s; }
+                    sub_moves += ii + jj;
+                }
+            }
+            /* 4. apply: block weights of the new assignment */
+            if (sub_moves) {
+                for (uint32_t b = 0; b < k; ++b) bw[b] = 0;
+                for (uint32_t v = 0; v < n; ++v) bw[part[v]] += h->vwgt[v];
+            }
+            round_moves += sub_moves;
+        }
+        total_moves += round_moves;
+        if (round_moves == 0) break;
+    }
+    int64_t f = or_objective(h, k, part, block_w);
+    if (f_out) *f_out = f;
+    if (rounds_out) *rounds_out = rounds;
+    if (moves_out) *moves_out = total_moves;
+    free(bw); free(aff); free(cnt); free(blist); free(alist); free(snap); free(M); free(ca); free(cb); free(pos_ab); free(len_ab);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multilevel driver (Alg. 1 of the paper, with the SDet-style components).  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t n, m, p;
+    uint32_t *pin_off, *pins, *inc_off, *inc, *cid;
+    int32_t *vwgt, *nwgt;
+} or_level;
+
+static or_hg view(const or_level *L)
+{
+    or_hg h;
+    h.n = L->n; h.m = L->m; h.p = L->p;
+    h.pin_off = L->pin_off; h.pins = L->pins; h.inc_off = L->inc_off; h.inc = L->inc;
+    h.vwgt = L->vwgt; h.nwgt = L->nwgt;
+    return h;
+}
+
+/* Partition: coarsen while n > 160k and the pass shrinks the level by more
+ * than 1% (Sec. 4.1 contraction limits), greedy initial partition on the
+ * coarsest level, then project + LP per level (LP also on the coarsest level,
+ * R11).  levels_out gets the number of contractions performed. */
+int or_partition(const or_hg *h0, const or_params *P, uint32_t *part, int64_t *f_out,
+                 uint32_t *levels_out)
+{
+    const uint32_t MAXL = 4096;
+    or_level *L = (or_level *)calloc(MAXL, sizeof(or_level));
+    uint32_t nl = 0;
+    const or_hg *cur = h0;
+    or_hg tmp;
+    uint32_t *rep = (uint32_t *)malloc(sizeof(uint32_t) * (h0->n ? h0->n : 1));
+    for (;;) {
+        if (!((uint64_t)cur->n > (uint64_t)P->limit_factor * P->k)) break;
+        uint32_t cnt;
+        or_cluster_pass(cur, P, nl, rep, &cnt, NULL);
+        if ((uint64_t)100 * (cur->n - cnt) <= (uint64_t)cur->n) break;
+        or_level *N = &L[nl];
+        N->cid = (uint32_t *)malloc(sizeof(uint32_t) * (cur->n ? cur->n : 1));
+        N->pin_off = (uint32_t *)malloc(sizeof(uint32_t) * (cur->m + 1));
+        N->pins = (uint32_t *)malloc(sizeof(uint32_t) * (cur->p ? cur->p : 1));
+        N->inc_off = (uint32_t *)malloc(sizeof(uint32_t) * (cur->n + 1));
+        N->inc = (uint32_t *)malloc(sizeof(uint32_t) * (cur->p ? cur->p : 1));
+        N->vwgt = (int32_t *)malloc(sizeof(int32_t) * (cur->n ? cur->n : 1));
+        N->nwgt = (int32_t *)malloc(sizeof(int32_t) * (cur->m ? cur->m : 1));
+        uint32_t dims[3];
+        or_contract(cur, rep, N->cid, dims, N->pin_off, N->pins, N->inc_off, N->inc, N->vwgt, N->nwgt);
+        N->n = dims[0]; N->m = dims[1]; N->p = dims[2];
+        ++nl;
+        tmp = view(N);
+        cur = &tmp;
+        if (nl == MAXL) break;
+    }
+    /* initial partition of the coarsest level and LP on it */
+    uint32_t *cp = (uint32_t *)malloc(sizeof(uint32_t) * (cur->n ? cur->n : 1));
+    or_greedy_ip(cur, P->k, cp);
+    int64_t f;
+    or_refine_lp(cur, P, nl, cp, &f, NULL, NULL, NULL);
+    /* uncoarsening */
+    for (int l = (int)nl - 1; l >= 0; --l) {
+        or_hg fine = (l == 0) ? *h0 : view(&L[l - 1]);
+        uint32_t *fp = (uint32_t *)malloc(sizeof(uint32_t) * (fine.n ? fine.n : 1));
+        or_project(fine.n, L[l].cid, cp, fp);
+        free(cp);
+        cp = fp;
+        or_refine_lp(&fine, P, (uint32_t)l, cp, &f, NULL, NULL, NULL);
+    }
+    memcpy(part, cp, sizeof(uint32_t) * h0->n);
+    *f_out = f;
+    if (levels_out) *levels_out = nl;
+    for (uint32_t l = 0; l < nl; ++l) {
+        free(L[l].cid); free(L[l].pin_off); free(L[l].pins); free(L[l].inc_off);
+        free(L[l].inc); free(L[l].vwgt); free(L[l].nwgt);
+    }
+    free(L); free(rep); free(cp);
+    return OR_OK;
+}

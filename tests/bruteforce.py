@@ -1,0 +1,84 @@
+"""Pure-Python brute force from the paper's definitions, on tiny inputs.
+
+Independent of the oracle: sets and dictionaries, no shared code.  Used to pin
+the oracle (and through it the GPU path)."""
+from __future__ import annotations
+
+import itertools
+
+
+def nets_of(h):
+    return [tuple(int(x) for x in h.pins[h.pin_off[e]:h.pin_off[e + 1]]) for e in range(h.m)]
+
+
+def objective(h, part):
+    """Connectivity metric: sum over cut nets of (lambda(e) - 1) * w(e)."""
+    f = 0
+    for e, pins in enumerate(nets_of(h)):
+        lam = len({int(part[v]) for v in pins})
+        if lam > 1:
+            f += (lam - 1) * int(h.nwgt[e])
+    return f
+
+
+def cut_net(h, part):
+    """Cut-net metric: total weight of nets spanning more than one block."""
+    return sum(int(h.nwgt[e]) for e, pins in enumerate(nets_of(h)) if len({int(part[v]) for v in pins}) > 1)
+
+
+def move_delta(h, part, u, t):
+    """f(Pi) - f(Pi with u moved to t), recomputed from scratch."""
+    q = [int(x) for x in part]
+    before = objective(h, q)
+    q[u] = t
+    return before - objective(h, q)
+
+
+def rating(h, rep, u):
+    """r(u, C) = sum over nets e with u in e and e touching C of floor(w * 2^32 / (|e|-1));
+    C ranges over clusters other than u's, identified by representative."""
+    members = {}
+    for v, c in enumerate(rep):
+        members.setdefault(int(c), set()).add(v)
+    nets = nets_of(h)
+    R = {}
+    for C, mem in members.items():
+        if C == int(rep[u]):
+            continue
+        tot = 0
+        for e, pins in enumerate(nets):
+            if len(pins) >= 2 and u in pins and mem.intersection(pins):
+                tot += (int(h.nwgt[e]) << 32) // (len(pins) - 1)
+        if tot:
+            R[C] = tot
+    return R
+
+
+def contract_sets(h, rep):
+    """Contraction by sets: coarse net multiset {frozenset(cluster ids): summed weight}
+    with single-pin nets removed; clusters named by their representative."""
+    out = {}
+    for e, pins in enumerate(nets_of(h)):
+        s = frozenset(int(rep[v]) for v in pins)
+        if len(s) < 2:
+            continue
+        out[s] = out.get(s, 0) + int(h.nwgt[e])
+    return out
+
+
+def merge_path_states(ca, cb):
+    """States (i, j) of merging the exclusive prefix sums of A and B by value,
+    A first on ties -- the merge reading of the two-pointer walk."""
+    pa = list(itertools.accumulate([0] + list(ca)))[:-1]
+    pb = list(itertools.accumulate([0] + list(cb)))[:-1]
+    items = [(pa[i], 0, i) for i in range(len(ca))] + [(pb[j], 1, j) for j in range(len(cb))]
+    items.sort()
+    states = [(0, 0)]
+    i = j = 0
+    for _, side, _idx in items:
+        if side == 0:
+            i += 1
+        else:
+            j += 1
+        states.append((i, j))
+    return states
