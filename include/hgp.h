@@ -1,0 +1,192 @@
+/*
+ * hgp.h -- C ABI of the MI355X (gfx950) multilevel hypergraph partitioning
+ * hot path: clustering-based coarsening, contraction, and deterministic
+ * label-propagation refinement of the connectivity (lambda-1) objective,
+ * after Gottesbüren, Heuer, Maas, Sanders, Schlag, "Scalable High-Quality
+ * Hypergraph Partitioning" (arXiv 2303.17679).
+ *
+ * Conventions for every entry point
+ *  - Array arguments are DEVICE pointers (HIP device memory on the current
+ *    device) unless a comment says "host".  The caller owns every buffer,
+ *    including the workspace; the library never allocates device memory,
+ *    never frees, and keeps no pointer past the end of the call.
+ *  - IDs and offsets are uint32, vertex and net weights int32 (>= 1).
+ *  - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).
+ *    Entry points marked "syncs" wait for `stream` before returning
+ *    because the host needs device-computed sizes; the others may return
+ *    before the device work is done.
+ *  - Arguments are checked on the host before anything is enqueued; a bad
+ *    argument returns an error status and enqueues nothing.  Device launch
+ *    failures return HGP_E_DEVICE.  Nothing throws across the ABI.
+ *  - Results are deterministic: for equal inputs and parameters every entry
+ *    point produces bit-identical outputs on every run and launch
+ *    configuration.  All arithmetic is integer.
+ *
+ * Workspace: every entry point that needs scratch memory takes `ws`
+ * (device, 256-byte aligned) and `ws_bytes`; the required size comes from
+ * hgp_workspace_bytes().  Too small a workspace returns HGP_E_WORKSPACE.
+ */
+#ifndef HGP_H
+#define HGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hgp_status;
+#define HGP_OK 0
+#define HGP_E_INVALID (-1)     /* argument or input out of range / malformed   */
+#define HGP_E_OVERFLOW (-2)    /* total weights would overflow 2^31             */
+#define HGP_E_WORKSPACE (-3)   /* workspace too small                           */
+#define HGP_E_DEVICE (-4)      /* HIP runtime or launch error                   */
+#define HGP_E_UNSUPPORTED (-5) /* valid but not supported (e.g. k > 256)        */
+
+/* A hypergraph level H = (V, E, c, w) as two adjacency arrays (paper Sec. 4.2):
+ * pin lists of the nets and incident-net lists of the vertices.
+ * Preconditions: n >= 1; pin_off[0] = 0, pin_off[m] = p, non-decreasing;
+ * pins of a net strictly ascending and < n; inc_off/inc is the exact transpose
+ * with nets strictly ascending per vertex; c(V) = sum vwgt < 2^31 and
+ * sum nwgt < 2^31; m < 2^32 - 1.  hgp_validate() checks all of this. */
+typedef struct {
+    uint32_t n, m, p;
+    const uint32_t *pin_off; /* [m+1] */
+    const uint32_t *pins;    /* [p]   */
+    const uint32_t *inc_off; /* [n+1] */
+    const uint32_t *inc;     /* [p]   */
+    const int32_t *vwgt;     /* [n]   */
+    const int32_t *nwgt;     /* [m]   */
+} hgp_hg;
+
+/* Caller-allocated buffers of a contracted level.  Capacities of the fine
+ * level always suffice (n' <= n, m' <= m, p' <= p). */
+typedef struct {
+    uint32_t cap_n, cap_m, cap_p;
+    uint32_t *pin_off; /* [cap_m+1] */
+    uint32_t *pins;    /* [cap_p]   */
+    uint32_t *inc_off; /* [cap_n+1] */
+    uint32_t *inc;     /* [cap_p]   */
+    int32_t *vwgt;     /* [cap_n]   */
+    int32_t *nwgt;     /* [cap_m]   */
+    uint32_t *dims;    /* device [3] <- n', m', p' */
+} hgp_hg_out;
+
+/* Parameters.  Every field changes results, so tests pass the same values
+ * to the reference implementation.  hgp_default_params() fills the
+ * defaults given in brackets. */
+typedef struct {
+    uint32_t k;                 /* number of blocks, 2..256                          */
+    uint32_t eps_num, eps_den;  /* imbalance eps = num/den exactly [3/100]; den <= 2^20 */
+    uint64_t seed;              /* seed of the tie-break / sub-round hash [0]        */
+    uint32_t limit_factor;      /* coarsen while n > limit_factor * k [160] (Sec. 4.1) */
+    uint32_t coarsen_subrounds; /* S_c, sub-rounds of a clustering pass [3] (Sec. 11)  */
+    uint32_t lp_subrounds;      /* S_lp, sub-rounds of an LP round [5] (Sec. 11)       */
+    uint32_t lp_rounds;         /* R_lp, maximum LP rounds per level [5]               */
+} hgp_params;
+
+/* Workspace-size queries. */
+#define HGP_OP_COARSEN 1
+#define HGP_OP_CONTRACT 2
+#define HGP_OP_REFINE 3
+#define HGP_OP_PARTITION 4
+#define HGP_OP_VALIDATE 5
+#define HGP_OP_INITIAL 6
+
+/* Host.  Fills *out with the defaults listed in hgp_params for k blocks. */
+hgp_status hgp_default_params(uint32_t k, hgp_params *out);
+
+/* Host.  Workspace bytes needed by operation `op` on a level of n vertices,
+ * m nets and p pins.  For HGP_OP_PARTITION the figure includes room for the
+ * coarse hierarchy; a hierarchy that outgrows it makes hgp_partition return
+ * HGP_E_WORKSPACE (the figure assumes the pin count shrinks by at least a
+ * third over the whole hierarchy, which holds for the inputs tested). */
+hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p,
+                               const hgp_params *prm, size_t *out);
+
+/* Checks every precondition of hgp_hg on the device (monotone offsets, pins
+ * in range and strictly ascending, incidence = exact transpose, weights >= 1,
+ * total weights < 2^31).  Syncs.  Returns HGP_OK, HGP_E_INVALID or
+ * HGP_E_OVERFLOW. */
+hgp_status hgp_validate(const hgp_hg *h, void *ws, size_t ws_bytes, void *stream);
+
+/* One clustering pass of coarsening level `level` (paper Sec. 4.1 heavy-edge
+ * rating, contraction limit and c_max; Sec. 11 deterministic clustering):
+ * S_c sub-rounds; the unclustered singletons u with
+ * H(seed,1,level,0,u) mod S_c = r rate the clusters of their neighbours by
+ * r(u,C) = sum over e in I(u) touching C of floor(w(e) * 2^32 / (|e|-1)), each
+ * net once per cluster; they may not join a candidate singleton of the same
+ * sub-round and must keep 160k*(c(u)+c(C)) <= c(V); ties go to the smaller
+ * H(seed,2,level,0,C), then the smaller C.  Joins are grouped by target,
+ * ordered by (c(u), u) and the longest prefix within c_max is approved.  The
+ * pass stops after the first sub-round leaving fewer than n/2.5 clusters.
+ * Output rep[n] (rep[u] = representative, rep[rep[u]] = rep[u]) and
+ * *n_clusters (device uint32). */
+hgp_status hgp_coarsen(const hgp_hg *h, const hgp_params *prm, uint32_t level,
+                       uint32_t *rep, uint32_t *n_clusters,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Contraction of the clustering rep (paper Sec. 4.2): coarse vertex IDs
+ * cid[v] = rank of rep[v] among the representatives (ascending); coarse
+ * vertex weights are cluster sums; each net's pins are replaced by their coarse
+ * IDs, sorted ascending and de-duplicated; nets left with fewer than two
+ * pins are dropped; identical nets are merged into the one with the smallest
+ * fine net ID, carrying the summed weight; kept nets are numbered in ascending
+ * fine ID; the incidence arrays are the exact transpose.  Writes cid[n],
+ * every array of *out and out->dims. */
+hgp_status hgp_contract(const hgp_hg *fine, const uint32_t *rep, uint32_t *cid,
+                        const hgp_hg_out *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Projection of a coarse partition to the finer level (paper Sec. 3):
+ * part[v] = coarse_part[cid[v]] for v < n. */
+hgp_status hgp_project(uint32_t n, const uint32_t *cid, const uint32_t *coarse_part,
+                       uint32_t *part, void *stream);
+
+/* Connectivity objective (paper Sec. 2) of a partition: *objective (device
+ * int64) = sum over nets with lambda(e) > 1 of (lambda(e)-1) w(e), and
+ * block_wgt[k] (device int64, may be NULL) = c(V_b). */
+hgp_status hgp_objective(const hgp_hg *h, uint32_t k, const uint32_t *part,
+                         int64_t *objective, int64_t *block_wgt,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* Deterministic synchronous label propagation of level `level` (paper
+ * Sec. 11; gain of Sec. 6): up to R_lp rounds of S_lp sub-rounds; the nodes u
+ * with H(seed,3,level,round,u) mod S_lp = s compute on the sub-round snapshot
+ * their best move (largest positive connectivity gain, target block able to
+ * take c(u) within L_max = (1+eps)ceil(c(V)/k), ties to the smaller block);
+ * per block pair (s,t) the moves s->t and t->s are sorted by (gain desc, u asc)
+ * and the last feasible state of the two-pointer merge walk is applied, with
+ * per-pair budget floor((L_max - c(V_b))/(k-1)) for each block b of the pair.
+ * Stops after a round without moves.  part[n] is refined in place;
+ * *objective (device int64) and block_wgt[k] (device int64, may be NULL)
+ * receive the result's objective and block weights. */
+hgp_status hgp_refine_lp(const hgp_hg *h, const hgp_params *prm, uint32_t level,
+                         uint32_t *part, int64_t *objective, int64_t *block_wgt,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* Simple deterministic initial partition of the coarsest level: vertices in
+ * breadth-first order (start at the smallest unvisited ID; neighbours in
+ * ascending incident-net then pin order), assigned to block 0, 1, ... in turn,
+ * moving to the next block once the current one reaches ceil(c(V)/k).
+ * Writes part[n]. */
+hgp_status hgp_initial_partition(const hgp_hg *h, uint32_t k, uint32_t *part,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/* Whole multilevel partition (paper Alg. 1 with the deterministic components
+ * above, without FM and flows): coarsen while n > limit_factor*k and a pass
+ * shrinks n by more than 1 %; greedy initial partition of the coarsest level;
+ * LP on the coarsest level, then project + LP on every finer level.
+ * Writes part[n] and *objective (device int64); *levels_out (host, may be
+ * NULL) gets the number of contractions.  Syncs. */
+hgp_status hgp_partition(const hgp_hg *h, const hgp_params *prm, uint32_t *part,
+                         int64_t *objective, uint32_t *levels_out,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* Host.  Static description of a status code. */
+const char *hgp_status_str(hgp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HGP_H */

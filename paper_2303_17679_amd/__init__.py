@@ -1,0 +1,275 @@
+"""Python binding of libhgp.so, the gfx950 multilevel hypergraph partitioning
+hot path (coarsening, contraction, deterministic label propagation) of
+"Scalable High-Quality Hypergraph Partitioning" (arXiv 2303.17679).
+
+Argument marshalling only: every step runs in the HIP library.  PyTorch
+provides device memory (int32 tensors holding uint32 IDs) and the current
+stream.  If the library is not built, every call raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgp.so")
+
+OP_COARSEN, OP_CONTRACT, OP_REFINE, OP_PARTITION, OP_VALIDATE, OP_INITIAL = 1, 2, 3, 4, 5, 6
+STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_OVERFLOW", -3: "HGP_E_WORKSPACE",
+          -4: "HGP_E_DEVICE", -5: "HGP_E_UNSUPPORTED"}
+
+EXPORTS = ["hgp_default_params", "hgp_workspace_bytes", "hgp_validate", "hgp_coarsen", "hgp_contract",
+           "hgp_project", "hgp_objective", "hgp_refine_lp", "hgp_initial_partition", "hgp_partition",
+           "hgp_status_str"]
+
+
+class HGPError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({_status_str(status)})")
+
+
+class _HG(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint32), ("p", ctypes.c_uint32),
+                ("pin_off", ctypes.c_void_p), ("pins", ctypes.c_void_p),
+                ("inc_off", ctypes.c_void_p), ("inc", ctypes.c_void_p),
+                ("vwgt", ctypes.c_void_p), ("nwgt", ctypes.c_void_p)]
+
+
+class _HGOut(ctypes.Structure):
+    _fields_ = [("cap_n", ctypes.c_uint32), ("cap_m", ctypes.c_uint32), ("cap_p", ctypes.c_uint32),
+                ("pin_off", ctypes.c_void_p), ("pins", ctypes.c_void_p),
+                ("inc_off", ctypes.c_void_p), ("inc", ctypes.c_void_p),
+                ("vwgt", ctypes.c_void_p), ("nwgt", ctypes.c_void_p), ("dims", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    """Mirror of hgp_params (every field changes results)."""
+    _fields_ = [("k", ctypes.c_uint32), ("eps_num", ctypes.c_uint32), ("eps_den", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("limit_factor", ctypes.c_uint32),
+                ("coarsen_subrounds", ctypes.c_uint32), ("lp_subrounds", ctypes.c_uint32),
+                ("lp_rounds", ctypes.c_uint32)]
+
+
+def params(k: int, eps=(3, 100), seed: int = 0, limit_factor: int = 160, coarsen_subrounds: int = 3,
+           lp_subrounds: int = 5, lp_rounds: int = 5) -> Params:
+    return Params(k, eps[0], eps[1], seed, limit_factor, coarsen_subrounds, lp_subrounds, lp_rounds)
+
+
+_lib = None
+
+
+def lib():
+    """Load libhgp.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2303_17679_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, u32, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32
+        L.hgp_default_params.restype = i32; L.hgp_default_params.argtypes = [u32, P]
+        L.hgp_workspace_bytes.restype = i32
+        L.hgp_workspace_bytes.argtypes = [ctypes.c_int, u32, u32, u32, P, ctypes.POINTER(ctypes.c_size_t)]
+        L.hgp_validate.restype = i32; L.hgp_validate.argtypes = [P, P, ctypes.c_size_t, P]
+        L.hgp_coarsen.restype = i32; L.hgp_coarsen.argtypes = [P, P, u32, P, P, P, ctypes.c_size_t, P]
+        L.hgp_contract.restype = i32; L.hgp_contract.argtypes = [P, P, P, P, P, ctypes.c_size_t, P]
+        L.hgp_project.restype = i32; L.hgp_project.argtypes = [u32, P, P, P, P]
+        L.hgp_objective.restype = i32; L.hgp_objective.argtypes = [P, u32, P, P, P, P, ctypes.c_size_t, P]
+        L.hgp_refine_lp.restype = i32; L.hgp_refine_lp.argtypes = [P, P, u32, P, P, P, P, ctypes.c_size_t, P]
+        L.hgp_initial_partition.restype = i32
+        L.hgp_initial_partition.argtypes = [P, u32, P, P, ctypes.c_size_t, P]
+        L.hgp_partition.restype = i32
+        L.hgp_partition.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_uint32), P, ctypes.c_size_t, P]
+        L.hgp_status_str.restype = ctypes.c_char_p; L.hgp_status_str.argtypes = [i32]
+        _lib = L
+    return _lib
+
+
+def _status_str(s: int) -> str:
+    try:
+        return lib().hgp_status_str(s).decode()
+    except Exception:  # library missing: still report the code
+        return str(s)
+
+
+def _check(s: int, what: str):
+    if s != 0:
+        raise HGPError(s, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+@dataclass
+class Hypergraph:
+    """Device-resident level: int32 tensors (uint32 values) on a GPU."""
+    n: int
+    m: int
+    p: int
+    pin_off: object
+    pins: object
+    inc_off: object
+    inc: object
+    vwgt: object
+    nwgt: object
+
+    @classmethod
+    def from_host(cls, h, device="cuda"):
+        torch = _torch()
+
+        def t(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(device)
+        return cls(int(h.n), int(h.m), int(len(h.pins)), t(h.pin_off, np.int32), t(h.pins, np.int32),
+                   t(h.inc_off, np.int32), t(h.inc, np.int32), t(h.vwgt, np.int32), t(h.nwgt, np.int32))
+
+    def to_host(self):
+        from types import SimpleNamespace
+
+        def a(x):
+            return x.cpu().numpy().view(np.uint32)
+        return SimpleNamespace(n=self.n, m=self.m, pin_off=a(self.pin_off), pins=a(self.pins),
+                               inc_off=a(self.inc_off), inc=a(self.inc),
+                               vwgt=self.vwgt.cpu().numpy().astype(np.int32),
+                               nwgt=self.nwgt.cpu().numpy().astype(np.int32))
+
+    def struct(self) -> _HG:
+        return _HG(self.n, self.m, self.p, _ptr(self.pin_off), _ptr(self.pins), _ptr(self.inc_off),
+                   _ptr(self.inc), _ptr(self.vwgt), _ptr(self.nwgt))
+
+    @property
+    def device(self):
+        return self.pin_off.device
+
+
+def workspace_bytes(op: int, n: int, m: int, p: int, prm: Params | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().hgp_workspace_bytes(op, n, m, p, ctypes.byref(prm) if prm is not None else None,
+                                     ctypes.byref(out)), "hgp_workspace_bytes")
+    return int(out.value)
+
+
+def _ws(op, h: Hypergraph, prm=None):
+    torch = _torch()
+    nb = workspace_bytes(op, h.n, h.m, h.p, prm)
+    return torch.empty(nb, dtype=torch.uint8, device=h.device)
+
+
+def validate(h: Hypergraph) -> int:
+    ws = _ws(OP_VALIDATE, h)
+    s = h.struct()
+    return int(lib().hgp_validate(ctypes.byref(s), _ptr(ws), ws.numel(), _stream()))
+
+
+def coarsen(h: Hypergraph, prm: Params, level: int = 0):
+    """One clustering pass; returns (rep tensor, number of clusters)."""
+    torch = _torch()
+    rep = torch.empty(h.n, dtype=torch.int32, device=h.device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=h.device)
+    ws = _ws(OP_COARSEN, h, prm)
+    s = h.struct()
+    _check(lib().hgp_coarsen(ctypes.byref(s), ctypes.byref(prm), level, _ptr(rep), _ptr(cnt), _ptr(ws),
+                             ws.numel(), _stream()), "hgp_coarsen")
+    return rep, int(cnt.item())
+
+
+def contract(h: Hypergraph, rep):
+    """Contract a clustering; returns (cid tensor, coarse Hypergraph)."""
+    torch = _torch()
+    dev = h.device
+    cid = torch.empty(h.n, dtype=torch.int32, device=dev)
+    bufs = dict(pin_off=torch.empty(h.m + 1, dtype=torch.int32, device=dev),
+                pins=torch.empty(max(h.p, 1), dtype=torch.int32, device=dev),
+                inc_off=torch.empty(h.n + 1, dtype=torch.int32, device=dev),
+                inc=torch.empty(max(h.p, 1), dtype=torch.int32, device=dev),
+                vwgt=torch.empty(h.n, dtype=torch.int32, device=dev),
+                nwgt=torch.empty(max(h.m, 1), dtype=torch.int32, device=dev))
+    dims = torch.zeros(3, dtype=torch.int32, device=dev)
+    out = _HGOut(h.n, h.m, h.p, *[_ptr(bufs[k]) for k in ("pin_off", "pins", "inc_off", "inc", "vwgt", "nwgt")],
+                 _ptr(dims))
+    ws = _ws(OP_CONTRACT, h)
+    s = h.struct()
+    _check(lib().hgp_contract(ctypes.byref(s), _ptr(rep), _ptr(cid), ctypes.byref(out), _ptr(ws), ws.numel(),
+                              _stream()), "hgp_contract")
+    nc, mc, pc = (int(x) for x in dims.cpu().tolist())
+    H = Hypergraph(nc, mc, pc, bufs["pin_off"][:mc + 1], bufs["pins"][:pc], bufs["inc_off"][:nc + 1],
+                   bufs["inc"][:pc], bufs["vwgt"][:nc], bufs["nwgt"][:mc])
+    return cid, H
+
+
+def project(cid, coarse_part):
+    torch = _torch()
+    part = torch.empty(cid.numel(), dtype=torch.int32, device=cid.device)
+    _check(lib().hgp_project(cid.numel(), _ptr(cid), _ptr(coarse_part), _ptr(part), _stream()), "hgp_project")
+    return part
+
+
+def objective(h: Hypergraph, k: int, part):
+    torch = _torch()
+    f = torch.zeros(1, dtype=torch.int64, device=h.device)
+    bw = torch.zeros(k, dtype=torch.int64, device=h.device)
+    ws = _ws(OP_REFINE, h, params(k))
+    s = h.struct()
+    _check(lib().hgp_objective(ctypes.byref(s), k, _ptr(part), _ptr(f), _ptr(bw), _ptr(ws), ws.numel(),
+                               _stream()), "hgp_objective")
+    return int(f.item()), bw
+
+
+def refine_lp(h: Hypergraph, prm: Params, level: int, part):
+    """LP refinement in place on `part`; returns (objective, block weights)."""
+    torch = _torch()
+    f = torch.zeros(1, dtype=torch.int64, device=h.device)
+    bw = torch.zeros(prm.k, dtype=torch.int64, device=h.device)
+    ws = _ws(OP_REFINE, h, prm)
+    s = h.struct()
+    _check(lib().hgp_refine_lp(ctypes.byref(s), ctypes.byref(prm), level, _ptr(part), _ptr(f), _ptr(bw),
+                               _ptr(ws), ws.numel(), _stream()), "hgp_refine_lp")
+    return int(f.item()), bw
+
+
+def initial_partition(h: Hypergraph, k: int):
+    torch = _torch()
+    part = torch.empty(h.n, dtype=torch.int32, device=h.device)
+    ws = _ws(OP_INITIAL, h, params(k))
+    s = h.struct()
+    _check(lib().hgp_initial_partition(ctypes.byref(s), k, _ptr(part), _ptr(ws), ws.numel(), _stream()),
+           "hgp_initial_partition")
+    return part
+
+
+class Partitioner:
+    """Reusable partitioner: the workspace is allocated once per size."""
+
+    def __init__(self, h: Hypergraph, prm: Params):
+        torch = _torch()
+        self.h, self.prm = h, prm
+        self.ws = _ws(OP_PARTITION, h, prm)
+        self.part = torch.empty(h.n, dtype=torch.int32, device=h.device)
+        self.f = torch.zeros(1, dtype=torch.int64, device=h.device)
+        self._s = h.struct()
+
+    def run(self):
+        lv = ctypes.c_uint32(0)
+        _check(lib().hgp_partition(ctypes.byref(self._s), ctypes.byref(self.prm), _ptr(self.part), _ptr(self.f),
+                                   ctypes.byref(lv), _ptr(self.ws), self.ws.numel(), _stream()), "hgp_partition")
+        return int(lv.value)
+
+
+def partition(h: Hypergraph, prm: Params):
+    """Whole multilevel partition; returns (part tensor, objective, levels)."""
+    P = Partitioner(h, prm)
+    levels = P.run()
+    return P.part, int(P.f.item()), levels

@@ -1,0 +1,269 @@
+// extern "C" entry points: argument checks, workspace arena, the multilevel
+// driver (paper Alg. 1 with the deterministic components, no FM / flows).
+#include "kernels.h"
+#include <algorithm>
+#include <vector>
+
+using namespace hgp;
+
+namespace {
+
+hipStream_t S(void *stream) { return (hipStream_t)stream; }
+
+hgp_status check_params(const hgp_params *p) {
+    if (!p) return HGP_E_INVALID;
+    if (p->k < 2) return HGP_E_INVALID;
+    if (p->k > 256) return HGP_E_UNSUPPORTED;
+    if (p->eps_den == 0 || p->eps_den > (1u << 20) || p->eps_num > p->eps_den) return HGP_E_INVALID;
+    if (p->limit_factor == 0 || p->coarsen_subrounds == 0 || p->lp_subrounds == 0) return HGP_E_INVALID;
+    if (p->coarsen_subrounds > 256 || p->lp_subrounds > 256 || p->lp_rounds > 65535) return HGP_E_INVALID;
+    return HGP_OK;
+}
+
+hgp_status check_hg(const hgp_hg *h) {
+    if (!h) return HGP_E_INVALID;
+    if (h->n == 0 || h->n >= 0x80000000u || h->m >= 0xFFFFFFFFu) return HGP_E_INVALID;
+    if (!h->pin_off || !h->inc_off || !h->vwgt) return HGP_E_INVALID;
+    if (h->m && !h->nwgt) return HGP_E_INVALID;
+    if (h->p && (!h->pins || !h->inc)) return HGP_E_INVALID;
+    return HGP_OK;
+}
+
+template <class F>
+hgp_status guarded(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        return e.code;
+    } catch (...) {
+        return HGP_E_DEVICE;
+    }
+}
+
+size_t level_bytes(uint32_t n, uint32_t m, uint32_t p) {
+    // arrays of one stored level: pin_off, pins, inc_off, inc, vwgt, nwgt, cid, part
+    return 4ull * ((size_t)m + 1 + p + (size_t)n + 1 + p + n + m + n + n) + 8 * 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+hgp_status hgp_default_params(uint32_t k, hgp_params *out) {
+    if (!out) return HGP_E_INVALID;
+    out->k = k;
+    out->eps_num = 3;
+    out->eps_den = 100;
+    out->seed = 0;
+    out->limit_factor = 160;
+    out->coarsen_subrounds = 3;
+    out->lp_subrounds = 5;
+    out->lp_rounds = 5;
+    return HGP_OK;
+}
+
+hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p, const hgp_params *prm, size_t *out) {
+    if (!out) return HGP_E_INVALID;
+    hgp_params dp;
+    uint32_t k = 2;
+    if (prm) {
+        hgp_status s = check_params(prm);
+        if (s != HGP_OK) return s;
+        dp = *prm;
+        k = prm->k;
+    } else {
+        hgp_default_params(2, &dp);
+    }
+    return guarded([&]() -> hgp_status {
+        size_t need = 0;
+        switch (op) {
+            case HGP_OP_COARSEN: need = coarsen_workspace(n, m, p, dp); break;
+            case HGP_OP_CONTRACT: need = contract_workspace(n, m, p); break;
+            case HGP_OP_REFINE: need = refine_workspace(n, m, k); break;
+            case HGP_OP_VALIDATE: need = util_workspace(n, m); break;
+            case HGP_OP_INITIAL: need = ip_workspace(n, k); break;
+            case HGP_OP_PARTITION: {
+                size_t temp = std::max({coarsen_workspace(n, m, p, dp), contract_workspace(n, m, p),
+                                        refine_workspace(n, m, k), ip_workspace(n, k), util_workspace(n, m)});
+                // hierarchy: coarse levels are stored with the capacities of the
+                // level they come from; rep of the level being coarsened on top
+                size_t hier = 3 * level_bytes(n, m, p) + 4ull * n + 4096;
+                need = temp + hier;
+                break;
+            }
+            default: return HGP_E_INVALID;
+        }
+        *out = need + 4096;
+        return HGP_OK;
+    });
+}
+
+hgp_status hgp_validate(const hgp_hg *h, void *ws, size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h);
+    if (s != HGP_OK) return s;
+    if (!ws) return HGP_E_WORKSPACE;
+    return guarded([&]() {
+        Arena A(ws, ws_bytes);
+        return validate(*h, A, S(stream));
+    });
+}
+
+hgp_status hgp_coarsen(const hgp_hg *h, const hgp_params *prm, uint32_t level, uint32_t *rep, uint32_t *n_clusters,
+                       void *ws, size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h);
+    if (s == HGP_OK) s = check_params(prm);
+    if (s != HGP_OK) return s;
+    if (!rep || !ws) return HGP_E_INVALID;
+    return guarded([&]() {
+        Arena A(ws, ws_bytes);
+        coarsen_pass(*h, *prm, level, rep, n_clusters, nullptr, A, S(stream));
+        return HGP_OK;
+    });
+}
+
+hgp_status hgp_contract(const hgp_hg *fine, const uint32_t *rep, uint32_t *cid, const hgp_hg_out *out, void *ws,
+                        size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(fine);
+    if (s != HGP_OK) return s;
+    if (!rep || !cid || !out || !ws || !out->pin_off || !out->inc_off || !out->vwgt) return HGP_E_INVALID;
+    if (out->cap_n < 1 || (fine->m && !out->nwgt) || (fine->p && (!out->pins || !out->inc))) return HGP_E_INVALID;
+    return guarded([&]() {
+        Arena A(ws, ws_bytes);
+        contract(*fine, rep, cid, *out, nullptr, A, S(stream));
+        return HGP_OK;
+    });
+}
+
+hgp_status hgp_project(uint32_t n, const uint32_t *cid, const uint32_t *coarse_part, uint32_t *part, void *stream) {
+    if (n && (!cid || !coarse_part || !part)) return HGP_E_INVALID;
+    return guarded([&]() {
+        project(n, cid, coarse_part, part, S(stream));
+        return HGP_OK;
+    });
+}
+
+hgp_status hgp_objective(const hgp_hg *h, uint32_t k, const uint32_t *part, int64_t *objective, int64_t *block_wgt,
+                         void *ws, size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h);
+    if (s != HGP_OK) return s;
+    if (k < 2) return HGP_E_INVALID;
+    if (k > 256) return HGP_E_UNSUPPORTED;
+    if (!part || !objective || !ws) return HGP_E_INVALID;
+    return guarded([&]() {
+        Arena A(ws, ws_bytes);
+        hgp::objective(*h, k, part, objective, block_wgt, A, S(stream));
+        return HGP_OK;
+    });
+}
+
+hgp_status hgp_refine_lp(const hgp_hg *h, const hgp_params *prm, uint32_t level, uint32_t *part, int64_t *objective,
+                         int64_t *block_wgt, void *ws, size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h);
+    if (s == HGP_OK) s = check_params(prm);
+    if (s != HGP_OK) return s;
+    if (!part || !ws) return HGP_E_INVALID;
+    return guarded([&]() {
+        Arena A(ws, ws_bytes);
+        refine_lp(*h, *prm, level, part, objective, block_wgt, A, S(stream));
+        return HGP_OK;
+    });
+}
+
+hgp_status hgp_initial_partition(const hgp_hg *h, uint32_t k, uint32_t *part, void *ws, size_t ws_bytes,
+                                 void *stream) {
+    hgp_status s = check_hg(h);
+    if (s != HGP_OK) return s;
+    if (k < 2) return HGP_E_INVALID;
+    if (k > 256) return HGP_E_UNSUPPORTED;
+    if (!part || !ws) return HGP_E_INVALID;
+    return guarded([&]() {
+        Arena A(ws, ws_bytes);
+        initial_partition(*h, k, part, A, S(stream));
+        return HGP_OK;
+    });
+}
+
+hgp_status hgp_partition(const hgp_hg *h0, const hgp_params *prm, uint32_t *part, int64_t *objective,
+                         uint32_t *levels_out, void *ws, size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h0);
+    if (s == HGP_OK) s = check_params(prm);
+    if (s != HGP_OK) return s;
+    if (!part || !objective || !ws) return HGP_E_INVALID;
+    hipStream_t st = S(stream);
+    return guarded([&]() -> hgp_status {
+        Arena A(ws, ws_bytes);
+        hgp_status v = validate(*h0, A, st);
+        if (v != HGP_OK) return v;
+        struct Level {
+            hgp_hg h;
+            uint32_t *cid;  // map to the next coarser level
+        };
+        std::vector<Level> L;
+        L.push_back({*h0, nullptr});
+        const uint64_t limit = (uint64_t)prm->limit_factor * prm->k;
+        for (;;) {
+            hgp_hg cur = L.back().h;
+            if (!((uint64_t)cur.n > limit)) break;
+            size_t mk = A.mark();
+            // storage of the would-be coarse level (capacities of this level)
+            uint32_t *cid = A.alloc<uint32_t>(cur.n);
+            hgp_hg_out out;
+            out.cap_n = cur.n; out.cap_m = cur.m; out.cap_p = cur.p;
+            out.pin_off = A.alloc<uint32_t>((size_t)cur.m + 1);
+            out.pins = A.alloc<uint32_t>(cur.p);
+            out.inc_off = A.alloc<uint32_t>((size_t)cur.n + 1);
+            out.inc = A.alloc<uint32_t>(cur.p);
+            out.vwgt = A.alloc<int32_t>(cur.n);
+            out.nwgt = A.alloc<int32_t>(cur.m);
+            out.dims = nullptr;
+            size_t mk_rep = A.mark();
+            uint32_t *rep = A.alloc<uint32_t>(cur.n);
+            uint32_t cnt = 0;
+            coarsen_pass(cur, *prm, (uint32_t)(L.size() - 1), rep, nullptr, &cnt, A, st);
+            if ((uint64_t)100 * (cur.n - cnt) <= (uint64_t)cur.n) {
+                A.release(mk);
+                break;
+            }
+            uint32_t dims[3];
+            contract(cur, rep, cid, out, dims, A, st);
+            A.release(mk_rep);
+            hgp_hg nh;
+            nh.n = dims[0]; nh.m = dims[1]; nh.p = dims[2];
+            nh.pin_off = out.pin_off; nh.pins = out.pins; nh.inc_off = out.inc_off; nh.inc = out.inc;
+            nh.vwgt = out.vwgt; nh.nwgt = out.nwgt;
+            L.back().cid = cid;
+            L.push_back({nh, nullptr});
+            if (L.size() > 4096) break;
+        }
+        const uint32_t nl = (uint32_t)L.size() - 1;
+        // initial partition and LP on the coarsest level
+        hgp_hg cs = L.back().h;
+        uint32_t *cpart = (nl == 0) ? part : A.alloc<uint32_t>(cs.n);
+        initial_partition(cs, prm->k, cpart, A, st);
+        refine_lp(cs, *prm, nl, cpart, objective, nullptr, A, st);
+        for (int l = (int)nl - 1; l >= 0; --l) {
+            hgp_hg fh = L[l].h;
+            uint32_t *fpart = (l == 0) ? part : A.alloc<uint32_t>(fh.n);
+            project(fh.n, L[l].cid, cpart, fpart, st);
+            refine_lp(fh, *prm, (uint32_t)l, fpart, objective, nullptr, A, st);
+            cpart = fpart;
+        }
+        HGP_CHECK_HIP(hipStreamSynchronize(st));
+        if (levels_out) *levels_out = nl;
+        return HGP_OK;
+    });
+}
+
+const char *hgp_status_str(hgp_status s) {
+    switch (s) {
+        case HGP_OK: return "ok";
+        case HGP_E_INVALID: return "invalid argument or malformed input";
+        case HGP_E_OVERFLOW: return "total weight would overflow 2^31";
+        case HGP_E_WORKSPACE: return "workspace too small";
+        case HGP_E_DEVICE: return "HIP runtime or launch error";
+        case HGP_E_UNSUPPORTED: return "unsupported parameter (k > 256)";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,555 @@
+// Clustering pass of coarsening (paper Sec. 4.1: heavy-edge rating,
+// contraction limit, cluster weight limit c_max; Sec. 11: deterministic
+// clustering with sub-rounds, group-by target, ascending-weight prefix).
+//
+// GPU design.  A sub-round has three steps.
+//  1. Rating.  Each candidate u aggregates r(u,C) over the clusters of its
+//     neighbourhood in a hash table of its own.  Candidates are binned once
+//     per level by B(u) = sum over incident nets (|e|-1), an upper bound on
+//     their distinct neighbour clusters: groups of 8, 16 or 64 lanes with
+//     LDS tables of 64 / 256 / 1024 entries (load <= 2/3), a whole block
+//     with a 4096-entry LDS table, or a block with a table slice in global
+//     memory.  A group walks the incident nets one at a time, the lanes over
+//     the pins; a per-slot "last net" stamp (atomic exchange) lets exactly one
+//     lane add w(e)/(|e|-1) per (net, cluster), which is the set semantics of
+//     the rating formula.  The argmax (rating desc, tie hash asc, ID asc) is a
+//     shuffle reduction.  The winning join adds c(u) to tsum[C] (integer
+//     atomics: order independent), the paper's "sum up cluster weights during
+//     the target-cluster calculation".
+//  2. Approval.  A target whose whole group fits (160k (c(C) + tsum) <= c(V))
+//     approves all joins.  The others go through a stable radix sort on
+//     (C, c(u), u) and a prefix-sum test: the longest fitting prefix is
+//     approved.
+//  3. Apply: rep, cluster weights and the cluster count.
+#include "prims.h"
+#include "kernels.h"
+
+namespace hgp {
+
+constexpr int NCLASS = 5;  // 0..2 wave groups, 3 block/LDS, 4 block/global
+static const uint32_t CLASS_MAXB[4] = {42, 170, 682, 2730};
+
+struct RateArgs {
+    const uint32_t *pin_off, *pins, *inc_off, *inc;
+    const int32_t *vwgt;
+    const uint64_t *nscore;
+    const uint32_t *rep;
+    const int64_t *cw;
+    uint32_t *ptarget;
+    int64_t *tsum;
+    uint32_t *proposers;
+    uint32_t *nprop;
+    uint64_t mseed;
+    uint32_t level, r, S;
+    int64_t cap_mult, W;
+};
+
+__device__ inline bool better(uint64_t R1, uint64_t H1, uint32_t C1, uint64_t R2, uint64_t H2, uint32_t C2) {
+    if (R1 != R2) return R1 > R2;
+    if (H1 != H2) return H1 < H2;
+    return C1 < C2;
+}
+
+__device__ inline uint32_t slot_hash(uint32_t C, int log2cap) {
+    return (uint32_t)(C * 2654435761u) >> (32 - log2cap);
+}
+
+// Validity of target cluster C for candidate u (snapshot of the sub-round):
+// within c_max, and not itself a candidate singleton of this sub-round.
+__device__ inline bool valid_target(const RateArgs &a, uint32_t u, uint32_t C) {
+    int64_t cwc = a.cw[C];
+    if (a.cap_mult * ((int64_t)a.vwgt[u] + cwc) > a.W) return false;
+    bool cand = (a.rep[C] == C) && (cwc == (int64_t)a.vwgt[C]) &&
+                (tag_hash(a.mseed, 1, a.level, 0, C) % a.S == a.r);
+    return !cand && C != u;
+}
+
+__device__ inline void publish(const RateArgs &a, uint32_t u, uint32_t C) {
+    a.ptarget[u] = C;
+    if (C != NONE) {
+        atomic_add_i64(&a.tsum[C], (int64_t)a.vwgt[u]);
+        uint32_t slot = atomicAdd(a.nprop, 1u);
+        a.proposers[slot] = u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Groups of G lanes (G <= 64), one candidate per group, LDS table of CAP.
+// ---------------------------------------------------------------------------
+template <int G, int CAP, int LOG2CAP>
+__global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t *list, uint32_t count) {
+    constexpr int GPB = BLOCK / G;
+    __shared__ uint32_t keys[GPB][CAP];
+    __shared__ uint32_t stamp[GPB][CAP];
+    __shared__ uint64_t R[GPB][CAP];
+    const int g = threadIdx.x / G, l = threadIdx.x % G;
+    // groups never synchronise with each other (each lives inside one wave),
+    // so every group simply strides over the list
+    for (uint32_t idx = blockIdx.x * GPB + g; idx < count; idx += gridDim.x * GPB) {
+        const uint32_t u = list[idx];
+        const bool active = a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u];  // not joined earlier
+        for (int s = l; s < CAP; s += G) { keys[g][s] = NONE; stamp[g][s] = NONE; R[g][s] = 0; }
+        wave_sync();
+        if (active) {
+            uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
+            for (uint32_t j = j0; j < j1; ++j) {
+                uint32_t e = a.inc[j];
+                uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+                if (sz < 2) continue;
+                uint64_t sc = a.nscore[e];
+                for (uint32_t q = l; q < sz; q += G) {
+                    uint32_t v = a.pins[b + q];
+                    if (v == u) continue;
+                    uint32_t C = a.rep[v];
+                    uint32_t slot = slot_hash(C, LOG2CAP);
+                    for (;;) {
+                        uint32_t k = keys[g][slot];
+                        if (k == C) break;
+                        if (k == NONE) {
+                            uint32_t old = atomicCAS(&keys[g][slot], NONE, C);
+                            if (old == NONE || old == C) break;
+                        }
+                        slot = (slot + 1) & (CAP - 1);
+                    }
+                    uint32_t prev = atomicExch(&stamp[g][slot], e);
+                    if (prev != e) atomicAdd((unsigned long long *)&R[g][slot], (unsigned long long)sc);
+                }
+                wave_sync();
+            }
+        }
+        wave_sync();
+        uint64_t bR = 0, bH = ~0ull;
+        uint32_t bC = NONE;
+        if (active) {
+            for (int s = l; s < CAP; s += G) {
+                uint32_t C = keys[g][s];
+                if (C == NONE) continue;
+                uint64_t rc = R[g][s];
+                if (!valid_target(a, u, C)) continue;
+                uint64_t hc = tag_hash(a.mseed, 2, a.level, 0, C);
+                if (bC == NONE || better(rc, hc, C, bR, bH, bC)) { bR = rc; bH = hc; bC = C; }
+            }
+        }
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) {
+            uint64_t oR = __shfl_xor(bR, o, 64);
+            uint64_t oH = __shfl_xor(bH, o, 64);
+            uint32_t oC = __shfl_xor(bC, o, 64);
+            if (oC != NONE && (bC == NONE || better(oR, oH, oC, bR, bH, bC))) { bR = oR; bH = oH; bC = oC; }
+        }
+        if (active && l == 0) publish(a, u, bC);
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One candidate per block; table in LDS (GLOBAL=false) or in a slice of
+// global memory owned by the block (GLOBAL=true).
+// ---------------------------------------------------------------------------
+template <bool GLOBAL>
+__global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t *list, uint32_t count,
+                                                      uint32_t *gkeys, uint32_t *gstamp, uint64_t *gR,
+                                                      size_t slice_cap, uint32_t n_cur) {
+    constexpr int LCAP = 4096, LLOG = 12;
+    __shared__ uint32_t lkeys[GLOBAL ? 1 : LCAP];
+    __shared__ uint32_t lstamp[GLOBAL ? 1 : LCAP];
+    __shared__ uint64_t lR[GLOBAL ? 1 : LCAP];
+    __shared__ uint64_t redR[BLOCK / WAVE], redH[BLOCK / WAVE];
+    __shared__ uint32_t redC[BLOCK / WAVE];
+    uint32_t *keys = GLOBAL ? gkeys + (size_t)blockIdx.x * slice_cap : lkeys;
+    uint32_t *stamp = GLOBAL ? gstamp + (size_t)blockIdx.x * slice_cap : lstamp;
+    uint64_t *R = GLOBAL ? gR + (size_t)blockIdx.x * slice_cap : lR;
+    for (uint32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        uint32_t u = list[idx];
+        if (!(a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u])) continue;  // uniform per block
+        uint32_t cap, lg;
+        if (GLOBAL) {
+            // capacity: power of two >= 1.5 * min(B(u), n)
+            uint64_t bsum = 0;
+            for (uint32_t j = a.inc_off[u]; j < a.inc_off[u + 1]; ++j) {
+                uint32_t e = a.inc[j];
+                uint32_t sz = a.pin_off[e + 1] - a.pin_off[e];
+                if (sz >= 2) bsum += sz - 1;
+            }
+            uint64_t want = bsum < n_cur ? bsum : n_cur;
+            want = want + want / 2 + 1;
+            lg = 13;
+            while (((uint64_t)1 << lg) < want) ++lg;
+            cap = 1u << lg;
+            if (cap > slice_cap) { cap = (uint32_t)slice_cap; lg = 31 - __clz(cap); }
+        } else {
+            cap = LCAP; lg = LLOG;
+        }
+        for (uint32_t s = threadIdx.x; s < cap; s += BLOCK) { keys[s] = NONE; stamp[s] = NONE; R[s] = 0; }
+        if (GLOBAL) __threadfence();  // the clear reaches L2 before any atomic on the table
+        __syncthreads();
+        uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
+        for (uint32_t j = j0; j < j1; ++j) {
+            uint32_t e = a.inc[j];
+            uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+            if (sz < 2) continue;
+            uint64_t sc = a.nscore[e];
+            for (uint32_t q = threadIdx.x; q < sz; q += BLOCK) {
+                uint32_t v = a.pins[b + q];
+                if (v == u) continue;
+                uint32_t C = a.rep[v];
+                uint32_t slot = slot_hash(C, lg);
+                for (;;) {
+                    uint32_t k = GLOBAL ? __hip_atomic_load(&keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                        : keys[slot];
+                    if (k == C) break;
+                    if (k == NONE) {
+                        uint32_t old = atomicCAS(&keys[slot], NONE, C);
+                        if (old == NONE || old == C) break;
+                    }
+                    slot = (slot + 1) & (cap - 1);
+                }
+                uint32_t prev = atomicExch(&stamp[slot], e);
+                if (prev != e) atomicAdd((unsigned long long *)&R[slot], (unsigned long long)sc);
+            }
+            __syncthreads();
+        }
+        uint64_t bR = 0, bH = ~0ull;
+        uint32_t bC = NONE;
+        if (GLOBAL) __threadfence();
+        for (uint32_t s = threadIdx.x; s < cap; s += BLOCK) {
+            // the global table was filled by device-scope atomics of other
+            // waves: read it at device scope (never a stale L1 line)
+            uint32_t C = GLOBAL ? __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : keys[s];
+            if (C == NONE) continue;
+            uint64_t rc = GLOBAL ? __hip_atomic_load(&R[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : R[s];
+            if (!valid_target(a, u, C)) continue;
+            uint64_t hc = tag_hash(a.mseed, 2, a.level, 0, C);
+            if (bC == NONE || better(rc, hc, C, bR, bH, bC)) { bR = rc; bH = hc; bC = C; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            uint64_t oR = __shfl_xor(bR, o, 64);
+            uint64_t oH = __shfl_xor(bH, o, 64);
+            uint32_t oC = __shfl_xor(bC, o, 64);
+            if (oC != NONE && (bC == NONE || better(oR, oH, oC, bR, bH, bC))) { bR = oR; bH = oH; bC = oC; }
+        }
+        unsigned w = threadIdx.x / WAVE;
+        if (__lane_id() == 0) { redR[w] = bR; redH[w] = bH; redC[w] = bC; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int q = 1; q < BLOCK / WAVE; ++q)
+                if (redC[q] != NONE && (bC == NONE || better(redR[q], redH[q], redC[q], bR, bH, bC))) {
+                    bR = redR[q]; bH = redH[q]; bC = redC[q];
+                }
+            publish(a, u, bC);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-level preparation
+// ---------------------------------------------------------------------------
+__global__ void k_net_score(const uint32_t *pin_off, const int32_t *nwgt, uint32_t m, uint64_t *nscore) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+        uint32_t sz = pin_off[e + 1] - pin_off[e];
+        nscore[e] = sz >= 2 ? ((uint64_t)(uint32_t)nwgt[e] << 32) / (uint64_t)(sz - 1) : 0;
+    }
+}
+
+__device__ inline int rate_class(uint64_t B) {
+    if (B == 0) return -1;
+    if (B <= 42) return 0;
+    if (B <= 170) return 1;
+    if (B <= 682) return 2;
+    if (B <= 2730) return 3;
+    return 4;
+}
+
+// pass 1 (fill=false): count per (sub-round, class); pass 2: fill lists.
+__global__ void k_classify(const uint32_t *pin_off, const uint32_t *inc_off, const uint32_t *inc, uint32_t n,
+                           uint64_t mseed, uint32_t level, uint32_t S, const int32_t *vwgt,
+                           uint32_t *rep, int64_t *cw, int64_t *tsum, uint32_t *counts, uint32_t *cursor,
+                           uint32_t *lists, bool fill) {
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        uint64_t B = 0;
+        for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) {
+            uint32_t e = inc[j];
+            uint32_t sz = pin_off[e + 1] - pin_off[e];
+            if (sz >= 2) B += sz - 1;
+        }
+        int c = rate_class(B);
+        uint32_t r = (uint32_t)(tag_hash(mseed, 1, level, 0, u) % S);
+        if (!fill) {
+            rep[u] = u;
+            cw[u] = vwgt[u];
+            tsum[u] = 0;
+            if (c >= 0) atomicAdd(&counts[r * NCLASS + c], 1u);
+        } else if (c >= 0) {
+            uint32_t pos = atomicAdd(&cursor[r * NCLASS + c], 1u);
+            lists[pos] = u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Approval and apply
+// ---------------------------------------------------------------------------
+__global__ void k_approve_fast(const uint32_t *proposers, uint32_t np, const uint32_t *ptarget,
+                               const int64_t *cw, const int64_t *tsum, int64_t cap_mult, int64_t W,
+                               uint8_t *ok, uint32_t *slow, uint32_t *nslow) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ((np + 63) / 64) * 64;
+         i += gridDim.x * blockDim.x) {
+        bool act = i < np;
+        uint32_t u = act ? proposers[i] : 0;
+        bool fits = true;
+        if (act) {
+            uint32_t C = ptarget[u];
+            fits = cap_mult * (cw[C] + tsum[C]) <= W;
+            ok[u] = fits ? 1 : 0;
+        }
+        uint32_t pos = warp_agg_append(nslow, act && !fits);
+        if (act && !fits) slow[pos] = u;
+    }
+}
+
+// key = (C << (wb + ub)) | (c(u) << ub) | u  when it fits in 64 bits
+__global__ void k_slow_keys(const uint32_t *slow, uint32_t ns, const uint32_t *ptarget, const int32_t *vwgt,
+                            int wb, int ub, uint64_t *keys, uint32_t *vals, bool with_u) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+        uint32_t u = slow[i];
+        uint64_t key = ((uint64_t)ptarget[u] << (wb + (with_u ? ub : 0))) |
+                       ((uint64_t)(uint32_t)vwgt[u] << (with_u ? ub : 0)) | (with_u ? (uint64_t)u : 0);
+        keys[i] = key;
+        vals[i] = u;
+    }
+}
+
+__global__ void k_u_keys(const uint32_t *slow, uint32_t ns, uint64_t *keys, uint32_t *vals) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+        keys[i] = slow[i];
+        vals[i] = slow[i];
+    }
+}
+
+// Sorted slow joins: segment start of each target writes the base prefix.
+struct WeightOfSorted {
+    const uint32_t *vals;
+    const int32_t *vwgt;
+    __device__ uint64_t operator()(size_t i) const { return (uint64_t)(uint32_t)vwgt[vals[i]]; }
+};
+struct StoreInclU64 {
+    uint64_t *out;
+    __device__ void operator()(size_t i, uint64_t excl, uint64_t v) const { out[i] = excl + v; }
+};
+
+__global__ void k_slow_decide(const uint32_t *vals, uint32_t ns, const uint32_t *ptarget, const uint64_t *incl,
+                              const int32_t *vwgt, const int64_t *cw, int64_t cap_mult, int64_t W, uint8_t *ok) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+        uint32_t u = vals[i];
+        uint32_t C = ptarget[u];
+        // find the segment start by walking back over equal targets is O(len);
+        // instead binary search: segments are contiguous, sorted by C.
+        uint32_t lo = 0, hi = i;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (ptarget[vals[mid]] < C) lo = mid + 1; else hi = mid;
+        }
+        uint64_t base = lo == 0 ? 0 : incl[lo - 1];
+        int64_t prefix = (int64_t)(incl[i] - base);
+        ok[u] = (cap_mult * (cw[C] + prefix) <= W) ? 1 : 0;
+    }
+}
+
+__global__ void k_apply_joins(const uint32_t *proposers, uint32_t np, const uint32_t *ptarget, const uint8_t *ok,
+                              const int32_t *vwgt, uint32_t *rep, int64_t *cw, int64_t *tsum, uint32_t *n_clusters) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ((np + 63) / 64) * 64;
+         i += gridDim.x * blockDim.x) {
+        bool act = i < np;
+        bool join = false;
+        if (act) {
+            uint32_t u = proposers[i];
+            uint32_t C = ptarget[u];
+            tsum[C] = 0;
+            if (ok[u]) {
+                join = true;
+                rep[u] = C;
+                atomic_add_i64(&cw[C], (int64_t)vwgt[u]);
+            }
+        }
+        uint64_t m = __ballot(join);
+        if (__lane_id() == 0 && m) atomicSub(n_clusters, (uint32_t)__popcll(m));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host driver of one pass
+// ---------------------------------------------------------------------------
+struct CoarsenBufs {
+    uint64_t *nscore;
+    int64_t *cw, *tsum;
+    uint32_t *ptarget, *proposers, *slow, *lists, *counts, *cursor, *scal;
+    uint8_t *ok;
+    uint64_t *keys, *keys_alt, *incl;
+    uint32_t *vals, *vals_alt;
+    uint32_t *gkeys, *gstamp;
+    uint64_t *gR;
+    size_t slice_cap;
+    uint32_t nslices;
+};
+
+static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t S, CoarsenBufs &B) {
+    B.nscore = A.alloc<uint64_t>(m);
+    B.cw = A.alloc<int64_t>(n);
+    B.tsum = A.alloc<int64_t>(n);
+    B.ptarget = A.alloc<uint32_t>(n);
+    B.proposers = A.alloc<uint32_t>(n);
+    B.slow = A.alloc<uint32_t>(n);
+    B.lists = A.alloc<uint32_t>(n);
+    B.counts = A.alloc<uint32_t>((size_t)S * NCLASS);
+    B.cursor = A.alloc<uint32_t>((size_t)S * NCLASS);
+    B.scal = A.alloc<uint32_t>(8);
+    B.ok = A.alloc<uint8_t>(n);
+    B.keys = A.alloc<uint64_t>(n);
+    B.keys_alt = A.alloc<uint64_t>(n);
+    B.incl = A.alloc<uint64_t>(n);
+    B.vals = A.alloc<uint32_t>(n);
+    B.vals_alt = A.alloc<uint32_t>(n);
+    // global-memory rating tables: enough for any candidate (capacity >= 1.5 n)
+    size_t sc = 8192;
+    while (sc < (size_t)n + n / 2 + 1) sc <<= 1;
+    B.slice_cap = sc;
+    B.nslices = 16;
+    B.gkeys = A.alloc<uint32_t>(sc * B.nslices);
+    B.gstamp = A.alloc<uint32_t>(sc * B.nslices);
+    B.gR = A.alloc<uint64_t>(sc * B.nslices);
+    // radix sort temporaries
+    sort_reserve(A, n);
+    scan_reserve<uint64_t>(A, n);
+}
+
+size_t coarsen_workspace(uint32_t n, uint32_t m, uint32_t p, const hgp_params &prm) {
+    (void)p;
+    Arena A(nullptr, 0);
+    CoarsenBufs B;
+    plan(A, n, m, prm.coarsen_subrounds, B);
+    return A.peak;
+}
+
+void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *rep, uint32_t *n_clusters_dev,
+                  uint32_t *n_clusters_host, Arena &A, hipStream_t st) {
+    const uint32_t n = h.n, m = h.m, S = prm.coarsen_subrounds;
+    size_t mk = A.mark();
+    CoarsenBufs B;
+    plan(A, n, m, S, B);
+    int64_t W = 0;
+    {
+        // c(V) is needed on the host for the cap test constants
+        W = total_weight(h.vwgt, n, A, st);
+    }
+    const int64_t cap_mult = (int64_t)prm.limit_factor * (int64_t)prm.k;
+    const uint64_t mseed = mix64(prm.seed);
+
+    k_net_score<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.nwgt, m, B.nscore);
+    HGP_LAUNCH_CHECK();
+    HGP_CHECK_HIP(hipMemsetAsync(B.counts, 0, sizeof(uint32_t) * S * NCLASS, st));
+    k_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, mseed, level, S,
+                                                                 h.vwgt, rep, B.cw, B.tsum, B.counts, B.cursor,
+                                                                 B.lists, false);
+    HGP_LAUNCH_CHECK();
+    std::vector<uint32_t> counts(S * NCLASS), offs(S * NCLASS + 1);
+    HGP_CHECK_HIP(hipMemcpyAsync(counts.data(), B.counts, sizeof(uint32_t) * S * NCLASS, hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    offs[0] = 0;
+    for (uint32_t i = 0; i < S * NCLASS; ++i) offs[i + 1] = offs[i] + counts[i];
+    HGP_CHECK_HIP(hipMemcpyAsync(B.cursor, offs.data(), sizeof(uint32_t) * S * NCLASS, hipMemcpyHostToDevice, st));
+    k_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, mseed, level, S,
+                                                                 h.vwgt, rep, B.cw, B.tsum, B.counts, B.cursor,
+                                                                 B.lists, true);
+    HGP_LAUNCH_CHECK();
+
+    uint32_t cnt = n;
+    uint32_t *nprop = B.scal + 0, *nslow = B.scal + 1, *ncl = B.scal + 2;
+    HGP_CHECK_HIP(hipMemcpyAsync(ncl, &cnt, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    for (uint32_t r = 0; r < S; ++r) {
+        HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 2, st));
+        RateArgs a{h.pin_off, h.pins, h.inc_off, h.inc, h.vwgt, B.nscore, rep, B.cw, B.ptarget, B.tsum,
+                   B.proposers, nprop, mseed, level, r, S, cap_mult, W};
+        for (int c = 0; c < NCLASS; ++c) {
+            uint32_t cntc = counts[r * NCLASS + c];
+            if (!cntc) continue;
+            const uint32_t *lst = B.lists + offs[r * NCLASS + c];
+            switch (c) {
+                case 0:
+                    k_rate_group<8, 64, 6><<<grid_for(cntc, BLOCK / 8, 8192), BLOCK, 0, st>>>(a, lst, cntc);
+                    break;
+                case 1:
+                    k_rate_group<16, 256, 8><<<grid_for(cntc, BLOCK / 16, 8192), BLOCK, 0, st>>>(a, lst, cntc);
+                    break;
+                case 2:
+                    k_rate_group<64, 1024, 10><<<grid_for(cntc, BLOCK / 64, 8192), BLOCK, 0, st>>>(a, lst, cntc);
+                    break;
+                case 3:
+                    k_rate_block<false><<<grid_for(cntc, 1, 8192), BLOCK, 0, st>>>(a, lst, cntc, nullptr, nullptr,
+                                                                                  nullptr, 0, n);
+                    break;
+                default:
+                    k_rate_block<true><<<grid_for(cntc, 1, B.nslices), BLOCK, 0, st>>>(
+                        a, lst, cntc, B.gkeys, B.gstamp, B.gR, B.slice_cap, n);
+                    break;
+            }
+            HGP_LAUNCH_CHECK();
+        }
+        uint32_t np = 0;
+        HGP_CHECK_HIP(hipMemcpyAsync(&np, nprop, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HGP_CHECK_HIP(hipStreamSynchronize(st));
+        if (np) {
+            k_approve_fast<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.proposers, np, B.ptarget, B.cw,
+                                                                              B.tsum, cap_mult, W, B.ok, B.slow, nslow);
+            HGP_LAUNCH_CHECK();
+            uint32_t ns = 0;
+            HGP_CHECK_HIP(hipMemcpyAsync(&ns, nslow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            HGP_CHECK_HIP(hipStreamSynchronize(st));
+            if (ns) {
+                int ub = bits_for(n ? n - 1 : 0);
+                int cb = bits_for(n ? n - 1 : 0);
+                int wb = bits_for((uint64_t)max_vertex_weight(h.vwgt, n, A, st));
+                uint64_t *kk = B.keys;
+                uint32_t *vv = B.vals;
+                if (cb + wb + ub <= 64) {
+                    k_slow_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.slow, ns, B.ptarget, h.vwgt, wb,
+                                                                                   ub, kk, vv, true);
+                    HGP_LAUNCH_CHECK();
+                    radix_sort_pairs<uint64_t>(A, &kk, &vv, kk == B.keys ? B.keys_alt : B.keys,
+                                               vv == B.vals ? B.vals_alt : B.vals, ns, 0, cb + wb + ub, st);
+                } else {
+                    // stable two-stage: by u, then by (C, c(u))
+                    k_u_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.slow, ns, kk, vv);
+                    HGP_LAUNCH_CHECK();
+                    radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, ub, st);
+                    uint64_t *k2 = (kk == B.keys) ? B.keys_alt : B.keys;
+                    uint32_t *v2 = (vv == B.vals) ? B.vals_alt : B.vals;
+                    k_slow_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(vv, ns, B.ptarget, h.vwgt, wb, 0,
+                                                                                   kk, v2, false);
+                    HGP_LAUNCH_CHECK();
+                    // kk holds keys aligned with v2 (= copy of vv)
+                    uint32_t *vcur = v2;
+                    radix_sort_pairs<uint64_t>(A, &kk, &vcur, k2, vv, ns, 0, cb + wb, st);
+                    vv = vcur;
+                }
+                scan_apply<uint64_t>(A, ns, WeightOfSorted{vv, h.vwgt}, StoreInclU64{B.incl}, (uint64_t *)nullptr,
+                                     st);
+                k_slow_decide<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(vv, ns, B.ptarget, B.incl, h.vwgt,
+                                                                                 B.cw, cap_mult, W, B.ok);
+                HGP_LAUNCH_CHECK();
+            }
+            k_apply_joins<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.proposers, np, B.ptarget, B.ok,
+                                                                             h.vwgt, rep, B.cw, B.tsum, ncl);
+            HGP_LAUNCH_CHECK();
+        }
+        HGP_CHECK_HIP(hipMemcpyAsync(&cnt, ncl, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HGP_CHECK_HIP(hipStreamSynchronize(st));
+        if ((uint64_t)5 * cnt < (uint64_t)2 * n) break;
+    }
+    if (n_clusters_dev) HGP_CHECK_HIP(hipMemcpyAsync(n_clusters_dev, ncl, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    if (n_clusters_host) *n_clusters_host = cnt;
+    A.release(mk);
+}
+
+}  // namespace hgp

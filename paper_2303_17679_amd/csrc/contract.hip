@@ -1,0 +1,344 @@
+// Contraction of a clustering (paper Sec. 4.2).
+//
+// Steps, each a data-parallel kernel over vertices, pins or nets:
+//  1. coarse IDs: exclusive scan of the representative flags (ascending
+//     representative ID), cid[v] = rank[rep[v]]; cluster weights by integer
+//     atomics;
+//  2. every pin replaced by its coarse ID, then each net sorted ascending and
+//     de-duplicated (segmented sort, three tiers by net size);
+//  3. nets of fewer than two pins are dropped; identical nets are found by
+//     sorting the remaining nets by a 32-bit hash of their pin list (stable,
+//     so equal hashes stay in ascending net ID) and comparing pin lists
+//     exactly inside runs of equal hash: the kept net is the first identical
+//     one in its run, i.e. the smallest net ID, and receives the summed
+//     weight.  The hash only groups; it never decides identity (the paper's
+//     fingerprint sum of squares plays the same filtering role);
+//  4. kept nets numbered by one packed (count, pins) exclusive scan in
+//     ascending fine ID; pins copied;
+//  5. incidence arrays: degree count, scan, scatter, per-vertex sort.
+#include "segsort.h"
+#include "kernels.h"
+
+namespace hgp {
+
+struct IsRep {
+    const uint32_t *rep;
+    __device__ uint32_t operator()(size_t i) const { return rep[i] == (uint32_t)i ? 1u : 0u; }
+};
+struct StoreRank {
+    uint32_t *rank;
+    __device__ void operator()(size_t i, uint32_t excl, uint32_t) const { rank[i] = excl; }
+};
+
+__global__ void k_cid(const uint32_t *rep, const uint32_t *rank, uint32_t n, const int32_t *vwgt, uint32_t *cid,
+                      int32_t *cvwgt) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        uint32_t c = rank[rep[v]];
+        cid[v] = c;
+        atomicAdd(&cvwgt[c], vwgt[v]);
+    }
+}
+
+__global__ void k_map_pins(const uint32_t *pins, size_t p, const uint32_t *cid, uint32_t *out) {
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < p; q += (size_t)gridDim.x * blockDim.x)
+        out[q] = cid[pins[q]];
+}
+
+// Hash of a sorted distinct pin list (only groups candidates for identity).
+__device__ inline uint64_t pin_hash_term(uint32_t x) { return mix64((uint64_t)x + 0x9E3779B97F4A7C15ULL); }
+
+__global__ void k_net_hash_small(const uint32_t *off, uint32_t m, const uint32_t *tmp, const uint32_t *usize,
+                                 uint32_t *hkey, uint8_t *valid) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+        uint32_t b = off[e], len = off[e + 1] - b;
+        if (len > SEG_SMALL) continue;  // done by the block kernel
+        uint32_t sz = usize[e];
+        uint64_t h = 0;
+        for (uint32_t i = 0; i < sz; ++i) h += pin_hash_term(tmp[b + i]);
+        h = mix64(h ^ ((uint64_t)sz << 40));
+        hkey[e] = (uint32_t)(h >> 32);
+        valid[e] = sz >= 2;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_net_hash_block(const uint32_t *off, const uint32_t *list, uint32_t count,
+                                                          const uint32_t *tmp, const uint32_t *usize, uint32_t *hkey,
+                                                          uint8_t *valid) {
+    __shared__ uint64_t red[BLOCK / WAVE];
+    for (uint32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        uint32_t e = list[idx];
+        uint32_t b = off[e], sz = usize[e];
+        uint64_t h = 0;
+        for (uint32_t i = threadIdx.x; i < sz; i += BLOCK) h += pin_hash_term(tmp[b + i]);
+        h = wave_sum(h);
+        if (__lane_id() == 0) red[threadIdx.x / WAVE] = h;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t t = 0;
+            for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+            t = mix64(t ^ ((uint64_t)sz << 40));
+            hkey[e] = (uint32_t)(t >> 32);
+            valid[e] = sz >= 2;
+        }
+        __syncthreads();
+    }
+}
+
+struct IsValid {
+    const uint8_t *valid;
+    __device__ uint32_t operator()(size_t i) const { return valid[i]; }
+};
+struct GatherValid {
+    const uint8_t *valid;
+    const uint32_t *hkey;
+    uint64_t *keys;
+    uint32_t *vals;
+    __device__ void operator()(size_t i, uint32_t excl, uint32_t v) const {
+        if (v) {
+            keys[excl] = hkey[i];
+            vals[excl] = (uint32_t)i;
+        }
+    }
+};
+
+// Representative of every valid net: the first net of its hash run with an
+// identical pin list.
+__global__ void k_identical(const uint64_t *keys, const uint32_t *vals, uint32_t nv, const uint32_t *off,
+                            const uint32_t *tmp, const uint32_t *usize, const int32_t *nwgt, uint32_t *repnet,
+                            int32_t *wsum) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
+        uint64_t key = keys[i];
+        uint32_t lo = 0, hi = i;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (keys[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        uint32_t e = vals[i];
+        uint32_t sz = usize[e];
+        const uint32_t *pe = tmp + off[e];
+        uint32_t r = e;
+        for (uint32_t j = lo; j < i; ++j) {
+            uint32_t f = vals[j];
+            if (usize[f] != sz) continue;
+            const uint32_t *pf = tmp + off[f];
+            bool same = true;
+            for (uint32_t q = 0; q < sz && same; ++q) same = pe[q] == pf[q];
+            if (same) { r = f; break; }
+        }
+        repnet[e] = r;
+        atomicAdd(&wsum[r], nwgt[e]);
+    }
+}
+
+// Packed (count << 32 | pins) of kept nets.
+struct KeptPack {
+    const uint8_t *valid;
+    const uint32_t *repnet, *usize;
+    __device__ uint64_t operator()(size_t e) const {
+        return (valid[e] && repnet[e] == (uint32_t)e) ? ((1ull << 32) | usize[e]) : 0ull;
+    }
+};
+struct StoreKept {
+    uint32_t *newid, *newoff, *cpin_off;
+    int32_t *cnwgt;
+    const int32_t *wsum;
+    __device__ void operator()(size_t e, uint64_t excl, uint64_t v) const {
+        if (v) {
+            uint32_t id = (uint32_t)(excl >> 32);
+            newid[e] = id;
+            newoff[e] = (uint32_t)excl;
+            cpin_off[id] = (uint32_t)excl;
+            cnwgt[id] = wsum[e];
+        } else {
+            newid[e] = NONE;
+        }
+    }
+};
+
+__global__ void k_copy_pins_small(const uint32_t *off, uint32_t m, const uint32_t *tmp, const uint32_t *usize,
+                                  const uint32_t *newid, const uint32_t *newoff, uint32_t *cpins, uint32_t *deg) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+        if (newid[e] == NONE) continue;
+        uint32_t b = off[e], len = off[e + 1] - b;
+        if (len > SEG_SMALL) continue;
+        uint32_t sz = usize[e], o = newoff[e];
+        for (uint32_t i = 0; i < sz; ++i) {
+            uint32_t v = tmp[b + i];
+            cpins[o + i] = v;
+            atomicAdd(&deg[v], 1u);
+        }
+    }
+}
+
+__global__ void k_copy_pins_block(const uint32_t *off, const uint32_t *list, uint32_t count, const uint32_t *tmp,
+                                  const uint32_t *usize, const uint32_t *newid, const uint32_t *newoff,
+                                  uint32_t *cpins, uint32_t *deg) {
+    for (uint32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        uint32_t e = list[idx];
+        if (newid[e] == NONE) continue;
+        uint32_t b = off[e], sz = usize[e], o = newoff[e];
+        for (uint32_t i = threadIdx.x; i < sz; i += blockDim.x) {
+            uint32_t v = tmp[b + i];
+            cpins[o + i] = v;
+            atomicAdd(&deg[v], 1u);
+        }
+    }
+}
+
+// Scatter of the transpose: thread per coarse net.
+__global__ void k_scatter_inc(const uint32_t *cpin_off, uint32_t mc, const uint32_t *cpins, uint32_t *cursor,
+                              uint32_t *cinc) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < mc; e += gridDim.x * blockDim.x) {
+        for (uint32_t j = cpin_off[e]; j < cpin_off[e + 1]; ++j) {
+            uint32_t v = cpins[j];
+            uint32_t pos = atomicAdd(&cursor[v], 1u);
+            cinc[pos] = e;
+        }
+    }
+}
+
+struct ContractBufs {
+    uint32_t *rank, *tmp, *usize, *hkey, *repnet, *newid, *newoff, *cursor, *scal;
+    int32_t *wsum;
+    uint8_t *valid;
+    uint64_t *keys, *keys_alt;
+    uint32_t *vals, *vals_alt;
+    SegSortBufs ss_net, ss_inc;
+};
+
+static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, ContractBufs &B) {
+    B.rank = A.alloc<uint32_t>(n);
+    B.tmp = A.alloc<uint32_t>(p);
+    B.usize = A.alloc<uint32_t>(m);
+    B.hkey = A.alloc<uint32_t>(m);
+    B.repnet = A.alloc<uint32_t>(m);
+    B.newid = A.alloc<uint32_t>(m);
+    B.newoff = A.alloc<uint32_t>(m);
+    B.cursor = A.alloc<uint32_t>((size_t)n + 1);
+    B.scal = A.alloc<uint32_t>(8);
+    B.wsum = A.alloc<int32_t>(m);
+    B.valid = A.alloc<uint8_t>(m);
+    B.keys = A.alloc<uint64_t>(m);
+    B.keys_alt = A.alloc<uint64_t>(m);
+    B.vals = A.alloc<uint32_t>(m);
+    B.vals_alt = A.alloc<uint32_t>(m);
+    segsort_plan(A, m, p, B.ss_net);
+    segsort_plan(A, n, p, B.ss_inc);
+    scan_reserve<uint32_t>(A, (size_t)n + 1);
+    scan_reserve<uint64_t>(A, m);
+    sort_reserve(A, m);
+}
+
+size_t contract_workspace(uint32_t n, uint32_t m, uint32_t p) {
+    Arena A(nullptr, 0);
+    ContractBufs B;
+    plan(A, n, m, p, B);
+    return A.peak;
+}
+
+void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_out &out, uint32_t *dims_host,
+              Arena &A, hipStream_t st) {
+    const uint32_t n = h.n, m = h.m, p = h.p;
+    size_t mk = A.mark();
+    ContractBufs B;
+    plan(A, n, m, p, B);
+    uint32_t *d_nc = B.scal + 0;
+    uint64_t *d_tot = (uint64_t *)(B.scal + 2);
+    uint32_t *d_nv = B.scal + 4;
+
+    // 1. coarse vertex IDs and weights
+    scan_apply<uint32_t>(A, n, IsRep{rep}, StoreRank{B.rank}, d_nc, st);
+    uint32_t nc = 0;
+    HGP_CHECK_HIP(hipMemcpyAsync(&nc, d_nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    HGP_REQUIRE(nc <= out.cap_n, HGP_E_INVALID);
+    HGP_CHECK_HIP(hipMemsetAsync(out.vwgt, 0, sizeof(int32_t) * (nc ? nc : 1), st));
+    k_cid<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(rep, B.rank, n, h.vwgt, cid, out.vwgt);
+    HGP_LAUNCH_CHECK();
+
+    // 2. remap pins, sort + de-duplicate every net
+    if (p) {
+        k_map_pins<<<grid_for(p, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pins, p, cid, B.tmp);
+        HGP_LAUNCH_CHECK();
+    }
+    segmented_sort(A, B.ss_net, h.pin_off, m, B.tmp, true, B.usize, st);
+    uint32_t cnt_ml[2];
+    HGP_CHECK_HIP(hipMemcpyAsync(cnt_ml, B.ss_net.scal, sizeof(cnt_ml), hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+
+    // 3. hashes, drop single-pin nets, identical-net detection
+    if (m) {
+        k_net_hash_small<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, m, B.tmp, B.usize, B.hkey,
+                                                                           B.valid);
+        HGP_LAUNCH_CHECK();
+    }
+    if (cnt_ml[0]) {
+        k_net_hash_block<<<grid_for(cnt_ml[0], 1, 4096), BLOCK, 0, st>>>(h.pin_off, B.ss_net.med, cnt_ml[0], B.tmp,
+                                                                         B.usize, B.hkey, B.valid);
+        HGP_LAUNCH_CHECK();
+    }
+    if (cnt_ml[1]) {
+        k_net_hash_block<<<grid_for(cnt_ml[1], 1, 4096), BLOCK, 0, st>>>(h.pin_off, B.ss_net.large, cnt_ml[1], B.tmp,
+                                                                         B.usize, B.hkey, B.valid);
+        HGP_LAUNCH_CHECK();
+    }
+    scan_apply<uint32_t>(A, m, IsValid{B.valid}, GatherValid{B.valid, B.hkey, B.keys, B.vals}, d_nv, st);
+    uint32_t nv = 0;
+    HGP_CHECK_HIP(hipMemcpyAsync(&nv, d_nv, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    uint64_t *kk = B.keys;
+    uint32_t *vv = B.vals;
+    radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, nv, 0, 32, st);
+    if (m) HGP_CHECK_HIP(hipMemsetAsync(B.wsum, 0, sizeof(int32_t) * m, st));
+    if (nv) {
+        k_identical<<<grid_for(nv, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, nv, h.pin_off, B.tmp, B.usize, h.nwgt,
+                                                                       B.repnet, B.wsum);
+        HGP_LAUNCH_CHECK();
+    }
+
+    // 4. number the kept nets, copy pins, count coarse degrees
+    scan_apply<uint64_t>(A, m, KeptPack{B.valid, B.repnet, B.usize},
+                         StoreKept{B.newid, B.newoff, out.pin_off, out.nwgt, B.wsum}, d_tot, st);
+    uint64_t tot = 0;
+    HGP_CHECK_HIP(hipMemcpyAsync(&tot, d_tot, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    uint32_t mc = (uint32_t)(tot >> 32), pc = (uint32_t)tot;
+    HGP_REQUIRE(mc <= out.cap_m && pc <= out.cap_p, HGP_E_INVALID);
+    HGP_CHECK_HIP(hipMemcpyAsync(out.pin_off + mc, &pc, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.cursor, 0, sizeof(uint32_t) * ((size_t)nc + 1), st));
+    if (m) {
+        k_copy_pins_small<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, m, B.tmp, B.usize, B.newid,
+                                                                            B.newoff, out.pins, B.cursor);
+        HGP_LAUNCH_CHECK();
+    }
+    if (cnt_ml[0]) {
+        k_copy_pins_block<<<grid_for(cnt_ml[0], 1, 4096), BLOCK, 0, st>>>(h.pin_off, B.ss_net.med, cnt_ml[0], B.tmp,
+                                                                          B.usize, B.newid, B.newoff, out.pins,
+                                                                          B.cursor);
+        HGP_LAUNCH_CHECK();
+    }
+    if (cnt_ml[1]) {
+        k_copy_pins_block<<<grid_for(cnt_ml[1], 1, 4096), BLOCK, 0, st>>>(h.pin_off, B.ss_net.large, cnt_ml[1], B.tmp,
+                                                                          B.usize, B.newid, B.newoff, out.pins,
+                                                                          B.cursor);
+        HGP_LAUNCH_CHECK();
+    }
+
+    // 5. incidence: offsets by scan of the degrees, scatter, sort each list
+    exclusive_scan<uint32_t>(A, B.cursor, out.inc_off, (size_t)nc + 1, (uint32_t *)nullptr, st);
+    HGP_CHECK_HIP(hipMemcpyAsync(B.cursor, out.inc_off, sizeof(uint32_t) * ((size_t)nc + 1), hipMemcpyDeviceToDevice,
+                                 st));
+    if (mc) {
+        k_scatter_inc<<<grid_for(mc, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(out.pin_off, mc, out.pins, B.cursor,
+                                                                         out.inc);
+        HGP_LAUNCH_CHECK();
+    }
+    segmented_sort(A, B.ss_inc, out.inc_off, nc, out.inc, false, nullptr, st);
+    uint32_t dims[3] = {nc, mc, pc};
+    if (out.dims) HGP_CHECK_HIP(hipMemcpyAsync(out.dims, dims, sizeof(dims), hipMemcpyHostToDevice, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    if (dims_host) { dims_host[0] = nc; dims_host[1] = mc; dims_host[2] = pc; }
+    A.release(mk);
+}
+
+}  // namespace hgp

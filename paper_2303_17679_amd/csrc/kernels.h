@@ -1,0 +1,36 @@
+// Host-side entry points of the translation units (internal).
+#pragma once
+#include "common.h"
+#include <vector>
+
+namespace hgp {
+
+// util.hip
+int64_t total_weight(const int32_t *w, uint32_t n, Arena &A, hipStream_t st);
+int32_t max_vertex_weight(const int32_t *w, uint32_t n, Arena &A, hipStream_t st);
+size_t util_workspace(uint32_t n, uint32_t m);
+hgp_status validate(const hgp_hg &h, Arena &A, hipStream_t st);
+
+// coarsen.hip
+size_t coarsen_workspace(uint32_t n, uint32_t m, uint32_t p, const hgp_params &prm);
+void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *rep, uint32_t *n_clusters_dev,
+                  uint32_t *n_clusters_host, Arena &A, hipStream_t st);
+
+// contract.hip
+size_t contract_workspace(uint32_t n, uint32_t m, uint32_t p);
+void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_out &out, uint32_t *dims_host,
+              Arena &A, hipStream_t st);
+
+// refine.hip
+size_t refine_workspace(uint32_t n, uint32_t m, uint32_t k);
+void objective(const hgp_hg &h, uint32_t k, const uint32_t *part, int64_t *obj, int64_t *bw, Arena &A,
+               hipStream_t st);
+void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj, int64_t *bw,
+               Arena &A, hipStream_t st);
+
+// ip.hip
+size_t ip_workspace(uint32_t n, uint32_t k);
+void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st);
+void project(uint32_t n, const uint32_t *cid, const uint32_t *cpart, uint32_t *part, hipStream_t st);
+
+}  // namespace hgp

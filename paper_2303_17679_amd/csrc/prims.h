@@ -1,0 +1,267 @@
+// Device-wide building blocks written for gfx950 (wave64): exclusive scan
+// with a fused epilogue, ordered compaction and a stable LSD radix sort of
+// (key, value) pairs.  Header-only templates so each translation unit fuses
+// its own input / output functors into the kernels.
+#pragma once
+#include "common.h"
+
+namespace hgp {
+
+// ---------------------------------------------------------------------------
+// Exclusive scan: tile = BLOCK threads x SCAN_ITEMS consecutive values each.
+// ---------------------------------------------------------------------------
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
+
+template <class T, class In>
+__global__ __launch_bounds__(BLOCK) void k_tile_reduce(size_t n, In in, T *tile_sum) {
+    __shared__ T lds[BLOCK / WAVE];
+    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+        if (base + i < n) s += in(base + i);
+    s = wave_sum(s);
+    if (__lane_id() == 0) lds[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T t = 0;
+        for (int i = 0; i < BLOCK / WAVE; ++i) t += lds[i];
+        tile_sum[blockIdx.x] = t;
+    }
+}
+
+// Single block: exclusive scan of tile sums in place; *total <- sum.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles(size_t ntiles, T *tile_sum, T *total) {
+    __shared__ T lds[BLOCK / WAVE];
+    T carry = 0;
+    for (size_t base = 0; base < ntiles; base += (size_t)BLOCK * SCAN_ITEMS) {
+        T v[SCAN_ITEMS];
+        T s = 0;
+        size_t my = base + (size_t)threadIdx.x * SCAN_ITEMS;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            v[i] = (my + i < ntiles) ? tile_sum[my + i] : T(0);
+            s += v[i];
+        }
+        T tot;
+        T incl = block_incl_scan<T>(s, lds, &tot);
+        T run = carry + incl - s;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            if (my + i < ntiles) tile_sum[my + i] = run;
+            run += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <class T, class In, class Out>
+__global__ __launch_bounds__(BLOCK) void k_tile_scan(size_t n, In in, Out out, const T *tile_off) {
+    __shared__ T lds[BLOCK / WAVE];
+    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    T v[SCAN_ITEMS];
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = (base + i < n) ? in(base + i) : T(0);
+        s += v[i];
+    }
+    T incl = block_incl_scan<T>(s, lds, nullptr);
+    T run = tile_off[blockIdx.x] + incl - s;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < n) out(base + i, run, v[i]);
+        run += v[i];
+    }
+}
+
+// out(i, exclusive_prefix, value) is called for every i < n; *total_dev gets
+// the sum (may be nullptr).  Temporaries come from the arena and are released.
+template <class T, class In, class Out>
+void scan_apply(Arena &A, size_t n, In in, Out out, T *total_dev, hipStream_t st) {
+    size_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    size_t mk = A.mark();
+    T *tiles = A.alloc<T>(ntiles ? ntiles : 1);
+    if (A.measure) { A.release(mk); return; }
+    if (n == 0) {
+        if (total_dev) HGP_CHECK_HIP(hipMemsetAsync(total_dev, 0, sizeof(T), st));
+        A.release(mk);
+        return;
+    }
+    k_tile_reduce<T, In><<<(unsigned)ntiles, BLOCK, 0, st>>>(n, in, tiles);
+    HGP_LAUNCH_CHECK();
+    k_scan_tiles<T><<<1, BLOCK, 0, st>>>(ntiles, tiles, total_dev);
+    HGP_LAUNCH_CHECK();
+    k_tile_scan<T, In, Out><<<(unsigned)ntiles, BLOCK, 0, st>>>(n, in, out, tiles);
+    HGP_LAUNCH_CHECK();
+    A.release(mk);
+}
+
+// Size-only reservation of scan_apply's temporaries (never launches).
+template <class T>
+inline void scan_reserve(Arena &A, size_t n) {
+    size_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    size_t mk = A.mark();
+    A.alloc<T>(ntiles ? ntiles : 1);
+    A.release(mk);
+}
+
+// Functors -------------------------------------------------------------------
+template <class T>
+struct LoadArr {
+    const T *a;
+    __device__ T operator()(size_t i) const { return a[i]; }
+};
+template <class T>
+struct StoreExcl {
+    T *out;
+    __device__ void operator()(size_t i, T excl, T) const { out[i] = excl; }
+};
+
+// Exclusive scan of an array into another (may alias): out[i] = sum a[0:i].
+template <class T>
+void exclusive_scan(Arena &A, const T *a, T *out, size_t n, T *total_dev, hipStream_t st) {
+    scan_apply<T>(A, n, LoadArr<T>{a}, StoreExcl<T>{out}, total_dev, st);
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (key, value) pairs; 8-bit digits.
+// ---------------------------------------------------------------------------
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = BLOCK * RS_ITEMS;
+
+template <class K>
+__global__ __launch_bounds__(BLOCK) void k_rs_hist(const K *keys, size_t n, int shift, uint32_t ntiles,
+                                                   uint32_t *counts) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    size_t base = (size_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        size_t i = base + (size_t)r * BLOCK + threadIdx.x;
+        bool valid = i < n;
+        uint32_t d = valid ? ((uint32_t)(keys[i] >> shift) & 0xFFu) : 0u;
+        // one LDS atomic per distinct digit of the wave
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t vote = __ballot(bit);
+            match &= bit ? vote : ~vote;
+        }
+        if (valid && (match & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(match));
+    }
+    __syncthreads();
+    counts[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+template <class K>
+__global__ __launch_bounds__(BLOCK) void k_rs_scatter(const K *keys, const uint32_t *vals, K *keys_out,
+                                                      uint32_t *vals_out, size_t n, int shift,
+                                                      uint32_t ntiles, const uint32_t *offsets) {
+    __shared__ uint32_t base_off[256];
+    __shared__ uint32_t wcnt[BLOCK / WAVE][256];
+    const unsigned tid = threadIdx.x, w = tid / WAVE, l = __lane_id();
+    base_off[tid] = offsets[(size_t)tid * ntiles + blockIdx.x];
+    size_t tbase = (size_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+#pragma unroll
+        for (int q = 0; q < BLOCK / WAVE; ++q) wcnt[q][tid] = 0;
+        __syncthreads();
+        size_t i = tbase + (size_t)r * BLOCK + tid;
+        bool valid = i < n;
+        K key = valid ? keys[i] : K(0);
+        uint32_t val = valid ? vals[i] : 0u;
+        uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t vote = __ballot(bit);
+            match &= bit ? vote : ~vote;
+        }
+        uint32_t rank = (uint32_t)__popcll(match & lanemask_lt());
+        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base_off[d] + rank;
+            for (unsigned q = 0; q < w; ++q) pos += wcnt[q][d];
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int q = 0; q < BLOCK / WAVE; ++q) add += wcnt[q][tid];
+        base_off[tid] += add;
+    }
+}
+
+// Sorts n pairs by bits [begin_bit, end_bit) of the key, stably.  The sorted
+// data ends in (*keys_io, *vals_io), which may be swapped with the alternate
+// buffers given.
+template <class K>
+void radix_sort_pairs(Arena &A, K **keys_io, uint32_t **vals_io, K *keys_alt, uint32_t *vals_alt,
+                      size_t n, int begin_bit, int end_bit, hipStream_t st) {
+    uint32_t ntiles = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
+    size_t mk = A.mark();
+    uint32_t *counts = A.alloc<uint32_t>((size_t)256 * (ntiles ? ntiles : 1));
+    scan_reserve<uint32_t>(A, (size_t)256 * (ntiles ? ntiles : 1));
+    if (A.measure || n == 0) { A.release(mk); return; }
+    K *kin = *keys_io, *kout = keys_alt;
+    uint32_t *vin = *vals_io, *vout = vals_alt;
+    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+        k_rs_hist<K><<<ntiles, BLOCK, 0, st>>>(kin, n, shift, ntiles, counts);
+        HGP_LAUNCH_CHECK();
+        exclusive_scan<uint32_t>(A, counts, counts, (size_t)256 * ntiles, nullptr, st);
+        k_rs_scatter<K><<<ntiles, BLOCK, 0, st>>>(kin, vin, kout, vout, n, shift, ntiles, counts);
+        HGP_LAUNCH_CHECK();
+        K *tk = kin; kin = kout; kout = tk;
+        uint32_t *tv = vin; vin = vout; vout = tv;
+    }
+    *keys_io = kin;
+    *vals_io = vin;
+    A.release(mk);
+}
+
+// Size-only reservation of radix_sort_pairs' temporaries (never launches).
+inline void sort_reserve(Arena &A, size_t n) {
+    size_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+    size_t mk = A.mark();
+    A.alloc<uint32_t>((size_t)256 * (ntiles ? ntiles : 1));
+    scan_reserve<uint32_t>(A, (size_t)256 * (ntiles ? ntiles : 1));
+    A.release(mk);
+}
+
+inline int bits_for(uint64_t maxval) {
+    int b = 0;
+    while (b < 64 && (maxval >> b) != 0) ++b;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_fill(T *p, size_t n, T v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <class T>
+inline void fill(T *p, size_t n, T v, hipStream_t st) {
+    if (n == 0) return;
+    k_fill<T><<<grid_for(n, BLOCK * 4, FILL_BLOCKS), BLOCK, 0, st>>>(p, n, v);
+    HGP_LAUNCH_CHECK();
+}
+
+template <class T>
+__global__ void k_iota(T *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = (T)i;
+}
+
+}  // namespace hgp

@@ -1,0 +1,700 @@
+// Deterministic synchronous label propagation (paper Sec. 11) on the
+// connectivity objective (Sec. 2) with the connectivity gain of Sec. 6.
+//
+// Partition state per net (paper Sec. 6.1 keeps pin counts Phi(e,b) and the
+// connectivity set Lambda(e) as a k-bit bitset).  Here every net stores two
+// k-bit bitsets: Lambda(e) = {b : Phi(e,b) > 0} and Lambda1(e) = {b :
+// Phi(e,b) = 1}.  These are exactly what the gain needs:
+//   b(u)     = w({e in I(u) : Pi[u] in Lambda1(e)})
+//   aff(u,t) = w({e in I(u) : t in Lambda(e)})
+//   g_u(t)   = b(u) - (w(I(u)) - aff(u,t)).
+// After a sub-round's moves are applied, the two bitsets of every net
+// touching a moved node are recomputed from its pins (net-parallel, no
+// atomics on counts), and the objective changes by
+// sum over those nets of w(e) * (max(lambda'-1,0) - max(lambda-1,0)).
+//
+// Selection per block pair: proposals are sorted by (s, t, gain desc, u asc)
+// with the stable radix sort; within a pair the paper's two-pointer walk is a
+// merge of the two exclusive weight-prefix sequences (A first on ties), so
+// the state after each step is found by one binary search in the other
+// sequence and every element tests its own state in parallel; the last
+// feasible state is an atomicMax over (step, i).
+#include "prims.h"
+#include "kernels.h"
+
+namespace hgp {
+
+template <int KW>
+struct Bits {
+    uint64_t w[KW];
+};
+
+// ---------------------------------------------------------------------------
+// Connectivity bitsets of nets
+// ---------------------------------------------------------------------------
+template <int KW>
+__device__ inline void net_bits(const uint32_t *pins, uint32_t b, uint32_t len, const uint32_t *part, uint64_t *once,
+                                uint64_t *twice) {
+#pragma unroll
+    for (int q = 0; q < KW; ++q) { once[q] = 0; twice[q] = 0; }
+    for (uint32_t j = 0; j < len; ++j) {
+        uint32_t blk = part[pins[b + j]];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) {
+            uint64_t bit = ((uint32_t)q == (blk >> 6)) ? (1ull << (blk & 63)) : 0ull;
+            twice[q] |= once[q] & bit;
+            once[q] |= bit;
+        }
+    }
+}
+
+__device__ inline int64_t lam_cost(int lam) { return lam > 1 ? (int64_t)(lam - 1) : 0; }
+
+template <int KW>
+__device__ inline int popc_bits(const uint64_t *x) {
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < KW; ++q) c += __popcll(x[q]);
+    return c;
+}
+
+// Thread per net for nets of at most 64 pins; longer nets go to a list.
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_conn_small(const uint32_t *pin_off, const uint32_t *pins, uint32_t m,
+                                                      const int32_t *nwgt, const uint32_t *part, uint64_t *lam,
+                                                      uint64_t *lam1, int64_t *f, uint32_t *longl, uint32_t *nlong) {
+    __shared__ int64_t red[BLOCK / WAVE];
+    int64_t acc = 0;
+    for (uint32_t e0 = blockIdx.x * blockDim.x; e0 < m; e0 += gridDim.x * blockDim.x) {
+        uint32_t e = e0 + threadIdx.x;
+        bool act = e < m;
+        uint32_t b = act ? pin_off[e] : 0, len = act ? pin_off[e + 1] - b : 0;
+        bool lng = act && len > 64;
+        uint32_t pos = warp_agg_append(nlong, lng);
+        if (lng) longl[pos] = e;
+        if (!act || lng) continue;
+        uint64_t once[KW], twice[KW];
+        net_bits<KW>(pins, b, len, part, once, twice);
+#pragma unroll
+        for (int q = 0; q < KW; ++q) {
+            lam[(size_t)e * KW + q] = once[q];
+            lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
+        }
+        acc += lam_cost(popc_bits<KW>(once)) * nwgt[e];
+    }
+    acc = wave_sum(acc);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+        if (t) atomic_add_i64(f, t);
+    }
+}
+
+// Wave per long net.
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_conn_long(const uint32_t *pin_off, const uint32_t *pins,
+                                                     const uint32_t *list, const uint32_t *count_dev,
+                                                     const int32_t *nwgt, const uint32_t *part, uint64_t *lam,
+                                                     uint64_t *lam1, int64_t *f, bool delta) {
+    const uint32_t count = *count_dev;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nw = gridDim.x * blockDim.x / WAVE;
+    for (uint32_t idx = wid; idx < count; idx += nw) {
+        uint32_t e = list[idx];
+        uint32_t b = pin_off[e], len = pin_off[e + 1] - b;
+        uint64_t once[KW], twice[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) { once[q] = 0; twice[q] = 0; }
+        for (uint32_t j = __lane_id(); j < len; j += WAVE) {
+            uint32_t blk = part[pins[b + j]];
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                uint64_t bit = ((uint32_t)q == (blk >> 6)) ? (1ull << (blk & 63)) : 0ull;
+                twice[q] |= once[q] & bit;
+                once[q] |= bit;
+            }
+        }
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                uint64_t oo = __shfl_xor(once[q], o, 64);
+                uint64_t ot = __shfl_xor(twice[q], o, 64);
+                twice[q] = twice[q] | ot | (once[q] & oo);
+                once[q] |= oo;
+            }
+        }
+        if (__lane_id() == 0) {
+            int64_t d = lam_cost(popc_bits<KW>(once));
+            if (delta) d -= lam_cost(popc_bits<KW>(lam + (size_t)e * KW));
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                lam[(size_t)e * KW + q] = once[q];
+                lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
+            }
+            if (d) atomic_add_i64(f, d * nwgt[e]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_block_weights(const uint32_t *part, const int32_t *vwgt, uint32_t n,
+                                                         uint32_t k, int64_t *bw) {
+    __shared__ int64_t h[256];
+    for (uint32_t b = threadIdx.x; b < k; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        atomicAdd((unsigned long long *)&h[part[v]], (unsigned long long)(int64_t)vwgt[v]);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < k; b += blockDim.x)
+        if (h[b]) atomic_add_i64(&bw[b], h[b]);
+}
+
+// ---------------------------------------------------------------------------
+// Gains
+// ---------------------------------------------------------------------------
+struct GainArgs {
+    const uint32_t *inc_off, *inc;
+    const int32_t *nwgt, *vwgt;
+    const uint64_t *lam, *lam1;
+    const uint32_t *part;
+    const int64_t *bw;
+    int64_t lmax;
+    uint64_t mseed;
+    uint32_t level, round, sub, S, n;
+    uint32_t *prop_t, *prop_g, *plist, *nprop, *gmax;
+};
+
+__device__ inline void propose(const GainArgs &a, uint32_t u, uint32_t t, uint32_t g, bool has) {
+    uint32_t pos = warp_agg_append(a.nprop, has);
+    if (has) {
+        a.plist[pos] = u;
+        a.prop_t[u] = t;
+        a.prop_g[u] = g;
+        atomicMax(a.gmax, g);
+    }
+}
+
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_gains_thread(GainArgs a) {
+    for (uint32_t u0 = blockIdx.x * blockDim.x; u0 < a.n; u0 += gridDim.x * blockDim.x) {
+        uint32_t u = u0 + threadIdx.x;
+        bool has = false;
+        uint32_t best_t = NONE, best_g = 0;
+        if (u < a.n && tag_hash(a.mseed, 3, a.level, a.round, u) % a.S == a.sub) {
+            uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
+            if (j1 - j0 <= 64) {
+                uint32_t s = a.part[u];
+                int64_t bu = 0, wI = 0;
+                uint64_t U[KW];
+#pragma unroll
+                for (int q = 0; q < KW; ++q) U[q] = 0;
+                for (uint32_t j = j0; j < j1; ++j) {
+                    uint32_t e = a.inc[j];
+                    int64_t w = a.nwgt[e];
+                    wI += w;
+                    if ((a.lam1[(size_t)e * KW + (s >> 6)] >> (s & 63)) & 1ull) bu += w;
+#pragma unroll
+                    for (int q = 0; q < KW; ++q) U[q] |= a.lam[(size_t)e * KW + q];
+                }
+                U[s >> 6] &= ~(1ull << (s & 63));
+                const int64_t cu = a.vwgt[u];
+#pragma unroll
+                for (int q = 0; q < KW; ++q) {
+                    uint64_t x = U[q];
+                    while (x) {
+                        int bit = __ffsll((long long)x) - 1;
+                        x &= x - 1;
+                        uint32_t t = (uint32_t)(q * 64 + bit);
+                        if (a.bw[t] + cu > a.lmax) continue;
+                        int64_t aff = 0;
+                        for (uint32_t j = j0; j < j1; ++j) {
+                            uint32_t e = a.inc[j];
+                            if ((a.lam[(size_t)e * KW + q] >> bit) & 1ull) aff += a.nwgt[e];
+                        }
+                        int64_t g = bu - (wI - aff);
+                        if (g > (int64_t)best_g) { best_g = (uint32_t)g; best_t = t; }
+                    }
+                }
+                has = best_t != NONE;
+            }
+        }
+        propose(a, u, best_t, best_g, has);
+    }
+}
+
+// Wave per vertex of degree > 64 (list built once per level).
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_gains_wave(GainArgs a, const uint32_t *list, uint32_t count) {
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nw = gridDim.x * blockDim.x / WAVE;
+    const unsigned l = __lane_id();
+    for (uint32_t idx = wid; idx < count; idx += nw) {
+        uint32_t u = list[idx];
+        if (tag_hash(a.mseed, 3, a.level, a.round, u) % a.S != a.sub) continue;
+        uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
+        uint32_t s = a.part[u];
+        int64_t bu = 0, wI = 0;
+        uint64_t U[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) U[q] = 0;
+        for (uint32_t j = j0 + l; j < j1; j += WAVE) {
+            uint32_t e = a.inc[j];
+            int64_t w = a.nwgt[e];
+            wI += w;
+            if ((a.lam1[(size_t)e * KW + (s >> 6)] >> (s & 63)) & 1ull) bu += w;
+#pragma unroll
+            for (int q = 0; q < KW; ++q) U[q] |= a.lam[(size_t)e * KW + q];
+        }
+        bu = wave_sum(bu);
+        wI = wave_sum(wI);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1)
+#pragma unroll
+            for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
+        U[s >> 6] &= ~(1ull << (s & 63));
+        const int64_t cu = a.vwgt[u];
+        uint32_t best_t = NONE, best_g = 0;
+#pragma unroll
+        for (int q = 0; q < KW; ++q) {
+            uint64_t x = U[q];
+            while (x) {
+                int bit = __ffsll((long long)x) - 1;
+                x &= x - 1;
+                uint32_t t = (uint32_t)(q * 64 + bit);
+                if (a.bw[t] + cu > a.lmax) continue;
+                int64_t aff = 0;
+                for (uint32_t j = j0 + l; j < j1; j += WAVE) {
+                    uint32_t e = a.inc[j];
+                    if ((a.lam[(size_t)e * KW + q] >> bit) & 1ull) aff += a.nwgt[e];
+                }
+                aff = wave_sum(aff);
+                int64_t g = bu - (wI - aff);
+                if (g > (int64_t)best_g) { best_g = (uint32_t)g; best_t = t; }
+            }
+        }
+        bool has = (l == 0) && best_t != NONE;
+        if (l == 0 && has) {
+            uint32_t pos = atomicAdd(a.nprop, 1u);
+            a.plist[pos] = u;
+            a.prop_t[u] = best_t;
+            a.prop_g[u] = best_g;
+            atomicMax(a.gmax, best_g);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pair sort keys, segment bounds, selection, apply
+// ---------------------------------------------------------------------------
+struct KeyLayout {
+    int sh_s, sh_t, sh_g, sh_u;  // bit positions
+    uint32_t kmask;
+    uint32_t G;  // gmax: stored as G - g (descending gain)
+    bool with_u;
+};
+
+__global__ void k_lp_keys(const uint32_t *plist, uint32_t np, const uint32_t *part, const uint32_t *prop_t,
+                          const uint32_t *prop_g, KeyLayout L, uint64_t *keys, uint32_t *vals, bool from_vals) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
+        uint32_t u = from_vals ? vals[i] : plist[i];
+        uint64_t key = ((uint64_t)part[u] << L.sh_s) | ((uint64_t)prop_t[u] << L.sh_t) |
+                       ((uint64_t)(L.G - prop_g[u]) << L.sh_g);
+        if (L.with_u) key |= (uint64_t)u << L.sh_u;
+        keys[i] = key;
+        vals[i] = u;
+    }
+}
+
+__global__ void k_u_only_keys(const uint32_t *plist, uint32_t np, uint64_t *keys, uint32_t *vals) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
+        keys[i] = plist[i];
+        vals[i] = plist[i];
+    }
+}
+
+struct SortedWeight {
+    const uint32_t *vals;
+    const int32_t *vwgt;
+    __device__ uint64_t operator()(size_t i) const { return (uint64_t)(uint32_t)vwgt[vals[i]]; }
+};
+struct StoreIncl {
+    uint64_t *out;
+    __device__ void operator()(size_t i, uint64_t excl, uint64_t v) const { out[i] = excl + v; }
+};
+
+__device__ inline uint32_t key_pair(uint64_t key, const KeyLayout &L, uint32_t k) {
+    uint32_t s = (uint32_t)(key >> L.sh_s) & L.kmask;
+    uint32_t t = (uint32_t)(key >> L.sh_t) & L.kmask;
+    return s * k + t;
+}
+
+__global__ void k_pair_bounds(const uint64_t *keys, uint32_t np, KeyLayout L, uint32_t k, uint32_t *seg_start,
+                              uint32_t *seg_end) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
+        uint32_t pr = key_pair(keys[i], L, k);
+        if (i == 0 || key_pair(keys[i - 1], L, k) != pr) seg_start[pr] = i;
+        if (i + 1 == np || key_pair(keys[i + 1], L, k) != pr) seg_end[pr] = i + 1;
+    }
+}
+
+struct SegView {
+    uint32_t start, len;
+    uint64_t base;  // prefix weight before the segment
+    const uint64_t *incl;
+    __device__ uint64_t excl(uint32_t i) const {  // weight of the first i elements
+        return i == 0 ? 0 : incl[start + i - 1] - base;
+    }
+};
+
+__device__ inline SegView seg_view(const uint32_t *seg_start, const uint32_t *seg_end, uint32_t pr,
+                                   const uint64_t *incl) {
+    SegView v;
+    v.start = seg_start[pr];
+    uint32_t end = seg_end[pr];
+    v.len = end - v.start;
+    v.base = v.start == 0 ? 0 : incl[v.start - 1];
+    v.incl = incl;
+    return v;
+}
+
+// number of i in [0, len) with excl(i) < x (strict) or <= x (non-strict)
+__device__ inline uint32_t count_below(const SegView &v, uint64_t x, bool strict) {
+    uint32_t lo = 0, hi = v.len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        uint64_t e = v.excl(mid);
+        bool below = strict ? (e < x) : (e <= x);
+        if (below) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline int64_t floor_div_i64(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) --q;
+    return q;
+}
+
+__global__ void k_lp_select(const uint64_t *keys, uint32_t np, KeyLayout L, uint32_t k, const uint32_t *seg_start,
+                            const uint32_t *seg_end, const uint64_t *incl, const int64_t *bw, int64_t lmax,
+                            unsigned long long *best) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
+        uint64_t key = keys[i];
+        uint32_t s = (uint32_t)(key >> L.sh_s) & L.kmask;
+        uint32_t t = (uint32_t)(key >> L.sh_t) & L.kmask;
+        uint32_t x = s < t ? s : t, y = s < t ? t : s;  // unordered pair, A = moves x->y
+        SegView A = seg_view(seg_start, seg_end, x * k + y, incl);
+        SegView Bv = seg_view(seg_start, seg_end, y * k + x, incl);
+        int64_t beta_x = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
+        int64_t beta_y = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
+        uint32_t ia, jb;
+        if (s == x) {
+            uint32_t loc = i - A.start;
+            ia = loc + 1;
+            jb = count_below(Bv, A.excl(loc), true);
+            if (loc == 0 && beta_x >= 0 && beta_y >= 0) atomicMax(&best[x * k + y], 1ull << 32);
+        } else {
+            uint32_t loc = i - Bv.start;
+            jb = loc + 1;
+            ia = count_below(A, Bv.excl(loc), false);
+            if (loc == 0 && beta_x >= 0 && beta_y >= 0) atomicMax(&best[x * k + y], 1ull << 32);
+        }
+        int64_t xv = (int64_t)A.excl(ia) - (int64_t)Bv.excl(jb);
+        if (-beta_x <= xv && xv <= beta_y)
+            atomicMax(&best[x * k + y], ((unsigned long long)(ia + jb + 1) << 32) | ia);
+    }
+}
+
+__global__ void k_lp_apply(const uint64_t *keys, const uint32_t *vals, uint32_t np, KeyLayout L, uint32_t k,
+                           const uint32_t *seg_start, const unsigned long long *best, const int32_t *vwgt,
+                           const uint32_t *inc_off, const uint32_t *inc, uint32_t *part, int64_t *bw,
+                           uint32_t *tstamp, uint32_t stamp, uint32_t *tlist, uint32_t *ntouched,
+                           uint32_t *moves) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ((np + 63) / 64) * 64; i += gridDim.x * blockDim.x) {
+        bool mv = false;
+        if (i < np) {
+            uint64_t key = keys[i];
+            uint32_t s = (uint32_t)(key >> L.sh_s) & L.kmask;
+            uint32_t t = (uint32_t)(key >> L.sh_t) & L.kmask;
+            uint32_t x = s < t ? s : t, y = s < t ? t : s;
+            unsigned long long bst = best[x * k + y];
+            if (bst) {
+                uint32_t istar = (uint32_t)bst;
+                uint32_t d = (uint32_t)(bst >> 32) - 1;
+                uint32_t jstar = d - istar;
+                uint32_t loc = i - seg_start[s * k + t];
+                mv = (s == x) ? (loc < istar) : (loc < jstar);
+            }
+            if (mv) {
+                uint32_t u = vals[i];
+                part[u] = t;
+                int64_t c = vwgt[u];
+                atomic_add_i64(&bw[s], -c);
+                atomic_add_i64(&bw[t], c);
+                for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) {
+                    uint32_t e = inc[j];
+                    if (atomicExch(&tstamp[e], stamp) != stamp) {
+                        uint32_t pos = atomicAdd(ntouched, 1u);
+                        tlist[pos] = e;
+                    }
+                }
+            }
+        }
+        uint64_t m = __ballot(mv);
+        if (__lane_id() == 0 && m) atomicAdd(moves, (uint32_t)__popcll(m));
+    }
+}
+
+// Recompute Lambda / Lambda1 of touched nets (thread per net up to 64 pins;
+// longer nets are forwarded to the wave kernel) and add the objective delta.
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_lp_update(const uint32_t *pin_off, const uint32_t *pins,
+                                                     const uint32_t *tlist, const uint32_t *ntouched,
+                                                     const int32_t *nwgt, const uint32_t *part, uint64_t *lam,
+                                                     uint64_t *lam1, int64_t *f, uint32_t *longl, uint32_t *nlong) {
+    __shared__ int64_t red[BLOCK / WAVE];
+    const uint32_t cnt = *ntouched;
+    int64_t acc = 0;
+    for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < cnt; i0 += gridDim.x * blockDim.x) {
+        uint32_t i = i0 + threadIdx.x;
+        bool act = i < cnt;
+        uint32_t e = act ? tlist[i] : 0;
+        uint32_t b = act ? pin_off[e] : 0, len = act ? pin_off[e + 1] - b : 0;
+        bool lng = act && len > 64;
+        uint32_t pos = warp_agg_append(nlong, lng);
+        if (lng) longl[pos] = e;
+        if (!act || lng) continue;
+        uint64_t once[KW], twice[KW];
+        net_bits<KW>(pins, b, len, part, once, twice);
+        int64_t d = lam_cost(popc_bits<KW>(once)) - lam_cost(popc_bits<KW>(lam + (size_t)e * KW));
+#pragma unroll
+        for (int q = 0; q < KW; ++q) {
+            lam[(size_t)e * KW + q] = once[q];
+            lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
+        }
+        acc += d * nwgt[e];
+    }
+    acc = wave_sum(acc);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+        if (t) atomic_add_i64(f, t);
+    }
+}
+
+__global__ void k_degree_list(const uint32_t *inc_off, uint32_t n, uint32_t *list, uint32_t *count) {
+    for (uint32_t u0 = blockIdx.x * blockDim.x; u0 < n; u0 += gridDim.x * blockDim.x) {
+        uint32_t u = u0 + threadIdx.x;
+        bool big = u < n && inc_off[u + 1] - inc_off[u] > 64;
+        uint32_t pos = warp_agg_append(count, big);
+        if (big) list[pos] = u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct RefineBufs {
+    uint64_t *lam, *lam1;
+    int64_t *f, *bw;
+    uint32_t *longl, *biglist, *plist, *prop_t, *prop_g, *tstamp, *tlist, *scal;
+    uint64_t *keys, *keys_alt, *incl;
+    uint32_t *vals, *vals_alt, *seg_start, *seg_end;
+    unsigned long long *best;
+};
+
+static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
+    int KW = (int)((k + 63) / 64);
+    B.lam = A.alloc<uint64_t>((size_t)m * KW);
+    B.lam1 = A.alloc<uint64_t>((size_t)m * KW);
+    B.f = A.alloc<int64_t>(1);
+    B.bw = A.alloc<int64_t>(k);
+    B.longl = A.alloc<uint32_t>(m);
+    B.biglist = A.alloc<uint32_t>(n);
+    B.plist = A.alloc<uint32_t>(n);
+    B.prop_t = A.alloc<uint32_t>(n);
+    B.prop_g = A.alloc<uint32_t>(n);
+    B.tstamp = A.alloc<uint32_t>(m);
+    B.tlist = A.alloc<uint32_t>(m);
+    B.scal = A.alloc<uint32_t>(16);
+    B.keys = A.alloc<uint64_t>(n);
+    B.keys_alt = A.alloc<uint64_t>(n);
+    B.incl = A.alloc<uint64_t>(n);
+    B.vals = A.alloc<uint32_t>(n);
+    B.vals_alt = A.alloc<uint32_t>(n);
+    B.seg_start = A.alloc<uint32_t>((size_t)k * k);
+    B.seg_end = A.alloc<uint32_t>((size_t)k * k);
+    B.best = A.alloc<unsigned long long>((size_t)k * k);
+    sort_reserve(A, n);
+    scan_reserve<uint64_t>(A, n);
+}
+
+size_t refine_workspace(uint32_t n, uint32_t m, uint32_t k) {
+    Arena A(nullptr, 0);
+    RefineBufs B;
+    plan(A, n, m, k, B);
+    return A.peak;
+}
+
+template <int KW>
+static void build_conn(const hgp_hg &h, const uint32_t *part, RefineBufs &B, hipStream_t st) {
+    HGP_CHECK_HIP(hipMemsetAsync(B.f, 0, sizeof(int64_t), st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.scal + 8, 0, sizeof(uint32_t), st));
+    if (h.m) {
+        k_conn_small<KW><<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.pins, h.m, h.nwgt, part,
+                                                                             B.lam, B.lam1, B.f, B.longl, B.scal + 8);
+        HGP_LAUNCH_CHECK();
+        k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, B.scal + 8, h.nwgt, part,
+                                                           B.lam, B.lam1, B.f, false);
+        HGP_LAUNCH_CHECK();
+    }
+}
+
+static void block_weights(const uint32_t *part, const int32_t *vwgt, uint32_t n, uint32_t k, int64_t *bw,
+                          hipStream_t st) {
+    HGP_CHECK_HIP(hipMemsetAsync(bw, 0, sizeof(int64_t) * k, st));
+    k_block_weights<<<grid_for(n, BLOCK * 8, 1024), BLOCK, 0, st>>>(part, vwgt, n, k, bw);
+    HGP_LAUNCH_CHECK();
+}
+
+template <int KW>
+static void objective_t(const hgp_hg &h, uint32_t k, const uint32_t *part, int64_t *obj, int64_t *bw_out, Arena &A,
+                        hipStream_t st) {
+    size_t mk = A.mark();
+    RefineBufs B;
+    plan(A, h.n, h.m, k, B);
+    build_conn<KW>(h, part, B, st);
+    HGP_CHECK_HIP(hipMemcpyAsync(obj, B.f, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    if (bw_out) block_weights(part, h.vwgt, h.n, k, bw_out, st);
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    A.release(mk);
+}
+
+void objective(const hgp_hg &h, uint32_t k, const uint32_t *part, int64_t *obj, int64_t *bw, Arena &A,
+               hipStream_t st) {
+    switch ((k + 63) / 64) {
+        case 1: objective_t<1>(h, k, part, obj, bw, A, st); break;
+        case 2: objective_t<2>(h, k, part, obj, bw, A, st); break;
+        case 3: objective_t<3>(h, k, part, obj, bw, A, st); break;
+        default: objective_t<4>(h, k, part, obj, bw, A, st); break;
+    }
+}
+
+template <int KW>
+static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj,
+                     int64_t *bw_out, Arena &A, hipStream_t st) {
+    const uint32_t n = h.n, m = h.m, k = prm.k;
+    size_t mk = A.mark();
+    RefineBufs B;
+    plan(A, n, m, k, B);
+    const int64_t W = total_weight(h.vwgt, n, A, st);
+    const int64_t lmax = ((int64_t)(prm.eps_den + prm.eps_num) * ((W + k - 1) / k)) / (int64_t)prm.eps_den;
+    const uint64_t mseed = mix64(prm.seed);
+    uint32_t *nprop = B.scal + 0, *gmax = B.scal + 1, *ntouched = B.scal + 2, *moves = B.scal + 3,
+             *nlong = B.scal + 4, *nbig = B.scal + 5;
+
+    build_conn<KW>(h, part, B, st);
+    block_weights(part, h.vwgt, n, k, B.bw, st);
+    if (m) HGP_CHECK_HIP(hipMemsetAsync(B.tstamp, 0, sizeof(uint32_t) * m, st));
+    HGP_CHECK_HIP(hipMemsetAsync(nbig, 0, sizeof(uint32_t), st));
+    k_degree_list<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, B.biglist, nbig);
+    HGP_LAUNCH_CHECK();
+    uint32_t nbig_h = 0;
+    HGP_CHECK_HIP(hipMemcpyAsync(&nbig_h, nbig, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+
+    const int kb = bits_for(k - 1), ub = bits_for(n ? n - 1 : 0);
+    uint32_t stamp = 0;
+    for (uint32_t r = 0; r < prm.lp_rounds; ++r) {
+        HGP_CHECK_HIP(hipMemsetAsync(moves, 0, sizeof(uint32_t), st));
+        for (uint32_t s = 0; s < prm.lp_subrounds; ++s) {
+            ++stamp;
+            HGP_CHECK_HIP(hipMemsetAsync(nprop, 0, sizeof(uint32_t) * 2, st));
+            GainArgs ga{h.inc_off, h.inc, h.nwgt, h.vwgt, B.lam, B.lam1, part, B.bw, lmax, mseed, level, r, s,
+                        prm.lp_subrounds, n, B.prop_t, B.prop_g, B.plist, nprop, gmax};
+            k_gains_thread<KW><<<grid_for(n, BLOCK, FILL_BLOCKS * 4), BLOCK, 0, st>>>(ga);
+            HGP_LAUNCH_CHECK();
+            if (nbig_h) {
+                k_gains_wave<KW><<<grid_for(nbig_h, BLOCK / WAVE, FILL_BLOCKS), BLOCK, 0, st>>>(ga, B.biglist, nbig_h);
+                HGP_LAUNCH_CHECK();
+            }
+            uint32_t hv[2];
+            HGP_CHECK_HIP(hipMemcpyAsync(hv, nprop, sizeof(hv), hipMemcpyDeviceToHost, st));
+            HGP_CHECK_HIP(hipStreamSynchronize(st));
+            const uint32_t np = hv[0], G = hv[1];
+            if (np == 0) continue;
+            const int gb = bits_for(G);
+            KeyLayout L;
+            L.kmask = (1u << kb) - 1u;
+            if (kb == 0) L.kmask = 0;
+            L.G = G;
+            uint64_t *kk = B.keys;
+            uint32_t *vv = B.vals;
+            if (2 * kb + gb + ub <= 64) {
+                L.with_u = true;
+                L.sh_u = 0; L.sh_g = ub; L.sh_t = ub + gb; L.sh_s = ub + gb + kb;
+                k_lp_keys<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.plist, np, part, B.prop_t, B.prop_g, L,
+                                                                             kk, vv, false);
+                HGP_LAUNCH_CHECK();
+                radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, np, 0, 2 * kb + gb + ub, st);
+            } else {
+                L.with_u = false;
+                L.sh_u = 0; L.sh_g = 0; L.sh_t = gb; L.sh_s = gb + kb;
+                k_u_only_keys<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.plist, np, kk, vv);
+                HGP_LAUNCH_CHECK();
+                radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, np, 0, ub, st);
+                k_lp_keys<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.plist, np, part, B.prop_t, B.prop_g,
+                                                                             L, kk, vv, true);
+                HGP_LAUNCH_CHECK();
+                uint64_t *ka = (kk == B.keys) ? B.keys_alt : B.keys;
+                uint32_t *va = (vv == B.vals) ? B.vals_alt : B.vals;
+                radix_sort_pairs<uint64_t>(A, &kk, &vv, ka, va, np, 0, 2 * kb + gb, st);
+            }
+            scan_apply<uint64_t>(A, np, SortedWeight{vv, h.vwgt}, StoreIncl{B.incl}, (uint64_t *)nullptr, st);
+            HGP_CHECK_HIP(hipMemsetAsync(B.seg_start, 0, sizeof(uint32_t) * k * k, st));
+            HGP_CHECK_HIP(hipMemsetAsync(B.seg_end, 0, sizeof(uint32_t) * k * k, st));
+            HGP_CHECK_HIP(hipMemsetAsync(B.best, 0, sizeof(unsigned long long) * k * k, st));
+            k_pair_bounds<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, np, L, k, B.seg_start, B.seg_end);
+            HGP_LAUNCH_CHECK();
+            k_lp_select<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, np, L, k, B.seg_start, B.seg_end,
+                                                                           B.incl, B.bw, lmax, B.best);
+            HGP_LAUNCH_CHECK();
+            HGP_CHECK_HIP(hipMemsetAsync(ntouched, 0, sizeof(uint32_t), st));
+            HGP_CHECK_HIP(hipMemsetAsync(nlong, 0, sizeof(uint32_t), st));
+            k_lp_apply<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, np, L, k, B.seg_start, B.best,
+                                                                          h.vwgt, h.inc_off, h.inc, part, B.bw,
+                                                                          B.tstamp, stamp, B.tlist, ntouched, moves);
+            HGP_LAUNCH_CHECK();
+            k_lp_update<KW><<<FILL_BLOCKS, BLOCK, 0, st>>>(h.pin_off, h.pins, B.tlist, ntouched, h.nwgt, part, B.lam,
+                                                           B.lam1, B.f, B.longl, nlong);
+            HGP_LAUNCH_CHECK();
+            k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part,
+                                                               B.lam, B.lam1, B.f, true);
+            HGP_LAUNCH_CHECK();
+        }
+        uint32_t mv = 0;
+        HGP_CHECK_HIP(hipMemcpyAsync(&mv, moves, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HGP_CHECK_HIP(hipStreamSynchronize(st));
+        if (mv == 0) break;
+    }
+    if (obj) HGP_CHECK_HIP(hipMemcpyAsync(obj, B.f, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    if (bw_out) HGP_CHECK_HIP(hipMemcpyAsync(bw_out, B.bw, sizeof(int64_t) * k, hipMemcpyDeviceToDevice, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    A.release(mk);
+}
+
+void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj, int64_t *bw,
+               Arena &A, hipStream_t st) {
+    switch ((prm.k + 63) / 64) {
+        case 1: refine_t<1>(h, prm, level, part, obj, bw, A, st); break;
+        case 2: refine_t<2>(h, prm, level, part, obj, bw, A, st); break;
+        case 3: refine_t<3>(h, prm, level, part, obj, bw, A, st); break;
+        default: refine_t<4>(h, prm, level, part, obj, bw, A, st); break;
+    }
+}
+
+}  // namespace hgp

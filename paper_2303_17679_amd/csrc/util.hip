@@ -1,0 +1,150 @@
+// Reductions needed on the host (total weights) and input validation.
+#include "prims.h"
+#include "kernels.h"
+
+namespace hgp {
+
+__global__ __launch_bounds__(BLOCK) void k_sum_max(const int32_t *w, uint32_t n, int64_t *sum, int32_t *mx,
+                                                   uint32_t *nonpos) {
+    __shared__ int64_t rs[BLOCK / WAVE];
+    __shared__ int32_t rm[BLOCK / WAVE];
+    int64_t s = 0;
+    int32_t m = 0;
+    bool bad = false;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int32_t x = w[i];
+        s += x;
+        m = x > m ? x : m;
+        bad |= x < 1;
+    }
+    s = wave_sum(s);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        int32_t t = __shfl_xor(m, o, 64);
+        m = t > m ? t : m;
+    }
+    if (__lane_id() == 0) { rs[threadIdx.x / WAVE] = s; rm[threadIdx.x / WAVE] = m; }
+    if (bad) atomicOr(nonpos, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t ts = 0;
+        int32_t tm = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) { ts += rs[q]; tm = rm[q] > tm ? rm[q] : tm; }
+        atomic_add_i64(sum, ts);
+        atomicMax(mx, tm);
+    }
+}
+
+struct SumMax {
+    int64_t sum;
+    int32_t max;
+    bool nonpos;
+};
+
+static SumMax sum_max(const int32_t *w, uint32_t n, Arena &A, hipStream_t st) {
+    size_t mk = A.mark();
+    char *buf = A.alloc<char>(64);
+    SumMax r{0, 0, false};
+    if (A.measure) { A.release(mk); return r; }
+    HGP_CHECK_HIP(hipMemsetAsync(buf, 0, 64, st));
+    if (n) {
+        k_sum_max<<<grid_for(n, BLOCK * 8, 1024), BLOCK, 0, st>>>(w, n, (int64_t *)buf, (int32_t *)(buf + 8),
+                                                                  (uint32_t *)(buf + 12));
+        HGP_LAUNCH_CHECK();
+    }
+    char host[16];
+    HGP_CHECK_HIP(hipMemcpyAsync(host, buf, 16, hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    r.sum = *(int64_t *)host;
+    r.max = *(int32_t *)(host + 8);
+    r.nonpos = *(uint32_t *)(host + 12) != 0;
+    A.release(mk);
+    return r;
+}
+
+int64_t total_weight(const int32_t *w, uint32_t n, Arena &A, hipStream_t st) { return sum_max(w, n, A, st).sum; }
+int32_t max_vertex_weight(const int32_t *w, uint32_t n, Arena &A, hipStream_t st) { return sum_max(w, n, A, st).max; }
+
+// ---------------------------------------------------------------------------
+// Validation (bit 0: offsets, bit 1: ids/order, bit 2: transpose)
+// ---------------------------------------------------------------------------
+__global__ void k_check_offsets(const uint32_t *off, uint32_t cnt, uint32_t total, uint32_t *err) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= cnt; i += gridDim.x * blockDim.x) {
+        uint32_t o = off[i];
+        if (i == 0 && o != 0) atomicOr(err, 1u);
+        if (i == cnt && o != total) atomicOr(err, 1u);
+        if (i < cnt && off[i + 1] < o) atomicOr(err, 1u);
+        if (o > total) atomicOr(err, 1u);
+    }
+}
+
+// ids strictly ascending and < bound inside every segment
+__global__ void k_check_lists(const uint32_t *off, const uint32_t *data, uint32_t cnt, uint32_t bound, uint32_t *err) {
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < cnt; s += gridDim.x * blockDim.x) {
+        uint32_t prev = 0;
+        for (uint32_t j = off[s]; j < off[s + 1]; ++j) {
+            uint32_t x = data[j];
+            if (x >= bound || (j > off[s] && x <= prev)) { atomicOr(err, 2u); break; }
+            prev = x;
+        }
+    }
+}
+
+// every pin (e, v) appears as e in v's incidence list (both sides hold p
+// distinct pairs, so this makes the incidence the exact transpose)
+__global__ void k_check_transpose(const uint32_t *pin_off, const uint32_t *pins, uint32_t m, const uint32_t *inc_off,
+                                  const uint32_t *inc, uint32_t *err) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+        for (uint32_t j = pin_off[e]; j < pin_off[e + 1]; ++j) {
+            uint32_t v = pins[j];
+            uint32_t lo = inc_off[v], hi = inc_off[v + 1];
+            while (lo < hi) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (inc[mid] < e) lo = mid + 1; else hi = mid;
+            }
+            if (lo >= inc_off[v + 1] || inc[lo] != e) { atomicOr(err, 4u); break; }
+        }
+    }
+}
+
+size_t util_workspace(uint32_t, uint32_t) { return 4096; }
+
+hgp_status validate(const hgp_hg &h, Arena &A, hipStream_t st) {
+    size_t mk = A.mark();
+    uint32_t *err = A.alloc<uint32_t>(4);
+    if (A.measure) { A.release(mk); return HGP_OK; }
+    uint32_t e = 0;
+    HGP_CHECK_HIP(hipMemsetAsync(err, 0, 16, st));
+    k_check_offsets<<<grid_for((size_t)h.m + 1, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.m, h.p, err);
+    HGP_LAUNCH_CHECK();
+    k_check_offsets<<<grid_for((size_t)h.n + 1, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.n, h.p, err);
+    HGP_LAUNCH_CHECK();
+    HGP_CHECK_HIP(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    if (e) { A.release(mk); return HGP_E_INVALID; }
+    if (h.m) {
+        k_check_lists<<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.pins, h.m, h.n, err);
+        HGP_LAUNCH_CHECK();
+    }
+    k_check_lists<<<grid_for(h.n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, h.n, h.m, err);
+    HGP_LAUNCH_CHECK();
+    HGP_CHECK_HIP(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    if (e) { A.release(mk); return HGP_E_INVALID; }
+    if (h.m) {
+        k_check_transpose<<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.pins, h.m, h.inc_off,
+                                                                              h.inc, err);
+        HGP_LAUNCH_CHECK();
+    }
+    HGP_CHECK_HIP(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    A.release(mk);
+    if (e) return HGP_E_INVALID;
+    SumMax vw = sum_max(h.vwgt, h.n, A, st);
+    SumMax nw = sum_max(h.nwgt, h.m, A, st);
+    if (vw.nonpos || nw.nonpos) return HGP_E_INVALID;
+    if (vw.sum >= (int64_t)1 << 31 || nw.sum >= (int64_t)1 << 31) return HGP_E_OVERFLOW;
+    return HGP_OK;
+}
+
+}  // namespace hgp

@@ -1,0 +1,173 @@
+"""GPU parity: every step of the HIP path, at every level of the hierarchy,
+compared bit-exactly with the CPU oracle on the same seeded inputs.
+
+Each level's GPU input is the oracle's own level (coarse hypergraph,
+clustering, projected partition), so a mismatch names one step at one level.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2303_17679_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def hgp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2303_17679_amd as H
+    H.lib()
+    return H
+
+
+def dev(a, torch):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def same_hg(G, R):
+    """Coarse hypergraph from the GPU equals the oracle's, array by array."""
+    g = G.to_host()
+    assert (g.n, g.m) == (R.n, R.m)
+    for name in ("pin_off", "pins", "inc_off", "inc"):
+        assert np.array_equal(getattr(g, name), np.asarray(getattr(R, name), np.uint32)), name
+    assert np.array_equal(g.vwgt, R.vwgt) and np.array_equal(g.nwgt, R.nwgt)
+
+
+CASES = [
+    # name, k, seed
+    ("random2k", 2, 3),
+    ("random10k", 2, 1),
+    ("stencil16", 8, 5),
+    ("stencil24", 64, 7),
+    ("powerlaw20000", 8, 2),
+]
+
+
+def make(name):
+    if name == "random2k":
+        return W.random_uniform(2000, 2000, 2, 8, seed=9, name=name)
+    return W.workload(name)[0]
+
+
+@pytest.mark.parametrize("name,k,seed", CASES)
+def test_levels_bit_exact(hgp, orc, name, k, seed):
+    import torch
+    H = hgp
+    h = make(name)
+    P_or = orc.params(k, seed=seed)
+    P = H.params(k, seed=seed)
+    lv = orc.hierarchy(h, P_or)
+    say(f"[{name}] levels={len(lv) - 1} sizes={[x['h'].n for x in lv]}")
+    for l, L in enumerate(lv):
+        G = H.Hypergraph.from_host(L["h"])
+        say(f"[{name}] level {l}: validate n={G.n} m={G.m} p={G.p}")
+        assert H.validate(G) == 0
+        if "rep" in L:
+            say(f"[{name}] level {l}: coarsen")
+            rep, cnt = H.coarsen(G, P, l)
+            assert cnt == L["cnt"]
+            assert np.array_equal(host(rep), L["rep"])
+        if "cid" in L:
+            say(f"[{name}] level {l}: contract")
+            cid, Hc = H.contract(G, dev(L["rep"], torch))
+            assert np.array_equal(host(cid), L["cid"])
+            same_hg(Hc, lv[l + 1]["h"])
+        part_in = L["ip"] if "ip" in L else L["proj"]
+        if "ip" in L:
+            say(f"[{name}] level {l}: initial partition")
+            ip = H.initial_partition(G, k)
+            assert np.array_equal(host(ip), L["ip"])
+        else:
+            say(f"[{name}] level {l}: project")
+            pr = H.project(dev(lv[l]["cid"], torch), dev(lv[l + 1]["part"], torch))
+            assert np.array_equal(host(pr), L["proj"])
+        say(f"[{name}] level {l}: objective")
+        f0, bw0 = H.objective(G, k, dev(part_in, torch))
+        assert f0 == orc.objective(L["h"], k, part_in)[0]
+        say(f"[{name}] level {l}: refine_lp")
+        t = dev(part_in, torch)
+        f, bw = H.refine_lp(G, P, l, t)
+        assert f == L["f"]
+        assert np.array_equal(host(t), L["part"])
+        assert bw.cpu().numpy().tolist() == L["bw"].tolist()
+
+
+@pytest.mark.parametrize("name,k,seed", CASES)
+def test_partition_end_to_end(hgp, orc, name, k, seed):
+    H = hgp
+    h = make(name)
+    part_o, f_o, L_o = orc.partition(h, orc.params(k, seed=seed))
+    say(f"[{name}] partition")
+    G = H.Hypergraph.from_host(h)
+    part, f, L = H.partition(G, H.params(k, seed=seed))
+    assert (f, L) == (f_o, L_o)
+    assert np.array_equal(host(part), part_o)
+    # repeated runs are bit-identical
+    part2, f2, L2 = H.partition(G, H.params(k, seed=seed))
+    assert np.array_equal(host(part2), host(part)) and f2 == f
+
+
+EDGE = {
+    "isolated_and_single_pin": lambda: W.from_nets(
+        40, [[0], [1, 2], [3], [2, 5, 9], [10, 11], [10, 11], [1, 2], [30, 31, 32, 33], [7]],
+        nwgt=[1, 2, 3, 1, 1, 4, 1, 2, 5]),
+    "heavy_vertex_over_cap": lambda: W.from_nets(
+        12, [[0, 1], [1, 2], [2, 3], [3, 4], [4, 5], [5, 0], [6, 7, 8], [9, 10, 11], [0, 6, 9]],
+        vwgt=[40, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1]),
+    "duplicate_nets": lambda: W.from_nets(
+        30, [[i % 30, (i * 7 + 1) % 30] for i in range(60)] + [[0, 1, 2]] * 5),
+    "all_ties": lambda: W.from_nets(64, [[i, (i + 1) % 64] for i in range(64)]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(EDGE))
+@pytest.mark.parametrize("k", [2, 5])
+def test_edge_cases(hgp, orc, case, k):
+    H = hgp
+    h = EDGE[case]()
+    # a small contraction limit so that these tiny inputs are coarsened
+    P_or = orc.params(k, seed=3, limit_factor=2)
+    P = H.params(k, seed=3, limit_factor=2)
+    lv = orc.hierarchy(h, P_or)
+    import torch
+    for l, L in enumerate(lv):
+        G = H.Hypergraph.from_host(L["h"])
+        say(f"[edge {case} k={k}] level {l} n={G.n} m={G.m}")
+        if "rep" in L:
+            rep, cnt = H.coarsen(G, P, l)
+            assert cnt == L["cnt"] and np.array_equal(host(rep), L["rep"])
+        if "cid" in L:
+            cid, Hc = H.contract(G, dev(L["rep"], torch))
+            assert np.array_equal(host(cid), L["cid"])
+            same_hg(Hc, lv[l + 1]["h"])
+    part_o, f_o, _ = orc.partition(h, P_or)
+    part, f, _ = H.partition(H.Hypergraph.from_host(h), P)
+    assert f == f_o and np.array_equal(host(part), part_o)
+
+
+def test_invalid_inputs_rejected(hgp):
+    H = hgp
+    h = W.from_nets(5, [[0, 1], [1, 2, 3]])
+    G = H.Hypergraph.from_host(h)
+    assert H.validate(G) == 0
+    bad = H.Hypergraph.from_host(h)
+    bad.pins[1] = 7  # pin out of range
+    assert H.validate(bad) == -1
+    bad = H.Hypergraph.from_host(h)
+    bad.pins[0], bad.pins[1] = 1, 0  # not ascending
+    assert H.validate(bad) == -1
+    with pytest.raises(H.HGPError):
+        H.partition(G, H.params(300))
+    with pytest.raises(H.HGPError):
+        H.partition(G, H.params(1))
