@@ -80,7 +80,7 @@ typedef struct {
     uint32_t k;                 /* number of blocks, 2..256                          */
     uint32_t eps_num, eps_den;  /* imbalance eps = num/den exactly [3/100]; den <= 2^20 */
     uint64_t seed;              /* seed of the tie-break / sub-round hash [0]        */
-    uint32_t limit_factor;      /* coarsen while n > limit_factor * k [160] (Sec. 4.1) */
+    uint32_t limit_factor;      /* coarsen while n > limit_factor * k [160] (Sec. 4.1); <= 2^20 */
     uint32_t coarsen_subrounds; /* S_c, sub-rounds of a clustering pass [3] (Sec. 11)  */
     uint32_t lp_subrounds;      /* S_lp, sub-rounds of an LP round [5] (Sec. 11)       */
     uint32_t lp_rounds;         /* R_lp, maximum LP rounds per level [5]               */

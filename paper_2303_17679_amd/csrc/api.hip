@@ -15,7 +15,8 @@ hgp_status check_params(const hgp_params *p) {
     if (p->k < 2) return HGP_E_INVALID;
     if (p->k > 256) return HGP_E_UNSUPPORTED;
     if (p->eps_den == 0 || p->eps_den > (1u << 20) || p->eps_num > p->eps_den) return HGP_E_INVALID;
-    if (p->limit_factor == 0 || p->coarsen_subrounds == 0 || p->lp_subrounds == 0) return HGP_E_INVALID;
+    if (p->limit_factor == 0 || p->limit_factor > (1u << 20)) return HGP_E_INVALID;
+    if (p->coarsen_subrounds == 0 || p->lp_subrounds == 0) return HGP_E_INVALID;
     if (p->coarsen_subrounds > 256 || p->lp_subrounds > 256 || p->lp_rounds > 65535) return HGP_E_INVALID;
     return HGP_OK;
 }
@@ -81,10 +82,10 @@ hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p, const
             case HGP_OP_CONTRACT: need = contract_workspace(n, m, p); break;
             case HGP_OP_REFINE: need = refine_workspace(n, m, k); break;
             case HGP_OP_VALIDATE: need = util_workspace(n, m); break;
-            case HGP_OP_INITIAL: need = ip_workspace(n, k); break;
+            case HGP_OP_INITIAL: need = ip_workspace(n, p, k); break;
             case HGP_OP_PARTITION: {
                 size_t temp = std::max({coarsen_workspace(n, m, p, dp), contract_workspace(n, m, p),
-                                        refine_workspace(n, m, k), ip_workspace(n, k), util_workspace(n, m)});
+                                        refine_workspace(n, m, k), ip_workspace(n, p, k), util_workspace(n, m)});
                 // hierarchy: coarse levels are stored with the capacities of the
                 // level they come from; rep of the level being coarsened on top
                 size_t hier = 3 * level_bytes(n, m, p) + 4ull * n + 4096;

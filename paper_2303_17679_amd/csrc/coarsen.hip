@@ -35,6 +35,7 @@ struct RateArgs {
     const uint64_t *nscore;
     const uint32_t *rep;
     const int64_t *cw;
+    const int64_t *tinfo;  // cluster weight of a valid target, TINFO_BAD otherwise
     uint32_t *ptarget;
     int64_t *tsum;
     uint32_t *proposers;
@@ -42,10 +43,31 @@ struct RateArgs {
     uint64_t mseed;
     uint32_t level, r, S;
     int64_t cap_mult, W;
+    bool dedup;  // false in the first sub-round: every cluster is a singleton
 };
 
-__device__ inline bool better(uint64_t R1, uint64_t H1, uint32_t C1, uint64_t R2, uint64_t H2, uint32_t C2) {
+// Larger than any cluster weight (< 2^31) while cap_mult * (c(u) + TINFO_BAD)
+// stays far from overflow (cap_mult = limit_factor * k < 2^26).
+constexpr int64_t TINFO_BAD = (int64_t)1 << 34;
+
+// tinfo[C]: cw[C] if C may be joined in sub-round r, TINFO_BAD if C is itself
+// a candidate singleton of the sub-round (no chains within a sub-round).
+__global__ void k_target_info(const uint32_t *rep, const int64_t *cw, const int32_t *vwgt, uint32_t n,
+                              uint64_t mseed, uint32_t level, uint32_t S, uint32_t r, int64_t *tinfo) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        int64_t c = cw[v];
+        bool cand = rep[v] == v && c == (int64_t)vwgt[v] && tag_hash(mseed, 1, level, 0, v) % S == r;
+        tinfo[v] = cand ? TINFO_BAD : c;
+    }
+}
+
+// (R1, C1) better than (R2, C2): larger rating, then smaller tie hash, then
+// smaller ID.  The tie hash is computed only when the ratings are equal.
+__device__ inline bool better_lazy(const RateArgs &a, uint64_t R1, uint32_t C1, uint64_t R2, uint32_t C2) {
+    if (C2 == NONE) return C1 != NONE;
+    if (C1 == NONE) return false;
     if (R1 != R2) return R1 > R2;
+    uint64_t H1 = tag_hash(a.mseed, 2, a.level, 0, C1), H2 = tag_hash(a.mseed, 2, a.level, 0, C2);
     if (H1 != H2) return H1 < H2;
     return C1 < C2;
 }
@@ -54,14 +76,10 @@ __device__ inline uint32_t slot_hash(uint32_t C, int log2cap) {
     return (uint32_t)(C * 2654435761u) >> (32 - log2cap);
 }
 
-// Validity of target cluster C for candidate u (snapshot of the sub-round):
-// within c_max, and not itself a candidate singleton of this sub-round.
+// Validity of target cluster C for candidate u on the sub-round snapshot:
+// within c_max and not a candidate singleton of the same sub-round.
 __device__ inline bool valid_target(const RateArgs &a, uint32_t u, uint32_t C) {
-    int64_t cwc = a.cw[C];
-    if (a.cap_mult * ((int64_t)a.vwgt[u] + cwc) > a.W) return false;
-    bool cand = (a.rep[C] == C) && (cwc == (int64_t)a.vwgt[C]) &&
-                (tag_hash(a.mseed, 1, a.level, 0, C) % a.S == a.r);
-    return !cand && C != u;
+    return C != u && a.cap_mult * ((int64_t)a.vwgt[u] + a.tinfo[C]) <= a.W;
 }
 
 __device__ inline void publish(const RateArgs &a, uint32_t u, uint32_t C) {
@@ -75,6 +93,7 @@ __device__ inline void publish(const RateArgs &a, uint32_t u, uint32_t C) {
 
 // ---------------------------------------------------------------------------
 // Groups of G lanes (G <= 64), one candidate per group, LDS table of CAP.
+// Occupied slots are listed so that argmax and clearing touch only them.
 // ---------------------------------------------------------------------------
 template <int G, int CAP, int LOG2CAP>
 __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t *list, uint32_t count) {
@@ -82,62 +101,71 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
     __shared__ uint32_t keys[GPB][CAP];
     __shared__ uint32_t stamp[GPB][CAP];
     __shared__ uint64_t R[GPB][CAP];
+    __shared__ uint16_t occ[GPB][CAP];
+    __shared__ uint32_t nocc[GPB];
     const int g = threadIdx.x / G, l = threadIdx.x % G;
+    for (int s = l; s < CAP; s += G) { keys[g][s] = NONE; stamp[g][s] = NONE; R[g][s] = 0; }
+    if (l == 0) nocc[g] = 0;
+    wave_sync();
     // groups never synchronise with each other (each lives inside one wave),
     // so every group simply strides over the list
     for (uint32_t idx = blockIdx.x * GPB + g; idx < count; idx += gridDim.x * GPB) {
         const uint32_t u = list[idx];
         const bool active = a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u];  // not joined earlier
-        for (int s = l; s < CAP; s += G) { keys[g][s] = NONE; stamp[g][s] = NONE; R[g][s] = 0; }
-        wave_sync();
-        if (active) {
-            uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
-            for (uint32_t j = j0; j < j1; ++j) {
-                uint32_t e = a.inc[j];
-                uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
-                if (sz < 2) continue;
-                uint64_t sc = a.nscore[e];
-                for (uint32_t q = l; q < sz; q += G) {
-                    uint32_t v = a.pins[b + q];
-                    if (v == u) continue;
-                    uint32_t C = a.rep[v];
-                    uint32_t slot = slot_hash(C, LOG2CAP);
-                    for (;;) {
-                        uint32_t k = keys[g][slot];
-                        if (k == C) break;
-                        if (k == NONE) {
-                            uint32_t old = atomicCAS(&keys[g][slot], NONE, C);
-                            if (old == NONE || old == C) break;
+        if (!active) continue;  // uniform within the group
+        const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
+        for (uint32_t j = j0; j < j1; ++j) {
+            uint32_t e = a.inc[j];
+            uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+            if (sz < 2) continue;
+            uint64_t sc = a.nscore[e];
+            for (uint32_t q = l; q < sz; q += G) {
+                uint32_t v = a.pins[b + q];
+                if (v == u) continue;
+                uint32_t C = a.rep[v];
+                uint32_t slot = slot_hash(C, LOG2CAP);
+                for (;;) {
+                    uint32_t k = keys[g][slot];
+                    if (k == C) break;
+                    if (k == NONE) {
+                        uint32_t old = atomicCAS(&keys[g][slot], NONE, C);
+                        if (old == NONE) {
+                            occ[g][atomicAdd(&nocc[g], 1u)] = (uint16_t)slot;
+                            break;
                         }
-                        slot = (slot + 1) & (CAP - 1);
+                        if (old == C) break;
                     }
-                    uint32_t prev = atomicExch(&stamp[g][slot], e);
-                    if (prev != e) atomicAdd((unsigned long long *)&R[g][slot], (unsigned long long)sc);
+                    slot = (slot + 1) & (CAP - 1);
                 }
-                wave_sync();
+                if (!a.dedup || atomicExch(&stamp[g][slot], e) != e)
+                    atomicAdd((unsigned long long *)&R[g][slot], (unsigned long long)sc);
             }
+            wave_sync();
         }
         wave_sync();
-        uint64_t bR = 0, bH = ~0ull;
+        const uint32_t no = nocc[g];
+        uint64_t bR = 0;
         uint32_t bC = NONE;
-        if (active) {
-            for (int s = l; s < CAP; s += G) {
-                uint32_t C = keys[g][s];
-                if (C == NONE) continue;
-                uint64_t rc = R[g][s];
-                if (!valid_target(a, u, C)) continue;
-                uint64_t hc = tag_hash(a.mseed, 2, a.level, 0, C);
-                if (bC == NONE || better(rc, hc, C, bR, bH, bC)) { bR = rc; bH = hc; bC = C; }
-            }
+        for (uint32_t i = l; i < no; i += G) {
+            uint32_t slot = occ[g][i];
+            uint32_t C = keys[g][slot];
+            uint64_t rc = R[g][slot];
+            keys[g][slot] = NONE;  // leave the table clean for the next candidate
+            stamp[g][slot] = NONE;
+            R[g][slot] = 0;
+            if (valid_target(a, u, C) && better_lazy(a, rc, C, bR, bC)) { bR = rc; bC = C; }
         }
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) {
             uint64_t oR = __shfl_xor(bR, o, 64);
-            uint64_t oH = __shfl_xor(bH, o, 64);
             uint32_t oC = __shfl_xor(bC, o, 64);
-            if (oC != NONE && (bC == NONE || better(oR, oH, oC, bR, bH, bC))) { bR = oR; bH = oH; bC = oC; }
+            if (better_lazy(a, oR, oC, bR, bC)) { bR = oR; bC = oC; }
         }
-        if (active && l == 0) publish(a, u, bC);
+        wave_sync();
+        if (l == 0) {
+            publish(a, u, bC);
+            nocc[g] = 0;
+        }
         wave_sync();
     }
 }
@@ -154,7 +182,7 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
     __shared__ uint32_t lkeys[GLOBAL ? 1 : LCAP];
     __shared__ uint32_t lstamp[GLOBAL ? 1 : LCAP];
     __shared__ uint64_t lR[GLOBAL ? 1 : LCAP];
-    __shared__ uint64_t redR[BLOCK / WAVE], redH[BLOCK / WAVE];
+    __shared__ uint64_t redR[BLOCK / WAVE];
     __shared__ uint32_t redC[BLOCK / WAVE];
     uint32_t *keys = GLOBAL ? gkeys + (size_t)blockIdx.x * slice_cap : lkeys;
     uint32_t *stamp = GLOBAL ? gstamp + (size_t)blockIdx.x * slice_cap : lstamp;
@@ -204,12 +232,12 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
                     }
                     slot = (slot + 1) & (cap - 1);
                 }
-                uint32_t prev = atomicExch(&stamp[slot], e);
-                if (prev != e) atomicAdd((unsigned long long *)&R[slot], (unsigned long long)sc);
+                if (!a.dedup || atomicExch(&stamp[slot], e) != e)
+                    atomicAdd((unsigned long long *)&R[slot], (unsigned long long)sc);
             }
             __syncthreads();
         }
-        uint64_t bR = 0, bH = ~0ull;
+        uint64_t bR = 0;
         uint32_t bC = NONE;
         if (GLOBAL) __threadfence();
         for (uint32_t s = threadIdx.x; s < cap; s += BLOCK) {
@@ -218,25 +246,20 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
             uint32_t C = GLOBAL ? __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : keys[s];
             if (C == NONE) continue;
             uint64_t rc = GLOBAL ? __hip_atomic_load(&R[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : R[s];
-            if (!valid_target(a, u, C)) continue;
-            uint64_t hc = tag_hash(a.mseed, 2, a.level, 0, C);
-            if (bC == NONE || better(rc, hc, C, bR, bH, bC)) { bR = rc; bH = hc; bC = C; }
+            if (valid_target(a, u, C) && better_lazy(a, rc, C, bR, bC)) { bR = rc; bC = C; }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             uint64_t oR = __shfl_xor(bR, o, 64);
-            uint64_t oH = __shfl_xor(bH, o, 64);
             uint32_t oC = __shfl_xor(bC, o, 64);
-            if (oC != NONE && (bC == NONE || better(oR, oH, oC, bR, bH, bC))) { bR = oR; bH = oH; bC = oC; }
+            if (better_lazy(a, oR, oC, bR, bC)) { bR = oR; bC = oC; }
         }
         unsigned w = threadIdx.x / WAVE;
-        if (__lane_id() == 0) { redR[w] = bR; redH[w] = bH; redC[w] = bC; }
+        if (__lane_id() == 0) { redR[w] = bR; redC[w] = bC; }
         __syncthreads();
         if (threadIdx.x == 0) {
             for (int q = 1; q < BLOCK / WAVE; ++q)
-                if (redC[q] != NONE && (bC == NONE || better(redR[q], redH[q], redC[q], bR, bH, bC))) {
-                    bR = redR[q]; bH = redH[q]; bC = redC[q];
-                }
+                if (better_lazy(a, redR[q], redC[q], bR, bC)) { bR = redR[q]; bC = redC[q]; }
             publish(a, u, bC);
         }
         __syncthreads();
@@ -263,28 +286,59 @@ __device__ inline int rate_class(uint64_t B) {
 }
 
 // pass 1 (fill=false): count per (sub-round, class); pass 2: fill lists.
-__global__ void k_classify(const uint32_t *pin_off, const uint32_t *inc_off, const uint32_t *inc, uint32_t n,
-                           uint64_t mseed, uint32_t level, uint32_t S, const int32_t *vwgt,
-                           uint32_t *rep, int64_t *cw, int64_t *tsum, uint32_t *counts, uint32_t *cursor,
-                           uint32_t *lists, bool fill) {
-    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
-        uint64_t B = 0;
-        for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) {
-            uint32_t e = inc[j];
-            uint32_t sz = pin_off[e + 1] - pin_off[e];
-            if (sz >= 2) B += sz - 1;
+// Counters are aggregated per block in LDS (one global atomic per key and
+// block), so millions of vertices never contend on a handful of addresses.
+constexpr int MAX_KEYS = 256 * NCLASS;
+__global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *pin_off, const uint32_t *inc_off,
+                                                    const uint32_t *inc, uint32_t n, uint64_t mseed, uint32_t level,
+                                                    uint32_t S, const int32_t *vwgt, uint32_t *rep, int64_t *cw,
+                                                    int64_t *tsum, uint32_t *counts, uint32_t *cursor,
+                                                    uint32_t *lists, bool fill) {
+    __shared__ uint32_t lcnt[MAX_KEYS];
+    __shared__ uint32_t lbase[MAX_KEYS];
+    const uint32_t nkeys = S * NCLASS;
+    for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) lcnt[i] = 0;
+    __syncthreads();
+    for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
+        const uint32_t u = u0 + threadIdx.x;
+        int key = -1;
+        uint32_t lrank = 0;
+        if (u < n) {
+            uint64_t B = 0;
+            for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) {
+                uint32_t e = inc[j];
+                uint32_t sz = pin_off[e + 1] - pin_off[e];
+                if (sz >= 2) B += sz - 1;
+            }
+            int c = rate_class(B);
+            uint32_t r = (uint32_t)(tag_hash(mseed, 1, level, 0, u) % S);
+            if (!fill) {
+                rep[u] = u;
+                cw[u] = vwgt[u];
+                tsum[u] = 0;
+            }
+            if (c >= 0) {
+                key = (int)(r * NCLASS + c);
+                lrank = atomicAdd(&lcnt[key], 1u);
+            }
         }
-        int c = rate_class(B);
-        uint32_t r = (uint32_t)(tag_hash(mseed, 1, level, 0, u) % S);
-        if (!fill) {
-            rep[u] = u;
-            cw[u] = vwgt[u];
-            tsum[u] = 0;
-            if (c >= 0) atomicAdd(&counts[r * NCLASS + c], 1u);
-        } else if (c >= 0) {
-            uint32_t pos = atomicAdd(&cursor[r * NCLASS + c], 1u);
-            lists[pos] = u;
+        if (fill) {
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) {
+                uint32_t c = lcnt[i];
+                lbase[i] = c ? atomicAdd(&cursor[i], c) : 0u;
+            }
+            __syncthreads();
+            if (key >= 0) lists[lbase[key] + lrank] = u;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) lcnt[i] = 0;
+            __syncthreads();
         }
+    }
+    if (!fill) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK)
+            if (lcnt[i]) atomicAdd(&counts[i], lcnt[i]);
     }
 }
 
@@ -383,7 +437,7 @@ __global__ void k_apply_joins(const uint32_t *proposers, uint32_t np, const uint
 // ---------------------------------------------------------------------------
 struct CoarsenBufs {
     uint64_t *nscore;
-    int64_t *cw, *tsum;
+    int64_t *cw, *tsum, *tinfo;
     uint32_t *ptarget, *proposers, *slow, *lists, *counts, *cursor, *scal;
     uint8_t *ok;
     uint64_t *keys, *keys_alt, *incl;
@@ -398,6 +452,7 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t S, CoarsenBufs &B) {
     B.nscore = A.alloc<uint64_t>(m);
     B.cw = A.alloc<int64_t>(n);
     B.tsum = A.alloc<int64_t>(n);
+    B.tinfo = A.alloc<int64_t>(n);
     B.ptarget = A.alloc<uint32_t>(n);
     B.proposers = A.alloc<uint32_t>(n);
     B.slow = A.alloc<uint32_t>(n);
@@ -469,8 +524,11 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     HGP_CHECK_HIP(hipMemcpyAsync(ncl, &cnt, sizeof(uint32_t), hipMemcpyHostToDevice, st));
     for (uint32_t r = 0; r < S; ++r) {
         HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 2, st));
-        RateArgs a{h.pin_off, h.pins, h.inc_off, h.inc, h.vwgt, B.nscore, rep, B.cw, B.ptarget, B.tsum,
-                   B.proposers, nprop, mseed, level, r, S, cap_mult, W};
+        k_target_info<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(rep, B.cw, h.vwgt, n, mseed, level, S, r,
+                                                                        B.tinfo);
+        HGP_LAUNCH_CHECK();
+        RateArgs a{h.pin_off, h.pins, h.inc_off, h.inc, h.vwgt, B.nscore, rep, B.cw, B.tinfo, B.ptarget, B.tsum,
+                   B.proposers, nprop, mseed, level, r, S, cap_mult, W, r > 0};
         for (int c = 0; c < NCLASS; ++c) {
             uint32_t cntc = counts[r * NCLASS + c];
             if (!cntc) continue;

@@ -4,12 +4,14 @@
 //
 // Order: breadth-first from the smallest unvisited vertex, neighbours taken
 // in ascending incident-net order and, inside a net, ascending pin order.
-// One workgroup computes it exactly, one BFS level at a time: every
-// occurrence of an unvisited vertex in the expansion of the frontier gets the
-// key (frontier position, offset in that vertex's expansion); the vertex
-// joins the next frontier at its smallest key, and the new frontier is laid
-// out in key order by a block scan (frontier vertices are processed in order
-// and each one's occurrences in order, so key order = thread order).
+// The order is built one BFS layer at a time with device-wide kernels: the
+// (frontier vertex, incident net) pairs of a layer are numbered by a scan
+// of the frontier degrees; every occurrence of an unvisited vertex gets the
+// key (frontier position, offset in that vertex's expansion), so a vertex
+// joins the next layer at its smallest key; winners are counted per pair and
+// laid out in pair order by a second scan, which is exactly key order.
+// Vertices without incident nets can never be reached and are appended in
+// ID order whenever the search passes them.
 // Fill: block b covers positions [S_b, S_{b+1}) of the order, where
 // S_{b+1} = 1 + first i >= S_b with weight(S_b..i) >= ceil(c(V)/k); the S_b
 // are found by pointer doubling over next(s), the last block takes the rest.
@@ -18,117 +20,119 @@
 
 namespace hgp {
 
-constexpr int BFS_THREADS = 1024;
-
-__device__ inline uint64_t aload(const uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// expansion offset of every incidence entry: sum of the sizes of the
+// earlier nets of the same vertex
+__global__ void k_exoff(const uint32_t *pin_off, const uint32_t *inc_off, const uint32_t *inc, uint32_t n,
+                        uint32_t *exoff) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        uint32_t acc = 0;
+        for (uint32_t j = inc_off[v]; j < inc_off[v + 1]; ++j) {
+            exoff[j] = acc;
+            uint32_t e = inc[j];
+            acc += pin_off[e + 1] - pin_off[e];
+        }
+    }
 }
 
-__global__ __launch_bounds__(BFS_THREADS) void k_bfs(const uint32_t *pin_off, const uint32_t *pins,
-                                                     const uint32_t *inc_off, const uint32_t *inc, uint32_t n,
-                                                     uint32_t *order, uint32_t *visited, unsigned long long *key) {
-    __shared__ uint32_t s_found;
-    __shared__ uint32_t wsum[BFS_THREADS / WAVE];
-    const uint32_t tid = threadIdx.x;
-    uint32_t pos = 0, next_start = 0;
-    while (pos < n) {
-        // smallest unvisited vertex >= next_start
-        for (uint32_t base = next_start;; base += BFS_THREADS) {
-            if (tid == 0) s_found = NONE;
-            __syncthreads();
-            uint32_t idx = base + tid;
-            if (idx < n && __hip_atomic_load(&visited[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-                atomicMin(&s_found, idx);
-            __syncthreads();
-            uint32_t f = s_found;
-            __syncthreads();
-            if (f != NONE || base + BFS_THREADS >= n) {
-                next_start = f;
-                break;
+// smallest unvisited vertex with incident nets in [from, n) -> *out (preset n)
+__global__ void k_find_start(const uint32_t *inc_off, const uint32_t *visited, uint32_t from, uint32_t n,
+                             uint32_t *out) {
+    for (uint32_t v = from + blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (!visited[v] && inc_off[v + 1] > inc_off[v]) atomicMin(out, v);
+}
+
+struct Unvisited {
+    const uint32_t *visited;
+    uint32_t from;
+    __device__ uint32_t operator()(size_t i) const { return visited[from + i] ? 0u : 1u; }
+};
+struct AppendOrder {
+    const uint32_t *visited;
+    uint32_t *order, *vis_w;
+    uint32_t from, pos;
+    __device__ void operator()(size_t i, uint32_t excl, uint32_t v) const {
+        if (v) order[pos + excl] = from + (uint32_t)i;
+    }
+};
+
+__global__ void k_mark_range(const uint32_t *order, uint32_t a, uint32_t b, uint32_t *visited,
+                             unsigned long long *key) {
+    for (uint32_t i = a + blockIdx.x * blockDim.x + threadIdx.x; i < b; i += gridDim.x * blockDim.x) {
+        uint32_t w = order[i];
+        visited[w] = 1;
+        key[w] = ~0ull;
+    }
+}
+
+__global__ void k_put_start(uint32_t *order, uint32_t pos, const uint32_t *start, uint32_t *visited) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t s = *start;
+        order[pos] = s;
+        visited[s] = 1;
+    }
+}
+
+struct FrontierDeg {
+    const uint32_t *order, *inc_off;
+    uint32_t fs;
+    __device__ uint32_t operator()(size_t i) const {
+        uint32_t v = order[fs + i];
+        return inc_off[v + 1] - inc_off[v];
+    }
+};
+
+// flat pair t -> (frontier index fi, incidence index jj)
+__device__ inline void pair_of(const uint32_t *D, uint32_t F, uint32_t t, const uint32_t *order, uint32_t fs,
+                               const uint32_t *inc_off, uint32_t &fi, uint32_t &jj) {
+    uint32_t lo = 0, hi = F - 1;  // largest fi with D[fi] <= t
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) >> 1;
+        if (D[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    fi = lo;
+    jj = inc_off[order[fs + fi]] + (t - D[fi]);
+}
+
+__global__ void k_bfs_keys(const uint32_t *D, uint32_t F, const uint32_t *Tdev, const uint32_t *order, uint32_t fs,
+                           const uint32_t *inc_off, const uint32_t *inc, const uint32_t *pin_off,
+                           const uint32_t *pins, const uint32_t *exoff, const uint32_t *visited,
+                           unsigned long long *key) {
+    const uint32_t T = *Tdev;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+        uint32_t fi, jj;
+        pair_of(D, F, t, order, fs, inc_off, fi, jj);
+        uint32_t e = inc[jj];
+        uint64_t base = ((uint64_t)fi << 32) | exoff[jj];
+        uint32_t b = pin_off[e];
+        for (uint32_t q = b; q < pin_off[e + 1]; ++q) {
+            uint32_t w = pins[q];
+            if (!visited[w]) atomicMin(&key[w], (unsigned long long)(base + (q - b)));
+        }
+    }
+}
+
+// winners of pair t: count (write=false) or append in key order (write=true)
+__global__ void k_bfs_winners(const uint32_t *D, uint32_t F, const uint32_t *Tdev, const uint32_t *order,
+                              uint32_t fs, const uint32_t *inc_off, const uint32_t *inc, const uint32_t *pin_off,
+                              const uint32_t *pins, const uint32_t *exoff, const uint32_t *visited,
+                              const unsigned long long *key, uint32_t *cnt, uint32_t *order_out, uint32_t pos,
+                              bool write) {
+    const uint32_t T = *Tdev;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+        uint32_t fi, jj;
+        pair_of(D, F, t, order, fs, inc_off, fi, jj);
+        uint32_t e = inc[jj];
+        uint64_t base = ((uint64_t)fi << 32) | exoff[jj];
+        uint32_t b = pin_off[e];
+        uint32_t c = 0, wp = write ? pos + cnt[t] : 0;
+        for (uint32_t q = b; q < pin_off[e + 1]; ++q) {
+            uint32_t w = pins[q];
+            if (!visited[w] && key[w] == base + (q - b)) {
+                if (write) order_out[wp + c] = w;
+                ++c;
             }
         }
-        const uint32_t start = next_start;  // exists because pos < n
-        if (start == NONE) break;            // unreachable for a consistent input
-        next_start = start + 1;
-        if (tid == 0) {
-            __hip_atomic_store(&visited[start], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            order[pos] = start;
-        }
-        uint32_t fstart = pos, fend = pos + 1;
-        pos += 1;
-        __syncthreads();
-        while (fstart < fend) {
-            // phase 1: smallest key of every unvisited vertex reached
-            for (uint32_t c = fstart; c < fend; c += BFS_THREADS) {
-                uint32_t fi = c + tid;
-                if (fi < fend) {
-                    uint32_t v = order[fi];
-                    uint64_t hi = (uint64_t)(fi - fstart) << 32;
-                    uint32_t off = 0;
-                    for (uint32_t j = inc_off[v]; j < inc_off[v + 1]; ++j) {
-                        uint32_t e = inc[j];
-                        for (uint32_t q = pin_off[e]; q < pin_off[e + 1]; ++q, ++off) {
-                            uint32_t w = pins[q];
-                            if (__hip_atomic_load(&visited[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-                                atomicMin(&key[w], (unsigned long long)(hi | off));
-                        }
-                    }
-                }
-            }
-            __threadfence();
-            __syncthreads();
-            // phase 2: winners appended in key order
-            uint32_t newpos = pos;
-            for (uint32_t c = fstart; c < fend; c += BFS_THREADS) {
-                uint32_t fi = c + tid;
-                uint32_t cnt = 0;
-                uint32_t v = 0;
-                uint64_t hi = (uint64_t)(fi - fstart) << 32;
-                if (fi < fend) {
-                    v = order[fi];
-                    uint32_t off = 0;
-                    for (uint32_t j = inc_off[v]; j < inc_off[v + 1]; ++j) {
-                        uint32_t e = inc[j];
-                        for (uint32_t q = pin_off[e]; q < pin_off[e + 1]; ++q, ++off) {
-                            uint32_t w = pins[q];
-                            if (__hip_atomic_load(&visited[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-                                aload((const uint64_t *)&key[w]) == (hi | off))
-                                ++cnt;
-                        }
-                    }
-                }
-                uint32_t tot;
-                uint32_t incl = block_incl_scan_n<uint32_t, BFS_THREADS>(cnt, wsum, &tot);
-                uint32_t wpos = newpos + incl - cnt;
-                if (fi < fend && cnt) {
-                    uint32_t off = 0;
-                    for (uint32_t j = inc_off[v]; j < inc_off[v + 1]; ++j) {
-                        uint32_t e = inc[j];
-                        for (uint32_t q = pin_off[e]; q < pin_off[e + 1]; ++q, ++off) {
-                            uint32_t w = pins[q];
-                            if (__hip_atomic_load(&visited[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-                                aload((const uint64_t *)&key[w]) == (hi | off))
-                                order[wpos++] = w;
-                        }
-                    }
-                }
-                newpos += tot;
-                __syncthreads();
-            }
-            __threadfence();
-            __syncthreads();
-            // phase 3: mark the new frontier visited, reset keys
-            for (uint32_t i = pos + tid; i < newpos; i += BFS_THREADS) {
-                uint32_t w = order[i];
-                __hip_atomic_store(&visited[w], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                atomicExch(&key[w], ~0ull);
-            }
-            __threadfence();
-            __syncthreads();
-            fstart = fend;
-            fend = newpos;
-            pos = newpos;
-        }
+        if (!write) cnt[t] = c;
     }
 }
 
@@ -187,39 +191,101 @@ __global__ void k_project(uint32_t n, const uint32_t *cid, const uint32_t *cpart
 }
 
 struct IpBufs {
-    uint32_t *order, *visited, *J, *S;
+    uint32_t *order, *visited, *J, *S, *exoff, *D, *cnt, *scal;
     unsigned long long *key;
     uint64_t *P;
 };
 
-static void plan(Arena &A, uint32_t n, uint32_t k, IpBufs &B) {
+static void plan(Arena &A, uint32_t n, uint32_t p, uint32_t k, IpBufs &B) {
     B.order = A.alloc<uint32_t>(n);
     B.visited = A.alloc<uint32_t>(n);
     B.key = A.alloc<unsigned long long>(n);
     B.P = A.alloc<uint64_t>(n);
     B.J = A.alloc<uint32_t>((size_t)8 * (n + 1));
     B.S = A.alloc<uint32_t>(k);
+    B.exoff = A.alloc<uint32_t>(p);
+    B.D = A.alloc<uint32_t>(n);
+    B.cnt = A.alloc<uint32_t>((size_t)p + 1);
+    B.scal = A.alloc<uint32_t>(8);
     scan_reserve<uint64_t>(A, n);
+    scan_reserve<uint32_t>(A, (size_t)p + 1);
 }
 
-size_t ip_workspace(uint32_t n, uint32_t k) {
+size_t ip_workspace(uint32_t n, uint32_t p, uint32_t k) {
     Arena A(nullptr, 0);
     IpBufs B;
-    plan(A, n, k, B);
+    plan(A, n, p, k, B);
     return A.peak;
+}
+
+static uint32_t read_u32(const uint32_t *d, hipStream_t st) {
+    uint32_t h = 0;
+    HGP_CHECK_HIP(hipMemcpyAsync(&h, d, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    return h;
 }
 
 void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st) {
     const uint32_t n = h.n;
     size_t mk = A.mark();
     IpBufs B;
-    plan(A, n, k, B);
+    plan(A, n, h.p, k, B);
     const int64_t W = total_weight(h.vwgt, n, A, st);
     const uint64_t T = (uint64_t)((W + k - 1) / k);
+    uint32_t *d_start = B.scal + 0, *d_cnt = B.scal + 1, *d_T = B.scal + 2, *d_W = B.scal + 3;
     HGP_CHECK_HIP(hipMemsetAsync(B.visited, 0, sizeof(uint32_t) * n, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.key, 0xFF, sizeof(unsigned long long) * n, st));
-    k_bfs<<<1, BFS_THREADS, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, n, B.order, B.visited, B.key);
+    k_exoff<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, B.exoff);
     HGP_LAUNCH_CHECK();
+    uint32_t pos = 0, next = 0;
+    while (pos < n) {
+        // next start vertex with incident nets; unreachable vertices before it join in ID order
+        HGP_CHECK_HIP(hipMemcpyAsync(d_start, &n, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        k_find_start<<<grid_for(n - next, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, B.visited, next, n,
+                                                                               d_start);
+        HGP_LAUNCH_CHECK();
+        const uint32_t s = read_u32(d_start, st);
+        if (s > next) {
+            scan_apply<uint32_t>(A, s - next, Unvisited{B.visited, next},
+                                 AppendOrder{B.visited, B.order, nullptr, next, pos}, d_cnt, st);
+            const uint32_t c = read_u32(d_cnt, st);
+            k_mark_range<<<grid_for(c, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.order, pos, pos + c, B.visited, B.key);
+            HGP_LAUNCH_CHECK();
+            pos += c;
+        }
+        if (s >= n) break;
+        k_put_start<<<1, 64, 0, st>>>(B.order, pos, d_start, B.visited);
+        HGP_LAUNCH_CHECK();
+        uint32_t fs = pos, fe = pos + 1;
+        pos += 1;
+        next = s + 1;
+        while (fs < fe) {
+            const uint32_t F = fe - fs;
+            scan_apply<uint32_t>(A, F, FrontierDeg{B.order, h.inc_off, fs}, StoreExcl<uint32_t>{B.D}, d_T, st);
+            const uint32_t Tn = read_u32(d_T, st);
+            if (Tn == 0) break;
+            const unsigned g = grid_for(Tn, BLOCK, FILL_BLOCKS);
+            k_bfs_keys<<<g, BLOCK, 0, st>>>(B.D, F, d_T, B.order, fs, h.inc_off, h.inc, h.pin_off, h.pins, B.exoff,
+                                            B.visited, B.key);
+            HGP_LAUNCH_CHECK();
+            k_bfs_winners<<<g, BLOCK, 0, st>>>(B.D, F, d_T, B.order, fs, h.inc_off, h.inc, h.pin_off, h.pins,
+                                               B.exoff, B.visited, B.key, B.cnt, B.order, pos, false);
+            HGP_LAUNCH_CHECK();
+            exclusive_scan<uint32_t>(A, B.cnt, B.cnt, Tn, d_W, st);
+            k_bfs_winners<<<g, BLOCK, 0, st>>>(B.D, F, d_T, B.order, fs, h.inc_off, h.inc, h.pin_off, h.pins,
+                                               B.exoff, B.visited, B.key, B.cnt, B.order, pos, true);
+            HGP_LAUNCH_CHECK();
+            const uint32_t Wn = read_u32(d_W, st);
+            if (Wn) {
+                k_mark_range<<<grid_for(Wn, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.order, pos, pos + Wn, B.visited,
+                                                                                B.key);
+                HGP_LAUNCH_CHECK();
+            }
+            fs = pos;
+            fe = pos + Wn;
+            pos += Wn;
+        }
+    }
     scan_apply<uint64_t>(A, n, OrderWeight{B.order, h.vwgt}, StoreInclP{B.P}, (uint64_t *)nullptr, st);
     k_next<<<grid_for((size_t)n + 1, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.P, n, T, B.J);
     HGP_LAUNCH_CHECK();

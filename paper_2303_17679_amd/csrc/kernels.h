@@ -29,7 +29,7 @@ void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t 
                Arena &A, hipStream_t st);
 
 // ip.hip
-size_t ip_workspace(uint32_t n, uint32_t k);
+size_t ip_workspace(uint32_t n, uint32_t p, uint32_t k);
 void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st);
 void project(uint32_t n, const uint32_t *cid, const uint32_t *cpart, uint32_t *part, hipStream_t st);
 

@@ -160,128 +160,141 @@ struct GainArgs {
     const uint64_t *lam, *lam1;
     const uint32_t *part;
     const int64_t *bw;
+    const uint32_t *bstamp;
+    uint32_t stamp;
     int64_t lmax;
     uint64_t mseed;
     uint32_t level, round, sub, S, n;
     uint32_t *prop_t, *prop_g, *plist, *nprop, *gmax;
 };
 
+// Called by every lane of the wave (uniformly); `has` is set by at most one
+// lane per proposing vertex.
 __device__ inline void propose(const GainArgs &a, uint32_t u, uint32_t t, uint32_t g, bool has) {
     uint32_t pos = warp_agg_append(a.nprop, has);
     if (has) {
         a.plist[pos] = u;
         a.prop_t[u] = t;
         a.prop_g[u] = g;
-        atomicMax(a.gmax, g);
+    }
+    uint32_t gm = has ? g : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t x = __shfl_xor(gm, o, 64);
+        gm = x > gm ? x : gm;
+    }
+    if (__lane_id() == 0 && gm) atomicMax(a.gmax, gm);
+}
+
+template <int G, class T>
+__device__ inline T group_sum(T v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Boundary nodes of the snapshot: pins of nets with lambda > 1.  Other nodes
+// have no move of positive gain (all their nets lie in their own block).
+template <int KW>
+__global__ void k_mark_boundary(const uint32_t *pin_off, const uint32_t *pins, uint32_t m, const uint64_t *lam,
+                                uint32_t *bstamp, uint32_t stamp) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+        if (popc_bits<KW>(lam + (size_t)e * KW) < 2) continue;
+        for (uint32_t j = pin_off[e]; j < pin_off[e + 1]; ++j) bstamp[pins[j]] = stamp;
     }
 }
 
-template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_gains_thread(GainArgs a) {
-    for (uint32_t u0 = blockIdx.x * blockDim.x; u0 < a.n; u0 += gridDim.x * blockDim.x) {
-        uint32_t u = u0 + threadIdx.x;
-        bool has = false;
-        uint32_t best_t = NONE, best_g = 0;
-        if (u < a.n && tag_hash(a.mseed, 3, a.level, a.round, u) % a.S == a.sub) {
-            uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
-            if (j1 - j0 <= 64) {
-                uint32_t s = a.part[u];
-                int64_t bu = 0, wI = 0;
-                uint64_t U[KW];
+// Groups of G lanes per node (G = 1, 8 or 64 by degree class); the lanes of a
+// group split the incident nets.  Best move: largest positive gain among the
+// blocks of the union of Lambda(e), ties to the smaller block.
+template <int KW, int G>
+__global__ __launch_bounds__(BLOCK) void k_gains_group(GainArgs a, const uint32_t *list, uint32_t count) {
+    constexpr int GPB = BLOCK / G;
+    const uint32_t g = threadIdx.x / G, l = threadIdx.x % G;
+    for (uint32_t base = blockIdx.x * GPB; base < count; base += gridDim.x * GPB) {
+        const uint32_t idx = base + g;
+        uint32_t u = 0, best_t = NONE, best_g = 0;
+        bool act = idx < count;
+        if (act) {
+            u = list[idx];
+            act = a.bstamp[u] == a.stamp && tag_hash(a.mseed, 3, a.level, a.round, u) % a.S == a.sub;
+        }
+        if (act) {  // uniform within the group
+            const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
+            const uint32_t s = a.part[u];
+            int64_t bu = 0, wI = 0;
+            uint64_t U[KW];
 #pragma unroll
-                for (int q = 0; q < KW; ++q) U[q] = 0;
-                for (uint32_t j = j0; j < j1; ++j) {
-                    uint32_t e = a.inc[j];
-                    int64_t w = a.nwgt[e];
-                    wI += w;
-                    if ((a.lam1[(size_t)e * KW + (s >> 6)] >> (s & 63)) & 1ull) bu += w;
+            for (int q = 0; q < KW; ++q) U[q] = 0;
+            for (uint32_t j = j0 + l; j < j1; j += G) {
+                uint32_t e = a.inc[j];
+                int64_t w = a.nwgt[e];
+                wI += w;
+                if ((a.lam1[(size_t)e * KW + (s >> 6)] >> (s & 63)) & 1ull) bu += w;
 #pragma unroll
-                    for (int q = 0; q < KW; ++q) U[q] |= a.lam[(size_t)e * KW + q];
-                }
-                U[s >> 6] &= ~(1ull << (s & 63));
-                const int64_t cu = a.vwgt[u];
+                for (int q = 0; q < KW; ++q) U[q] |= a.lam[(size_t)e * KW + q];
+            }
+            bu = group_sum<G>(bu);
+            wI = group_sum<G>(wI);
 #pragma unroll
-                for (int q = 0; q < KW; ++q) {
-                    uint64_t x = U[q];
-                    while (x) {
-                        int bit = __ffsll((long long)x) - 1;
-                        x &= x - 1;
-                        uint32_t t = (uint32_t)(q * 64 + bit);
-                        if (a.bw[t] + cu > a.lmax) continue;
-                        int64_t aff = 0;
-                        for (uint32_t j = j0; j < j1; ++j) {
-                            uint32_t e = a.inc[j];
-                            if ((a.lam[(size_t)e * KW + q] >> bit) & 1ull) aff += a.nwgt[e];
-                        }
-                        int64_t g = bu - (wI - aff);
-                        if (g > (int64_t)best_g) { best_g = (uint32_t)g; best_t = t; }
+            for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+                for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
+            U[s >> 6] &= ~(1ull << (s & 63));
+            const int64_t cu = a.vwgt[u];
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                uint64_t x = U[q];
+                while (x) {
+                    int bit = __ffsll((long long)x) - 1;
+                    x &= x - 1;
+                    uint32_t t = (uint32_t)(q * 64 + bit);
+                    if (a.bw[t] + cu > a.lmax) continue;
+                    int64_t aff = 0;
+                    for (uint32_t j = j0 + l; j < j1; j += G) {
+                        uint32_t e = a.inc[j];
+                        if ((a.lam[(size_t)e * KW + q] >> bit) & 1ull) aff += a.nwgt[e];
                     }
+                    aff = group_sum<G>(aff);
+                    int64_t gn = bu - (wI - aff);
+                    if (gn > (int64_t)best_g) { best_g = (uint32_t)gn; best_t = t; }
                 }
-                has = best_t != NONE;
             }
         }
-        propose(a, u, best_t, best_g, has);
+        propose(a, u, best_t, best_g, act && l == 0 && best_t != NONE);
     }
 }
 
-// Wave per vertex of degree > 64 (list built once per level).
-template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_gains_wave(GainArgs a, const uint32_t *list, uint32_t count) {
-    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    const uint32_t nw = gridDim.x * blockDim.x / WAVE;
-    const unsigned l = __lane_id();
-    for (uint32_t idx = wid; idx < count; idx += nw) {
-        uint32_t u = list[idx];
-        if (tag_hash(a.mseed, 3, a.level, a.round, u) % a.S != a.sub) continue;
-        uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
-        uint32_t s = a.part[u];
-        int64_t bu = 0, wI = 0;
-        uint64_t U[KW];
-#pragma unroll
-        for (int q = 0; q < KW; ++q) U[q] = 0;
-        for (uint32_t j = j0 + l; j < j1; j += WAVE) {
-            uint32_t e = a.inc[j];
-            int64_t w = a.nwgt[e];
-            wI += w;
-            if ((a.lam1[(size_t)e * KW + (s >> 6)] >> (s & 63)) & 1ull) bu += w;
-#pragma unroll
-            for (int q = 0; q < KW; ++q) U[q] |= a.lam[(size_t)e * KW + q];
-        }
-        bu = wave_sum(bu);
-        wI = wave_sum(wI);
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1)
-#pragma unroll
-            for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
-        U[s >> 6] &= ~(1ull << (s & 63));
-        const int64_t cu = a.vwgt[u];
-        uint32_t best_t = NONE, best_g = 0;
-#pragma unroll
-        for (int q = 0; q < KW; ++q) {
-            uint64_t x = U[q];
-            while (x) {
-                int bit = __ffsll((long long)x) - 1;
-                x &= x - 1;
-                uint32_t t = (uint32_t)(q * 64 + bit);
-                if (a.bw[t] + cu > a.lmax) continue;
-                int64_t aff = 0;
-                for (uint32_t j = j0 + l; j < j1; j += WAVE) {
-                    uint32_t e = a.inc[j];
-                    if ((a.lam[(size_t)e * KW + q] >> bit) & 1ull) aff += a.nwgt[e];
-                }
-                aff = wave_sum(aff);
-                int64_t g = bu - (wI - aff);
-                if (g > (int64_t)best_g) { best_g = (uint32_t)g; best_t = t; }
+// Degree classes (<= 8, <= 64, larger): count pass, then fill pass.
+__global__ __launch_bounds__(BLOCK) void k_deg_classify(const uint32_t *inc_off, uint32_t n, uint32_t *counts,
+                                                        uint32_t *cursor, uint32_t *lists, bool fill) {
+    __shared__ uint32_t lcnt[3], lbase[3];
+    if (threadIdx.x < 3) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
+        const uint32_t u = u0 + threadIdx.x;
+        int key = -1;
+        uint32_t lrank = 0;
+        if (u < n) {
+            uint32_t d = inc_off[u + 1] - inc_off[u];
+            if (d > 0) {
+                key = d <= 8 ? 0 : (d <= 64 ? 1 : 2);
+                lrank = atomicAdd(&lcnt[key], 1u);
             }
         }
-        bool has = (l == 0) && best_t != NONE;
-        if (l == 0 && has) {
-            uint32_t pos = atomicAdd(a.nprop, 1u);
-            a.plist[pos] = u;
-            a.prop_t[u] = best_t;
-            a.prop_g[u] = best_g;
-            atomicMax(a.gmax, best_g);
+        if (fill) {
+            __syncthreads();
+            if (threadIdx.x < 3) lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], lcnt[threadIdx.x]) : 0u;
+            __syncthreads();
+            if (key >= 0) lists[lbase[key] + lrank] = u;
+            __syncthreads();
+            if (threadIdx.x < 3) lcnt[threadIdx.x] = 0;
+            __syncthreads();
         }
+    }
+    if (!fill) {
+        __syncthreads();
+        if (threadIdx.x < 3 && lcnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], lcnt[threadIdx.x]);
     }
 }
 
@@ -407,13 +420,19 @@ __global__ void k_lp_select(const uint64_t *keys, uint32_t np, KeyLayout L, uint
     }
 }
 
-__global__ void k_lp_apply(const uint64_t *keys, const uint32_t *vals, uint32_t np, KeyLayout L, uint32_t k,
-                           const uint32_t *seg_start, const unsigned long long *best, const int32_t *vwgt,
-                           const uint32_t *inc_off, const uint32_t *inc, uint32_t *part, int64_t *bw,
-                           uint32_t *tstamp, uint32_t stamp, uint32_t *tlist, uint32_t *ntouched,
-                           uint32_t *moves) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ((np + 63) / 64) * 64; i += gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(BLOCK) void k_lp_apply(const uint64_t *keys, const uint32_t *vals, uint32_t np,
+                                                    KeyLayout L, uint32_t k, const uint32_t *seg_start,
+                                                    const unsigned long long *best, const int32_t *vwgt,
+                                                    const uint32_t *inc_off, const uint32_t *inc, uint32_t *part,
+                                                    int64_t *bw, uint32_t *tstamp, uint32_t stamp, uint32_t *tlist,
+                                                    uint32_t *ntouched, uint32_t *moves) {
+    __shared__ int64_t dbw[256];
+    for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
+    __syncthreads();
+    for (uint32_t base = blockIdx.x * BLOCK; base < np; base += gridDim.x * BLOCK) {
+        const uint32_t i = base + threadIdx.x;
         bool mv = false;
+        uint32_t u = 0, j0 = 0, deg = 0;
         if (i < np) {
             uint64_t key = keys[i];
             uint32_t s = (uint32_t)(key >> L.sh_s) & L.kmask;
@@ -428,23 +447,238 @@ __global__ void k_lp_apply(const uint64_t *keys, const uint32_t *vals, uint32_t 
                 mv = (s == x) ? (loc < istar) : (loc < jstar);
             }
             if (mv) {
-                uint32_t u = vals[i];
+                u = vals[i];
                 part[u] = t;
                 int64_t c = vwgt[u];
-                atomic_add_i64(&bw[s], -c);
-                atomic_add_i64(&bw[t], c);
-                for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) {
-                    uint32_t e = inc[j];
-                    if (atomicExch(&tstamp[e], stamp) != stamp) {
-                        uint32_t pos = atomicAdd(ntouched, 1u);
-                        tlist[pos] = e;
+                atomicAdd((unsigned long long *)&dbw[s], (unsigned long long)(-c));
+                atomicAdd((unsigned long long *)&dbw[t], (unsigned long long)c);
+                j0 = inc_off[u];
+                deg = inc_off[u + 1] - j0;
+            }
+        }
+        uint64_t mm = __ballot(mv);
+        if (__lane_id() == 0 && mm) atomicAdd(moves, (uint32_t)__popcll(mm));
+        // touched nets, one wave-aggregated append per incidence column
+        uint32_t maxdeg = deg;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            uint32_t x = __shfl_xor(maxdeg, o, 64);
+            maxdeg = x > maxdeg ? x : maxdeg;
+        }
+        for (uint32_t j = 0; j < maxdeg; ++j) {
+            bool fresh = false;
+            uint32_t e = 0;
+            if (j < deg) {
+                e = inc[j0 + j];
+                fresh = atomicExch(&tstamp[e], stamp) != stamp;
+            }
+            uint32_t pos = warp_agg_append(ntouched, fresh);
+            if (fresh) tlist[pos] = e;
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < k; b += BLOCK)
+        if (dbw[b]) atomic_add_i64(&bw[b], dbw[b]);
+}
+
+// ---------------------------------------------------------------------------
+// Small sub-rounds: one workgroup does sort, prefix sums, selection and apply
+// in LDS (one launch instead of ~35).  Requires np <= FUSED_MAX and the full
+// key (s, t, G-g, u) to fit in 64 bits.
+// ---------------------------------------------------------------------------
+constexpr int FUSED_MAX = 4096;
+constexpr int FUSED_THREADS = 1024;
+
+__device__ inline uint32_t lower_pair(const uint64_t *skey, uint32_t np, int sh_t, uint64_t target) {
+    uint32_t lo = 0, hi = np;  // first j with (skey[j] >> sh_t) >= target
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if ((skey[mid] >> sh_t) < target) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+struct LSeg {
+    uint32_t start, len;
+    uint32_t base;
+    const uint32_t *incl;
+    __device__ uint32_t excl(uint32_t i) const { return i == 0 ? 0u : incl[start + i - 1] - base; }
+};
+
+__device__ inline uint32_t lcount_below(const LSeg &v, uint32_t x, bool strict) {
+    uint32_t lo = 0, hi = v.len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        uint32_t e = v.excl(mid);
+        bool below = strict ? (e < x) : (e <= x);
+        if (below) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(FUSED_THREADS) void k_lp_fused(const uint32_t *plist, uint32_t np, const uint32_t *prop_t,
+                                                            const uint32_t *prop_g, KeyLayout L, uint32_t k,
+                                                            const int32_t *vwgt, const uint32_t *inc_off,
+                                                            const uint32_t *inc, uint32_t *part, int64_t *bw,
+                                                            int64_t lmax, uint32_t *tstamp, uint32_t stamp,
+                                                            uint32_t *tlist, uint32_t *ntouched, uint32_t *moves) {
+    __shared__ uint64_t skey[FUSED_MAX];
+    __shared__ uint32_t sval[FUSED_MAX];
+    __shared__ uint32_t sincl[FUSED_MAX];
+    __shared__ unsigned long long sbest[FUSED_MAX];
+    __shared__ int64_t dbw[256];
+    __shared__ uint32_t wsum[FUSED_THREADS / WAVE];
+    const uint32_t tid = threadIdx.x;
+    const int kb = L.sh_s - L.sh_t;
+    uint32_t n2 = 1;
+    while (n2 < np) n2 <<= 1;
+    for (uint32_t i = tid; i < n2; i += FUSED_THREADS) {
+        if (i < np) {
+            uint32_t u = plist[i];
+            skey[i] = ((uint64_t)part[u] << L.sh_s) | ((uint64_t)prop_t[u] << L.sh_t) |
+                      ((uint64_t)(L.G - prop_g[u]) << L.sh_g) | ((uint64_t)u << L.sh_u);
+            sval[i] = u;
+        } else {
+            skey[i] = ~0ull;
+            sval[i] = 0;
+        }
+    }
+    for (uint32_t b = tid; b < k; b += FUSED_THREADS) dbw[b] = 0;
+    __syncthreads();
+    // bitonic sort of n2 keys (padding keys are the largest)
+    for (uint32_t kk = 2; kk <= n2; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = tid; i < n2; i += FUSED_THREADS) {
+                uint32_t l = i ^ j;
+                if (l > i) {
+                    uint64_t a = skey[i], b = skey[l];
+                    bool up = (i & kk) == 0;
+                    if ((a > b) == up) {
+                        skey[i] = b; skey[l] = a;
+                        uint32_t t = sval[i]; sval[i] = sval[l]; sval[l] = t;
                     }
                 }
             }
+            __syncthreads();
         }
-        uint64_t m = __ballot(mv);
-        if (__lane_id() == 0 && m) atomicAdd(moves, (uint32_t)__popcll(m));
     }
+    // inclusive prefix of node weights in sorted order
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < np; c0 += FUSED_THREADS) {
+        uint32_t i = c0 + tid;
+        uint32_t w = i < np ? (uint32_t)vwgt[sval[i]] : 0u;
+        uint32_t tot;
+        uint32_t incl = block_incl_scan_n<uint32_t, FUSED_THREADS>(w, wsum, &tot);
+        if (i < np) { sincl[i] = carry + incl; sbest[i] = 0; }
+        carry += tot;
+    }
+    __syncthreads();
+    // selection: each element tests the merge-walk state right after it
+    for (uint32_t i = tid; i < np; i += FUSED_THREADS) {
+        uint64_t key = skey[i];
+        uint32_t s = (uint32_t)(key >> L.sh_s) & L.kmask;
+        uint32_t t = (uint32_t)(key >> L.sh_t) & L.kmask;
+        uint32_t x = s < t ? s : t, y = s < t ? t : s;
+        uint64_t pa = ((uint64_t)x << kb) | y, pb = ((uint64_t)y << kb) | x;
+        LSeg A, Bv;
+        A.start = lower_pair(skey, np, L.sh_t, pa);
+        A.len = lower_pair(skey, np, L.sh_t, pa + 1) - A.start;
+        Bv.start = lower_pair(skey, np, L.sh_t, pb);
+        Bv.len = lower_pair(skey, np, L.sh_t, pb + 1) - Bv.start;
+        A.base = A.start ? sincl[A.start - 1] : 0u;
+        Bv.base = Bv.start ? sincl[Bv.start - 1] : 0u;
+        A.incl = sincl; Bv.incl = sincl;
+        uint32_t leader = A.len ? A.start : Bv.start;
+        int64_t beta_x = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
+        int64_t beta_y = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
+        uint32_t ia, jb, loc;
+        if (s == x) {
+            loc = i - A.start;
+            ia = loc + 1;
+            jb = lcount_below(Bv, A.excl(loc), true);
+        } else {
+            loc = i - Bv.start;
+            jb = loc + 1;
+            ia = lcount_below(A, Bv.excl(loc), false);
+        }
+        if (loc == 0 && beta_x >= 0 && beta_y >= 0) atomicMax(&sbest[leader], 1ull << 32);
+        int64_t xv = (int64_t)A.excl(ia) - (int64_t)Bv.excl(jb);
+        if (-beta_x <= xv && xv <= beta_y)
+            atomicMax(&sbest[leader], ((unsigned long long)(ia + jb + 1) << 32) | ia);
+    }
+    __syncthreads();
+    // apply: (1) movers compacted into LDS in sorted order, block weights
+    uint32_t *mlist = sincl;  // free after the selection
+    uint32_t nmv = 0;
+    for (uint32_t c0 = 0; c0 < np; c0 += FUSED_THREADS) {
+        uint32_t i = c0 + tid;
+        bool mv = false;
+        uint32_t s = 0, t = 0;
+        if (i < np) {
+            uint64_t key = skey[i];
+            s = (uint32_t)(key >> L.sh_s) & L.kmask;
+            t = (uint32_t)(key >> L.sh_t) & L.kmask;
+            uint32_t x = s < t ? s : t, y = s < t ? t : s;
+            uint64_t pa = ((uint64_t)x << kb) | y, pb = ((uint64_t)y << kb) | x;
+            uint32_t as = lower_pair(skey, np, L.sh_t, pa);
+            uint32_t al = lower_pair(skey, np, L.sh_t, pa + 1) - as;
+            uint32_t bs = lower_pair(skey, np, L.sh_t, pb);
+            unsigned long long bst = sbest[al ? as : bs];
+            if (bst) {
+                uint32_t istar = (uint32_t)bst;
+                uint32_t d = (uint32_t)(bst >> 32) - 1;
+                uint32_t jstar = d - istar;
+                mv = (s == x) ? (i - as < istar) : (i - bs < jstar);
+            }
+        }
+        uint32_t tot;
+        uint32_t incl = block_incl_scan_n<uint32_t, FUSED_THREADS>(mv ? 1u : 0u, wsum, &tot);
+        if (mv) {
+            uint32_t u = sval[i];
+            mlist[nmv + incl - 1] = u;
+            part[u] = t;
+            int64_t c = vwgt[u];
+            atomicAdd((unsigned long long *)&dbw[s], (unsigned long long)(-c));
+            atomicAdd((unsigned long long *)&dbw[t], (unsigned long long)c);
+        }
+        nmv += tot;
+    }
+    __syncthreads();
+    // (2) exclusive degree prefix of the movers (kept in skey, free now)
+    uint64_t *mpre = skey;
+    uint32_t dcarry = 0;
+    for (uint32_t c0 = 0; c0 < nmv; c0 += FUSED_THREADS) {
+        uint32_t i = c0 + tid;
+        uint32_t d = 0;
+        if (i < nmv) { uint32_t u = mlist[i]; d = inc_off[u + 1] - inc_off[u]; }
+        uint32_t tot;
+        uint32_t incl = block_incl_scan_n<uint32_t, FUSED_THREADS>(d, wsum, &tot);
+        if (i < nmv) mpre[i] = dcarry + incl - d;
+        dcarry += tot;
+    }
+    __syncthreads();
+    // (3) every (mover, incident net) pair in parallel: touched-net list
+    for (uint32_t f0 = 0; f0 < dcarry; f0 += FUSED_THREADS) {
+        uint32_t f = f0 + tid;
+        bool fresh = false;
+        uint32_t e = 0;
+        if (f < dcarry) {
+            uint32_t lo = 0, hi = nmv - 1;  // largest mover index with mpre <= f
+            while (lo < hi) {
+                uint32_t mid = (lo + hi + 1) >> 1;
+                if (mpre[mid] <= f) lo = mid; else hi = mid - 1;
+            }
+            uint32_t u = mlist[lo];
+            e = inc[inc_off[u] + (f - (uint32_t)mpre[lo])];
+            fresh = atomicExch(&tstamp[e], stamp) != stamp;
+        }
+        uint32_t pos = warp_agg_append(ntouched, fresh);
+        if (fresh) tlist[pos] = e;
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < k; b += FUSED_THREADS)
+        if (dbw[b]) atomic_add_i64(&bw[b], dbw[b]);
+    if (tid == 0 && nmv) atomicAdd(moves, nmv);
 }
 
 // Recompute Lambda / Lambda1 of touched nets (thread per net up to 64 pins;
@@ -486,22 +720,13 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update(const uint32_t *pin_off, co
     }
 }
 
-__global__ void k_degree_list(const uint32_t *inc_off, uint32_t n, uint32_t *list, uint32_t *count) {
-    for (uint32_t u0 = blockIdx.x * blockDim.x; u0 < n; u0 += gridDim.x * blockDim.x) {
-        uint32_t u = u0 + threadIdx.x;
-        bool big = u < n && inc_off[u + 1] - inc_off[u] > 64;
-        uint32_t pos = warp_agg_append(count, big);
-        if (big) list[pos] = u;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 struct RefineBufs {
     uint64_t *lam, *lam1;
     int64_t *f, *bw;
-    uint32_t *longl, *biglist, *plist, *prop_t, *prop_g, *tstamp, *tlist, *scal;
+    uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bstamp, *tlist, *scal;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt, *seg_start, *seg_end;
     unsigned long long *best;
@@ -514,7 +739,8 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.f = A.alloc<int64_t>(1);
     B.bw = A.alloc<int64_t>(k);
     B.longl = A.alloc<uint32_t>(m);
-    B.biglist = A.alloc<uint32_t>(n);
+    B.dlists = A.alloc<uint32_t>(n);
+    B.bstamp = A.alloc<uint32_t>(n);
     B.plist = A.alloc<uint32_t>(n);
     B.prop_t = A.alloc<uint32_t>(n);
     B.prop_g = A.alloc<uint32_t>(n);
@@ -543,12 +769,12 @@ size_t refine_workspace(uint32_t n, uint32_t m, uint32_t k) {
 template <int KW>
 static void build_conn(const hgp_hg &h, const uint32_t *part, RefineBufs &B, hipStream_t st) {
     HGP_CHECK_HIP(hipMemsetAsync(B.f, 0, sizeof(int64_t), st));
-    HGP_CHECK_HIP(hipMemsetAsync(B.scal + 8, 0, sizeof(uint32_t), st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.scal + 12, 0, sizeof(uint32_t), st));
     if (h.m) {
         k_conn_small<KW><<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.pins, h.m, h.nwgt, part,
-                                                                             B.lam, B.lam1, B.f, B.longl, B.scal + 8);
+                                                                             B.lam, B.lam1, B.f, B.longl, B.scal + 12);
         HGP_LAUNCH_CHECK();
-        k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, B.scal + 8, h.nwgt, part,
+        k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, B.scal + 12, h.nwgt, part,
                                                            B.lam, B.lam1, B.f, false);
         HGP_LAUNCH_CHECK();
     }
@@ -594,18 +820,25 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const int64_t W = total_weight(h.vwgt, n, A, st);
     const int64_t lmax = ((int64_t)(prm.eps_den + prm.eps_num) * ((W + k - 1) / k)) / (int64_t)prm.eps_den;
     const uint64_t mseed = mix64(prm.seed);
-    uint32_t *nprop = B.scal + 0, *gmax = B.scal + 1, *ntouched = B.scal + 2, *moves = B.scal + 3,
-             *nlong = B.scal + 4, *nbig = B.scal + 5;
+    // device scalars: ntouched and nlong are adjacent so one memset clears both
+    uint32_t *nprop = B.scal + 0, *gmax = B.scal + 1, *ntouched = B.scal + 2, *nlong = B.scal + 3,
+             *moves = B.scal + 4, *dcnt = B.scal + 5 /* [3] */, *dcur = B.scal + 8 /* [3] */;
 
     build_conn<KW>(h, part, B, st);
     block_weights(part, h.vwgt, n, k, B.bw, st);
     if (m) HGP_CHECK_HIP(hipMemsetAsync(B.tstamp, 0, sizeof(uint32_t) * m, st));
-    HGP_CHECK_HIP(hipMemsetAsync(nbig, 0, sizeof(uint32_t), st));
-    k_degree_list<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, B.biglist, nbig);
+    HGP_CHECK_HIP(hipMemsetAsync(B.bstamp, 0, sizeof(uint32_t) * n, st));
+    // degree classes of the nodes (lanes per node 1 / 8 / 64)
+    HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * 3, st));
+    k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt, dcur, B.dlists, false);
     HGP_LAUNCH_CHECK();
-    uint32_t nbig_h = 0;
-    HGP_CHECK_HIP(hipMemcpyAsync(&nbig_h, nbig, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    uint32_t dc[3], doff[4] = {0, 0, 0, 0};
+    HGP_CHECK_HIP(hipMemcpyAsync(dc, dcnt, sizeof(dc), hipMemcpyDeviceToHost, st));
     HGP_CHECK_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < 3; ++c) doff[c + 1] = doff[c] + dc[c];
+    HGP_CHECK_HIP(hipMemcpyAsync(dcur, doff, sizeof(uint32_t) * 3, hipMemcpyHostToDevice, st));
+    k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt, dcur, B.dlists, true);
+    HGP_LAUNCH_CHECK();
 
     const int kb = bits_for(k - 1), ub = bits_for(n ? n - 1 : 0);
     uint32_t stamp = 0;
@@ -614,12 +847,25 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         for (uint32_t s = 0; s < prm.lp_subrounds; ++s) {
             ++stamp;
             HGP_CHECK_HIP(hipMemsetAsync(nprop, 0, sizeof(uint32_t) * 2, st));
-            GainArgs ga{h.inc_off, h.inc, h.nwgt, h.vwgt, B.lam, B.lam1, part, B.bw, lmax, mseed, level, r, s,
-                        prm.lp_subrounds, n, B.prop_t, B.prop_g, B.plist, nprop, gmax};
-            k_gains_thread<KW><<<grid_for(n, BLOCK, FILL_BLOCKS * 4), BLOCK, 0, st>>>(ga);
-            HGP_LAUNCH_CHECK();
-            if (nbig_h) {
-                k_gains_wave<KW><<<grid_for(nbig_h, BLOCK / WAVE, FILL_BLOCKS), BLOCK, 0, st>>>(ga, B.biglist, nbig_h);
+            if (m) {
+                k_mark_boundary<KW><<<grid_for(m, BLOCK, FILL_BLOCKS * 2), BLOCK, 0, st>>>(h.pin_off, h.pins, m, B.lam,
+                                                                                          B.bstamp, stamp);
+                HGP_LAUNCH_CHECK();
+            }
+            GainArgs ga{h.inc_off, h.inc, h.nwgt, h.vwgt, B.lam, B.lam1, part, B.bw, B.bstamp, stamp, lmax,
+                        mseed, level, r, s, prm.lp_subrounds, n, B.prop_t, B.prop_g, B.plist, nprop, gmax};
+            if (dc[0]) {
+                k_gains_group<KW, 1><<<grid_for(dc[0], BLOCK, FILL_BLOCKS * 2), BLOCK, 0, st>>>(ga, B.dlists, dc[0]);
+                HGP_LAUNCH_CHECK();
+            }
+            if (dc[1]) {
+                k_gains_group<KW, 8><<<grid_for(dc[1], BLOCK / 8, FILL_BLOCKS * 2), BLOCK, 0, st>>>(
+                    ga, B.dlists + doff[1], dc[1]);
+                HGP_LAUNCH_CHECK();
+            }
+            if (dc[2]) {
+                k_gains_group<KW, 64><<<grid_for(dc[2], BLOCK / 64, FILL_BLOCKS * 2), BLOCK, 0, st>>>(
+                    ga, B.dlists + doff[2], dc[2]);
                 HGP_LAUNCH_CHECK();
             }
             uint32_t hv[2];
@@ -632,6 +878,22 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             L.kmask = (1u << kb) - 1u;
             if (kb == 0) L.kmask = 0;
             L.G = G;
+            if (np <= (uint32_t)FUSED_MAX && 2 * kb + gb + ub <= 64) {
+                L.with_u = true;
+                L.sh_u = 0; L.sh_g = ub; L.sh_t = ub + gb; L.sh_s = ub + gb + kb;
+                HGP_CHECK_HIP(hipMemsetAsync(ntouched, 0, sizeof(uint32_t) * 2, st));  // ntouched, nlong
+                k_lp_fused<<<1, FUSED_THREADS, 0, st>>>(B.plist, np, B.prop_t, B.prop_g, L, k, h.vwgt, h.inc_off,
+                                                        h.inc, part, B.bw, lmax, B.tstamp, stamp, B.tlist, ntouched,
+                                                        moves);
+                HGP_LAUNCH_CHECK();
+                k_lp_update<KW><<<FILL_BLOCKS / 8, BLOCK, 0, st>>>(h.pin_off, h.pins, B.tlist, ntouched, h.nwgt, part,
+                                                                   B.lam, B.lam1, B.f, B.longl, nlong);
+                HGP_LAUNCH_CHECK();
+                k_conn_long<KW><<<FILL_BLOCKS / 8, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part,
+                                                                   B.lam, B.lam1, B.f, true);
+                HGP_LAUNCH_CHECK();
+                continue;
+            }
             uint64_t *kk = B.keys;
             uint32_t *vv = B.vals;
             if (2 * kb + gb + ub <= 64) {
@@ -663,8 +925,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             k_lp_select<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, np, L, k, B.seg_start, B.seg_end,
                                                                            B.incl, B.bw, lmax, B.best);
             HGP_LAUNCH_CHECK();
-            HGP_CHECK_HIP(hipMemsetAsync(ntouched, 0, sizeof(uint32_t), st));
-            HGP_CHECK_HIP(hipMemsetAsync(nlong, 0, sizeof(uint32_t), st));
+            HGP_CHECK_HIP(hipMemsetAsync(ntouched, 0, sizeof(uint32_t) * 2, st));  // ntouched, nlong
             k_lp_apply<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, np, L, k, B.seg_start, B.best,
                                                                           h.vwgt, h.inc_off, h.inc, part, B.bw,
                                                                           B.tstamp, stamp, B.tlist, ntouched, moves);
