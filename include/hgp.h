@@ -183,6 +183,39 @@ hgp_status hgp_partition(const hgp_hg *h, const hgp_params *prm, uint32_t *part,
                          int64_t *objective, uint32_t *levels_out,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* Measurement support (host).  Kernel ids for the timing calls below. */
+#define HGP_KID_RATE_G8 0       /* rating, groups of 8 lanes, 64-entry tables    */
+#define HGP_KID_RATE_G16 1      /* rating, groups of 16 lanes, 256-entry tables  */
+#define HGP_KID_RATE_G64 2      /* rating, one wave, 1024-entry tables           */
+#define HGP_KID_RATE_BLOCK 3    /* rating, one workgroup per candidate           */
+#define HGP_KID_GAINS_G1 4      /* LP gains, one lane per node                   */
+#define HGP_KID_GAINS_G8 5      /* LP gains, 8 lanes per node                    */
+#define HGP_KID_GAINS_G64 6     /* LP gains, one wave per node                   */
+#define HGP_KID_LP_FUSED 7      /* LP selection + apply, one workgroup           */
+#define HGP_KID_MARK_BOUNDARY 8 /* LP boundary marking                           */
+#define HGP_KID_COUNT 9
+
+/* Host.  Bytes of device scratch that accounting needs for levels of at most
+ * n_max vertices and m_max nets. */
+hgp_status hgp_timing_scratch_bytes(uint32_t n_max, uint32_t m_max, size_t *out);
+
+/* Host.  Starts measuring the kernels whose ids are set in `mask` (bit i =
+ * kernel id i).  account = 0: every launch of those kernels is bracketed by a
+ * pair of HIP events recorded on its stream.  account = 1: instead, each such
+ * launch is preceded by an accounting kernel that adds the launch's
+ * compulsory bytes (each distinct array element it must read or write,
+ * counted once) to a device counter; `scratch` (device, hgp_timing_scratch_bytes
+ * bytes) holds the counters and stamp arrays.  Measurement is global to the
+ * process and not thread safe. */
+hgp_status hgp_timing_begin(uint32_t mask, int account, void *scratch, size_t scratch_bytes,
+                            uint32_t n_max, uint32_t m_max);
+
+/* Host.  Waits for the device, then for kernel ids i < count writes
+ * total_ms[i] (summed event time), launches[i] and bytes[i] (accounted
+ * compulsory bytes, 0 when not accounting), and stops measuring.  Any of the
+ * three pointers may be NULL. */
+hgp_status hgp_timing_end(uint32_t count, double *total_ms, uint64_t *launches, double *bytes);
+
 /* Host.  Static description of a status code. */
 const char *hgp_status_str(hgp_status s);
 

@@ -24,7 +24,11 @@ STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_OVERFLOW", -3: "HGP_E_WOR
 
 EXPORTS = ["hgp_default_params", "hgp_workspace_bytes", "hgp_validate", "hgp_coarsen", "hgp_contract",
            "hgp_project", "hgp_objective", "hgp_refine_lp", "hgp_initial_partition", "hgp_partition",
-           "hgp_status_str"]
+           "hgp_timing_scratch_bytes", "hgp_timing_begin", "hgp_timing_end", "hgp_status_str"]
+
+# kernel ids of the measurement calls, with the kernel symbol each one names
+KERNELS = ["k_rate_group<8, 64, 6>", "k_rate_group<16, 256, 8>", "k_rate_group<64, 1024, 10>", "k_rate_block",
+           "k_gains_group<*, 1>", "k_gains_group<*, 8>", "k_gains_group<*, 64>", "k_lp_fused", "k_mark_boundary"]
 
 
 class HGPError(RuntimeError):
@@ -85,6 +89,12 @@ def lib():
         L.hgp_partition.restype = i32
         L.hgp_partition.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_uint32), P, ctypes.c_size_t, P]
         L.hgp_status_str.restype = ctypes.c_char_p; L.hgp_status_str.argtypes = [i32]
+        L.hgp_timing_scratch_bytes.restype = i32
+        L.hgp_timing_scratch_bytes.argtypes = [u32, u32, ctypes.POINTER(ctypes.c_size_t)]
+        L.hgp_timing_begin.restype = i32
+        L.hgp_timing_begin.argtypes = [u32, ctypes.c_int, P, ctypes.c_size_t, u32, u32]
+        L.hgp_timing_end.restype = i32
+        L.hgp_timing_end.argtypes = [u32, P, P, P]
         _lib = L
     return _lib
 
@@ -273,3 +283,27 @@ def partition(h: Hypergraph, prm: Params):
     P = Partitioner(h, prm)
     levels = P.run()
     return P.part, int(P.f.item()), levels
+
+
+class KernelTimer:
+    """Per-kernel measurement through the library's event timing and
+    compulsory-byte accounting (see hgp_timing_begin)."""
+
+    def __init__(self, n_max: int, m_max: int, device="cuda"):
+        torch = _torch()
+        nb = ctypes.c_size_t(0)
+        _check(lib().hgp_timing_scratch_bytes(n_max, m_max, ctypes.byref(nb)), "hgp_timing_scratch_bytes")
+        self.scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        self.n_max, self.m_max = n_max, m_max
+
+    def begin(self, mask: int, account: bool = False):
+        _check(lib().hgp_timing_begin(mask, int(account), _ptr(self.scratch), self.scratch.numel(), self.n_max,
+                                      self.m_max), "hgp_timing_begin")
+
+    def end(self):
+        k = len(KERNELS)
+        ms = (ctypes.c_double * k)()
+        ln = (ctypes.c_uint64 * k)()
+        by = (ctypes.c_double * k)()
+        _check(lib().hgp_timing_end(k, ms, ln, by), "hgp_timing_end")
+        return [dict(kernel=KERNELS[i], ms=ms[i], launches=int(ln[i]), bytes=by[i]) for i in range(k)]

@@ -23,6 +23,7 @@
 //  3. Apply: rep, cluster weights and the cluster count.
 #include "prims.h"
 #include "kernels.h"
+#include "timing.h"
 
 namespace hgp {
 
@@ -91,6 +92,30 @@ __device__ inline void publish(const RateArgs &a, uint32_t u, uint32_t C) {
     }
 }
 
+// Nets with at most LANE_NET pins are rated by a single lane: it loads the
+// net's pins and their clusters at once and drops repeated clusters in
+// registers, so every distinct (net, cluster) pair adds w(e)/(|e|-1) exactly
+// once without any ordering between lanes.  Larger nets are processed by the
+// whole group, one net at a time, with a per-slot "last net" stamp.
+constexpr uint32_t LANE_NET = 16;
+
+template <class Insert>
+__device__ inline void rate_small_net(const RateArgs &a, uint32_t u, uint32_t b, uint32_t sz, uint64_t sc,
+                                      Insert &&insert) {
+    uint32_t C[LANE_NET];
+#pragma unroll
+    for (uint32_t q = 0; q < LANE_NET; ++q) C[q] = q < sz ? a.pins[b + q] : NONE;
+#pragma unroll
+    for (uint32_t q = 0; q < LANE_NET; ++q) C[q] = (C[q] != NONE && C[q] != u) ? a.rep[C[q]] : NONE;
+#pragma unroll
+    for (uint32_t q = 0; q < LANE_NET; ++q) {
+        bool fresh = C[q] != NONE;
+#pragma unroll
+        for (uint32_t r = 0; r < q; ++r) fresh = fresh && C[r] != C[q];
+        if (fresh) insert(C[q], sc);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Groups of G lanes (G <= 64), one candidate per group, LDS table of CAP.
 // Occupied slots are listed so that argmax and clearing touch only them.
@@ -114,46 +139,86 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
         const bool active = a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u];  // not joined earlier
         if (!active) continue;  // uniform within the group
         const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
-        for (uint32_t j = j0; j < j1; ++j) {
+        auto insert = [&](uint32_t C, uint64_t sc) -> uint32_t {
+            uint32_t slot = slot_hash(C, LOG2CAP);
+            for (;;) {
+                uint32_t k = keys[g][slot];
+                if (k == C) break;
+                if (k == NONE) {
+                    uint32_t old = atomicCAS(&keys[g][slot], NONE, C);
+                    if (old == NONE) {
+                        occ[g][atomicAdd(&nocc[g], 1u)] = (uint16_t)slot;
+                        break;
+                    }
+                    if (old == C) break;
+                }
+                slot = (slot + 1) & (CAP - 1);
+            }
+            return slot;
+        };
+        // phase 1: small nets, one lane each
+        bool big = false;
+        for (uint32_t j = j0 + l; j < j1; j += G) {
             uint32_t e = a.inc[j];
             uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+            if (sz > LANE_NET) { big = true; continue; }
             if (sz < 2) continue;
-            uint64_t sc = a.nscore[e];
-            for (uint32_t q = l; q < sz; q += G) {
-                uint32_t v = a.pins[b + q];
-                if (v == u) continue;
-                uint32_t C = a.rep[v];
-                uint32_t slot = slot_hash(C, LOG2CAP);
-                for (;;) {
-                    uint32_t k = keys[g][slot];
-                    if (k == C) break;
-                    if (k == NONE) {
-                        uint32_t old = atomicCAS(&keys[g][slot], NONE, C);
-                        if (old == NONE) {
-                            occ[g][atomicAdd(&nocc[g], 1u)] = (uint16_t)slot;
-                            break;
-                        }
-                        if (old == C) break;
-                    }
-                    slot = (slot + 1) & (CAP - 1);
+            rate_small_net(a, u, b, sz, a.nscore[e], [&](uint32_t C, uint64_t sc) {
+                uint32_t slot = insert(C, sc);
+                atomicAdd((unsigned long long *)&R[g][slot], (unsigned long long)sc);
+            });
+        }
+        // phase 2: large nets, the whole group on one net at a time
+        uint64_t bigmask = __ballot(big);
+        const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << ((__lane_id() / G) * G));
+        wave_sync();
+        if (bigmask & gmask) {
+            for (uint32_t j = j0; j < j1; ++j) {
+                uint32_t e = a.inc[j];
+                uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+                if (sz <= LANE_NET) continue;
+                uint64_t sc = a.nscore[e];
+                for (uint32_t q = l; q < sz; q += G) {
+                    uint32_t v = a.pins[b + q];
+                    if (v == u) continue;
+                    uint32_t slot = insert(a.rep[v], sc);
+                    if (!a.dedup || atomicExch(&stamp[g][slot], e) != e)
+                        atomicAdd((unsigned long long *)&R[g][slot], (unsigned long long)sc);
                 }
-                if (!a.dedup || atomicExch(&stamp[g][slot], e) != e)
-                    atomicAdd((unsigned long long *)&R[g][slot], (unsigned long long)sc);
+                wave_sync();
             }
-            wave_sync();
         }
         wave_sync();
         const uint32_t no = nocc[g];
+        const int64_t cu = a.vwgt[u];
         uint64_t bR = 0;
         uint32_t bC = NONE;
-        for (uint32_t i = l; i < no; i += G) {
-            uint32_t slot = occ[g][i];
-            uint32_t C = keys[g][slot];
-            uint64_t rc = R[g][slot];
-            keys[g][slot] = NONE;  // leave the table clean for the next candidate
-            stamp[g][slot] = NONE;
-            R[g][slot] = 0;
-            if (valid_target(a, u, C) && better_lazy(a, rc, C, bR, bC)) { bR = rc; bC = C; }
+        // four slots per lane at a time so that their tinfo loads overlap
+        for (uint32_t i0 = 0; i0 < no; i0 += 4 * G) {
+            uint32_t Cs[4];
+            uint64_t Rs[4];
+            int64_t Ts[4];
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) {
+                uint32_t i = i0 + k4 * G + l;
+                Cs[k4] = NONE;
+                Rs[k4] = 0;
+                if (i < no) {
+                    uint32_t slot = occ[g][i];
+                    Cs[k4] = keys[g][slot];
+                    Rs[k4] = R[g][slot];
+                    keys[g][slot] = NONE;  // leave the table clean for the next candidate
+                    stamp[g][slot] = NONE;
+                    R[g][slot] = 0;
+                }
+            }
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) Ts[k4] = Cs[k4] != NONE ? a.tinfo[Cs[k4]] : TINFO_BAD;
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) {
+                bool ok = Cs[k4] != NONE && Cs[k4] != u && a.cap_mult * (cu + Ts[k4]) <= a.W;
+                if (ok && better_lazy(a, Rs[k4], Cs[k4], bR, bC)) { bR = Rs[k4]; bC = Cs[k4]; }
+            }
         }
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) {
@@ -212,30 +277,50 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
         if (GLOBAL) __threadfence();  // the clear reaches L2 before any atomic on the table
         __syncthreads();
         uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
-        for (uint32_t j = j0; j < j1; ++j) {
+        auto insert = [&](uint32_t C) -> uint32_t {
+            uint32_t slot = slot_hash(C, lg);
+            for (;;) {
+                uint32_t k = GLOBAL ? __hip_atomic_load(&keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : keys[slot];
+                if (k == C) break;
+                if (k == NONE) {
+                    uint32_t old = atomicCAS(&keys[slot], NONE, C);
+                    if (old == NONE || old == C) break;
+                }
+                slot = (slot + 1) & (cap - 1);
+            }
+            return slot;
+        };
+        // phase 1: small nets, one thread each
+        int big = 0;
+        for (uint32_t j = j0 + threadIdx.x; j < j1; j += BLOCK) {
             uint32_t e = a.inc[j];
             uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+            if (sz > LANE_NET) { big = 1; continue; }
             if (sz < 2) continue;
-            uint64_t sc = a.nscore[e];
-            for (uint32_t q = threadIdx.x; q < sz; q += BLOCK) {
-                uint32_t v = a.pins[b + q];
-                if (v == u) continue;
-                uint32_t C = a.rep[v];
-                uint32_t slot = slot_hash(C, lg);
-                for (;;) {
-                    uint32_t k = GLOBAL ? __hip_atomic_load(&keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                        : keys[slot];
-                    if (k == C) break;
-                    if (k == NONE) {
-                        uint32_t old = atomicCAS(&keys[slot], NONE, C);
-                        if (old == NONE || old == C) break;
-                    }
-                    slot = (slot + 1) & (cap - 1);
+            rate_small_net(a, u, b, sz, a.nscore[e], [&](uint32_t C, uint64_t sc) {
+                uint32_t slot = insert(C);
+                atomicAdd((unsigned long long *)&R[slot], (unsigned long long)sc);
+            });
+        }
+        // phase 2: large nets, the whole block on one net at a time
+        const int anybig = __syncthreads_or(big);
+        __syncthreads();  // phase-1 table updates complete before anyone reads the table
+        if (anybig) {
+            for (uint32_t j = j0; j < j1; ++j) {
+                uint32_t e = a.inc[j];
+                uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+                if (sz <= LANE_NET) continue;
+                uint64_t sc = a.nscore[e];
+                for (uint32_t q = threadIdx.x; q < sz; q += BLOCK) {
+                    uint32_t v = a.pins[b + q];
+                    if (v == u) continue;
+                    uint32_t slot = insert(a.rep[v]);
+                    if (!a.dedup || atomicExch(&stamp[slot], e) != e)
+                        atomicAdd((unsigned long long *)&R[slot], (unsigned long long)sc);
                 }
-                if (!a.dedup || atomicExch(&stamp[slot], e) != e)
-                    atomicAdd((unsigned long long *)&R[slot], (unsigned long long)sc);
+                __syncthreads();
             }
-            __syncthreads();
         }
         uint64_t bR = 0;
         uint32_t bC = NONE;
@@ -263,6 +348,49 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
             publish(a, u, bC);
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Measurement only: compulsory bytes of one rating launch -- every distinct
+// array element the launch must read or write, counted once (candidate data,
+// incidence lists, the offsets / score / pins of every distinct net touched,
+// the cluster of every distinct pin vertex, the target info of every distinct
+// cluster, the target written).  Never runs in a timed step.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_account_rate(RateArgs a, const uint32_t *list, uint32_t count,
+                                                        uint32_t *nmark, uint32_t *vmark, uint32_t *cmark,
+                                                        uint32_t stamp, unsigned long long *acc) {
+    __shared__ unsigned long long red[BLOCK / WAVE];
+    unsigned long long bytes = 0;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
+        const uint32_t u = list[idx];
+        bytes += 4 + 4 + 8 + 4;  // list entry, rep[u], cw[u], vwgt[u]
+        if (!(a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u])) continue;
+        const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
+        bytes += 4 + 4ull * (j1 - j0) + 4;  // inc_off, incidence list, target
+        for (uint32_t j = j0; j < j1; ++j) {
+            uint32_t e = a.inc[j];
+            uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+            bool first = atomicExch(&nmark[e], stamp) != stamp;
+            if (sz < 2) { if (first) bytes += 4; continue; }
+            if (first) bytes += 4 + 8 + 4ull * sz;  // pin offset, score, pins
+            for (uint32_t q = 0; q < sz; ++q) {
+                uint32_t v = a.pins[b + q];
+                if (v == u) continue;
+                if (atomicExch(&vmark[v], stamp) != stamp) bytes += 4;  // rep[v]
+                uint32_t C = a.rep[v];
+                if (atomicExch(&cmark[C], stamp) != stamp) bytes += 8;  // tinfo[C]
+            }
+        }
+    }
+    bytes = wave_sum(bytes);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = bytes;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+        atomicAdd(acc, t);
     }
 }
 
@@ -533,6 +661,16 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             uint32_t cntc = counts[r * NCLASS + c];
             if (!cntc) continue;
             const uint32_t *lst = B.lists + offs[r * NCLASS + c];
+            const int kid = c == 0 ? KID_RATE_G8 : c == 1 ? KID_RATE_G16 : c == 2 ? KID_RATE_G64 : KID_RATE_BLOCK;
+            if (accounting(kid)) {
+                Timing &T = timing();
+                ++T.stamp;
+                k_account_rate<<<grid_for(cntc, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+                    a, lst, cntc, T.marks, T.marks + T.marks_len, T.marks + 2 * T.marks_len, T.stamp,
+                    (unsigned long long *)T.acc_dev + kid);
+                HGP_LAUNCH_CHECK();
+            }
+            TimedLaunch tl(kid, st);
             switch (c) {
                 case 0:
                     k_rate_group<8, 64, 6><<<grid_for(cntc, BLOCK / 8, 8192), BLOCK, 0, st>>>(a, lst, cntc);

@@ -21,6 +21,7 @@
 // feasible state is an atomicMax over (step, i).
 #include "prims.h"
 #include "kernels.h"
+#include "timing.h"
 
 namespace hgp {
 
@@ -166,16 +167,19 @@ struct GainArgs {
     uint64_t mseed;
     uint32_t level, round, sub, S, n;
     uint32_t *prop_t, *prop_g, *plist, *nprop, *gmax;
+    uint32_t *pw;  // [k*k] total weight proposed per ordered block pair
+    uint32_t k;
 };
 
 // Called by every lane of the wave (uniformly); `has` is set by at most one
 // lane per proposing vertex.
-__device__ inline void propose(const GainArgs &a, uint32_t u, uint32_t t, uint32_t g, bool has) {
+__device__ inline void propose(const GainArgs &a, uint32_t u, uint32_t s, uint32_t t, uint32_t g, bool has) {
     uint32_t pos = warp_agg_append(a.nprop, has);
     if (has) {
         a.plist[pos] = u;
         a.prop_t[u] = t;
         a.prop_g[u] = g;
+        atomicAdd(&a.pw[s * a.k + t], (uint32_t)a.vwgt[u]);
     }
     uint32_t gm = has ? g : 0u;
 #pragma unroll
@@ -213,7 +217,7 @@ __global__ __launch_bounds__(BLOCK) void k_gains_group(GainArgs a, const uint32_
     const uint32_t g = threadIdx.x / G, l = threadIdx.x % G;
     for (uint32_t base = blockIdx.x * GPB; base < count; base += gridDim.x * GPB) {
         const uint32_t idx = base + g;
-        uint32_t u = 0, best_t = NONE, best_g = 0;
+        uint32_t u = 0, best_t = NONE, best_g = 0, s = 0;
         bool act = idx < count;
         if (act) {
             u = list[idx];
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(BLOCK) void k_gains_group(GainArgs a, const uint32_
         }
         if (act) {  // uniform within the group
             const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
-            const uint32_t s = a.part[u];
+            s = a.part[u];
             int64_t bu = 0, wI = 0;
             uint64_t U[KW];
 #pragma unroll
@@ -261,7 +265,54 @@ __global__ __launch_bounds__(BLOCK) void k_gains_group(GainArgs a, const uint32_
                 }
             }
         }
-        propose(a, u, best_t, best_g, act && l == 0 && best_t != NONE);
+        propose(a, u, s, best_t, best_g, act && l == 0 && best_t != NONE);
+    }
+}
+
+// Measurement only: compulsory bytes of one gains launch (list, boundary
+// stamp, and for every candidate its node data, incidence list and the
+// weight / Lambda / Lambda1 of every distinct incident net, counted once).
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs a, const uint32_t *list, uint32_t count,
+                                                         uint32_t *nmark, uint32_t stamp, unsigned long long *acc) {
+    __shared__ unsigned long long red[BLOCK / WAVE];
+    unsigned long long bytes = 0;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
+        const uint32_t u = list[idx];
+        bytes += 4 + 4;  // list entry, boundary stamp
+        if (!(a.bstamp[u] == a.stamp && tag_hash(a.mseed, 3, a.level, a.round, u) % a.S == a.sub)) continue;
+        const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
+        bytes += 4 + 4 + 4 + 4ull * (j1 - j0);  // inc_off, part, vwgt, incidence list
+        for (uint32_t j = j0; j < j1; ++j)
+            if (atomicExch(&nmark[a.inc[j]], stamp) != stamp) bytes += 4 + 16ull * KW;
+    }
+    bytes = wave_sum(bytes);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = bytes;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+        atomicAdd(acc, t);
+    }
+}
+
+// Measurement only: compulsory bytes of one boundary-marking launch.
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_account_mark(const uint32_t *pin_off, uint32_t m, const uint64_t *lam,
+                                                        unsigned long long *acc) {
+    __shared__ unsigned long long red[BLOCK / WAVE];
+    unsigned long long bytes = 0;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+        bytes += 8ull * KW;  // Lambda
+        if (popc_bits<KW>(lam + (size_t)e * KW) >= 2) bytes += 4 + 8ull * (pin_off[e + 1] - pin_off[e]);
+    }
+    bytes = wave_sum(bytes);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = bytes;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+        atomicAdd(acc, t);
     }
 }
 
@@ -423,16 +474,14 @@ __global__ void k_lp_select(const uint64_t *keys, uint32_t np, KeyLayout L, uint
 __global__ __launch_bounds__(BLOCK) void k_lp_apply(const uint64_t *keys, const uint32_t *vals, uint32_t np,
                                                     KeyLayout L, uint32_t k, const uint32_t *seg_start,
                                                     const unsigned long long *best, const int32_t *vwgt,
-                                                    const uint32_t *inc_off, const uint32_t *inc, uint32_t *part,
-                                                    int64_t *bw, uint32_t *tstamp, uint32_t stamp, uint32_t *tlist,
-                                                    uint32_t *ntouched, uint32_t *moves) {
+                                                    uint32_t *part, int64_t *bw, uint32_t *mlist, uint32_t *nmov) {
     __shared__ int64_t dbw[256];
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
     __syncthreads();
     for (uint32_t base = blockIdx.x * BLOCK; base < np; base += gridDim.x * BLOCK) {
         const uint32_t i = base + threadIdx.x;
         bool mv = false;
-        uint32_t u = 0, j0 = 0, deg = 0;
+        uint32_t u = 0;
         if (i < np) {
             uint64_t key = keys[i];
             uint32_t s = (uint32_t)(key >> L.sh_s) & L.kmask;
@@ -452,33 +501,68 @@ __global__ __launch_bounds__(BLOCK) void k_lp_apply(const uint64_t *keys, const 
                 int64_t c = vwgt[u];
                 atomicAdd((unsigned long long *)&dbw[s], (unsigned long long)(-c));
                 atomicAdd((unsigned long long *)&dbw[t], (unsigned long long)c);
-                j0 = inc_off[u];
-                deg = inc_off[u + 1] - j0;
             }
         }
-        uint64_t mm = __ballot(mv);
-        if (__lane_id() == 0 && mm) atomicAdd(moves, (uint32_t)__popcll(mm));
-        // touched nets, one wave-aggregated append per incidence column
-        uint32_t maxdeg = deg;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            uint32_t x = __shfl_xor(maxdeg, o, 64);
-            maxdeg = x > maxdeg ? x : maxdeg;
-        }
-        for (uint32_t j = 0; j < maxdeg; ++j) {
-            bool fresh = false;
-            uint32_t e = 0;
-            if (j < deg) {
-                e = inc[j0 + j];
-                fresh = atomicExch(&tstamp[e], stamp) != stamp;
-            }
-            uint32_t pos = warp_agg_append(ntouched, fresh);
-            if (fresh) tlist[pos] = e;
-        }
+        uint32_t pos = warp_agg_append(nmov, mv);
+        if (mv) mlist[pos] = u;
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK)
         if (dbw[b]) atomic_add_i64(&bw[b], dbw[b]);
+}
+
+// ---------------------------------------------------------------------------
+// Whole-pair fast path.  The two-pointer walk of a block pair ends in the
+// state that takes every move of both directions; being the last state
+// visited, it is the selected one whenever it is feasible.  So if
+// -beta_x <= w(M_xy) - w(M_yx) <= beta_y all moves of the pair are applied at
+// once, in any order, and only the remaining pairs need the sorted walk.
+// Block-weight changes go to dbw_g so that the sorted walk still reads the
+// snapshot block weights.  Movers are appended to the sub-round's mover list.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const uint32_t *np_dev,
+                                                   const uint32_t *prop_t, const uint32_t *pw, uint32_t k,
+                                                   const int32_t *vwgt, uint32_t *part, const int64_t *bw,
+                                                   int64_t lmax, int64_t *dbw_g, uint32_t *mlist, uint32_t *moves,
+                                                   uint32_t *slow, uint32_t *nslow) {
+    __shared__ int64_t dbw[256];
+    for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
+    __syncthreads();
+    const uint32_t np = *np_dev;
+    for (uint32_t base = blockIdx.x * BLOCK; base < np; base += gridDim.x * BLOCK) {
+        const uint32_t i = base + threadIdx.x;
+        bool mv = false, isslow = false;
+        uint32_t u = 0;
+        if (i < np) {
+            u = plist[i];
+            const uint32_t s = part[u], t = prop_t[u];
+            const uint32_t x = s < t ? s : t, y = s < t ? t : s;
+            const int64_t xf = (int64_t)pw[x * k + y] - (int64_t)pw[y * k + x];
+            const int64_t beta_x = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
+            const int64_t beta_y = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
+            if (-beta_x <= xf && xf <= beta_y) {
+                mv = true;
+                part[u] = t;
+                int64_t c = vwgt[u];
+                atomicAdd((unsigned long long *)&dbw[s], (unsigned long long)(-c));
+                atomicAdd((unsigned long long *)&dbw[t], (unsigned long long)c);
+            } else {
+                isslow = true;
+            }
+        }
+        uint32_t sp = warp_agg_append(nslow, isslow);
+        if (isslow) slow[sp] = u;
+        uint32_t mp = warp_agg_append(moves, mv);
+        if (mv) mlist[mp] = u;
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < k; b += BLOCK)
+        if (dbw[b]) atomic_add_i64(&dbw_g[b], dbw[b]);
+}
+
+__global__ void k_add_dbw(int64_t *bw, const int64_t *dbw_g, uint32_t k) {
+    for (uint32_t b = threadIdx.x; b < k; b += blockDim.x)
+        if (dbw_g[b]) bw[b] += dbw_g[b];
 }
 
 // ---------------------------------------------------------------------------
@@ -516,12 +600,12 @@ __device__ inline uint32_t lcount_below(const LSeg &v, uint32_t x, bool strict) 
     return lo;
 }
 
-__global__ __launch_bounds__(FUSED_THREADS) void k_lp_fused(const uint32_t *plist, uint32_t np, const uint32_t *prop_t,
+__global__ __launch_bounds__(FUSED_THREADS) void k_lp_fused(const uint32_t *plist, const uint32_t *np_dev,
+                                                            const int64_t *dbw_g, const uint32_t *prop_t,
                                                             const uint32_t *prop_g, KeyLayout L, uint32_t k,
                                                             const int32_t *vwgt, const uint32_t *inc_off,
                                                             const uint32_t *inc, uint32_t *part, int64_t *bw,
-                                                            int64_t lmax, uint32_t *tstamp, uint32_t stamp,
-                                                            uint32_t *tlist, uint32_t *ntouched, uint32_t *moves) {
+                                                            int64_t lmax, uint32_t *mlist_g, uint32_t *moves) {
     __shared__ uint64_t skey[FUSED_MAX];
     __shared__ uint32_t sval[FUSED_MAX];
     __shared__ uint32_t sincl[FUSED_MAX];
@@ -529,6 +613,13 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_lp_fused(const uint32_t *plis
     __shared__ int64_t dbw[256];
     __shared__ uint32_t wsum[FUSED_THREADS / WAVE];
     const uint32_t tid = threadIdx.x;
+    const uint32_t np = *np_dev;
+    if (np == 0 || np > (uint32_t)FUSED_MAX) {  // nothing to sort (the host never sends more than FUSED_MAX)
+        if (np == 0)
+            for (uint32_t b = tid; b < k; b += FUSED_THREADS)
+                if (dbw_g[b]) bw[b] += dbw_g[b];
+        return;
+    }
     const int kb = L.sh_s - L.sh_t;
     uint32_t n2 = 1;
     while (n2 < np) n2 <<= 1;
@@ -644,41 +735,66 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_lp_fused(const uint32_t *plis
         nmv += tot;
     }
     __syncthreads();
-    // (2) exclusive degree prefix of the movers (kept in skey, free now)
-    uint64_t *mpre = skey;
-    uint32_t dcarry = 0;
-    for (uint32_t c0 = 0; c0 < nmv; c0 += FUSED_THREADS) {
-        uint32_t i = c0 + tid;
-        uint32_t d = 0;
-        if (i < nmv) { uint32_t u = mlist[i]; d = inc_off[u + 1] - inc_off[u]; }
-        uint32_t tot;
-        uint32_t incl = block_incl_scan_n<uint32_t, FUSED_THREADS>(d, wsum, &tot);
-        if (i < nmv) mpre[i] = dcarry + incl - d;
-        dcarry += tot;
-    }
+    // (2) movers appended to the global mover list (their nets are updated later)
+    __shared__ uint32_t mbase;
+    if (tid == 0) mbase = nmv ? atomicAdd(moves, nmv) : 0u;
     __syncthreads();
-    // (3) every (mover, incident net) pair in parallel: touched-net list
-    for (uint32_t f0 = 0; f0 < dcarry; f0 += FUSED_THREADS) {
-        uint32_t f = f0 + tid;
-        bool fresh = false;
-        uint32_t e = 0;
-        if (f < dcarry) {
-            uint32_t lo = 0, hi = nmv - 1;  // largest mover index with mpre <= f
-            while (lo < hi) {
-                uint32_t mid = (lo + hi + 1) >> 1;
-                if (mpre[mid] <= f) lo = mid; else hi = mid - 1;
+    for (uint32_t i = tid; i < nmv; i += FUSED_THREADS) mlist_g[mbase + i] = mlist[i];
+    __syncthreads();
+    for (uint32_t b = tid; b < k; b += FUSED_THREADS) {
+        int64_t d = dbw[b] + dbw_g[b];
+        if (d) bw[b] += d;
+    }
+}
+
+// Lambda / Lambda1 of every net of a moved node, recomputed once: G lanes per
+// mover; the first lane to stamp a net in this sub-round owns it.  Nets of
+// more than 64 pins are forwarded to the wave kernel.  The objective changes
+// by w(e) (max(lambda'-1,0) - max(lambda-1,0)); the sub-round's move count is
+// added to the round's.
+template <int KW, int G>
+__global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_off, const uint32_t *pins,
+                                                            const uint32_t *inc_off, const uint32_t *inc,
+                                                            const uint32_t *mlist, const uint32_t *nmov,
+                                                            const int32_t *nwgt, const uint32_t *part,
+                                                            uint64_t *lam, uint64_t *lam1, uint32_t *tstamp,
+                                                            uint32_t stamp, int64_t *f, uint32_t *longl,
+                                                            uint32_t *nlong, uint32_t *moves) {
+    __shared__ int64_t red[BLOCK / WAVE];
+    constexpr int GPB = BLOCK / G;
+    const uint32_t cnt = *nmov;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && cnt) atomicAdd(moves, cnt);
+    const uint32_t g = threadIdx.x / G, l = threadIdx.x % G;
+    int64_t acc = 0;
+    for (uint32_t idx = blockIdx.x * GPB + g; idx < cnt; idx += gridDim.x * GPB) {
+        const uint32_t u = mlist[idx];
+        for (uint32_t j = inc_off[u] + l; j < inc_off[u + 1]; j += G) {
+            const uint32_t e = inc[j];
+            if (atomicExch(&tstamp[e], stamp) == stamp) continue;
+            const uint32_t b = pin_off[e], len = pin_off[e + 1] - b;
+            if (len > 64) {
+                longl[atomicAdd(nlong, 1u)] = e;
+                continue;
             }
-            uint32_t u = mlist[lo];
-            e = inc[inc_off[u] + (f - (uint32_t)mpre[lo])];
-            fresh = atomicExch(&tstamp[e], stamp) != stamp;
+            uint64_t once[KW], twice[KW];
+            net_bits<KW>(pins, b, len, part, once, twice);
+            int64_t d = lam_cost(popc_bits<KW>(once)) - lam_cost(popc_bits<KW>(lam + (size_t)e * KW));
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                lam[(size_t)e * KW + q] = once[q];
+                lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
+            }
+            acc += d * nwgt[e];
         }
-        uint32_t pos = warp_agg_append(ntouched, fresh);
-        if (fresh) tlist[pos] = e;
     }
+    acc = wave_sum(acc);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
     __syncthreads();
-    for (uint32_t b = tid; b < k; b += FUSED_THREADS)
-        if (dbw[b]) atomic_add_i64(&bw[b], dbw[b]);
-    if (tid == 0 && nmv) atomicAdd(moves, nmv);
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+        if (t) atomic_add_i64(f, t);
+    }
 }
 
 // Recompute Lambda / Lambda1 of touched nets (thread per net up to 64 pins;
@@ -726,7 +842,8 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update(const uint32_t *pin_off, co
 struct RefineBufs {
     uint64_t *lam, *lam1;
     int64_t *f, *bw;
-    uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bstamp, *tlist, *scal;
+    uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bstamp, *tlist, *scal, *pw, *slow, *mlist;
+    int64_t *dbw_g;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt, *seg_start, *seg_end;
     unsigned long long *best;
@@ -755,6 +872,10 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.seg_start = A.alloc<uint32_t>((size_t)k * k);
     B.seg_end = A.alloc<uint32_t>((size_t)k * k);
     B.best = A.alloc<unsigned long long>((size_t)k * k);
+    B.pw = A.alloc<uint32_t>((size_t)k * k);
+    B.slow = A.alloc<uint32_t>(n);
+    B.mlist = A.alloc<uint32_t>(n);
+    B.dbw_g = A.alloc<int64_t>(k);
     sort_reserve(A, n);
     scan_reserve<uint64_t>(A, n);
 }
@@ -822,7 +943,8 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const uint64_t mseed = mix64(prm.seed);
     // device scalars: ntouched and nlong are adjacent so one memset clears both
     uint32_t *nprop = B.scal + 0, *gmax = B.scal + 1, *ntouched = B.scal + 2, *nlong = B.scal + 3,
-             *moves = B.scal + 4, *dcnt = B.scal + 5 /* [3] */, *dcur = B.scal + 8 /* [3] */;
+             *moves = B.scal + 4, *dcnt = B.scal + 5 /* [3] */, *dcur = B.scal + 8 /* [3] */,
+             *nslow = B.scal + 13, *nmov = B.scal + 14;
 
     build_conn<KW>(h, part, B, st);
     block_weights(part, h.vwgt, n, k, B.bw, st);
@@ -847,23 +969,45 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         for (uint32_t s = 0; s < prm.lp_subrounds; ++s) {
             ++stamp;
             HGP_CHECK_HIP(hipMemsetAsync(nprop, 0, sizeof(uint32_t) * 2, st));
+            HGP_CHECK_HIP(hipMemsetAsync(B.pw, 0, sizeof(uint32_t) * k * k, st));
             if (m) {
+                if (accounting(KID_MARK_BOUNDARY)) {
+                    k_account_mark<KW><<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+                        h.pin_off, m, B.lam, (unsigned long long *)timing().acc_dev + KID_MARK_BOUNDARY);
+                    HGP_LAUNCH_CHECK();
+                }
+                TimedLaunch tl(KID_MARK_BOUNDARY, st);
                 k_mark_boundary<KW><<<grid_for(m, BLOCK, FILL_BLOCKS * 2), BLOCK, 0, st>>>(h.pin_off, h.pins, m, B.lam,
                                                                                           B.bstamp, stamp);
                 HGP_LAUNCH_CHECK();
             }
-            GainArgs ga{h.inc_off, h.inc, h.nwgt, h.vwgt, B.lam, B.lam1, part, B.bw, B.bstamp, stamp, lmax,
-                        mseed, level, r, s, prm.lp_subrounds, n, B.prop_t, B.prop_g, B.plist, nprop, gmax};
+            const GainArgs ga{h.inc_off, h.inc, h.nwgt, h.vwgt, B.lam, B.lam1, part, B.bw, B.bstamp, stamp, lmax,
+                              mseed, level, r, s, prm.lp_subrounds, n, B.prop_t, B.prop_g, B.plist, nprop, gmax,
+                              B.pw, k};
+            auto account_gains = [&](int kid, const uint32_t *lst, uint32_t cnt) {
+                if (!accounting(kid)) return;
+                Timing &T = timing();
+                ++T.stamp;
+                k_account_gains<KW><<<grid_for(cnt, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+                    ga, lst, cnt, T.marks, T.stamp, (unsigned long long *)T.acc_dev + kid);
+                HGP_LAUNCH_CHECK();
+            };
             if (dc[0]) {
+                account_gains(KID_GAINS_G1, B.dlists, dc[0]);
+                TimedLaunch tl(KID_GAINS_G1, st);
                 k_gains_group<KW, 1><<<grid_for(dc[0], BLOCK, FILL_BLOCKS * 2), BLOCK, 0, st>>>(ga, B.dlists, dc[0]);
                 HGP_LAUNCH_CHECK();
             }
             if (dc[1]) {
+                account_gains(KID_GAINS_G8, B.dlists + doff[1], dc[1]);
+                TimedLaunch tl(KID_GAINS_G8, st);
                 k_gains_group<KW, 8><<<grid_for(dc[1], BLOCK / 8, FILL_BLOCKS * 2), BLOCK, 0, st>>>(
                     ga, B.dlists + doff[1], dc[1]);
                 HGP_LAUNCH_CHECK();
             }
             if (dc[2]) {
+                account_gains(KID_GAINS_G64, B.dlists + doff[2], dc[2]);
+                TimedLaunch tl(KID_GAINS_G64, st);
                 k_gains_group<KW, 64><<<grid_for(dc[2], BLOCK / 64, FILL_BLOCKS * 2), BLOCK, 0, st>>>(
                     ga, B.dlists + doff[2], dc[2]);
                 HGP_LAUNCH_CHECK();
@@ -876,62 +1020,78 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             const int gb = bits_for(G);
             KeyLayout L;
             L.kmask = (1u << kb) - 1u;
-            if (kb == 0) L.kmask = 0;
             L.G = G;
-            if (np <= (uint32_t)FUSED_MAX && 2 * kb + gb + ub <= 64) {
-                L.with_u = true;
-                L.sh_u = 0; L.sh_g = ub; L.sh_t = ub + gb; L.sh_s = ub + gb + kb;
-                HGP_CHECK_HIP(hipMemsetAsync(ntouched, 0, sizeof(uint32_t) * 2, st));  // ntouched, nlong
-                k_lp_fused<<<1, FUSED_THREADS, 0, st>>>(B.plist, np, B.prop_t, B.prop_g, L, k, h.vwgt, h.inc_off,
-                                                        h.inc, part, B.bw, lmax, B.tstamp, stamp, B.tlist, ntouched,
-                                                        moves);
-                HGP_LAUNCH_CHECK();
-                k_lp_update<KW><<<FILL_BLOCKS / 8, BLOCK, 0, st>>>(h.pin_off, h.pins, B.tlist, ntouched, h.nwgt, part,
-                                                                   B.lam, B.lam1, B.f, B.longl, nlong);
-                HGP_LAUNCH_CHECK();
-                k_conn_long<KW><<<FILL_BLOCKS / 8, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part,
-                                                                   B.lam, B.lam1, B.f, true);
-                HGP_LAUNCH_CHECK();
-                continue;
-            }
-            uint64_t *kk = B.keys;
-            uint32_t *vv = B.vals;
-            if (2 * kb + gb + ub <= 64) {
-                L.with_u = true;
-                L.sh_u = 0; L.sh_g = ub; L.sh_t = ub + gb; L.sh_s = ub + gb + kb;
-                k_lp_keys<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.plist, np, part, B.prop_t, B.prop_g, L,
-                                                                             kk, vv, false);
-                HGP_LAUNCH_CHECK();
-                radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, np, 0, 2 * kb + gb + ub, st);
-            } else {
-                L.with_u = false;
-                L.sh_u = 0; L.sh_g = 0; L.sh_t = gb; L.sh_s = gb + kb;
-                k_u_only_keys<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.plist, np, kk, vv);
-                HGP_LAUNCH_CHECK();
-                radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, np, 0, ub, st);
-                k_lp_keys<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.plist, np, part, B.prop_t, B.prop_g,
-                                                                             L, kk, vv, true);
-                HGP_LAUNCH_CHECK();
-                uint64_t *ka = (kk == B.keys) ? B.keys_alt : B.keys;
-                uint32_t *va = (vv == B.vals) ? B.vals_alt : B.vals;
-                radix_sort_pairs<uint64_t>(A, &kk, &vv, ka, va, np, 0, 2 * kb + gb, st);
-            }
-            scan_apply<uint64_t>(A, np, SortedWeight{vv, h.vwgt}, StoreIncl{B.incl}, (uint64_t *)nullptr, st);
-            HGP_CHECK_HIP(hipMemsetAsync(B.seg_start, 0, sizeof(uint32_t) * k * k, st));
-            HGP_CHECK_HIP(hipMemsetAsync(B.seg_end, 0, sizeof(uint32_t) * k * k, st));
-            HGP_CHECK_HIP(hipMemsetAsync(B.best, 0, sizeof(unsigned long long) * k * k, st));
-            k_pair_bounds<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, np, L, k, B.seg_start, B.seg_end);
-            HGP_LAUNCH_CHECK();
-            k_lp_select<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, np, L, k, B.seg_start, B.seg_end,
-                                                                           B.incl, B.bw, lmax, B.best);
-            HGP_LAUNCH_CHECK();
+            // pairs whose whole move sets are feasible: applied directly
             HGP_CHECK_HIP(hipMemsetAsync(ntouched, 0, sizeof(uint32_t) * 2, st));  // ntouched, nlong
-            k_lp_apply<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, np, L, k, B.seg_start, B.best,
-                                                                          h.vwgt, h.inc_off, h.inc, part, B.bw,
-                                                                          B.tstamp, stamp, B.tlist, ntouched, moves);
+            HGP_CHECK_HIP(hipMemsetAsync(nslow, 0, sizeof(uint32_t) * 2, st));     // nslow, nmov
+            HGP_CHECK_HIP(hipMemsetAsync(B.dbw_g, 0, sizeof(int64_t) * k, st));
+            k_lp_fast<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.plist, nprop, B.prop_t, B.pw, k, h.vwgt,
+                                                                         part, B.bw, lmax, B.dbw_g, B.mlist, nmov,
+                                                                         B.slow, nslow);
             HGP_LAUNCH_CHECK();
-            k_lp_update<KW><<<FILL_BLOCKS, BLOCK, 0, st>>>(h.pin_off, h.pins, B.tlist, ntouched, h.nwgt, part, B.lam,
-                                                           B.lam1, B.f, B.longl, nlong);
+            // the other pairs: sorted two-pointer walk over the slow list
+            uint32_t ns = np;  // upper bound unless read back
+            const bool fits = 2 * kb + gb + ub <= 64;
+            if (!(np <= (uint32_t)FUSED_MAX && fits)) {
+                HGP_CHECK_HIP(hipMemcpyAsync(&ns, nslow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+                HGP_CHECK_HIP(hipStreamSynchronize(st));
+            }
+            if (ns <= (uint32_t)FUSED_MAX && fits) {
+                L.with_u = true;
+                L.sh_u = 0; L.sh_g = ub; L.sh_t = ub + gb; L.sh_s = ub + gb + kb;
+                if (accounting(KID_LP_FUSED))  // per proposal: list, block, target, gain, weight; block weights
+                    timing().acc_host[KID_LP_FUSED] += 20.0 * ns + 24.0 * k;
+                TimedLaunch tl(KID_LP_FUSED, st);
+                k_lp_fused<<<1, FUSED_THREADS, 0, st>>>(B.slow, nslow, B.dbw_g, B.prop_t, B.prop_g, L, k, h.vwgt,
+                                                        h.inc_off, h.inc, part, B.bw, lmax, B.mlist, nmov);
+                HGP_LAUNCH_CHECK();
+            } else {
+                const uint32_t *pl = B.slow;
+                uint64_t *kk = B.keys;
+                uint32_t *vv = B.vals;
+                if (fits) {
+                    L.with_u = true;
+                    L.sh_u = 0; L.sh_g = ub; L.sh_t = ub + gb; L.sh_s = ub + gb + kb;
+                    k_lp_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(pl, ns, part, B.prop_t, B.prop_g,
+                                                                                 L, kk, vv, false);
+                    HGP_LAUNCH_CHECK();
+                    radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, 2 * kb + gb + ub, st);
+                } else {
+                    L.with_u = false;
+                    L.sh_u = 0; L.sh_g = 0; L.sh_t = gb; L.sh_s = gb + kb;
+                    k_u_only_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(pl, ns, kk, vv);
+                    HGP_LAUNCH_CHECK();
+                    radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, ub, st);
+                    k_lp_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(pl, ns, part, B.prop_t, B.prop_g,
+                                                                                 L, kk, vv, true);
+                    HGP_LAUNCH_CHECK();
+                    uint64_t *ka = (kk == B.keys) ? B.keys_alt : B.keys;
+                    uint32_t *va = (vv == B.vals) ? B.vals_alt : B.vals;
+                    radix_sort_pairs<uint64_t>(A, &kk, &vv, ka, va, ns, 0, 2 * kb + gb, st);
+                }
+                scan_apply<uint64_t>(A, ns, SortedWeight{vv, h.vwgt}, StoreIncl{B.incl}, (uint64_t *)nullptr, st);
+                HGP_CHECK_HIP(hipMemsetAsync(B.seg_start, 0, sizeof(uint32_t) * k * k, st));
+                HGP_CHECK_HIP(hipMemsetAsync(B.seg_end, 0, sizeof(uint32_t) * k * k, st));
+                HGP_CHECK_HIP(hipMemsetAsync(B.best, 0, sizeof(unsigned long long) * k * k, st));
+                if (ns) {
+                    k_pair_bounds<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, ns, L, k, B.seg_start,
+                                                                                     B.seg_end);
+                    HGP_LAUNCH_CHECK();
+                    k_lp_select<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, ns, L, k, B.seg_start,
+                                                                                   B.seg_end, B.incl, B.bw, lmax,
+                                                                                   B.best);
+                    HGP_LAUNCH_CHECK();
+                    k_lp_apply<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, ns, L, k, B.seg_start,
+                                                                                  B.best, h.vwgt, part, B.bw, B.mlist,
+                                                                                  nmov);
+                    HGP_LAUNCH_CHECK();
+                }
+                k_add_dbw<<<1, 256, 0, st>>>(B.bw, B.dbw_g, k);
+                HGP_LAUNCH_CHECK();
+            }
+            k_lp_update_movers<KW, 16><<<FILL_BLOCKS / 2, BLOCK, 0, st>>>(
+                h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, h.nwgt, part, B.lam, B.lam1, B.tstamp, stamp, B.f,
+                B.longl, nlong, moves);
             HGP_LAUNCH_CHECK();
             k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part,
                                                                B.lam, B.lam1, B.f, true);

@@ -1,0 +1,50 @@
+// Measurement support: per-kernel HIP-event timing on the launch stream and
+// exact accounting of the compulsory (algorithmic) bytes of each launch.
+// Host-side state only; nothing here runs unless a caller enables it.
+#pragma once
+#include "common.h"
+#include <vector>
+
+namespace hgp {
+
+enum KernelId : int {
+    KID_RATE_G8 = 0,   // k_rate_group<8, 64>: rating, groups of 8 lanes
+    KID_RATE_G16,      // k_rate_group<16, 256>
+    KID_RATE_G64,      // k_rate_group<64, 1024>
+    KID_RATE_BLOCK,    // k_rate_block (LDS and global tables)
+    KID_GAINS_G1,      // k_gains_group<*, 1>
+    KID_GAINS_G8,      // k_gains_group<*, 8>
+    KID_GAINS_G64,     // k_gains_group<*, 64>
+    KID_LP_FUSED,      // k_lp_fused
+    KID_MARK_BOUNDARY, // k_mark_boundary
+    KID_COUNT
+};
+
+struct Timing {
+    uint32_t mask = 0;         // kernels whose launches are timed
+    bool account = false;      // run the byte-accounting kernels
+    uint64_t *acc_dev = nullptr;   // device [KID_COUNT] byte accumulators
+    uint32_t *marks = nullptr;     // device stamp arrays for accounting
+    size_t marks_len = 0;          // entries per stamp array
+    uint32_t stamp = 0;
+    std::vector<hipEvent_t> pool;  // free events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KID_COUNT];
+    uint64_t launches[KID_COUNT] = {};
+    double acc_host[KID_COUNT] = {};  // bytes counted on the host (sizes known there)
+    uint64_t acc_launches[KID_COUNT] = {};
+};
+
+Timing &timing();
+
+// Records an event pair around the enclosed launch when kernel `kid` is timed.
+struct TimedLaunch {
+    int kid;
+    hipStream_t st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TimedLaunch(int k, hipStream_t s);
+    ~TimedLaunch();
+};
+
+inline bool accounting(int kid) { return timing().account && (timing().mask >> kid & 1u); }
+
+}  // namespace hgp
