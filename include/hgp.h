@@ -184,16 +184,15 @@ hgp_status hgp_partition(const hgp_hg *h, const hgp_params *prm, uint32_t *part,
                          void *ws, size_t ws_bytes, void *stream);
 
 /* Measurement support (host).  Kernel ids for the timing calls below. */
-#define HGP_KID_RATE_G8 0       /* rating, groups of 8 lanes, 64-entry tables    */
-#define HGP_KID_RATE_G16 1      /* rating, groups of 16 lanes, 256-entry tables  */
-#define HGP_KID_RATE_G64 2      /* rating, one wave, 1024-entry tables           */
-#define HGP_KID_RATE_BLOCK 3    /* rating, one workgroup per candidate           */
-#define HGP_KID_GAINS_G1 4      /* LP gains, one lane per node                   */
-#define HGP_KID_GAINS_G8 5      /* LP gains, 8 lanes per node                    */
-#define HGP_KID_GAINS_G64 6     /* LP gains, one wave per node                   */
-#define HGP_KID_LP_FUSED 7      /* LP selection + apply, one workgroup           */
-#define HGP_KID_MARK_BOUNDARY 8 /* LP boundary marking                           */
-#define HGP_KID_COUNT 9
+#define HGP_KID_RATE_G8 0    /* rating, groups of 8 lanes, 64-entry tables    */
+#define HGP_KID_RATE_G16 1   /* rating, groups of 16 lanes, 256-entry tables  */
+#define HGP_KID_RATE_G64 2   /* rating, one wave, 1024-entry tables           */
+#define HGP_KID_RATE_BLOCK 3 /* rating, one workgroup per candidate           */
+#define HGP_KID_GAINS 4      /* LP best moves                                 */
+#define HGP_KID_LP_FAST 5    /* LP whole-pair approvals                       */
+#define HGP_KID_LP_FUSED 6   /* LP sorted pair walk, one workgroup            */
+#define HGP_KID_LP_UPDATE 7  /* LP connectivity update of touched nets        */
+#define HGP_KID_COUNT 8
 
 /* Host.  Bytes of device scratch that accounting needs for levels of at most
  * n_max vertices and m_max nets. */

@@ -98,7 +98,9 @@ template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_conn_long(const uint32_t *pin_off, const uint32_t *pins,
                                                      const uint32_t *list, const uint32_t *count_dev,
                                                      const int32_t *nwgt, const uint32_t *part, uint64_t *lam,
-                                                     uint64_t *lam1, int64_t *f, bool delta) {
+                                                     uint64_t *lam1, int64_t *f, bool delta, uint32_t *bcnt,
+                                                     const uint32_t *abort) {
+    if (abort && *abort) return;
     const uint32_t count = *count_dev;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
@@ -127,15 +129,21 @@ __global__ __launch_bounds__(BLOCK) void k_conn_long(const uint32_t *pin_off, co
                 once[q] |= oo;
             }
         }
+        const int lnew = popc_bits<KW>(once);
+        const int lold = delta ? popc_bits<KW>(lam + (size_t)e * KW) : 0;  // read before lane 0 rewrites
+        wave_sync();
         if (__lane_id() == 0) {
-            int64_t d = lam_cost(popc_bits<KW>(once));
-            if (delta) d -= lam_cost(popc_bits<KW>(lam + (size_t)e * KW));
+            int64_t d = lam_cost(lnew) - (delta ? lam_cost(lold) : 0);
 #pragma unroll
             for (int q = 0; q < KW; ++q) {
                 lam[(size_t)e * KW + q] = once[q];
                 lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
             }
             if (d) atomic_add_i64(f, d * nwgt[e]);
+        }
+        if (delta && bcnt && (lnew > 1) != (lold > 1)) {
+            const uint32_t dl = lnew > 1 ? 1u : 0xFFFFFFFFu;
+            for (uint32_t j = __lane_id(); j < len; j += WAVE) atomicAdd(&bcnt[pins[b + j]], dl);
         }
     }
 }
@@ -161,14 +169,14 @@ struct GainArgs {
     const uint64_t *lam, *lam1;
     const uint32_t *part;
     const int64_t *bw;
-    const uint32_t *bstamp;
-    uint32_t stamp;
+    const uint32_t *bcnt;  // incident nets with lambda > 1 (boundary iff > 0)
     int64_t lmax;
     uint64_t mseed;
     uint32_t level, round, sub, S, n;
     uint32_t *prop_t, *prop_g, *plist, *nprop, *gmax;
     uint32_t *pw;  // [k*k] total weight proposed per ordered block pair
     uint32_t k;
+    const uint32_t *abort;  // set when the round must be resumed by the host
 };
 
 // Called by every lane of the wave (uniformly); `has` is set by at most one
@@ -197,31 +205,22 @@ __device__ inline T group_sum(T v) {
     return v;
 }
 
-// Boundary nodes of the snapshot: pins of nets with lambda > 1.  Other nodes
-// have no move of positive gain (all their nets lie in their own block).
-template <int KW>
-__global__ void k_mark_boundary(const uint32_t *pin_off, const uint32_t *pins, uint32_t m, const uint64_t *lam,
-                                uint32_t *bstamp, uint32_t stamp) {
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
-        if (popc_bits<KW>(lam + (size_t)e * KW) < 2) continue;
-        for (uint32_t j = pin_off[e]; j < pin_off[e + 1]; ++j) bstamp[pins[j]] = stamp;
-    }
-}
-
 // Groups of G lanes per node (G = 1, 8 or 64 by degree class); the lanes of a
 // group split the incident nets.  Best move: largest positive gain among the
-// blocks of the union of Lambda(e), ties to the smaller block.
+// blocks of the union of Lambda(e), ties to the smaller block.  Only boundary
+// nodes (an incident net with lambda > 1) can have a positive gain.
 template <int KW, int G>
-__global__ __launch_bounds__(BLOCK) void k_gains_group(GainArgs a, const uint32_t *list, uint32_t count) {
+__device__ inline void gains_body(const GainArgs &a, const uint32_t *list, uint32_t count, uint32_t blk,
+                                  uint32_t nblk) {
     constexpr int GPB = BLOCK / G;
     const uint32_t g = threadIdx.x / G, l = threadIdx.x % G;
-    for (uint32_t base = blockIdx.x * GPB; base < count; base += gridDim.x * GPB) {
+    for (uint32_t base = blk * GPB; base < count; base += nblk * GPB) {
         const uint32_t idx = base + g;
         uint32_t u = 0, best_t = NONE, best_g = 0, s = 0;
         bool act = idx < count;
         if (act) {
             u = list[idx];
-            act = a.bstamp[u] == a.stamp && tag_hash(a.mseed, 3, a.level, a.round, u) % a.S == a.sub;
+            act = a.bcnt[u] > 0 && tag_hash(a.mseed, 3, a.level, a.round, u) % a.S == a.sub;
         }
         if (act) {  // uniform within the group
             const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
@@ -269,6 +268,39 @@ __global__ __launch_bounds__(BLOCK) void k_gains_group(GainArgs a, const uint32_
     }
 }
 
+// One launch for the three degree classes: blocks [0, nb0) take class 0
+// (1 lane per node), [nb0, nb0 + nb1) class 1 (8 lanes), the rest class 2 (64).
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_gains(GainArgs a, const uint32_t *lists, uint32_t c0, uint32_t c1,
+                                                 uint32_t c2, uint32_t nb0, uint32_t nb1, uint32_t nb2) {
+    if (*a.abort) return;
+    const uint32_t b = blockIdx.x;
+    if (b < nb0) gains_body<KW, 1>(a, lists, c0, b, nb0);
+    else if (b < nb0 + nb1) gains_body<KW, 8>(a, lists + c0, c1, b - nb0, nb1);
+    else gains_body<KW, 64>(a, lists + c0 + c1, c2, b - nb0 - nb1, nb2);
+}
+
+// Boundary count of every node from scratch (once per level).
+template <int KW>
+__global__ void k_init_bcnt(const uint32_t *inc_off, const uint32_t *inc, uint32_t n, const uint64_t *lam,
+                            uint32_t *bcnt) {
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        uint32_t c = 0;
+        for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) c += popc_bits<KW>(lam + (size_t)inc[j] * KW) > 1;
+        bcnt[u] = c;
+    }
+}
+
+// Per-sub-round counters and pair sums back to zero.
+__global__ void k_lp_reset(uint32_t *scal, uint32_t *pw, uint32_t kk, int64_t *dbw_g, uint32_t k) {
+    if (scal[15]) return;  // the round was cut short: later sub-rounds are replayed
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+    if (tid < 4) scal[tid] = 0;                  // nprop, gmax, ntouched, nlong
+    if (tid == 4) { scal[13] = 0; scal[14] = 0; }  // nslow, nmov
+    for (uint32_t i = tid; i < kk; i += nt) pw[i] = 0;
+    for (uint32_t i = tid; i < k; i += nt) dbw_g[i] = 0;
+}
+
 // Measurement only: compulsory bytes of one gains launch (list, boundary
 // stamp, and for every candidate its node data, incidence list and the
 // weight / Lambda / Lambda1 of every distinct incident net, counted once).
@@ -279,32 +311,12 @@ __global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs a, const uint3
     unsigned long long bytes = 0;
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
         const uint32_t u = list[idx];
-        bytes += 4 + 4;  // list entry, boundary stamp
-        if (!(a.bstamp[u] == a.stamp && tag_hash(a.mseed, 3, a.level, a.round, u) % a.S == a.sub)) continue;
+        bytes += 4 + 4;  // list entry, boundary count
+        if (!(a.bcnt[u] > 0 && tag_hash(a.mseed, 3, a.level, a.round, u) % a.S == a.sub)) continue;
         const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
         bytes += 4 + 4 + 4 + 4ull * (j1 - j0);  // inc_off, part, vwgt, incidence list
         for (uint32_t j = j0; j < j1; ++j)
             if (atomicExch(&nmark[a.inc[j]], stamp) != stamp) bytes += 4 + 16ull * KW;
-    }
-    bytes = wave_sum(bytes);
-    if (__lane_id() == 0) red[threadIdx.x / WAVE] = bytes;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
-        atomicAdd(acc, t);
-    }
-}
-
-// Measurement only: compulsory bytes of one boundary-marking launch.
-template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_account_mark(const uint32_t *pin_off, uint32_t m, const uint64_t *lam,
-                                                        unsigned long long *acc) {
-    __shared__ unsigned long long red[BLOCK / WAVE];
-    unsigned long long bytes = 0;
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
-        bytes += 8ull * KW;  // Lambda
-        if (popc_bits<KW>(lam + (size_t)e * KW) >= 2) bytes += 4 + 8ull * (pin_off[e + 1] - pin_off[e]);
     }
     bytes = wave_sum(bytes);
     if (__lane_id() == 0) red[threadIdx.x / WAVE] = bytes;
@@ -524,7 +536,8 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
                                                    const uint32_t *prop_t, const uint32_t *pw, uint32_t k,
                                                    const int32_t *vwgt, uint32_t *part, const int64_t *bw,
                                                    int64_t lmax, int64_t *dbw_g, uint32_t *mlist, uint32_t *moves,
-                                                   uint32_t *slow, uint32_t *nslow) {
+                                                   uint32_t *slow, uint32_t *nslow, const uint32_t *abort) {
+    if (*abort) return;
     __shared__ int64_t dbw[256];
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
     __syncthreads();
@@ -602,7 +615,9 @@ __device__ inline uint32_t lcount_below(const LSeg &v, uint32_t x, bool strict) 
 
 __global__ __launch_bounds__(FUSED_THREADS) void k_lp_fused(const uint32_t *plist, const uint32_t *np_dev,
                                                             const int64_t *dbw_g, const uint32_t *prop_t,
-                                                            const uint32_t *prop_g, KeyLayout L, uint32_t k,
+                                                            const uint32_t *prop_g, const uint32_t *gmax_dev,
+                                                            int kb_bits, int ub_bits, uint32_t *abort, uint32_t sub_id,
+                                                            uint32_t k,
                                                             const int32_t *vwgt, const uint32_t *inc_off,
                                                             const uint32_t *inc, uint32_t *part, int64_t *bw,
                                                             int64_t lmax, uint32_t *mlist_g, uint32_t *moves) {
@@ -613,14 +628,28 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_lp_fused(const uint32_t *plis
     __shared__ int64_t dbw[256];
     __shared__ uint32_t wsum[FUSED_THREADS / WAVE];
     const uint32_t tid = threadIdx.x;
+    if (*abort) return;
     const uint32_t np = *np_dev;
-    if (np == 0 || np > (uint32_t)FUSED_MAX) {  // nothing to sort (the host never sends more than FUSED_MAX)
-        if (np == 0)
-            for (uint32_t b = tid; b < k; b += FUSED_THREADS)
-                if (dbw_g[b]) bw[b] += dbw_g[b];
+    if (np == 0) {
+        for (uint32_t b = tid; b < k; b += FUSED_THREADS)
+            if (dbw_g[b]) bw[b] += dbw_g[b];
         return;
     }
-    const int kb = L.sh_s - L.sh_t;
+    // key (s, t, G-g, u) of this sub-round's gains
+    const uint32_t G = *gmax_dev;
+    const int gb = G ? 32 - __clz(G) : 0;
+    if (np > (uint32_t)FUSED_MAX || 2 * kb_bits + gb + ub_bits > 64) {
+        // beyond one workgroup: the host runs the device-wide path for this
+        // sub-round and replays the rest of the round (nothing applied here)
+        if (tid == 0) { abort[0] = 1; abort[1] = sub_id; }
+        return;
+    }
+    KeyLayout L;
+    L.kmask = (1u << kb_bits) - 1u;
+    L.G = G;
+    L.with_u = true;
+    L.sh_u = 0; L.sh_g = ub_bits; L.sh_t = ub_bits + gb; L.sh_s = ub_bits + gb + kb_bits;
+    const int kb = kb_bits;
     uint32_t n2 = 1;
     while (n2 < np) n2 <<= 1;
     for (uint32_t i = tid; i < n2; i += FUSED_THREADS) {
@@ -747,6 +776,38 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_lp_fused(const uint32_t *plis
     }
 }
 
+// Measurement only: compulsory bytes of one update launch (mover list and
+// incidence lists; for every distinct touched net its stamp, offsets, pins,
+// their blocks, weight, old Lambda and new Lambda / Lambda1).
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_account_update(const uint32_t *pin_off, const uint32_t *inc_off,
+                                                          const uint32_t *inc, const uint32_t *mlist,
+                                                          const uint32_t *nmov, uint32_t *nmark, uint32_t stamp,
+                                                          unsigned long long *acc) {
+    __shared__ unsigned long long red[BLOCK / WAVE];
+    unsigned long long bytes = 0;
+    const uint32_t cnt = *nmov;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < cnt; idx += gridDim.x * blockDim.x) {
+        const uint32_t u = mlist[idx];
+        const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
+        bytes += 4 + 8 + 4ull * (j1 - j0);
+        for (uint32_t j = j0; j < j1; ++j) {
+            const uint32_t e = inc[j];
+            if (atomicExch(&nmark[e], stamp) == stamp) continue;
+            const uint32_t len = pin_off[e + 1] - pin_off[e];
+            bytes += 8 + 8 + 8ull * len + 4 + 24ull * KW;
+        }
+    }
+    bytes = wave_sum(bytes);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = bytes;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+        atomicAdd(acc, t);
+    }
+}
+
 // Lambda / Lambda1 of every net of a moved node, recomputed once: G lanes per
 // mover; the first lane to stamp a net in this sub-round owns it.  Nets of
 // more than 64 pins are forwarded to the wave kernel.  The objective changes
@@ -759,7 +820,9 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
                                                             const int32_t *nwgt, const uint32_t *part,
                                                             uint64_t *lam, uint64_t *lam1, uint32_t *tstamp,
                                                             uint32_t stamp, int64_t *f, uint32_t *longl,
-                                                            uint32_t *nlong, uint32_t *moves) {
+                                                            uint32_t *nlong, uint32_t *moves, uint32_t *bcnt,
+                                                            const uint32_t *abort) {
+    if (*abort) return;
     __shared__ int64_t red[BLOCK / WAVE];
     constexpr int GPB = BLOCK / G;
     const uint32_t cnt = *nmov;
@@ -778,13 +841,18 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
             }
             uint64_t once[KW], twice[KW];
             net_bits<KW>(pins, b, len, part, once, twice);
-            int64_t d = lam_cost(popc_bits<KW>(once)) - lam_cost(popc_bits<KW>(lam + (size_t)e * KW));
+            const int lnew = popc_bits<KW>(once), lold = popc_bits<KW>(lam + (size_t)e * KW);
+            int64_t d = lam_cost(lnew) - lam_cost(lold);
 #pragma unroll
             for (int q = 0; q < KW; ++q) {
                 lam[(size_t)e * KW + q] = once[q];
                 lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
             }
             acc += d * nwgt[e];
+            if ((lnew > 1) != (lold > 1)) {  // cut status flipped: boundary counts of its pins
+                const uint32_t delta = lnew > 1 ? 1u : 0xFFFFFFFFu;
+                for (uint32_t q = b; q < b + len; ++q) atomicAdd(&bcnt[pins[q]], delta);
+            }
         }
     }
     acc = wave_sum(acc);
@@ -842,7 +910,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update(const uint32_t *pin_off, co
 struct RefineBufs {
     uint64_t *lam, *lam1;
     int64_t *f, *bw;
-    uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bstamp, *tlist, *scal, *pw, *slow, *mlist;
+    uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *tlist, *scal, *pw, *slow, *mlist;
     int64_t *dbw_g;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt, *seg_start, *seg_end;
@@ -857,13 +925,13 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.bw = A.alloc<int64_t>(k);
     B.longl = A.alloc<uint32_t>(m);
     B.dlists = A.alloc<uint32_t>(n);
-    B.bstamp = A.alloc<uint32_t>(n);
+    B.bcnt = A.alloc<uint32_t>(n);
     B.plist = A.alloc<uint32_t>(n);
     B.prop_t = A.alloc<uint32_t>(n);
     B.prop_g = A.alloc<uint32_t>(n);
     B.tstamp = A.alloc<uint32_t>(m);
     B.tlist = A.alloc<uint32_t>(m);
-    B.scal = A.alloc<uint32_t>(16);
+    B.scal = A.alloc<uint32_t>(32);
     B.keys = A.alloc<uint64_t>(n);
     B.keys_alt = A.alloc<uint64_t>(n);
     B.incl = A.alloc<uint64_t>(n);
@@ -896,7 +964,7 @@ static void build_conn(const hgp_hg &h, const uint32_t *part, RefineBufs &B, hip
                                                                              B.lam, B.lam1, B.f, B.longl, B.scal + 12);
         HGP_LAUNCH_CHECK();
         k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, B.scal + 12, h.nwgt, part,
-                                                           B.lam, B.lam1, B.f, false);
+                                                           B.lam, B.lam1, B.f, false, nullptr, nullptr);
         HGP_LAUNCH_CHECK();
     }
 }
@@ -949,7 +1017,8 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     build_conn<KW>(h, part, B, st);
     block_weights(part, h.vwgt, n, k, B.bw, st);
     if (m) HGP_CHECK_HIP(hipMemsetAsync(B.tstamp, 0, sizeof(uint32_t) * m, st));
-    HGP_CHECK_HIP(hipMemsetAsync(B.bstamp, 0, sizeof(uint32_t) * n, st));
+    k_init_bcnt<KW><<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n, B.lam, B.bcnt);
+    HGP_LAUNCH_CHECK();
     // degree classes of the nodes (lanes per node 1 / 8 / 64)
     HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * 3, st));
     k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt, dcur, B.dlists, false);
@@ -958,144 +1027,138 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     HGP_CHECK_HIP(hipMemcpyAsync(dc, dcnt, sizeof(dc), hipMemcpyDeviceToHost, st));
     HGP_CHECK_HIP(hipStreamSynchronize(st));
     for (int c = 0; c < 3; ++c) doff[c + 1] = doff[c] + dc[c];
+    const uint32_t nbg[3] = {dc[0] ? grid_for(dc[0], BLOCK, 2048) : 0u, dc[1] ? grid_for(dc[1], BLOCK / 8, 2048) : 0u,
+                             dc[2] ? grid_for(dc[2], BLOCK / 64, 2048) : 0u};
     HGP_CHECK_HIP(hipMemcpyAsync(dcur, doff, sizeof(uint32_t) * 3, hipMemcpyHostToDevice, st));
     k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt, dcur, B.dlists, true);
     HGP_LAUNCH_CHECK();
 
     const int kb = bits_for(k - 1), ub = bits_for(n ? n - 1 : 0);
-    uint32_t stamp = 0;
-    for (uint32_t r = 0; r < prm.lp_rounds; ++r) {
-        HGP_CHECK_HIP(hipMemsetAsync(moves, 0, sizeof(uint32_t), st));
-        for (uint32_t s = 0; s < prm.lp_subrounds; ++s) {
-            ++stamp;
-            HGP_CHECK_HIP(hipMemsetAsync(nprop, 0, sizeof(uint32_t) * 2, st));
-            HGP_CHECK_HIP(hipMemsetAsync(B.pw, 0, sizeof(uint32_t) * k * k, st));
-            if (m) {
-                if (accounting(KID_MARK_BOUNDARY)) {
-                    k_account_mark<KW><<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
-                        h.pin_off, m, B.lam, (unsigned long long *)timing().acc_dev + KID_MARK_BOUNDARY);
-                    HGP_LAUNCH_CHECK();
-                }
-                TimedLaunch tl(KID_MARK_BOUNDARY, st);
-                k_mark_boundary<KW><<<grid_for(m, BLOCK, FILL_BLOCKS * 2), BLOCK, 0, st>>>(h.pin_off, h.pins, m, B.lam,
-                                                                                          B.bstamp, stamp);
-                HGP_LAUNCH_CHECK();
-            }
-            const GainArgs ga{h.inc_off, h.inc, h.nwgt, h.vwgt, B.lam, B.lam1, part, B.bw, B.bstamp, stamp, lmax,
-                              mseed, level, r, s, prm.lp_subrounds, n, B.prop_t, B.prop_g, B.plist, nprop, gmax,
-                              B.pw, k};
-            auto account_gains = [&](int kid, const uint32_t *lst, uint32_t cnt) {
-                if (!accounting(kid)) return;
-                Timing &T = timing();
-                ++T.stamp;
-                k_account_gains<KW><<<grid_for(cnt, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
-                    ga, lst, cnt, T.marks, T.stamp, (unsigned long long *)T.acc_dev + kid);
-                HGP_LAUNCH_CHECK();
-            };
-            if (dc[0]) {
-                account_gains(KID_GAINS_G1, B.dlists, dc[0]);
-                TimedLaunch tl(KID_GAINS_G1, st);
-                k_gains_group<KW, 1><<<grid_for(dc[0], BLOCK, FILL_BLOCKS * 2), BLOCK, 0, st>>>(ga, B.dlists, dc[0]);
-                HGP_LAUNCH_CHECK();
-            }
-            if (dc[1]) {
-                account_gains(KID_GAINS_G8, B.dlists + doff[1], dc[1]);
-                TimedLaunch tl(KID_GAINS_G8, st);
-                k_gains_group<KW, 8><<<grid_for(dc[1], BLOCK / 8, FILL_BLOCKS * 2), BLOCK, 0, st>>>(
-                    ga, B.dlists + doff[1], dc[1]);
-                HGP_LAUNCH_CHECK();
-            }
-            if (dc[2]) {
-                account_gains(KID_GAINS_G64, B.dlists + doff[2], dc[2]);
-                TimedLaunch tl(KID_GAINS_G64, st);
-                k_gains_group<KW, 64><<<grid_for(dc[2], BLOCK / 64, FILL_BLOCKS * 2), BLOCK, 0, st>>>(
-                    ga, B.dlists + doff[2], dc[2]);
-                HGP_LAUNCH_CHECK();
-            }
-            uint32_t hv[2];
-            HGP_CHECK_HIP(hipMemcpyAsync(hv, nprop, sizeof(hv), hipMemcpyDeviceToHost, st));
-            HGP_CHECK_HIP(hipStreamSynchronize(st));
-            const uint32_t np = hv[0], G = hv[1];
-            if (np == 0) continue;
-            const int gb = bits_for(G);
-            KeyLayout L;
-            L.kmask = (1u << kb) - 1u;
-            L.G = G;
-            // pairs whose whole move sets are feasible: applied directly
-            HGP_CHECK_HIP(hipMemsetAsync(ntouched, 0, sizeof(uint32_t) * 2, st));  // ntouched, nlong
-            HGP_CHECK_HIP(hipMemsetAsync(nslow, 0, sizeof(uint32_t) * 2, st));     // nslow, nmov
-            HGP_CHECK_HIP(hipMemsetAsync(B.dbw_g, 0, sizeof(int64_t) * k, st));
-            k_lp_fast<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.plist, nprop, B.prop_t, B.pw, k, h.vwgt,
-                                                                         part, B.bw, lmax, B.dbw_g, B.mlist, nmov,
-                                                                         B.slow, nslow);
-            HGP_LAUNCH_CHECK();
-            // the other pairs: sorted two-pointer walk over the slow list
-            uint32_t ns = np;  // upper bound unless read back
-            const bool fits = 2 * kb + gb + ub <= 64;
-            if (!(np <= (uint32_t)FUSED_MAX && fits)) {
-                HGP_CHECK_HIP(hipMemcpyAsync(&ns, nslow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-                HGP_CHECK_HIP(hipStreamSynchronize(st));
-            }
-            if (ns <= (uint32_t)FUSED_MAX && fits) {
+    uint32_t *abort = B.scal + 15;  // [2]: flag, sub-round that raised it (scal[16])
+    HGP_CHECK_HIP(hipMemsetAsync(abort, 0, sizeof(uint32_t) * 2, st));
+    const uint32_t S = prm.lp_subrounds;
+
+    // Device-wide selection of the slow pairs of sub-round (r, s): only after
+    // the one-workgroup path declined (its count exceeded FUSED_MAX or the key
+    // did not fit 64 bits).  The counts are read back here (the host has
+    // synchronised).
+    auto slow_path = [&](uint32_t ns, uint32_t G) {
+        const int gb = bits_for(G);
+        KeyLayout L;
+        L.kmask = (1u << kb) - 1u;
+        L.G = G;
+        const bool fits = 2 * kb + gb + ub <= 64;
+        const uint32_t *pl = B.slow;
+        uint64_t *kk = B.keys;
+        uint32_t *vv = B.vals;
+        if (ns) {
+            if (fits) {
                 L.with_u = true;
                 L.sh_u = 0; L.sh_g = ub; L.sh_t = ub + gb; L.sh_s = ub + gb + kb;
-                if (accounting(KID_LP_FUSED))  // per proposal: list, block, target, gain, weight; block weights
-                    timing().acc_host[KID_LP_FUSED] += 20.0 * ns + 24.0 * k;
-                TimedLaunch tl(KID_LP_FUSED, st);
-                k_lp_fused<<<1, FUSED_THREADS, 0, st>>>(B.slow, nslow, B.dbw_g, B.prop_t, B.prop_g, L, k, h.vwgt,
-                                                        h.inc_off, h.inc, part, B.bw, lmax, B.mlist, nmov);
+                k_lp_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(pl, ns, part, B.prop_t, B.prop_g, L, kk,
+                                                                             vv, false);
                 HGP_LAUNCH_CHECK();
+                radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, 2 * kb + gb + ub, st);
             } else {
-                const uint32_t *pl = B.slow;
-                uint64_t *kk = B.keys;
-                uint32_t *vv = B.vals;
-                if (fits) {
-                    L.with_u = true;
-                    L.sh_u = 0; L.sh_g = ub; L.sh_t = ub + gb; L.sh_s = ub + gb + kb;
-                    k_lp_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(pl, ns, part, B.prop_t, B.prop_g,
-                                                                                 L, kk, vv, false);
-                    HGP_LAUNCH_CHECK();
-                    radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, 2 * kb + gb + ub, st);
-                } else {
-                    L.with_u = false;
-                    L.sh_u = 0; L.sh_g = 0; L.sh_t = gb; L.sh_s = gb + kb;
-                    k_u_only_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(pl, ns, kk, vv);
-                    HGP_LAUNCH_CHECK();
-                    radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, ub, st);
-                    k_lp_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(pl, ns, part, B.prop_t, B.prop_g,
-                                                                                 L, kk, vv, true);
-                    HGP_LAUNCH_CHECK();
-                    uint64_t *ka = (kk == B.keys) ? B.keys_alt : B.keys;
-                    uint32_t *va = (vv == B.vals) ? B.vals_alt : B.vals;
-                    radix_sort_pairs<uint64_t>(A, &kk, &vv, ka, va, ns, 0, 2 * kb + gb, st);
-                }
-                scan_apply<uint64_t>(A, ns, SortedWeight{vv, h.vwgt}, StoreIncl{B.incl}, (uint64_t *)nullptr, st);
-                HGP_CHECK_HIP(hipMemsetAsync(B.seg_start, 0, sizeof(uint32_t) * k * k, st));
-                HGP_CHECK_HIP(hipMemsetAsync(B.seg_end, 0, sizeof(uint32_t) * k * k, st));
-                HGP_CHECK_HIP(hipMemsetAsync(B.best, 0, sizeof(unsigned long long) * k * k, st));
-                if (ns) {
-                    k_pair_bounds<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, ns, L, k, B.seg_start,
-                                                                                     B.seg_end);
-                    HGP_LAUNCH_CHECK();
-                    k_lp_select<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, ns, L, k, B.seg_start,
-                                                                                   B.seg_end, B.incl, B.bw, lmax,
-                                                                                   B.best);
-                    HGP_LAUNCH_CHECK();
-                    k_lp_apply<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, ns, L, k, B.seg_start,
-                                                                                  B.best, h.vwgt, part, B.bw, B.mlist,
-                                                                                  nmov);
-                    HGP_LAUNCH_CHECK();
-                }
-                k_add_dbw<<<1, 256, 0, st>>>(B.bw, B.dbw_g, k);
+                L.with_u = false;
+                L.sh_u = 0; L.sh_g = 0; L.sh_t = gb; L.sh_s = gb + kb;
+                k_u_only_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(pl, ns, kk, vv);
                 HGP_LAUNCH_CHECK();
+                radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, ub, st);
+                k_lp_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(pl, ns, part, B.prop_t, B.prop_g, L, kk,
+                                                                             vv, true);
+                HGP_LAUNCH_CHECK();
+                uint64_t *ka = (kk == B.keys) ? B.keys_alt : B.keys;
+                uint32_t *va = (vv == B.vals) ? B.vals_alt : B.vals;
+                radix_sort_pairs<uint64_t>(A, &kk, &vv, ka, va, ns, 0, 2 * kb + gb, st);
             }
+            scan_apply<uint64_t>(A, ns, SortedWeight{vv, h.vwgt}, StoreIncl{B.incl}, (uint64_t *)nullptr, st);
+            HGP_CHECK_HIP(hipMemsetAsync(B.seg_start, 0, sizeof(uint32_t) * k * k, st));
+            HGP_CHECK_HIP(hipMemsetAsync(B.seg_end, 0, sizeof(uint32_t) * k * k, st));
+            HGP_CHECK_HIP(hipMemsetAsync(B.best, 0, sizeof(unsigned long long) * k * k, st));
+            k_pair_bounds<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, ns, L, k, B.seg_start, B.seg_end);
+            HGP_LAUNCH_CHECK();
+            k_lp_select<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, ns, L, k, B.seg_start, B.seg_end,
+                                                                           B.incl, B.bw, lmax, B.best);
+            HGP_LAUNCH_CHECK();
+            k_lp_apply<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, ns, L, k, B.seg_start, B.best,
+                                                                          h.vwgt, part, B.bw, B.mlist, nmov);
+            HGP_LAUNCH_CHECK();
+        }
+        k_add_dbw<<<1, 256, 0, st>>>(B.bw, B.dbw_g, k);
+        HGP_LAUNCH_CHECK();
+    };
+    // Update of the nets touched by the sub-round's moves.
+    auto update = [&](uint32_t stamp) {
+        if (accounting(KID_LP_UPDATE)) {
+            Timing &T = timing();
+            ++T.stamp;
+            k_account_update<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, B.mlist, nmov, T.marks,
+                                                                    T.stamp,
+                                                                    (unsigned long long *)T.acc_dev + KID_LP_UPDATE);
+            HGP_LAUNCH_CHECK();
+        }
+        {
+            TimedLaunch tl(KID_LP_UPDATE, st);
             k_lp_update_movers<KW, 16><<<FILL_BLOCKS / 2, BLOCK, 0, st>>>(
-                h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, h.nwgt, part, B.lam, B.lam1, B.tstamp, stamp, B.f,
-                B.longl, nlong, moves);
+                h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, h.nwgt, part, B.lam, B.lam1, B.tstamp, stamp,
+                B.f, B.longl, nlong, moves, B.bcnt, abort);
             HGP_LAUNCH_CHECK();
-            k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part,
-                                                               B.lam, B.lam1, B.f, true);
+        }
+        k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part, B.lam,
+                                                           B.lam1, B.f, true, B.bcnt, abort);
+        HGP_LAUNCH_CHECK();
+    };
+    // One sub-round, entirely on the device (no host round trip).
+    auto subround = [&](uint32_t r, uint32_t s) {
+        const uint32_t stamp = 1 + r * S + s;
+        k_lp_reset<<<grid_for((size_t)k * k, BLOCK, 64), BLOCK, 0, st>>>(B.scal, B.pw, k * k, B.dbw_g, k);
+        HGP_LAUNCH_CHECK();
+        const GainArgs ga{h.inc_off, h.inc, h.nwgt, h.vwgt, B.lam, B.lam1, part, B.bw, B.bcnt, lmax, mseed, level, r,
+                          s, S, n, B.prop_t, B.prop_g, B.plist, nprop, gmax, B.pw, k, abort};
+        if (accounting(KID_GAINS)) {
+            Timing &T = timing();
+            ++T.stamp;
+            k_account_gains<KW><<<grid_for(dc[0] + dc[1] + dc[2], BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+                ga, B.dlists, dc[0] + dc[1] + dc[2], T.marks, T.stamp, (unsigned long long *)T.acc_dev + KID_GAINS);
             HGP_LAUNCH_CHECK();
+        }
+        if (nbg[0] + nbg[1] + nbg[2]) {
+            TimedLaunch tl(KID_GAINS, st);
+            k_gains<KW><<<nbg[0] + nbg[1] + nbg[2], BLOCK, 0, st>>>(ga, B.dlists, dc[0], dc[1], dc[2], nbg[0], nbg[1],
+                                                                    nbg[2]);
+            HGP_LAUNCH_CHECK();
+        }
+        {  // pairs whose whole move sets are feasible: applied directly
+            TimedLaunch tl(KID_LP_FAST, st);
+            k_lp_fast<<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(B.plist, nprop, B.prop_t, B.pw, k, h.vwgt, part, B.bw, lmax,
+                                                         B.dbw_g, B.mlist, nmov, B.slow, nslow, abort);
+            HGP_LAUNCH_CHECK();
+        }
+        {  // the other pairs: sorted two-pointer walk in one workgroup
+            TimedLaunch tl(KID_LP_FUSED, st);
+            k_lp_fused<<<1, FUSED_THREADS, 0, st>>>(B.slow, nslow, B.dbw_g, B.prop_t, B.prop_g, gmax, kb, ub, abort, s,
+                                                    k, h.vwgt, h.inc_off, h.inc, part, B.bw, lmax, B.mlist, nmov);
+            HGP_LAUNCH_CHECK();
+        }
+        update(stamp);
+    };
+
+    for (uint32_t r = 0; r < prm.lp_rounds; ++r) {
+        HGP_CHECK_HIP(hipMemsetAsync(moves, 0, sizeof(uint32_t), st));
+        for (uint32_t s = 0; s < S; ++s) subround(r, s);
+        for (;;) {
+            uint32_t hv[17];
+            HGP_CHECK_HIP(hipMemcpyAsync(hv, B.scal, sizeof(hv), hipMemcpyDeviceToHost, st));
+            HGP_CHECK_HIP(hipStreamSynchronize(st));
+            if (!hv[15]) break;
+            // sub-round hv[16] declined in the one-workgroup selection: finish
+            // it device-wide, then replay the remaining sub-rounds of the round
+            const uint32_t s0 = hv[16];
+            HGP_CHECK_HIP(hipMemsetAsync(abort, 0, sizeof(uint32_t) * 2, st));
+            slow_path(hv[13], hv[1]);
+            update(1 + r * S + s0);
+            for (uint32_t s = s0 + 1; s < S; ++s) subround(r, s);
         }
         uint32_t mv = 0;
         HGP_CHECK_HIP(hipMemcpyAsync(&mv, moves, sizeof(uint32_t), hipMemcpyDeviceToHost, st));

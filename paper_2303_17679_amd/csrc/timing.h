@@ -12,11 +12,10 @@ enum KernelId : int {
     KID_RATE_G16,      // k_rate_group<16, 256>
     KID_RATE_G64,      // k_rate_group<64, 1024>
     KID_RATE_BLOCK,    // k_rate_block (LDS and global tables)
-    KID_GAINS_G1,      // k_gains_group<*, 1>
-    KID_GAINS_G8,      // k_gains_group<*, 8>
-    KID_GAINS_G64,     // k_gains_group<*, 64>
-    KID_LP_FUSED,      // k_lp_fused
-    KID_MARK_BOUNDARY, // k_mark_boundary
+    KID_GAINS,         // k_gains: LP best moves, all degree classes
+    KID_LP_FAST,       // k_lp_fast: whole-pair approvals
+    KID_LP_FUSED,      // k_lp_fused: sorted pair walk, one workgroup
+    KID_LP_UPDATE,     // k_lp_update_movers: Lambda / Lambda1 / objective of touched nets
     KID_COUNT
 };
 
