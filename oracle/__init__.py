@@ -73,6 +73,7 @@ def lib():
         L.or_refine_lp.restype = ctypes.c_int
         L.or_refine_lp.argtypes = [P, P, u32, P, P, P, P, P]
         L.or_partition.restype = ctypes.c_int; L.or_partition.argtypes = [P, P, P, P, P]
+        L.or_lp_proposals.restype = u32; L.or_lp_proposals.argtypes = [P, P, u32, u32, u32, P, P, P]
         _lib = L
     return _lib
 
@@ -201,6 +202,15 @@ def refine_lp(h, P: Params, level: int, part):
     rounds = np.zeros(1, np.uint32); moves = np.zeros(1, np.uint64)
     assert lib().or_refine_lp(v.ref, ctypes.byref(P), level, _ptr(part), _ptr(f), _ptr(bw), _ptr(rounds), _ptr(moves)) == 0
     return part, int(f[0]), bw, int(rounds[0]), int(moves[0])
+
+
+def lp_proposals(h, P: Params, level: int, r: int, s: int, part):
+    v = _View(h)
+    part = np.ascontiguousarray(part, np.uint32)
+    t = np.empty(h.n, np.uint32)
+    g = np.empty(h.n, np.int64)
+    lib().or_lp_proposals(v.ref, ctypes.byref(P), level, r, s, _ptr(part), _ptr(t), _ptr(g))
+    return t, g
 
 
 def partition(h, P: Params):

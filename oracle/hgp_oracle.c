@@ -541,6 +541,37 @@ static uint32_t best_move(const or_hg *h, const uint32_t *part, const int64_t *b
     return best;
 }
 
+/* The proposals of one LP sub-round (step 1 of Sec. 11's synchronous LP) on
+ * the partition `part`: prop_t[u] = best target block or OR_NONE, prop_g[u]
+ * its gain, for every node of sub-round s of round r.  Exposed for tests. */
+uint32_t or_lp_proposals(const or_hg *h, const or_params *P, uint32_t level, uint32_t r, uint32_t s,
+                         const uint32_t *part, uint32_t *prop_t, int64_t *prop_g)
+{
+    const uint32_t n = h->n, k = P->k;
+    const int64_t W = or_total_weight(h);
+    const int64_t lmax = or_lmax(W, k, P->eps_num, P->eps_den);
+    int64_t *bw = (int64_t *)malloc(sizeof(int64_t) * k);
+    int64_t *aff = (int64_t *)calloc(k, sizeof(int64_t));
+    uint32_t *cnt = (uint32_t *)calloc(k, sizeof(uint32_t));
+    uint32_t *blist = (uint32_t *)malloc(sizeof(uint32_t) * k);
+    uint32_t *alist = (uint32_t *)malloc(sizeof(uint32_t) * k);
+    or_objective(h, k, part, bw);
+    uint32_t np = 0;
+    for (uint32_t u = 0; u < n; ++u) {
+        prop_t[u] = OR_NONE;
+        prop_g[u] = 0;
+        if (or_hash(P->seed, 3, level, r, u) % P->lp_subrounds != s) continue;
+        int64_t g;
+        uint32_t t = best_move(h, part, bw, lmax, u, aff, cnt, blist, alist, &g);
+        if (t == OR_NONE) continue;
+        prop_t[u] = t;
+        prop_g[u] = g;
+        ++np;
+    }
+    free(bw); free(aff); free(cnt); free(blist); free(alist);
+    return np;
+}
+
 /* LP refinement of one level.  part is refined in place; returns the
  * objective and block weights of the result. */
 int or_refine_lp(const or_hg *h, const or_params *P, uint32_t level, uint32_t *part,

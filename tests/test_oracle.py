@@ -357,3 +357,77 @@ def test_cluster_pass_cap_and_invariants(orc):
     assert all(160 * 4 * cw[c] <= Wt or cw[c] == h.vwgt[c] for c in range(h.n) if rep[c] == c)
     # pass cut: stops after the first sub-round that leaves fewer than n/2.5 clusters
     assert run == 3 or 5 * cnt < 2 * h.n
+
+
+def bfs_order_reference(h):
+    """The initial partition's order from its definition, in plain Python:
+    breadth first from the smallest unvisited vertex, neighbours in ascending
+    incident-net order and ascending pin order inside a net."""
+    nets = bf.nets_of(h)
+    inc = [[] for _ in range(h.n)]
+    for e, pins in enumerate(nets):
+        for v in pins:
+            inc[v].append(e)
+    seen, order = set(), []
+    for start in range(h.n):
+        if start in seen:
+            continue
+        seen.add(start)
+        queue = [start]
+        while queue:
+            v = queue.pop(0)
+            order.append(v)
+            for e in sorted(inc[v]):
+                for w in nets[e]:
+                    if w not in seen:
+                        seen.add(w)
+                        queue.append(w)
+    return order
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_greedy_ip_matches_definition(orc, seed):
+    h = tiny(seed, n=40, m=30, smax=4, vmax=3, single=True)
+    order = bfs_order_reference(h)
+    for k in (2, 3, 6):
+        T = -(-int(h.vwgt.sum()) // k)
+        expect = [0] * h.n
+        b, cb = 0, 0
+        for v in order:
+            expect[v] = b
+            cb += int(h.vwgt[v])
+            if cb >= T and b < k - 1:
+                b, cb = b + 1, 0
+        assert orc.greedy_ip(h, k).tolist() == expect
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_lp_proposals_bruteforce(orc, seed):
+    # best move of every candidate: the largest positive objective decrease
+    # among blocks that can take the node within L_max, ties to the smaller block
+    h = tiny(seed, n=10, m=12, smax=4, wmax=4, vmax=2, single=True)
+    rs = np.random.RandomState(900 + seed)
+    k = 3
+    part = rs.randint(0, k, size=h.n).astype(np.uint32)
+    for eps in ((3, 100), (1, 2)):
+        P = orc.params(k, eps=eps, seed=seed, lp_subrounds=2)
+        Wt = int(h.vwgt.sum())
+        lm = orc.lmax(Wt, k, eps)
+        bw = [int(h.vwgt[part == b].sum()) for b in range(k)]
+        for s in range(2):
+            t, g = orc.lp_proposals(h, P, 0, 1, s, part)
+            for u in range(h.n):
+                if orc.hash_(seed, 3, 0, 1, u) % 2 != s:
+                    assert t[u] == orc.NONE
+                    continue
+                best = None
+                for tt in range(k):
+                    if tt == part[u] or bw[tt] + int(h.vwgt[u]) > lm:
+                        continue
+                    d = bf.move_delta(h, part, u, tt)
+                    if d > 0 and (best is None or d > best[0]):
+                        best = (d, tt)
+                if best is None:
+                    assert t[u] == orc.NONE
+                else:
+                    assert (int(t[u]), int(g[u])) == (best[1], best[0])
