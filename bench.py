@@ -58,6 +58,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain elementwise copy of 1 GiB (read 1 GiB, write 1 GiB) three times, "
+                         "the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -66,6 +69,18 @@ def main():
 
     import torch
     import paper_2303_17679_amd as H
+
+    if args.copy_calibration:
+        n = 1 << 28  # int32 elements: 1 GiB each way
+        src = torch.arange(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}}),
+              flush=True)
+        return
 
     h, k = W.workload(args.workload)
     G = H.Hypergraph.from_host(h)
