@@ -159,6 +159,22 @@ __device__ inline T block_incl_scan_n(T v, T *lds /*[NT/WAVE]*/, T *total) {
 }
 
 // Atomic add for int64 in global memory.
+// XCD-aware split of the index range [0, count) over a grid of nblk
+// workgroups.  gfx950 dispatches workgroup b to XCD b % 8, and each XCD has
+// its own L2, so XCD x takes the x-th contiguous eighth of the range and its
+// workgroups (wi = 0 .. nw-1) stride over that eighth.  Neighbouring items
+// (which share cache lines and, in the meshes and locally numbered inputs,
+// incident nets) then stay in one L2.  Any grid size is valid.
+struct XcdSlice {
+    uint32_t lo, hi, wi, nw;
+};
+__device__ inline XcdSlice xcd_slice(uint32_t blk, uint32_t nblk, uint32_t count) {
+    if (nblk < 8) return {0u, count, blk, nblk};
+    const uint32_t x = blk % 8;
+    return {(uint32_t)((uint64_t)count * x / 8), (uint32_t)((uint64_t)count * (x + 1) / 8), blk / 8,
+            nblk / 8 + (x < nblk % 8 ? 1u : 0u)};
+}
+
 __device__ inline void atomic_add_i64(int64_t *p, int64_t v) {
     atomicAdd((unsigned long long *)p, (unsigned long long)v);
 }

@@ -207,60 +207,116 @@ __device__ inline T group_sum(T v) {
 
 // Groups of G lanes per node (G = 1, 8 or 64 by degree class); the lanes of a
 // group split the incident nets.  Best move: largest positive gain among the
-// blocks of the union of Lambda(e), ties to the smaller block.  Only boundary
-// nodes (an incident net with lambda > 1) can have a positive gain.
+// blocks of the union of Lambda(e), ties to the smaller block.  The list holds
+// only candidates (boundary vertices of the sub-round).  For G < 64 a lane
+// has at most 8 nets: their weight and Lambda words stay in registers for
+// the per-target affinity sums, and all loads of a lane are issued before
+// any is used.
 template <int KW, int G>
 __device__ inline void gains_body(const GainArgs &a, const uint32_t *list, uint32_t count, uint32_t blk,
                                   uint32_t nblk) {
     constexpr int GPB = BLOCK / G;
+    constexpr bool CACHE = G < 64;
+    constexpr int NC = CACHE ? 8 : 1;
     const uint32_t g = threadIdx.x / G, l = threadIdx.x % G;
-    for (uint32_t base = blk * GPB; base < count; base += nblk * GPB) {
+    const XcdSlice xs = xcd_slice(blk, nblk, count);
+    for (uint32_t base = xs.lo + xs.wi * GPB; base < xs.hi; base += xs.nw * GPB) {
         const uint32_t idx = base + g;
         uint32_t u = 0, best_t = NONE, best_g = 0, s = 0;
-        bool act = idx < count;
-        if (act) {
-            u = list[idx];
-            act = a.bcnt[u] > 0 && tag_hash(a.mseed, 3, a.level, a.round, u) % a.S == a.sub;
-        }
+        const bool act = idx < xs.hi;
         if (act) {  // uniform within the group
+            u = list[idx];
             const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
             s = a.part[u];
+            const int64_t cu = a.vwgt[u];
             int64_t bu = 0, wI = 0;
             uint64_t U[KW];
 #pragma unroll
             for (int q = 0; q < KW; ++q) U[q] = 0;
-            for (uint32_t j = j0 + l; j < j1; j += G) {
-                uint32_t e = a.inc[j];
-                int64_t w = a.nwgt[e];
-                wI += w;
-                if ((a.lam1[(size_t)e * KW + (s >> 6)] >> (s & 63)) & 1ull) bu += w;
+            if constexpr (CACHE) {
+                uint32_t ev[NC];
+                int32_t wv[NC];
+                uint64_t lv[NC][KW];
 #pragma unroll
-                for (int q = 0; q < KW; ++q) U[q] |= a.lam[(size_t)e * KW + q];
-            }
-            bu = group_sum<G>(bu);
-            wI = group_sum<G>(wI);
+                for (int c = 0; c < NC; ++c) {
+                    const uint32_t j = j0 + l + (uint32_t)c * G;
+                    ev[c] = j < j1 ? a.inc[j] : NONE;
+                }
 #pragma unroll
-            for (int o = G / 2; o > 0; o >>= 1)
+                for (int c = 0; c < NC; ++c) {
+                    uint64_t one = 0;
+                    wv[c] = 0;
 #pragma unroll
-                for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
-            U[s >> 6] &= ~(1ull << (s & 63));
-            const int64_t cu = a.vwgt[u];
+                    for (int q = 0; q < KW; ++q) lv[c][q] = 0;
+                    if (ev[c] != NONE) {
+                        const size_t e = ev[c];
+                        wv[c] = a.nwgt[e];
 #pragma unroll
-            for (int q = 0; q < KW; ++q) {
-                uint64_t x = U[q];
-                while (x) {
-                    int bit = __ffsll((long long)x) - 1;
-                    x &= x - 1;
-                    uint32_t t = (uint32_t)(q * 64 + bit);
-                    if (a.bw[t] + cu > a.lmax) continue;
-                    int64_t aff = 0;
-                    for (uint32_t j = j0 + l; j < j1; j += G) {
-                        uint32_t e = a.inc[j];
-                        if ((a.lam[(size_t)e * KW + q] >> bit) & 1ull) aff += a.nwgt[e];
+                        for (int q = 0; q < KW; ++q) lv[c][q] = a.lam[e * KW + q];
+                        one = a.lam1[e * KW + (s >> 6)];
                     }
-                    aff = group_sum<G>(aff);
-                    int64_t gn = bu - (wI - aff);
-                    if (gn > (int64_t)best_g) { best_g = (uint32_t)gn; best_t = t; }
+                    wI += wv[c];
+                    if ((one >> (s & 63)) & 1ull) bu += wv[c];
+#pragma unroll
+                    for (int q = 0; q < KW; ++q) U[q] |= lv[c][q];
+                }
+                bu = group_sum<G>(bu);
+                wI = group_sum<G>(wI);
+#pragma unroll
+                for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+                    for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
+                U[s >> 6] &= ~(1ull << (s & 63));
+#pragma unroll
+                for (int q = 0; q < KW; ++q) {
+                    uint64_t x = U[q];
+                    while (x) {
+                        const int bit = __ffsll((long long)x) - 1;
+                        x &= x - 1;
+                        const uint32_t t = (uint32_t)(q * 64 + bit);
+                        if (a.bw[t] + cu > a.lmax) continue;
+                        int64_t aff = 0;
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            if ((lv[c][q] >> bit) & 1ull) aff += wv[c];
+                        aff = group_sum<G>(aff);
+                        const int64_t gn = bu - (wI - aff);
+                        if (gn > (int64_t)best_g) { best_g = (uint32_t)gn; best_t = t; }
+                    }
+                }
+            } else {
+                for (uint32_t j = j0 + l; j < j1; j += G) {
+                    const size_t e = a.inc[j];
+                    const int64_t w = a.nwgt[e];
+                    wI += w;
+                    if ((a.lam1[e * KW + (s >> 6)] >> (s & 63)) & 1ull) bu += w;
+#pragma unroll
+                    for (int q = 0; q < KW; ++q) U[q] |= a.lam[e * KW + q];
+                }
+                bu = group_sum<G>(bu);
+                wI = group_sum<G>(wI);
+#pragma unroll
+                for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+                    for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
+                U[s >> 6] &= ~(1ull << (s & 63));
+#pragma unroll
+                for (int q = 0; q < KW; ++q) {
+                    uint64_t x = U[q];
+                    while (x) {
+                        const int bit = __ffsll((long long)x) - 1;
+                        x &= x - 1;
+                        const uint32_t t = (uint32_t)(q * 64 + bit);
+                        if (a.bw[t] + cu > a.lmax) continue;
+                        int64_t aff = 0;
+                        for (uint32_t j = j0 + l; j < j1; j += G) {
+                            const size_t e = a.inc[j];
+                            if ((a.lam[e * KW + q] >> bit) & 1ull) aff += a.nwgt[e];
+                        }
+                        aff = group_sum<G>(aff);
+                        const int64_t gn = bu - (wI - aff);
+                        if (gn > (int64_t)best_g) { best_g = (uint32_t)gn; best_t = t; }
+                    }
                 }
             }
         }
@@ -269,15 +325,90 @@ __device__ inline void gains_body(const GainArgs &a, const uint32_t *list, uint3
 }
 
 // One launch for the three degree classes: blocks [0, nb0) take class 0
-// (1 lane per node), [nb0, nb0 + nb1) class 1 (8 lanes), the rest class 2 (64).
+// (1 lane per node), [nb0, nb0 + nb1) class 1 (8 lanes), the rest class 2
+// (64).  List c starts at off[c]; its length is the device count ccnt[c].
+struct ClassLists {
+    uint32_t off[3];
+    uint32_t nb[3];
+};
+
 template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_gains(GainArgs a, const uint32_t *lists, uint32_t c0, uint32_t c1,
-                                                 uint32_t c2, uint32_t nb0, uint32_t nb1, uint32_t nb2) {
+__global__ __launch_bounds__(BLOCK) void k_gains(GainArgs a, const uint32_t *lists, ClassLists cl,
+                                                 const uint32_t *ccnt) {
     if (*a.abort) return;
     const uint32_t b = blockIdx.x;
-    if (b < nb0) gains_body<KW, 1>(a, lists, c0, b, nb0);
-    else if (b < nb0 + nb1) gains_body<KW, 8>(a, lists + c0, c1, b - nb0, nb1);
-    else gains_body<KW, 64>(a, lists + c0 + c1, c2, b - nb0 - nb1, nb2);
+    if (b < cl.nb[0]) gains_body<KW, 1>(a, lists + cl.off[0], ccnt[0], b, cl.nb[0]);
+    else if (b < cl.nb[0] + cl.nb[1]) gains_body<KW, 8>(a, lists + cl.off[1], ccnt[1], b - cl.nb[0], cl.nb[1]);
+    else gains_body<KW, 64>(a, lists + cl.off[2], ccnt[2], b - cl.nb[0] - cl.nb[1], cl.nb[2]);
+}
+
+// Candidates of LP sub-round (r, s): the boundary vertices (an incident net
+// with lambda > 1 -- no other vertex can have a positive gain) whose
+// sub-round hash selects s, appended to the list of their degree class.
+// Class c's list starts at off[c] and can hold every vertex of the class.
+// Each workgroup compacts one contiguous chunk of `per` * BLOCK vertices:
+// it counts first, reserves its ranges with one atomic per class, then
+// writes its candidates in ascending vertex order.
+__device__ inline int lp_cand_class(const uint32_t *inc_off, const uint32_t *bcnt, uint32_t n, uint64_t mseed,
+                                    uint32_t level, uint32_t r, uint32_t s, uint32_t S, uint32_t u) {
+    if (u >= n || bcnt[u] == 0 || tag_hash(mseed, 3, level, r, u) % S != s) return -1;
+    const uint32_t d = inc_off[u + 1] - inc_off[u];
+    return d <= 8 ? 0 : (d <= 64 ? 1 : 2);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, const uint32_t *bcnt, uint32_t n,
+                                                    uint32_t per, uint64_t mseed, uint32_t level, uint32_t r,
+                                                    uint32_t s, uint32_t S, ClassLists cl, uint32_t *ccnt,
+                                                    uint32_t *lists, const uint32_t *abort) {
+    constexpr int NW = BLOCK / WAVE;
+    __shared__ uint32_t wc[3][NW];
+    __shared__ uint32_t base[3];
+    if (*abort) return;
+    const uint32_t lo = blockIdx.x * per * BLOCK;
+    if (lo >= n) return;  // uniform per block
+    const uint32_t w = threadIdx.x / WAVE;
+    uint32_t c0 = 0, c1 = 0, c2 = 0;
+    for (uint32_t it = 0; it < per; ++it) {
+        const int key = lp_cand_class(inc_off, bcnt, n, mseed, level, r, s, S, lo + it * BLOCK + threadIdx.x);
+        c0 += key == 0;
+        c1 += key == 1;
+        c2 += key == 2;
+    }
+    c0 = wave_sum(c0);
+    c1 = wave_sum(c1);
+    c2 = wave_sum(c2);
+    if (__lane_id() == 0) { wc[0][w] = c0; wc[1][w] = c1; wc[2][w] = c2; }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint32_t t = 0;
+        for (int q = 0; q < NW; ++q) t += wc[threadIdx.x][q];
+        base[threadIdx.x] = t ? atomicAdd(&ccnt[threadIdx.x], t) : 0u;
+    }
+    __syncthreads();
+    uint32_t run[3] = {base[0], base[1], base[2]};
+    for (uint32_t it = 0; it < per; ++it) {
+        const uint32_t u = lo + it * BLOCK + threadIdx.x;
+        const int key = lp_cand_class(inc_off, bcnt, n, mseed, level, r, s, S, u);
+        uint64_t bal[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) bal[c] = __ballot(key == c);
+        __syncthreads();  // the previous iteration's reads of wc are done
+        if (__lane_id() == 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) wc[c][w] = (uint32_t)__popcll(bal[c]);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            uint32_t before = 0, total = 0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                before += (q < (int)w) ? wc[c][q] : 0u;
+                total += wc[c][q];
+            }
+            if (key == c) lists[cl.off[c] + run[c] + before + (uint32_t)__popcll(bal[c] & lanemask_lt())] = u;
+            run[c] += total;
+        }
+    }
 }
 
 // Boundary count of every node from scratch (once per level).
@@ -297,26 +428,29 @@ __global__ void k_lp_reset(uint32_t *scal, uint32_t *pw, uint32_t kk, int64_t *d
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
     if (tid < 4) scal[tid] = 0;                  // nprop, gmax, ntouched, nlong
     if (tid == 4) { scal[13] = 0; scal[14] = 0; }  // nslow, nmov
+    if (tid >= 5 && tid < 8) scal[20 + tid - 5] = 0;  // candidates per degree class
     for (uint32_t i = tid; i < kk; i += nt) pw[i] = 0;
     for (uint32_t i = tid; i < k; i += nt) dbw_g[i] = 0;
 }
 
-// Measurement only: compulsory bytes of one gains launch (list, boundary
-// stamp, and for every candidate its node data, incidence list and the
-// weight / Lambda / Lambda1 of every distinct incident net, counted once).
+// Measurement only: compulsory bytes of one gains launch: for every
+// candidate its list entry, offsets, block, weight and incidence list; for
+// every distinct incident net its weight, Lambda words and the one Lambda1
+// word the gain reads, counted once.
 template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs a, const uint32_t *list, uint32_t count,
-                                                         uint32_t *nmark, uint32_t stamp, unsigned long long *acc) {
+__global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs a, const uint32_t *lists, ClassLists cl,
+                                                         const uint32_t *ccnt, uint32_t *nmark, uint32_t stamp,
+                                                         unsigned long long *acc) {
     __shared__ unsigned long long red[BLOCK / WAVE];
     unsigned long long bytes = 0;
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
-        const uint32_t u = list[idx];
-        bytes += 4 + 4;  // list entry, boundary count
-        if (!(a.bcnt[u] > 0 && tag_hash(a.mseed, 3, a.level, a.round, u) % a.S == a.sub)) continue;
+    const uint32_t c0 = ccnt[0], c1 = ccnt[1], total = c0 + c1 + ccnt[2];
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+        const uint32_t u = idx < c0 ? lists[cl.off[0] + idx]
+                                    : (idx < c0 + c1 ? lists[cl.off[1] + idx - c0] : lists[cl.off[2] + idx - c0 - c1]);
         const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
-        bytes += 4 + 4 + 4 + 4ull * (j1 - j0);  // inc_off, part, vwgt, incidence list
+        bytes += 4 + 8 + 4 + 4 + 4ull * (j1 - j0);  // list entry, inc_off pair, part, vwgt, incidence list
         for (uint32_t j = j0; j < j1; ++j)
-            if (atomicExch(&nmark[a.inc[j]], stamp) != stamp) bytes += 4 + 16ull * KW;
+            if (atomicExch(&nmark[a.inc[j]], stamp) != stamp) bytes += 4 + 8ull * KW + 8;
     }
     bytes = wave_sum(bytes);
     if (__lane_id() == 0) red[threadIdx.x / WAVE] = bytes;
@@ -328,37 +462,18 @@ __global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs a, const uint3
     }
 }
 
-// Degree classes (<= 8, <= 64, larger): count pass, then fill pass.
-__global__ __launch_bounds__(BLOCK) void k_deg_classify(const uint32_t *inc_off, uint32_t n, uint32_t *counts,
-                                                        uint32_t *cursor, uint32_t *lists, bool fill) {
-    __shared__ uint32_t lcnt[3], lbase[3];
+// Vertices per degree class (<= 8, <= 64, larger incident nets; degree-0
+// vertices are in none): sizes the candidate lists of the level.
+__global__ __launch_bounds__(BLOCK) void k_deg_classify(const uint32_t *inc_off, uint32_t n, uint32_t *counts) {
+    __shared__ uint32_t lcnt[3];
     if (threadIdx.x < 3) lcnt[threadIdx.x] = 0;
     __syncthreads();
-    for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
-        const uint32_t u = u0 + threadIdx.x;
-        int key = -1;
-        uint32_t lrank = 0;
-        if (u < n) {
-            uint32_t d = inc_off[u + 1] - inc_off[u];
-            if (d > 0) {
-                key = d <= 8 ? 0 : (d <= 64 ? 1 : 2);
-                lrank = atomicAdd(&lcnt[key], 1u);
-            }
-        }
-        if (fill) {
-            __syncthreads();
-            if (threadIdx.x < 3) lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], lcnt[threadIdx.x]) : 0u;
-            __syncthreads();
-            if (key >= 0) lists[lbase[key] + lrank] = u;
-            __syncthreads();
-            if (threadIdx.x < 3) lcnt[threadIdx.x] = 0;
-            __syncthreads();
-        }
+    for (uint32_t u = blockIdx.x * BLOCK + threadIdx.x; u < n; u += gridDim.x * BLOCK) {
+        const uint32_t d = inc_off[u + 1] - inc_off[u];
+        if (d > 0) atomicAdd(&lcnt[d <= 8 ? 0 : (d <= 64 ? 1 : 2)], 1u);
     }
-    if (!fill) {
-        __syncthreads();
-        if (threadIdx.x < 3 && lcnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], lcnt[threadIdx.x]);
-    }
+    __syncthreads();
+    if (threadIdx.x < 3 && lcnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], lcnt[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,7 +1126,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const uint64_t mseed = mix64(prm.seed);
     // device scalars: ntouched and nlong are adjacent so one memset clears both
     uint32_t *nprop = B.scal + 0, *gmax = B.scal + 1, *ntouched = B.scal + 2, *nlong = B.scal + 3,
-             *moves = B.scal + 4, *dcnt = B.scal + 5 /* [3] */, *dcur = B.scal + 8 /* [3] */,
+             *moves = B.scal + 4, *dcnt = B.scal + 5 /* [3] */,
              *nslow = B.scal + 13, *nmov = B.scal + 14;
 
     build_conn<KW>(h, part, B, st);
@@ -1021,22 +1136,30 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     HGP_LAUNCH_CHECK();
     // degree classes of the nodes (lanes per node 1 / 8 / 64)
     HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * 3, st));
-    k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt, dcur, B.dlists, false);
+    k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt);
     HGP_LAUNCH_CHECK();
     uint32_t dc[3], doff[4] = {0, 0, 0, 0};
     HGP_CHECK_HIP(hipMemcpyAsync(dc, dcnt, sizeof(dc), hipMemcpyDeviceToHost, st));
     HGP_CHECK_HIP(hipStreamSynchronize(st));
     for (int c = 0; c < 3; ++c) doff[c + 1] = doff[c] + dc[c];
-    const uint32_t nbg[3] = {dc[0] ? grid_for(dc[0], BLOCK, 2048) : 0u, dc[1] ? grid_for(dc[1], BLOCK / 8, 2048) : 0u,
-                             dc[2] ? grid_for(dc[2], BLOCK / 64, 2048) : 0u};
-    HGP_CHECK_HIP(hipMemcpyAsync(dcur, doff, sizeof(uint32_t) * 3, hipMemcpyHostToDevice, st));
-    k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt, dcur, B.dlists, true);
-    HGP_LAUNCH_CHECK();
+    // per sub-round a class holds about 1/S of its vertices (fewer: only the
+    // boundary); the grid strides over whatever the device count is
+    const uint32_t S = prm.lp_subrounds;
+    ClassLists cl;
+    for (int c = 0; c < 3; ++c) {
+        const uint32_t per = c == 0 ? BLOCK : (c == 1 ? BLOCK / 8 : BLOCK / 64);
+        cl.off[c] = doff[c];
+        cl.nb[c] = dc[c] ? grid_for((dc[c] + S - 1) / S, per, 2048) : 0u;
+    }
+    const uint32_t nbg_all = cl.nb[0] + cl.nb[1] + cl.nb[2];
+    // candidate compaction: chunks of cand_per * BLOCK vertices per workgroup
+    const uint32_t cand_per = std::max(1u, std::min(16u, (uint32_t)((n + BLOCK * 2048u - 1) / (BLOCK * 2048u))));
+    const uint32_t cand_blocks = (uint32_t)((n + (size_t)cand_per * BLOCK - 1) / ((size_t)cand_per * BLOCK));
+    uint32_t *ccnt = B.scal + 20;  // [3] candidates per class in the current sub-round
 
     const int kb = bits_for(k - 1), ub = bits_for(n ? n - 1 : 0);
     uint32_t *abort = B.scal + 15;  // [2]: flag, sub-round that raised it (scal[16])
     HGP_CHECK_HIP(hipMemsetAsync(abort, 0, sizeof(uint32_t) * 2, st));
-    const uint32_t S = prm.lp_subrounds;
 
     // Device-wide selection of the slow pairs of sub-round (r, s): only after
     // the one-workgroup path declined (its count exceeded FUSED_MAX or the key
@@ -1116,17 +1239,19 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         HGP_LAUNCH_CHECK();
         const GainArgs ga{h.inc_off, h.inc, h.nwgt, h.vwgt, B.lam, B.lam1, part, B.bw, B.bcnt, lmax, mseed, level, r,
                           s, S, n, B.prop_t, B.prop_g, B.plist, nprop, gmax, B.pw, k, abort};
+        k_lp_cands<<<cand_blocks, BLOCK, 0, st>>>(h.inc_off, B.bcnt, n, cand_per, mseed, level, r, s, S, cl, ccnt,
+                                                  B.dlists, abort);
+        HGP_LAUNCH_CHECK();
         if (accounting(KID_GAINS)) {
             Timing &T = timing();
             ++T.stamp;
-            k_account_gains<KW><<<grid_for(dc[0] + dc[1] + dc[2], BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
-                ga, B.dlists, dc[0] + dc[1] + dc[2], T.marks, T.stamp, (unsigned long long *)T.acc_dev + KID_GAINS);
+            k_account_gains<KW><<<grid_for(n / S + 1, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+                ga, B.dlists, cl, ccnt, T.marks, T.stamp, (unsigned long long *)T.acc_dev + KID_GAINS);
             HGP_LAUNCH_CHECK();
         }
-        if (nbg[0] + nbg[1] + nbg[2]) {
+        if (nbg_all) {
             TimedLaunch tl(KID_GAINS, st);
-            k_gains<KW><<<nbg[0] + nbg[1] + nbg[2], BLOCK, 0, st>>>(ga, B.dlists, dc[0], dc[1], dc[2], nbg[0], nbg[1],
-                                                                    nbg[2]);
+            k_gains<KW><<<nbg_all, BLOCK, 0, st>>>(ga, B.dlists, cl, ccnt);
             HGP_LAUNCH_CHECK();
         }
         {  // pairs whose whole move sets are feasible: applied directly

@@ -302,6 +302,9 @@ def workload(name: str) -> tuple[HostHypergraph, int]:
         return stencil3d(160, name=name), 64
     if name == "rmat24":
         return rmat(24, 2**28, seed=3, name=name), 128
+    if name.startswith("rmat"):  # e.g. rmat16: edge factor 16
+        sc = int(name[len("rmat"):])
+        return rmat(sc, 16 << sc, seed=3, name=name), 128
     if name.startswith("stencil"):
         return stencil3d(int(name[len("stencil"):]), name=name), 64
     if name.startswith("powerlaw"):  # e.g. powerlaw50000

@@ -51,12 +51,17 @@ CASES = [
     ("stencil16", 8, 5),
     ("stencil24", 64, 7),
     ("powerlaw20000", 8, 2),
+    ("stencil32", 100, 11),   # two Lambda words per net
+    ("rmat16", 128, 4),       # 2-pin nets with duplicate edges, two words
+    ("random120k", 256, 6),   # four words per net
 ]
 
 
 def make(name):
     if name == "random2k":
         return W.random_uniform(2000, 2000, 2, 8, seed=9, name=name)
+    if name == "random120k":
+        return W.random_uniform(120000, 120000, 2, 8, seed=4, name=name)
     return W.workload(name)[0]
 
 
