@@ -83,13 +83,13 @@ __device__ inline bool valid_target(const RateArgs &a, uint32_t u, uint32_t C) {
     return C != u && a.cap_mult * ((int64_t)a.vwgt[u] + a.tinfo[C]) <= a.W;
 }
 
+// Called by the publishing lanes only; the proposer list slot is reserved
+// with one atomic per wave.
 __device__ inline void publish(const RateArgs &a, uint32_t u, uint32_t C) {
     a.ptarget[u] = C;
-    if (C != NONE) {
-        atomic_add_i64(&a.tsum[C], (int64_t)a.vwgt[u]);
-        uint32_t slot = atomicAdd(a.nprop, 1u);
-        a.proposers[slot] = u;
-    }
+    if (C != NONE) atomic_add_i64(&a.tsum[C], (int64_t)a.vwgt[u]);
+    const uint32_t slot = warp_agg_append(a.nprop, C != NONE);
+    if (C != NONE) a.proposers[slot] = u;
 }
 
 // Nets with at most LANE_NET pins are rated by a single lane: it loads the

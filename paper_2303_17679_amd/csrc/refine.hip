@@ -38,13 +38,22 @@ __device__ inline void net_bits(const uint32_t *pins, uint32_t b, uint32_t len, 
                                 uint64_t *twice) {
 #pragma unroll
     for (int q = 0; q < KW; ++q) { once[q] = 0; twice[q] = 0; }
-    for (uint32_t j = 0; j < len; ++j) {
-        uint32_t blk = part[pins[b + j]];
+    // eight pins at a time: all pin loads, then all block loads, then the fold
+    for (uint32_t j0 = 0; j0 < len; j0 += 8) {
+        uint32_t blk[8];
 #pragma unroll
-        for (int q = 0; q < KW; ++q) {
-            uint64_t bit = ((uint32_t)q == (blk >> 6)) ? (1ull << (blk & 63)) : 0ull;
-            twice[q] |= once[q] & bit;
-            once[q] |= bit;
+        for (uint32_t c = 0; c < 8; ++c) blk[c] = j0 + c < len ? pins[b + j0 + c] : NONE;
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c) blk[c] = blk[c] != NONE ? part[blk[c]] : NONE;
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c) {
+            if (blk[c] == NONE) continue;
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                const uint64_t bit = ((uint32_t)q == (blk[c] >> 6)) ? (1ull << (blk[c] & 63)) : 0ull;
+                twice[q] |= once[q] & bit;
+                once[q] |= bit;
+            }
         }
     }
 }
@@ -367,9 +376,11 @@ __global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, con
     const uint32_t lo = blockIdx.x * per * BLOCK;
     if (lo >= n) return;  // uniform per block
     const uint32_t w = threadIdx.x / WAVE;
-    uint32_t c0 = 0, c1 = 0, c2 = 0;
+    // the class of each of this thread's vertices, 2 bits each (3 = none)
+    uint32_t packed = 0, c0 = 0, c1 = 0, c2 = 0;
     for (uint32_t it = 0; it < per; ++it) {
         const int key = lp_cand_class(inc_off, bcnt, n, mseed, level, r, s, S, lo + it * BLOCK + threadIdx.x);
+        packed |= (uint32_t)(key < 0 ? 3 : key) << (2 * it);
         c0 += key == 0;
         c1 += key == 1;
         c2 += key == 2;
@@ -388,7 +399,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, con
     uint32_t run[3] = {base[0], base[1], base[2]};
     for (uint32_t it = 0; it < per; ++it) {
         const uint32_t u = lo + it * BLOCK + threadIdx.x;
-        const int key = lp_cand_class(inc_off, bcnt, n, mseed, level, r, s, S, u);
+        const int key = (int)((packed >> (2 * it)) & 3u);
         uint64_t bal[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) bal[c] = __ballot(key == c);
@@ -1152,7 +1163,14 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         cl.nb[c] = dc[c] ? grid_for((dc[c] + S - 1) / S, per, 2048) : 0u;
     }
     const uint32_t nbg_all = cl.nb[0] + cl.nb[1] + cl.nb[2];
+    // grids of the per-sub-round kernels, sized by what one sub-round can hold
+    // (about n / S proposals and movers); every kernel strides over its count
+    const size_t per_sub = (size_t)n / S + 1;
+    const uint32_t fast_blocks = grid_for(per_sub, BLOCK, FILL_BLOCKS / 4);
+    const uint32_t upd_blocks = grid_for(per_sub, BLOCK / 16, FILL_BLOCKS / 2);
+    const uint32_t long_blocks = grid_for((size_t)m + 1, 64 * (BLOCK / WAVE), FILL_BLOCKS / 4);
     // candidate compaction: chunks of cand_per * BLOCK vertices per workgroup
+    // (at most 16 per thread: the kernel keeps 2 bits per vertex in one word)
     const uint32_t cand_per = std::max(1u, std::min(16u, (uint32_t)((n + BLOCK * 2048u - 1) / (BLOCK * 2048u))));
     const uint32_t cand_blocks = (uint32_t)((n + (size_t)cand_per * BLOCK - 1) / ((size_t)cand_per * BLOCK));
     uint32_t *ccnt = B.scal + 20;  // [3] candidates per class in the current sub-round
@@ -1223,12 +1241,12 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         }
         {
             TimedLaunch tl(KID_LP_UPDATE, st);
-            k_lp_update_movers<KW, 16><<<FILL_BLOCKS / 2, BLOCK, 0, st>>>(
+            k_lp_update_movers<KW, 16><<<upd_blocks, BLOCK, 0, st>>>(
                 h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, h.nwgt, part, B.lam, B.lam1, B.tstamp, stamp,
                 B.f, B.longl, nlong, moves, B.bcnt, abort);
             HGP_LAUNCH_CHECK();
         }
-        k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part, B.lam,
+        k_conn_long<KW><<<long_blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part, B.lam,
                                                            B.lam1, B.f, true, B.bcnt, abort);
         HGP_LAUNCH_CHECK();
     };
@@ -1256,7 +1274,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         }
         {  // pairs whose whole move sets are feasible: applied directly
             TimedLaunch tl(KID_LP_FAST, st);
-            k_lp_fast<<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(B.plist, nprop, B.prop_t, B.pw, k, h.vwgt, part, B.bw, lmax,
+            k_lp_fast<<<fast_blocks, BLOCK, 0, st>>>(B.plist, nprop, B.prop_t, B.pw, k, h.vwgt, part, B.bw, lmax,
                                                          B.dbw_g, B.mlist, nmov, B.slow, nslow, abort);
             HGP_LAUNCH_CHECK();
         }
