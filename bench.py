@@ -29,7 +29,156 @@ WORKLOADS = {
     "powerlaw1m": "power-law hypergraph, seed 2, n=m=1,000,000, Zipf(2.1) net sizes in [2,1000], Zipf(2.3) "
                   "vertex degrees, net weights in [1,4], k=8, eps=0.03",
     "random10k": "random hypergraph, seed 1, n=m=10,000, net sizes in [2,8], k=2, eps=0.03",
+    "batch": "4096 VLSI-like hypergraphs, seed 4: n log-uniform in [1e3, 2e5], m = 1.1 n, net size "
+             "2+Geometric(0.4) capped at 50, 90% of pins within a 256-ID window around the net's anchor, vertex "
+             "weights in [1,10], k uniform in {2,4,8}, eps=0.03; all partitioned by one hgp_partition_batch call",
+    "serve": "Poisson stream of partition requests, seed 5: sizes log-uniform in [1e4, 1e7] pins, family uniform "
+             "over {random, power-law, stencil, R-MAT}, k uniform in {2..64}, eps=0.03, admitted by workspace "
+             "footprint into a continuous-admission server; arrival rate 0.8 x the measured saturation rate",
 }
+
+
+def _gen_vlsi(args):
+    n, i = args
+    return W.vlsi(n, i)
+
+
+def _gen_req(args):
+    fam, P, j = args
+    return W.serve_request(fam, P, j)
+
+
+def _pool_map(fn, items):
+    import multiprocessing as mp
+    procs = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("fork").Pool(procs) as pool:
+        return pool.map(fn, items, chunksize=max(1, len(items) // (procs * 8)))
+
+
+def run_batch(args):
+    """Batched throughput: one hgp_partition_batch call over the whole batch,
+    against the one-at-a-time path (hgp_partition per instance) on a sample."""
+    import numpy as np
+    ns, ks = W.vlsi_params(args.count)
+    t0 = time.perf_counter()
+    hosts = _pool_map(_gen_vlsi, [(int(ns[i]), i) for i in range(args.count)])
+    print(f"[bench] generated {args.count} instances in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    import torch
+    import paper_2303_17679_amd as H
+    hs = [H.Hypergraph.from_host(h) for h in hosts]
+    prms = [H.params(int(ks[i]), seed=args.seed) for i in range(args.count)]
+    pins = sum(h.p for h in hosts)
+    del hosts
+    torch.cuda.synchronize()
+    H.partition_batch(hs[:32], prms[:32], lanes=args.lanes)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        parts, objs, levels = H.partition_batch(hs, prms, lanes=args.lanes)
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / args.steps
+    # one-at-a-time path on every `stride`-th instance (same size mix)
+    sample = list(range(0, args.count, args.plain_stride))
+    t0 = time.perf_counter()
+    same = True
+    for i in sample:
+        part, f, lv = H.partition(hs[i], prms[i])
+        same &= bool(f == int(objs[i].item()) and lv == levels[i] and torch.equal(part, parts[i]))
+    torch.cuda.synchronize()
+    Tp = time.perf_counter() - t0
+    plain = sum(hs[i].p for i in sample) / Tp
+    value = pins / T
+    return {
+        "metric": "pins/s for coarsen+LP refine, batched (one call over all instances)",
+        "value": value, "unit": "pins/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": 1000.0 * T, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32/int64 (integer only)", "data": "synthetic",
+        "config": {"workload": "batch", "description": WORKLOADS["batch"], "instances": args.count, "pins": pins,
+                   "lanes": args.lanes, "parallelism": "single GPU"},
+        "plain_path": {"pins_per_s": plain, "sample": f"every {args.plain_stride}th instance "
+                       f"({len(sample)} instances, {sum(hs[i].p for i in sample)} pins), hgp_partition one at a time",
+                       "results_identical": same},
+        "speedup_vs_plain": value / plain,
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
+def run_serve(args):
+    """Serving: calibrate the saturation rate closed-loop, then replay the
+    trace open-loop with Poisson arrivals at 0.8 x that rate."""
+    import numpy as np
+    trace = W.serve_trace(args.count)
+    t0 = time.perf_counter()
+    hosts = _pool_map(_gen_req, [(fam, P, j) for j, (fam, P, k) in enumerate(trace)])
+    print(f"[bench] generated {args.count} requests in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    import torch
+    import paper_2303_17679_amd as H
+    hs = [H.Hypergraph.from_host(h) for h in hosts]
+    prms = [H.params(k, seed=args.seed) for (_, _, k) in trace]
+    pins = [h.p for h in hosts]
+    del hosts
+    need = [H.workspace_bytes(H.OP_PARTITION, g.n, g.m, g.p, p) for g, p in zip(hs, prms)]
+    pool = max(int(args.pool_gib * (1 << 30)), max(need) + 4096)
+    torch.cuda.synchronize()
+
+    def closed_loop(lanes, idx):
+        S = H.Server(lanes=lanes, pool_bytes=pool)
+        t0 = time.perf_counter()
+        tk = [S.submit(hs[i], prms[i]) for i in idx]
+        for t, _, _ in tk:
+            S.wait(t)
+        T = time.perf_counter() - t0
+        S.close()
+        return T
+
+    closed_loop(args.lanes, list(range(min(8, args.count))))  # warm-up
+    T_sat = closed_loop(args.lanes, list(range(args.count)))
+    sat = args.count / T_sat
+    rate = 0.8 * sat
+    gaps = -np.log1p(-W._unit_real(W.rng(5, 9, np.arange(args.count)))) / rate
+    arrive = np.cumsum(gaps)
+    S = H.Server(lanes=args.lanes, pool_bytes=pool)
+    tickets = []
+    t0 = time.perf_counter()
+    for j in range(args.count):
+        dt = arrive[j] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(S.submit(hs[j], prms[j]))
+    lat, qms = [], []
+    for t, _, _ in tickets:
+        _, l_ms, q_ms = S.wait(t)
+        lat.append(l_ms)
+        qms.append(q_ms)
+    T_open = time.perf_counter() - t0
+    S.close()
+    # plain path: one request at a time, FIFO, closed loop, on a sample
+    sample = list(range(0, args.count, args.plain_stride))
+    t0 = time.perf_counter()
+    for i in sample:
+        H.partition(hs[i], prms[i])
+    torch.cuda.synchronize()
+    Tp = time.perf_counter() - t0
+    plain = sum(pins[i] for i in sample) / Tp
+    lat = np.array(lat)
+    return {
+        "metric": "batched p99 latency (served requests, open loop at 0.8 x saturation)",
+        "value": float(np.percentile(lat, 99)), "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1000.0 * T_open, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32/int64 (integer only)", "data": "synthetic",
+        "config": {"workload": "serve", "description": WORKLOADS["serve"], "requests": args.count,
+                   "pins": int(sum(pins)), "lanes": args.lanes, "pool_bytes": pool, "parallelism": "single GPU"},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "queue_p50_ms": float(np.percentile(qms, 50)), "queue_p99_ms": float(np.percentile(qms, 99)),
+        "served_pins_per_s": float(sum(pins)) / T_open, "arrival_rate_per_s": rate,
+        "saturated_pins_per_s": float(sum(pins)) / T_sat,
+        "plain_path": {"pins_per_s": plain, "sample": f"every {args.plain_stride}th request "
+                       f"({len(sample)} requests), hgp_partition one at a time"},
+        "speedup_vs_plain": (float(sum(pins)) / T_sat) / plain,
+        "roofline": None, "cpu_baseline": None,
+    }
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -58,6 +207,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--count", type=int, default=None, help="instances (batch) or requests (serve)")
+    ap.add_argument("--lanes", type=int, default=16, help="concurrent requests (batch, serve)")
+    ap.add_argument("--plain-stride", type=int, default=16, help="one-at-a-time comparison on every Nth request")
+    ap.add_argument("--pool-gib", type=float, default=32.0, help="server pool (serve)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain elementwise copy of 1 GiB (read 1 GiB, write 1 GiB) three times, "
                          "the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -66,6 +219,15 @@ def main():
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload in ("batch", "serve"):
+        if args.count is None:
+            args.count = 4096 if args.workload == "batch" else 200
+        if args.workload == "batch" and args.steps == 5:
+            args.steps = 1
+        line = run_batch(args) if args.workload == "batch" else run_serve(args)
+        print(json.dumps(line), flush=True)
+        return
 
     import torch
     import paper_2303_17679_amd as H

@@ -183,6 +183,64 @@ hgp_status hgp_partition(const hgp_hg *h, const hgp_params *prm, uint32_t *part,
                          int64_t *objective, uint32_t *levels_out,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Many hypergraphs at once.  Each request runs exactly the driver of
+ * hgp_partition, so its results are bit-identical to a call on its own; what
+ * changes is that requests overlap on the device.
+ * ------------------------------------------------------------------------ */
+
+/* A partition server (host object).  `lanes` (1..64) worker threads, each
+ * with its own HIP stream, take requests in arrival order; a request is
+ * admitted when a lane is free and its workspace
+ * (hgp_workspace_bytes(HGP_OP_PARTITION, ...)) fits in the free part of
+ * `pool` (device, 256-byte aligned, pool_bytes, owned by the caller and
+ * untouched by anything else until hgp_server_destroy returns).  A request
+ * that does not fit may be passed by later ones, at most 64 times; after
+ * that it waits at the head until memory frees up.  Requests admitted while
+ * others run overlap with them on the device (continuous admission).
+ * Fails with HGP_E_INVALID while measurement (hgp_timing_begin) is active. */
+typedef struct hgp_server hgp_server;
+hgp_status hgp_server_create(uint32_t lanes, void *pool, size_t pool_bytes, hgp_server **out);
+
+/* Queues one partition of h with parameters prm (both copied; the arrays
+ * they point to, part[n] and *objective must stay valid until the request
+ * is waited for).  The request starts after the work enqueued on `stream`
+ * so far (its inputs may be produced there).  Returns a ticket in *ticket.
+ * HGP_E_WORKSPACE: the request's workspace exceeds the whole pool. */
+hgp_status hgp_server_submit(hgp_server *s, const hgp_hg *h, const hgp_params *prm, uint32_t *part,
+                             int64_t *objective, void *stream, uint64_t *ticket);
+
+/* Blocks until request `ticket` has finished (its results are then complete
+ * on the device) and returns its status: the status hgp_partition would have
+ * returned.  *levels_out (host, may be NULL) gets the number of
+ * contractions, *latency_ms (may be NULL) the time from submission to
+ * completion, *queue_ms (may be NULL) the time from submission to
+ * admission.  A ticket can be waited for once. */
+hgp_status hgp_server_wait(hgp_server *s, uint64_t ticket, uint32_t *levels_out, double *latency_ms,
+                           double *queue_ms);
+
+/* Finishes the running requests, cancels the queued ones (their wait
+ * returns HGP_E_INVALID), joins the workers and frees the host object. */
+hgp_status hgp_server_destroy(hgp_server *s);
+
+/* Host.  Pool bytes with which hgp_partition_batch keeps `lanes` requests of
+ * the batch in flight: lanes x the largest request's workspace. */
+hgp_status hgp_batch_workspace_bytes(const hgp_hg *hs, const hgp_params *ps, uint32_t count, uint32_t lanes,
+                                     size_t *out);
+
+/* Partitions count independent hypergraphs hs[i] with parameters ps[i]
+ * (host arrays of views and parameters; the views' arrays are device
+ * pointers) through a server of `lanes` lanes over the workspace, largest
+ * first.  parts: host array of count device pointers (part of hypergraph i,
+ * [hs[i].n]); objectives: device int64 [count]; levels_out: host uint32
+ * [count] or NULL.  Results equal hgp_partition on each hypergraph.  The
+ * workspace must hold at least the largest request's workspace
+ * (hgp_batch_workspace_bytes with lanes = 1); more lets more requests run
+ * at once.  Returns the first failing request's status.  Syncs. */
+hgp_status hgp_partition_batch(const hgp_hg *hs, const hgp_params *ps, uint32_t count, uint32_t lanes,
+                               uint32_t *const *parts, int64_t *objectives, uint32_t *levels_out, void *ws,
+                               size_t ws_bytes, void *stream);
+
 /* Measurement support (host).  Kernel ids for the timing calls below. */
 #define HGP_KID_RATE_G8 0    /* rating, groups of 8 lanes, 64-entry tables    */
 #define HGP_KID_RATE_G16 1   /* rating, groups of 16 lanes, 256-entry tables  */

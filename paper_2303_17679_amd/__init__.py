@@ -24,7 +24,9 @@ STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_OVERFLOW", -3: "HGP_E_WOR
 
 EXPORTS = ["hgp_default_params", "hgp_workspace_bytes", "hgp_validate", "hgp_coarsen", "hgp_contract",
            "hgp_project", "hgp_objective", "hgp_refine_lp", "hgp_initial_partition", "hgp_partition",
-           "hgp_timing_scratch_bytes", "hgp_timing_begin", "hgp_timing_end", "hgp_status_str"]
+           "hgp_timing_scratch_bytes", "hgp_timing_begin", "hgp_timing_end", "hgp_status_str",
+           "hgp_server_create", "hgp_server_submit", "hgp_server_wait", "hgp_server_destroy",
+           "hgp_batch_workspace_bytes", "hgp_partition_batch"]
 
 # kernel ids of the measurement calls, with the kernel symbol each one names
 KERNELS = ["k_rate_group<8, 64, 6>", "k_rate_group<16, 256, 8>", "k_rate_group<64, 1024, 10>", "k_rate_block",
@@ -95,6 +97,18 @@ def lib():
         L.hgp_timing_begin.argtypes = [u32, ctypes.c_int, P, ctypes.c_size_t, u32, u32]
         L.hgp_timing_end.restype = i32
         L.hgp_timing_end.argtypes = [u32, P, P, P]
+        L.hgp_server_create.restype = i32
+        L.hgp_server_create.argtypes = [u32, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]
+        L.hgp_server_submit.restype = i32
+        L.hgp_server_submit.argtypes = [P, P, P, P, P, P, ctypes.POINTER(ctypes.c_uint64)]
+        L.hgp_server_wait.restype = i32
+        L.hgp_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.hgp_server_destroy.restype = i32; L.hgp_server_destroy.argtypes = [P]
+        L.hgp_batch_workspace_bytes.restype = i32
+        L.hgp_batch_workspace_bytes.argtypes = [P, P, u32, u32, ctypes.POINTER(ctypes.c_size_t)]
+        L.hgp_partition_batch.restype = i32
+        L.hgp_partition_batch.argtypes = [P, P, u32, u32, P, P, P, P, ctypes.c_size_t, P]
         _lib = L
     return _lib
 
@@ -307,3 +321,75 @@ class KernelTimer:
         by = (ctypes.c_double * k)()
         _check(lib().hgp_timing_end(k, ms, ln, by), "hgp_timing_end")
         return [dict(kernel=KERNELS[i], ms=ms[i], launches=int(ln[i]), bytes=by[i]) for i in range(k)]
+
+
+def partition_batch(hs, prms, lanes: int = 8, ws_bytes: int | None = None):
+    """Partitions the Hypergraphs hs[i] with Params prms[i] in one batch call
+    (hgp_partition_batch).  Returns (list of part tensors, objectives (int64
+    tensor), levels list)."""
+    torch = _torch()
+    count = len(hs)
+    HG = _HG * count
+    PA = Params * count
+    structs = HG(*[h.struct() for h in hs])
+    params_ = PA(*prms)
+    need = ctypes.c_size_t(0)
+    _check(lib().hgp_batch_workspace_bytes(structs, params_, count, lanes, ctypes.byref(need)),
+           "hgp_batch_workspace_bytes")
+    nb = int(need.value) if ws_bytes is None else int(ws_bytes)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=hs[0].device)
+    parts = [torch.empty(h.n, dtype=torch.int32, device=h.device) for h in hs]
+    pptr = (ctypes.c_void_p * count)(*[p.data_ptr() for p in parts])
+    objs = torch.zeros(count, dtype=torch.int64, device=hs[0].device)
+    lv = (ctypes.c_uint32 * count)()
+    _check(lib().hgp_partition_batch(structs, params_, count, lanes, pptr, _ptr(objs), lv, _ptr(ws), ws.numel(),
+                                     _stream()), "hgp_partition_batch")
+    return parts, objs, list(lv)
+
+
+class Server:
+    """Continuous-admission partition server (hgp_server_*): requests are
+    admitted as lanes and pool memory free up and run overlapped."""
+
+    def __init__(self, lanes: int, pool_bytes: int, device="cuda"):
+        torch = _torch()
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=device)
+        self._h = ctypes.c_void_p(0)
+        _check(lib().hgp_server_create(lanes, _ptr(self.pool), self.pool.numel(), ctypes.byref(self._h)),
+               "hgp_server_create")
+        self._live = {}
+
+    def submit(self, h: Hypergraph, prm: Params):
+        """Queues one request; returns (ticket, part tensor, objective tensor)."""
+        torch = _torch()
+        part = torch.empty(h.n, dtype=torch.int32, device=h.device)
+        obj = torch.zeros(1, dtype=torch.int64, device=h.device)
+        s = h.struct()
+        p = Params(prm.k, prm.eps_num, prm.eps_den, prm.seed, prm.limit_factor, prm.coarsen_subrounds,
+                   prm.lp_subrounds, prm.lp_rounds)
+        t = ctypes.c_uint64(0)
+        _check(lib().hgp_server_submit(self._h, ctypes.byref(s), ctypes.byref(p), _ptr(part), _ptr(obj), _stream(),
+                                       ctypes.byref(t)), "hgp_server_submit")
+        self._live[t.value] = (h, part, obj)  # keep the inputs alive until the wait
+        return t.value, part, obj
+
+    def wait(self, ticket: int):
+        """Blocks until the request is done; returns (levels, latency_ms, queue_ms)."""
+        lv = ctypes.c_uint32(0)
+        lat = ctypes.c_double(0)
+        qm = ctypes.c_double(0)
+        st = lib().hgp_server_wait(self._h, ticket, ctypes.byref(lv), ctypes.byref(lat), ctypes.byref(qm))
+        self._live.pop(ticket, None)
+        _check(st, "hgp_server_wait")
+        return int(lv.value), lat.value, qm.value
+
+    def close(self):
+        if self._h:
+            lib().hgp_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -184,6 +184,78 @@ hgp_status hgp_initial_partition(const hgp_hg *h, uint32_t k, uint32_t *part, vo
     });
 }
 
+}  // extern "C"
+
+namespace {
+// The multilevel driver (paper Alg. 1 with the deterministic components, no
+// FM / flows) on one hypergraph, scratch from A, work on st.  Syncs.  Throws
+// Error on workspace or device failures.
+hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part, int64_t *objective,
+                         uint32_t *levels_out, Arena &A, hipStream_t st) {
+    hgp_status v = validate(*h0, A, st);
+    if (v != HGP_OK) return v;
+    struct Level {
+        hgp_hg h;
+        uint32_t *cid;  // map to the next coarser level
+    };
+    std::vector<Level> L;
+    L.push_back({*h0, nullptr});
+    const uint64_t limit = (uint64_t)prm->limit_factor * prm->k;
+    for (;;) {
+        hgp_hg cur = L.back().h;
+        if (!((uint64_t)cur.n > limit)) break;
+        size_t mk = A.mark();
+        // storage of the would-be coarse level (capacities of this level)
+        uint32_t *cid = A.alloc<uint32_t>(cur.n);
+        hgp_hg_out out;
+        out.cap_n = cur.n; out.cap_m = cur.m; out.cap_p = cur.p;
+        out.pin_off = A.alloc<uint32_t>((size_t)cur.m + 1);
+        out.pins = A.alloc<uint32_t>(cur.p);
+        out.inc_off = A.alloc<uint32_t>((size_t)cur.n + 1);
+        out.inc = A.alloc<uint32_t>(cur.p);
+        out.vwgt = A.alloc<int32_t>(cur.n);
+        out.nwgt = A.alloc<int32_t>(cur.m);
+        out.dims = nullptr;
+        size_t mk_rep = A.mark();
+        uint32_t *rep = A.alloc<uint32_t>(cur.n);
+        uint32_t cnt = 0;
+        coarsen_pass(cur, *prm, (uint32_t)(L.size() - 1), rep, nullptr, &cnt, A, st);
+        if ((uint64_t)100 * (cur.n - cnt) <= (uint64_t)cur.n) {
+            A.release(mk);
+            break;
+        }
+        uint32_t dims[3];
+        contract(cur, rep, cid, out, dims, A, st);
+        A.release(mk_rep);
+        hgp_hg nh;
+        nh.n = dims[0]; nh.m = dims[1]; nh.p = dims[2];
+        nh.pin_off = out.pin_off; nh.pins = out.pins; nh.inc_off = out.inc_off; nh.inc = out.inc;
+        nh.vwgt = out.vwgt; nh.nwgt = out.nwgt;
+        L.back().cid = cid;
+        L.push_back({nh, nullptr});
+        if (L.size() > 4096) break;
+    }
+    const uint32_t nl = (uint32_t)L.size() - 1;
+    // initial partition and LP on the coarsest level
+    hgp_hg cs = L.back().h;
+    uint32_t *cpart = (nl == 0) ? part : A.alloc<uint32_t>(cs.n);
+    initial_partition(cs, prm->k, cpart, A, st);
+    refine_lp(cs, *prm, nl, cpart, objective, nullptr, A, st);
+    for (int l = (int)nl - 1; l >= 0; --l) {
+        hgp_hg fh = L[l].h;
+        uint32_t *fpart = (l == 0) ? part : A.alloc<uint32_t>(fh.n);
+        project(fh.n, L[l].cid, cpart, fpart, st);
+        refine_lp(fh, *prm, (uint32_t)l, fpart, objective, nullptr, A, st);
+        cpart = fpart;
+    }
+    stream_sync(st);
+    if (levels_out) *levels_out = nl;
+    return HGP_OK;
+}
+}  // namespace
+
+extern "C" {
+
 hgp_status hgp_partition(const hgp_hg *h0, const hgp_params *prm, uint32_t *part, int64_t *objective,
                          uint32_t *levels_out, void *ws, size_t ws_bytes, void *stream) {
     hgp_status s = check_hg(h0);
@@ -193,65 +265,7 @@ hgp_status hgp_partition(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
     hipStream_t st = S(stream);
     return guarded([&]() -> hgp_status {
         Arena A(ws, ws_bytes);
-        hgp_status v = validate(*h0, A, st);
-        if (v != HGP_OK) return v;
-        struct Level {
-            hgp_hg h;
-            uint32_t *cid;  // map to the next coarser level
-        };
-        std::vector<Level> L;
-        L.push_back({*h0, nullptr});
-        const uint64_t limit = (uint64_t)prm->limit_factor * prm->k;
-        for (;;) {
-            hgp_hg cur = L.back().h;
-            if (!((uint64_t)cur.n > limit)) break;
-            size_t mk = A.mark();
-            // storage of the would-be coarse level (capacities of this level)
-            uint32_t *cid = A.alloc<uint32_t>(cur.n);
-            hgp_hg_out out;
-            out.cap_n = cur.n; out.cap_m = cur.m; out.cap_p = cur.p;
-            out.pin_off = A.alloc<uint32_t>((size_t)cur.m + 1);
-            out.pins = A.alloc<uint32_t>(cur.p);
-            out.inc_off = A.alloc<uint32_t>((size_t)cur.n + 1);
-            out.inc = A.alloc<uint32_t>(cur.p);
-            out.vwgt = A.alloc<int32_t>(cur.n);
-            out.nwgt = A.alloc<int32_t>(cur.m);
-            out.dims = nullptr;
-            size_t mk_rep = A.mark();
-            uint32_t *rep = A.alloc<uint32_t>(cur.n);
-            uint32_t cnt = 0;
-            coarsen_pass(cur, *prm, (uint32_t)(L.size() - 1), rep, nullptr, &cnt, A, st);
-            if ((uint64_t)100 * (cur.n - cnt) <= (uint64_t)cur.n) {
-                A.release(mk);
-                break;
-            }
-            uint32_t dims[3];
-            contract(cur, rep, cid, out, dims, A, st);
-            A.release(mk_rep);
-            hgp_hg nh;
-            nh.n = dims[0]; nh.m = dims[1]; nh.p = dims[2];
-            nh.pin_off = out.pin_off; nh.pins = out.pins; nh.inc_off = out.inc_off; nh.inc = out.inc;
-            nh.vwgt = out.vwgt; nh.nwgt = out.nwgt;
-            L.back().cid = cid;
-            L.push_back({nh, nullptr});
-            if (L.size() > 4096) break;
-        }
-        const uint32_t nl = (uint32_t)L.size() - 1;
-        // initial partition and LP on the coarsest level
-        hgp_hg cs = L.back().h;
-        uint32_t *cpart = (nl == 0) ? part : A.alloc<uint32_t>(cs.n);
-        initial_partition(cs, prm->k, cpart, A, st);
-        refine_lp(cs, *prm, nl, cpart, objective, nullptr, A, st);
-        for (int l = (int)nl - 1; l >= 0; --l) {
-            hgp_hg fh = L[l].h;
-            uint32_t *fpart = (l == 0) ? part : A.alloc<uint32_t>(fh.n);
-            project(fh.n, L[l].cid, cpart, fpart, st);
-            refine_lp(fh, *prm, (uint32_t)l, fpart, objective, nullptr, A, st);
-            cpart = fpart;
-        }
-        HGP_CHECK_HIP(hipStreamSynchronize(st));
-        if (levels_out) *levels_out = nl;
-        return HGP_OK;
+        return partition_one(h0, prm, part, objective, levels_out, A, st);
     });
 }
 

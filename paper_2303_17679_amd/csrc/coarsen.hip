@@ -242,13 +242,18 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
 template <bool GLOBAL>
 __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t *list, uint32_t count,
                                                       uint32_t *gkeys, uint32_t *gstamp, uint64_t *gR,
-                                                      size_t slice_cap, uint32_t n_cur) {
+                                                      uint32_t *gocc, size_t slice_cap, uint32_t n_cur,
+                                                      const uint32_t *bound) {
     constexpr int LCAP = 4096, LLOG = 12;
     __shared__ uint32_t lkeys[GLOBAL ? 1 : LCAP];
     __shared__ uint32_t lstamp[GLOBAL ? 1 : LCAP];
     __shared__ uint64_t lR[GLOBAL ? 1 : LCAP];
     __shared__ uint64_t redR[BLOCK / WAVE];
     __shared__ uint32_t redC[BLOCK / WAVE];
+    __shared__ uint32_t nocc;
+    // global tables start clean and are left clean: only the slots a
+    // candidate occupied (listed in occ) are read back and reset
+    uint32_t *occ = GLOBAL ? gocc + (size_t)blockIdx.x * slice_cap : nullptr;
     uint32_t *keys = GLOBAL ? gkeys + (size_t)blockIdx.x * slice_cap : lkeys;
     uint32_t *stamp = GLOBAL ? gstamp + (size_t)blockIdx.x * slice_cap : lstamp;
     uint64_t *R = GLOBAL ? gR + (size_t)blockIdx.x * slice_cap : lR;
@@ -257,24 +262,18 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
         if (!(a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u])) continue;  // uniform per block
         uint32_t cap, lg;
         if (GLOBAL) {
-            // capacity: power of two >= 1.5 * min(B(u), n)
-            uint64_t bsum = 0;
-            for (uint32_t j = a.inc_off[u]; j < a.inc_off[u + 1]; ++j) {
-                uint32_t e = a.inc[j];
-                uint32_t sz = a.pin_off[e + 1] - a.pin_off[e];
-                if (sz >= 2) bsum += sz - 1;
-            }
-            uint64_t want = bsum < n_cur ? bsum : n_cur;
+            // capacity: power of two >= 1.5 D + 1 for D = min(B(u), n - 1)
+            // distinct clusters; the host sized the slices for the largest D
+            uint64_t want = bound[u] < n_cur - 1 ? bound[u] : n_cur - 1;
             want = want + want / 2 + 1;
             lg = 13;
             while (((uint64_t)1 << lg) < want) ++lg;
             cap = 1u << lg;
-            if (cap > slice_cap) { cap = (uint32_t)slice_cap; lg = 31 - __clz(cap); }
+            if (threadIdx.x == 0) nocc = 0;
         } else {
             cap = LCAP; lg = LLOG;
+            for (uint32_t s = threadIdx.x; s < cap; s += BLOCK) { keys[s] = NONE; stamp[s] = NONE; R[s] = 0; }
         }
-        for (uint32_t s = threadIdx.x; s < cap; s += BLOCK) { keys[s] = NONE; stamp[s] = NONE; R[s] = 0; }
-        if (GLOBAL) __threadfence();  // the clear reaches L2 before any atomic on the table
         __syncthreads();
         uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
         auto insert = [&](uint32_t C) -> uint32_t {
@@ -285,7 +284,11 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
                 if (k == C) break;
                 if (k == NONE) {
                     uint32_t old = atomicCAS(&keys[slot], NONE, C);
-                    if (old == NONE || old == C) break;
+                    if (old == NONE) {
+                        if (GLOBAL) occ[atomicAdd(&nocc, 1u)] = slot;
+                        break;
+                    }
+                    if (old == C) break;
                 }
                 slot = (slot + 1) & (cap - 1);
             }
@@ -324,14 +327,27 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
         }
         uint64_t bR = 0;
         uint32_t bC = NONE;
-        if (GLOBAL) __threadfence();
-        for (uint32_t s = threadIdx.x; s < cap; s += BLOCK) {
-            // the global table was filled by device-scope atomics of other
-            // waves: read it at device scope (never a stale L1 line)
-            uint32_t C = GLOBAL ? __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : keys[s];
-            if (C == NONE) continue;
-            uint64_t rc = GLOBAL ? __hip_atomic_load(&R[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : R[s];
-            if (valid_target(a, u, C) && better_lazy(a, rc, C, bR, bC)) { bR = rc; bC = C; }
+        if (GLOBAL) {
+            __threadfence();
+            const uint32_t no = nocc;
+            for (uint32_t i = threadIdx.x; i < no; i += BLOCK) {
+                // the table was filled by device-scope atomics of other waves:
+                // read it at device scope (never a stale L1 line), then reset
+                const uint32_t s = occ[i];
+                const uint32_t C = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t rc = __hip_atomic_load(&R[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                keys[s] = NONE;
+                stamp[s] = NONE;
+                R[s] = 0;
+                if (valid_target(a, u, C) && better_lazy(a, rc, C, bR, bC)) { bR = rc; bC = C; }
+            }
+            __threadfence();  // the reset is visible before the next candidate's atomics
+        } else {
+            for (uint32_t s = threadIdx.x; s < cap; s += BLOCK) {
+                const uint32_t C = keys[s];
+                if (C == NONE) continue;
+                if (valid_target(a, u, C) && better_lazy(a, R[s], C, bR, bC)) { bR = R[s]; bC = C; }
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -413,32 +429,67 @@ __device__ inline int rate_class(uint64_t B) {
     return 4;
 }
 
+// B(u) = sum over incident nets of at least two pins of (|e| - 1), a bound
+// on the clusters a rating of u can touch.  Thread per vertex; a vertex of
+// more than 32 incident nets is summed by its whole wave.
+__global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, const uint32_t *inc_off,
+                                                    const uint32_t *inc, uint32_t n, uint32_t *bound) {
+    for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
+        const uint32_t u = u0 + threadIdx.x;
+        uint32_t j0 = 0, j1 = 0;
+        if (u < n) { j0 = inc_off[u]; j1 = inc_off[u + 1]; }
+        const bool heavy = j1 - j0 > 32;
+        uint64_t b = 0;
+        if (!heavy)
+            for (uint32_t j = j0; j < j1; ++j) {
+                const uint32_t e = inc[j];
+                const uint32_t sz = pin_off[e + 1] - pin_off[e];
+                if (sz >= 2) b += sz - 1;
+            }
+        uint64_t hm = __ballot(heavy);
+        while (hm) {  // the wave sums each heavy vertex together
+            const int h = __ffsll((long long)hm) - 1;
+            hm &= hm - 1;
+            const uint32_t hj0 = __shfl(j0, h, 64), hj1 = __shfl(j1, h, 64);
+            uint64_t t = 0;
+            for (uint32_t j = hj0 + __lane_id(); j < hj1; j += WAVE) {
+                const uint32_t e = inc[j];
+                const uint32_t sz = pin_off[e + 1] - pin_off[e];
+                if (sz >= 2) t += sz - 1;
+            }
+            t = wave_sum(t);
+            if ((int)__lane_id() == h) b = t;
+        }
+        if (u < n) bound[u] = b > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)b;
+    }
+}
+
 // pass 1 (fill=false): count per (sub-round, class); pass 2: fill lists.
 // Counters are aggregated per block in LDS (one global atomic per key and
 // block), so millions of vertices never contend on a handful of addresses.
 constexpr int MAX_KEYS = 256 * NCLASS;
-__global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *pin_off, const uint32_t *inc_off,
-                                                    const uint32_t *inc, uint32_t n, uint64_t mseed, uint32_t level,
-                                                    uint32_t S, const int32_t *vwgt, uint32_t *rep, int64_t *cw,
-                                                    int64_t *tsum, uint32_t *counts, uint32_t *cursor,
+// The class of a candidate follows D = min(B(u), n - 1), a bound on the
+// distinct clusters it rates; counts[S * NCLASS] receives the largest D of
+// the global-table class.
+__global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *bound, uint32_t n, uint64_t mseed,
+                                                    uint32_t level, uint32_t S, const int32_t *vwgt, uint32_t *rep,
+                                                    int64_t *cw, int64_t *tsum, uint32_t *counts, uint32_t *cursor,
                                                     uint32_t *lists, bool fill) {
     __shared__ uint32_t lcnt[MAX_KEYS];
     __shared__ uint32_t lbase[MAX_KEYS];
+    __shared__ uint32_t lmaxd;
     const uint32_t nkeys = S * NCLASS;
     for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) lcnt[i] = 0;
+    if (threadIdx.x == 0) lmaxd = 0;
     __syncthreads();
     for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
         const uint32_t u = u0 + threadIdx.x;
         int key = -1;
         uint32_t lrank = 0;
         if (u < n) {
-            uint64_t B = 0;
-            for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) {
-                uint32_t e = inc[j];
-                uint32_t sz = pin_off[e + 1] - pin_off[e];
-                if (sz >= 2) B += sz - 1;
-            }
-            int c = rate_class(B);
+            const uint32_t D = bound[u] < n - 1 ? bound[u] : n - 1;
+            const int c = rate_class(D);
+            if (c == NCLASS - 1 && !fill) atomicMax(&lmaxd, D);
             uint32_t r = (uint32_t)(tag_hash(mseed, 1, level, 0, u) % S);
             if (!fill) {
                 rep[u] = u;
@@ -467,6 +518,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *pin_off, con
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK)
             if (lcnt[i]) atomicAdd(&counts[i], lcnt[i]);
+        if (threadIdx.x == 0 && lmaxd) atomicMax(&counts[nkeys], lmaxd);
     }
 }
 
@@ -570,11 +622,13 @@ struct CoarsenBufs {
     uint8_t *ok;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt;
-    uint32_t *gkeys, *gstamp;
-    uint64_t *gR;
-    size_t slice_cap;
-    uint32_t nslices;
+    uint32_t *bound;
+    char *greg;         // reserved region of the global rating tables
+    size_t greg_bytes;  // 16 tables for the worst case D = n - 1
 };
+
+// One global-table entry: key, stamp, occupancy slot (4 B each), rating (8 B).
+constexpr size_t GENTRY_BYTES = 20;
 
 static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t S, CoarsenBufs &B) {
     B.nscore = A.alloc<uint64_t>(m);
@@ -585,7 +639,8 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t S, CoarsenBufs &B) {
     B.proposers = A.alloc<uint32_t>(n);
     B.slow = A.alloc<uint32_t>(n);
     B.lists = A.alloc<uint32_t>(n);
-    B.counts = A.alloc<uint32_t>((size_t)S * NCLASS);
+    B.counts = A.alloc<uint32_t>((size_t)S * NCLASS + 1);
+    B.bound = A.alloc<uint32_t>(n);
     B.cursor = A.alloc<uint32_t>((size_t)S * NCLASS);
     B.scal = A.alloc<uint32_t>(8);
     B.ok = A.alloc<uint8_t>(n);
@@ -594,14 +649,12 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t S, CoarsenBufs &B) {
     B.incl = A.alloc<uint64_t>(n);
     B.vals = A.alloc<uint32_t>(n);
     B.vals_alt = A.alloc<uint32_t>(n);
-    // global-memory rating tables: enough for any candidate (capacity >= 1.5 n)
+    // global-memory rating tables: room for 16 tables of the largest
+    // possible capacity (>= 1.5 n); smaller candidates get more, smaller tables
     size_t sc = 8192;
     while (sc < (size_t)n + n / 2 + 1) sc <<= 1;
-    B.slice_cap = sc;
-    B.nslices = 16;
-    B.gkeys = A.alloc<uint32_t>(sc * B.nslices);
-    B.gstamp = A.alloc<uint32_t>(sc * B.nslices);
-    B.gR = A.alloc<uint64_t>(sc * B.nslices);
+    B.greg_bytes = 16 * sc * GENTRY_BYTES;
+    B.greg = A.alloc<char>(B.greg_bytes);
     // radix sort temporaries
     sort_reserve(A, n);
     scan_reserve<uint64_t>(A, n);
@@ -631,20 +684,41 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
 
     k_net_score<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.nwgt, m, B.nscore);
     HGP_LAUNCH_CHECK();
-    HGP_CHECK_HIP(hipMemsetAsync(B.counts, 0, sizeof(uint32_t) * S * NCLASS, st));
-    k_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, mseed, level, S,
-                                                                 h.vwgt, rep, B.cw, B.tsum, B.counts, B.cursor,
-                                                                 B.lists, false);
+    HGP_CHECK_HIP(hipMemsetAsync(B.counts, 0, sizeof(uint32_t) * (S * NCLASS + 1), st));
+    k_vertex_b<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, B.bound);
     HGP_LAUNCH_CHECK();
-    std::vector<uint32_t> counts(S * NCLASS), offs(S * NCLASS + 1);
-    HGP_CHECK_HIP(hipMemcpyAsync(counts.data(), B.counts, sizeof(uint32_t) * S * NCLASS, hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    k_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
+                                                                 B.tsum, B.counts, B.cursor, B.lists, false);
+    HGP_LAUNCH_CHECK();
+    std::vector<uint32_t> counts(S * NCLASS + 1), offs(S * NCLASS + 1);
+    HGP_CHECK_HIP(hipMemcpyAsync(counts.data(), B.counts, sizeof(uint32_t) * (S * NCLASS + 1), hipMemcpyDeviceToHost,
+                                 st));
+    stream_sync(st);
+    // global rating tables, carved from the reserved region: capacity for the
+    // largest D of the global class, as many tables as fit (16 .. 1024)
+    uint32_t *gkeys = nullptr, *gstamp = nullptr, *gocc = nullptr;
+    uint64_t *gR = nullptr;
+    size_t slice_cap = 8192;
+    uint32_t nslices = 0;
+    bool any_global = false;
+    for (uint32_t r = 0; r < S; ++r) any_global |= counts[r * NCLASS + NCLASS - 1] > 0;
+    if (any_global) {
+        const uint64_t D = counts[S * NCLASS];
+        while (slice_cap < D + D / 2 + 1) slice_cap <<= 1;
+        nslices = (uint32_t)std::min<size_t>(1024, B.greg_bytes / (slice_cap * GENTRY_BYTES));
+        const size_t e = slice_cap * nslices;
+        gR = (uint64_t *)B.greg;
+        gkeys = (uint32_t *)(B.greg + 8 * e);
+        gstamp = gkeys + e;
+        gocc = gstamp + e;
+        HGP_CHECK_HIP(hipMemsetAsync(gR, 0, 8 * e, st));
+        HGP_CHECK_HIP(hipMemsetAsync(gkeys, 0xFF, 8 * e, st));  // keys and stamps
+    }
     offs[0] = 0;
     for (uint32_t i = 0; i < S * NCLASS; ++i) offs[i + 1] = offs[i] + counts[i];
     HGP_CHECK_HIP(hipMemcpyAsync(B.cursor, offs.data(), sizeof(uint32_t) * S * NCLASS, hipMemcpyHostToDevice, st));
-    k_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, mseed, level, S,
-                                                                 h.vwgt, rep, B.cw, B.tsum, B.counts, B.cursor,
-                                                                 B.lists, true);
+    k_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
+                                                                 B.tsum, B.counts, B.cursor, B.lists, true);
     HGP_LAUNCH_CHECK();
 
     uint32_t cnt = n;
@@ -682,26 +756,26 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                     k_rate_group<64, 1024, 10><<<grid_for(cntc, BLOCK / 64, 8192), BLOCK, 0, st>>>(a, lst, cntc);
                     break;
                 case 3:
-                    k_rate_block<false><<<grid_for(cntc, 1, 8192), BLOCK, 0, st>>>(a, lst, cntc, nullptr, nullptr,
-                                                                                  nullptr, 0, n);
+                    k_rate_block<false><<<grid_for(cntc, 1, 8192), BLOCK, 0, st>>>(
+                        a, lst, cntc, nullptr, nullptr, nullptr, nullptr, 0, n, B.bound);
                     break;
                 default:
-                    k_rate_block<true><<<grid_for(cntc, 1, B.nslices), BLOCK, 0, st>>>(
-                        a, lst, cntc, B.gkeys, B.gstamp, B.gR, B.slice_cap, n);
+                    k_rate_block<true><<<grid_for(cntc, 1, nslices), BLOCK, 0, st>>>(
+                        a, lst, cntc, gkeys, gstamp, gR, gocc, slice_cap, n, B.bound);
                     break;
             }
             HGP_LAUNCH_CHECK();
         }
         uint32_t np = 0;
         HGP_CHECK_HIP(hipMemcpyAsync(&np, nprop, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        HGP_CHECK_HIP(hipStreamSynchronize(st));
+        stream_sync(st);
         if (np) {
             k_approve_fast<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.proposers, np, B.ptarget, B.cw,
                                                                               B.tsum, cap_mult, W, B.ok, B.slow, nslow);
             HGP_LAUNCH_CHECK();
             uint32_t ns = 0;
             HGP_CHECK_HIP(hipMemcpyAsync(&ns, nslow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-            HGP_CHECK_HIP(hipStreamSynchronize(st));
+            stream_sync(st);
             if (ns) {
                 int ub = bits_for(n ? n - 1 : 0);
                 int cb = bits_for(n ? n - 1 : 0);
@@ -740,7 +814,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             HGP_LAUNCH_CHECK();
         }
         HGP_CHECK_HIP(hipMemcpyAsync(&cnt, ncl, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        HGP_CHECK_HIP(hipStreamSynchronize(st));
+        stream_sync(st);
         if ((uint64_t)5 * cnt < (uint64_t)2 * n) break;
     }
     if (n_clusters_dev) HGP_CHECK_HIP(hipMemcpyAsync(n_clusters_dev, ncl, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));

@@ -25,6 +25,13 @@ struct Error {
         if (e_ != hipSuccess) throw ::hgp::Error{HGP_E_DEVICE}; \
     } while (0)
 
+// Host waits for a stream.  By default they spin (lowest latency for a single
+// caller).  The worker threads of a partition server set blocking_waits: the
+// wait then sleeps in the driver, so that many waiting lanes do not occupy
+// the host cores that the launching lanes need.
+inline thread_local bool blocking_waits = false;
+void stream_sync(hipStream_t st);
+
 #define HGP_LAUNCH_CHECK() HGP_CHECK_HIP(hipGetLastError())
 
 #define HGP_REQUIRE(cond, code)                 \

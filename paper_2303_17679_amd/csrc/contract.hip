@@ -250,7 +250,7 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
     scan_apply<uint32_t>(A, n, IsRep{rep}, StoreRank{B.rank}, d_nc, st);
     uint32_t nc = 0;
     HGP_CHECK_HIP(hipMemcpyAsync(&nc, d_nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     HGP_REQUIRE(nc <= out.cap_n, HGP_E_INVALID);
     HGP_CHECK_HIP(hipMemsetAsync(out.vwgt, 0, sizeof(int32_t) * (nc ? nc : 1), st));
     k_cid<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(rep, B.rank, n, h.vwgt, cid, out.vwgt);
@@ -264,7 +264,7 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
     segmented_sort(A, B.ss_net, h.pin_off, m, B.tmp, true, B.usize, st);
     uint32_t cnt_ml[2];
     HGP_CHECK_HIP(hipMemcpyAsync(cnt_ml, B.ss_net.scal, sizeof(cnt_ml), hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
 
     // 3. hashes, drop single-pin nets, identical-net detection
     if (m) {
@@ -285,7 +285,7 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
     scan_apply<uint32_t>(A, m, IsValid{B.valid}, GatherValid{B.valid, B.hkey, B.keys, B.vals}, d_nv, st);
     uint32_t nv = 0;
     HGP_CHECK_HIP(hipMemcpyAsync(&nv, d_nv, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     uint64_t *kk = B.keys;
     uint32_t *vv = B.vals;
     radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, nv, 0, 32, st);
@@ -301,7 +301,7 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
                          StoreKept{B.newid, B.newoff, out.pin_off, out.nwgt, B.wsum}, d_tot, st);
     uint64_t tot = 0;
     HGP_CHECK_HIP(hipMemcpyAsync(&tot, d_tot, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     uint32_t mc = (uint32_t)(tot >> 32), pc = (uint32_t)tot;
     HGP_REQUIRE(mc <= out.cap_m && pc <= out.cap_p, HGP_E_INVALID);
     HGP_CHECK_HIP(hipMemcpyAsync(out.pin_off + mc, &pc, sizeof(uint32_t), hipMemcpyHostToDevice, st));
@@ -336,7 +336,7 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
     segmented_sort(A, B.ss_inc, out.inc_off, nc, out.inc, false, nullptr, st);
     uint32_t dims[3] = {nc, mc, pc};
     if (out.dims) HGP_CHECK_HIP(hipMemcpyAsync(out.dims, dims, sizeof(dims), hipMemcpyHostToDevice, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     if (dims_host) { dims_host[0] = nc; dims_host[1] = mc; dims_host[2] = pc; }
     A.release(mk);
 }

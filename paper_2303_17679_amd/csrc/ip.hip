@@ -221,7 +221,7 @@ size_t ip_workspace(uint32_t n, uint32_t p, uint32_t k) {
 static uint32_t read_u32(const uint32_t *d, hipStream_t st) {
     uint32_t h = 0;
     HGP_CHECK_HIP(hipMemcpyAsync(&h, d, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     return h;
 }
 
@@ -300,7 +300,7 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
     HGP_LAUNCH_CHECK();
     k_assign<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.order, n, B.S, k, part);
     HGP_LAUNCH_CHECK();
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     A.release(mk);
 }
 

@@ -30,6 +30,20 @@ struct Bits {
     uint64_t w[KW];
 };
 
+// Connectivity record of one net: Lambda (blocks holding a pin of the net)
+// and Lambda1 (blocks holding exactly one pin) as k-bit sets, and the net
+// weight.  A gain or an update that touches a net reads one record: 32 bytes
+// for k <= 64, half of a 64-byte HBM sector, where three separate arrays
+// would cost three sectors.
+template <int KW>
+struct alignas(16) NetRec {
+    uint64_t lam[KW];
+    uint64_t lam1[KW];
+    int64_t w;
+};
+static_assert(sizeof(NetRec<1>) == 32 && sizeof(NetRec<2>) == 48 && sizeof(NetRec<4>) == 80, "record size");
+inline size_t netrec_bytes(int KW) { return 16u * (size_t)(KW + 1); }
+
 // ---------------------------------------------------------------------------
 // Connectivity bitsets of nets
 // ---------------------------------------------------------------------------
@@ -71,8 +85,8 @@ __device__ inline int popc_bits(const uint64_t *x) {
 // Thread per net for nets of at most 64 pins; longer nets go to a list.
 template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_conn_small(const uint32_t *pin_off, const uint32_t *pins, uint32_t m,
-                                                      const int32_t *nwgt, const uint32_t *part, uint64_t *lam,
-                                                      uint64_t *lam1, int64_t *f, uint32_t *longl, uint32_t *nlong) {
+                                                      const int32_t *nwgt, const uint32_t *part, NetRec<KW> *nr,
+                                                      int64_t *f, uint32_t *longl, uint32_t *nlong) {
     __shared__ int64_t red[BLOCK / WAVE];
     int64_t acc = 0;
     for (uint32_t e0 = blockIdx.x * blockDim.x; e0 < m; e0 += gridDim.x * blockDim.x) {
@@ -85,12 +99,15 @@ __global__ __launch_bounds__(BLOCK) void k_conn_small(const uint32_t *pin_off, c
         if (!act || lng) continue;
         uint64_t once[KW], twice[KW];
         net_bits<KW>(pins, b, len, part, once, twice);
+        NetRec<KW> R;
 #pragma unroll
         for (int q = 0; q < KW; ++q) {
-            lam[(size_t)e * KW + q] = once[q];
-            lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
+            R.lam[q] = once[q];
+            R.lam1[q] = once[q] & ~twice[q];
         }
-        acc += lam_cost(popc_bits<KW>(once)) * nwgt[e];
+        R.w = nwgt[e];
+        nr[e] = R;
+        acc += lam_cost(popc_bits<KW>(once)) * R.w;
     }
     acc = wave_sum(acc);
     if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
@@ -106,9 +123,8 @@ __global__ __launch_bounds__(BLOCK) void k_conn_small(const uint32_t *pin_off, c
 template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_conn_long(const uint32_t *pin_off, const uint32_t *pins,
                                                      const uint32_t *list, const uint32_t *count_dev,
-                                                     const int32_t *nwgt, const uint32_t *part, uint64_t *lam,
-                                                     uint64_t *lam1, int64_t *f, bool delta, uint32_t *bcnt,
-                                                     const uint32_t *abort) {
+                                                     const int32_t *nwgt, const uint32_t *part, NetRec<KW> *nr,
+                                                     int64_t *f, bool delta, uint32_t *bcnt, const uint32_t *abort) {
     if (abort && *abort) return;
     const uint32_t count = *count_dev;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -139,16 +155,19 @@ __global__ __launch_bounds__(BLOCK) void k_conn_long(const uint32_t *pin_off, co
             }
         }
         const int lnew = popc_bits<KW>(once);
-        const int lold = delta ? popc_bits<KW>(lam + (size_t)e * KW) : 0;  // read before lane 0 rewrites
+        const int lold = delta ? popc_bits<KW>(nr[e].lam) : 0;  // read before lane 0 rewrites
         wave_sync();
         if (__lane_id() == 0) {
             int64_t d = lam_cost(lnew) - (delta ? lam_cost(lold) : 0);
+            NetRec<KW> R;
 #pragma unroll
             for (int q = 0; q < KW; ++q) {
-                lam[(size_t)e * KW + q] = once[q];
-                lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
+                R.lam[q] = once[q];
+                R.lam1[q] = once[q] & ~twice[q];
             }
-            if (d) atomic_add_i64(f, d * nwgt[e]);
+            R.w = nwgt[e];
+            nr[e] = R;
+            if (d) atomic_add_i64(f, d * R.w);
         }
         if (delta && bcnt && (lnew > 1) != (lold > 1)) {
             const uint32_t dl = lnew > 1 ? 1u : 0xFFFFFFFFu;
@@ -172,10 +191,11 @@ __global__ __launch_bounds__(BLOCK) void k_block_weights(const uint32_t *part, c
 // ---------------------------------------------------------------------------
 // Gains
 // ---------------------------------------------------------------------------
+template <int KW>
 struct GainArgs {
     const uint32_t *inc_off, *inc;
-    const int32_t *nwgt, *vwgt;
-    const uint64_t *lam, *lam1;
+    const int32_t *vwgt;
+    const NetRec<KW> *nr;
     const uint32_t *part;
     const int64_t *bw;
     const uint32_t *bcnt;  // incident nets with lambda > 1 (boundary iff > 0)
@@ -190,7 +210,8 @@ struct GainArgs {
 
 // Called by every lane of the wave (uniformly); `has` is set by at most one
 // lane per proposing vertex.
-__device__ inline void propose(const GainArgs &a, uint32_t u, uint32_t s, uint32_t t, uint32_t g, bool has) {
+template <int KW>
+__device__ inline void propose(const GainArgs<KW> &a, uint32_t u, uint32_t s, uint32_t t, uint32_t g, bool has) {
     uint32_t pos = warp_agg_append(a.nprop, has);
     if (has) {
         a.plist[pos] = u;
@@ -222,7 +243,7 @@ __device__ inline T group_sum(T v) {
 // the per-target affinity sums, and all loads of a lane are issued before
 // any is used.
 template <int KW, int G>
-__device__ inline void gains_body(const GainArgs &a, const uint32_t *list, uint32_t count, uint32_t blk,
+__device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, uint32_t count, uint32_t blk,
                                   uint32_t nblk) {
     constexpr int GPB = BLOCK / G;
     constexpr bool CACHE = G < 64;
@@ -258,11 +279,11 @@ __device__ inline void gains_body(const GainArgs &a, const uint32_t *list, uint3
 #pragma unroll
                     for (int q = 0; q < KW; ++q) lv[c][q] = 0;
                     if (ev[c] != NONE) {
-                        const size_t e = ev[c];
-                        wv[c] = a.nwgt[e];
+                        const NetRec<KW> &R = a.nr[ev[c]];
+                        wv[c] = (int32_t)R.w;
 #pragma unroll
-                        for (int q = 0; q < KW; ++q) lv[c][q] = a.lam[e * KW + q];
-                        one = a.lam1[e * KW + (s >> 6)];
+                        for (int q = 0; q < KW; ++q) lv[c][q] = R.lam[q];
+                        one = R.lam1[s >> 6];
                     }
                     wI += wv[c];
                     if ((one >> (s & 63)) & 1ull) bu += wv[c];
@@ -294,13 +315,30 @@ __device__ inline void gains_body(const GainArgs &a, const uint32_t *list, uint3
                     }
                 }
             } else {
-                for (uint32_t j = j0 + l; j < j1; j += G) {
-                    const size_t e = a.inc[j];
-                    const int64_t w = a.nwgt[e];
-                    wI += w;
-                    if ((a.lam1[e * KW + (s >> 6)] >> (s & 63)) & 1ull) bu += w;
+                // one wave per node: the affinity of every block in one pass
+                // over the incident nets (per-wave LDS histogram), so a node
+                // of high degree costs sum of lambda(e), not degree x blocks
+                static_assert(G == WAVE, "the histogram path is wave per node");
+                __shared__ int64_t affs[BLOCK / WAVE][64 * KW];
+                int64_t *aff = affs[g];
 #pragma unroll
-                    for (int q = 0; q < KW; ++q) U[q] |= a.lam[e * KW + q];
+                for (int q = 0; q < KW; ++q) aff[q * 64 + l] = 0;
+                wave_sync();
+                for (uint32_t j = j0 + l; j < j1; j += G) {
+                    const NetRec<KW> &R = a.nr[a.inc[j]];
+                    const int64_t w = R.w;
+                    wI += w;
+                    if ((R.lam1[s >> 6] >> (s & 63)) & 1ull) bu += w;
+#pragma unroll
+                    for (int q = 0; q < KW; ++q) {
+                        uint64_t x = R.lam[q];
+                        U[q] |= x;
+                        while (x) {
+                            const int bit = __ffsll((long long)x) - 1;
+                            x &= x - 1;
+                            atomicAdd((unsigned long long *)&aff[q * 64 + bit], (unsigned long long)w);
+                        }
+                    }
                 }
                 bu = group_sum<G>(bu);
                 wI = group_sum<G>(wI);
@@ -309,24 +347,22 @@ __device__ inline void gains_body(const GainArgs &a, const uint32_t *list, uint3
 #pragma unroll
                     for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
                 U[s >> 6] &= ~(1ull << (s & 63));
+                wave_sync();  // every histogram update is done
+                // lane l judges blocks q * 64 + l (ascending per lane)
 #pragma unroll
                 for (int q = 0; q < KW; ++q) {
-                    uint64_t x = U[q];
-                    while (x) {
-                        const int bit = __ffsll((long long)x) - 1;
-                        x &= x - 1;
-                        const uint32_t t = (uint32_t)(q * 64 + bit);
-                        if (a.bw[t] + cu > a.lmax) continue;
-                        int64_t aff = 0;
-                        for (uint32_t j = j0 + l; j < j1; j += G) {
-                            const size_t e = a.inc[j];
-                            if ((a.lam[e * KW + q] >> bit) & 1ull) aff += a.nwgt[e];
-                        }
-                        aff = group_sum<G>(aff);
-                        const int64_t gn = bu - (wI - aff);
-                        if (gn > (int64_t)best_g) { best_g = (uint32_t)gn; best_t = t; }
-                    }
+                    const uint32_t t = (uint32_t)(q * 64) + l;
+                    if (!((U[q] >> l) & 1ull) || a.bw[t] + cu > a.lmax) continue;
+                    const int64_t gn = bu - (wI - aff[t]);
+                    if (gn > (int64_t)best_g) { best_g = (uint32_t)gn; best_t = t; }
                 }
+                // largest gain, then smallest block
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const uint32_t og = __shfl_xor(best_g, o, 64), ot = __shfl_xor(best_t, o, 64);
+                    if (og > best_g || (og == best_g && ot < best_t)) { best_g = og; best_t = ot; }
+                }
+                wave_sync();  // the histogram is read before the next node clears it
             }
         }
         propose(a, u, s, best_t, best_g, act && l == 0 && best_t != NONE);
@@ -342,7 +378,7 @@ struct ClassLists {
 };
 
 template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_gains(GainArgs a, const uint32_t *lists, ClassLists cl,
+__global__ __launch_bounds__(BLOCK) void k_gains(GainArgs<KW> a, const uint32_t *lists, ClassLists cl,
                                                  const uint32_t *ccnt) {
     if (*a.abort) return;
     const uint32_t b = blockIdx.x;
@@ -424,11 +460,11 @@ __global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, con
 
 // Boundary count of every node from scratch (once per level).
 template <int KW>
-__global__ void k_init_bcnt(const uint32_t *inc_off, const uint32_t *inc, uint32_t n, const uint64_t *lam,
+__global__ void k_init_bcnt(const uint32_t *inc_off, const uint32_t *inc, uint32_t n, const NetRec<KW> *nr,
                             uint32_t *bcnt) {
     for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
         uint32_t c = 0;
-        for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) c += popc_bits<KW>(lam + (size_t)inc[j] * KW) > 1;
+        for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) c += popc_bits<KW>(nr[inc[j]].lam) > 1;
         bcnt[u] = c;
     }
 }
@@ -449,7 +485,7 @@ __global__ void k_lp_reset(uint32_t *scal, uint32_t *pw, uint32_t kk, int64_t *d
 // every distinct incident net its weight, Lambda words and the one Lambda1
 // word the gain reads, counted once.
 template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs a, const uint32_t *lists, ClassLists cl,
+__global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs<KW> a, const uint32_t *lists, ClassLists cl,
                                                          const uint32_t *ccnt, uint32_t *nmark, uint32_t stamp,
                                                          unsigned long long *acc) {
     __shared__ unsigned long long red[BLOCK / WAVE];
@@ -943,8 +979,7 @@ template <int KW, int G>
 __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_off, const uint32_t *pins,
                                                             const uint32_t *inc_off, const uint32_t *inc,
                                                             const uint32_t *mlist, const uint32_t *nmov,
-                                                            const int32_t *nwgt, const uint32_t *part,
-                                                            uint64_t *lam, uint64_t *lam1, uint32_t *tstamp,
+                                                            const uint32_t *part, NetRec<KW> *nr, uint32_t *tstamp,
                                                             uint32_t stamp, int64_t *f, uint32_t *longl,
                                                             uint32_t *nlong, uint32_t *moves, uint32_t *bcnt,
                                                             const uint32_t *abort) {
@@ -967,14 +1002,15 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
             }
             uint64_t once[KW], twice[KW];
             net_bits<KW>(pins, b, len, part, once, twice);
-            const int lnew = popc_bits<KW>(once), lold = popc_bits<KW>(lam + (size_t)e * KW);
-            int64_t d = lam_cost(lnew) - lam_cost(lold);
+            NetRec<KW> &R = nr[e];
+            const int lnew = popc_bits<KW>(once), lold = popc_bits<KW>(R.lam);
+            const int64_t d = lam_cost(lnew) - lam_cost(lold);
 #pragma unroll
             for (int q = 0; q < KW; ++q) {
-                lam[(size_t)e * KW + q] = once[q];
-                lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
+                R.lam[q] = once[q];
+                R.lam1[q] = once[q] & ~twice[q];
             }
-            acc += d * nwgt[e];
+            acc += d * R.w;
             if ((lnew > 1) != (lold > 1)) {  // cut status flipped: boundary counts of its pins
                 const uint32_t delta = lnew > 1 ? 1u : 0xFFFFFFFFu;
                 for (uint32_t q = b; q < b + len; ++q) atomicAdd(&bcnt[pins[q]], delta);
@@ -991,52 +1027,13 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
     }
 }
 
-// Recompute Lambda / Lambda1 of touched nets (thread per net up to 64 pins;
-// longer nets are forwarded to the wave kernel) and add the objective delta.
-template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_lp_update(const uint32_t *pin_off, const uint32_t *pins,
-                                                     const uint32_t *tlist, const uint32_t *ntouched,
-                                                     const int32_t *nwgt, const uint32_t *part, uint64_t *lam,
-                                                     uint64_t *lam1, int64_t *f, uint32_t *longl, uint32_t *nlong) {
-    __shared__ int64_t red[BLOCK / WAVE];
-    const uint32_t cnt = *ntouched;
-    int64_t acc = 0;
-    for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < cnt; i0 += gridDim.x * blockDim.x) {
-        uint32_t i = i0 + threadIdx.x;
-        bool act = i < cnt;
-        uint32_t e = act ? tlist[i] : 0;
-        uint32_t b = act ? pin_off[e] : 0, len = act ? pin_off[e + 1] - b : 0;
-        bool lng = act && len > 64;
-        uint32_t pos = warp_agg_append(nlong, lng);
-        if (lng) longl[pos] = e;
-        if (!act || lng) continue;
-        uint64_t once[KW], twice[KW];
-        net_bits<KW>(pins, b, len, part, once, twice);
-        int64_t d = lam_cost(popc_bits<KW>(once)) - lam_cost(popc_bits<KW>(lam + (size_t)e * KW));
-#pragma unroll
-        for (int q = 0; q < KW; ++q) {
-            lam[(size_t)e * KW + q] = once[q];
-            lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
-        }
-        acc += d * nwgt[e];
-    }
-    acc = wave_sum(acc);
-    if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
-        if (t) atomic_add_i64(f, t);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 struct RefineBufs {
-    uint64_t *lam, *lam1;
+    void *nr;  // NetRec<KW>[m]
     int64_t *f, *bw;
-    uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *tlist, *scal, *pw, *slow, *mlist;
+    uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *pw, *slow, *mlist;
     int64_t *dbw_g;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt, *seg_start, *seg_end;
@@ -1045,8 +1042,7 @@ struct RefineBufs {
 
 static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     int KW = (int)((k + 63) / 64);
-    B.lam = A.alloc<uint64_t>((size_t)m * KW);
-    B.lam1 = A.alloc<uint64_t>((size_t)m * KW);
+    B.nr = A.alloc<char>((size_t)m * netrec_bytes(KW));
     B.f = A.alloc<int64_t>(1);
     B.bw = A.alloc<int64_t>(k);
     B.longl = A.alloc<uint32_t>(m);
@@ -1056,7 +1052,6 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.prop_t = A.alloc<uint32_t>(n);
     B.prop_g = A.alloc<uint32_t>(n);
     B.tstamp = A.alloc<uint32_t>(m);
-    B.tlist = A.alloc<uint32_t>(m);
     B.scal = A.alloc<uint32_t>(32);
     B.keys = A.alloc<uint64_t>(n);
     B.keys_alt = A.alloc<uint64_t>(n);
@@ -1086,11 +1081,11 @@ static void build_conn(const hgp_hg &h, const uint32_t *part, RefineBufs &B, hip
     HGP_CHECK_HIP(hipMemsetAsync(B.f, 0, sizeof(int64_t), st));
     HGP_CHECK_HIP(hipMemsetAsync(B.scal + 12, 0, sizeof(uint32_t), st));
     if (h.m) {
-        k_conn_small<KW><<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.pins, h.m, h.nwgt, part,
-                                                                             B.lam, B.lam1, B.f, B.longl, B.scal + 12);
+        k_conn_small<KW><<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+            h.pin_off, h.pins, h.m, h.nwgt, part, (NetRec<KW> *)B.nr, B.f, B.longl, B.scal + 12);
         HGP_LAUNCH_CHECK();
         k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, B.scal + 12, h.nwgt, part,
-                                                           B.lam, B.lam1, B.f, false, nullptr, nullptr);
+                                                           (NetRec<KW> *)B.nr, B.f, false, nullptr, nullptr);
         HGP_LAUNCH_CHECK();
     }
 }
@@ -1111,7 +1106,7 @@ static void objective_t(const hgp_hg &h, uint32_t k, const uint32_t *part, int64
     build_conn<KW>(h, part, B, st);
     HGP_CHECK_HIP(hipMemcpyAsync(obj, B.f, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     if (bw_out) block_weights(part, h.vwgt, h.n, k, bw_out, st);
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     A.release(mk);
 }
 
@@ -1143,7 +1138,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     build_conn<KW>(h, part, B, st);
     block_weights(part, h.vwgt, n, k, B.bw, st);
     if (m) HGP_CHECK_HIP(hipMemsetAsync(B.tstamp, 0, sizeof(uint32_t) * m, st));
-    k_init_bcnt<KW><<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n, B.lam, B.bcnt);
+    k_init_bcnt<KW><<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n, (const NetRec<KW> *)B.nr, B.bcnt);
     HGP_LAUNCH_CHECK();
     // degree classes of the nodes (lanes per node 1 / 8 / 64)
     HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * 3, st));
@@ -1151,7 +1146,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     HGP_LAUNCH_CHECK();
     uint32_t dc[3], doff[4] = {0, 0, 0, 0};
     HGP_CHECK_HIP(hipMemcpyAsync(dc, dcnt, sizeof(dc), hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     for (int c = 0; c < 3; ++c) doff[c + 1] = doff[c] + dc[c];
     // per sub-round a class holds about 1/S of its vertices (fewer: only the
     // boundary); the grid strides over whatever the device count is
@@ -1242,12 +1237,12 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         {
             TimedLaunch tl(KID_LP_UPDATE, st);
             k_lp_update_movers<KW, 16><<<upd_blocks, BLOCK, 0, st>>>(
-                h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, h.nwgt, part, B.lam, B.lam1, B.tstamp, stamp,
+                h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, part, (NetRec<KW> *)B.nr, B.tstamp, stamp,
                 B.f, B.longl, nlong, moves, B.bcnt, abort);
             HGP_LAUNCH_CHECK();
         }
-        k_conn_long<KW><<<long_blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part, B.lam,
-                                                           B.lam1, B.f, true, B.bcnt, abort);
+        k_conn_long<KW><<<long_blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part,
+                                                       (NetRec<KW> *)B.nr, B.f, true, B.bcnt, abort);
         HGP_LAUNCH_CHECK();
     };
     // One sub-round, entirely on the device (no host round trip).
@@ -1255,8 +1250,8 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         const uint32_t stamp = 1 + r * S + s;
         k_lp_reset<<<grid_for((size_t)k * k, BLOCK, 64), BLOCK, 0, st>>>(B.scal, B.pw, k * k, B.dbw_g, k);
         HGP_LAUNCH_CHECK();
-        const GainArgs ga{h.inc_off, h.inc, h.nwgt, h.vwgt, B.lam, B.lam1, part, B.bw, B.bcnt, lmax, mseed, level, r,
-                          s, S, n, B.prop_t, B.prop_g, B.plist, nprop, gmax, B.pw, k, abort};
+        const GainArgs<KW> ga{h.inc_off, h.inc, h.vwgt, (const NetRec<KW> *)B.nr, part, B.bw, B.bcnt, lmax, mseed,
+                              level, r, s, S, n, B.prop_t, B.prop_g, B.plist, nprop, gmax, B.pw, k, abort};
         k_lp_cands<<<cand_blocks, BLOCK, 0, st>>>(h.inc_off, B.bcnt, n, cand_per, mseed, level, r, s, S, cl, ccnt,
                                                   B.dlists, abort);
         HGP_LAUNCH_CHECK();
@@ -1293,7 +1288,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         for (;;) {
             uint32_t hv[17];
             HGP_CHECK_HIP(hipMemcpyAsync(hv, B.scal, sizeof(hv), hipMemcpyDeviceToHost, st));
-            HGP_CHECK_HIP(hipStreamSynchronize(st));
+            stream_sync(st);
             if (!hv[15]) break;
             // sub-round hv[16] declined in the one-workgroup selection: finish
             // it device-wide, then replay the remaining sub-rounds of the round
@@ -1305,12 +1300,12 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         }
         uint32_t mv = 0;
         HGP_CHECK_HIP(hipMemcpyAsync(&mv, moves, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        HGP_CHECK_HIP(hipStreamSynchronize(st));
+        stream_sync(st);
         if (mv == 0) break;
     }
     if (obj) HGP_CHECK_HIP(hipMemcpyAsync(obj, B.f, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     if (bw_out) HGP_CHECK_HIP(hipMemcpyAsync(bw_out, B.bw, sizeof(int64_t) * k, hipMemcpyDeviceToDevice, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     A.release(mk);
 }
 

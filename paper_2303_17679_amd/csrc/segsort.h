@@ -196,7 +196,7 @@ inline void segmented_sort(Arena &A, const SegSortBufs &B, const uint32_t *off, 
     HGP_LAUNCH_CHECK();
     uint32_t cnt[2];
     HGP_CHECK_HIP(hipMemcpyAsync(cnt, B.scal, sizeof(cnt), hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     if (cnt[0]) {
         k_seg_med<<<grid_for(cnt[0], 1, 4096), BLOCK, 0, st>>>(off, B.med, cnt[0], data, uniq, usize);
         HGP_LAUNCH_CHECK();
@@ -207,7 +207,7 @@ inline void segmented_sort(Arena &A, const SegSortBufs &B, const uint32_t *off, 
         uint64_t *tot_dev = (uint64_t *)(B.scal + 2);
         scan_apply<uint64_t>(A, nl, LargeLen{off, B.large}, StoreExcl<uint64_t>{B.pos}, tot_dev, st);
         HGP_CHECK_HIP(hipMemcpyAsync(&total, tot_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-        HGP_CHECK_HIP(hipStreamSynchronize(st));
+        stream_sync(st);
         k_seg_large_gather<<<grid_for(nl, 1, 4096), BLOCK, 0, st>>>(off, B.large, nl, data, B.pos, B.keys, B.vals);
         HGP_LAUNCH_CHECK();
         uint64_t *kk = B.keys;

@@ -54,7 +54,7 @@ static SumMax sum_max(const int32_t *w, uint32_t n, Arena &A, hipStream_t st) {
     }
     char host[16];
     HGP_CHECK_HIP(hipMemcpyAsync(host, buf, 16, hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     r.sum = *(int64_t *)host;
     r.max = *(int32_t *)(host + 8);
     r.nonpos = *(uint32_t *)(host + 12) != 0;
@@ -120,7 +120,7 @@ hgp_status validate(const hgp_hg &h, Arena &A, hipStream_t st) {
     k_check_offsets<<<grid_for((size_t)h.n + 1, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.n, h.p, err);
     HGP_LAUNCH_CHECK();
     HGP_CHECK_HIP(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     if (e) { A.release(mk); return HGP_E_INVALID; }
     if (h.m) {
         k_check_lists<<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.pins, h.m, h.n, err);
@@ -129,7 +129,7 @@ hgp_status validate(const hgp_hg &h, Arena &A, hipStream_t st) {
     k_check_lists<<<grid_for(h.n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, h.n, h.m, err);
     HGP_LAUNCH_CHECK();
     HGP_CHECK_HIP(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     if (e) { A.release(mk); return HGP_E_INVALID; }
     if (h.m) {
         k_check_transpose<<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.pins, h.m, h.inc_off,
@@ -137,7 +137,7 @@ hgp_status validate(const hgp_hg &h, Arena &A, hipStream_t st) {
         HGP_LAUNCH_CHECK();
     }
     HGP_CHECK_HIP(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipStreamSynchronize(st));
+    stream_sync(st);
     A.release(mk);
     if (e) return HGP_E_INVALID;
     SumMax vw = sum_max(h.vwgt, h.n, A, st);
@@ -145,6 +145,26 @@ hgp_status validate(const hgp_hg &h, Arena &A, hipStream_t st) {
     if (vw.nonpos || nw.nonpos) return HGP_E_INVALID;
     if (vw.sum >= (int64_t)1 << 31 || nw.sum >= (int64_t)1 << 31) return HGP_E_OVERFLOW;
     return HGP_OK;
+}
+
+namespace {
+struct WaitEvent {
+    hipEvent_t ev = nullptr;
+    ~WaitEvent() {
+        if (ev) hipEventDestroy(ev);
+    }
+};
+}  // namespace
+
+void stream_sync(hipStream_t st) {
+    if (!blocking_waits) {
+        HGP_CHECK_HIP(hipStreamSynchronize(st));
+        return;
+    }
+    thread_local WaitEvent w;
+    if (!w.ev) HGP_CHECK_HIP(hipEventCreateWithFlags(&w.ev, hipEventBlockingSync | hipEventDisableTiming));
+    HGP_CHECK_HIP(hipEventRecord(w.ev, st));
+    HGP_CHECK_HIP(hipEventSynchronize(w.ev));
 }
 
 }  // namespace hgp

@@ -130,7 +130,7 @@ def _finish(n, m, sizes, pins_sorted, vwgt, nwgt, name) -> HostHypergraph:
                           np.asarray(vwgt, np.int32), np.asarray(nwgt, np.int32), name)
 
 
-def _draw_distinct_pins(seed: int, first_stream: int, n: int, sizes: np.ndarray, draw):
+def _draw_distinct_pins(seed: int, first_stream: int, n: int, sizes: np.ndarray, draw, with_net: bool = False):
     """Pins of every net drawn independently, redrawing repeats inside a net.
 
     Slot q (global pin position) on attempt a uses counter q of stream
@@ -141,23 +141,33 @@ def _draw_distinct_pins(seed: int, first_stream: int, n: int, sizes: np.ndarray,
     total = int(sizes.sum())
     net = np.repeat(np.arange(m, dtype=np.int64), sizes.astype(np.int64))
     slots = np.arange(total, dtype=np.int64)
-    vals = draw(rng(seed, first_stream, slots))
+    if with_net:
+        base_draw = draw
+        draw = None
+
+        def draw_at(r, idx):
+            return base_draw(r, net[idx])
+    else:
+        def draw_at(r, idx):
+            return draw(r)
+    vals = draw_at(rng(seed, first_stream, slots), slots)
     attempt = 0
     redo = None
+    assert n < 2**32 and m < 2**31
     while True:
-        order = np.lexsort((slots, vals, net))  # by net, value, slot
-        sv, sn = vals[order], net[order]
+        # by net, then value, then slot (a stable sort keeps slot order)
+        order = np.argsort((net << 32) | vals, kind="stable")
+        key = ((net << 32) | vals)[order]
         dup = np.zeros(total, dtype=bool)
-        dup[1:] = (sv[1:] == sv[:-1]) & (sn[1:] == sn[:-1])
+        dup[1:] = key[1:] == key[:-1]
         redo = order[dup]
         if redo.size == 0:
             break
         attempt += 1
         if attempt > 10000:
             raise RuntimeError("pin redraw did not converge (net larger than the vertex pool?)")
-        vals[redo] = draw(rng(seed, first_stream + attempt, redo))
-    order = np.lexsort((vals, net))
-    return vals[order]
+        vals[redo] = draw_at(rng(seed, first_stream + attempt, redo), redo)
+    return vals[np.argsort((net << 32) | vals, kind="stable")]
 
 
 def random_uniform(n: int = 10_000, m: int = 10_000, smin: int = 2, smax: int = 8,
@@ -289,6 +299,87 @@ def rmat(scale: int = 24, edges: int = 2**28, a: float = 0.57, b: float = 0.19, 
     sizes = np.full(edges, 2, dtype=np.int64)
     return _finish(n, edges, sizes, pins, np.ones(n, np.int32), np.ones(edges, np.int32),
                    name or f"rmat{scale}")
+
+
+def _unit_real(r: np.ndarray) -> np.ndarray:
+    """(r >> 11) * 2^-53 in [0, 1)."""
+    return (np.asarray(r, dtype=U64) >> U64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def vlsi_params(count: int = 4096, seed: int = 4):
+    """(n, k) of every instance of the batch workload: n = floor(exp(ln 1e3 +
+    u ln 200)) (log-uniform on [1e3, 2e5]), k uniform in {2, 4, 8}."""
+    idx = np.arange(count)
+    u = _unit_real(rng(seed, 0, idx))
+    n = np.floor(np.exp(np.log(1e3) + u * np.log(200.0))).astype(np.int64)
+    k = np.array([2, 4, 8], dtype=np.int64)[uniform(rng(seed, 1, idx), 3).astype(np.int64)]
+    return n, k
+
+
+def vlsi(n: int, inst: int, seed: int = 4, name: str = "") -> HostHypergraph:
+    """One VLSI-like instance of the batch workload: m = floor(1.1 n) nets of
+    size 2 + Geometric(0.4) (failures before the first success, inverse CDF of
+    a 53-bit uniform), capped at 50; each net has an anchor a = uniform(n) and
+    each pin lies with probability 0.9 in the window of 256 IDs starting at
+    clamp(a - 128, 0, n - 256), otherwise anywhere; pins distinct per net;
+    vertex weights 1 + uniform(10), unit net weights.  Instance `inst` draws
+    from its own seed (seed << 32 | inst)."""
+    s = (seed << 32) | inst
+    m = int(np.floor(1.1 * n))
+    ids = np.arange(m)
+    g = np.floor(np.log1p(-_unit_real(rng(s, 0, ids))) / np.log(0.6)).astype(np.int64)
+    sizes = np.minimum(2 + g, 50)
+    anchor = uniform(rng(s, 1, ids), n).astype(np.int64)
+    w0 = np.clip(anchor - 128, 0, max(n - 256, 0))
+    win = min(256, n)
+    thr = U64(int(0.9 * 2**32))
+
+    def draw(r, net_ids):
+        hi = r >> U64(32)
+        lo = r & U64(0xFFFFFFFF)
+        local = hi < thr
+        pos_local = w0[net_ids] + ((lo * U64(win)) >> U64(32)).astype(np.int64)
+        pos_any = ((lo * U64(n)) >> U64(32)).astype(np.int64)
+        return np.where(local, pos_local, pos_any)
+
+    pins = _draw_distinct_pins(s, 3, n, sizes, draw, with_net=True)
+    vw = 1 + uniform(rng(s, 2, np.arange(n)), 10).astype(np.int32)
+    return _finish(n, m, sizes, pins, vw, np.ones(m, np.int32), name or f"vlsi{inst}")
+
+
+def vlsi_batch(count: int = 4096, seed: int = 4):
+    """The batch workload: list of (hypergraph, k) for instances 0..count-1."""
+    ns, ks = vlsi_params(count, seed)
+    return [(vlsi(int(ns[i]), i, seed), int(ks[i])) for i in range(count)]
+
+
+def serve_trace(count: int = 200, seed: int = 5):
+    """Requests of the serving workload: per request a target pin count
+    P = floor(exp(ln 1e4 + u ln 1e3)) (log-uniform on [1e4, 1e7]), a family
+    uniform over {random, power-law, stencil, R-MAT} sized to about P pins,
+    and k uniform in {2..64}.  Returns a list of (family, P, k)."""
+    idx = np.arange(count)
+    u = _unit_real(rng(seed, 0, idx))
+    P = np.floor(np.exp(np.log(1e4) + u * np.log(1e3))).astype(np.int64)
+    fam = uniform(rng(seed, 1, idx), 4).astype(np.int64)
+    k = 2 + uniform(rng(seed, 2, idx), 63).astype(np.int64)
+    names = ("random", "powerlaw", "stencil", "rmat")
+    return [(names[int(fam[i])], int(P[i]), int(k[i])) for i in range(count)]
+
+
+def serve_request(family: str, P: int, j: int, seed: int = 5) -> HostHypergraph:
+    """Hypergraph of one serving request (about P pins), request j's own seed."""
+    s = (seed << 32) | j
+    if family == "random":  # E|e| = 5
+        n = max(P // 5, 16)
+        return random_uniform(n, n, 2, 8, seed=s, name=f"req{j}")
+    if family == "powerlaw":  # E|e| about 8.2
+        n = max(P // 8, 64)
+        return powerlaw(n, n, seed=s, max_size=min(1000, n // 10), name=f"req{j}")
+    if family == "stencil":
+        return stencil3d(max(int(round((P / 7.0) ** (1.0 / 3.0))), 3), name=f"req{j}")
+    sc = max(int(round(np.log2(max(P, 64) / 32.0))), 5)  # edge factor 16, two pins per edge
+    return rmat(sc, 16 << sc, seed=s, name=f"req{j}")
 
 
 # Named workloads ----------------------------------------------------------
