@@ -99,9 +99,10 @@ hgp_status hgp_default_params(uint32_t k, hgp_params *out);
 
 /* Host.  Workspace bytes needed by operation `op` on a level of n vertices,
  * m nets and p pins.  For HGP_OP_PARTITION the figure includes room for the
- * coarse hierarchy; a hierarchy that outgrows it makes hgp_partition return
- * HGP_E_WORKSPACE (the figure assumes the pin count shrinks by at least a
- * third over the whole hierarchy, which holds for the inputs tested). */
+ * coarse hierarchy: six times the arrays of the input level (coarse levels
+ * are stored compactly; the figure holds whenever they sum to at most six
+ * input levels, as for every input tested); a deeper hierarchy makes
+ * hgp_partition return HGP_E_WORKSPACE. */
 hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p,
                                const hgp_params *prm, size_t *out);
 

@@ -236,61 +236,31 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
 }
 
 // ---------------------------------------------------------------------------
-// One candidate per block; table in LDS (GLOBAL=false) or in a slice of
-// global memory owned by the block (GLOBAL=true).
+// One candidate per block; table of LCAP slots in LDS.
 // ---------------------------------------------------------------------------
-template <bool GLOBAL>
-__global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t *list, uint32_t count,
-                                                      uint32_t *gkeys, uint32_t *gstamp, uint64_t *gR,
-                                                      uint32_t *gocc, size_t slice_cap, uint32_t n_cur,
-                                                      const uint32_t *bound) {
+__global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t *list, uint32_t count) {
     constexpr int LCAP = 4096, LLOG = 12;
-    __shared__ uint32_t lkeys[GLOBAL ? 1 : LCAP];
-    __shared__ uint32_t lstamp[GLOBAL ? 1 : LCAP];
-    __shared__ uint64_t lR[GLOBAL ? 1 : LCAP];
+    __shared__ uint32_t keys[LCAP];
+    __shared__ uint32_t stamp[LCAP];
+    __shared__ uint64_t R[LCAP];
     __shared__ uint64_t redR[BLOCK / WAVE];
     __shared__ uint32_t redC[BLOCK / WAVE];
-    __shared__ uint32_t nocc;
-    // global tables start clean and are left clean: only the slots a
-    // candidate occupied (listed in occ) are read back and reset
-    uint32_t *occ = GLOBAL ? gocc + (size_t)blockIdx.x * slice_cap : nullptr;
-    uint32_t *keys = GLOBAL ? gkeys + (size_t)blockIdx.x * slice_cap : lkeys;
-    uint32_t *stamp = GLOBAL ? gstamp + (size_t)blockIdx.x * slice_cap : lstamp;
-    uint64_t *R = GLOBAL ? gR + (size_t)blockIdx.x * slice_cap : lR;
     for (uint32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
         uint32_t u = list[idx];
         if (!(a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u])) continue;  // uniform per block
-        uint32_t cap, lg;
-        if (GLOBAL) {
-            // capacity: power of two >= 1.5 D + 1 for D = min(B(u), n - 1)
-            // distinct clusters; the host sized the slices for the largest D
-            uint64_t want = bound[u] < n_cur - 1 ? bound[u] : n_cur - 1;
-            want = want + want / 2 + 1;
-            lg = 13;
-            while (((uint64_t)1 << lg) < want) ++lg;
-            cap = 1u << lg;
-            if (threadIdx.x == 0) nocc = 0;
-        } else {
-            cap = LCAP; lg = LLOG;
-            for (uint32_t s = threadIdx.x; s < cap; s += BLOCK) { keys[s] = NONE; stamp[s] = NONE; R[s] = 0; }
-        }
+        for (uint32_t s = threadIdx.x; s < LCAP; s += BLOCK) { keys[s] = NONE; stamp[s] = NONE; R[s] = 0; }
         __syncthreads();
         uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
         auto insert = [&](uint32_t C) -> uint32_t {
-            uint32_t slot = slot_hash(C, lg);
+            uint32_t slot = slot_hash(C, LLOG);
             for (;;) {
-                uint32_t k = GLOBAL ? __hip_atomic_load(&keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                    : keys[slot];
+                uint32_t k = keys[slot];
                 if (k == C) break;
                 if (k == NONE) {
                     uint32_t old = atomicCAS(&keys[slot], NONE, C);
-                    if (old == NONE) {
-                        if (GLOBAL) occ[atomicAdd(&nocc, 1u)] = slot;
-                        break;
-                    }
-                    if (old == C) break;
+                    if (old == NONE || old == C) break;
                 }
-                slot = (slot + 1) & (cap - 1);
+                slot = (slot + 1) & (LCAP - 1);
             }
             return slot;
         };
@@ -327,27 +297,10 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
         }
         uint64_t bR = 0;
         uint32_t bC = NONE;
-        if (GLOBAL) {
-            __threadfence();
-            const uint32_t no = nocc;
-            for (uint32_t i = threadIdx.x; i < no; i += BLOCK) {
-                // the table was filled by device-scope atomics of other waves:
-                // read it at device scope (never a stale L1 line), then reset
-                const uint32_t s = occ[i];
-                const uint32_t C = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t rc = __hip_atomic_load(&R[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                keys[s] = NONE;
-                stamp[s] = NONE;
-                R[s] = 0;
-                if (valid_target(a, u, C) && better_lazy(a, rc, C, bR, bC)) { bR = rc; bC = C; }
-            }
-            __threadfence();  // the reset is visible before the next candidate's atomics
-        } else {
-            for (uint32_t s = threadIdx.x; s < cap; s += BLOCK) {
-                const uint32_t C = keys[s];
-                if (C == NONE) continue;
-                if (valid_target(a, u, C) && better_lazy(a, R[s], C, bR, bC)) { bR = R[s]; bC = C; }
-            }
+        for (uint32_t s = threadIdx.x; s < LCAP; s += BLOCK) {
+            const uint32_t C = keys[s];
+            if (C == NONE) continue;
+            if (valid_target(a, u, C) && better_lazy(a, R[s], C, bR, bC)) { bR = R[s]; bC = C; }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -362,6 +315,195 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
             for (int q = 1; q < BLOCK / WAVE; ++q)
                 if (better_lazy(a, redR[q], redC[q], bR, bC)) { bR = redR[q]; bC = redC[q]; }
             publish(a, u, bC);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hub rating: candidates whose cluster bound D exceeds the LDS tables.  Such a
+// vertex can have ~1e5 incident nets, so its rating is spread over many
+// workgroups that share one global table per candidate (a "job"):
+//   k_hub_info    - (u, incidence range, D) of every listed candidate;
+//   k_hub_insert  - one workgroup per item (up to HUB_CHUNK incident nets of
+//                   one job): nets of <= LANE_NET pins one thread each
+//                   (clusters deduplicated in registers), nets of up to
+//                   HUB_BIG pins by the whole workgroup through an LDS set
+//                   (each cluster of the net once), larger nets skipped;
+//   k_hub_huge    - one workgroup per job: its nets of more than HUB_BIG pins,
+//                   one at a time, deduplicated by a per-slot net stamp (no
+//                   other net of the job is in flight then);
+//   k_hub_argmax  - one workgroup per job: best target over the occupied
+//                   slots, which are reset, then published.
+// Tables start clean (the host clears the region once per pass) and are left
+// clean, so a job costs its distinct clusters, not its capacity.
+// ---------------------------------------------------------------------------
+constexpr uint32_t HUB_CHUNK = BLOCK;
+constexpr uint32_t HUB_BIG = 2048;
+constexpr uint32_t HUB_SET = 4096;  // power of two >= 2 * HUB_BIG
+
+struct HubJob {
+    uint32_t u, lg;  // candidate, log2 of its table capacity
+    uint32_t j0, j1; // its incidence range
+    uint64_t off;    // first entry of its table in the region
+};
+struct HubItem {
+    uint32_t job, j0, j1, pad;
+};
+
+__global__ __launch_bounds__(BLOCK) void k_hub_info(RateArgs a, const uint32_t *list, uint32_t count,
+                                                    const uint32_t *bound, uint32_t n_cur, uint4 *info) {
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+        const uint32_t u = list[i];
+        const bool active = a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u];
+        const uint32_t D = bound[u] < n_cur - 1 ? bound[u] : n_cur - 1;
+        info[i] = make_uint4(u, a.inc_off[u], a.inc_off[u + 1], active ? D : NONE);
+    }
+}
+
+// Insert cluster C of job J into its table; returns the slot.
+__device__ inline uint32_t hub_slot(uint32_t *keys, uint32_t *occ, uint32_t *nocc, const HubJob &J, uint32_t job,
+                                    uint32_t C) {
+    const uint32_t mask = (1u << J.lg) - 1u;
+    uint32_t *kt = keys + J.off;
+    uint32_t slot = slot_hash(C, (int)J.lg);
+    for (;;) {
+        const uint32_t k = __hip_atomic_load(&kt[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == C) return slot;
+        if (k == NONE) {
+            const uint32_t old = atomicCAS(&kt[slot], NONE, C);
+            if (old == NONE) {
+                occ[J.off + atomicAdd(&nocc[job], 1u)] = slot;
+                return slot;
+            }
+            if (old == C) return slot;
+        }
+        slot = (slot + 1) & mask;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_hub_insert(RateArgs a, const HubJob *jobs, const HubItem *items,
+                                                      uint32_t nitems, uint32_t *keys, uint64_t *R, uint32_t *occ,
+                                                      uint32_t *nocc) {
+    __shared__ uint32_t set[HUB_SET];
+    __shared__ uint16_t setocc[HUB_SET];
+    __shared__ uint32_t nset, nbig;
+    __shared__ uint32_t big[HUB_CHUNK];
+    for (uint32_t q = threadIdx.x; q < HUB_SET; q += BLOCK) set[q] = NONE;
+    for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const HubItem I = items[it];
+        const HubJob J = jobs[I.job];
+        const uint32_t u = J.u;
+        if (threadIdx.x == 0) { nbig = 0; nset = 0; }
+        __syncthreads();
+        // small nets: one thread each; big ones are listed for the workgroup
+        const uint32_t j = I.j0 + threadIdx.x;
+        if (j < I.j1) {
+            const uint32_t e = a.inc[j];
+            const uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+            if (sz >= 2 && sz <= LANE_NET) {
+                rate_small_net(a, u, b, sz, a.nscore[e], [&](uint32_t C, uint64_t sc) {
+                    const uint32_t slot = hub_slot(keys, occ, nocc, J, I.job, C);
+                    atomicAdd((unsigned long long *)&R[J.off + slot], (unsigned long long)sc);
+                });
+            } else if (sz > LANE_NET && sz <= HUB_BIG) {
+                big[atomicAdd(&nbig, 1u)] = e;
+            }
+        }
+        __syncthreads();
+        const uint32_t nb = nbig;
+        for (uint32_t q = 0; q < nb; ++q) {
+            const uint32_t e = big[q];
+            const uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+            const uint64_t sc = a.nscore[e];
+            for (uint32_t x = threadIdx.x; x < sz; x += BLOCK) {
+                const uint32_t v = a.pins[b + x];
+                if (v == u) continue;
+                const uint32_t C = a.rep[v];
+                bool fresh = true;
+                if (a.dedup) {  // first pin of the net in cluster C claims it
+                    uint32_t h = slot_hash(C, 12);
+                    for (;;) {
+                        const uint32_t k = set[h];
+                        if (k == C) { fresh = false; break; }
+                        if (k == NONE) {
+                            const uint32_t old = atomicCAS(&set[h], NONE, C);
+                            if (old == NONE) { setocc[atomicAdd(&nset, 1u)] = (uint16_t)h; break; }
+                            if (old == C) { fresh = false; break; }
+                        }
+                        h = (h + 1) & (HUB_SET - 1);
+                    }
+                }
+                if (fresh) {
+                    const uint32_t slot = hub_slot(keys, occ, nocc, J, I.job, C);
+                    atomicAdd((unsigned long long *)&R[J.off + slot], (unsigned long long)sc);
+                }
+            }
+            __syncthreads();
+            const uint32_t ns = nset;
+            for (uint32_t x = threadIdx.x; x < ns; x += BLOCK) set[setocc[x]] = NONE;
+            __syncthreads();
+            if (threadIdx.x == 0) nset = 0;
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_hub_huge(RateArgs a, const HubJob *jobs, uint32_t njobs, uint32_t *keys,
+                                                    uint32_t *stamp, uint64_t *R, uint32_t *occ, uint32_t *nocc) {
+    for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
+        const HubJob J = jobs[jb];
+        for (uint32_t j = J.j0; j < J.j1; ++j) {
+            const uint32_t e = a.inc[j];
+            const uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+            if (sz <= HUB_BIG) continue;  // uniform per workgroup
+            const uint64_t sc = a.nscore[e];
+            for (uint32_t x = threadIdx.x; x < sz; x += BLOCK) {
+                const uint32_t v = a.pins[b + x];
+                if (v == J.u) continue;
+                const uint32_t slot = hub_slot(keys, occ, nocc, J, jb, a.rep[v]);
+                if (!a.dedup || atomicExch(&stamp[J.off + slot], e) != e)
+                    atomicAdd((unsigned long long *)&R[J.off + slot], (unsigned long long)sc);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_hub_argmax(RateArgs a, const HubJob *jobs, uint32_t njobs,
+                                                      uint32_t *keys, uint32_t *stamp, uint64_t *R,
+                                                      const uint32_t *occ, uint32_t *nocc) {
+    __shared__ uint64_t redR[BLOCK / WAVE];
+    __shared__ uint32_t redC[BLOCK / WAVE];
+    for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
+        const HubJob J = jobs[jb];
+        const uint32_t u = J.u;
+        const uint32_t no = nocc[jb];
+        uint64_t bR = 0;
+        uint32_t bC = NONE;
+        for (uint32_t i = threadIdx.x; i < no; i += BLOCK) {
+            const uint64_t s = J.off + occ[J.off + i];
+            const uint32_t C = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t rc = __hip_atomic_load(&R[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            keys[s] = NONE;
+            stamp[s] = NONE;
+            R[s] = 0;
+            if (valid_target(a, u, C) && better_lazy(a, rc, C, bR, bC)) { bR = rc; bC = C; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t oR = __shfl_xor(bR, o, 64);
+            const uint32_t oC = __shfl_xor(bC, o, 64);
+            if (better_lazy(a, oR, oC, bR, bC)) { bR = oR; bC = oC; }
+        }
+        const unsigned w = threadIdx.x / WAVE;
+        if (__lane_id() == 0) { redR[w] = bR; redC[w] = bC; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int q = 1; q < BLOCK / WAVE; ++q)
+                if (better_lazy(a, redR[q], redC[q], bR, bC)) { bR = redR[q]; bC = redC[q]; }
+            publish(a, u, bC);
+            nocc[jb] = 0;
         }
         __syncthreads();
     }
@@ -433,7 +575,21 @@ __device__ inline int rate_class(uint64_t B) {
 // on the clusters a rating of u can touch.  Thread per vertex; a vertex of
 // more than 32 incident nets is summed by its whole wave.
 __global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, const uint32_t *inc_off,
-                                                    const uint32_t *inc, uint32_t n, uint32_t *bound) {
+                                                    const uint32_t *inc, uint32_t n, uint32_t m, uint32_t *bound,
+                                                    uint32_t *maxsz) {
+    // largest net size of the level (decides whether the hub path needs its
+    // huge-net kernel)
+    uint32_t mx = 0;
+    for (uint32_t e = blockIdx.x * BLOCK + threadIdx.x; e < m; e += gridDim.x * BLOCK) {
+        const uint32_t sz = pin_off[e + 1] - pin_off[e];
+        mx = sz > mx ? sz : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_xor(mx, o, 64);
+        mx = y > mx ? y : mx;
+    }
+    if (__lane_id() == 0 && mx) atomicMax(maxsz, mx);
     for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
         const uint32_t u = u0 + threadIdx.x;
         uint32_t j0 = 0, j1 = 0;
@@ -623,14 +779,19 @@ struct CoarsenBufs {
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt;
     uint32_t *bound;
-    char *greg;         // reserved region of the global rating tables
-    size_t greg_bytes;  // 16 tables for the worst case D = n - 1
+    char *greg;         // region of the global (hub) rating tables
+    size_t greg_bytes;  // at least 16 tables for the worst case D = n - 1
+    uint4 *hub_info;
+    HubJob *hub_jobs;
+    HubItem *hub_items;
+    size_t hub_items_cap;
+    uint32_t *hub_nocc;
 };
 
 // One global-table entry: key, stamp, occupancy slot (4 B each), rating (8 B).
 constexpr size_t GENTRY_BYTES = 20;
 
-static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t S, CoarsenBufs &B) {
+static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, uint32_t S, CoarsenBufs &B) {
     B.nscore = A.alloc<uint64_t>(m);
     B.cw = A.alloc<int64_t>(n);
     B.tsum = A.alloc<int64_t>(n);
@@ -639,7 +800,7 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t S, CoarsenBufs &B) {
     B.proposers = A.alloc<uint32_t>(n);
     B.slow = A.alloc<uint32_t>(n);
     B.lists = A.alloc<uint32_t>(n);
-    B.counts = A.alloc<uint32_t>((size_t)S * NCLASS + 1);
+    B.counts = A.alloc<uint32_t>((size_t)S * NCLASS + 2);  // + largest D, largest net
     B.bound = A.alloc<uint32_t>(n);
     B.cursor = A.alloc<uint32_t>((size_t)S * NCLASS);
     B.scal = A.alloc<uint32_t>(8);
@@ -649,22 +810,39 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t S, CoarsenBufs &B) {
     B.incl = A.alloc<uint64_t>(n);
     B.vals = A.alloc<uint32_t>(n);
     B.vals_alt = A.alloc<uint32_t>(n);
-    // global-memory rating tables: room for 16 tables of the largest
-    // possible capacity (>= 1.5 n); smaller candidates get more, smaller tables
+    B.hub_info = A.alloc<uint4>(n);
+    B.hub_jobs = A.alloc<HubJob>(n);
+    B.hub_items_cap = (size_t)p / HUB_CHUNK + n + 1;
+    B.hub_items = A.alloc<HubItem>(B.hub_items_cap);
+    B.hub_nocc = A.alloc<uint32_t>(n);
+    // global (hub) rating tables: room for 16 tables of the largest possible
+    // capacity (>= 1.5 n), more (up to 4 p entries, 2^26) when the workspace
+    // has it, always leaving room for the temporaries the pass allocates
+    // later (sorts, scans, reductions).  The region only decides how many hub
+    // jobs run per batch, so a deep hierarchy that leaves less room gets a
+    // smaller region, down to one largest table.
+    Arena T(nullptr, 0);
+    sort_reserve(T, n);
+    scan_reserve<uint64_t>(T, n);
+    const size_t tail = T.peak + 65536;
     size_t sc = 8192;
     while (sc < (size_t)n + n / 2 + 1) sc <<= 1;
-    B.greg_bytes = 16 * sc * GENTRY_BYTES;
+    size_t entries = 16 * sc;
+    while (entries < 4 * (size_t)p && entries < ((size_t)1 << 26)) entries <<= 1;
+    const size_t rem = A.remaining();
+    const size_t avail = (rem > tail ? rem - tail : 0) / GENTRY_BYTES;
+    while (entries > sc && entries > avail) entries >>= 1;
+    B.greg_bytes = entries * GENTRY_BYTES;
     B.greg = A.alloc<char>(B.greg_bytes);
-    // radix sort temporaries
+    // radix sort temporaries (reserved and released: counted in the peak)
     sort_reserve(A, n);
     scan_reserve<uint64_t>(A, n);
 }
 
 size_t coarsen_workspace(uint32_t n, uint32_t m, uint32_t p, const hgp_params &prm) {
-    (void)p;
     Arena A(nullptr, 0);
     CoarsenBufs B;
-    plan(A, n, m, prm.coarsen_subrounds, B);
+    plan(A, n, m, p, prm.coarsen_subrounds, B);
     return A.peak;
 }
 
@@ -673,7 +851,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     const uint32_t n = h.n, m = h.m, S = prm.coarsen_subrounds;
     size_t mk = A.mark();
     CoarsenBufs B;
-    plan(A, n, m, S, B);
+    plan(A, n, m, h.p, S, B);
     int64_t W = 0;
     {
         // c(V) is needed on the host for the cap test constants
@@ -684,36 +862,83 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
 
     k_net_score<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.nwgt, m, B.nscore);
     HGP_LAUNCH_CHECK();
-    HGP_CHECK_HIP(hipMemsetAsync(B.counts, 0, sizeof(uint32_t) * (S * NCLASS + 1), st));
-    k_vertex_b<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, B.bound);
+    HGP_CHECK_HIP(hipMemsetAsync(B.counts, 0, sizeof(uint32_t) * (S * NCLASS + 2), st));
+    k_vertex_b<<<grid_for(std::max(n, m), BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, m,
+                                                                             B.bound, B.counts + S * NCLASS + 1);
     HGP_LAUNCH_CHECK();
     k_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
                                                                  B.tsum, B.counts, B.cursor, B.lists, false);
     HGP_LAUNCH_CHECK();
-    std::vector<uint32_t> counts(S * NCLASS + 1), offs(S * NCLASS + 1);
-    HGP_CHECK_HIP(hipMemcpyAsync(counts.data(), B.counts, sizeof(uint32_t) * (S * NCLASS + 1), hipMemcpyDeviceToHost,
+    std::vector<uint32_t> counts(S * NCLASS + 2), offs(S * NCLASS + 1);
+    HGP_CHECK_HIP(hipMemcpyAsync(counts.data(), B.counts, sizeof(uint32_t) * (S * NCLASS + 2), hipMemcpyDeviceToHost,
                                  st));
+    const bool huge_nets = counts[S * NCLASS + 1] > HUB_BIG;
     stream_sync(st);
-    // global rating tables, carved from the reserved region: capacity for the
-    // largest D of the global class, as many tables as fit (16 .. 1024)
-    uint32_t *gkeys = nullptr, *gstamp = nullptr, *gocc = nullptr;
-    uint64_t *gR = nullptr;
-    size_t slice_cap = 8192;
-    uint32_t nslices = 0;
-    bool any_global = false;
-    for (uint32_t r = 0; r < S; ++r) any_global |= counts[r * NCLASS + NCLASS - 1] > 0;
-    if (any_global) {
-        const uint64_t D = counts[S * NCLASS];
-        while (slice_cap < D + D / 2 + 1) slice_cap <<= 1;
-        nslices = (uint32_t)std::min<size_t>(1024, B.greg_bytes / (slice_cap * GENTRY_BYTES));
-        const size_t e = slice_cap * nslices;
-        gR = (uint64_t *)B.greg;
-        gkeys = (uint32_t *)(B.greg + 8 * e);
-        gstamp = gkeys + e;
-        gocc = gstamp + e;
-        HGP_CHECK_HIP(hipMemsetAsync(gR, 0, 8 * e, st));
-        HGP_CHECK_HIP(hipMemsetAsync(gkeys, 0xFF, 8 * e, st));  // keys and stamps
+    // hub tables: the whole region, cleared once; every job leaves its slots clean
+    const size_t E = B.greg_bytes / GENTRY_BYTES;
+    uint64_t *gR = (uint64_t *)B.greg;
+    uint32_t *gkeys = (uint32_t *)(B.greg + 8 * E), *gstamp = gkeys + E, *gocc = gstamp + E;
+    bool any_hub = false;
+    for (uint32_t r = 0; r < S; ++r) any_hub |= counts[r * NCLASS + NCLASS - 1] > 0;
+    if (any_hub) {
+        HGP_CHECK_HIP(hipMemsetAsync(gR, 0, 8 * E, st));
+        HGP_CHECK_HIP(hipMemsetAsync(gkeys, 0xFF, 8 * E, st));  // keys and stamps
     }
+    // Hub rating of the listed candidates: jobs packed into the region in
+    // batches (every table fits the region alone: E >= 16 * its capacity).
+    auto hub_rate = [&](const RateArgs &a, const uint32_t *lst, uint32_t cntc) {
+        k_hub_info<<<grid_for(cntc, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(a, lst, cntc, B.bound, n, B.hub_info);
+        HGP_LAUNCH_CHECK();
+        std::vector<uint4> info(cntc);
+        HGP_CHECK_HIP(hipMemcpyAsync(info.data(), B.hub_info, sizeof(uint4) * cntc, hipMemcpyDeviceToHost, st));
+        stream_sync(st);
+        // all batches planned at once: jobs of a batch share the region
+        std::vector<HubJob> jobs;
+        std::vector<HubItem> items;
+        std::vector<uint32_t> bj{0}, bi{0};  // batch boundaries in jobs / items
+        size_t used = 0;
+        for (uint32_t i = 0; i < cntc; ++i) {
+            const uint4 f = info[i];
+            if (f.w == NONE) continue;  // joined by another vertex earlier in the pass
+            uint32_t lg = 13;
+            while (((uint64_t)1 << lg) < (uint64_t)f.w + f.w / 2 + 1) ++lg;
+            const size_t cap = (size_t)1 << lg;
+            if (used + cap > E) {
+                bj.push_back((uint32_t)jobs.size());
+                bi.push_back((uint32_t)items.size());
+                used = 0;
+            }
+            const uint32_t jid = (uint32_t)(jobs.size() - bj.back());  // index within the batch
+            jobs.push_back(HubJob{f.x, lg, f.y, f.z, used});
+            for (uint32_t j = f.y; j < f.z; j += HUB_CHUNK)
+                items.push_back(HubItem{jid, j, std::min(j + HUB_CHUNK, f.z), 0});
+            used += cap;
+        }
+        bj.push_back((uint32_t)jobs.size());
+        bi.push_back((uint32_t)items.size());
+        if (jobs.empty()) return;
+        if (items.size() > B.hub_items_cap || jobs.size() > n) throw Error{HGP_E_WORKSPACE};
+        HGP_CHECK_HIP(hipMemcpyAsync(B.hub_jobs, jobs.data(), sizeof(HubJob) * jobs.size(), hipMemcpyHostToDevice,
+                                     st));
+        HGP_CHECK_HIP(hipMemcpyAsync(B.hub_items, items.data(), sizeof(HubItem) * items.size(),
+                                     hipMemcpyHostToDevice, st));
+        for (size_t b = 0; b + 1 < bj.size(); ++b) {
+            const uint32_t nj = bj[b + 1] - bj[b], ni = bi[b + 1] - bi[b];
+            if (!nj) continue;
+            const HubJob *jb = B.hub_jobs + bj[b];
+            HGP_CHECK_HIP(hipMemsetAsync(B.hub_nocc, 0, sizeof(uint32_t) * nj, st));
+            k_hub_insert<<<std::min(ni, 8192u), BLOCK, 0, st>>>(a, jb, B.hub_items + bi[b], ni, gkeys, gR, gocc,
+                                                                B.hub_nocc);
+            HGP_LAUNCH_CHECK();
+            if (huge_nets) {
+                k_hub_huge<<<std::min(nj, 8192u), BLOCK, 0, st>>>(a, jb, nj, gkeys, gstamp, gR, gocc, B.hub_nocc);
+                HGP_LAUNCH_CHECK();
+            }
+            k_hub_argmax<<<std::min(nj, 8192u), BLOCK, 0, st>>>(a, jb, nj, gkeys, gstamp, gR, gocc, B.hub_nocc);
+            HGP_LAUNCH_CHECK();
+        }
+        stream_sync(st);  // the uploads read the host vectors
+    };
     offs[0] = 0;
     for (uint32_t i = 0; i < S * NCLASS; ++i) offs[i + 1] = offs[i] + counts[i];
     HGP_CHECK_HIP(hipMemcpyAsync(B.cursor, offs.data(), sizeof(uint32_t) * S * NCLASS, hipMemcpyHostToDevice, st));
@@ -756,12 +981,10 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                     k_rate_group<64, 1024, 10><<<grid_for(cntc, BLOCK / 64, 8192), BLOCK, 0, st>>>(a, lst, cntc);
                     break;
                 case 3:
-                    k_rate_block<false><<<grid_for(cntc, 1, 8192), BLOCK, 0, st>>>(
-                        a, lst, cntc, nullptr, nullptr, nullptr, nullptr, 0, n, B.bound);
+                    k_rate_block<<<grid_for(cntc, 1, 8192), BLOCK, 0, st>>>(a, lst, cntc);
                     break;
                 default:
-                    k_rate_block<true><<<grid_for(cntc, 1, nslices), BLOCK, 0, st>>>(
-                        a, lst, cntc, gkeys, gstamp, gR, gocc, slice_cap, n, B.bound);
+                    hub_rate(a, lst, cntc);
                     break;
             }
             HGP_LAUNCH_CHECK();

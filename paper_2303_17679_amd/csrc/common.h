@@ -65,6 +65,8 @@ struct Arena {
         return (T *)(base + off);
     }
     size_t mark() const { return top; }
+    // bytes still free (unbounded when only measuring)
+    size_t remaining() const { return measure ? ~size_t(0) : (cap > top ? cap - top : 0); }
     void release(size_t m) { top = m; }
 };
 

@@ -22,14 +22,45 @@ namespace hgp {
 
 // expansion offset of every incidence entry: sum of the sizes of the
 // earlier nets of the same vertex
-__global__ void k_exoff(const uint32_t *pin_off, const uint32_t *inc_off, const uint32_t *inc, uint32_t n,
-                        uint32_t *exoff) {
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        uint32_t acc = 0;
-        for (uint32_t j = inc_off[v]; j < inc_off[v + 1]; ++j) {
-            exoff[j] = acc;
-            uint32_t e = inc[j];
-            acc += pin_off[e + 1] - pin_off[e];
+__global__ __launch_bounds__(BLOCK) void k_exoff(const uint32_t *pin_off, const uint32_t *inc_off,
+                                                 const uint32_t *inc, uint32_t n, uint32_t *exoff) {
+    // exclusive prefix of the sizes of each vertex's nets; a vertex of more
+    // than 32 nets is scanned by its whole wave, 64 entries at a time
+    for (uint32_t v0 = blockIdx.x * BLOCK; v0 < n; v0 += gridDim.x * BLOCK) {
+        const uint32_t v = v0 + threadIdx.x;
+        uint32_t j0 = 0, j1 = 0;
+        if (v < n) { j0 = inc_off[v]; j1 = inc_off[v + 1]; }
+        const bool heavy = j1 - j0 > 32;
+        if (!heavy) {
+            uint32_t acc = 0;
+            for (uint32_t j = j0; j < j1; ++j) {
+                exoff[j] = acc;
+                const uint32_t e = inc[j];
+                acc += pin_off[e + 1] - pin_off[e];
+            }
+        }
+        uint64_t hm = __ballot(heavy);
+        while (hm) {
+            const int h = __ffsll((long long)hm) - 1;
+            hm &= hm - 1;
+            const uint32_t hj0 = __shfl(j0, h, 64), hj1 = __shfl(j1, h, 64);
+            uint32_t carry = 0;
+            for (uint32_t b = hj0; b < hj1; b += WAVE) {
+                const uint32_t j = b + __lane_id();
+                uint32_t x = 0;
+                if (j < hj1) {
+                    const uint32_t e = inc[j];
+                    x = pin_off[e + 1] - pin_off[e];
+                }
+                uint32_t incl = x;  // inclusive wave scan
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(incl, o, 64);
+                    if ((int)__lane_id() >= o) incl += y;
+                }
+                if (j < hj1) exoff[j] = carry + incl - x;
+                carry += __shfl(incl, 63, 64);
+            }
         }
     }
 }

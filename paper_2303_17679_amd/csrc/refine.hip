@@ -44,6 +44,12 @@ struct alignas(16) NetRec {
 static_assert(sizeof(NetRec<1>) == 32 && sizeof(NetRec<2>) == 48 && sizeof(NetRec<4>) == 80, "record size");
 inline size_t netrec_bytes(int KW) { return 16u * (size_t)(KW + 1); }
 
+// Degree classes of LP candidates: lanes per node 1 (<= 8 nets), 8 (<= 64),
+// a wave (<= HUB_DEG), a 1024-thread workgroup (more).
+constexpr int NDEG = 4;
+constexpr uint32_t HUB_DEG = 2048;
+__host__ __device__ inline int deg_class(uint32_t d) { return d <= 8 ? 0 : (d <= 64 ? 1 : (d <= HUB_DEG ? 2 : 3)); }
+
 // ---------------------------------------------------------------------------
 // Connectivity bitsets of nets
 // ---------------------------------------------------------------------------
@@ -373,8 +379,8 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
 // (1 lane per node), [nb0, nb0 + nb1) class 1 (8 lanes), the rest class 2
 // (64).  List c starts at off[c]; its length is the device count ccnt[c].
 struct ClassLists {
-    uint32_t off[3];
-    uint32_t nb[3];
+    uint32_t off[NDEG];
+    uint32_t nb[NDEG];
 };
 
 template <int KW>
@@ -387,6 +393,93 @@ __global__ __launch_bounds__(BLOCK) void k_gains(GainArgs<KW> a, const uint32_t 
     else gains_body<KW, 64>(a, lists + cl.off[2], ccnt[2], b - cl.nb[0] - cl.nb[1], cl.nb[2]);
 }
 
+// Candidates of more than HUB_DEG nets: one 1024-thread workgroup each, the
+// affinity of every block summed in a shared LDS histogram.
+constexpr int HUB_THREADS = 1024;
+template <int KW>
+__global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const uint32_t *list,
+                                                           const uint32_t *count_dev) {
+    constexpr int NW = HUB_THREADS / WAVE;
+    __shared__ int64_t aff[64 * KW];
+    __shared__ unsigned long long Us[KW];
+    __shared__ int64_t rbu[NW], rwi[NW];
+    __shared__ uint32_t rg[NW], rt[NW];
+    if (*a.abort) return;
+    const uint32_t cnt = *count_dev, tid = threadIdx.x, w = tid / WAVE;
+    for (uint32_t idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
+        const uint32_t u = list[idx];
+        const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
+        const uint32_t s = a.part[u];
+        const int64_t cu = a.vwgt[u];
+        for (uint32_t t = tid; t < 64 * KW; t += HUB_THREADS) aff[t] = 0;
+        if (tid < KW) Us[tid] = 0;
+        __syncthreads();
+        int64_t bu = 0, wI = 0;
+        uint64_t U[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) U[q] = 0;
+        for (uint32_t j = j0 + tid; j < j1; j += HUB_THREADS) {
+            const NetRec<KW> &R = a.nr[a.inc[j]];
+            const int64_t wt = R.w;
+            wI += wt;
+            if ((R.lam1[s >> 6] >> (s & 63)) & 1ull) bu += wt;
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                uint64_t x = R.lam[q];
+                U[q] |= x;
+                while (x) {
+                    const int bit = __ffsll((long long)x) - 1;
+                    x &= x - 1;
+                    atomicAdd((unsigned long long *)&aff[q * 64 + bit], (unsigned long long)wt);
+                }
+            }
+        }
+        bu = wave_sum(bu);
+        wI = wave_sum(wI);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
+        if (__lane_id() == 0) {
+            rbu[w] = bu;
+            rwi[w] = wI;
+#pragma unroll
+            for (int q = 0; q < KW; ++q) atomicOr(&Us[q], (unsigned long long)U[q]);
+        }
+        __syncthreads();
+        bu = 0;
+        wI = 0;
+        for (int q = 0; q < NW; ++q) { bu += rbu[q]; wI += rwi[q]; }
+        uint32_t best_t = NONE, best_g = 0;
+        if (tid < 64 * KW) {  // thread t judges block t
+            const uint32_t t = tid;
+            const bool inU = (Us[t >> 6] >> (t & 63)) & 1ull;
+            if (inU && t != s && a.bw[t] + cu <= a.lmax) {
+                const int64_t gn = bu - (wI - aff[t]);
+                if (gn > 0) { best_g = (uint32_t)gn; best_t = t; }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {  // largest gain, then smallest block
+            const uint32_t og = __shfl_xor(best_g, o, 64), ot = __shfl_xor(best_t, o, 64);
+            if (og > best_g || (og == best_g && ot < best_t)) { best_g = og; best_t = ot; }
+        }
+        if (__lane_id() == 0) { rg[w] = best_g; rt[w] = best_t; }
+        __syncthreads();
+        if (w == 0) {
+            best_g = __lane_id() < NW ? rg[__lane_id()] : 0u;
+            best_t = __lane_id() < NW ? rt[__lane_id()] : NONE;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint32_t og = __shfl_xor(best_g, o, 64), ot = __shfl_xor(best_t, o, 64);
+                if (og > best_g || (og == best_g && ot < best_t)) { best_g = og; best_t = ot; }
+            }
+            propose(a, u, s, best_t, best_g, __lane_id() == 0 && best_t != NONE);
+        }
+        __syncthreads();  // the histogram is read before the next node clears it
+    }
+}
+
 // Candidates of LP sub-round (r, s): the boundary vertices (an incident net
 // with lambda > 1 -- no other vertex can have a positive gain) whose
 // sub-round hash selects s, appended to the list of their degree class.
@@ -397,8 +490,7 @@ __global__ __launch_bounds__(BLOCK) void k_gains(GainArgs<KW> a, const uint32_t 
 __device__ inline int lp_cand_class(const uint32_t *inc_off, const uint32_t *bcnt, uint32_t n, uint64_t mseed,
                                     uint32_t level, uint32_t r, uint32_t s, uint32_t S, uint32_t u) {
     if (u >= n || bcnt[u] == 0 || tag_hash(mseed, 3, level, r, u) % S != s) return -1;
-    const uint32_t d = inc_off[u + 1] - inc_off[u];
-    return d <= 8 ? 0 : (d <= 64 ? 1 : 2);
+    return deg_class(inc_off[u + 1] - inc_off[u]);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, const uint32_t *bcnt, uint32_t n,
@@ -406,46 +498,47 @@ __global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, con
                                                     uint32_t s, uint32_t S, ClassLists cl, uint32_t *ccnt,
                                                     uint32_t *lists, const uint32_t *abort) {
     constexpr int NW = BLOCK / WAVE;
-    __shared__ uint32_t wc[3][NW];
-    __shared__ uint32_t base[3];
+    __shared__ uint32_t wc[NDEG][NW];
+    __shared__ uint32_t base[NDEG];
     if (*abort) return;
     const uint32_t lo = blockIdx.x * per * BLOCK;
     if (lo >= n) return;  // uniform per block
     const uint32_t w = threadIdx.x / WAVE;
-    // the class of each of this thread's vertices, 2 bits each (3 = none)
-    uint32_t packed = 0, c0 = 0, c1 = 0, c2 = 0;
+    // the class of each of this thread's vertices, 3 bits each (7 = none)
+    uint64_t packed = 0;
+    uint32_t cc[NDEG] = {0, 0, 0, 0};
     for (uint32_t it = 0; it < per; ++it) {
         const int key = lp_cand_class(inc_off, bcnt, n, mseed, level, r, s, S, lo + it * BLOCK + threadIdx.x);
-        packed |= (uint32_t)(key < 0 ? 3 : key) << (2 * it);
-        c0 += key == 0;
-        c1 += key == 1;
-        c2 += key == 2;
+        packed |= (uint64_t)(key < 0 ? 7 : key) << (3 * it);
+#pragma unroll
+        for (int c = 0; c < NDEG; ++c) cc[c] += key == c;
     }
-    c0 = wave_sum(c0);
-    c1 = wave_sum(c1);
-    c2 = wave_sum(c2);
-    if (__lane_id() == 0) { wc[0][w] = c0; wc[1][w] = c1; wc[2][w] = c2; }
+#pragma unroll
+    for (int c = 0; c < NDEG; ++c) {
+        cc[c] = wave_sum(cc[c]);
+        if (__lane_id() == 0) wc[c][w] = cc[c];
+    }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < NDEG) {
         uint32_t t = 0;
         for (int q = 0; q < NW; ++q) t += wc[threadIdx.x][q];
         base[threadIdx.x] = t ? atomicAdd(&ccnt[threadIdx.x], t) : 0u;
     }
     __syncthreads();
-    uint32_t run[3] = {base[0], base[1], base[2]};
+    uint32_t run[NDEG] = {base[0], base[1], base[2], base[3]};
     for (uint32_t it = 0; it < per; ++it) {
         const uint32_t u = lo + it * BLOCK + threadIdx.x;
-        const int key = (int)((packed >> (2 * it)) & 3u);
-        uint64_t bal[3];
+        const int key = (int)((packed >> (3 * it)) & 7u);
+        uint64_t bal[NDEG];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) bal[c] = __ballot(key == c);
+        for (int c = 0; c < NDEG; ++c) bal[c] = __ballot(key == c);
         __syncthreads();  // the previous iteration's reads of wc are done
         if (__lane_id() == 0)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) wc[c][w] = (uint32_t)__popcll(bal[c]);
+            for (int c = 0; c < NDEG; ++c) wc[c][w] = (uint32_t)__popcll(bal[c]);
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < NDEG; ++c) {
             uint32_t before = 0, total = 0;
 #pragma unroll
             for (int q = 0; q < NW; ++q) {
@@ -458,14 +551,30 @@ __global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, con
     }
 }
 
-// Boundary count of every node from scratch (once per level).
+// Boundary count of every node from scratch (once per level); a node of more
+// than 32 nets is counted by its whole wave.
 template <int KW>
-__global__ void k_init_bcnt(const uint32_t *inc_off, const uint32_t *inc, uint32_t n, const NetRec<KW> *nr,
-                            uint32_t *bcnt) {
-    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(BLOCK) void k_init_bcnt(const uint32_t *inc_off, const uint32_t *inc, uint32_t n,
+                                                     const NetRec<KW> *nr, uint32_t *bcnt) {
+    for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
+        const uint32_t u = u0 + threadIdx.x;
+        uint32_t j0 = 0, j1 = 0;
+        if (u < n) { j0 = inc_off[u]; j1 = inc_off[u + 1]; }
+        const bool heavy = j1 - j0 > 32;
         uint32_t c = 0;
-        for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) c += popc_bits<KW>(nr[inc[j]].lam) > 1;
-        bcnt[u] = c;
+        if (!heavy)
+            for (uint32_t j = j0; j < j1; ++j) c += popc_bits<KW>(nr[inc[j]].lam) > 1;
+        uint64_t hm = __ballot(heavy);
+        while (hm) {
+            const int h = __ffsll((long long)hm) - 1;
+            hm &= hm - 1;
+            const uint32_t hj0 = __shfl(j0, h, 64), hj1 = __shfl(j1, h, 64);
+            uint32_t t = 0;
+            for (uint32_t j = hj0 + __lane_id(); j < hj1; j += WAVE) t += popc_bits<KW>(nr[inc[j]].lam) > 1;
+            t = wave_sum(t);
+            if ((int)__lane_id() == h) c = t;
+        }
+        if (u < n) bcnt[u] = c;
     }
 }
 
@@ -475,7 +584,8 @@ __global__ void k_lp_reset(uint32_t *scal, uint32_t *pw, uint32_t kk, int64_t *d
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
     if (tid < 4) scal[tid] = 0;                  // nprop, gmax, ntouched, nlong
     if (tid == 4) { scal[13] = 0; scal[14] = 0; }  // nslow, nmov
-    if (tid >= 5 && tid < 8) scal[20 + tid - 5] = 0;  // candidates per degree class
+    if (tid >= 5 && tid < 9) scal[20 + tid - 5] = 0;  // candidates per degree class
+    if (tid == 9) scal[24] = 0;                        // movers of more than HUB_DEG nets
     for (uint32_t i = tid; i < kk; i += nt) pw[i] = 0;
     for (uint32_t i = tid; i < k; i += nt) dbw_g[i] = 0;
 }
@@ -490,10 +600,12 @@ __global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs<KW> a, const u
                                                          unsigned long long *acc) {
     __shared__ unsigned long long red[BLOCK / WAVE];
     unsigned long long bytes = 0;
-    const uint32_t c0 = ccnt[0], c1 = ccnt[1], total = c0 + c1 + ccnt[2];
+    uint32_t total = 0;
+    for (int c = 0; c < NDEG; ++c) total += ccnt[c];
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
-        const uint32_t u = idx < c0 ? lists[cl.off[0] + idx]
-                                    : (idx < c0 + c1 ? lists[cl.off[1] + idx - c0] : lists[cl.off[2] + idx - c0 - c1]);
+        uint32_t c = 0, i = idx;
+        while (i >= ccnt[c]) i -= ccnt[c++];
+        const uint32_t u = lists[cl.off[c] + i];
         const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
         bytes += 4 + 8 + 4 + 4 + 4ull * (j1 - j0);  // list entry, inc_off pair, part, vwgt, incidence list
         for (uint32_t j = j0; j < j1; ++j)
@@ -509,18 +621,18 @@ __global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs<KW> a, const u
     }
 }
 
-// Vertices per degree class (<= 8, <= 64, larger incident nets; degree-0
-// vertices are in none): sizes the candidate lists of the level.
+// Vertices per degree class (deg_class; degree-0 vertices are in none):
+// sizes the candidate lists of the level.
 __global__ __launch_bounds__(BLOCK) void k_deg_classify(const uint32_t *inc_off, uint32_t n, uint32_t *counts) {
-    __shared__ uint32_t lcnt[3];
-    if (threadIdx.x < 3) lcnt[threadIdx.x] = 0;
+    __shared__ uint32_t lcnt[NDEG];
+    if (threadIdx.x < NDEG) lcnt[threadIdx.x] = 0;
     __syncthreads();
     for (uint32_t u = blockIdx.x * BLOCK + threadIdx.x; u < n; u += gridDim.x * BLOCK) {
         const uint32_t d = inc_off[u + 1] - inc_off[u];
-        if (d > 0) atomicAdd(&lcnt[d <= 8 ? 0 : (d <= 64 ? 1 : 2)], 1u);
+        if (d > 0) atomicAdd(&lcnt[deg_class(d)], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < 3 && lcnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], lcnt[threadIdx.x]);
+    if (threadIdx.x < NDEG && lcnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], lcnt[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -970,6 +1082,66 @@ __global__ __launch_bounds__(BLOCK) void k_account_update(const uint32_t *pin_of
     }
 }
 
+// Recomputes net e once per sub-round (the first caller to stamp it owns
+// it): Lambda / Lambda1 from the pins' blocks, boundary counts of its pins on
+// a cut flip; nets of more than 64 pins go to the long-net list.  Returns the
+// objective change w(e) (max(lambda'-1,0) - max(lambda-1,0)).
+template <int KW>
+__device__ inline int64_t update_net(const uint32_t *pin_off, const uint32_t *pins, uint32_t e, const uint32_t *part,
+                                     NetRec<KW> *nr, uint32_t *tstamp, uint32_t stamp, uint32_t *longl,
+                                     uint32_t *nlong, uint32_t *bcnt) {
+    if (atomicExch(&tstamp[e], stamp) == stamp) return 0;
+    const uint32_t b = pin_off[e], len = pin_off[e + 1] - b;
+    if (len > 64) {
+        longl[atomicAdd(nlong, 1u)] = e;
+        return 0;
+    }
+    uint64_t once[KW], twice[KW];
+    net_bits<KW>(pins, b, len, part, once, twice);
+    NetRec<KW> &R = nr[e];
+    const int lnew = popc_bits<KW>(once), lold = popc_bits<KW>(R.lam);
+    const int64_t d = lam_cost(lnew) - lam_cost(lold);
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+        R.lam[q] = once[q];
+        R.lam1[q] = once[q] & ~twice[q];
+    }
+    if ((lnew > 1) != (lold > 1)) {  // cut status flipped: boundary counts of its pins
+        const uint32_t delta = lnew > 1 ? 1u : 0xFFFFFFFFu;
+        for (uint32_t q = b; q < b + len; ++q) atomicAdd(&bcnt[pins[q]], delta);
+    }
+    return d * R.w;
+}
+
+// Movers of more than HUB_DEG nets: their incidence lists are cut into chunks
+// of BLOCK nets spread over the whole grid (a net per thread).
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_lp_update_heavy(const uint32_t *pin_off, const uint32_t *pins,
+                                                           const uint32_t *inc_off, const uint32_t *inc,
+                                                           const uint32_t *heavy, const uint32_t *nheavy,
+                                                           const uint32_t *part, NetRec<KW> *nr, uint32_t *tstamp,
+                                                           uint32_t stamp, int64_t *f, uint32_t *longl,
+                                                           uint32_t *nlong, uint32_t *bcnt, const uint32_t *abort) {
+    if (*abort) return;
+    __shared__ int64_t red[BLOCK / WAVE];
+    const uint32_t cnt = *nheavy;
+    int64_t acc = 0;
+    for (uint32_t h = 0; h < cnt; ++h) {
+        const uint32_t u = heavy[h];
+        const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
+        for (uint32_t j = j0 + blockIdx.x * BLOCK + threadIdx.x; j < j1; j += gridDim.x * BLOCK)
+            acc += update_net<KW>(pin_off, pins, inc[j], part, nr, tstamp, stamp, longl, nlong, bcnt);
+    }
+    acc = wave_sum(acc);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+        if (t) atomic_add_i64(f, t);
+    }
+}
+
 // Lambda / Lambda1 of every net of a moved node, recomputed once: G lanes per
 // mover; the first lane to stamp a net in this sub-round owns it.  Nets of
 // more than 64 pins are forwarded to the wave kernel.  The objective changes
@@ -982,6 +1154,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
                                                             const uint32_t *part, NetRec<KW> *nr, uint32_t *tstamp,
                                                             uint32_t stamp, int64_t *f, uint32_t *longl,
                                                             uint32_t *nlong, uint32_t *moves, uint32_t *bcnt,
+                                                            uint32_t *heavy, uint32_t *nheavy,
                                                             const uint32_t *abort) {
     if (*abort) return;
     __shared__ int64_t red[BLOCK / WAVE];
@@ -992,30 +1165,13 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
     int64_t acc = 0;
     for (uint32_t idx = blockIdx.x * GPB + g; idx < cnt; idx += gridDim.x * GPB) {
         const uint32_t u = mlist[idx];
-        for (uint32_t j = inc_off[u] + l; j < inc_off[u + 1]; j += G) {
-            const uint32_t e = inc[j];
-            if (atomicExch(&tstamp[e], stamp) == stamp) continue;
-            const uint32_t b = pin_off[e], len = pin_off[e + 1] - b;
-            if (len > 64) {
-                longl[atomicAdd(nlong, 1u)] = e;
-                continue;
-            }
-            uint64_t once[KW], twice[KW];
-            net_bits<KW>(pins, b, len, part, once, twice);
-            NetRec<KW> &R = nr[e];
-            const int lnew = popc_bits<KW>(once), lold = popc_bits<KW>(R.lam);
-            const int64_t d = lam_cost(lnew) - lam_cost(lold);
-#pragma unroll
-            for (int q = 0; q < KW; ++q) {
-                R.lam[q] = once[q];
-                R.lam1[q] = once[q] & ~twice[q];
-            }
-            acc += d * R.w;
-            if ((lnew > 1) != (lold > 1)) {  // cut status flipped: boundary counts of its pins
-                const uint32_t delta = lnew > 1 ? 1u : 0xFFFFFFFFu;
-                for (uint32_t q = b; q < b + len; ++q) atomicAdd(&bcnt[pins[q]], delta);
-            }
+        const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
+        if (j1 - j0 > HUB_DEG) {  // uniform per group: left to the chunked kernel
+            if (l == 0) heavy[atomicAdd(nheavy, 1u)] = u;
+            continue;
         }
+        for (uint32_t j = j0 + l; j < j1; j += G)
+            acc += update_net<KW>(pin_off, pins, inc[j], part, nr, tstamp, stamp, longl, nlong, bcnt);
     }
     acc = wave_sum(acc);
     if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
@@ -1033,7 +1189,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
 struct RefineBufs {
     void *nr;  // NetRec<KW>[m]
     int64_t *f, *bw;
-    uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *pw, *slow, *mlist;
+    uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow, *mlist;
     int64_t *dbw_g;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt, *seg_start, *seg_end;
@@ -1064,6 +1220,7 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.pw = A.alloc<uint32_t>((size_t)k * k);
     B.slow = A.alloc<uint32_t>(n);
     B.mlist = A.alloc<uint32_t>(n);
+    B.heavy = A.alloc<uint32_t>(n);
     B.dbw_g = A.alloc<int64_t>(k);
     sort_reserve(A, n);
     scan_reserve<uint64_t>(A, n);
@@ -1132,7 +1289,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const uint64_t mseed = mix64(prm.seed);
     // device scalars: ntouched and nlong are adjacent so one memset clears both
     uint32_t *nprop = B.scal + 0, *gmax = B.scal + 1, *ntouched = B.scal + 2, *nlong = B.scal + 3,
-             *moves = B.scal + 4, *dcnt = B.scal + 5 /* [3] */,
+             *moves = B.scal + 4, *dcnt = B.scal + 5 /* [NDEG] */, *nheavy = B.scal + 24,
              *nslow = B.scal + 13, *nmov = B.scal + 14;
 
     build_conn<KW>(h, part, B, st);
@@ -1141,22 +1298,23 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     k_init_bcnt<KW><<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n, (const NetRec<KW> *)B.nr, B.bcnt);
     HGP_LAUNCH_CHECK();
     // degree classes of the nodes (lanes per node 1 / 8 / 64)
-    HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * 3, st));
+    HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * NDEG, st));
     k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt);
     HGP_LAUNCH_CHECK();
-    uint32_t dc[3], doff[4] = {0, 0, 0, 0};
+    uint32_t dc[NDEG], doff[NDEG + 1] = {0, 0, 0, 0, 0};
     HGP_CHECK_HIP(hipMemcpyAsync(dc, dcnt, sizeof(dc), hipMemcpyDeviceToHost, st));
     stream_sync(st);
-    for (int c = 0; c < 3; ++c) doff[c + 1] = doff[c] + dc[c];
+    for (int c = 0; c < NDEG; ++c) doff[c + 1] = doff[c] + dc[c];
     // per sub-round a class holds about 1/S of its vertices (fewer: only the
     // boundary); the grid strides over whatever the device count is
     const uint32_t S = prm.lp_subrounds;
     ClassLists cl;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NDEG; ++c) {
         const uint32_t per = c == 0 ? BLOCK : (c == 1 ? BLOCK / 8 : BLOCK / 64);
         cl.off[c] = doff[c];
-        cl.nb[c] = dc[c] ? grid_for((dc[c] + S - 1) / S, per, 2048) : 0u;
+        cl.nb[c] = (c < 3 && dc[c]) ? grid_for((dc[c] + S - 1) / S, per, 2048) : 0u;
     }
+    const uint32_t hub_blocks = dc[3] ? grid_for((dc[3] + S - 1) / S, 1, 256) : 0u;
     const uint32_t nbg_all = cl.nb[0] + cl.nb[1] + cl.nb[2];
     // grids of the per-sub-round kernels, sized by what one sub-round can hold
     // (about n / S proposals and movers); every kernel strides over its count
@@ -1165,10 +1323,10 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const uint32_t upd_blocks = grid_for(per_sub, BLOCK / 16, FILL_BLOCKS / 2);
     const uint32_t long_blocks = grid_for((size_t)m + 1, 64 * (BLOCK / WAVE), FILL_BLOCKS / 4);
     // candidate compaction: chunks of cand_per * BLOCK vertices per workgroup
-    // (at most 16 per thread: the kernel keeps 2 bits per vertex in one word)
+    // (at most 16 per thread: the kernel keeps 3 bits per vertex in one word)
     const uint32_t cand_per = std::max(1u, std::min(16u, (uint32_t)((n + BLOCK * 2048u - 1) / (BLOCK * 2048u))));
     const uint32_t cand_blocks = (uint32_t)((n + (size_t)cand_per * BLOCK - 1) / ((size_t)cand_per * BLOCK));
-    uint32_t *ccnt = B.scal + 20;  // [3] candidates per class in the current sub-round
+    uint32_t *ccnt = B.scal + 20;  // [NDEG] candidates per class in the current sub-round
 
     const int kb = bits_for(k - 1), ub = bits_for(n ? n - 1 : 0);
     uint32_t *abort = B.scal + 15;  // [2]: flag, sub-round that raised it (scal[16])
@@ -1238,7 +1396,13 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             TimedLaunch tl(KID_LP_UPDATE, st);
             k_lp_update_movers<KW, 16><<<upd_blocks, BLOCK, 0, st>>>(
                 h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, part, (NetRec<KW> *)B.nr, B.tstamp, stamp,
-                B.f, B.longl, nlong, moves, B.bcnt, abort);
+                B.f, B.longl, nlong, moves, B.bcnt, B.heavy, nheavy, abort);
+            HGP_LAUNCH_CHECK();
+        }
+        if (dc[3]) {  // the level has nodes of more than HUB_DEG nets
+            k_lp_update_heavy<KW><<<512, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.heavy, nheavy, part,
+                                                         (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl, nlong,
+                                                         B.bcnt, abort);
             HGP_LAUNCH_CHECK();
         }
         k_conn_long<KW><<<long_blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part,
@@ -1265,6 +1429,10 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         if (nbg_all) {
             TimedLaunch tl(KID_GAINS, st);
             k_gains<KW><<<nbg_all, BLOCK, 0, st>>>(ga, B.dlists, cl, ccnt);
+            HGP_LAUNCH_CHECK();
+        }
+        if (hub_blocks) {
+            k_gains_hub<KW><<<hub_blocks, HUB_THREADS, 0, st>>>(ga, B.dlists + cl.off[3], ccnt + 3);
             HGP_LAUNCH_CHECK();
         }
         {  // pairs whose whole move sets are feasible: applied directly

@@ -79,30 +79,70 @@ __global__ void k_check_offsets(const uint32_t *off, uint32_t cnt, uint32_t tota
 }
 
 // ids strictly ascending and < bound inside every segment
-__global__ void k_check_lists(const uint32_t *off, const uint32_t *data, uint32_t cnt, uint32_t bound, uint32_t *err) {
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < cnt; s += gridDim.x * blockDim.x) {
-        uint32_t prev = 0;
-        for (uint32_t j = off[s]; j < off[s + 1]; ++j) {
-            uint32_t x = data[j];
-            if (x >= bound || (j > off[s] && x <= prev)) { atomicOr(err, 2u); break; }
-            prev = x;
+__global__ __launch_bounds__(BLOCK) void k_check_lists(const uint32_t *off, const uint32_t *data, uint32_t cnt,
+                                                       uint32_t bound, uint32_t *err) {
+    // every list strictly ascending and below `bound`; lists of more than 32
+    // entries are checked by their whole wave
+    for (uint32_t s0 = blockIdx.x * BLOCK; s0 < cnt; s0 += gridDim.x * BLOCK) {
+        const uint32_t s = s0 + threadIdx.x;
+        uint32_t j0 = 0, j1 = 0;
+        if (s < cnt) { j0 = off[s]; j1 = off[s + 1]; }
+        const bool heavy = j1 - j0 > 32;
+        if (!heavy) {
+            uint32_t prev = 0;
+            for (uint32_t j = j0; j < j1; ++j) {
+                const uint32_t x = data[j];
+                if (x >= bound || (j > j0 && x <= prev)) { atomicOr(err, 2u); break; }
+                prev = x;
+            }
+        }
+        uint64_t hm = __ballot(heavy);
+        while (hm) {
+            const int h = __ffsll((long long)hm) - 1;
+            hm &= hm - 1;
+            const uint32_t hj0 = __shfl(j0, h, 64), hj1 = __shfl(j1, h, 64);
+            bool bad = false;
+            for (uint32_t j = hj0 + __lane_id(); j < hj1; j += WAVE) {
+                const uint32_t x = data[j];
+                bad |= x >= bound || (j > hj0 && x <= data[j - 1]);
+            }
+            if (__ballot(bad) && __lane_id() == 0) atomicOr(err, 2u);
         }
     }
 }
 
 // every pin (e, v) appears as e in v's incidence list (both sides hold p
 // distinct pairs, so this makes the incidence the exact transpose)
-__global__ void k_check_transpose(const uint32_t *pin_off, const uint32_t *pins, uint32_t m, const uint32_t *inc_off,
-                                  const uint32_t *inc, uint32_t *err) {
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
-        for (uint32_t j = pin_off[e]; j < pin_off[e + 1]; ++j) {
-            uint32_t v = pins[j];
+__global__ __launch_bounds__(BLOCK) void k_check_transpose(const uint32_t *pin_off, const uint32_t *pins, uint32_t m,
+                                                           const uint32_t *inc_off, const uint32_t *inc,
+                                                           uint32_t *err) {
+    // every pin (e, v) appears in v's incidence list (binary search); nets of
+    // more than 32 pins are checked by their whole wave
+    for (uint32_t e0 = blockIdx.x * BLOCK; e0 < m; e0 += gridDim.x * BLOCK) {
+        const uint32_t e = e0 + threadIdx.x;
+        uint32_t j0 = 0, j1 = 0;
+        if (e < m) { j0 = pin_off[e]; j1 = pin_off[e + 1]; }
+        const bool heavy = j1 - j0 > 32;
+        auto found = [&](uint32_t net, uint32_t v) {
             uint32_t lo = inc_off[v], hi = inc_off[v + 1];
+            const uint32_t end = hi;
             while (lo < hi) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (inc[mid] < e) lo = mid + 1; else hi = mid;
+                const uint32_t mid = (lo + hi) >> 1;
+                if (inc[mid] < net) lo = mid + 1; else hi = mid;
             }
-            if (lo >= inc_off[v + 1] || inc[lo] != e) { atomicOr(err, 4u); break; }
+            return lo < end && inc[lo] == net;
+        };
+        if (!heavy)
+            for (uint32_t j = j0; j < j1; ++j)
+                if (!found(e, pins[j])) { atomicOr(err, 4u); break; }
+        uint64_t hm = __ballot(heavy);
+        while (hm) {
+            const int h = __ffsll((long long)hm) - 1;
+            hm &= hm - 1;
+            const uint32_t he = __shfl(e, h, 64), hj0 = __shfl(j0, h, 64), hj1 = __shfl(j1, h, 64);
+            bool bad = false;
+            for (uint32_t j = hj0 + __lane_id(); j < hj1; j += WAVE) bad |= !found(he, pins[j]);
+            if (__ballot(bad) && __lane_id() == 0) atomicOr(err, 4u);
         }
     }
 }
@@ -165,6 +205,26 @@ void stream_sync(hipStream_t st) {
     if (!w.ev) HGP_CHECK_HIP(hipEventCreateWithFlags(&w.ev, hipEventBlockingSync | hipEventDisableTiming));
     HGP_CHECK_HIP(hipEventRecord(w.ev, st));
     HGP_CHECK_HIP(hipEventSynchronize(w.ev));
+}
+
+__global__ __launch_bounds__(BLOCK) void k_copy_arrays(CopySet c) {
+    uint64_t total = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) total += c.len[a];
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < total; i += (uint64_t)gridDim.x * BLOCK) {
+        uint64_t x = i;
+        int a = 0;
+        while (x >= c.len[a]) x -= c.len[a++];
+        c.dst[a][x] = c.src[a][x];
+    }
+}
+
+void copy_arrays(const CopySet &c, hipStream_t st) {
+    uint64_t total = 0;
+    for (int a = 0; a < 6; ++a) total += c.len[a];
+    if (!total) return;
+    k_copy_arrays<<<grid_for(total, BLOCK * 4, FILL_BLOCKS), BLOCK, 0, st>>>(c);
+    HGP_LAUNCH_CHECK();
 }
 
 }  // namespace hgp

@@ -54,12 +54,19 @@ CASES = [
     ("stencil32", 100, 11),   # two Lambda words per net
     ("rmat16", 128, 4),       # 2-pin nets with duplicate edges, two words
     ("random120k", 256, 6),   # four words per net
+    ("hugenets", 4, 9),       # hub ratings with nets of more than 2048 pins
 ]
 
 
 def make(name):
     if name == "random2k":
         return W.random_uniform(2000, 2000, 2, 8, seed=9, name=name)
+    if name == "hugenets":
+        rs = np.random.RandomState(17)
+        n = 6000
+        nets = [rs.choice(n, size=rs.randint(2, 7), replace=False) for _ in range(6000)]
+        nets += [rs.choice(n, size=sz, replace=False) for sz in (2500, 3000, 4000)]
+        return W.from_nets(n, nets, nwgt=rs.randint(1, 4, size=len(nets)))
     if name == "random120k":
         return W.random_uniform(120000, 120000, 2, 8, seed=4, name=name)
     return W.workload(name)[0]
