@@ -484,34 +484,48 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
 // with lambda > 1 -- no other vertex can have a positive gain) whose
 // sub-round hash selects s, appended to the list of their degree class.
 // Class c's list starts at off[c] and can hold every vertex of the class.
-// Each workgroup compacts one contiguous chunk of `per` * BLOCK vertices:
-// it counts first, reserves its ranges with one atomic per class, then
-// writes its candidates in ascending vertex order.
-__device__ inline int lp_cand_class(const uint32_t *inc_off, const uint32_t *bcnt, uint32_t n, uint64_t mseed,
-                                    uint32_t level, uint32_t r, uint32_t s, uint32_t S, uint32_t u) {
-    if (u >= n || bcnt[u] == 0 || tag_hash(mseed, 3, level, r, u) % S != s) return -1;
-    return deg_class(inc_off[u + 1] - inc_off[u]);
-}
-
+// Each workgroup compacts one contiguous chunk of CAND_PER * BLOCK vertices
+// (1 on small levels, 8 on large ones): it loads all its boundary counts at
+// once, counts per class, reserves its ranges with one atomic per class,
+// then writes its candidates in ascending vertex order.
+template <uint32_t CAND_PER>
 __global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, const uint32_t *bcnt, uint32_t n,
-                                                    uint32_t per, uint64_t mseed, uint32_t level, uint32_t r,
-                                                    uint32_t s, uint32_t S, ClassLists cl, uint32_t *ccnt,
-                                                    uint32_t *lists, const uint32_t *abort) {
+                                                    uint64_t mseed, uint32_t level, uint32_t r, uint32_t s,
+                                                    uint32_t S, ClassLists cl, uint32_t *ccnt, uint32_t *lists,
+                                                    const uint32_t *abort) {
     constexpr int NW = BLOCK / WAVE;
     __shared__ uint32_t wc[NDEG][NW];
     __shared__ uint32_t base[NDEG];
     if (*abort) return;
-    const uint32_t lo = blockIdx.x * per * BLOCK;
+    const uint32_t lo = blockIdx.x * CAND_PER * BLOCK;
     if (lo >= n) return;  // uniform per block
     const uint32_t w = threadIdx.x / WAVE;
-    // the class of each of this thread's vertices, 3 bits each (7 = none)
-    uint64_t packed = 0;
-    uint32_t cc[NDEG] = {0, 0, 0, 0};
-    for (uint32_t it = 0; it < per; ++it) {
-        const int key = lp_cand_class(inc_off, bcnt, n, mseed, level, r, s, S, lo + it * BLOCK + threadIdx.x);
-        packed |= (uint64_t)(key < 0 ? 7 : key) << (3 * it);
+    uint32_t bc[CAND_PER];
 #pragma unroll
-        for (int c = 0; c < NDEG; ++c) cc[c] += key == c;
+    for (uint32_t it = 0; it < CAND_PER; ++it) {
+        const uint32_t u = lo + it * BLOCK + threadIdx.x;
+        bc[it] = u < n ? bcnt[u] : 0u;
+    }
+    bool sel[CAND_PER];
+#pragma unroll
+    for (uint32_t it = 0; it < CAND_PER; ++it) {
+        const uint32_t u = lo + it * BLOCK + threadIdx.x;
+        sel[it] = bc[it] > 0 && tag_hash(mseed, 3, level, r, u) % S == s;
+    }
+    uint32_t d0[CAND_PER], d1[CAND_PER];
+#pragma unroll
+    for (uint32_t it = 0; it < CAND_PER; ++it) {
+        const uint32_t u = lo + it * BLOCK + threadIdx.x;
+        d0[it] = sel[it] ? inc_off[u] : 0u;
+        d1[it] = sel[it] ? inc_off[u + 1] : 0u;
+    }
+    int key[CAND_PER];
+    uint32_t cc[NDEG] = {0, 0, 0, 0};
+#pragma unroll
+    for (uint32_t it = 0; it < CAND_PER; ++it) {
+        key[it] = sel[it] ? deg_class(d1[it] - d0[it]) : -1;
+#pragma unroll
+        for (int c = 0; c < NDEG; ++c) cc[c] += key[it] == c;
     }
 #pragma unroll
     for (int c = 0; c < NDEG; ++c) {
@@ -526,12 +540,12 @@ __global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, con
     }
     __syncthreads();
     uint32_t run[NDEG] = {base[0], base[1], base[2], base[3]};
-    for (uint32_t it = 0; it < per; ++it) {
+#pragma unroll
+    for (uint32_t it = 0; it < CAND_PER; ++it) {
         const uint32_t u = lo + it * BLOCK + threadIdx.x;
-        const int key = (int)((packed >> (3 * it)) & 7u);
         uint64_t bal[NDEG];
 #pragma unroll
-        for (int c = 0; c < NDEG; ++c) bal[c] = __ballot(key == c);
+        for (int c = 0; c < NDEG; ++c) bal[c] = __ballot(key[it] == c);
         __syncthreads();  // the previous iteration's reads of wc are done
         if (__lane_id() == 0)
 #pragma unroll
@@ -545,7 +559,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, con
                 before += (q < (int)w) ? wc[c][q] : 0u;
                 total += wc[c][q];
             }
-            if (key == c) lists[cl.off[c] + run[c] + before + (uint32_t)__popcll(bal[c] & lanemask_lt())] = u;
+            if (key[it] == c) lists[cl.off[c] + run[c] + before + (uint32_t)__popcll(bal[c] & lanemask_lt())] = u;
             run[c] += total;
         }
     }
@@ -1301,9 +1315,11 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * NDEG, st));
     k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt);
     HGP_LAUNCH_CHECK();
-    uint32_t dc[NDEG], doff[NDEG + 1] = {0, 0, 0, 0, 0};
-    HGP_CHECK_HIP(hipMemcpyAsync(dc, dcnt, sizeof(dc), hipMemcpyDeviceToHost, st));
+    uint32_t dc[NDEG], doff[NDEG + 1] = {0, 0, 0, 0, 0}, hs[16];
+    HGP_CHECK_HIP(hipMemcpyAsync(hs, B.scal, sizeof(hs), hipMemcpyDeviceToHost, st));
     stream_sync(st);
+    for (int c = 0; c < NDEG; ++c) dc[c] = hs[5 + c];
+    const bool long_nets = hs[12] > 0;  // nets of more than 64 pins exist on this level
     for (int c = 0; c < NDEG; ++c) doff[c + 1] = doff[c] + dc[c];
     // per sub-round a class holds about 1/S of its vertices (fewer: only the
     // boundary); the grid strides over whatever the device count is
@@ -1320,11 +1336,13 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     // (about n / S proposals and movers); every kernel strides over its count
     const size_t per_sub = (size_t)n / S + 1;
     const uint32_t fast_blocks = grid_for(per_sub, BLOCK, FILL_BLOCKS / 4);
-    const uint32_t upd_blocks = grid_for(per_sub, BLOCK / 16, FILL_BLOCKS / 2);
+    // lanes per mover by the level's average degree (a lane per incident net)
+    const uint64_t avg_deg = n ? ((uint64_t)h.p + n - 1) / n : 1;
+    const uint32_t upd_g = avg_deg <= 8 ? 8u : (avg_deg <= 24 ? 16u : 64u);
+    const uint32_t upd_blocks = grid_for(per_sub, BLOCK / upd_g, FILL_BLOCKS / 2);
     const uint32_t long_blocks = grid_for((size_t)m + 1, 64 * (BLOCK / WAVE), FILL_BLOCKS / 4);
     // candidate compaction: chunks of cand_per * BLOCK vertices per workgroup
-    // (at most 16 per thread: the kernel keeps 3 bits per vertex in one word)
-    const uint32_t cand_per = std::max(1u, std::min(16u, (uint32_t)((n + BLOCK * 2048u - 1) / (BLOCK * 2048u))));
+    const uint32_t cand_per = n > 2048u * BLOCK ? 8u : 1u;
     const uint32_t cand_blocks = (uint32_t)((n + (size_t)cand_per * BLOCK - 1) / ((size_t)cand_per * BLOCK));
     uint32_t *ccnt = B.scal + 20;  // [NDEG] candidates per class in the current sub-round
 
@@ -1394,9 +1412,14 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         }
         {
             TimedLaunch tl(KID_LP_UPDATE, st);
-            k_lp_update_movers<KW, 16><<<upd_blocks, BLOCK, 0, st>>>(
-                h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, part, (NetRec<KW> *)B.nr, B.tstamp, stamp,
-                B.f, B.longl, nlong, moves, B.bcnt, B.heavy, nheavy, abort);
+            auto launch = [&](auto kern, uint32_t blocks) {
+                kern<<<blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, part,
+                                               (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl, nlong, moves,
+                                               B.bcnt, B.heavy, nheavy, abort);
+            };
+            if (upd_g == 8) launch(k_lp_update_movers<KW, 8>, upd_blocks);
+            else if (upd_g == 16) launch(k_lp_update_movers<KW, 16>, upd_blocks);
+            else launch(k_lp_update_movers<KW, 64>, upd_blocks);
             HGP_LAUNCH_CHECK();
         }
         if (dc[3]) {  // the level has nodes of more than HUB_DEG nets
@@ -1405,9 +1428,11 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
                                                          B.bcnt, abort);
             HGP_LAUNCH_CHECK();
         }
-        k_conn_long<KW><<<long_blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part,
-                                                       (NetRec<KW> *)B.nr, B.f, true, B.bcnt, abort);
-        HGP_LAUNCH_CHECK();
+        if (long_nets) {
+            k_conn_long<KW><<<long_blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part,
+                                                           (NetRec<KW> *)B.nr, B.f, true, B.bcnt, abort);
+            HGP_LAUNCH_CHECK();
+        }
     };
     // One sub-round, entirely on the device (no host round trip).
     auto subround = [&](uint32_t r, uint32_t s) {
@@ -1416,8 +1441,12 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         HGP_LAUNCH_CHECK();
         const GainArgs<KW> ga{h.inc_off, h.inc, h.vwgt, (const NetRec<KW> *)B.nr, part, B.bw, B.bcnt, lmax, mseed,
                               level, r, s, S, n, B.prop_t, B.prop_g, B.plist, nprop, gmax, B.pw, k, abort};
-        k_lp_cands<<<cand_blocks, BLOCK, 0, st>>>(h.inc_off, B.bcnt, n, cand_per, mseed, level, r, s, S, cl, ccnt,
-                                                  B.dlists, abort);
+        if (cand_per == 8)
+            k_lp_cands<8><<<cand_blocks, BLOCK, 0, st>>>(h.inc_off, B.bcnt, n, mseed, level, r, s, S, cl, ccnt,
+                                                         B.dlists, abort);
+        else
+            k_lp_cands<1><<<cand_blocks, BLOCK, 0, st>>>(h.inc_off, B.bcnt, n, mseed, level, r, s, S, cl, ccnt,
+                                                         B.dlists, abort);
         HGP_LAUNCH_CHECK();
         if (accounting(KID_GAINS)) {
             Timing &T = timing();
