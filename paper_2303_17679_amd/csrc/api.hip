@@ -195,6 +195,7 @@ hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
                          uint32_t *levels_out, Arena &A, hipStream_t st) {
     hgp_status v = validate(*h0, A, st);
     if (v != HGP_OK) return v;
+    const int64_t W = total_weight(h0->vwgt, h0->n, A, st);  // c(V): the same on every level
     struct Level {
         hgp_hg h;
         uint32_t *cid;  // map to the next coarser level
@@ -222,7 +223,7 @@ hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
         size_t mk_rep = A.mark();
         uint32_t *rep = A.alloc<uint32_t>(cur.n);
         uint32_t cnt = 0;
-        coarsen_pass(cur, *prm, (uint32_t)(L.size() - 1), rep, nullptr, &cnt, A, st);
+        coarsen_pass(cur, *prm, (uint32_t)(L.size() - 1), rep, nullptr, &cnt, A, st, W);
         if ((uint64_t)100 * (cur.n - cnt) <= (uint64_t)cur.n) {
             A.release(mk);
             break;
@@ -257,13 +258,13 @@ hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
     // initial partition and LP on the coarsest level
     hgp_hg cs = L.back().h;
     uint32_t *cpart = (nl == 0) ? part : A.alloc<uint32_t>(cs.n);
-    initial_partition(cs, prm->k, cpart, A, st);
-    refine_lp(cs, *prm, nl, cpart, objective, nullptr, A, st);
+    initial_partition(cs, prm->k, cpart, A, st, W);
+    refine_lp(cs, *prm, nl, cpart, objective, nullptr, A, st, W);
     for (int l = (int)nl - 1; l >= 0; --l) {
         hgp_hg fh = L[l].h;
         uint32_t *fpart = (l == 0) ? part : A.alloc<uint32_t>(fh.n);
         project(fh.n, L[l].cid, cpart, fpart, st);
-        refine_lp(fh, *prm, (uint32_t)l, fpart, objective, nullptr, A, st);
+        refine_lp(fh, *prm, (uint32_t)l, fpart, objective, nullptr, A, st, W);
         cpart = fpart;
     }
     stream_sync(st);

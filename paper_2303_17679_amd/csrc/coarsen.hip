@@ -45,7 +45,16 @@ struct RateArgs {
     uint32_t level, r, S;
     int64_t cap_mult, W;
     bool dedup;  // false in the first sub-round: every cluster is a singleton
+    const uint32_t *ncl;  // clusters after the previous sub-round
+    uint32_t n_cur;       // vertices of the level
 };
+
+// The pass stops once the clustering has shrunk the level below n / 2.5
+// (checked after every sub-round): the kernels of the remaining sub-rounds
+// see it on the device and do nothing.
+__device__ inline bool pass_cut(const uint32_t *ncl, uint32_t n) {
+    return (uint64_t)5 * *ncl < (uint64_t)2 * n;
+}
 
 // Larger than any cluster weight (< 2^31) while cap_mult * (c(u) + TINFO_BAD)
 // stays far from overflow (cap_mult = limit_factor * k < 2^26).
@@ -54,7 +63,9 @@ constexpr int64_t TINFO_BAD = (int64_t)1 << 34;
 // tinfo[C]: cw[C] if C may be joined in sub-round r, TINFO_BAD if C is itself
 // a candidate singleton of the sub-round (no chains within a sub-round).
 __global__ void k_target_info(const uint32_t *rep, const int64_t *cw, const int32_t *vwgt, uint32_t n,
-                              uint64_t mseed, uint32_t level, uint32_t S, uint32_t r, int64_t *tinfo) {
+                              uint64_t mseed, uint32_t level, uint32_t S, uint32_t r, int64_t *tinfo,
+                              const uint32_t *ncl) {
+    if (pass_cut(ncl, n)) return;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         int64_t c = cw[v];
         bool cand = rep[v] == v && c == (int64_t)vwgt[v] && tag_hash(mseed, 1, level, 0, v) % S == r;
@@ -123,6 +134,7 @@ __device__ inline void rate_small_net(const RateArgs &a, uint32_t u, uint32_t b,
 template <int G, int CAP, int LOG2CAP>
 __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t *list, uint32_t count) {
     constexpr int GPB = BLOCK / G;
+    if (pass_cut(a.ncl, a.n_cur)) return;
     __shared__ uint32_t keys[GPB][CAP];
     __shared__ uint32_t stamp[GPB][CAP];
     __shared__ uint64_t R[GPB][CAP];
@@ -240,6 +252,7 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t *list, uint32_t count) {
     constexpr int LCAP = 4096, LLOG = 12;
+    if (pass_cut(a.ncl, a.n_cur)) return;
     __shared__ uint32_t keys[LCAP];
     __shared__ uint32_t stamp[LCAP];
     __shared__ uint64_t R[LCAP];
@@ -355,7 +368,7 @@ __global__ __launch_bounds__(BLOCK) void k_hub_info(RateArgs a, const uint32_t *
                                                     const uint32_t *bound, uint32_t n_cur, uint4 *info) {
     for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
         const uint32_t u = list[i];
-        const bool active = a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u];
+        const bool active = a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u] && !pass_cut(a.ncl, a.n_cur);
         const uint32_t D = bound[u] < n_cur - 1 ? bound[u] : n_cur - 1;
         info[i] = make_uint4(u, a.inc_off[u], a.inc_off[u + 1], active ? D : NONE);
     }
@@ -520,6 +533,7 @@ __global__ __launch_bounds__(BLOCK) void k_account_rate(RateArgs a, const uint32
                                                         uint32_t *nmark, uint32_t *vmark, uint32_t *cmark,
                                                         uint32_t stamp, unsigned long long *acc) {
     __shared__ unsigned long long red[BLOCK / WAVE];
+    if (pass_cut(a.ncl, a.n_cur)) return;
     unsigned long long bytes = 0;
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
         const uint32_t u = list[idx];
@@ -681,9 +695,10 @@ __global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *bound, uint3
 // ---------------------------------------------------------------------------
 // Approval and apply
 // ---------------------------------------------------------------------------
-__global__ void k_approve_fast(const uint32_t *proposers, uint32_t np, const uint32_t *ptarget,
+__global__ void k_approve_fast(const uint32_t *proposers, const uint32_t *np_dev, const uint32_t *ptarget,
                                const int64_t *cw, const int64_t *tsum, int64_t cap_mult, int64_t W,
                                uint8_t *ok, uint32_t *slow, uint32_t *nslow) {
+    const uint32_t np = *np_dev;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ((np + 63) / 64) * 64;
          i += gridDim.x * blockDim.x) {
         bool act = i < np;
@@ -747,8 +762,10 @@ __global__ void k_slow_decide(const uint32_t *vals, uint32_t ns, const uint32_t 
     }
 }
 
-__global__ void k_apply_joins(const uint32_t *proposers, uint32_t np, const uint32_t *ptarget, const uint8_t *ok,
-                              const int32_t *vwgt, uint32_t *rep, int64_t *cw, int64_t *tsum, uint32_t *n_clusters) {
+__global__ void k_apply_joins(const uint32_t *proposers, const uint32_t *np_dev, const uint32_t *ptarget,
+                              const uint8_t *ok, const int32_t *vwgt, uint32_t *rep, int64_t *cw, int64_t *tsum,
+                              uint32_t *n_clusters) {
+    const uint32_t np = *np_dev;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ((np + 63) / 64) * 64;
          i += gridDim.x * blockDim.x) {
         bool act = i < np;
@@ -847,16 +864,13 @@ size_t coarsen_workspace(uint32_t n, uint32_t m, uint32_t p, const hgp_params &p
 }
 
 void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *rep, uint32_t *n_clusters_dev,
-                  uint32_t *n_clusters_host, Arena &A, hipStream_t st) {
+                  uint32_t *n_clusters_host, Arena &A, hipStream_t st, int64_t W_known) {
     const uint32_t n = h.n, m = h.m, S = prm.coarsen_subrounds;
     size_t mk = A.mark();
     CoarsenBufs B;
     plan(A, n, m, h.p, S, B);
-    int64_t W = 0;
-    {
-        // c(V) is needed on the host for the cap test constants
-        W = total_weight(h.vwgt, n, A, st);
-    }
+    // c(V) is needed on the host for the cap test constants
+    const int64_t W = W_known >= 0 ? W_known : total_weight(h.vwgt, n, A, st);
     const int64_t cap_mult = (int64_t)prm.limit_factor * (int64_t)prm.k;
     const uint64_t mseed = mix64(prm.seed);
 
@@ -952,10 +966,12 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     for (uint32_t r = 0; r < S; ++r) {
         HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 2, st));
         k_target_info<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(rep, B.cw, h.vwgt, n, mseed, level, S, r,
-                                                                        B.tinfo);
+                                                                        B.tinfo, ncl);
         HGP_LAUNCH_CHECK();
         RateArgs a{h.pin_off, h.pins, h.inc_off, h.inc, h.vwgt, B.nscore, rep, B.cw, B.tinfo, B.ptarget, B.tsum,
-                   B.proposers, nprop, mseed, level, r, S, cap_mult, W, r > 0};
+                   B.proposers, nprop, mseed, level, r, S, cap_mult, W, r > 0, ncl, n};
+        uint32_t cand = 0;  // candidates listed for the sub-round: a bound on its proposals
+        for (int c = 0; c < NCLASS; ++c) cand += counts[r * NCLASS + c];
         for (int c = 0; c < NCLASS; ++c) {
             uint32_t cntc = counts[r * NCLASS + c];
             if (!cntc) continue;
@@ -989,16 +1005,19 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             }
             HGP_LAUNCH_CHECK();
         }
-        uint32_t np = 0;
-        HGP_CHECK_HIP(hipMemcpyAsync(&np, nprop, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        stream_sync(st);
-        if (np) {
-            k_approve_fast<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.proposers, np, B.ptarget, B.cw,
-                                                                              B.tsum, cap_mult, W, B.ok, B.slow, nslow);
+        if (cand) {
+            k_approve_fast<<<grid_for(cand, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.proposers, nprop, B.ptarget, B.cw,
+                                                                                B.tsum, cap_mult, W, B.ok, B.slow,
+                                                                                nslow);
             HGP_LAUNCH_CHECK();
-            uint32_t ns = 0;
-            HGP_CHECK_HIP(hipMemcpyAsync(&ns, nslow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            // one read-back per sub-round: the joins that need the sorted
+            // approval, and the cluster count after the previous sub-round
+            uint32_t hv[3];
+            HGP_CHECK_HIP(hipMemcpyAsync(hv, B.scal, sizeof(hv), hipMemcpyDeviceToHost, st));
             stream_sync(st);
+            const uint32_t ns = hv[1];
+            cnt = hv[2];
+            if ((uint64_t)5 * cnt < (uint64_t)2 * n) break;  // the pass was cut: nothing was proposed
             if (ns) {
                 int ub = bits_for(n ? n - 1 : 0);
                 int cb = bits_for(n ? n - 1 : 0);
@@ -1032,14 +1051,13 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                                                                                  B.cw, cap_mult, W, B.ok);
                 HGP_LAUNCH_CHECK();
             }
-            k_apply_joins<<<grid_for(np, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.proposers, np, B.ptarget, B.ok,
-                                                                             h.vwgt, rep, B.cw, B.tsum, ncl);
+            k_apply_joins<<<grid_for(cand, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.proposers, nprop, B.ptarget, B.ok,
+                                                                               h.vwgt, rep, B.cw, B.tsum, ncl);
             HGP_LAUNCH_CHECK();
         }
-        HGP_CHECK_HIP(hipMemcpyAsync(&cnt, ncl, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        stream_sync(st);
-        if ((uint64_t)5 * cnt < (uint64_t)2 * n) break;
     }
+    HGP_CHECK_HIP(hipMemcpyAsync(&cnt, ncl, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    stream_sync(st);
     if (n_clusters_dev) HGP_CHECK_HIP(hipMemcpyAsync(n_clusters_dev, ncl, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
     if (n_clusters_host) *n_clusters_host = cnt;
     A.release(mk);

@@ -221,10 +221,240 @@ __global__ void k_project(uint32_t n, const uint32_t *cid, const uint32_t *cpart
         part[v] = cpart[cid[v]];
 }
 
+// ---------------------------------------------------------------------------
+// Small coarsest levels: the whole order and fill in one workgroup (no host
+// round trip per layer).  The order is the same: within a layer the
+// expansion (frontier vertex, incident net, pin) is flattened to one index x
+// in lexicographic order, which is the key order of the device-wide path, so
+// a vertex joins the next layer at its smallest x and the winners are laid
+// out in x order.  Used when the whole expansion (sum over nets of |e|^2)
+// is small; it costs about one workgroup step per IPS_THREADS pins.
+// ---------------------------------------------------------------------------
+constexpr int IPS_THREADS = 1024;
+constexpr uint32_t IPS_MAX_N = 1u << 16;
+constexpr uint32_t IPS_MAX_P = 1u << 20;
+constexpr uint64_t IPS_MAX_SQ = 1ull << 18;  // sum over nets of |e|^2
+
+// sum over nets of |e|^2
+__global__ void k_sq_sizes(const uint32_t *pin_off, uint32_t m, unsigned long long *out) {
+    unsigned long long acc = 0;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+        const unsigned long long z = pin_off[e + 1] - pin_off[e];
+        acc += z * z;
+    }
+    acc = wave_sum(acc);
+    if (__lane_id() == 0 && acc) atomicAdd(out, acc);
+}
+
+__device__ inline uint32_t ips_min(uint32_t v, uint32_t *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_xor(v, o, 64);
+        v = y < v ? y : v;
+    }
+    __syncthreads();
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    uint32_t r = red[0];
+    for (int i = 1; i < IPS_THREADS / WAVE; ++i) r = red[i] < r ? red[i] : r;
+    __syncthreads();  // red is reused by the caller
+    return r;
+}
+
+// Owner lookups over an exclusive prefix A[0..len) of positive sizes
+// (A[0] = 0): the owner of position x is the largest i with A[i] <= x.  A
+// window of IPS_THREADS consecutive positions starting at c0 is covered by
+// at most IPS_THREADS + 1 segments starting at the owner of c0 (`cur`), so
+// those starts are staged in LDS and every lookup is an LDS search.
+template <class T>
+__device__ inline void ips_stage(const T *A, uint32_t len, uint32_t cur, T *win) {
+    for (uint32_t j = threadIdx.x; j <= (uint32_t)IPS_THREADS; j += IPS_THREADS)
+        win[j] = cur + j < len ? A[cur + j] : ~(T)0;
+    __syncthreads();
+}
+template <class T>
+__device__ inline uint32_t ips_owner(const T *win, uint32_t cur, T x) {
+    uint32_t lo = 0, hi = IPS_THREADS;  // largest j with win[j] <= x (win[0] <= x)
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (win[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return cur + lo;
+}
+
+__global__ __launch_bounds__(IPS_THREADS) void k_ip_small(const uint32_t *pin_off, const uint32_t *pins,
+                                                          const uint32_t *inc_off, const uint32_t *inc,
+                                                          const int32_t *vwgt, uint32_t n, uint32_t k, uint64_t T,
+                                                          unsigned long long *key, uint32_t *D, uint32_t *pe,
+                                                          uint64_t *E, uint32_t *order, uint64_t *P, uint32_t *S,
+                                                          uint32_t *part) {
+    __shared__ uint32_t red[IPS_THREADS / WAVE];
+    __shared__ uint64_t red64[IPS_THREADS / WAVE];
+    __shared__ uint32_t vis[IPS_MAX_N / 32];  // visited bitmap
+    __shared__ uint64_t win[IPS_THREADS + 1];
+    __shared__ uint32_t win32[IPS_THREADS + 1];
+    const uint32_t tid = threadIdx.x;
+    auto visited = [&](uint32_t v) -> bool { return (vis[v >> 5] >> (v & 31)) & 1u; };
+    auto visit = [&](uint32_t v) { atomicOr(&vis[v >> 5], 1u << (v & 31)); };
+    for (uint32_t i = tid; i < (n + 31) / 32; i += IPS_THREADS) vis[i] = 0;
+    for (uint32_t v = tid; v < n; v += IPS_THREADS) key[v] = ~0ull;
+    __syncthreads();
+    uint32_t pos = 0, next = 0;
+    while (pos < n) {
+        // smallest unvisited vertex with incident nets at or after `next`;
+        // the unvisited vertices before it have no nets and join in ID order
+        uint32_t s = n;
+        for (uint32_t c0 = next; c0 < n; c0 += IPS_THREADS) {
+            const uint32_t v = c0 + tid;
+            const bool cand = v < n && !visited(v) && inc_off[v + 1] > inc_off[v];
+            s = ips_min(cand ? v : n, red);
+            if (s < n) break;
+        }
+        for (uint32_t c0 = next; c0 < s; c0 += IPS_THREADS) {
+            const uint32_t v = c0 + tid;
+            const uint32_t un = (v < s && !visited(v)) ? 1u : 0u;
+            uint32_t tot;
+            const uint32_t incl = block_incl_scan_n<uint32_t, IPS_THREADS>(un, red, &tot);
+            if (un) {
+                order[pos + incl - 1] = v;
+                visit(v);
+            }
+            pos += tot;
+        }
+        if (s >= n) break;
+        if (tid == 0) { order[pos] = s; visit(s); }
+        uint32_t fs = pos, fe = pos + 1;
+        pos += 1;
+        next = s + 1;
+        __syncthreads();
+        while (fs < fe) {
+            const uint32_t F = fe - fs;
+            // D: exclusive prefix of the frontier degrees (pairs of the layer)
+            uint32_t Tn = 0;
+            for (uint32_t c0 = 0; c0 < F; c0 += IPS_THREADS) {
+                const uint32_t i = c0 + tid;
+                uint32_t d = 0;
+                if (i < F) {
+                    const uint32_t v = order[fs + i];
+                    d = inc_off[v + 1] - inc_off[v];
+                }
+                uint32_t tot;
+                const uint32_t incl = block_incl_scan_n<uint32_t, IPS_THREADS>(d, red, &tot);
+                if (i < F) D[i] = Tn + incl - d;
+                Tn += tot;
+            }
+            __syncthreads();
+            // E: exclusive prefix of the pair net sizes (pins of the expansion)
+            uint64_t X = 0;
+            uint32_t cur = 0;  // frontier index owning pair c0
+            for (uint32_t c0 = 0; c0 < Tn; c0 += IPS_THREADS) {
+                ips_stage<uint32_t>(D, F, cur, win32);
+                const uint32_t t = c0 + tid;
+                uint64_t sz = 0;
+                if (t < Tn) {
+                    const uint32_t fi = ips_owner<uint32_t>(win32, cur, t);
+                    const uint32_t e = inc[inc_off[order[fs + fi]] + (t - D[fi])];
+                    pe[t] = e;
+                    sz = pin_off[e + 1] - pin_off[e];
+                }
+                cur = ips_owner<uint32_t>(win32, cur, c0 + IPS_THREADS);
+                uint64_t tot;
+                const uint64_t incl = block_incl_scan_n<uint64_t, IPS_THREADS>(sz, red64, &tot);
+                if (t < Tn) E[t] = X + incl - sz;
+                X += tot;
+            }
+            __syncthreads();
+            // keys: smallest expansion index per unvisited vertex
+            cur = 0;
+            for (uint64_t c0 = 0; c0 < X; c0 += IPS_THREADS) {
+                ips_stage<uint64_t>(E, Tn, cur, win);
+                const uint64_t x = c0 + tid;
+                if (x < X) {
+                    const uint32_t t = ips_owner<uint64_t>(win, cur, x);
+                    const uint32_t e = pe[t];
+                    const uint32_t w = pins[pin_off[e] + (uint32_t)(x - E[t])];
+                    if (!visited(w)) atomicMin(&key[w], (unsigned long long)x);
+                }
+                cur = ips_owner<uint64_t>(win, cur, c0 + IPS_THREADS);
+                __syncthreads();  // the window is restaged
+            }
+            // winners in expansion order
+            uint32_t Wn = 0;
+            cur = 0;
+            for (uint64_t c0 = 0; c0 < X; c0 += IPS_THREADS) {
+                ips_stage<uint64_t>(E, Tn, cur, win);
+                const uint64_t x = c0 + tid;
+                uint32_t w = 0, wn = 0;
+                if (x < X) {
+                    const uint32_t t = ips_owner<uint64_t>(win, cur, x);
+                    const uint32_t e = pe[t];
+                    w = pins[pin_off[e] + (uint32_t)(x - E[t])];
+                    // the key is read back at L2, where the atomics were applied
+                    wn = (!visited(w) && atomicOr(&key[w], 0ull) == x) ? 1u : 0u;
+                }
+                cur = ips_owner<uint64_t>(win, cur, c0 + IPS_THREADS);
+                uint32_t tot;
+                const uint32_t incl = block_incl_scan_n<uint32_t, IPS_THREADS>(wn, red, &tot);
+                if (wn) order[pos + Wn + incl - 1] = w;
+                Wn += tot;
+            }
+            __syncthreads();
+            for (uint32_t i = pos + tid; i < pos + Wn; i += IPS_THREADS) {
+                const uint32_t w = order[i];
+                visit(w);
+                atomicExch(&key[w], ~0ull);
+            }
+            __syncthreads();
+            fs = pos;
+            fe = pos + Wn;
+            pos += Wn;
+        }
+    }
+    __syncthreads();
+    // fill: P = inclusive prefix of the weights in order
+    uint64_t carry = 0;
+    for (uint32_t c0 = 0; c0 < n; c0 += IPS_THREADS) {
+        const uint32_t i = c0 + tid;
+        const uint64_t w = i < n ? (uint64_t)(uint32_t)vwgt[order[i]] : 0ull;
+        uint64_t tot;
+        const uint64_t incl = block_incl_scan_n<uint64_t, IPS_THREADS>(w, red64, &tot);
+        if (i < n) P[i] = carry + incl;
+        carry += tot;
+    }
+    __syncthreads();
+    // block b starts at S_b; S_{b+1} = 1 + first i >= S_b whose prefix from
+    // S_b reaches T (the last block takes the rest)
+    if (tid == 0) {
+        uint32_t sb = 0;
+        S[0] = 0;
+        for (uint32_t b = 1; b < k; ++b) {
+            if (sb < n) {
+                const uint64_t target = (sb == 0 ? 0ull : P[sb - 1]) + T;
+                uint32_t lo = sb, hi = n;  // first i in [sb, n) with P[i] >= target, or n
+                while (lo < hi) {
+                    const uint32_t mid = lo + ((hi - lo) >> 1);
+                    if (P[mid] >= target) hi = mid; else lo = mid + 1;
+                }
+                sb = lo < n ? lo + 1 : n;
+            }
+            S[b] = sb;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += IPS_THREADS) {
+        uint32_t lo = 0, hi = k - 1;  // largest b with S[b] <= i
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (S[mid] <= i) lo = mid; else hi = mid - 1;
+        }
+        part[order[i]] = lo;
+    }
+}
+
 struct IpBufs {
     uint32_t *order, *visited, *J, *S, *exoff, *D, *cnt, *scal;
     unsigned long long *key;
-    uint64_t *P;
+    uint64_t *P, *E;
 };
 
 static void plan(Arena &A, uint32_t n, uint32_t p, uint32_t k, IpBufs &B) {
@@ -237,6 +467,7 @@ static void plan(Arena &A, uint32_t n, uint32_t p, uint32_t k, IpBufs &B) {
     B.exoff = A.alloc<uint32_t>(p);
     B.D = A.alloc<uint32_t>(n);
     B.cnt = A.alloc<uint32_t>((size_t)p + 1);
+    B.E = A.alloc<uint64_t>(std::min<size_t>(p, IPS_MAX_P) + 1);
     B.scal = A.alloc<uint32_t>(8);
     scan_reserve<uint64_t>(A, n);
     scan_reserve<uint32_t>(A, (size_t)p + 1);
@@ -256,13 +487,34 @@ static uint32_t read_u32(const uint32_t *d, hipStream_t st) {
     return h;
 }
 
-void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st) {
+void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st, int64_t W_known) {
     const uint32_t n = h.n;
     size_t mk = A.mark();
     IpBufs B;
     plan(A, n, h.p, k, B);
-    const int64_t W = total_weight(h.vwgt, n, A, st);
+    const int64_t W = W_known >= 0 ? W_known : total_weight(h.vwgt, n, A, st);
     const uint64_t T = (uint64_t)((W + k - 1) / k);
+    bool small = n > 0 && n <= IPS_MAX_N && h.p <= IPS_MAX_P;
+    if (small) {
+        unsigned long long *sq = (unsigned long long *)B.P;  // scratch until the fill
+        HGP_CHECK_HIP(hipMemsetAsync(sq, 0, sizeof(unsigned long long), st));
+        if (h.m) {
+            k_sq_sizes<<<grid_for(h.m, BLOCK, 256), BLOCK, 0, st>>>(h.pin_off, h.m, sq);
+            HGP_LAUNCH_CHECK();
+        }
+        unsigned long long sqh = 0;
+        HGP_CHECK_HIP(hipMemcpyAsync(&sqh, sq, sizeof(sqh), hipMemcpyDeviceToHost, st));
+        stream_sync(st);
+        small = sqh <= IPS_MAX_SQ;
+    }
+    if (small) {
+        k_ip_small<<<1, IPS_THREADS, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, h.vwgt, n, k, T, B.key, B.D,
+                                              B.cnt, B.E, B.order, B.P, B.S, part);
+        HGP_LAUNCH_CHECK();
+        stream_sync(st);
+        A.release(mk);
+        return;
+    }
     uint32_t *d_start = B.scal + 0, *d_cnt = B.scal + 1, *d_T = B.scal + 2, *d_W = B.scal + 3;
     HGP_CHECK_HIP(hipMemsetAsync(B.visited, 0, sizeof(uint32_t) * n, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.key, 0xFF, sizeof(unsigned long long) * n, st));

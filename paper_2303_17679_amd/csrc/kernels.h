@@ -21,8 +21,10 @@ void copy_arrays(const CopySet &c, hipStream_t st);
 
 // coarsen.hip
 size_t coarsen_workspace(uint32_t n, uint32_t m, uint32_t p, const hgp_params &prm);
+// W_known: c(V) when the caller knows it (it is the same on every level), or
+// -1 to compute it here (one reduction and a sync).
 void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *rep, uint32_t *n_clusters_dev,
-                  uint32_t *n_clusters_host, Arena &A, hipStream_t st);
+                  uint32_t *n_clusters_host, Arena &A, hipStream_t st, int64_t W_known = -1);
 
 // contract.hip
 size_t contract_workspace(uint32_t n, uint32_t m, uint32_t p);
@@ -34,11 +36,11 @@ size_t refine_workspace(uint32_t n, uint32_t m, uint32_t k);
 void objective(const hgp_hg &h, uint32_t k, const uint32_t *part, int64_t *obj, int64_t *bw, Arena &A,
                hipStream_t st);
 void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj, int64_t *bw,
-               Arena &A, hipStream_t st);
+               Arena &A, hipStream_t st, int64_t W_known = -1);
 
 // ip.hip
 size_t ip_workspace(uint32_t n, uint32_t p, uint32_t k);
-void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st);
+void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st, int64_t W_known = -1);
 void project(uint32_t n, const uint32_t *cid, const uint32_t *cpart, uint32_t *part, hipStream_t st);
 
 }  // namespace hgp

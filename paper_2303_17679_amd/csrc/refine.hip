@@ -210,6 +210,7 @@ struct GainArgs {
     uint32_t level, round, sub, S, n;
     uint32_t *prop_t, *prop_g, *plist, *nprop, *gmax;
     uint32_t *pw;  // [k*k] total weight proposed per ordered block pair
+    uint32_t *pc;  // [k*k] number of proposals per ordered block pair
     uint32_t k;
     const uint32_t *abort;  // set when the round must be resumed by the host
 };
@@ -224,6 +225,7 @@ __device__ inline void propose(const GainArgs<KW> &a, uint32_t u, uint32_t s, ui
         a.prop_t[u] = t;
         a.prop_g[u] = g;
         atomicAdd(&a.pw[s * a.k + t], (uint32_t)a.vwgt[u]);
+        atomicAdd(&a.pc[s * a.k + t], 1u);
     }
     uint32_t gm = has ? g : 0u;
 #pragma unroll
@@ -480,6 +482,29 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
     }
 }
 
+// Per-sub-round state (scalar counters, pair sums) back to zero, and the
+// previous sub-round's block-weight changes folded into the block weights.
+// Runs at the start of a sub-round, after every reader of that state.  The
+// candidate counts ccnt are cleared by k_pair_plan instead (this kernel
+// counts into them).
+struct SubReset {
+    uint32_t *scal, *pw, *pc;
+    uint32_t kk, k;
+    int64_t *bw, *dbw_g;
+};
+__device__ inline void subround_reset(const SubReset &z) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+    if (tid < 4) z.scal[tid] = 0;                    // nprop, gmax, ntouched, nlong
+    if (tid == 4) { z.scal[13] = 0; z.scal[14] = 0; }  // oversized-pair proposals, movers
+    if (tid == 5) { z.scal[24] = 0; z.scal[25] = 0; }  // movers of more than HUB_DEG nets, slow pairs
+    for (uint32_t i = tid; i < z.kk; i += nt) { z.pw[i] = 0; z.pc[i] = 0; }
+    if (blockIdx.x == 0)
+        for (uint32_t b = threadIdx.x; b < z.k; b += blockDim.x) {
+            const int64_t d = z.dbw_g[b];
+            if (d) { z.bw[b] += d; z.dbw_g[b] = 0; }
+        }
+}
+
 // Candidates of LP sub-round (r, s): the boundary vertices (an incident net
 // with lambda > 1 -- no other vertex can have a positive gain) whose
 // sub-round hash selects s, appended to the list of their degree class.
@@ -492,11 +517,12 @@ template <uint32_t CAND_PER>
 __global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, const uint32_t *bcnt, uint32_t n,
                                                     uint64_t mseed, uint32_t level, uint32_t r, uint32_t s,
                                                     uint32_t S, ClassLists cl, uint32_t *ccnt, uint32_t *lists,
-                                                    const uint32_t *abort) {
+                                                    SubReset z, const uint32_t *abort) {
     constexpr int NW = BLOCK / WAVE;
     __shared__ uint32_t wc[NDEG][NW];
     __shared__ uint32_t base[NDEG];
     if (*abort) return;
+    subround_reset(z);
     const uint32_t lo = blockIdx.x * CAND_PER * BLOCK;
     if (lo >= n) return;  // uniform per block
     const uint32_t w = threadIdx.x / WAVE;
@@ -590,18 +616,6 @@ __global__ __launch_bounds__(BLOCK) void k_init_bcnt(const uint32_t *inc_off, co
         }
         if (u < n) bcnt[u] = c;
     }
-}
-
-// Per-sub-round counters and pair sums back to zero.
-__global__ void k_lp_reset(uint32_t *scal, uint32_t *pw, uint32_t kk, int64_t *dbw_g, uint32_t k) {
-    if (scal[15]) return;  // the round was cut short: later sub-rounds are replayed
-    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
-    if (tid < 4) scal[tid] = 0;                  // nprop, gmax, ntouched, nlong
-    if (tid == 4) { scal[13] = 0; scal[14] = 0; }  // nslow, nmov
-    if (tid >= 5 && tid < 9) scal[20 + tid - 5] = 0;  // candidates per degree class
-    if (tid == 9) scal[24] = 0;                        // movers of more than HUB_DEG nets
-    for (uint32_t i = tid; i < kk; i += nt) pw[i] = 0;
-    for (uint32_t i = tid; i < k; i += nt) dbw_g[i] = 0;
 }
 
 // Measurement only: compulsory bytes of one gains launch: for every
@@ -819,12 +833,15 @@ __global__ __launch_bounds__(BLOCK) void k_lp_apply(const uint64_t *keys, const 
 // once, in any order, and only the remaining pairs need the sorted walk.
 // Block-weight changes go to dbw_g so that the sorted walk still reads the
 // snapshot block weights.  Movers are appended to the sub-round's mover list.
+// The proposals of the other pairs go to their pair's segment of `seg`
+// (k_pair_plan has laid the segments out).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const uint32_t *np_dev,
                                                    const uint32_t *prop_t, const uint32_t *pw, uint32_t k,
                                                    const int32_t *vwgt, uint32_t *part, const int64_t *bw,
                                                    int64_t lmax, int64_t *dbw_g, uint32_t *mlist, uint32_t *moves,
-                                                   uint32_t *slow, uint32_t *nslow, const uint32_t *abort) {
+                                                   const uint32_t *pbase, uint32_t *pcur, uint32_t *seg,
+                                                   const uint32_t *abort) {
     if (*abort) return;
     __shared__ int64_t dbw[256];
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
@@ -832,7 +849,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
     const uint32_t np = *np_dev;
     for (uint32_t base = blockIdx.x * BLOCK; base < np; base += gridDim.x * BLOCK) {
         const uint32_t i = base + threadIdx.x;
-        bool mv = false, isslow = false;
+        bool mv = false;
         uint32_t u = 0;
         if (i < np) {
             u = plist[i];
@@ -848,11 +865,10 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
                 atomicAdd((unsigned long long *)&dbw[s], (unsigned long long)(-c));
                 atomicAdd((unsigned long long *)&dbw[t], (unsigned long long)c);
             } else {
-                isslow = true;
+                const uint32_t pi = x * k + y;
+                seg[pbase[pi] + atomicAdd(&pcur[pi], 1u)] = u;
             }
         }
-        uint32_t sp = warp_agg_append(nslow, isslow);
-        if (isslow) slow[sp] = u;
         uint32_t mp = warp_agg_append(moves, mv);
         if (mv) mlist[mp] = u;
     }
@@ -861,28 +877,96 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
         if (dbw[b]) atomic_add_i64(&dbw_g[b], dbw[b]);
 }
 
-__global__ void k_add_dbw(int64_t *bw, const int64_t *dbw_g, uint32_t k) {
+__global__ void k_add_dbw(int64_t *bw, int64_t *dbw_g, uint32_t k) {
     for (uint32_t b = threadIdx.x; b < k; b += blockDim.x)
-        if (dbw_g[b]) bw[b] += dbw_g[b];
+        if (dbw_g[b]) { bw[b] += dbw_g[b]; dbw_g[b] = 0; }
 }
 
 // ---------------------------------------------------------------------------
-// Small sub-rounds: one workgroup does sort, prefix sums, selection and apply
-// in LDS (one launch instead of ~35).  Requires np <= FUSED_MAX and the full
-// key (s, t, G-g, u) to fit in 64 bits.
+// Pairs whose whole move sets do not fit: one workgroup per block pair.
+//   k_pair_plan  (one workgroup) applies the whole-pair test of k_lp_fast to
+//                every unordered pair {x < y} with proposals and gives each
+//                pair that fails it a segment of `seg` (exclusive prefix of
+//                the failing pairs' proposal counts) and a slot in the pair
+//                list.  It also clears the candidate counts of the sub-round,
+//                whose lists k_gains has consumed.
+//   k_lp_fast    scatters those pairs' proposals into their segments, in no
+//                particular order.
+//   k_lp_pairs   sorts each segment in LDS by (direction, gain desc, u asc) --
+//                a total order, so the arbitrary segment order does not
+//                matter -- walks the merge path of the pair and applies the
+//                approved prefixes.  A pair of more than PAIR_MAX proposals is
+//                handed to the device-wide path: its proposals go to the slow
+//                list and the abort word records the sub-round, after which
+//                the host finishes the sub-round and replays the rest of the
+//                round.
+// Block-weight changes go to dbw_g; every test of the sub-round reads the
+// snapshot block weights.
 // ---------------------------------------------------------------------------
-constexpr int FUSED_MAX = 4096;
-constexpr int FUSED_THREADS = 1024;
+constexpr int PLAN_THREADS = 1024;
+constexpr int PAIR_THREADS = 512;
+constexpr uint32_t PAIR_MAX = 4096;
 
-__device__ inline uint32_t lower_pair(const uint64_t *skey, uint32_t np, int sh_t, uint64_t target) {
-    uint32_t lo = 0, hi = np;  // first j with (skey[j] >> sh_t) >= target
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if ((skey[mid] >> sh_t) < target) lo = mid + 1; else hi = mid;
+// Pair entries i = x * k + y, PLAN_PER consecutive entries per thread and
+// round (one block scan per round); every load of a round is issued before
+// any is used.
+constexpr uint32_t PLAN_PER = 4;
+__global__ __launch_bounds__(PLAN_THREADS) void k_pair_plan(const uint32_t *pw, const uint32_t *pc, uint32_t k,
+                                                            const int64_t *bw, int64_t lmax, uint32_t *pbase,
+                                                            uint32_t *pcur, uint32_t *spairs, uint32_t *nsp,
+                                                            uint32_t *ccnt, const uint32_t *abort) {
+    __shared__ uint64_t wsum[PLAN_THREADS / WAVE];
+    __shared__ int64_t sbeta[256];
+    if (*abort) return;
+    const uint32_t tid = threadIdx.x;
+    if (tid < NDEG) ccnt[tid] = 0;
+    for (uint32_t b = tid; b < k; b += PLAN_THREADS) sbeta[b] = floor_div_i64(lmax - bw[b], (int64_t)k - 1);
+    __syncthreads();
+    const uint32_t kk = k * k;
+    uint64_t carry = 0;  // (failing pairs << 32) | their proposals
+    for (uint32_t c0 = 0; c0 < kk; c0 += PLAN_THREADS * PLAN_PER) {
+        const uint32_t i0 = c0 + tid * PLAN_PER;
+        uint32_t x[PLAN_PER], y[PLAN_PER], ca[PLAN_PER], cb[PLAN_PER], wa[PLAN_PER], wb[PLAN_PER];
+#pragma unroll
+        for (uint32_t q = 0; q < PLAN_PER; ++q) {
+            const uint32_t i = i0 + q < kk ? i0 + q : 0u;
+            x[q] = i / k;
+            y[q] = i - x[q] * k;
+            const uint32_t it = y[q] * k + x[q];
+            ca[q] = pc[i];
+            cb[q] = pc[it];
+            wa[q] = pw[i];
+            wb[q] = pw[it];
+        }
+        uint32_t cnt[PLAN_PER];
+        uint64_t mine = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < PLAN_PER; ++q) {
+            const uint32_t c = ca[q] + cb[q];
+            const int64_t xf = (int64_t)wa[q] - (int64_t)wb[q];
+            const bool fail = i0 + q < kk && x[q] < y[q] && c && !(-sbeta[x[q]] <= xf && xf <= sbeta[y[q]]);
+            cnt[q] = fail ? c : 0u;
+            if (fail) mine += (1ull << 32) | c;
+        }
+        uint64_t tot;
+        const uint64_t incl = block_incl_scan_n<uint64_t, PLAN_THREADS>(mine, wsum, &tot);
+        uint64_t ex = carry + incl - mine;
+#pragma unroll
+        for (uint32_t q = 0; q < PLAN_PER; ++q) {
+            if (!cnt[q]) continue;
+            const uint32_t i = i0 + q;
+            pbase[i] = (uint32_t)ex;
+            pcur[i] = 0;
+            spairs[(uint32_t)(ex >> 32)] = i;
+            ex += (1ull << 32) | cnt[q];
+        }
+        carry += tot;
     }
-    return lo;
+    if (tid == 0) *nsp = (uint32_t)(carry >> 32);
 }
 
+// Merge-path view of one direction of a pair: element i of the direction is
+// sorted position start + i; excl(i) is the weight of its first i elements.
 struct LSeg {
     uint32_t start, len;
     uint32_t base;
@@ -901,166 +985,116 @@ __device__ inline uint32_t lcount_below(const LSeg &v, uint32_t x, bool strict) 
     return lo;
 }
 
-__global__ __launch_bounds__(FUSED_THREADS) void k_lp_fused(const uint32_t *plist, const uint32_t *np_dev,
-                                                            const int64_t *dbw_g, const uint32_t *prop_t,
-                                                            const uint32_t *prop_g, const uint32_t *gmax_dev,
-                                                            int kb_bits, int ub_bits, uint32_t *abort, uint32_t sub_id,
-                                                            uint32_t k,
-                                                            const int32_t *vwgt, const uint32_t *inc_off,
-                                                            const uint32_t *inc, uint32_t *part, int64_t *bw,
-                                                            int64_t lmax, uint32_t *mlist_g, uint32_t *moves) {
-    __shared__ uint64_t skey[FUSED_MAX];
-    __shared__ uint32_t sval[FUSED_MAX];
-    __shared__ uint32_t sincl[FUSED_MAX];
-    __shared__ unsigned long long sbest[FUSED_MAX];
-    __shared__ int64_t dbw[256];
-    __shared__ uint32_t wsum[FUSED_THREADS / WAVE];
+__global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *spairs, const uint32_t *nsp_dev,
+                                                           const uint32_t *pbase, const uint32_t *pc,
+                                                           const uint32_t *seg, uint32_t k, const uint32_t *prop_g,
+                                                           const int32_t *vwgt, uint32_t *part, const int64_t *bw,
+                                                           int64_t lmax, int64_t *dbw_g, uint32_t *mlist,
+                                                           uint32_t *nmov, uint32_t *slow, uint32_t *nslow,
+                                                           uint32_t *abort, uint32_t sub_id) {
+    __shared__ uint64_t skey[PAIR_MAX];
+    __shared__ uint32_t sincl[PAIR_MAX];
+    __shared__ uint32_t wsum[PAIR_THREADS / WAVE];
+    __shared__ unsigned long long sbest;
+    // an earlier sub-round was cut short (a block of this launch may raise
+    // the word for this sub-round: that does not stop the others)
+    const uint32_t aw = *abort;
+    if (aw && aw != sub_id + 1) return;
     const uint32_t tid = threadIdx.x;
-    if (*abort) return;
-    const uint32_t np = *np_dev;
-    if (np == 0) {
-        for (uint32_t b = tid; b < k; b += FUSED_THREADS)
-            if (dbw_g[b]) bw[b] += dbw_g[b];
-        return;
-    }
-    // key (s, t, G-g, u) of this sub-round's gains
-    const uint32_t G = *gmax_dev;
-    const int gb = G ? 32 - __clz(G) : 0;
-    if (np > (uint32_t)FUSED_MAX || 2 * kb_bits + gb + ub_bits > 64) {
-        // beyond one workgroup: the host runs the device-wide path for this
-        // sub-round and replays the rest of the round (nothing applied here)
-        if (tid == 0) { abort[0] = 1; abort[1] = sub_id; }
-        return;
-    }
-    KeyLayout L;
-    L.kmask = (1u << kb_bits) - 1u;
-    L.G = G;
-    L.with_u = true;
-    L.sh_u = 0; L.sh_g = ub_bits; L.sh_t = ub_bits + gb; L.sh_s = ub_bits + gb + kb_bits;
-    const int kb = kb_bits;
-    uint32_t n2 = 1;
-    while (n2 < np) n2 <<= 1;
-    for (uint32_t i = tid; i < n2; i += FUSED_THREADS) {
-        if (i < np) {
-            uint32_t u = plist[i];
-            skey[i] = ((uint64_t)part[u] << L.sh_s) | ((uint64_t)prop_t[u] << L.sh_t) |
-                      ((uint64_t)(L.G - prop_g[u]) << L.sh_g) | ((uint64_t)u << L.sh_u);
-            sval[i] = u;
-        } else {
-            skey[i] = ~0ull;
-            sval[i] = 0;
+    const uint32_t ns = *nsp_dev;
+    for (uint32_t q = blockIdx.x; q < ns; q += gridDim.x) {
+        const uint32_t pi = spairs[q];
+        const uint32_t x = pi / k, y = pi % k;
+        const uint32_t nA = pc[pi], L = nA + pc[y * k + x];
+        const uint32_t base = pbase[pi];
+        if (L > PAIR_MAX) {  // uniform per block
+            for (uint32_t c0 = 0; c0 < L; c0 += PAIR_THREADS) {
+                const uint32_t i = c0 + tid;
+                const uint32_t pos = warp_agg_append(nslow, i < L);
+                if (i < L) slow[pos] = seg[base + i];
+            }
+            if (tid == 0) atomicExch(abort, sub_id + 1);
+            continue;
         }
-    }
-    for (uint32_t b = tid; b < k; b += FUSED_THREADS) dbw[b] = 0;
-    __syncthreads();
-    // bitonic sort of n2 keys (padding keys are the largest)
-    for (uint32_t kk = 2; kk <= n2; kk <<= 1) {
-        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = tid; i < n2; i += FUSED_THREADS) {
-                uint32_t l = i ^ j;
-                if (l > i) {
-                    uint64_t a = skey[i], b = skey[l];
-                    bool up = (i & kk) == 0;
-                    if ((a > b) == up) {
-                        skey[i] = b; skey[l] = a;
-                        uint32_t t = sval[i]; sval[i] = sval[l]; sval[l] = t;
+        uint32_t n2 = 1;
+        while (n2 < L) n2 <<= 1;
+        // key: direction (0: x -> y), then gain descending, then u (< 2^31)
+        for (uint32_t i = tid; i < n2; i += PAIR_THREADS) {
+            uint64_t key = ~0ull;
+            if (i < L) {
+                const uint32_t u = seg[base + i];
+                const uint64_t dir = part[u] == x ? 0ull : 1ull;
+                key = (dir << 63) | ((uint64_t)(0xFFFFFFFFu - prop_g[u]) << 31) | (uint64_t)u;
+            }
+            skey[i] = key;
+        }
+        if (tid == 0) sbest = 0;
+        __syncthreads();
+        for (uint32_t kk = 2; kk <= n2; kk <<= 1) {
+            for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = tid; i < n2; i += PAIR_THREADS) {
+                    const uint32_t l = i ^ j;
+                    if (l > i) {
+                        const uint64_t a = skey[i], b = skey[l];
+                        if ((a > b) == ((i & kk) == 0)) { skey[i] = b; skey[l] = a; }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
-    }
-    // inclusive prefix of node weights in sorted order
-    uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < np; c0 += FUSED_THREADS) {
-        uint32_t i = c0 + tid;
-        uint32_t w = i < np ? (uint32_t)vwgt[sval[i]] : 0u;
-        uint32_t tot;
-        uint32_t incl = block_incl_scan_n<uint32_t, FUSED_THREADS>(w, wsum, &tot);
-        if (i < np) { sincl[i] = carry + incl; sbest[i] = 0; }
-        carry += tot;
-    }
-    __syncthreads();
-    // selection: each element tests the merge-walk state right after it
-    for (uint32_t i = tid; i < np; i += FUSED_THREADS) {
-        uint64_t key = skey[i];
-        uint32_t s = (uint32_t)(key >> L.sh_s) & L.kmask;
-        uint32_t t = (uint32_t)(key >> L.sh_t) & L.kmask;
-        uint32_t x = s < t ? s : t, y = s < t ? t : s;
-        uint64_t pa = ((uint64_t)x << kb) | y, pb = ((uint64_t)y << kb) | x;
+        // inclusive prefix of vertex weights in sorted order (c(V) < 2^31)
+        uint32_t carry = 0;
+        for (uint32_t c0 = 0; c0 < L; c0 += PAIR_THREADS) {
+            const uint32_t i = c0 + tid;
+            const uint32_t w = i < L ? (uint32_t)vwgt[(uint32_t)(skey[i] & 0x7FFFFFFFu)] : 0u;
+            uint32_t tot;
+            const uint32_t incl = block_incl_scan_n<uint32_t, PAIR_THREADS>(w, wsum, &tot);
+            if (i < L) sincl[i] = carry + incl;
+            carry += tot;
+        }
+        __syncthreads();
         LSeg A, Bv;
-        A.start = lower_pair(skey, np, L.sh_t, pa);
-        A.len = lower_pair(skey, np, L.sh_t, pa + 1) - A.start;
-        Bv.start = lower_pair(skey, np, L.sh_t, pb);
-        Bv.len = lower_pair(skey, np, L.sh_t, pb + 1) - Bv.start;
-        A.base = A.start ? sincl[A.start - 1] : 0u;
-        Bv.base = Bv.start ? sincl[Bv.start - 1] : 0u;
-        A.incl = sincl; Bv.incl = sincl;
-        uint32_t leader = A.len ? A.start : Bv.start;
-        int64_t beta_x = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
-        int64_t beta_y = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
-        uint32_t ia, jb, loc;
-        if (s == x) {
-            loc = i - A.start;
-            ia = loc + 1;
-            jb = lcount_below(Bv, A.excl(loc), true);
-        } else {
-            loc = i - Bv.start;
-            jb = loc + 1;
-            ia = lcount_below(A, Bv.excl(loc), false);
+        A.start = 0; A.len = nA; A.base = 0; A.incl = sincl;
+        Bv.start = nA; Bv.len = L - nA; Bv.base = nA ? sincl[nA - 1] : 0u; Bv.incl = sincl;
+        const int64_t beta_x = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
+        const int64_t beta_y = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
+        if (tid == 0 && beta_x >= 0 && beta_y >= 0) atomicMax(&sbest, 1ull << 32);  // the start state
+        // every element tests the walk state right after it
+        for (uint32_t i = tid; i < L; i += PAIR_THREADS) {
+            uint32_t ia, jb;
+            if (i < nA) {
+                ia = i + 1;
+                jb = lcount_below(Bv, A.excl(i), true);
+            } else {
+                jb = i - nA + 1;
+                ia = lcount_below(A, Bv.excl(i - nA), false);
+            }
+            const int64_t xv = (int64_t)A.excl(ia) - (int64_t)Bv.excl(jb);
+            if (-beta_x <= xv && xv <= beta_y) atomicMax(&sbest, ((unsigned long long)(ia + jb + 1) << 32) | ia);
         }
-        if (loc == 0 && beta_x >= 0 && beta_y >= 0) atomicMax(&sbest[leader], 1ull << 32);
-        int64_t xv = (int64_t)A.excl(ia) - (int64_t)Bv.excl(jb);
-        if (-beta_x <= xv && xv <= beta_y)
-            atomicMax(&sbest[leader], ((unsigned long long)(ia + jb + 1) << 32) | ia);
-    }
-    __syncthreads();
-    // apply: (1) movers compacted into LDS in sorted order, block weights
-    uint32_t *mlist = sincl;  // free after the selection
-    uint32_t nmv = 0;
-    for (uint32_t c0 = 0; c0 < np; c0 += FUSED_THREADS) {
-        uint32_t i = c0 + tid;
-        bool mv = false;
-        uint32_t s = 0, t = 0;
-        if (i < np) {
-            uint64_t key = skey[i];
-            s = (uint32_t)(key >> L.sh_s) & L.kmask;
-            t = (uint32_t)(key >> L.sh_t) & L.kmask;
-            uint32_t x = s < t ? s : t, y = s < t ? t : s;
-            uint64_t pa = ((uint64_t)x << kb) | y, pb = ((uint64_t)y << kb) | x;
-            uint32_t as = lower_pair(skey, np, L.sh_t, pa);
-            uint32_t al = lower_pair(skey, np, L.sh_t, pa + 1) - as;
-            uint32_t bs = lower_pair(skey, np, L.sh_t, pb);
-            unsigned long long bst = sbest[al ? as : bs];
-            if (bst) {
-                uint32_t istar = (uint32_t)bst;
-                uint32_t d = (uint32_t)(bst >> 32) - 1;
-                uint32_t jstar = d - istar;
-                mv = (s == x) ? (i - as < istar) : (i - bs < jstar);
+        __syncthreads();
+        const unsigned long long bst = sbest;
+        uint32_t istar = 0, jstar = 0;
+        if (bst) {
+            istar = (uint32_t)bst;
+            jstar = (uint32_t)(bst >> 32) - 1 - istar;
+        }
+        for (uint32_t c0 = 0; c0 < L; c0 += PAIR_THREADS) {
+            const uint32_t i = c0 + tid;
+            const bool mv = i < L && (i < nA ? i < istar : i - nA < jstar);
+            const uint32_t u = i < L ? (uint32_t)(skey[i] & 0x7FFFFFFFu) : 0u;
+            if (mv) part[u] = i < nA ? y : x;
+            const uint32_t pos = warp_agg_append(nmov, mv);
+            if (mv) mlist[pos] = u;
+        }
+        if (tid == 0 && bst) {
+            const int64_t wa = A.excl(istar), wb = Bv.excl(jstar);
+            if (wa != wb) {
+                atomic_add_i64(&dbw_g[x], wb - wa);
+                atomic_add_i64(&dbw_g[y], wa - wb);
             }
         }
-        uint32_t tot;
-        uint32_t incl = block_incl_scan_n<uint32_t, FUSED_THREADS>(mv ? 1u : 0u, wsum, &tot);
-        if (mv) {
-            uint32_t u = sval[i];
-            mlist[nmv + incl - 1] = u;
-            part[u] = t;
-            int64_t c = vwgt[u];
-            atomicAdd((unsigned long long *)&dbw[s], (unsigned long long)(-c));
-            atomicAdd((unsigned long long *)&dbw[t], (unsigned long long)c);
-        }
-        nmv += tot;
-    }
-    __syncthreads();
-    // (2) movers appended to the global mover list (their nets are updated later)
-    __shared__ uint32_t mbase;
-    if (tid == 0) mbase = nmv ? atomicAdd(moves, nmv) : 0u;
-    __syncthreads();
-    for (uint32_t i = tid; i < nmv; i += FUSED_THREADS) mlist_g[mbase + i] = mlist[i];
-    __syncthreads();
-    for (uint32_t b = tid; b < k; b += FUSED_THREADS) {
-        int64_t d = dbw[b] + dbw_g[b];
-        if (d) bw[b] += d;
+        __syncthreads();  // the arrays are reused by the next pair
     }
 }
 
@@ -1204,6 +1238,7 @@ struct RefineBufs {
     void *nr;  // NetRec<KW>[m]
     int64_t *f, *bw;
     uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow, *mlist;
+    uint32_t *pc, *pbase, *pcur, *spairs, *seg;  // per-pair proposal counts, segments of over-budget pairs
     int64_t *dbw_g;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt, *seg_start, *seg_end;
@@ -1232,6 +1267,11 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.seg_end = A.alloc<uint32_t>((size_t)k * k);
     B.best = A.alloc<unsigned long long>((size_t)k * k);
     B.pw = A.alloc<uint32_t>((size_t)k * k);
+    B.pc = A.alloc<uint32_t>((size_t)k * k);
+    B.pbase = A.alloc<uint32_t>((size_t)k * k);
+    B.pcur = A.alloc<uint32_t>((size_t)k * k);
+    B.spairs = A.alloc<uint32_t>((size_t)k * k);
+    B.seg = A.alloc<uint32_t>(n);
     B.slow = A.alloc<uint32_t>(n);
     B.mlist = A.alloc<uint32_t>(n);
     B.heavy = A.alloc<uint32_t>(n);
@@ -1293,12 +1333,12 @@ void objective(const hgp_hg &h, uint32_t k, const uint32_t *part, int64_t *obj, 
 
 template <int KW>
 static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj,
-                     int64_t *bw_out, Arena &A, hipStream_t st) {
+                     int64_t *bw_out, Arena &A, hipStream_t st, int64_t W_known) {
     const uint32_t n = h.n, m = h.m, k = prm.k;
     size_t mk = A.mark();
     RefineBufs B;
     plan(A, n, m, k, B);
-    const int64_t W = total_weight(h.vwgt, n, A, st);
+    const int64_t W = W_known >= 0 ? W_known : total_weight(h.vwgt, n, A, st);
     const int64_t lmax = ((int64_t)(prm.eps_den + prm.eps_num) * ((W + k - 1) / k)) / (int64_t)prm.eps_den;
     const uint64_t mseed = mix64(prm.seed);
     // device scalars: ntouched and nlong are adjacent so one memset clears both
@@ -1347,13 +1387,22 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     uint32_t *ccnt = B.scal + 20;  // [NDEG] candidates per class in the current sub-round
 
     const int kb = bits_for(k - 1), ub = bits_for(n ? n - 1 : 0);
-    uint32_t *abort = B.scal + 15;  // [2]: flag, sub-round that raised it (scal[16])
-    HGP_CHECK_HIP(hipMemsetAsync(abort, 0, sizeof(uint32_t) * 2, st));
+    // abort word: 1 + the sub-round whose selection handed a pair to the
+    // device-wide path (0: none); later kernels of the round skip their work
+    uint32_t *abort = B.scal + 15;
+    uint32_t *nsp = B.scal + 25;  // over-budget pairs of the sub-round
+    // all per-sub-round state starts at zero (afterwards the first kernel of
+    // each sub-round clears it)
+    HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 32, st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.pw, 0, sizeof(uint32_t) * k * k, st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.pc, 0, sizeof(uint32_t) * k * k, st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.dbw_g, 0, sizeof(int64_t) * k, st));
+    const SubReset zr{B.scal, B.pw, B.pc, k * k, k, B.bw, B.dbw_g};
+    const uint32_t pair_blocks = std::min<uint32_t>(k * (k - 1) / 2, 1024u);
 
-    // Device-wide selection of the slow pairs of sub-round (r, s): only after
-    // the one-workgroup path declined (its count exceeded FUSED_MAX or the key
-    // did not fit 64 bits).  The counts are read back here (the host has
-    // synchronised).
+    // Device-wide selection of the pairs that sub-round (r, s) handed over
+    // (more than PAIR_MAX proposals in one pair).  The counts are read back
+    // here (the host has synchronised).
     auto slow_path = [&](uint32_t ns, uint32_t G) {
         const int gb = bits_for(G);
         KeyLayout L;
@@ -1437,16 +1486,14 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     // One sub-round, entirely on the device (no host round trip).
     auto subround = [&](uint32_t r, uint32_t s) {
         const uint32_t stamp = 1 + r * S + s;
-        k_lp_reset<<<grid_for((size_t)k * k, BLOCK, 64), BLOCK, 0, st>>>(B.scal, B.pw, k * k, B.dbw_g, k);
-        HGP_LAUNCH_CHECK();
         const GainArgs<KW> ga{h.inc_off, h.inc, h.vwgt, (const NetRec<KW> *)B.nr, part, B.bw, B.bcnt, lmax, mseed,
-                              level, r, s, S, n, B.prop_t, B.prop_g, B.plist, nprop, gmax, B.pw, k, abort};
+                              level, r, s, S, n, B.prop_t, B.prop_g, B.plist, nprop, gmax, B.pw, B.pc, k, abort};
         if (cand_per == 8)
             k_lp_cands<8><<<cand_blocks, BLOCK, 0, st>>>(h.inc_off, B.bcnt, n, mseed, level, r, s, S, cl, ccnt,
-                                                         B.dlists, abort);
+                                                         B.dlists, zr, abort);
         else
             k_lp_cands<1><<<cand_blocks, BLOCK, 0, st>>>(h.inc_off, B.bcnt, n, mseed, level, r, s, S, cl, ccnt,
-                                                         B.dlists, abort);
+                                                         B.dlists, zr, abort);
         HGP_LAUNCH_CHECK();
         if (accounting(KID_GAINS)) {
             Timing &T = timing();
@@ -1464,16 +1511,20 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             k_gains_hub<KW><<<hub_blocks, HUB_THREADS, 0, st>>>(ga, B.dlists + cl.off[3], ccnt + 3);
             HGP_LAUNCH_CHECK();
         }
+        k_pair_plan<<<1, PLAN_THREADS, 0, st>>>(B.pw, B.pc, k, B.bw, lmax, B.pbase, B.pcur, B.spairs, nsp, ccnt,
+                                                abort);
+        HGP_LAUNCH_CHECK();
         {  // pairs whose whole move sets are feasible: applied directly
             TimedLaunch tl(KID_LP_FAST, st);
             k_lp_fast<<<fast_blocks, BLOCK, 0, st>>>(B.plist, nprop, B.prop_t, B.pw, k, h.vwgt, part, B.bw, lmax,
-                                                         B.dbw_g, B.mlist, nmov, B.slow, nslow, abort);
+                                                     B.dbw_g, B.mlist, nmov, B.pbase, B.pcur, B.seg, abort);
             HGP_LAUNCH_CHECK();
         }
-        {  // the other pairs: sorted two-pointer walk in one workgroup
-            TimedLaunch tl(KID_LP_FUSED, st);
-            k_lp_fused<<<1, FUSED_THREADS, 0, st>>>(B.slow, nslow, B.dbw_g, B.prop_t, B.prop_g, gmax, kb, ub, abort, s,
-                                                    k, h.vwgt, h.inc_off, h.inc, part, B.bw, lmax, B.mlist, nmov);
+        {  // the other pairs: sorted two-pointer walk, a workgroup per pair
+            TimedLaunch tl(KID_LP_PAIRS, st);
+            k_lp_pairs<<<pair_blocks, PAIR_THREADS, 0, st>>>(B.spairs, nsp, B.pbase, B.pc, B.seg, k, B.prop_g, h.vwgt,
+                                                             part, B.bw, lmax, B.dbw_g, B.mlist, nmov, B.slow, nslow,
+                                                             abort, s);
             HGP_LAUNCH_CHECK();
         }
         update(stamp);
@@ -1482,24 +1533,24 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     for (uint32_t r = 0; r < prm.lp_rounds; ++r) {
         HGP_CHECK_HIP(hipMemsetAsync(moves, 0, sizeof(uint32_t), st));
         for (uint32_t s = 0; s < S; ++s) subround(r, s);
+        uint32_t hv[17];
         for (;;) {
-            uint32_t hv[17];
             HGP_CHECK_HIP(hipMemcpyAsync(hv, B.scal, sizeof(hv), hipMemcpyDeviceToHost, st));
             stream_sync(st);
             if (!hv[15]) break;
-            // sub-round hv[16] declined in the one-workgroup selection: finish
-            // it device-wide, then replay the remaining sub-rounds of the round
-            const uint32_t s0 = hv[16];
-            HGP_CHECK_HIP(hipMemsetAsync(abort, 0, sizeof(uint32_t) * 2, st));
+            // sub-round hv[15] - 1 handed pairs to the device-wide path: finish
+            // it there, then replay the remaining sub-rounds of the round
+            const uint32_t s0 = hv[15] - 1;
+            HGP_CHECK_HIP(hipMemsetAsync(abort, 0, sizeof(uint32_t), st));
             slow_path(hv[13], hv[1]);
             update(1 + r * S + s0);
             for (uint32_t s = s0 + 1; s < S; ++s) subround(r, s);
         }
-        uint32_t mv = 0;
-        HGP_CHECK_HIP(hipMemcpyAsync(&mv, moves, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        stream_sync(st);
-        if (mv == 0) break;
+        if (hv[4] == 0) break;  // no move in the whole round
     }
+    // the last sub-round's block-weight changes
+    k_add_dbw<<<1, 256, 0, st>>>(B.bw, B.dbw_g, k);
+    HGP_LAUNCH_CHECK();
     if (obj) HGP_CHECK_HIP(hipMemcpyAsync(obj, B.f, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     if (bw_out) HGP_CHECK_HIP(hipMemcpyAsync(bw_out, B.bw, sizeof(int64_t) * k, hipMemcpyDeviceToDevice, st));
     stream_sync(st);
@@ -1507,12 +1558,12 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
 }
 
 void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj, int64_t *bw,
-               Arena &A, hipStream_t st) {
+               Arena &A, hipStream_t st, int64_t W_known) {
     switch ((prm.k + 63) / 64) {
-        case 1: refine_t<1>(h, prm, level, part, obj, bw, A, st); break;
-        case 2: refine_t<2>(h, prm, level, part, obj, bw, A, st); break;
-        case 3: refine_t<3>(h, prm, level, part, obj, bw, A, st); break;
-        default: refine_t<4>(h, prm, level, part, obj, bw, A, st); break;
+        case 1: refine_t<1>(h, prm, level, part, obj, bw, A, st, W_known); break;
+        case 2: refine_t<2>(h, prm, level, part, obj, bw, A, st, W_known); break;
+        case 3: refine_t<3>(h, prm, level, part, obj, bw, A, st, W_known); break;
+        default: refine_t<4>(h, prm, level, part, obj, bw, A, st, W_known); break;
     }
 }
 

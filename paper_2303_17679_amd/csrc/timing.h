@@ -14,7 +14,7 @@ enum KernelId : int {
     KID_RATE_BLOCK,    // k_rate_block (LDS and global tables)
     KID_GAINS,         // k_gains: LP best moves, all degree classes
     KID_LP_FAST,       // k_lp_fast: whole-pair approvals
-    KID_LP_FUSED,      // k_lp_fused: sorted pair walk, one workgroup
+    KID_LP_PAIRS,      // k_lp_pairs: sorted pair walk, a workgroup per over-budget block pair
     KID_LP_UPDATE,     // k_lp_update_movers: Lambda / Lambda1 / objective of touched nets
     KID_COUNT
 };

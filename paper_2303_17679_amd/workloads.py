@@ -91,12 +91,28 @@ class HostHypergraph:
         return self.inc[self.inc_off[v]:self.inc_off[v + 1]]
 
 
+def _stable_argsort(keys: np.ndarray) -> np.ndarray:
+    """Stable argsort of an integer array.  Large arrays go through torch's
+    multithreaded CPU radix sort (same permutation: a stable order is unique)."""
+    if keys.size < (1 << 22):
+        return np.argsort(keys, kind="stable")
+    import torch
+    _, idx = torch.sort(torch.from_numpy(np.ascontiguousarray(keys).astype(np.int64)), stable=True)
+    return idx.numpy()
+
+
+def _workers() -> int:
+    import os
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 def transpose(n: int, m: int, pin_off: np.ndarray, pins: np.ndarray):
     """Incidence CSR (nets ascending per vertex) from the pin CSR."""
     sizes = np.diff(pin_off.astype(np.int64))
     net_of_pin = np.repeat(np.arange(m, dtype=np.uint32), sizes)
-    order = np.argsort(pins, kind="stable")
+    order = _stable_argsort(pins)
     inc = net_of_pin[order].astype(np.uint32)
+    del order, net_of_pin
     deg = np.bincount(pins.astype(np.int64), minlength=n).astype(np.int64)
     inc_off = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(deg, out=inc_off[1:])
@@ -270,7 +286,7 @@ def rmat(scale: int = 24, edges: int = 2**28, a: float = 0.57, b: float = 0.19, 
                 d = d * 2 + db
         return s, d
 
-    for lo in range(0, edges, chunk):
+    def fill(lo):
         ids = np.arange(lo, min(edges, lo + chunk), dtype=np.int64)
         s, d = gen(ids, 0)
         attempt = 0
@@ -282,6 +298,12 @@ def rmat(scale: int = 24, edges: int = 2**28, a: float = 0.57, b: float = 0.19, 
             bad = bad[s2 == d2]
         src[lo:lo + ids.size] = s
         dst[lo:lo + ids.size] = d
+
+    # chunks are independent (counter-based draws); numpy releases the GIL in
+    # its element-wise loops, so threads run them in parallel
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(fill, range(0, edges, chunk)))
     perm_key = rng(seed, 0, np.arange(n))
     order = np.argsort(perm_key, kind="stable")
     relabel = np.empty(n, dtype=np.int64)

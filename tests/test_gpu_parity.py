@@ -54,6 +54,7 @@ CASES = [
     ("stencil32", 100, 11),   # two Lambda words per net
     ("rmat16", 128, 4),       # 2-pin nets with duplicate edges, two words
     ("random120k", 256, 6),   # four words per net
+    ("random120k", 2, 5),     # one block pair of more than 4096 proposals: device-wide selection and replay
     ("hugenets", 4, 9),       # hub ratings with nets of more than 2048 pins
 ]
 
@@ -166,6 +167,23 @@ def test_edge_cases(hgp, orc, case, k):
     part_o, f_o, _ = orc.partition(h, P_or)
     part, f, _ = H.partition(H.Hypergraph.from_host(h), P)
     assert f == f_o and np.array_equal(host(part), part_o)
+
+
+IP_CASES = ["random2k", "stencil16", "hugenets", "powerlaw20000", "random120k", "edge:isolated_and_single_pin",
+            "edge:duplicate_nets"]
+
+
+@pytest.mark.parametrize("name", IP_CASES)
+@pytest.mark.parametrize("k", [2, 7])
+def test_initial_partition_paths(hgp, orc, name, k):
+    """The greedy initial partition on whole inputs: up to 65536 vertices (and
+    2^20 pins) one workgroup builds the order, above that the device-wide
+    layer-by-layer path does (random120k)."""
+    H = hgp
+    h = EDGE[name[5:]]() if name.startswith("edge:") else make(name)
+    say(f"[ip {name} k={k}] n={h.n} p={h.p}")
+    ip = H.initial_partition(H.Hypergraph.from_host(h), k)
+    assert np.array_equal(host(ip), orc.greedy_ip(h, k))
 
 
 def test_invalid_inputs_rejected(hgp):
