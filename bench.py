@@ -29,6 +29,8 @@ WORKLOADS = {
     "powerlaw1m": "power-law hypergraph, seed 2, n=m=1,000,000, Zipf(2.1) net sizes in [2,1000], Zipf(2.3) "
                   "vertex degrees, net weights in [1,4], k=8, eps=0.03",
     "random10k": "random hypergraph, seed 1, n=m=10,000, net sizes in [2,8], k=2, eps=0.03",
+    "rmat24": "graph variant: R-MAT (a,b,c)=(0.57,0.19,0.19), seed 3, 2^24 vertices, 2^28 edges as 2-pin nets "
+              "(self-loops redrawn, duplicate edges kept), unit weights, k=128, eps=0.03",
     "batch": "4096 VLSI-like hypergraphs, seed 4: n log-uniform in [1e3, 2e5], m = 1.1 n, net size "
              "2+Geometric(0.4) capped at 50, 90% of pins within a 256-ID window around the net's anchor, vertex "
              "weights in [1,10], k uniform in {2,4,8}, eps=0.03; all partitioned by one hgp_partition_batch call",

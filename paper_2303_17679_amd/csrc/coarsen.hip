@@ -346,10 +346,13 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
 //   k_hub_huge    - one workgroup per job: its nets of more than HUB_BIG pins,
 //                   one at a time, deduplicated by a per-slot net stamp (no
 //                   other net of the job is in flight then);
-//   k_hub_argmax  - one workgroup per job: best target over the occupied
-//                   slots, which are reset, then published.
+//   k_hub_argmax  - one workgroup per slice of ARG_SLICE slots of a job's
+//                   table: the best target of the slice (used slots are
+//                   reset);
+//   k_hub_pick    - a wave per job: the best of its slices, published.
 // Tables start clean (the host clears the region once per pass) and are left
-// clean, so a job costs its distinct clusters, not its capacity.
+// clean.  No list of used slots is kept: a shared counter per job would be
+// one address that every insert of the job hits.
 // ---------------------------------------------------------------------------
 constexpr uint32_t HUB_CHUNK = BLOCK;
 constexpr uint32_t HUB_BIG = 2048;
@@ -359,7 +362,11 @@ struct HubJob {
     uint32_t u, lg;  // candidate, log2 of its table capacity
     uint32_t j0, j1; // its incidence range
     uint64_t off;    // first entry of its table in the region
+    uint32_t pbase, nslice;  // its argmax slices: partial results [pbase, pbase + nslice)
 };
+constexpr uint32_t ARG_SLICE = 4096;  // table slots per argmax workgroup
+constexpr uint32_t HUB_WORK = 8192;   // about this many pins per insert item
+constexpr uint32_t HUB_MIN_NETS = 32; // but at least this many incident nets
 struct HubItem {
     uint32_t job, j0, j1, pad;
 };
@@ -375,8 +382,7 @@ __global__ __launch_bounds__(BLOCK) void k_hub_info(RateArgs a, const uint32_t *
 }
 
 // Insert cluster C of job J into its table; returns the slot.
-__device__ inline uint32_t hub_slot(uint32_t *keys, uint32_t *occ, uint32_t *nocc, const HubJob &J, uint32_t job,
-                                    uint32_t C) {
+__device__ inline uint32_t hub_slot(uint32_t *keys, const HubJob &J, uint32_t C) {
     const uint32_t mask = (1u << J.lg) - 1u;
     uint32_t *kt = keys + J.off;
     uint32_t slot = slot_hash(C, (int)J.lg);
@@ -385,85 +391,113 @@ __device__ inline uint32_t hub_slot(uint32_t *keys, uint32_t *occ, uint32_t *noc
         if (k == C) return slot;
         if (k == NONE) {
             const uint32_t old = atomicCAS(&kt[slot], NONE, C);
-            if (old == NONE) {
-                occ[J.off + atomicAdd(&nocc[job], 1u)] = slot;
-                return slot;
-            }
-            if (old == C) return slot;
+            if (old == NONE || old == C) return slot;
         }
         slot = (slot + 1) & mask;
     }
 }
 
+// Nets of more than LANE_NET pins are taken in windows of whole nets with at
+// most HUB_WIN pins together; the workgroup spreads each window's pins over
+// all its threads, and a (net, cluster) set in LDS lets the first pin of a
+// net in a cluster claim the pair.
+constexpr uint32_t HUB_WIN = 2048;
 __global__ __launch_bounds__(BLOCK) void k_hub_insert(RateArgs a, const HubJob *jobs, const HubItem *items,
-                                                      uint32_t nitems, uint32_t *keys, uint64_t *R, uint32_t *occ,
-                                                      uint32_t *nocc) {
-    __shared__ uint32_t set[HUB_SET];
+                                                      uint32_t nitems, uint32_t *keys, uint64_t *R) {
+    __shared__ unsigned long long set[HUB_SET];  // (net index in the item << 32) | cluster
     __shared__ uint16_t setocc[HUB_SET];
-    __shared__ uint32_t nset, nbig;
-    __shared__ uint32_t big[HUB_CHUNK];
-    for (uint32_t q = threadIdx.x; q < HUB_SET; q += BLOCK) set[q] = NONE;
+    __shared__ uint32_t nset;
+    __shared__ uint32_t bstart[HUB_CHUNK + 1];  // first flattened pin of each listed net
+    __shared__ uint32_t bpin[HUB_CHUNK];        // its first pin in the pin array
+    __shared__ uint64_t bsc[HUB_CHUNK];         // its score
+    __shared__ uint32_t wsum[BLOCK / WAVE];
+    constexpr unsigned long long EMPTY = ~0ull;
+    for (uint32_t q = threadIdx.x; q < HUB_SET; q += BLOCK) set[q] = EMPTY;
+    if (threadIdx.x == 0) nset = 0;
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const HubItem I = items[it];
         const HubJob J = jobs[I.job];
         const uint32_t u = J.u;
-        if (threadIdx.x == 0) { nbig = 0; nset = 0; }
         __syncthreads();
-        // small nets: one thread each; big ones are listed for the workgroup
+        // small nets: one thread each; the others are listed in incidence order
         const uint32_t j = I.j0 + threadIdx.x;
+        uint32_t bsz = 0, e = 0, b = 0;
         if (j < I.j1) {
-            const uint32_t e = a.inc[j];
-            const uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
+            e = a.inc[j];
+            b = a.pin_off[e];
+            const uint32_t sz = a.pin_off[e + 1] - b;
             if (sz >= 2 && sz <= LANE_NET) {
                 rate_small_net(a, u, b, sz, a.nscore[e], [&](uint32_t C, uint64_t sc) {
-                    const uint32_t slot = hub_slot(keys, occ, nocc, J, I.job, C);
+                    const uint32_t slot = hub_slot(keys, J, C);
                     atomicAdd((unsigned long long *)&R[J.off + slot], (unsigned long long)sc);
                 });
             } else if (sz > LANE_NET && sz <= HUB_BIG) {
-                big[atomicAdd(&nbig, 1u)] = e;
+                bsz = sz;
             }
         }
+        uint32_t tot_n, tot_p;
+        const uint32_t rank = block_incl_scan<uint32_t>(bsz ? 1u : 0u, wsum, &tot_n) - (bsz ? 1u : 0u);
+        const uint32_t pre = block_incl_scan<uint32_t>(bsz, wsum, &tot_p) - bsz;
+        if (bsz) {
+            bstart[rank] = pre;
+            bpin[rank] = b;
+            bsc[rank] = a.nscore[e];
+        }
+        if (threadIdx.x == 0) bstart[tot_n] = tot_p;
         __syncthreads();
-        const uint32_t nb = nbig;
-        for (uint32_t q = 0; q < nb; ++q) {
-            const uint32_t e = big[q];
-            const uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
-            const uint64_t sc = a.nscore[e];
-            for (uint32_t x = threadIdx.x; x < sz; x += BLOCK) {
-                const uint32_t v = a.pins[b + x];
+        const uint32_t nb = tot_n;
+        for (uint32_t w0 = 0; w0 < nb;) {
+            // the window: nets w0 .. w1-1, at least one, at most HUB_WIN pins
+            uint32_t lo = w0 + 1, hi = nb;  // largest w1 with bstart[w1] - bstart[w0] <= HUB_WIN
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (bstart[mid] - bstart[w0] <= HUB_WIN) lo = mid; else hi = mid - 1;
+            }
+            const uint32_t w1 = lo;
+            for (uint32_t x = bstart[w0] + threadIdx.x; x < bstart[w1]; x += BLOCK) {
+                uint32_t tl = w0, th = w1 - 1;  // net of flattened pin x
+                while (tl < th) {
+                    const uint32_t mid = (tl + th + 1) >> 1;
+                    if (bstart[mid] <= x) tl = mid; else th = mid - 1;
+                }
+                const uint32_t v = a.pins[bpin[tl] + (x - bstart[tl])];
                 if (v == u) continue;
                 const uint32_t C = a.rep[v];
                 bool fresh = true;
-                if (a.dedup) {  // first pin of the net in cluster C claims it
-                    uint32_t h = slot_hash(C, 12);
+                if (a.dedup) {  // first pin of the net in cluster C claims the pair
+                    const unsigned long long key = ((unsigned long long)tl << 32) | C;
+                    uint32_t h = slot_hash(C ^ (tl * 0x9E3779B9u), 12);
                     for (;;) {
-                        const uint32_t k = set[h];
-                        if (k == C) { fresh = false; break; }
-                        if (k == NONE) {
-                            const uint32_t old = atomicCAS(&set[h], NONE, C);
-                            if (old == NONE) { setocc[atomicAdd(&nset, 1u)] = (uint16_t)h; break; }
-                            if (old == C) { fresh = false; break; }
+                        const unsigned long long k = set[h];
+                        if (k == key) { fresh = false; break; }
+                        if (k == EMPTY) {
+                            const unsigned long long old = atomicCAS(&set[h], EMPTY, key);
+                            if (old == EMPTY) { setocc[atomicAdd(&nset, 1u)] = (uint16_t)h; break; }
+                            if (old == key) { fresh = false; break; }
                         }
                         h = (h + 1) & (HUB_SET - 1);
                     }
                 }
                 if (fresh) {
-                    const uint32_t slot = hub_slot(keys, occ, nocc, J, I.job, C);
-                    atomicAdd((unsigned long long *)&R[J.off + slot], (unsigned long long)sc);
+                    const uint32_t slot = hub_slot(keys, J, C);
+                    atomicAdd((unsigned long long *)&R[J.off + slot], (unsigned long long)bsc[tl]);
                 }
             }
             __syncthreads();
-            const uint32_t ns = nset;
-            for (uint32_t x = threadIdx.x; x < ns; x += BLOCK) set[setocc[x]] = NONE;
-            __syncthreads();
-            if (threadIdx.x == 0) nset = 0;
-            __syncthreads();
+            if (a.dedup) {
+                const uint32_t ns = nset;
+                for (uint32_t x = threadIdx.x; x < ns; x += BLOCK) set[setocc[x]] = EMPTY;
+                __syncthreads();
+                if (threadIdx.x == 0) nset = 0;
+                __syncthreads();
+            }
+            w0 = w1;
         }
     }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_hub_huge(RateArgs a, const HubJob *jobs, uint32_t njobs, uint32_t *keys,
-                                                    uint32_t *stamp, uint64_t *R, uint32_t *occ, uint32_t *nocc) {
+                                                    uint32_t *stamp, uint64_t *R) {
     for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
         const HubJob J = jobs[jb];
         for (uint32_t j = J.j0; j < J.j1; ++j) {
@@ -474,7 +508,7 @@ __global__ __launch_bounds__(BLOCK) void k_hub_huge(RateArgs a, const HubJob *jo
             for (uint32_t x = threadIdx.x; x < sz; x += BLOCK) {
                 const uint32_t v = a.pins[b + x];
                 if (v == J.u) continue;
-                const uint32_t slot = hub_slot(keys, occ, nocc, J, jb, a.rep[v]);
+                const uint32_t slot = hub_slot(keys, J, a.rep[v]);
                 if (!a.dedup || atomicExch(&stamp[J.off + slot], e) != e)
                     atomicAdd((unsigned long long *)&R[J.off + slot], (unsigned long long)sc);
             }
@@ -483,20 +517,23 @@ __global__ __launch_bounds__(BLOCK) void k_hub_huge(RateArgs a, const HubJob *jo
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_hub_argmax(RateArgs a, const HubJob *jobs, uint32_t njobs,
-                                                      uint32_t *keys, uint32_t *stamp, uint64_t *R,
-                                                      const uint32_t *occ, uint32_t *nocc) {
+__global__ __launch_bounds__(BLOCK) void k_hub_argmax(RateArgs a, const HubJob *jobs, const HubItem *aitems,
+                                                      uint32_t naitems, uint32_t *keys, uint32_t *stamp, uint64_t *R,
+                                                      uint64_t *partR, uint32_t *partC) {
     __shared__ uint64_t redR[BLOCK / WAVE];
     __shared__ uint32_t redC[BLOCK / WAVE];
-    for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
-        const HubJob J = jobs[jb];
+    for (uint32_t it = blockIdx.x; it < naitems; it += gridDim.x) {
+        const HubItem I = aitems[it];
+        const HubJob J = jobs[I.job];
         const uint32_t u = J.u;
-        const uint32_t no = nocc[jb];
+        const uint32_t cap = 1u << J.lg;
+        const uint32_t i0 = I.j0 * ARG_SLICE, i1 = cap < i0 + ARG_SLICE ? cap : i0 + ARG_SLICE;
         uint64_t bR = 0;
         uint32_t bC = NONE;
-        for (uint32_t i = threadIdx.x; i < no; i += BLOCK) {
-            const uint64_t s = J.off + occ[J.off + i];
+        for (uint32_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
+            const uint64_t s = J.off + i;
             const uint32_t C = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (C == NONE) continue;
             const uint64_t rc = __hip_atomic_load(&R[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             keys[s] = NONE;
             stamp[s] = NONE;
@@ -515,10 +552,32 @@ __global__ __launch_bounds__(BLOCK) void k_hub_argmax(RateArgs a, const HubJob *
         if (threadIdx.x == 0) {
             for (int q = 1; q < BLOCK / WAVE; ++q)
                 if (better_lazy(a, redR[q], redC[q], bR, bC)) { bR = redR[q]; bC = redC[q]; }
-            publish(a, u, bC);
-            nocc[jb] = 0;
+            partR[J.pbase + I.j0] = bR;
+            partC[J.pbase + I.j0] = bC;
         }
         __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_hub_pick(RateArgs a, const HubJob *jobs, uint32_t njobs,
+                                                    const uint64_t *partR, const uint32_t *partC) {
+    const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nw = gridDim.x * BLOCK / WAVE;
+    for (uint32_t jb = wid; jb < njobs; jb += nw) {
+        const HubJob J = jobs[jb];
+        uint64_t bR = 0;
+        uint32_t bC = NONE;
+        for (uint32_t q = __lane_id(); q < J.nslice; q += WAVE) {
+            const uint64_t r = partR[J.pbase + q];
+            const uint32_t c = partC[J.pbase + q];
+            if (better_lazy(a, r, c, bR, bC)) { bR = r; bC = c; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t oR = __shfl_xor(bR, o, 64);
+            const uint32_t oC = __shfl_xor(bC, o, 64);
+            if (better_lazy(a, oR, oC, bR, bC)) { bR = oR; bC = oC; }
+        }
+        if (__lane_id() == 0) publish(a, J.u, bC);
     }
 }
 
@@ -631,6 +690,36 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, con
             if ((int)__lane_id() == h) b = t;
         }
         if (u < n) bound[u] = b > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)b;
+    }
+}
+
+// The same bound with a wave per vertex, for levels whose average degree is
+// high (coarse levels): every vertex is summed by all 64 lanes at once.
+__global__ __launch_bounds__(BLOCK) void k_vertex_b_wave(const uint32_t *pin_off, const uint32_t *inc_off,
+                                                         const uint32_t *inc, uint32_t n, uint32_t m,
+                                                         uint32_t *bound, uint32_t *maxsz) {
+    uint32_t mx = 0;
+    for (uint32_t e = blockIdx.x * BLOCK + threadIdx.x; e < m; e += gridDim.x * BLOCK) {
+        const uint32_t sz = pin_off[e + 1] - pin_off[e];
+        mx = sz > mx ? sz : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_xor(mx, o, 64);
+        mx = y > mx ? y : mx;
+    }
+    if (__lane_id() == 0 && mx) atomicMax(maxsz, mx);
+    const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nw = gridDim.x * BLOCK / WAVE;
+    for (uint32_t u = wid; u < n; u += nw) {
+        const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
+        uint64_t t = 0;
+        for (uint32_t j = j0 + __lane_id(); j < j1; j += WAVE) {
+            const uint32_t e = inc[j];
+            const uint32_t sz = pin_off[e + 1] - pin_off[e];
+            if (sz >= 2) t += sz - 1;
+        }
+        t = wave_sum(t);
+        if (__lane_id() == 0) bound[u] = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
     }
 }
 
@@ -802,11 +891,14 @@ struct CoarsenBufs {
     HubJob *hub_jobs;
     HubItem *hub_items;
     size_t hub_items_cap;
-    uint32_t *hub_nocc;
+    HubItem *hub_aitems;     // argmax slices of one batch
+    size_t hub_aitems_cap;
+    uint64_t *hub_partR;     // best target per slice
+    uint32_t *hub_partC;
 };
 
-// One global-table entry: key, stamp, occupancy slot (4 B each), rating (8 B).
-constexpr size_t GENTRY_BYTES = 20;
+// One global-table entry: key, stamp (4 B each), rating (8 B).
+constexpr size_t GENTRY_BYTES = 16;
 
 static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, uint32_t S, CoarsenBufs &B) {
     B.nscore = A.alloc<uint64_t>(m);
@@ -829,9 +921,15 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, uint32_t S, Coars
     B.vals_alt = A.alloc<uint32_t>(n);
     B.hub_info = A.alloc<uint4>(n);
     B.hub_jobs = A.alloc<HubJob>(n);
-    B.hub_items_cap = (size_t)p / HUB_CHUNK + n + 1;
+    B.hub_items_cap = (size_t)p / HUB_MIN_NETS + n + 1;
     B.hub_items = A.alloc<HubItem>(B.hub_items_cap);
-    B.hub_nocc = A.alloc<uint32_t>(n);
+    // argmax slices of one batch: a batch's tables fit the region (at most
+    // 2^26 entries), so it has at most one slice per job plus one per
+    // ARG_SLICE entries of the region
+    B.hub_aitems_cap = (size_t)n + ((size_t)1 << 26) / ARG_SLICE + 1;
+    B.hub_aitems = A.alloc<HubItem>(B.hub_aitems_cap);
+    B.hub_partR = A.alloc<uint64_t>(B.hub_aitems_cap);
+    B.hub_partC = A.alloc<uint32_t>(B.hub_aitems_cap);
     // global (hub) rating tables: room for 16 tables of the largest possible
     // capacity (>= 1.5 n), more (up to 4 p entries, 2^26) when the workspace
     // has it, always leaving room for the temporaries the pass allocates
@@ -877,8 +975,12 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     k_net_score<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.nwgt, m, B.nscore);
     HGP_LAUNCH_CHECK();
     HGP_CHECK_HIP(hipMemsetAsync(B.counts, 0, sizeof(uint32_t) * (S * NCLASS + 2), st));
-    k_vertex_b<<<grid_for(std::max(n, m), BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, m,
-                                                                             B.bound, B.counts + S * NCLASS + 1);
+    if ((uint64_t)h.p >= (uint64_t)16 * n)  // average degree of at least 16: a wave per vertex
+        k_vertex_b_wave<<<grid_for((size_t)std::max(n, m) * WAVE, BLOCK, 4 * FILL_BLOCKS), BLOCK, 0, st>>>(
+            h.pin_off, h.inc_off, h.inc, n, m, B.bound, B.counts + S * NCLASS + 1);
+    else
+        k_vertex_b<<<grid_for(std::max(n, m), BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+            h.pin_off, h.inc_off, h.inc, n, m, B.bound, B.counts + S * NCLASS + 1);
     HGP_LAUNCH_CHECK();
     k_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
                                                                  B.tsum, B.counts, B.cursor, B.lists, false);
@@ -891,7 +993,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     // hub tables: the whole region, cleared once; every job leaves its slots clean
     const size_t E = B.greg_bytes / GENTRY_BYTES;
     uint64_t *gR = (uint64_t *)B.greg;
-    uint32_t *gkeys = (uint32_t *)(B.greg + 8 * E), *gstamp = gkeys + E, *gocc = gstamp + E;
+    uint32_t *gkeys = (uint32_t *)(B.greg + 8 * E), *gstamp = gkeys + E;
     bool any_hub = false;
     for (uint32_t r = 0; r < S; ++r) any_hub |= counts[r * NCLASS + NCLASS - 1] > 0;
     if (any_hub) {
@@ -908,9 +1010,10 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
         stream_sync(st);
         // all batches planned at once: jobs of a batch share the region
         std::vector<HubJob> jobs;
-        std::vector<HubItem> items;
-        std::vector<uint32_t> bj{0}, bi{0};  // batch boundaries in jobs / items
+        std::vector<HubItem> items, aitems;
+        std::vector<uint32_t> bj{0}, bi{0}, ba{0};  // batch boundaries in jobs / items / argmax slices
         size_t used = 0;
+        uint32_t pb = 0;  // partial results of the batch so far
         for (uint32_t i = 0; i < cntc; ++i) {
             const uint4 f = info[i];
             if (f.w == NONE) continue;  // joined by another vertex earlier in the pass
@@ -920,16 +1023,28 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             if (used + cap > E) {
                 bj.push_back((uint32_t)jobs.size());
                 bi.push_back((uint32_t)items.size());
+                ba.push_back((uint32_t)aitems.size());
                 used = 0;
+                pb = 0;
             }
             const uint32_t jid = (uint32_t)(jobs.size() - bj.back());  // index within the batch
-            jobs.push_back(HubJob{f.x, lg, f.y, f.z, used});
-            for (uint32_t j = f.y; j < f.z; j += HUB_CHUNK)
-                items.push_back(HubItem{jid, j, std::min(j + HUB_CHUNK, f.z), 0});
+            // the argmax reads the whole table (slots left empty are skipped)
+            const uint32_t nsl = (uint32_t)((cap + ARG_SLICE - 1) / ARG_SLICE);
+            jobs.push_back(HubJob{f.x, lg, f.y, f.z, used, pb, nsl});
+            for (uint32_t q = 0; q < nsl; ++q) aitems.push_back(HubItem{jid, q, 0, 0});
+            pb += nsl;
+            // insert items of about HUB_WORK pins (by the average net size)
+            const uint32_t deg = f.z - f.y;
+            const uint64_t avg = deg ? std::max<uint64_t>(1, (uint64_t)f.w / deg) : 1;
+            const uint32_t per = (uint32_t)std::min<uint64_t>(
+                HUB_CHUNK, std::max<uint64_t>(HUB_MIN_NETS, HUB_WORK / avg));
+            for (uint32_t j = f.y; j < f.z; j += per)
+                items.push_back(HubItem{jid, j, std::min(j + per, f.z), 0});
             used += cap;
         }
         bj.push_back((uint32_t)jobs.size());
         bi.push_back((uint32_t)items.size());
+        ba.push_back((uint32_t)aitems.size());
         if (jobs.empty()) return;
         if (items.size() > B.hub_items_cap || jobs.size() > n) throw Error{HGP_E_WORKSPACE};
         HGP_CHECK_HIP(hipMemcpyAsync(B.hub_jobs, jobs.data(), sizeof(HubJob) * jobs.size(), hipMemcpyHostToDevice,
@@ -937,18 +1052,23 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
         HGP_CHECK_HIP(hipMemcpyAsync(B.hub_items, items.data(), sizeof(HubItem) * items.size(),
                                      hipMemcpyHostToDevice, st));
         for (size_t b = 0; b + 1 < bj.size(); ++b) {
-            const uint32_t nj = bj[b + 1] - bj[b], ni = bi[b + 1] - bi[b];
+            const uint32_t nj = bj[b + 1] - bj[b], ni = bi[b + 1] - bi[b], na = ba[b + 1] - ba[b];
             if (!nj) continue;
+            if (na > B.hub_aitems_cap) throw Error{HGP_E_WORKSPACE};
             const HubJob *jb = B.hub_jobs + bj[b];
-            HGP_CHECK_HIP(hipMemsetAsync(B.hub_nocc, 0, sizeof(uint32_t) * nj, st));
-            k_hub_insert<<<std::min(ni, 8192u), BLOCK, 0, st>>>(a, jb, B.hub_items + bi[b], ni, gkeys, gR, gocc,
-                                                                B.hub_nocc);
+            HGP_CHECK_HIP(hipMemcpyAsync(B.hub_aitems, aitems.data() + ba[b], sizeof(HubItem) * na,
+                                         hipMemcpyHostToDevice, st));
+            k_hub_insert<<<std::min(ni, 8192u), BLOCK, 0, st>>>(a, jb, B.hub_items + bi[b], ni, gkeys, gR);
             HGP_LAUNCH_CHECK();
             if (huge_nets) {
-                k_hub_huge<<<std::min(nj, 8192u), BLOCK, 0, st>>>(a, jb, nj, gkeys, gstamp, gR, gocc, B.hub_nocc);
+                k_hub_huge<<<std::min(nj, 8192u), BLOCK, 0, st>>>(a, jb, nj, gkeys, gstamp, gR);
                 HGP_LAUNCH_CHECK();
             }
-            k_hub_argmax<<<std::min(nj, 8192u), BLOCK, 0, st>>>(a, jb, nj, gkeys, gstamp, gR, gocc, B.hub_nocc);
+            k_hub_argmax<<<std::min(na, 8192u), BLOCK, 0, st>>>(a, jb, B.hub_aitems, na, gkeys, gstamp, gR,
+                                                                B.hub_partR, B.hub_partC);
+            HGP_LAUNCH_CHECK();
+            k_hub_pick<<<grid_for((size_t)nj * WAVE, BLOCK, 1024), BLOCK, 0, st>>>(a, jb, nj, B.hub_partR,
+                                                                                  B.hub_partC);
             HGP_LAUNCH_CHECK();
         }
         stream_sync(st);  // the uploads read the host vectors
@@ -976,6 +1096,10 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             uint32_t cntc = counts[r * NCLASS + c];
             if (!cntc) continue;
             const uint32_t *lst = B.lists + offs[r * NCLASS + c];
+            if (c == NCLASS - 1) {  // hub candidates: several kernels with host planning, not a timed one
+                hub_rate(a, lst, cntc);
+                continue;
+            }
             const int kid = c == 0 ? KID_RATE_G8 : c == 1 ? KID_RATE_G16 : c == 2 ? KID_RATE_G64 : KID_RATE_BLOCK;
             if (accounting(kid)) {
                 Timing &T = timing();
@@ -996,11 +1120,8 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                 case 2:
                     k_rate_group<64, 1024, 10><<<grid_for(cntc, BLOCK / 64, 8192), BLOCK, 0, st>>>(a, lst, cntc);
                     break;
-                case 3:
-                    k_rate_block<<<grid_for(cntc, 1, 8192), BLOCK, 0, st>>>(a, lst, cntc);
-                    break;
                 default:
-                    hub_rate(a, lst, cntc);
+                    k_rate_block<<<grid_for(cntc, 1, 8192), BLOCK, 0, st>>>(a, lst, cntc);
                     break;
             }
             HGP_LAUNCH_CHECK();

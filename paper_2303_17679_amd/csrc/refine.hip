@@ -482,6 +482,21 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
     }
 }
 
+// The same count with a wave per node, for levels whose average degree is
+// high (coarse levels).
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_init_bcnt_wave(const uint32_t *inc_off, const uint32_t *inc, uint32_t n,
+                                                          const NetRec<KW> *nr, uint32_t *bcnt) {
+    const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nw = gridDim.x * BLOCK / WAVE;
+    for (uint32_t u = wid; u < n; u += nw) {
+        const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
+        uint32_t t = 0;
+        for (uint32_t j = j0 + __lane_id(); j < j1; j += WAVE) t += popc_bits<KW>(nr[inc[j]].lam) > 1;
+        t = wave_sum(t);
+        if (__lane_id() == 0) bcnt[u] = t;
+    }
+}
+
 // Per-sub-round state (scalar counters, pair sums) back to zero, and the
 // previous sub-round's block-weight changes folded into the block weights.
 // Runs at the start of a sub-round, after every reader of that state.  The
@@ -1349,7 +1364,12 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     build_conn<KW>(h, part, B, st);
     block_weights(part, h.vwgt, n, k, B.bw, st);
     if (m) HGP_CHECK_HIP(hipMemsetAsync(B.tstamp, 0, sizeof(uint32_t) * m, st));
-    k_init_bcnt<KW><<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n, (const NetRec<KW> *)B.nr, B.bcnt);
+    if ((uint64_t)h.p >= (uint64_t)16 * n)  // average degree of at least 16: a wave per node
+        k_init_bcnt_wave<KW><<<grid_for((size_t)n * WAVE, BLOCK, 4 * FILL_BLOCKS), BLOCK, 0, st>>>(
+            h.inc_off, h.inc, n, (const NetRec<KW> *)B.nr, B.bcnt);
+    else
+        k_init_bcnt<KW><<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n,
+                                                                           (const NetRec<KW> *)B.nr, B.bcnt);
     HGP_LAUNCH_CHECK();
     // degree classes of the nodes (lanes per node 1 / 8 / 64)
     HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * NDEG, st));
