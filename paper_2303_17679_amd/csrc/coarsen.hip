@@ -496,6 +496,168 @@ __global__ __launch_bounds__(BLOCK) void k_hub_insert(RateArgs a, const HubJob *
     }
 }
 
+// ---------------------------------------------------------------------------
+// Hub jobs of moderate bound D (and levels without nets of more than HUB_BIG
+// pins): the rating is aggregated in LDS instead of a global table, one
+// workgroup per job with a table of LHUB_CAP slots.  The kernel can also
+// split the clusters into P partitions by a hash (a workgroup per (job,
+// partition), each reading all of the job's pins), but P = 1 is used: with
+// D <= LHUB_PART the table cannot fill (D bounds the distinct clusters), and
+// splitting costs more pin reads than the global table it replaces.  A table
+// that does fill marks the job, which is then rated on the global path.
+// ---------------------------------------------------------------------------
+constexpr int LHUB_THREADS = 512;
+constexpr uint32_t LHUB_CAP = 8192, LHUB_LG = 13;
+constexpr uint32_t LHUB_PART = 5461;  // clusters per partition at most (load 2/3)
+constexpr uint32_t LHUB_MAXP = 1;
+
+__device__ inline uint32_t lhub_part(uint32_t C, uint32_t P) {
+    return (uint32_t)(((uint64_t)(C * 0x85EBCA6Bu) * P) >> 32);
+}
+
+__global__ __launch_bounds__(LHUB_THREADS) void k_hub_lds(RateArgs a, const HubJob *jobs, const HubItem *litems,
+                                                          uint32_t nl, uint64_t *partR, uint32_t *partC,
+                                                          uint32_t *ovf_flag, uint32_t *ovf_list, uint32_t *ovf_cnt) {
+    __shared__ uint32_t tkey[LHUB_CAP];
+    __shared__ unsigned long long tR[LHUB_CAP];
+    __shared__ unsigned long long set[HUB_SET];  // (net index in the chunk << 32) | cluster
+    __shared__ uint16_t setocc[HUB_SET];
+    __shared__ uint32_t nset, ovf;
+    __shared__ uint32_t bstart[LHUB_THREADS + 1];
+    __shared__ uint32_t bpin[LHUB_THREADS];
+    __shared__ uint64_t bsc[LHUB_THREADS];
+    __shared__ uint32_t wsum[LHUB_THREADS / WAVE];
+    __shared__ uint64_t redR[LHUB_THREADS / WAVE];
+    __shared__ uint32_t redC[LHUB_THREADS / WAVE];
+    constexpr unsigned long long EMPTY = ~0ull;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t q = tid; q < HUB_SET; q += LHUB_THREADS) set[q] = EMPTY;
+    if (tid == 0) nset = 0;
+    for (uint32_t it = blockIdx.x; it < nl; it += gridDim.x) {
+        const HubItem I = litems[it];
+        const HubJob J = jobs[I.job];
+        const uint32_t u = J.u, P = J.lg, part = I.j0;
+        __syncthreads();
+        for (uint32_t q = tid; q < LHUB_CAP; q += LHUB_THREADS) { tkey[q] = NONE; tR[q] = 0; }
+        if (tid == 0) ovf = 0;
+        __syncthreads();
+        auto tins = [&](uint32_t C, uint64_t sc) {
+            uint32_t slot = slot_hash(C, LHUB_LG);
+            for (uint32_t probe = 0; probe < LHUB_CAP; ++probe) {
+                const uint32_t k = tkey[slot];
+                if (k == C) { atomicAdd(&tR[slot], (unsigned long long)sc); return; }
+                if (k == NONE) {
+                    const uint32_t old = atomicCAS(&tkey[slot], NONE, C);
+                    if (old == NONE || old == C) { atomicAdd(&tR[slot], (unsigned long long)sc); return; }
+                }
+                slot = (slot + 1) & (LHUB_CAP - 1);
+            }
+            ovf = 1;  // the table is full
+        };
+        for (uint32_t c0 = J.j0; c0 < J.j1; c0 += LHUB_THREADS) {
+            // nets of <= LANE_NET pins: one thread each; the others are listed
+            const uint32_t j = c0 + tid;
+            uint32_t bsz = 0, e = 0, b = 0;
+            if (j < J.j1) {
+                e = a.inc[j];
+                b = a.pin_off[e];
+                const uint32_t sz = a.pin_off[e + 1] - b;
+                if (sz >= 2 && sz <= LANE_NET) {
+                    rate_small_net(a, u, b, sz, a.nscore[e], [&](uint32_t C, uint64_t sc) {
+                        if (lhub_part(C, P) == part) tins(C, sc);
+                    });
+                } else if (sz > LANE_NET) {
+                    bsz = sz;  // <= HUB_BIG on the levels that take this path
+                }
+            }
+            uint32_t tot_n, tot_p;
+            const uint32_t rank =
+                block_incl_scan_n<uint32_t, LHUB_THREADS>(bsz ? 1u : 0u, wsum, &tot_n) - (bsz ? 1u : 0u);
+            const uint32_t pre = block_incl_scan_n<uint32_t, LHUB_THREADS>(bsz, wsum, &tot_p) - bsz;
+            if (bsz) {
+                bstart[rank] = pre;
+                bpin[rank] = b;
+                bsc[rank] = a.nscore[e];
+            }
+            if (tid == 0) bstart[tot_n] = tot_p;
+            __syncthreads();
+            const uint32_t nb = tot_n;
+            for (uint32_t w0 = 0; w0 < nb;) {
+                uint32_t lo = w0 + 1, hi = nb;  // window: nets w0 .. w1-1 of at most HUB_WIN pins
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (bstart[mid] - bstart[w0] <= HUB_WIN) lo = mid; else hi = mid - 1;
+                }
+                const uint32_t w1 = lo;
+                for (uint32_t x = bstart[w0] + tid; x < bstart[w1]; x += LHUB_THREADS) {
+                    uint32_t tl = w0, th = w1 - 1;
+                    while (tl < th) {
+                        const uint32_t mid = (tl + th + 1) >> 1;
+                        if (bstart[mid] <= x) tl = mid; else th = mid - 1;
+                    }
+                    const uint32_t v = a.pins[bpin[tl] + (x - bstart[tl])];
+                    if (v == u) continue;
+                    const uint32_t C = a.rep[v];
+                    if (lhub_part(C, P) != part) continue;
+                    bool fresh = true;
+                    if (a.dedup) {
+                        const unsigned long long key = ((unsigned long long)tl << 32) | C;
+                        uint32_t h = slot_hash(C ^ (tl * 0x9E3779B9u), 12);
+                        for (;;) {
+                            const unsigned long long k = set[h];
+                            if (k == key) { fresh = false; break; }
+                            if (k == EMPTY) {
+                                const unsigned long long old = atomicCAS(&set[h], EMPTY, key);
+                                if (old == EMPTY) { setocc[atomicAdd(&nset, 1u)] = (uint16_t)h; break; }
+                                if (old == key) { fresh = false; break; }
+                            }
+                            h = (h + 1) & (HUB_SET - 1);
+                        }
+                    }
+                    if (fresh) tins(C, bsc[tl]);
+                }
+                __syncthreads();
+                if (a.dedup) {
+                    const uint32_t ns = nset;
+                    for (uint32_t x = tid; x < ns; x += LHUB_THREADS) set[setocc[x]] = EMPTY;
+                    __syncthreads();
+                    if (tid == 0) nset = 0;
+                    __syncthreads();
+                }
+                w0 = w1;
+            }
+            __syncthreads();  // bstart / bpin / bsc are rewritten by the next chunk
+        }
+        __syncthreads();
+        uint64_t bR = 0;
+        uint32_t bC = NONE;
+        if (!ovf) {
+            for (uint32_t q = tid; q < LHUB_CAP; q += LHUB_THREADS) {
+                const uint32_t C = tkey[q];
+                if (C == NONE) continue;
+                const uint64_t rc = tR[q];
+                if (valid_target(a, u, C) && better_lazy(a, rc, C, bR, bC)) { bR = rc; bC = C; }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t oR = __shfl_xor(bR, o, 64);
+            const uint32_t oC = __shfl_xor(bC, o, 64);
+            if (better_lazy(a, oR, oC, bR, bC)) { bR = oR; bC = oC; }
+        }
+        const unsigned w = tid / WAVE;
+        if (__lane_id() == 0) { redR[w] = bR; redC[w] = bC; }
+        __syncthreads();
+        if (tid == 0) {
+            for (int q = 1; q < LHUB_THREADS / WAVE; ++q)
+                if (better_lazy(a, redR[q], redC[q], bR, bC)) { bR = redR[q]; bC = redC[q]; }
+            partR[J.pbase + part] = bR;
+            partC[J.pbase + part] = bC;
+            if (ovf && atomicExch(&ovf_flag[I.job], 1u) == 0u) ovf_list[atomicAdd(ovf_cnt, 1u)] = I.job;
+        }
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_hub_huge(RateArgs a, const HubJob *jobs, uint32_t njobs, uint32_t *keys,
                                                     uint32_t *stamp, uint64_t *R) {
     for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
@@ -559,10 +721,13 @@ __global__ __launch_bounds__(BLOCK) void k_hub_argmax(RateArgs a, const HubJob *
     }
 }
 
+// skip (may be null): jobs whose LDS table filled up (rated again later)
 __global__ __launch_bounds__(BLOCK) void k_hub_pick(RateArgs a, const HubJob *jobs, uint32_t njobs,
-                                                    const uint64_t *partR, const uint32_t *partC) {
+                                                    const uint64_t *partR, const uint32_t *partC,
+                                                    const uint32_t *skip) {
     const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nw = gridDim.x * BLOCK / WAVE;
     for (uint32_t jb = wid; jb < njobs; jb += nw) {
+        if (skip && skip[jb]) continue;  // uniform per wave
         const HubJob J = jobs[jb];
         uint64_t bR = 0;
         uint32_t bC = NONE;
@@ -895,6 +1060,8 @@ struct CoarsenBufs {
     size_t hub_aitems_cap;
     uint64_t *hub_partR;     // best target per slice
     uint32_t *hub_partC;
+    uint32_t *hub_ovf;       // [n + 1]: LDS jobs whose table filled up (flags), their count last
+    uint32_t *hub_ovf_list;  // [n]
 };
 
 // One global-table entry: key, stamp (4 B each), rating (8 B).
@@ -930,6 +1097,8 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, uint32_t S, Coars
     B.hub_aitems = A.alloc<HubItem>(B.hub_aitems_cap);
     B.hub_partR = A.alloc<uint64_t>(B.hub_aitems_cap);
     B.hub_partC = A.alloc<uint32_t>(B.hub_aitems_cap);
+    B.hub_ovf = A.alloc<uint32_t>((size_t)n + 1);
+    B.hub_ovf_list = A.alloc<uint32_t>(n);
     // global (hub) rating tables: room for 16 tables of the largest possible
     // capacity (>= 1.5 n), more (up to 4 p entries, 2^26) when the workspace
     // has it, always leaving room for the temporaries the pass allocates
@@ -1002,12 +1171,8 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     }
     // Hub rating of the listed candidates: jobs packed into the region in
     // batches (every table fits the region alone: E >= 16 * its capacity).
-    auto hub_rate = [&](const RateArgs &a, const uint32_t *lst, uint32_t cntc) {
-        k_hub_info<<<grid_for(cntc, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(a, lst, cntc, B.bound, n, B.hub_info);
-        HGP_LAUNCH_CHECK();
-        std::vector<uint4> info(cntc);
-        HGP_CHECK_HIP(hipMemcpyAsync(info.data(), B.hub_info, sizeof(uint4) * cntc, hipMemcpyDeviceToHost, st));
-        stream_sync(st);
+    auto global_rate = [&](const RateArgs &a, const std::vector<uint4> &info) {
+        const uint32_t cntc = (uint32_t)info.size();
         // all batches planned at once: jobs of a batch share the region
         std::vector<HubJob> jobs;
         std::vector<HubItem> items, aitems;
@@ -1068,10 +1233,81 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                                                                 B.hub_partR, B.hub_partC);
             HGP_LAUNCH_CHECK();
             k_hub_pick<<<grid_for((size_t)nj * WAVE, BLOCK, 1024), BLOCK, 0, st>>>(a, jb, nj, B.hub_partR,
-                                                                                  B.hub_partC);
+                                                                                  B.hub_partC, nullptr);
             HGP_LAUNCH_CHECK();
         }
         stream_sync(st);  // the uploads read the host vectors
+    };
+    // Hub candidates: bounds up to LHUB_PART * LHUB_MAXP take the LDS path
+    // (unless the level has nets of more than HUB_BIG pins), the others and
+    // any LDS job whose table filled up the global-table path.
+    auto hub_rate = [&](const RateArgs &a, const uint32_t *lst, uint32_t cntc) {
+        k_hub_info<<<grid_for(cntc, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(a, lst, cntc, B.bound, n, B.hub_info);
+        HGP_LAUNCH_CHECK();
+        std::vector<uint4> info(cntc), ginfo, linfo;
+        HGP_CHECK_HIP(hipMemcpyAsync(info.data(), B.hub_info, sizeof(uint4) * cntc, hipMemcpyDeviceToHost, st));
+        stream_sync(st);
+        for (const uint4 &f : info) {
+            if (f.w == NONE) continue;  // joined by another vertex earlier in the pass
+            if (!huge_nets && f.w <= LHUB_PART * LHUB_MAXP) linfo.push_back(f);
+            else ginfo.push_back(f);
+        }
+        std::vector<HubJob> ljobs;
+        std::vector<HubItem> litems;
+        std::vector<uint32_t> lj{0}, la{0};  // batch boundaries in jobs / items (partials <= hub_aitems_cap)
+        if (!linfo.empty()) {
+            uint32_t pb = 0;
+            for (const uint4 &f : linfo) {
+                const uint32_t P = std::max<uint32_t>(1u, (f.w + LHUB_PART - 1) / LHUB_PART);
+                if (pb + P > B.hub_aitems_cap) {
+                    lj.push_back((uint32_t)ljobs.size());
+                    la.push_back((uint32_t)litems.size());
+                    pb = 0;
+                }
+                const uint32_t jid = (uint32_t)(ljobs.size() - lj.back());
+                ljobs.push_back(HubJob{f.x, P, f.y, f.z, 0, pb, P});
+                for (uint32_t q = 0; q < P; ++q) litems.push_back(HubItem{jid, q, 0, 0});
+                pb += P;
+            }
+            lj.push_back((uint32_t)ljobs.size());
+            la.push_back((uint32_t)litems.size());
+            HGP_CHECK_HIP(hipMemcpyAsync(B.hub_jobs, ljobs.data(), sizeof(HubJob) * ljobs.size(),
+                                         hipMemcpyHostToDevice, st));
+            HGP_CHECK_HIP(hipMemsetAsync(B.hub_ovf, 0, sizeof(uint32_t) * (ljobs.size() + 1), st));
+            uint32_t *ovf_cnt = B.hub_ovf + n;
+            HGP_CHECK_HIP(hipMemsetAsync(ovf_cnt, 0, sizeof(uint32_t), st));
+            for (size_t b = 0; b + 1 < lj.size(); ++b) {
+                const uint32_t nj = lj[b + 1] - lj[b], nl = la[b + 1] - la[b];
+                if (!nj) continue;
+                const HubJob *jb = B.hub_jobs + lj[b];
+                HGP_CHECK_HIP(hipMemcpyAsync(B.hub_aitems, litems.data() + la[b], sizeof(HubItem) * nl,
+                                             hipMemcpyHostToDevice, st));
+                k_hub_lds<<<std::min(nl, 8192u), LHUB_THREADS, 0, st>>>(a, jb, B.hub_aitems, nl, B.hub_partR,
+                                                                        B.hub_partC, B.hub_ovf + lj[b],
+                                                                        B.hub_ovf_list, ovf_cnt);
+                HGP_LAUNCH_CHECK();
+                k_hub_pick<<<grid_for((size_t)nj * WAVE, BLOCK, 1024), BLOCK, 0, st>>>(a, jb, nj, B.hub_partR,
+                                                                                      B.hub_partC, B.hub_ovf + lj[b]);
+                HGP_LAUNCH_CHECK();
+            }
+        }
+        if (!ginfo.empty()) global_rate(a, ginfo);
+        if (!linfo.empty()) {
+            // jobs whose LDS table filled up (indices within their batch)
+            uint32_t no = 0;
+            HGP_CHECK_HIP(hipMemcpyAsync(&no, B.hub_ovf + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            stream_sync(st);
+            if (no) {
+                std::vector<uint32_t> flags(ljobs.size());
+                HGP_CHECK_HIP(hipMemcpyAsync(flags.data(), B.hub_ovf, sizeof(uint32_t) * flags.size(),
+                                             hipMemcpyDeviceToHost, st));
+                stream_sync(st);
+                std::vector<uint4> again;
+                for (size_t q = 0; q < flags.size(); ++q)
+                    if (flags[q]) again.push_back(linfo[q]);
+                global_rate(a, again);
+            }
+        }
     };
     offs[0] = 0;
     for (uint32_t i = 0; i < S * NCLASS; ++i) offs[i + 1] = offs[i] + counts[i];
