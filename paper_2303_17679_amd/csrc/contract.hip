@@ -51,7 +51,7 @@ __global__ void k_net_hash_small(const uint32_t *off, uint32_t m, const uint32_t
                                  uint32_t *hkey, uint8_t *valid) {
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
         uint32_t b = off[e], len = off[e + 1] - b;
-        if (len > SEG_SMALL) continue;  // done by the block kernel
+        if (len > SEG_WAVE) continue;  // done by the block kernel
         uint32_t sz = usize[e];
         uint64_t h = 0;
         for (uint32_t i = 0; i < sz; ++i) h += pin_hash_term(tmp[b + i]);
@@ -160,7 +160,7 @@ __global__ void k_copy_pins_small(const uint32_t *off, uint32_t m, const uint32_
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
         if (newid[e] == NONE) continue;
         uint32_t b = off[e], len = off[e + 1] - b;
-        if (len > SEG_SMALL) continue;
+        if (len > SEG_WAVE) continue;  // done by the block kernel
         uint32_t sz = usize[e], o = newoff[e];
         for (uint32_t i = 0; i < sz; ++i) {
             uint32_t v = tmp[b + i];

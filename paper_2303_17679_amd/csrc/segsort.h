@@ -1,7 +1,8 @@
 // Segmented ascending sort of uint32 values inside CSR segments, with an
 // optional de-duplication that moves the distinct values to the front of
-// each segment and records their count.  Three tiers by segment length:
+// each segment and records their count.  Four tiers by segment length:
 //   <= 16    one thread per segment, a sorting network in registers;
+//   <= 64    one wave per segment, a value per lane, bitonic sort by shuffles;
 //   <= 4096  one block per segment, bitonic sort in LDS;
 //   larger   all such segments together through the device radix sort on
 //            (segment rank, value) keys, then a block per segment compacts.
@@ -11,6 +12,7 @@
 namespace hgp {
 
 constexpr uint32_t SEG_SMALL = 16;
+constexpr uint32_t SEG_WAVE = 64;
 constexpr uint32_t SEG_MED = 4096;
 
 __device__ inline void cswap(uint32_t &a, uint32_t &b) {
@@ -39,15 +41,19 @@ __device__ inline void sort16(uint32_t (&r)[16]) {
 }
 
 // Small segments: sort (+unique).  Segments longer than SEG_SMALL are
-// appended to the medium / large lists.
+// appended to the wave / medium / large lists.
 __global__ void k_seg_small(const uint32_t *off, uint32_t nseg, uint32_t *data, bool uniq, uint32_t *usize,
-                            uint32_t *med, uint32_t *nmed, uint32_t *large, uint32_t *nlarge) {
+                            uint32_t *med, uint32_t *nmed, uint32_t *large, uint32_t *nlarge, uint32_t *wavel,
+                            uint32_t *nwave) {
     for (uint32_t s0 = blockIdx.x * blockDim.x; s0 < nseg; s0 += gridDim.x * blockDim.x) {
         uint32_t s = s0 + threadIdx.x;
         bool act = s < nseg;
         uint32_t b = act ? off[s] : 0, len = act ? off[s + 1] - b : 0;
-        bool ismed = act && len > SEG_SMALL && len <= SEG_MED;
+        bool iswave = act && len > SEG_SMALL && len <= SEG_WAVE;
+        bool ismed = act && len > SEG_WAVE && len <= SEG_MED;
         bool islarge = act && len > SEG_MED;
+        uint32_t pw = warp_agg_append(nwave, iswave);
+        if (iswave) wavel[pw] = s;
         uint32_t pm = warp_agg_append(nmed, ismed);
         if (ismed) med[pm] = s;
         uint32_t pl = warp_agg_append(nlarge, islarge);
@@ -71,6 +77,37 @@ __global__ void k_seg_small(const uint32_t *off, uint32_t nseg, uint32_t *data, 
                 }
             }
             usize[s] = w;
+        }
+    }
+}
+
+// Segments of SEG_SMALL+1 .. SEG_WAVE values: one wave each, a value per lane,
+// bitonic sort by shuffles; the distinct values are compacted by a ballot.
+__global__ __launch_bounds__(BLOCK) void k_seg_wave(const uint32_t *off, const uint32_t *list, uint32_t count,
+                                                    uint32_t *data, bool uniq, uint32_t *usize) {
+    const uint32_t lane = __lane_id();
+    const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nw = gridDim.x * BLOCK / WAVE;
+    for (uint32_t idx = wid; idx < count; idx += nw) {
+        const uint32_t s = list[idx];
+        const uint32_t b = off[s], len = off[s + 1] - b;
+        uint32_t x = lane < len ? data[b + lane] : 0xFFFFFFFFu;
+#pragma unroll
+        for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                const uint32_t y = __shfl_xor(x, (int)j, 64);
+                const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+                x = (lower == up) ? (x < y ? x : y) : (x < y ? y : x);
+            }
+        }
+        if (!uniq) {
+            if (lane < len) data[b + lane] = x;
+        } else {
+            const uint32_t prev = __shfl_up(x, 1, 64);
+            const bool keep = lane < len && (lane == 0 || x != prev);
+            const uint64_t mk = __ballot(keep);
+            if (keep) data[b + (uint32_t)__popcll(mk & lanemask_lt())] = x;
+            if (lane == 0) usize[s] = (uint32_t)__popcll(mk);
         }
     }
 }
@@ -167,7 +204,7 @@ struct LargeLen {
 };
 
 struct SegSortBufs {
-    uint32_t *med, *large, *scal;
+    uint32_t *med, *large, *wavel, *scal;
     uint64_t *pos, *keys, *keys_alt;
     uint32_t *vals, *vals_alt;
 };
@@ -175,8 +212,9 @@ struct SegSortBufs {
 // Workspace for segments holding at most `total` values.
 inline void segsort_plan(Arena &A, uint32_t nseg, size_t total, SegSortBufs &B) {
     B.med = A.alloc<uint32_t>(nseg);
+    B.wavel = A.alloc<uint32_t>(nseg);
     B.large = A.alloc<uint32_t>(total / SEG_MED + 1);
-    B.scal = A.alloc<uint32_t>(4);
+    B.scal = A.alloc<uint32_t>(6);
     B.pos = A.alloc<uint64_t>(total / SEG_MED + 2);
     B.keys = A.alloc<uint64_t>(total);
     B.keys_alt = A.alloc<uint64_t>(total);
@@ -189,14 +227,19 @@ inline void segsort_plan(Arena &A, uint32_t nseg, size_t total, SegSortBufs &B) 
 // Sorts (and with uniq, de-duplicates) every segment.  Syncs the stream.
 inline void segmented_sort(Arena &A, const SegSortBufs &B, const uint32_t *off, uint32_t nseg, uint32_t *data,
                            bool uniq, uint32_t *usize, hipStream_t st) {
-    HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 4, st));  // callers read the counts
+    HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 6, st));  // callers read the counts
     if (nseg == 0) return;
     k_seg_small<<<grid_for(nseg, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(off, nseg, data, uniq, usize, B.med, B.scal,
-                                                                     B.large, B.scal + 1);
+                                                                     B.large, B.scal + 1, B.wavel, B.scal + 4);
     HGP_LAUNCH_CHECK();
-    uint32_t cnt[2];
+    uint32_t cnt[5];
     HGP_CHECK_HIP(hipMemcpyAsync(cnt, B.scal, sizeof(cnt), hipMemcpyDeviceToHost, st));
     stream_sync(st);
+    if (cnt[4]) {
+        k_seg_wave<<<grid_for((size_t)cnt[4] * WAVE, BLOCK, 8192), BLOCK, 0, st>>>(off, B.wavel, cnt[4], data, uniq,
+                                                                                   usize);
+        HGP_LAUNCH_CHECK();
+    }
     if (cnt[0]) {
         k_seg_med<<<grid_for(cnt[0], 1, 4096), BLOCK, 0, st>>>(off, B.med, cnt[0], data, uniq, usize);
         HGP_LAUNCH_CHECK();
