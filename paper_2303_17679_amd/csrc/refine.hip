@@ -377,22 +377,44 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
     }
 }
 
-// One launch for the three degree classes: blocks [0, nb0) take class 0
-// (1 lane per node), [nb0, nb0 + nb1) class 1 (8 lanes), the rest class 2
-// (64).  List c starts at off[c]; its length is the device count ccnt[c].
-struct ClassLists {
-    uint32_t off[NDEG];
-    uint32_t nb[NDEG];
-};
-
+// Candidates and gains of LP sub-round (r, s) in one launch.  The
+// candidates are the boundary vertices (an incident net with lambda > 1 --
+// no other vertex can have a positive gain) whose sub-round hash selects s.
+// Each workgroup takes chunks of `ch` consecutive vertices (the chunks of
+// one XCD are contiguous), lists the chunk's candidates in LDS by degree
+// class and rates them: 1 lane per node up to 8 nets, 8 lanes up to 64, a
+// wave up to HUB_DEG; larger nodes go to the hub list for k_gains_hub.
+// Block 0 also clears the counters that only the later kernels of the
+// sub-round use.
+constexpr uint32_t GAIN_CH = 2048;  // largest chunk
 template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_gains(GainArgs<KW> a, const uint32_t *lists, ClassLists cl,
-                                                 const uint32_t *ccnt) {
+__global__ __launch_bounds__(BLOCK) void k_gains(GainArgs<KW> a, uint32_t ch, uint32_t nchunks, uint32_t *hubl,
+                                                 uint32_t *nhub, uint32_t *scal) {
+    __shared__ uint32_t lst[3][GAIN_CH];
+    __shared__ uint32_t lcnt[3];
     if (*a.abort) return;
-    const uint32_t b = blockIdx.x;
-    if (b < cl.nb[0]) gains_body<KW, 1>(a, lists + cl.off[0], ccnt[0], b, cl.nb[0]);
-    else if (b < cl.nb[0] + cl.nb[1]) gains_body<KW, 8>(a, lists + cl.off[1], ccnt[1], b - cl.nb[0], cl.nb[1]);
-    else gains_body<KW, 64>(a, lists + cl.off[2], ccnt[2], b - cl.nb[0] - cl.nb[1], cl.nb[2]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[2] = 0; scal[3] = 0;     // ntouched, nlong
+        scal[13] = 0; scal[14] = 0;   // oversized-pair proposals, movers
+        scal[24] = 0;                 // movers of more than HUB_DEG nets
+    }
+    const XcdSlice xs = xcd_slice(blockIdx.x, gridDim.x, nchunks);
+    for (uint32_t c = xs.lo + xs.wi; c < xs.hi; c += xs.nw) {
+        const uint32_t lo = c * ch, hi = lo + ch < a.n ? lo + ch : a.n;
+        if (threadIdx.x < 3) lcnt[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t v = lo + threadIdx.x; v < hi; v += BLOCK) {
+            if (a.bcnt[v] == 0 || tag_hash(a.mseed, 3, a.level, a.round, v) % a.S != a.sub) continue;
+            const int cls = deg_class(a.inc_off[v + 1] - a.inc_off[v]);
+            if (cls == 3) hubl[atomicAdd(nhub, 1u)] = v;
+            else lst[cls][atomicAdd(&lcnt[cls], 1u)] = v;
+        }
+        __syncthreads();
+        gains_body<KW, 1>(a, lst[0], lcnt[0], 0, 1);
+        gains_body<KW, 8>(a, lst[1], lcnt[1], 0, 1);
+        gains_body<KW, 64>(a, lst[2], lcnt[2], 0, 1);
+        __syncthreads();  // the lists are rewritten by the next chunk
+    }
 }
 
 // Candidates of more than HUB_DEG nets: one 1024-thread workgroup each, the
@@ -497,115 +519,6 @@ __global__ __launch_bounds__(BLOCK) void k_init_bcnt_wave(const uint32_t *inc_of
     }
 }
 
-// Per-sub-round state (scalar counters, pair sums) back to zero, and the
-// previous sub-round's block-weight changes folded into the block weights.
-// Runs at the start of a sub-round, after every reader of that state.  The
-// candidate counts ccnt are cleared by k_pair_plan instead (this kernel
-// counts into them).
-struct SubReset {
-    uint32_t *scal, *pw, *pc;
-    uint32_t kk, k;
-    int64_t *bw, *dbw_g;
-};
-__device__ inline void subround_reset(const SubReset &z) {
-    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
-    if (tid < 4) z.scal[tid] = 0;                    // nprop, gmax, ntouched, nlong
-    if (tid == 4) { z.scal[13] = 0; z.scal[14] = 0; }  // oversized-pair proposals, movers
-    if (tid == 5) { z.scal[24] = 0; z.scal[25] = 0; }  // movers of more than HUB_DEG nets, slow pairs
-    for (uint32_t i = tid; i < z.kk; i += nt) { z.pw[i] = 0; z.pc[i] = 0; }
-    if (blockIdx.x == 0)
-        for (uint32_t b = threadIdx.x; b < z.k; b += blockDim.x) {
-            const int64_t d = z.dbw_g[b];
-            if (d) { z.bw[b] += d; z.dbw_g[b] = 0; }
-        }
-}
-
-// Candidates of LP sub-round (r, s): the boundary vertices (an incident net
-// with lambda > 1 -- no other vertex can have a positive gain) whose
-// sub-round hash selects s, appended to the list of their degree class.
-// Class c's list starts at off[c] and can hold every vertex of the class.
-// Each workgroup compacts one contiguous chunk of CAND_PER * BLOCK vertices
-// (1 on small levels, 8 on large ones): it loads all its boundary counts at
-// once, counts per class, reserves its ranges with one atomic per class,
-// then writes its candidates in ascending vertex order.
-template <uint32_t CAND_PER>
-__global__ __launch_bounds__(BLOCK) void k_lp_cands(const uint32_t *inc_off, const uint32_t *bcnt, uint32_t n,
-                                                    uint64_t mseed, uint32_t level, uint32_t r, uint32_t s,
-                                                    uint32_t S, ClassLists cl, uint32_t *ccnt, uint32_t *lists,
-                                                    SubReset z, const uint32_t *abort) {
-    constexpr int NW = BLOCK / WAVE;
-    __shared__ uint32_t wc[NDEG][NW];
-    __shared__ uint32_t base[NDEG];
-    if (*abort) return;
-    subround_reset(z);
-    const uint32_t lo = blockIdx.x * CAND_PER * BLOCK;
-    if (lo >= n) return;  // uniform per block
-    const uint32_t w = threadIdx.x / WAVE;
-    uint32_t bc[CAND_PER];
-#pragma unroll
-    for (uint32_t it = 0; it < CAND_PER; ++it) {
-        const uint32_t u = lo + it * BLOCK + threadIdx.x;
-        bc[it] = u < n ? bcnt[u] : 0u;
-    }
-    bool sel[CAND_PER];
-#pragma unroll
-    for (uint32_t it = 0; it < CAND_PER; ++it) {
-        const uint32_t u = lo + it * BLOCK + threadIdx.x;
-        sel[it] = bc[it] > 0 && tag_hash(mseed, 3, level, r, u) % S == s;
-    }
-    uint32_t d0[CAND_PER], d1[CAND_PER];
-#pragma unroll
-    for (uint32_t it = 0; it < CAND_PER; ++it) {
-        const uint32_t u = lo + it * BLOCK + threadIdx.x;
-        d0[it] = sel[it] ? inc_off[u] : 0u;
-        d1[it] = sel[it] ? inc_off[u + 1] : 0u;
-    }
-    int key[CAND_PER];
-    uint32_t cc[NDEG] = {0, 0, 0, 0};
-#pragma unroll
-    for (uint32_t it = 0; it < CAND_PER; ++it) {
-        key[it] = sel[it] ? deg_class(d1[it] - d0[it]) : -1;
-#pragma unroll
-        for (int c = 0; c < NDEG; ++c) cc[c] += key[it] == c;
-    }
-#pragma unroll
-    for (int c = 0; c < NDEG; ++c) {
-        cc[c] = wave_sum(cc[c]);
-        if (__lane_id() == 0) wc[c][w] = cc[c];
-    }
-    __syncthreads();
-    if (threadIdx.x < NDEG) {
-        uint32_t t = 0;
-        for (int q = 0; q < NW; ++q) t += wc[threadIdx.x][q];
-        base[threadIdx.x] = t ? atomicAdd(&ccnt[threadIdx.x], t) : 0u;
-    }
-    __syncthreads();
-    uint32_t run[NDEG] = {base[0], base[1], base[2], base[3]};
-#pragma unroll
-    for (uint32_t it = 0; it < CAND_PER; ++it) {
-        const uint32_t u = lo + it * BLOCK + threadIdx.x;
-        uint64_t bal[NDEG];
-#pragma unroll
-        for (int c = 0; c < NDEG; ++c) bal[c] = __ballot(key[it] == c);
-        __syncthreads();  // the previous iteration's reads of wc are done
-        if (__lane_id() == 0)
-#pragma unroll
-            for (int c = 0; c < NDEG; ++c) wc[c][w] = (uint32_t)__popcll(bal[c]);
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < NDEG; ++c) {
-            uint32_t before = 0, total = 0;
-#pragma unroll
-            for (int q = 0; q < NW; ++q) {
-                before += (q < (int)w) ? wc[c][q] : 0u;
-                total += wc[c][q];
-            }
-            if (key[it] == c) lists[cl.off[c] + run[c] + before + (uint32_t)__popcll(bal[c] & lanemask_lt())] = u;
-            run[c] += total;
-        }
-    }
-}
-
 // Boundary count of every node from scratch (once per level); a node of more
 // than 32 nets is counted by its whole wave.
 template <int KW>
@@ -633,24 +546,24 @@ __global__ __launch_bounds__(BLOCK) void k_init_bcnt(const uint32_t *inc_off, co
     }
 }
 
-// Measurement only: compulsory bytes of one gains launch: for every
-// candidate its list entry, offsets, block, weight and incidence list; for
-// every distinct incident net its weight, Lambda words and the one Lambda1
-// word the gain reads, counted once.
+// Measurement only: compulsory bytes of one gains launch: the boundary
+// count of every vertex; for every boundary vertex the sub-round selects, its
+// incidence offsets (and a hub-list entry for the nodes left to k_gains_hub);
+// for every candidate it rates, its block, weight and incidence list; for
+// every distinct incident net of those its weight, Lambda words and the one
+// Lambda1 word the gain reads, counted once.
 template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs<KW> a, const uint32_t *lists, ClassLists cl,
-                                                         const uint32_t *ccnt, uint32_t *nmark, uint32_t stamp,
+__global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs<KW> a, uint32_t *nmark, uint32_t stamp,
                                                          unsigned long long *acc) {
     __shared__ unsigned long long red[BLOCK / WAVE];
     unsigned long long bytes = 0;
-    uint32_t total = 0;
-    for (int c = 0; c < NDEG; ++c) total += ccnt[c];
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
-        uint32_t c = 0, i = idx;
-        while (i >= ccnt[c]) i -= ccnt[c++];
-        const uint32_t u = lists[cl.off[c] + i];
-        const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
-        bytes += 4 + 8 + 4 + 4 + 4ull * (j1 - j0);  // list entry, inc_off pair, part, vwgt, incidence list
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
+        bytes += 4;  // boundary count
+        if (a.bcnt[v] == 0 || tag_hash(a.mseed, 3, a.level, a.round, v) % a.S != a.sub) continue;
+        const uint32_t j0 = a.inc_off[v], j1 = a.inc_off[v + 1];
+        bytes += 8;
+        if (deg_class(j1 - j0) == 3) { bytes += 4; continue; }
+        bytes += 4 + 4 + 4ull * (j1 - j0);  // block, weight, incidence list
         for (uint32_t j = j0; j < j1; ++j)
             if (atomicExch(&nmark[a.inc[j]], stamp) != stamp) bytes += 4 + 8ull * KW + 8;
     }
@@ -903,8 +816,7 @@ __global__ void k_add_dbw(int64_t *bw, int64_t *dbw_g, uint32_t k) {
 //                every unordered pair {x < y} with proposals and gives each
 //                pair that fails it a segment of `seg` (exclusive prefix of
 //                the failing pairs' proposal counts) and a slot in the pair
-//                list.  It also clears the candidate counts of the sub-round,
-//                whose lists k_gains has consumed.
+//                list.
 //   k_lp_fast    scatters those pairs' proposals into their segments, in no
 //                particular order.
 //   k_lp_pairs   sorts each segment in LDS by (direction, gain desc, u asc) --
@@ -929,12 +841,11 @@ constexpr uint32_t PLAN_PER = 4;
 __global__ __launch_bounds__(PLAN_THREADS) void k_pair_plan(const uint32_t *pw, const uint32_t *pc, uint32_t k,
                                                             const int64_t *bw, int64_t lmax, uint32_t *pbase,
                                                             uint32_t *pcur, uint32_t *spairs, uint32_t *nsp,
-                                                            uint32_t *ccnt, const uint32_t *abort) {
+                                                            const uint32_t *abort) {
     __shared__ uint64_t wsum[PLAN_THREADS / WAVE];
     __shared__ int64_t sbeta[256];
     if (*abort) return;
     const uint32_t tid = threadIdx.x;
-    if (tid < NDEG) ccnt[tid] = 0;
     for (uint32_t b = tid; b < k; b += PLAN_THREADS) sbeta[b] = floor_div_i64(lmax - bw[b], (int64_t)k - 1);
     __syncthreads();
     const uint32_t kk = k * k;
@@ -1210,6 +1121,26 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_heavy(const uint32_t *pin_o
 // more than 64 pins are forwarded to the wave kernel.  The objective changes
 // by w(e) (max(lambda'-1,0) - max(lambda-1,0)); the sub-round's move count is
 // added to the round's.
+// State the next sub-round's gains start from: its proposal counters and pair
+// sums at zero, and this sub-round's block-weight changes in the block
+// weights.  Cleared by the last kernel of a sub-round that every sub-round
+// runs (the update), after every reader.
+struct NextSub {
+    uint32_t *scal, *pw, *pc;
+    uint32_t kk, k;
+    int64_t *bw, *dbw_g;
+};
+__device__ inline void next_subround(const NextSub &z) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+    if (tid == 0) { z.scal[0] = 0; z.scal[1] = 0; z.scal[26] = 0; }  // nprop, gmax, hub candidates
+    for (uint32_t i = tid; i < z.kk; i += nt) { z.pw[i] = 0; z.pc[i] = 0; }
+    if (blockIdx.x == 0)
+        for (uint32_t b = threadIdx.x; b < z.k; b += blockDim.x) {
+            const int64_t d = z.dbw_g[b];
+            if (d) { z.bw[b] += d; z.dbw_g[b] = 0; }
+        }
+}
+
 template <int KW, int G>
 __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_off, const uint32_t *pins,
                                                             const uint32_t *inc_off, const uint32_t *inc,
@@ -1217,9 +1148,10 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
                                                             const uint32_t *part, NetRec<KW> *nr, uint32_t *tstamp,
                                                             uint32_t stamp, int64_t *f, uint32_t *longl,
                                                             uint32_t *nlong, uint32_t *moves, uint32_t *bcnt,
-                                                            uint32_t *heavy, uint32_t *nheavy,
+                                                            uint32_t *heavy, uint32_t *nheavy, NextSub z,
                                                             const uint32_t *abort) {
     if (*abort) return;
+    next_subround(z);
     __shared__ int64_t red[BLOCK / WAVE];
     constexpr int GPB = BLOCK / G;
     const uint32_t cnt = *nmov;
@@ -1252,7 +1184,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
 struct RefineBufs {
     void *nr;  // NetRec<KW>[m]
     int64_t *f, *bw;
-    uint32_t *longl, *dlists, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow, *mlist;
+    uint32_t *longl, *dlists /* hub candidates */, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow, *mlist;
     uint32_t *pc, *pbase, *pcur, *spairs, *seg;  // per-pair proposal counts, segments of over-budget pairs
     int64_t *dbw_g;
     uint64_t *keys, *keys_alt, *incl;
@@ -1375,23 +1307,20 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * NDEG, st));
     k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt);
     HGP_LAUNCH_CHECK();
-    uint32_t dc[NDEG], doff[NDEG + 1] = {0, 0, 0, 0, 0}, hs[16];
+    uint32_t dc[NDEG], hs[16];
     HGP_CHECK_HIP(hipMemcpyAsync(hs, B.scal, sizeof(hs), hipMemcpyDeviceToHost, st));
     stream_sync(st);
     for (int c = 0; c < NDEG; ++c) dc[c] = hs[5 + c];
     const bool long_nets = hs[12] > 0;  // nets of more than 64 pins exist on this level
-    for (int c = 0; c < NDEG; ++c) doff[c + 1] = doff[c] + dc[c];
-    // per sub-round a class holds about 1/S of its vertices (fewer: only the
-    // boundary); the grid strides over whatever the device count is
     const uint32_t S = prm.lp_subrounds;
-    ClassLists cl;
-    for (int c = 0; c < NDEG; ++c) {
-        const uint32_t per = c == 0 ? BLOCK : (c == 1 ? BLOCK / 8 : BLOCK / 64);
-        cl.off[c] = doff[c];
-        cl.nb[c] = (c < 3 && dc[c]) ? grid_for((dc[c] + S - 1) / S, per, 2048) : 0u;
-    }
+    // gains: chunks of `gch` vertices (a power of two in [64, GAIN_CH], about
+    // n / 1024, so that even small levels spread over many workgroups)
+    uint32_t gch = 64;
+    while (gch < GAIN_CH && (size_t)gch * 2048 <= n) gch <<= 1;
+    const uint32_t gchunks = (uint32_t)(((size_t)n + gch - 1) / gch);
+    const uint32_t gain_blocks = std::min<uint32_t>(gchunks, 4096u);
     const uint32_t hub_blocks = dc[3] ? grid_for((dc[3] + S - 1) / S, 1, 256) : 0u;
-    const uint32_t nbg_all = cl.nb[0] + cl.nb[1] + cl.nb[2];
+    uint32_t *nhub = B.scal + 26;  // hub candidates of the sub-round (list in dlists)
     // grids of the per-sub-round kernels, sized by what one sub-round can hold
     // (about n / S proposals and movers); every kernel strides over its count
     const size_t per_sub = (size_t)n / S + 1;
@@ -1401,23 +1330,20 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const uint32_t upd_g = avg_deg <= 8 ? 8u : (avg_deg <= 24 ? 16u : 64u);
     const uint32_t upd_blocks = grid_for(per_sub, BLOCK / upd_g, FILL_BLOCKS / 2);
     const uint32_t long_blocks = grid_for((size_t)m + 1, 64 * (BLOCK / WAVE), FILL_BLOCKS / 4);
-    // candidate compaction: chunks of cand_per * BLOCK vertices per workgroup
-    const uint32_t cand_per = n > 2048u * BLOCK ? 8u : 1u;
-    const uint32_t cand_blocks = (uint32_t)((n + (size_t)cand_per * BLOCK - 1) / ((size_t)cand_per * BLOCK));
-    uint32_t *ccnt = B.scal + 20;  // [NDEG] candidates per class in the current sub-round
 
     const int kb = bits_for(k - 1), ub = bits_for(n ? n - 1 : 0);
     // abort word: 1 + the sub-round whose selection handed a pair to the
     // device-wide path (0: none); later kernels of the round skip their work
     uint32_t *abort = B.scal + 15;
     uint32_t *nsp = B.scal + 25;  // over-budget pairs of the sub-round
-    // all per-sub-round state starts at zero (afterwards the first kernel of
-    // each sub-round clears it)
+    // all per-sub-round state starts at zero (afterwards the kernels of each
+    // sub-round clear it for the next: the gains kernel what only later
+    // kernels use, the update kernel the rest)
     HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 32, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.pw, 0, sizeof(uint32_t) * k * k, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.pc, 0, sizeof(uint32_t) * k * k, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.dbw_g, 0, sizeof(int64_t) * k, st));
-    const SubReset zr{B.scal, B.pw, B.pc, k * k, k, B.bw, B.dbw_g};
+    const NextSub zn{B.scal, B.pw, B.pc, k * k, k, B.bw, B.dbw_g};
     const uint32_t pair_blocks = std::min<uint32_t>(k * (k - 1) / 2, 1024u);
 
     // Device-wide selection of the pairs that sub-round (r, s) handed over
@@ -1484,7 +1410,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             auto launch = [&](auto kern, uint32_t blocks) {
                 kern<<<blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, part,
                                                (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl, nlong, moves,
-                                               B.bcnt, B.heavy, nheavy, abort);
+                                               B.bcnt, B.heavy, nheavy, zn, abort);
             };
             if (upd_g == 8) launch(k_lp_update_movers<KW, 8>, upd_blocks);
             else if (upd_g == 16) launch(k_lp_update_movers<KW, 16>, upd_blocks);
@@ -1508,31 +1434,23 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         const uint32_t stamp = 1 + r * S + s;
         const GainArgs<KW> ga{h.inc_off, h.inc, h.vwgt, (const NetRec<KW> *)B.nr, part, B.bw, B.bcnt, lmax, mseed,
                               level, r, s, S, n, B.prop_t, B.prop_g, B.plist, nprop, gmax, B.pw, B.pc, k, abort};
-        if (cand_per == 8)
-            k_lp_cands<8><<<cand_blocks, BLOCK, 0, st>>>(h.inc_off, B.bcnt, n, mseed, level, r, s, S, cl, ccnt,
-                                                         B.dlists, zr, abort);
-        else
-            k_lp_cands<1><<<cand_blocks, BLOCK, 0, st>>>(h.inc_off, B.bcnt, n, mseed, level, r, s, S, cl, ccnt,
-                                                         B.dlists, zr, abort);
-        HGP_LAUNCH_CHECK();
         if (accounting(KID_GAINS)) {
             Timing &T = timing();
             ++T.stamp;
-            k_account_gains<KW><<<grid_for(n / S + 1, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
-                ga, B.dlists, cl, ccnt, T.marks, T.stamp, (unsigned long long *)T.acc_dev + KID_GAINS);
+            k_account_gains<KW><<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+                ga, T.marks, T.stamp, (unsigned long long *)T.acc_dev + KID_GAINS);
             HGP_LAUNCH_CHECK();
         }
-        if (nbg_all) {
+        if (n) {
             TimedLaunch tl(KID_GAINS, st);
-            k_gains<KW><<<nbg_all, BLOCK, 0, st>>>(ga, B.dlists, cl, ccnt);
+            k_gains<KW><<<gain_blocks, BLOCK, 0, st>>>(ga, gch, gchunks, B.dlists, nhub, B.scal);
             HGP_LAUNCH_CHECK();
         }
         if (hub_blocks) {
-            k_gains_hub<KW><<<hub_blocks, HUB_THREADS, 0, st>>>(ga, B.dlists + cl.off[3], ccnt + 3);
+            k_gains_hub<KW><<<hub_blocks, HUB_THREADS, 0, st>>>(ga, B.dlists, nhub);
             HGP_LAUNCH_CHECK();
         }
-        k_pair_plan<<<1, PLAN_THREADS, 0, st>>>(B.pw, B.pc, k, B.bw, lmax, B.pbase, B.pcur, B.spairs, nsp, ccnt,
-                                                abort);
+        k_pair_plan<<<1, PLAN_THREADS, 0, st>>>(B.pw, B.pc, k, B.bw, lmax, B.pbase, B.pcur, B.spairs, nsp, abort);
         HGP_LAUNCH_CHECK();
         {  // pairs whose whole move sets are feasible: applied directly
             TimedLaunch tl(KID_LP_FAST, st);
