@@ -1016,6 +1016,67 @@ __global__ void k_slow_decide(const uint32_t *vals, uint32_t ns, const uint32_t 
     }
 }
 
+// The sorted approval of up to SLOW_SMALL joins in one workgroup: keys
+// (C, c(u), u) sorted in LDS (bitonic), prefix sums of c(u), and the same
+// decision as k_slow_decide.  Needs the key to fit 64 bits.
+constexpr uint32_t SLOW_SMALL = 4096;
+constexpr int SLOW_THREADS = 1024;
+__global__ __launch_bounds__(SLOW_THREADS) void k_slow_small(const uint32_t *slow, uint32_t ns,
+                                                             const uint32_t *ptarget, const int32_t *vwgt,
+                                                             const int64_t *cw, int64_t cap_mult, int64_t W,
+                                                             uint8_t *ok, int wb, int ub) {
+    __shared__ uint64_t key[SLOW_SMALL];
+    __shared__ uint64_t incl[SLOW_SMALL];
+    __shared__ uint64_t wsum[SLOW_THREADS / WAVE];
+    const uint32_t tid = threadIdx.x;
+    const int cs = wb + ub;
+    const uint64_t umask = (1ull << ub) - 1ull, wmask = (1ull << wb) - 1ull;
+    uint32_t n2 = 1;
+    while (n2 < ns) n2 <<= 1;
+    for (uint32_t i = tid; i < n2; i += SLOW_THREADS) {
+        uint64_t k = ~0ull;
+        if (i < ns) {
+            const uint32_t u = slow[i];
+            k = ((uint64_t)ptarget[u] << cs) | ((uint64_t)(uint32_t)vwgt[u] << ub) | (uint64_t)u;
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= n2; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = tid; i < n2; i += SLOW_THREADS) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint64_t a = key[i], b = key[l];
+                    if ((a > b) == ((i & kk) == 0)) { key[i] = b; key[l] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    uint64_t carry = 0;
+    for (uint32_t c0 = 0; c0 < ns; c0 += SLOW_THREADS) {
+        const uint32_t i = c0 + tid;
+        const uint64_t w = i < ns ? (key[i] >> ub) & wmask : 0ull;
+        uint64_t tot;
+        const uint64_t inc = block_incl_scan_n<uint64_t, SLOW_THREADS>(w, wsum, &tot);
+        if (i < ns) incl[i] = carry + inc;
+        carry += tot;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < ns; i += SLOW_THREADS) {
+        const uint64_t C = key[i] >> cs;
+        uint32_t lo = 0, hi = i;  // first position of target C
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((key[mid] >> cs) < C) lo = mid + 1; else hi = mid;
+        }
+        const uint64_t base = lo == 0 ? 0 : incl[lo - 1];
+        const int64_t prefix = (int64_t)(incl[i] - base);
+        ok[(uint32_t)(key[i] & umask)] = (cap_mult * (cw[C] + prefix) <= W) ? 1 : 0;
+    }
+}
+
 __global__ void k_apply_joins(const uint32_t *proposers, const uint32_t *np_dev, const uint32_t *ptarget,
                               const uint8_t *ok, const int32_t *vwgt, uint32_t *rep, int64_t *cw, int64_t *tsum,
                               uint32_t *n_clusters) {
@@ -1317,6 +1378,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     HGP_LAUNCH_CHECK();
 
     uint32_t cnt = n;
+    int wb = -1;  // bits of the largest vertex weight (read when the sorted approval first runs)
     uint32_t *nprop = B.scal + 0, *nslow = B.scal + 1, *ncl = B.scal + 2;
     HGP_CHECK_HIP(hipMemcpyAsync(ncl, &cnt, sizeof(uint32_t), hipMemcpyHostToDevice, st));
     for (uint32_t r = 0; r < S; ++r) {
@@ -1378,35 +1440,41 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             if (ns) {
                 int ub = bits_for(n ? n - 1 : 0);
                 int cb = bits_for(n ? n - 1 : 0);
-                int wb = bits_for((uint64_t)max_vertex_weight(h.vwgt, n, A, st));
+                if (wb < 0) wb = bits_for((uint64_t)max_vertex_weight(h.vwgt, n, A, st));  // once per pass
                 uint64_t *kk = B.keys;
                 uint32_t *vv = B.vals;
-                if (cb + wb + ub <= 64) {
-                    k_slow_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.slow, ns, B.ptarget, h.vwgt, wb,
-                                                                                   ub, kk, vv, true);
+                if (ns <= SLOW_SMALL && cb + wb + ub <= 64) {
+                    k_slow_small<<<1, SLOW_THREADS, 0, st>>>(B.slow, ns, B.ptarget, h.vwgt, B.cw, cap_mult, W, B.ok,
+                                                             wb, ub);
                     HGP_LAUNCH_CHECK();
-                    radix_sort_pairs<uint64_t>(A, &kk, &vv, kk == B.keys ? B.keys_alt : B.keys,
-                                               vv == B.vals ? B.vals_alt : B.vals, ns, 0, cb + wb + ub, st);
                 } else {
-                    // stable two-stage: by u, then by (C, c(u))
-                    k_u_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.slow, ns, kk, vv);
+                    if (cb + wb + ub <= 64) {
+                        k_slow_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.slow, ns, B.ptarget,
+                                                                                       h.vwgt, wb, ub, kk, vv, true);
+                        HGP_LAUNCH_CHECK();
+                        radix_sort_pairs<uint64_t>(A, &kk, &vv, kk == B.keys ? B.keys_alt : B.keys,
+                                                   vv == B.vals ? B.vals_alt : B.vals, ns, 0, cb + wb + ub, st);
+                    } else {
+                        // stable two-stage: by u, then by (C, c(u))
+                        k_u_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.slow, ns, kk, vv);
+                        HGP_LAUNCH_CHECK();
+                        radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, ub, st);
+                        uint64_t *k2 = (kk == B.keys) ? B.keys_alt : B.keys;
+                        uint32_t *v2 = (vv == B.vals) ? B.vals_alt : B.vals;
+                        k_slow_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(vv, ns, B.ptarget, h.vwgt,
+                                                                                       wb, 0, kk, v2, false);
+                        HGP_LAUNCH_CHECK();
+                        // kk holds keys aligned with v2 (= copy of vv)
+                        uint32_t *vcur = v2;
+                        radix_sort_pairs<uint64_t>(A, &kk, &vcur, k2, vv, ns, 0, cb + wb, st);
+                        vv = vcur;
+                    }
+                    scan_apply<uint64_t>(A, ns, WeightOfSorted{vv, h.vwgt}, StoreInclU64{B.incl},
+                                         (uint64_t *)nullptr, st);
+                    k_slow_decide<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(vv, ns, B.ptarget, B.incl,
+                                                                                     h.vwgt, B.cw, cap_mult, W, B.ok);
                     HGP_LAUNCH_CHECK();
-                    radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, ub, st);
-                    uint64_t *k2 = (kk == B.keys) ? B.keys_alt : B.keys;
-                    uint32_t *v2 = (vv == B.vals) ? B.vals_alt : B.vals;
-                    k_slow_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(vv, ns, B.ptarget, h.vwgt, wb, 0,
-                                                                                   kk, v2, false);
-                    HGP_LAUNCH_CHECK();
-                    // kk holds keys aligned with v2 (= copy of vv)
-                    uint32_t *vcur = v2;
-                    radix_sort_pairs<uint64_t>(A, &kk, &vcur, k2, vv, ns, 0, cb + wb, st);
-                    vv = vcur;
                 }
-                scan_apply<uint64_t>(A, ns, WeightOfSorted{vv, h.vwgt}, StoreInclU64{B.incl}, (uint64_t *)nullptr,
-                                     st);
-                k_slow_decide<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(vv, ns, B.ptarget, B.incl, h.vwgt,
-                                                                                 B.cw, cap_mult, W, B.ok);
-                HGP_LAUNCH_CHECK();
             }
             k_apply_joins<<<grid_for(cand, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.proposers, nprop, B.ptarget, B.ok,
                                                                                h.vwgt, rep, B.cw, B.tsum, ncl);
@@ -1415,7 +1483,8 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     }
     HGP_CHECK_HIP(hipMemcpyAsync(&cnt, ncl, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     stream_sync(st);
-    if (n_clusters_dev) HGP_CHECK_HIP(hipMemcpyAsync(n_clusters_dev, ncl, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    if (n_clusters_dev)
+        HGP_CHECK_HIP(hipMemcpyAsync(n_clusters_dev, ncl, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
     if (n_clusters_host) *n_clusters_host = cnt;
     A.release(mk);
 }

@@ -1184,7 +1184,8 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
 struct RefineBufs {
     void *nr;  // NetRec<KW>[m]
     int64_t *f, *bw;
-    uint32_t *longl, *dlists /* hub candidates */, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow, *mlist;
+    uint32_t *longl, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow, *mlist;
+    uint32_t *dlists;  // hub candidates of the sub-round
     uint32_t *pc, *pbase, *pcur, *spairs, *seg;  // per-pair proposal counts, segments of over-budget pairs
     int64_t *dbw_g;
     uint64_t *keys, *keys_alt, *incl;
