@@ -78,6 +78,35 @@ __global__ __launch_bounds__(BLOCK) void k_tile_scan(size_t n, In in, Out out, c
     }
 }
 
+// Short inputs (at most SCAN_SMALL_TILES tiles): one block walks the tiles in
+// order with a carry, one launch instead of three.
+constexpr size_t SCAN_SMALL_TILES = 4;
+template <class T, class In, class Out>
+__global__ __launch_bounds__(BLOCK) void k_scan_small(size_t n, In in, Out out, T *total) {
+    __shared__ T lds[BLOCK / WAVE];
+    T carry = 0;
+    for (size_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
+        const size_t base = t0 + (size_t)threadIdx.x * SCAN_ITEMS;
+        T v[SCAN_ITEMS];
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            v[i] = (base + i < n) ? in(base + i) : T(0);
+            s += v[i];
+        }
+        T tot;
+        const T incl = block_incl_scan<T>(s, lds, &tot);
+        T run = carry + incl - s;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            if (base + i < n) out(base + i, run, v[i]);
+            run += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
 // out(i, exclusive_prefix, value) is called for every i < n; *total_dev gets
 // the sum (may be nullptr).  Temporaries come from the arena and are released.
 template <class T, class In, class Out>
@@ -88,6 +117,12 @@ void scan_apply(Arena &A, size_t n, In in, Out out, T *total_dev, hipStream_t st
     if (A.measure) { A.release(mk); return; }
     if (n == 0) {
         if (total_dev) HGP_CHECK_HIP(hipMemsetAsync(total_dev, 0, sizeof(T), st));
+        A.release(mk);
+        return;
+    }
+    if (ntiles <= SCAN_SMALL_TILES) {
+        k_scan_small<T, In, Out><<<1, BLOCK, 0, st>>>(n, in, out, total_dev);
+        HGP_LAUNCH_CHECK();
         A.release(mk);
         return;
     }
