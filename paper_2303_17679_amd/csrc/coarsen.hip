@@ -39,8 +39,6 @@ struct RateArgs {
     const int64_t *tinfo;  // cluster weight of a valid target, TINFO_BAD otherwise
     uint32_t *ptarget;
     int64_t *tsum;
-    uint32_t *proposers;
-    uint32_t *nprop;
     uint64_t mseed;
     uint32_t level, r, S;
     int64_t cap_mult, W;
@@ -62,14 +60,17 @@ constexpr int64_t TINFO_BAD = (int64_t)1 << 34;
 
 // tinfo[C]: cw[C] if C may be joined in sub-round r, TINFO_BAD if C is itself
 // a candidate singleton of the sub-round (no chains within a sub-round).
+// Every vertex of the sub-round starts with no target.
 __global__ void k_target_info(const uint32_t *rep, const int64_t *cw, const int32_t *vwgt, uint32_t n,
                               uint64_t mseed, uint32_t level, uint32_t S, uint32_t r, int64_t *tinfo,
-                              const uint32_t *ncl) {
+                              uint32_t *ptarget, const uint32_t *ncl) {
     if (pass_cut(ncl, n)) return;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         int64_t c = cw[v];
-        bool cand = rep[v] == v && c == (int64_t)vwgt[v] && tag_hash(mseed, 1, level, 0, v) % S == r;
+        const bool mine = tag_hash(mseed, 1, level, 0, v) % S == r;
+        bool cand = rep[v] == v && c == (int64_t)vwgt[v] && mine;
         tinfo[v] = cand ? TINFO_BAD : c;
+        if (mine) ptarget[v] = NONE;
     }
 }
 
@@ -94,13 +95,14 @@ __device__ inline bool valid_target(const RateArgs &a, uint32_t u, uint32_t C) {
     return C != u && a.cap_mult * ((int64_t)a.vwgt[u] + a.tinfo[C]) <= a.W;
 }
 
-// Called by the publishing lanes only; the proposer list slot is reserved
-// with one atomic per wave.
+// Called by the publishing lanes only.  The sub-round's candidate list is
+// its proposer list: k_target_info has set ptarget to NONE for every
+// candidate, so no proposer is appended anywhere (a shared append counter
+// costs one serialised device-scope atomic per wave).
 __device__ inline void publish(const RateArgs &a, uint32_t u, uint32_t C) {
+    if (C == NONE) return;
     a.ptarget[u] = C;
-    if (C != NONE) atomic_add_i64(&a.tsum[C], (int64_t)a.vwgt[u]);
-    const uint32_t slot = warp_agg_append(a.nprop, C != NONE);
-    if (C != NONE) a.proposers[slot] = u;
+    atomic_add_i64(&a.tsum[C], (int64_t)a.vwgt[u]);
 }
 
 // Nets with at most LANE_NET pins are rated by a single lane: it loads the
@@ -809,16 +811,15 @@ __device__ inline int rate_class(uint64_t B) {
     return 4;
 }
 
-// B(u) = sum over incident nets of at least two pins of (|e| - 1), a bound
-// on the clusters a rating of u can touch.  Thread per vertex; a vertex of
-// more than 32 incident nets is summed by its whole wave.
-__global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, const uint32_t *inc_off,
-                                                    const uint32_t *inc, uint32_t n, uint32_t m, uint32_t *bound,
-                                                    uint32_t *maxsz) {
-    // largest net size of the level (decides whether the hub path needs its
-    // huge-net kernel)
+// Largest net size of the level, by the first NETMAX_BLOCKS blocks only: one
+// device-scope atomic per block (atomics on one address are serialised).
+constexpr uint32_t NETMAX_BLOCKS = 256;
+__device__ inline void net_size_max(const uint32_t *pin_off, uint32_t m, uint32_t *maxsz) {
+    if (blockIdx.x >= NETMAX_BLOCKS) return;
+    __shared__ uint32_t red[BLOCK / WAVE];
+    const uint32_t nb = gridDim.x < NETMAX_BLOCKS ? gridDim.x : NETMAX_BLOCKS;
     uint32_t mx = 0;
-    for (uint32_t e = blockIdx.x * BLOCK + threadIdx.x; e < m; e += gridDim.x * BLOCK) {
+    for (uint32_t e = blockIdx.x * BLOCK + threadIdx.x; e < m; e += nb * BLOCK) {
         const uint32_t sz = pin_off[e + 1] - pin_off[e];
         mx = sz > mx ? sz : mx;
     }
@@ -827,7 +828,23 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, con
         const uint32_t y = __shfl_xor(mx, o, 64);
         mx = y > mx ? y : mx;
     }
-    if (__lane_id() == 0 && mx) atomicMax(maxsz, mx);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < BLOCK / WAVE; ++q) mx = red[q] > mx ? red[q] : mx;
+        if (mx) atomicMax(maxsz, mx);
+    }
+}
+
+// B(u) = sum over incident nets of at least two pins of (|e| - 1), a bound
+// on the clusters a rating of u can touch.  Thread per vertex; a vertex of
+// more than 32 incident nets is summed by its whole wave.
+__global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, const uint32_t *inc_off,
+                                                    const uint32_t *inc, uint32_t n, uint32_t m, uint32_t *bound,
+                                                    uint32_t *maxsz) {
+    // largest net size of the level (decides whether the hub path needs its
+    // huge-net kernel)
+    net_size_max(pin_off, m, maxsz);
     for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
         const uint32_t u = u0 + threadIdx.x;
         uint32_t j0 = 0, j1 = 0;
@@ -863,17 +880,7 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, con
 __global__ __launch_bounds__(BLOCK) void k_vertex_b_wave(const uint32_t *pin_off, const uint32_t *inc_off,
                                                          const uint32_t *inc, uint32_t n, uint32_t m,
                                                          uint32_t *bound, uint32_t *maxsz) {
-    uint32_t mx = 0;
-    for (uint32_t e = blockIdx.x * BLOCK + threadIdx.x; e < m; e += gridDim.x * BLOCK) {
-        const uint32_t sz = pin_off[e + 1] - pin_off[e];
-        mx = sz > mx ? sz : mx;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t y = __shfl_xor(mx, o, 64);
-        mx = y > mx ? y : mx;
-    }
-    if (__lane_id() == 0 && mx) atomicMax(maxsz, mx);
+    net_size_max(pin_off, m, maxsz);
     const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nw = gridDim.x * BLOCK / WAVE;
     for (uint32_t u = wid; u < n; u += nw) {
         const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
@@ -889,12 +896,23 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_b_wave(const uint32_t *pin_off
 }
 
 // pass 1 (fill=false): count per (sub-round, class); pass 2: fill lists.
-// Counters are aggregated per block in LDS (one global atomic per key and
-// block), so millions of vertices never contend on a handful of addresses.
+// Counters are aggregated per block in LDS: each block adds its counts with
+// one global atomic per key (and in pass 2 reserves its ranges the same way),
+// so millions of vertices never contend on a handful of addresses.  At most
+// CLASSIFY_BLOCKS blocks, since atomics on one address are serialised.
 constexpr int MAX_KEYS = 256 * NCLASS;
+constexpr unsigned CLASSIFY_BLOCKS = 512;
 // The class of a candidate follows D = min(B(u), n - 1), a bound on the
 // distinct clusters it rates; counts[S * NCLASS] receives the largest D of
 // the global-table class.
+__device__ inline int classify_key(const uint32_t *bound, uint32_t n, uint64_t mseed, uint32_t level, uint32_t S,
+                                   uint32_t u, uint32_t *D) {
+    *D = bound[u] < n - 1 ? bound[u] : n - 1;
+    const int c = rate_class(*D);
+    if (c < 0) return -1;
+    return (int)((uint32_t)(tag_hash(mseed, 1, level, 0, u) % S) * NCLASS + c);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *bound, uint32_t n, uint64_t mseed,
                                                     uint32_t level, uint32_t S, const int32_t *vwgt, uint32_t *rep,
                                                     int64_t *cw, int64_t *tsum, uint32_t *counts, uint32_t *cursor,
@@ -906,60 +924,52 @@ __global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *bound, uint3
     for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) lcnt[i] = 0;
     if (threadIdx.x == 0) lmaxd = 0;
     __syncthreads();
-    for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
-        const uint32_t u = u0 + threadIdx.x;
-        int key = -1;
-        uint32_t lrank = 0;
-        if (u < n) {
-            const uint32_t D = bound[u] < n - 1 ? bound[u] : n - 1;
-            const int c = rate_class(D);
-            if (c == NCLASS - 1 && !fill) atomicMax(&lmaxd, D);
-            uint32_t r = (uint32_t)(tag_hash(mseed, 1, level, 0, u) % S);
-            if (!fill) {
-                rep[u] = u;
-                cw[u] = vwgt[u];
-                tsum[u] = 0;
-            }
-            if (c >= 0) {
-                key = (int)(r * NCLASS + c);
-                lrank = atomicAdd(&lcnt[key], 1u);
-            }
+    for (uint32_t u = blockIdx.x * BLOCK + threadIdx.x; u < n; u += gridDim.x * BLOCK) {
+        uint32_t D;
+        const int key = classify_key(bound, n, mseed, level, S, u, &D);
+        if (!fill) {
+            rep[u] = u;
+            cw[u] = vwgt[u];
+            tsum[u] = 0;
+            if (key >= 0 && (uint32_t)key % NCLASS == NCLASS - 1) atomicMax(&lmaxd, D);
         }
-        if (fill) {
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) {
-                uint32_t c = lcnt[i];
-                lbase[i] = c ? atomicAdd(&cursor[i], c) : 0u;
-            }
-            __syncthreads();
-            if (key >= 0) lists[lbase[key] + lrank] = u;
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) lcnt[i] = 0;
-            __syncthreads();
-        }
+        if (key >= 0) atomicAdd(&lcnt[key], 1u);
     }
+    __syncthreads();
     if (!fill) {
-        __syncthreads();
         for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK)
             if (lcnt[i]) atomicAdd(&counts[i], lcnt[i]);
         if (threadIdx.x == 0 && lmaxd) atomicMax(&counts[nkeys], lmaxd);
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) {
+        const uint32_t c = lcnt[i];
+        lbase[i] = c ? atomicAdd(&cursor[i], c) : 0u;
+        lcnt[i] = 0;
+    }
+    __syncthreads();
+    for (uint32_t u = blockIdx.x * BLOCK + threadIdx.x; u < n; u += gridDim.x * BLOCK) {
+        uint32_t D;
+        const int key = classify_key(bound, n, mseed, level, S, u, &D);
+        if (key >= 0) lists[lbase[key] + atomicAdd(&lcnt[key], 1u)] = u;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Approval and apply
 // ---------------------------------------------------------------------------
-__global__ void k_approve_fast(const uint32_t *proposers, const uint32_t *np_dev, const uint32_t *ptarget,
-                               const int64_t *cw, const int64_t *tsum, int64_t cap_mult, int64_t W,
-                               uint8_t *ok, uint32_t *slow, uint32_t *nslow) {
-    const uint32_t np = *np_dev;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ((np + 63) / 64) * 64;
+// Proposers are the candidates of the sub-round's list whose target is set.
+__global__ void k_approve_fast(const uint32_t *cands, uint32_t nc, const uint32_t *ptarget, const int64_t *cw,
+                               const int64_t *tsum, int64_t cap_mult, int64_t W, uint8_t *ok, uint32_t *slow,
+                               uint32_t *nslow, const uint32_t *ncl, uint32_t n) {
+    if (pass_cut(ncl, n)) return;  // nothing was rated
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ((nc + 63) / 64) * 64;
          i += gridDim.x * blockDim.x) {
-        bool act = i < np;
-        uint32_t u = act ? proposers[i] : 0;
+        const uint32_t u = i < nc ? cands[i] : 0;
+        const uint32_t C = i < nc ? ptarget[u] : NONE;
+        const bool act = C != NONE;
         bool fits = true;
         if (act) {
-            uint32_t C = ptarget[u];
             fits = cap_mult * (cw[C] + tsum[C]) <= W;
             ok[u] = fits ? 1 : 0;
         }
@@ -1077,26 +1087,32 @@ __global__ __launch_bounds__(SLOW_THREADS) void k_slow_small(const uint32_t *slo
     }
 }
 
-__global__ void k_apply_joins(const uint32_t *proposers, const uint32_t *np_dev, const uint32_t *ptarget,
-                              const uint8_t *ok, const int32_t *vwgt, uint32_t *rep, int64_t *cw, int64_t *tsum,
-                              uint32_t *n_clusters) {
-    const uint32_t np = *np_dev;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ((np + 63) / 64) * 64;
-         i += gridDim.x * blockDim.x) {
-        bool act = i < np;
-        bool join = false;
-        if (act) {
-            uint32_t u = proposers[i];
-            uint32_t C = ptarget[u];
-            tsum[C] = 0;
-            if (ok[u]) {
-                join = true;
-                rep[u] = C;
-                atomic_add_i64(&cw[C], (int64_t)vwgt[u]);
-            }
+// The joins of a block are counted in LDS and leave the cluster count with
+// one atomic per block (APPLY_BLOCKS at most).
+constexpr unsigned APPLY_BLOCKS = 512;
+__global__ __launch_bounds__(BLOCK) void k_apply_joins(const uint32_t *cands, uint32_t nc, const uint32_t *ptarget,
+                                                       const uint8_t *ok, const int32_t *vwgt, uint32_t *rep,
+                                                       int64_t *cw, int64_t *tsum, uint32_t *n_clusters) {
+    __shared__ uint32_t red[BLOCK / WAVE];
+    uint32_t joins = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+        const uint32_t u = cands[i];
+        const uint32_t C = ptarget[u];
+        if (C == NONE) continue;
+        tsum[C] = 0;
+        if (ok[u]) {
+            ++joins;
+            rep[u] = C;
+            atomic_add_i64(&cw[C], (int64_t)vwgt[u]);
         }
-        uint64_t m = __ballot(join);
-        if (__lane_id() == 0 && m) atomicSub(n_clusters, (uint32_t)__popcll(m));
+    }
+    joins = wave_sum(joins);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = joins;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+        if (t) atomicSub(n_clusters, t);
     }
 }
 
@@ -1106,7 +1122,7 @@ __global__ void k_apply_joins(const uint32_t *proposers, const uint32_t *np_dev,
 struct CoarsenBufs {
     uint64_t *nscore;
     int64_t *cw, *tsum, *tinfo;
-    uint32_t *ptarget, *proposers, *slow, *lists, *counts, *cursor, *scal;
+    uint32_t *ptarget, *slow, *lists, *counts, *cursor, *scal;
     uint8_t *ok;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt;
@@ -1134,7 +1150,6 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, uint32_t S, Coars
     B.tsum = A.alloc<int64_t>(n);
     B.tinfo = A.alloc<int64_t>(n);
     B.ptarget = A.alloc<uint32_t>(n);
-    B.proposers = A.alloc<uint32_t>(n);
     B.slow = A.alloc<uint32_t>(n);
     B.lists = A.alloc<uint32_t>(n);
     B.counts = A.alloc<uint32_t>((size_t)S * NCLASS + 2);  // + largest D, largest net
@@ -1212,7 +1227,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
         k_vertex_b<<<grid_for(std::max(n, m), BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
             h.pin_off, h.inc_off, h.inc, n, m, B.bound, B.counts + S * NCLASS + 1);
     HGP_LAUNCH_CHECK();
-    k_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
+    k_classify<<<grid_for(n, BLOCK, CLASSIFY_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
                                                                  B.tsum, B.counts, B.cursor, B.lists, false);
     HGP_LAUNCH_CHECK();
     std::vector<uint32_t> counts(S * NCLASS + 2), offs(S * NCLASS + 1);
@@ -1373,21 +1388,22 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     offs[0] = 0;
     for (uint32_t i = 0; i < S * NCLASS; ++i) offs[i + 1] = offs[i] + counts[i];
     HGP_CHECK_HIP(hipMemcpyAsync(B.cursor, offs.data(), sizeof(uint32_t) * S * NCLASS, hipMemcpyHostToDevice, st));
-    k_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
+    k_classify<<<grid_for(n, BLOCK, CLASSIFY_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
                                                                  B.tsum, B.counts, B.cursor, B.lists, true);
     HGP_LAUNCH_CHECK();
 
     uint32_t cnt = n;
     int wb = -1;  // bits of the largest vertex weight (read when the sorted approval first runs)
-    uint32_t *nprop = B.scal + 0, *nslow = B.scal + 1, *ncl = B.scal + 2;
+    uint32_t *nslow = B.scal + 1, *ncl = B.scal + 2;
     HGP_CHECK_HIP(hipMemcpyAsync(ncl, &cnt, sizeof(uint32_t), hipMemcpyHostToDevice, st));
     for (uint32_t r = 0; r < S; ++r) {
         HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 2, st));
         k_target_info<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(rep, B.cw, h.vwgt, n, mseed, level, S, r,
-                                                                        B.tinfo, ncl);
+                                                                        B.tinfo, B.ptarget, ncl);
         HGP_LAUNCH_CHECK();
         RateArgs a{h.pin_off, h.pins, h.inc_off, h.inc, h.vwgt, B.nscore, rep, B.cw, B.tinfo, B.ptarget, B.tsum,
-                   B.proposers, nprop, mseed, level, r, S, cap_mult, W, r > 0, ncl, n};
+                   mseed, level, r, S, cap_mult, W, r > 0, ncl, n};
+        const uint32_t *cands = B.lists + offs[r * NCLASS];  // the sub-round's candidates, all classes
         uint32_t cand = 0;  // candidates listed for the sub-round: a bound on its proposals
         for (int c = 0; c < NCLASS; ++c) cand += counts[r * NCLASS + c];
         for (int c = 0; c < NCLASS; ++c) {
@@ -1425,9 +1441,9 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             HGP_LAUNCH_CHECK();
         }
         if (cand) {
-            k_approve_fast<<<grid_for(cand, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.proposers, nprop, B.ptarget, B.cw,
+            k_approve_fast<<<grid_for(cand, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(cands, cand, B.ptarget, B.cw,
                                                                                 B.tsum, cap_mult, W, B.ok, B.slow,
-                                                                                nslow);
+                                                                                nslow, ncl, n);
             HGP_LAUNCH_CHECK();
             // one read-back per sub-round: the joins that need the sorted
             // approval, and the cluster count after the previous sub-round
@@ -1476,8 +1492,8 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                     HGP_LAUNCH_CHECK();
                 }
             }
-            k_apply_joins<<<grid_for(cand, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.proposers, nprop, B.ptarget, B.ok,
-                                                                               h.vwgt, rep, B.cw, B.tsum, ncl);
+            k_apply_joins<<<grid_for(cand, BLOCK, APPLY_BLOCKS), BLOCK, 0, st>>>(cands, cand, B.ptarget, B.ok,
+                                                                                h.vwgt, rep, B.cw, B.tsum, ncl);
             HGP_LAUNCH_CHECK();
         }
     }

@@ -40,11 +40,13 @@ __device__ inline void sort16(uint32_t (&r)[16]) {
     }
 }
 
-// Small segments: sort (+unique).  Segments longer than SEG_SMALL are
-// appended to the wave / medium / large lists.
+// Small segments: sort (+unique).  Segments longer than SEG_MED and up to
+// SEG_MED are appended to the large / medium lists; segments of the wave tier
+// are only flagged (a plain store): k_seg_wave finds them itself, since they
+// can be as many as the segments and a shared append counter costs one
+// serialised device-scope atomic per wave.
 __global__ void k_seg_small(const uint32_t *off, uint32_t nseg, uint32_t *data, bool uniq, uint32_t *usize,
-                            uint32_t *med, uint32_t *nmed, uint32_t *large, uint32_t *nlarge, uint32_t *wavel,
-                            uint32_t *nwave) {
+                            uint32_t *med, uint32_t *nmed, uint32_t *large, uint32_t *nlarge, uint32_t *wflag) {
     for (uint32_t s0 = blockIdx.x * blockDim.x; s0 < nseg; s0 += gridDim.x * blockDim.x) {
         uint32_t s = s0 + threadIdx.x;
         bool act = s < nseg;
@@ -52,8 +54,7 @@ __global__ void k_seg_small(const uint32_t *off, uint32_t nseg, uint32_t *data, 
         bool iswave = act && len > SEG_SMALL && len <= SEG_WAVE;
         bool ismed = act && len > SEG_WAVE && len <= SEG_MED;
         bool islarge = act && len > SEG_MED;
-        uint32_t pw = warp_agg_append(nwave, iswave);
-        if (iswave) wavel[pw] = s;
+        if (__ballot(iswave) && __lane_id() == 0) *wflag = 1u;
         uint32_t pm = warp_agg_append(nmed, ismed);
         if (ismed) med[pm] = s;
         uint32_t pl = warp_agg_append(nlarge, islarge);
@@ -83,12 +84,18 @@ __global__ void k_seg_small(const uint32_t *off, uint32_t nseg, uint32_t *data, 
 
 // Segments of SEG_SMALL+1 .. SEG_WAVE values: one wave each, a value per lane,
 // bitonic sort by shuffles; the distinct values are compacted by a ballot.
-__global__ __launch_bounds__(BLOCK) void k_seg_wave(const uint32_t *off, const uint32_t *list, uint32_t count,
-                                                    uint32_t *data, bool uniq, uint32_t *usize) {
+// A wave takes 64 consecutive segments at a time and sorts those of the tier.
+__global__ __launch_bounds__(BLOCK) void k_seg_wave(const uint32_t *off, uint32_t nseg, uint32_t *data, bool uniq,
+                                                    uint32_t *usize) {
     const uint32_t lane = __lane_id();
     const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nw = gridDim.x * BLOCK / WAVE;
-    for (uint32_t idx = wid; idx < count; idx += nw) {
-        const uint32_t s = list[idx];
+    for (uint32_t s0 = wid * WAVE; s0 < nseg; s0 += nw * WAVE) {
+      const uint32_t sl = s0 + lane;
+      const uint32_t ll = sl < nseg ? off[sl + 1] - off[sl] : 0;
+      uint64_t todo = __ballot(ll > SEG_SMALL && ll <= SEG_WAVE);
+      while (todo) {
+        const uint32_t s = s0 + (uint32_t)(__ffsll((long long)todo) - 1);
+        todo &= todo - 1;
         const uint32_t b = off[s], len = off[s + 1] - b;
         uint32_t x = lane < len ? data[b + lane] : 0xFFFFFFFFu;
 #pragma unroll
@@ -109,6 +116,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg_wave(const uint32_t *off, const u
             if (keep) data[b + (uint32_t)__popcll(mk & lanemask_lt())] = x;
             if (lane == 0) usize[s] = (uint32_t)__popcll(mk);
         }
+      }
     }
 }
 
@@ -204,7 +212,7 @@ struct LargeLen {
 };
 
 struct SegSortBufs {
-    uint32_t *med, *large, *wavel, *scal;
+    uint32_t *med, *large, *scal;
     uint64_t *pos, *keys, *keys_alt;
     uint32_t *vals, *vals_alt;
 };
@@ -212,7 +220,6 @@ struct SegSortBufs {
 // Workspace for segments holding at most `total` values.
 inline void segsort_plan(Arena &A, uint32_t nseg, size_t total, SegSortBufs &B) {
     B.med = A.alloc<uint32_t>(nseg);
-    B.wavel = A.alloc<uint32_t>(nseg);
     B.large = A.alloc<uint32_t>(total / SEG_MED + 1);
     B.scal = A.alloc<uint32_t>(6);
     B.pos = A.alloc<uint64_t>(total / SEG_MED + 2);
@@ -230,14 +237,13 @@ inline void segmented_sort(Arena &A, const SegSortBufs &B, const uint32_t *off, 
     HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 6, st));  // callers read the counts
     if (nseg == 0) return;
     k_seg_small<<<grid_for(nseg, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(off, nseg, data, uniq, usize, B.med, B.scal,
-                                                                     B.large, B.scal + 1, B.wavel, B.scal + 4);
+                                                                     B.large, B.scal + 1, B.scal + 4);
     HGP_LAUNCH_CHECK();
     uint32_t cnt[5];
     HGP_CHECK_HIP(hipMemcpyAsync(cnt, B.scal, sizeof(cnt), hipMemcpyDeviceToHost, st));
     stream_sync(st);
-    if (cnt[4]) {
-        k_seg_wave<<<grid_for((size_t)cnt[4] * WAVE, BLOCK, 8192), BLOCK, 0, st>>>(off, B.wavel, cnt[4], data, uniq,
-                                                                                   usize);
+    if (cnt[4]) {  // some segment of the wave tier
+        k_seg_wave<<<grid_for(nseg, BLOCK, 8192), BLOCK, 0, st>>>(off, nseg, data, uniq, usize);
         HGP_LAUNCH_CHECK();
     }
     if (cnt[0]) {
