@@ -188,6 +188,24 @@ __device__ inline void atomic_add_i64(int64_t *p, int64_t v) {
     atomicAdd((unsigned long long *)p, (unsigned long long)v);
 }
 
+// Device-scope atomics on one address are serialised (about 80 million per
+// second on the whole chip), so accumulators that every workgroup feeds are
+// spread over SPREAD slots 128 bytes apart: a workgroup adds into slot
+// blockIdx.x % SPREAD and the reader sums the slots.
+constexpr uint32_t SPREAD = 64;
+constexpr uint32_t SPREAD_I64 = 16;  // slot stride in int64 (128 bytes)
+constexpr uint32_t SPREAD_U32 = 32;  // slot stride in uint32 (128 bytes)
+__device__ inline void spread_add_i64(int64_t *acc, int64_t v) {
+    atomicAdd((unsigned long long *)&acc[(blockIdx.x % SPREAD) * SPREAD_I64], (unsigned long long)v);
+}
+// Sum of a spread accumulator by one wave (lane i reads slot i).
+__device__ inline int64_t spread_total_wave(const int64_t *acc) {
+    int64_t x = acc[(__lane_id() % SPREAD) * SPREAD_I64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
 __device__ inline uint32_t warp_agg_append(uint32_t *counter, bool pred) {
     // Returns the slot of this lane in an append-only list (only valid if pred).
     uint64_t m = __ballot(pred);

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(BLOCK) void k_conn_small(const uint32_t *pin_off, c
     if (threadIdx.x == 0) {
         int64_t t = 0;
         for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
-        if (t) atomic_add_i64(f, t);
+        if (t) spread_add_i64(f, t);
     }
 }
 
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(BLOCK) void k_conn_long(const uint32_t *pin_off, co
             }
             R.w = nwgt[e];
             nr[e] = R;
-            if (d) atomic_add_i64(f, d * R.w);
+            if (d) spread_add_i64(f, d * R.w);
         }
         if (delta && bcnt && (lnew > 1) != (lold > 1)) {
             const uint32_t dl = lnew > 1 ? 1u : 0xFFFFFFFFu;
@@ -208,32 +208,36 @@ struct GainArgs {
     int64_t lmax;
     uint64_t mseed;
     uint32_t level, round, sub, S, n;
-    uint32_t *prop_t, *prop_g, *plist, *nprop, *gmax;
+    uint32_t *prop_t, *prop_g;
+    // proposals: NSLOT lists, list j (at plist + j * slot_cap, its length
+    // in pcnt[j * SPREAD_U32]) holds the proposers of the vertex chunks
+    // c = j (mod NSLOT), chunks of `ch` consecutive vertices
+    uint32_t *plist, *pcnt;
+    uint32_t ch, slot_cap;
     uint32_t *pw;  // [k*k] total weight proposed per ordered block pair
     uint32_t *pc;  // [k*k] number of proposals per ordered block pair
     uint32_t k;
     const uint32_t *abort;  // set when the round must be resumed by the host
 };
 
+// Proposal lists: NSLOT lists by vertex chunk (see GainArgs).  A list holds
+// at most the vertices of its chunks, ceil(chunks / NSLOT) * ch.
+constexpr uint32_t NSLOT = SPREAD;
+
 // Called by every lane of the wave (uniformly); `has` is set by at most one
-// lane per proposing vertex.
+// lane per proposing vertex, and every proposing lane of the call belongs
+// to list `slot`.
 template <int KW>
-__device__ inline void propose(const GainArgs<KW> &a, uint32_t u, uint32_t s, uint32_t t, uint32_t g, bool has) {
-    uint32_t pos = warp_agg_append(a.nprop, has);
+__device__ inline void propose(const GainArgs<KW> &a, uint32_t u, uint32_t s, uint32_t t, uint32_t g, bool has,
+                               uint32_t slot) {
+    const uint32_t pos = warp_agg_append(&a.pcnt[slot * SPREAD_U32], has);
     if (has) {
-        a.plist[pos] = u;
+        a.plist[(size_t)slot * a.slot_cap + pos] = u;
         a.prop_t[u] = t;
         a.prop_g[u] = g;
         atomicAdd(&a.pw[s * a.k + t], (uint32_t)a.vwgt[u]);
         atomicAdd(&a.pc[s * a.k + t], 1u);
     }
-    uint32_t gm = has ? g : 0u;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint32_t x = __shfl_xor(gm, o, 64);
-        gm = x > gm ? x : gm;
-    }
-    if (__lane_id() == 0 && gm) atomicMax(a.gmax, gm);
 }
 
 template <int G, class T>
@@ -252,7 +256,7 @@ __device__ inline T group_sum(T v) {
 // any is used.
 template <int KW, int G>
 __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, uint32_t count, uint32_t blk,
-                                  uint32_t nblk) {
+                                  uint32_t nblk, uint32_t slot) {
     constexpr int GPB = BLOCK / G;
     constexpr bool CACHE = G < 64;
     constexpr int NC = CACHE ? 8 : 1;
@@ -373,7 +377,7 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
                 wave_sync();  // the histogram is read before the next node clears it
             }
         }
-        propose(a, u, s, best_t, best_g, act && l == 0 && best_t != NONE);
+        propose(a, u, s, best_t, best_g, act && l == 0 && best_t != NONE, slot);
     }
 }
 
@@ -410,9 +414,9 @@ __global__ __launch_bounds__(BLOCK) void k_gains(GainArgs<KW> a, uint32_t ch, ui
             else lst[cls][atomicAdd(&lcnt[cls], 1u)] = v;
         }
         __syncthreads();
-        gains_body<KW, 1>(a, lst[0], lcnt[0], 0, 1);
-        gains_body<KW, 8>(a, lst[1], lcnt[1], 0, 1);
-        gains_body<KW, 64>(a, lst[2], lcnt[2], 0, 1);
+        gains_body<KW, 1>(a, lst[0], lcnt[0], 0, 1, c % NSLOT);
+        gains_body<KW, 8>(a, lst[1], lcnt[1], 0, 1, c % NSLOT);
+        gains_body<KW, 64>(a, lst[2], lcnt[2], 0, 1, c % NSLOT);
         __syncthreads();  // the lists are rewritten by the next chunk
     }
 }
@@ -498,7 +502,7 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
                 const uint32_t og = __shfl_xor(best_g, o, 64), ot = __shfl_xor(best_t, o, 64);
                 if (og > best_g || (og == best_g && ot < best_t)) { best_g = og; best_t = ot; }
             }
-            propose(a, u, s, best_t, best_g, __lane_id() == 0 && best_t != NONE);
+            propose(a, u, s, best_t, best_g, __lane_id() == 0 && best_t != NONE, (u / a.ch) % NSLOT);
         }
         __syncthreads();  // the histogram is read before the next node clears it
     }
@@ -716,14 +720,13 @@ __global__ void k_lp_select(const uint64_t *keys, uint32_t np, KeyLayout L, uint
 __global__ __launch_bounds__(BLOCK) void k_lp_apply(const uint64_t *keys, const uint32_t *vals, uint32_t np,
                                                     KeyLayout L, uint32_t k, const uint32_t *seg_start,
                                                     const unsigned long long *best, const int32_t *vwgt,
-                                                    uint32_t *part, int64_t *bw, uint32_t *mlist, uint32_t *nmov) {
+                                                    uint32_t *part, int64_t *bw) {
     __shared__ int64_t dbw[256];
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
     __syncthreads();
     for (uint32_t base = blockIdx.x * BLOCK; base < np; base += gridDim.x * BLOCK) {
         const uint32_t i = base + threadIdx.x;
         bool mv = false;
-        uint32_t u = 0;
         if (i < np) {
             uint64_t key = keys[i];
             uint32_t s = (uint32_t)(key >> L.sh_s) & L.kmask;
@@ -738,15 +741,13 @@ __global__ __launch_bounds__(BLOCK) void k_lp_apply(const uint64_t *keys, const 
                 mv = (s == x) ? (loc < istar) : (loc < jstar);
             }
             if (mv) {
-                u = vals[i];
+                const uint32_t u = vals[i];
                 part[u] = t;
                 int64_t c = vwgt[u];
                 atomicAdd((unsigned long long *)&dbw[s], (unsigned long long)(-c));
                 atomicAdd((unsigned long long *)&dbw[t], (unsigned long long)c);
             }
         }
-        uint32_t pos = warp_agg_append(nmov, mv);
-        if (mv) mlist[pos] = u;
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK)
@@ -760,34 +761,33 @@ __global__ __launch_bounds__(BLOCK) void k_lp_apply(const uint64_t *keys, const 
 // -beta_x <= w(M_xy) - w(M_yx) <= beta_y all moves of the pair are applied at
 // once, in any order, and only the remaining pairs need the sorted walk.
 // Block-weight changes go to dbw_g so that the sorted walk still reads the
-// snapshot block weights.  Movers are appended to the sub-round's mover list.
-// The proposals of the other pairs go to their pair's segment of `seg`
-// (k_pair_plan has laid the segments out).
+// snapshot block weights.  Movers are not listed: a proposer has moved iff
+// its block is now its proposed target.  The proposals of the other pairs go
+// to their pair's segment of `seg` (k_pair_plan has laid the segments out).
+// Workgroup b reads proposal list b % NSLOT (the grid is a multiple of NSLOT).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const uint32_t *np_dev,
+__global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const uint32_t *pcnt, uint32_t slot_cap,
                                                    const uint32_t *prop_t, const uint32_t *pw, uint32_t k,
                                                    const int32_t *vwgt, uint32_t *part, const int64_t *bw,
-                                                   int64_t lmax, int64_t *dbw_g, uint32_t *mlist, uint32_t *moves,
-                                                   const uint32_t *pbase, uint32_t *pcur, uint32_t *seg,
-                                                   const uint32_t *abort) {
+                                                   int64_t lmax, int64_t *dbw_g, const uint32_t *pbase,
+                                                   uint32_t *pcur, uint32_t *seg, const uint32_t *abort) {
     if (*abort) return;
     __shared__ int64_t dbw[256];
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
     __syncthreads();
-    const uint32_t np = *np_dev;
-    for (uint32_t base = blockIdx.x * BLOCK; base < np; base += gridDim.x * BLOCK) {
+    const uint32_t sl = blockIdx.x % NSLOT, bj = blockIdx.x / NSLOT, nbj = gridDim.x / NSLOT;
+    const uint32_t np = pcnt[sl * SPREAD_U32];
+    const uint32_t *pl = plist + (size_t)sl * slot_cap;
+    for (uint32_t base = bj * BLOCK; base < np; base += nbj * BLOCK) {
         const uint32_t i = base + threadIdx.x;
-        bool mv = false;
-        uint32_t u = 0;
         if (i < np) {
-            u = plist[i];
+            const uint32_t u = pl[i];
             const uint32_t s = part[u], t = prop_t[u];
             const uint32_t x = s < t ? s : t, y = s < t ? t : s;
             const int64_t xf = (int64_t)pw[x * k + y] - (int64_t)pw[y * k + x];
             const int64_t beta_x = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
             const int64_t beta_y = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
             if (-beta_x <= xf && xf <= beta_y) {
-                mv = true;
                 part[u] = t;
                 int64_t c = vwgt[u];
                 atomicAdd((unsigned long long *)&dbw[s], (unsigned long long)(-c));
@@ -797,8 +797,6 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
                 seg[pbase[pi] + atomicAdd(&pcur[pi], 1u)] = u;
             }
         }
-        uint32_t mp = warp_agg_append(moves, mv);
-        if (mv) mlist[mp] = u;
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK)
@@ -808,6 +806,34 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
 __global__ void k_add_dbw(int64_t *bw, int64_t *dbw_g, uint32_t k) {
     for (uint32_t b = threadIdx.x; b < k; b += blockDim.x)
         if (dbw_g[b]) { bw[b] += dbw_g[b]; dbw_g[b] = 0; }
+}
+
+// Total of the spread objective accumulator (one wave).
+__global__ void k_objective_total(const int64_t *f, int64_t *out) {
+    const int64_t t = spread_total_wave(f);
+    if (threadIdx.x == 0) *out = t;
+}
+
+// Largest proposed gain of the device-wide path's proposals.
+__global__ __launch_bounds__(BLOCK) void k_gain_max(const uint32_t *list, uint32_t cnt, const uint32_t *prop_g,
+                                                    uint32_t *out) {
+    __shared__ uint32_t red[BLOCK / WAVE];
+    uint32_t mx = 0;
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < cnt; i += gridDim.x * BLOCK) {
+        const uint32_t g = prop_g[list[i]];
+        mx = g > mx ? g : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_xor(mx, o, 64);
+        mx = y > mx ? y : mx;
+    }
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < BLOCK / WAVE; ++q) mx = red[q] > mx ? red[q] : mx;
+        if (mx) atomicMax(out, mx);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -915,9 +941,8 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *spair
                                                            const uint32_t *pbase, const uint32_t *pc,
                                                            const uint32_t *seg, uint32_t k, const uint32_t *prop_g,
                                                            const int32_t *vwgt, uint32_t *part, const int64_t *bw,
-                                                           int64_t lmax, int64_t *dbw_g, uint32_t *mlist,
-                                                           uint32_t *nmov, uint32_t *slow, uint32_t *nslow,
-                                                           uint32_t *abort, uint32_t sub_id) {
+                                                           int64_t lmax, int64_t *dbw_g, uint32_t *slow,
+                                                           uint32_t *nslow, uint32_t *abort, uint32_t sub_id) {
     __shared__ uint64_t skey[PAIR_MAX];
     __shared__ uint32_t sincl[PAIR_MAX];
     __shared__ uint32_t wsum[PAIR_THREADS / WAVE];
@@ -1005,14 +1030,8 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *spair
             istar = (uint32_t)bst;
             jstar = (uint32_t)(bst >> 32) - 1 - istar;
         }
-        for (uint32_t c0 = 0; c0 < L; c0 += PAIR_THREADS) {
-            const uint32_t i = c0 + tid;
-            const bool mv = i < L && (i < nA ? i < istar : i - nA < jstar);
-            const uint32_t u = i < L ? (uint32_t)(skey[i] & 0x7FFFFFFFu) : 0u;
-            if (mv) part[u] = i < nA ? y : x;
-            const uint32_t pos = warp_agg_append(nmov, mv);
-            if (mv) mlist[pos] = u;
-        }
+        for (uint32_t i = tid; i < L; i += PAIR_THREADS)
+            if (i < nA ? i < istar : i - nA < jstar) part[(uint32_t)(skey[i] & 0x7FFFFFFFu)] = i < nA ? y : x;
         if (tid == 0 && bst) {
             const int64_t wa = A.excl(istar), wb = Bv.excl(jstar);
             if (wa != wb) {
@@ -1029,16 +1048,21 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *spair
 // their blocks, weight, old Lambda and new Lambda / Lambda1).
 template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_account_update(const uint32_t *pin_off, const uint32_t *inc_off,
-                                                          const uint32_t *inc, const uint32_t *mlist,
-                                                          const uint32_t *nmov, uint32_t *nmark, uint32_t stamp,
-                                                          unsigned long long *acc) {
+                                                          const uint32_t *inc, const uint32_t *plist,
+                                                          const uint32_t *pcnt, uint32_t slot_cap,
+                                                          const uint32_t *part, const uint32_t *prop_t,
+                                                          uint32_t *nmark, uint32_t stamp, unsigned long long *acc) {
     __shared__ unsigned long long red[BLOCK / WAVE];
     unsigned long long bytes = 0;
-    const uint32_t cnt = *nmov;
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < cnt; idx += gridDim.x * blockDim.x) {
-        const uint32_t u = mlist[idx];
+    const uint32_t sl = blockIdx.x % NSLOT, bj = blockIdx.x / NSLOT, nbj = gridDim.x / NSLOT;
+    const uint32_t cnt = pcnt[sl * SPREAD_U32];
+    const uint32_t *pl = plist + (size_t)sl * slot_cap;
+    for (uint32_t idx = bj * blockDim.x + threadIdx.x; idx < cnt; idx += nbj * blockDim.x) {
+        const uint32_t u = pl[idx];
+        bytes += 4 + 4 + 4;  // proposal entry, block, target
+        if (part[u] != prop_t[u]) continue;
         const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
-        bytes += 4 + 8 + 4ull * (j1 - j0);
+        bytes += 8 + 4ull * (j1 - j0);
         for (uint32_t j = j0; j < j1; ++j) {
             const uint32_t e = inc[j];
             if (atomicExch(&nmark[e], stamp) == stamp) continue;
@@ -1112,7 +1136,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_heavy(const uint32_t *pin_o
     if (threadIdx.x == 0) {
         int64_t t = 0;
         for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
-        if (t) atomic_add_i64(f, t);
+        if (t) spread_add_i64(f, t);
     }
 }
 
@@ -1125,14 +1149,18 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_heavy(const uint32_t *pin_o
 // sums at zero, and this sub-round's block-weight changes in the block
 // weights.  Cleared by the last kernel of a sub-round that every sub-round
 // runs (the update), after every reader.
+// The proposal-list lengths come in two sets used by alternate sub-rounds:
+// the update reads its own sub-round's set and clears the other one.
 struct NextSub {
     uint32_t *scal, *pw, *pc;
     uint32_t kk, k;
     int64_t *bw, *dbw_g;
+    uint32_t *pcnt_next;
 };
 __device__ inline void next_subround(const NextSub &z) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
-    if (tid == 0) { z.scal[0] = 0; z.scal[1] = 0; z.scal[26] = 0; }  // nprop, gmax, hub candidates
+    if (tid == 0) z.scal[26] = 0;  // hub candidates
+    if (tid < NSLOT) z.pcnt_next[tid * SPREAD_U32] = 0;
     for (uint32_t i = tid; i < z.kk; i += nt) { z.pw[i] = 0; z.pc[i] = 0; }
     if (blockIdx.x == 0)
         for (uint32_t b = threadIdx.x; b < z.k; b += blockDim.x) {
@@ -1141,10 +1169,14 @@ __device__ inline void next_subround(const NextSub &z) {
         }
 }
 
+// The movers are the proposers now in their target block; workgroup b reads
+// proposal list b % NSLOT (the grid is a multiple of NSLOT).  `moves` is set
+// when the sub-round moved a node.
 template <int KW, int G>
 __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_off, const uint32_t *pins,
                                                             const uint32_t *inc_off, const uint32_t *inc,
-                                                            const uint32_t *mlist, const uint32_t *nmov,
+                                                            const uint32_t *plist, const uint32_t *pcnt,
+                                                            uint32_t slot_cap, const uint32_t *prop_t,
                                                             const uint32_t *part, NetRec<KW> *nr, uint32_t *tstamp,
                                                             uint32_t stamp, int64_t *f, uint32_t *longl,
                                                             uint32_t *nlong, uint32_t *moves, uint32_t *bcnt,
@@ -1153,13 +1185,20 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
     if (*abort) return;
     next_subround(z);
     __shared__ int64_t red[BLOCK / WAVE];
+    __shared__ uint32_t moved_any;
     constexpr int GPB = BLOCK / G;
-    const uint32_t cnt = *nmov;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && cnt) atomicAdd(moves, cnt);
+    const uint32_t sl = blockIdx.x % NSLOT, bj = blockIdx.x / NSLOT, nbj = gridDim.x / NSLOT;
+    const uint32_t cnt = pcnt[sl * SPREAD_U32];
+    const uint32_t *pl = plist + (size_t)sl * slot_cap;
+    if (threadIdx.x == 0) moved_any = 0;
+    __syncthreads();
     const uint32_t g = threadIdx.x / G, l = threadIdx.x % G;
     int64_t acc = 0;
-    for (uint32_t idx = blockIdx.x * GPB + g; idx < cnt; idx += gridDim.x * GPB) {
-        const uint32_t u = mlist[idx];
+    bool moved = false;
+    for (uint32_t idx = bj * GPB + g; idx < cnt; idx += nbj * GPB) {
+        const uint32_t u = pl[idx];
+        if (part[u] != prop_t[u]) continue;  // proposed but not moved (uniform per group)
+        moved = true;
         const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
         if (j1 - j0 > HUB_DEG) {  // uniform per group: left to the chunked kernel
             if (l == 0) heavy[atomicAdd(nheavy, 1u)] = u;
@@ -1169,12 +1208,14 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
             acc += update_net<KW>(pin_off, pins, inc[j], part, nr, tstamp, stamp, longl, nlong, bcnt);
     }
     acc = wave_sum(acc);
+    if (moved) moved_any = 1u;
     if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t t = 0;
         for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
-        if (t) atomic_add_i64(f, t);
+        if (t) spread_add_i64(f, t);
+        if (moved_any) *moves = 1u;  // a plain store: only ever set to 1
     }
 }
 
@@ -1183,8 +1224,10 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
 // ---------------------------------------------------------------------------
 struct RefineBufs {
     void *nr;  // NetRec<KW>[m]
-    int64_t *f, *bw;
-    uint32_t *longl, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow, *mlist;
+    int64_t *f;     // objective, spread over SPREAD slots
+    int64_t *bw;
+    uint32_t *longl, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow;
+    uint32_t *pcnt;  // [2][NSLOT * SPREAD_U32] proposal-list lengths, alternate sub-rounds
     uint32_t *dlists;  // hub candidates of the sub-round
     uint32_t *pc, *pbase, *pcur, *spairs, *seg;  // per-pair proposal counts, segments of over-budget pairs
     int64_t *dbw_g;
@@ -1196,12 +1239,13 @@ struct RefineBufs {
 static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     int KW = (int)((k + 63) / 64);
     B.nr = A.alloc<char>((size_t)m * netrec_bytes(KW));
-    B.f = A.alloc<int64_t>(1);
+    B.f = A.alloc<int64_t>((size_t)SPREAD * SPREAD_I64);
+    B.pcnt = A.alloc<uint32_t>((size_t)2 * NSLOT * SPREAD_U32);
     B.bw = A.alloc<int64_t>(k);
     B.longl = A.alloc<uint32_t>(m);
     B.dlists = A.alloc<uint32_t>(n);
     B.bcnt = A.alloc<uint32_t>(n);
-    B.plist = A.alloc<uint32_t>(n);
+    B.plist = A.alloc<uint32_t>((size_t)n + (size_t)(NSLOT + 1) * GAIN_CH);  // NSLOT lists (see GainArgs)
     B.prop_t = A.alloc<uint32_t>(n);
     B.prop_g = A.alloc<uint32_t>(n);
     B.tstamp = A.alloc<uint32_t>(m);
@@ -1221,7 +1265,6 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.spairs = A.alloc<uint32_t>((size_t)k * k);
     B.seg = A.alloc<uint32_t>(n);
     B.slow = A.alloc<uint32_t>(n);
-    B.mlist = A.alloc<uint32_t>(n);
     B.heavy = A.alloc<uint32_t>(n);
     B.dbw_g = A.alloc<int64_t>(k);
     sort_reserve(A, n);
@@ -1237,7 +1280,7 @@ size_t refine_workspace(uint32_t n, uint32_t m, uint32_t k) {
 
 template <int KW>
 static void build_conn(const hgp_hg &h, const uint32_t *part, RefineBufs &B, hipStream_t st) {
-    HGP_CHECK_HIP(hipMemsetAsync(B.f, 0, sizeof(int64_t), st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.f, 0, sizeof(int64_t) * SPREAD * SPREAD_I64, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.scal + 12, 0, sizeof(uint32_t), st));
     if (h.m) {
         k_conn_small<KW><<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
@@ -1263,7 +1306,8 @@ static void objective_t(const hgp_hg &h, uint32_t k, const uint32_t *part, int64
     RefineBufs B;
     plan(A, h.n, h.m, k, B);
     build_conn<KW>(h, part, B, st);
-    HGP_CHECK_HIP(hipMemcpyAsync(obj, B.f, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    k_objective_total<<<1, WAVE, 0, st>>>(B.f, obj);
+    HGP_LAUNCH_CHECK();
     if (bw_out) block_weights(part, h.vwgt, h.n, k, bw_out, st);
     stream_sync(st);
     A.release(mk);
@@ -1290,9 +1334,9 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const int64_t lmax = ((int64_t)(prm.eps_den + prm.eps_num) * ((W + k - 1) / k)) / (int64_t)prm.eps_den;
     const uint64_t mseed = mix64(prm.seed);
     // device scalars: ntouched and nlong are adjacent so one memset clears both
-    uint32_t *nprop = B.scal + 0, *gmax = B.scal + 1, *ntouched = B.scal + 2, *nlong = B.scal + 3,
+    uint32_t *gmax = B.scal + 1, *ntouched = B.scal + 2, *nlong = B.scal + 3,
              *moves = B.scal + 4, *dcnt = B.scal + 5 /* [NDEG] */, *nheavy = B.scal + 24,
-             *nslow = B.scal + 13, *nmov = B.scal + 14;
+             *nslow = B.scal + 13;
 
     build_conn<KW>(h, part, B, st);
     block_weights(part, h.vwgt, n, k, B.bw, st);
@@ -1320,16 +1364,20 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     while (gch < GAIN_CH && (size_t)gch * 2048 <= n) gch <<= 1;
     const uint32_t gchunks = (uint32_t)(((size_t)n + gch - 1) / gch);
     const uint32_t gain_blocks = std::min<uint32_t>(gchunks, 4096u);
+    // capacity of one proposal list: the vertices of its chunks
+    const uint32_t slot_cap = (gchunks + NSLOT - 1) / NSLOT * gch;
     const uint32_t hub_blocks = dc[3] ? grid_for((dc[3] + S - 1) / S, 1, 256) : 0u;
     uint32_t *nhub = B.scal + 26;  // hub candidates of the sub-round (list in dlists)
     // grids of the per-sub-round kernels, sized by what one sub-round can hold
     // (about n / S proposals and movers); every kernel strides over its count
     const size_t per_sub = (size_t)n / S + 1;
-    const uint32_t fast_blocks = grid_for(per_sub, BLOCK, FILL_BLOCKS / 4);
+    // (the kernels that read the proposal lists take a multiple of NSLOT)
+    auto slot_grid = [](uint32_t g) { return (g + NSLOT - 1) / NSLOT * NSLOT; };
+    const uint32_t fast_blocks = slot_grid(grid_for(per_sub, BLOCK, FILL_BLOCKS / 4));
     // lanes per mover by the level's average degree (a lane per incident net)
     const uint64_t avg_deg = n ? ((uint64_t)h.p + n - 1) / n : 1;
     const uint32_t upd_g = avg_deg <= 8 ? 8u : (avg_deg <= 24 ? 16u : 64u);
-    const uint32_t upd_blocks = grid_for(per_sub, BLOCK / upd_g, FILL_BLOCKS / 2);
+    const uint32_t upd_blocks = slot_grid(grid_for(per_sub, BLOCK / upd_g, FILL_BLOCKS / 2));
     const uint32_t long_blocks = grid_for((size_t)m + 1, 64 * (BLOCK / WAVE), FILL_BLOCKS / 4);
 
     const int kb = bits_for(k - 1), ub = bits_for(n ? n - 1 : 0);
@@ -1344,13 +1392,23 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     HGP_CHECK_HIP(hipMemsetAsync(B.pw, 0, sizeof(uint32_t) * k * k, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.pc, 0, sizeof(uint32_t) * k * k, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.dbw_g, 0, sizeof(int64_t) * k, st));
-    const NextSub zn{B.scal, B.pw, B.pc, k * k, k, B.bw, B.dbw_g};
+    HGP_CHECK_HIP(hipMemsetAsync(B.pcnt, 0, sizeof(uint32_t) * 2 * NSLOT * SPREAD_U32, st));
+    // proposal-list lengths of sub-round `stamp` (stamps are consecutive)
+    auto pcnt_of = [&](uint32_t stamp) { return B.pcnt + (stamp & 1u) * NSLOT * SPREAD_U32; };
     const uint32_t pair_blocks = std::min<uint32_t>(k * (k - 1) / 2, 1024u);
 
     // Device-wide selection of the pairs that sub-round (r, s) handed over
     // (more than PAIR_MAX proposals in one pair).  The counts are read back
     // here (the host has synchronised).
-    auto slow_path = [&](uint32_t ns, uint32_t G) {
+    auto slow_path = [&](uint32_t ns) {
+        uint32_t G = 0;  // largest gain of the handed-over proposals
+        if (ns) {
+            HGP_CHECK_HIP(hipMemsetAsync(gmax, 0, sizeof(uint32_t), st));
+            k_gain_max<<<grid_for(ns, BLOCK, 64), BLOCK, 0, st>>>(B.slow, ns, B.prop_g, gmax);
+            HGP_LAUNCH_CHECK();
+            HGP_CHECK_HIP(hipMemcpyAsync(&G, gmax, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            stream_sync(st);
+        }
         const int gb = bits_for(G);
         KeyLayout L;
         L.kmask = (1u << kb) - 1u;
@@ -1390,7 +1448,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
                                                                            B.incl, B.bw, lmax, B.best);
             HGP_LAUNCH_CHECK();
             k_lp_apply<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, ns, L, k, B.seg_start, B.best,
-                                                                          h.vwgt, part, B.bw, B.mlist, nmov);
+                                                                          h.vwgt, part, B.bw);
             HGP_LAUNCH_CHECK();
         }
         k_add_dbw<<<1, 256, 0, st>>>(B.bw, B.dbw_g, k);
@@ -1401,17 +1459,20 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         if (accounting(KID_LP_UPDATE)) {
             Timing &T = timing();
             ++T.stamp;
-            k_account_update<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, B.mlist, nmov, T.marks,
-                                                                    T.stamp,
+            static_assert((FILL_BLOCKS / 4) % NSLOT == 0, "the proposal lists need a multiple of NSLOT");
+            k_account_update<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, B.plist,
+                                                                    pcnt_of(stamp), slot_cap, part, B.prop_t,
+                                                                    T.marks, T.stamp,
                                                                     (unsigned long long *)T.acc_dev + KID_LP_UPDATE);
             HGP_LAUNCH_CHECK();
         }
         {
             TimedLaunch tl(KID_LP_UPDATE, st);
+            const NextSub zn{B.scal, B.pw, B.pc, k * k, k, B.bw, B.dbw_g, pcnt_of(stamp + 1)};
             auto launch = [&](auto kern, uint32_t blocks) {
-                kern<<<blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.mlist, nmov, part,
-                                               (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl, nlong, moves,
-                                               B.bcnt, B.heavy, nheavy, zn, abort);
+                kern<<<blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.plist, pcnt_of(stamp), slot_cap,
+                                               B.prop_t, part, (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl,
+                                               nlong, moves, B.bcnt, B.heavy, nheavy, zn, abort);
             };
             if (upd_g == 8) launch(k_lp_update_movers<KW, 8>, upd_blocks);
             else if (upd_g == 16) launch(k_lp_update_movers<KW, 16>, upd_blocks);
@@ -1434,7 +1495,8 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     auto subround = [&](uint32_t r, uint32_t s) {
         const uint32_t stamp = 1 + r * S + s;
         const GainArgs<KW> ga{h.inc_off, h.inc, h.vwgt, (const NetRec<KW> *)B.nr, part, B.bw, B.bcnt, lmax, mseed,
-                              level, r, s, S, n, B.prop_t, B.prop_g, B.plist, nprop, gmax, B.pw, B.pc, k, abort};
+                              level, r, s, S, n, B.prop_t, B.prop_g, B.plist, pcnt_of(stamp), gch, slot_cap,
+                              B.pw, B.pc, k, abort};
         if (accounting(KID_GAINS)) {
             Timing &T = timing();
             ++T.stamp;
@@ -1455,14 +1517,14 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         HGP_LAUNCH_CHECK();
         {  // pairs whose whole move sets are feasible: applied directly
             TimedLaunch tl(KID_LP_FAST, st);
-            k_lp_fast<<<fast_blocks, BLOCK, 0, st>>>(B.plist, nprop, B.prop_t, B.pw, k, h.vwgt, part, B.bw, lmax,
-                                                     B.dbw_g, B.mlist, nmov, B.pbase, B.pcur, B.seg, abort);
+            k_lp_fast<<<fast_blocks, BLOCK, 0, st>>>(B.plist, pcnt_of(stamp), slot_cap, B.prop_t, B.pw, k, h.vwgt,
+                                                     part, B.bw, lmax, B.dbw_g, B.pbase, B.pcur, B.seg, abort);
             HGP_LAUNCH_CHECK();
         }
         {  // the other pairs: sorted two-pointer walk, a workgroup per pair
             TimedLaunch tl(KID_LP_PAIRS, st);
             k_lp_pairs<<<pair_blocks, PAIR_THREADS, 0, st>>>(B.spairs, nsp, B.pbase, B.pc, B.seg, k, B.prop_g, h.vwgt,
-                                                             part, B.bw, lmax, B.dbw_g, B.mlist, nmov, B.slow, nslow,
+                                                             part, B.bw, lmax, B.dbw_g, B.slow, nslow,
                                                              abort, s);
             HGP_LAUNCH_CHECK();
         }
@@ -1481,7 +1543,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             // it there, then replay the remaining sub-rounds of the round
             const uint32_t s0 = hv[15] - 1;
             HGP_CHECK_HIP(hipMemsetAsync(abort, 0, sizeof(uint32_t), st));
-            slow_path(hv[13], hv[1]);
+            slow_path(hv[13]);
             update(1 + r * S + s0);
             for (uint32_t s = s0 + 1; s < S; ++s) subround(r, s);
         }
@@ -1490,7 +1552,10 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     // the last sub-round's block-weight changes
     k_add_dbw<<<1, 256, 0, st>>>(B.bw, B.dbw_g, k);
     HGP_LAUNCH_CHECK();
-    if (obj) HGP_CHECK_HIP(hipMemcpyAsync(obj, B.f, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    if (obj) {
+        k_objective_total<<<1, WAVE, 0, st>>>(B.f, obj);
+        HGP_LAUNCH_CHECK();
+    }
     if (bw_out) HGP_CHECK_HIP(hipMemcpyAsync(bw_out, B.bw, sizeof(int64_t) * k, hipMemcpyDeviceToDevice, st));
     stream_sync(st);
     A.release(mk);
