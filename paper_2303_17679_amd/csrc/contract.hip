@@ -91,7 +91,7 @@ struct IsValid {
 struct GatherValid {
     const uint8_t *valid;
     const uint32_t *hkey;
-    uint64_t *keys;
+    uint32_t *keys;
     uint32_t *vals;
     __device__ void operator()(size_t i, uint32_t excl, uint32_t v) const {
         if (v) {
@@ -102,16 +102,23 @@ struct GatherValid {
 };
 
 // Representative of every valid net: the first net of its hash run with an
-// identical pin list.
-__global__ void k_identical(const uint64_t *keys, const uint32_t *vals, uint32_t nv, const uint32_t *off,
+// identical pin list.  The run start is found by stepping back over a few
+// neighbours (most hashes are unique), else by binary search.
+__global__ void k_identical(const uint32_t *keys, const uint32_t *vals, uint32_t nv, const uint32_t *off,
                             const uint32_t *tmp, const uint32_t *usize, const int32_t *nwgt, uint32_t *repnet,
                             int32_t *wsum) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
-        uint64_t key = keys[i];
-        uint32_t lo = 0, hi = i;
-        while (lo < hi) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (keys[mid] < key) lo = mid + 1; else hi = mid;
+        const uint32_t key = keys[i];
+        uint32_t lo = i;
+        int steps = 0;
+        while (lo > 0 && steps < 4 && keys[lo - 1] == key) { --lo; ++steps; }
+        if (lo > 0 && keys[lo - 1] == key) {  // a long run
+            uint32_t a = 0, b = lo;
+            while (a < b) {
+                const uint32_t mid = (a + b) >> 1;
+                if (keys[mid] < key) a = mid + 1; else b = mid;
+            }
+            lo = a;
         }
         uint32_t e = vals[i];
         uint32_t sz = usize[e];
@@ -155,55 +162,62 @@ struct StoreKept {
     }
 };
 
+// Pins of the kept nets into the coarse pin array, and (pin, net) pairs in
+// net order for the transpose: sorting them stably by pin gives every coarse
+// vertex its incident nets in increasing order.
 __global__ void k_copy_pins_small(const uint32_t *off, uint32_t m, const uint32_t *tmp, const uint32_t *usize,
-                                  const uint32_t *newid, const uint32_t *newoff, uint32_t *cpins, uint32_t *deg) {
+                                  const uint32_t *newid, const uint32_t *newoff, uint32_t *cpins, uint32_t *tkey,
+                                  uint32_t *tnet) {
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
-        if (newid[e] == NONE) continue;
+        const uint32_t id = newid[e];
+        if (id == NONE) continue;
         uint32_t b = off[e], len = off[e + 1] - b;
         if (len > SEG_WAVE) continue;  // done by the block kernel
         uint32_t sz = usize[e], o = newoff[e];
         for (uint32_t i = 0; i < sz; ++i) {
             uint32_t v = tmp[b + i];
             cpins[o + i] = v;
-            atomicAdd(&deg[v], 1u);
+            tkey[o + i] = v;
+            tnet[o + i] = id;
         }
     }
 }
 
 __global__ void k_copy_pins_block(const uint32_t *off, const uint32_t *list, uint32_t count, const uint32_t *tmp,
                                   const uint32_t *usize, const uint32_t *newid, const uint32_t *newoff,
-                                  uint32_t *cpins, uint32_t *deg) {
+                                  uint32_t *cpins, uint32_t *tkey, uint32_t *tnet) {
     for (uint32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
         uint32_t e = list[idx];
-        if (newid[e] == NONE) continue;
+        const uint32_t id = newid[e];
+        if (id == NONE) continue;
         uint32_t b = off[e], sz = usize[e], o = newoff[e];
         for (uint32_t i = threadIdx.x; i < sz; i += blockDim.x) {
             uint32_t v = tmp[b + i];
             cpins[o + i] = v;
-            atomicAdd(&deg[v], 1u);
+            tkey[o + i] = v;
+            tnet[o + i] = id;
         }
     }
 }
 
-// Scatter of the transpose: thread per coarse net.
-__global__ void k_scatter_inc(const uint32_t *cpin_off, uint32_t mc, const uint32_t *cpins, uint32_t *cursor,
-                              uint32_t *cinc) {
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < mc; e += gridDim.x * blockDim.x) {
-        for (uint32_t j = cpin_off[e]; j < cpin_off[e + 1]; ++j) {
-            uint32_t v = cpins[j];
-            uint32_t pos = atomicAdd(&cursor[v], 1u);
-            cinc[pos] = e;
-        }
+// Incidence offsets from the pins sorted by vertex: inc_off[v] is the first
+// position whose vertex is >= v (every v in [0, nc] is written once).
+__global__ void k_inc_offsets(const uint32_t *skey, uint32_t pc, uint32_t nc, uint32_t *inc_off) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= pc; i += gridDim.x * blockDim.x) {
+        const uint32_t lo = i == 0 ? 0u : skey[i - 1] + 1;  // first vertex not yet started
+        const uint32_t hi = i == pc ? nc : skey[i];         // last vertex that starts here
+        for (uint32_t v = lo; v <= hi; ++v) inc_off[v] = i;
     }
 }
 
 struct ContractBufs {
-    uint32_t *rank, *tmp, *usize, *hkey, *repnet, *newid, *newoff, *cursor, *scal;
+    uint32_t *rank, *tmp, *usize, *hkey, *repnet, *newid, *newoff, *scal;
     int32_t *wsum;
     uint8_t *valid;
     uint64_t *keys, *keys_alt;
     uint32_t *vals, *vals_alt;
-    SegSortBufs ss_net, ss_inc;
+    uint32_t *tkey, *tkey_alt, *tnet;  // transpose: (pin, net) pairs and the sort's second buffer
+    SegSortBufs ss_net;
 };
 
 static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, ContractBufs &B) {
@@ -214,7 +228,6 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, ContractBufs &B) 
     B.repnet = A.alloc<uint32_t>(m);
     B.newid = A.alloc<uint32_t>(m);
     B.newoff = A.alloc<uint32_t>(m);
-    B.cursor = A.alloc<uint32_t>((size_t)n + 1);
     B.scal = A.alloc<uint32_t>(8);
     B.wsum = A.alloc<int32_t>(m);
     B.valid = A.alloc<uint8_t>(m);
@@ -222,11 +235,13 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, ContractBufs &B) 
     B.keys_alt = A.alloc<uint64_t>(m);
     B.vals = A.alloc<uint32_t>(m);
     B.vals_alt = A.alloc<uint32_t>(m);
+    B.tkey = A.alloc<uint32_t>(p);
+    B.tkey_alt = A.alloc<uint32_t>(p);
+    B.tnet = A.alloc<uint32_t>(p);
     segsort_plan(A, m, p, B.ss_net);
-    segsort_plan(A, n, p, B.ss_inc);
     scan_reserve<uint32_t>(A, (size_t)n + 1);
     scan_reserve<uint64_t>(A, m);
-    sort_reserve(A, m);
+    sort_reserve(A, p > m ? p : m);
 }
 
 size_t contract_workspace(uint32_t n, uint32_t m, uint32_t p) {
@@ -282,13 +297,13 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
                                                                          B.usize, B.hkey, B.valid);
         HGP_LAUNCH_CHECK();
     }
-    scan_apply<uint32_t>(A, m, IsValid{B.valid}, GatherValid{B.valid, B.hkey, B.keys, B.vals}, d_nv, st);
+    scan_apply<uint32_t>(A, m, IsValid{B.valid}, GatherValid{B.valid, B.hkey, (uint32_t *)B.keys, B.vals}, d_nv, st);
     uint32_t nv = 0;
     HGP_CHECK_HIP(hipMemcpyAsync(&nv, d_nv, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     stream_sync(st);
-    uint64_t *kk = B.keys;
+    uint32_t *kk = (uint32_t *)B.keys;  // 32-bit hash keys in the 64-bit buffers
     uint32_t *vv = B.vals;
-    radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, nv, 0, 32, st);
+    radix_sort_pairs<uint32_t>(A, &kk, &vv, (uint32_t *)B.keys_alt, B.vals_alt, nv, 0, 32, st);
     if (m) HGP_CHECK_HIP(hipMemsetAsync(B.wsum, 0, sizeof(int32_t) * m, st));
     if (nv) {
         k_identical<<<grid_for(nv, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, nv, h.pin_off, B.tmp, B.usize, h.nwgt,
@@ -305,35 +320,40 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
     uint32_t mc = (uint32_t)(tot >> 32), pc = (uint32_t)tot;
     HGP_REQUIRE(mc <= out.cap_m && pc <= out.cap_p, HGP_E_INVALID);
     HGP_CHECK_HIP(hipMemcpyAsync(out.pin_off + mc, &pc, sizeof(uint32_t), hipMemcpyHostToDevice, st));
-    HGP_CHECK_HIP(hipMemsetAsync(B.cursor, 0, sizeof(uint32_t) * ((size_t)nc + 1), st));
+    // the transpose's net ids start where the stable sort by vertex (8-bit
+    // digits) leaves them: in out.inc after an even number of passes
+    const int vbits = bits_for(nc ? nc - 1 : 0);
+    const bool even = ((vbits + 7) / 8) % 2 == 0;
+    uint32_t *tnet = even ? out.inc : B.tnet, *tnet_alt = even ? B.tnet : out.inc;
     if (m) {
         k_copy_pins_small<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, m, B.tmp, B.usize, B.newid,
-                                                                            B.newoff, out.pins, B.cursor);
+                                                                            B.newoff, out.pins, B.tkey, tnet);
         HGP_LAUNCH_CHECK();
     }
     if (cnt_ml[0]) {
         k_copy_pins_block<<<grid_for(cnt_ml[0], 1, 4096), BLOCK, 0, st>>>(h.pin_off, B.ss_net.med, cnt_ml[0], B.tmp,
                                                                           B.usize, B.newid, B.newoff, out.pins,
-                                                                          B.cursor);
+                                                                          B.tkey, tnet);
         HGP_LAUNCH_CHECK();
     }
     if (cnt_ml[1]) {
         k_copy_pins_block<<<grid_for(cnt_ml[1], 1, 4096), BLOCK, 0, st>>>(h.pin_off, B.ss_net.large, cnt_ml[1], B.tmp,
                                                                           B.usize, B.newid, B.newoff, out.pins,
-                                                                          B.cursor);
+                                                                          B.tkey, tnet);
         HGP_LAUNCH_CHECK();
     }
 
-    // 5. incidence: offsets by scan of the degrees, scatter, sort each list
-    exclusive_scan<uint32_t>(A, B.cursor, out.inc_off, (size_t)nc + 1, (uint32_t *)nullptr, st);
-    HGP_CHECK_HIP(hipMemcpyAsync(B.cursor, out.inc_off, sizeof(uint32_t) * ((size_t)nc + 1), hipMemcpyDeviceToDevice,
-                                 st));
-    if (mc) {
-        k_scatter_inc<<<grid_for(mc, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(out.pin_off, mc, out.pins, B.cursor,
-                                                                         out.inc);
+    // 5. incidence: the (pin, net) pairs sorted stably by pin (nets of a
+    // vertex in increasing order), offsets from the sorted pins
+    uint32_t *tk = B.tkey, *tv = tnet;
+    radix_sort_pairs<uint32_t>(A, &tk, &tv, B.tkey_alt, tnet_alt, pc, 0, vbits, st);
+    HGP_REQUIRE(pc == 0 || tv == out.inc, HGP_E_INVALID);
+    if (pc) {
+        k_inc_offsets<<<grid_for((size_t)pc + 1, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(tk, pc, nc, out.inc_off);
         HGP_LAUNCH_CHECK();
+    } else {
+        HGP_CHECK_HIP(hipMemsetAsync(out.inc_off, 0, sizeof(uint32_t) * ((size_t)nc + 1), st));
     }
-    segmented_sort(A, B.ss_inc, out.inc_off, nc, out.inc, false, nullptr, st);
     uint32_t dims[3] = {nc, mc, pc};
     if (out.dims) HGP_CHECK_HIP(hipMemcpyAsync(out.dims, dims, sizeof(dims), hipMemcpyHostToDevice, st));
     stream_sync(st);
