@@ -79,6 +79,9 @@ inline unsigned grid_for(size_t work, int per_block, unsigned max_blocks = 65535
 
 // Number of blocks of a grid-stride kernel that fill the chip (256 CUs).
 constexpr unsigned FILL_BLOCKS = 2048;
+// Grid cap of kernels that end in one device-scope atomic per workgroup on a
+// few shared addresses (such atomics are serialised).
+constexpr unsigned REDUCE_BLOCKS = 256;
 
 // ---------------------------------------------------------------------------
 // Device helpers

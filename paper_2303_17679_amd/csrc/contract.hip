@@ -101,39 +101,47 @@ struct GatherValid {
     }
 };
 
-// Representative of every valid net: the first net of its hash run with an
-// identical pin list.  The run start is found by stepping back over a few
-// neighbours (most hashes are unique), else by binary search.
+// Representative of every valid net: the first net, in the order the nets
+// are sorted by the upper HASH_SORT_BITS bits of their hash (stably, so by
+// net within equal bits), with an identical pin list -- the smallest net ID
+// among identical nets.  The run of equal sorted bits is found by stepping
+// back over a few neighbours (runs are short), else by binary search.
+// wsum[r] receives the weights of the nets r represents besides itself.
+constexpr int HASH_SORT_BITS = 24;
 __global__ void k_identical(const uint32_t *keys, const uint32_t *vals, uint32_t nv, const uint32_t *off,
                             const uint32_t *tmp, const uint32_t *usize, const int32_t *nwgt, uint32_t *repnet,
                             int32_t *wsum) {
+    constexpr int SH = 32 - HASH_SORT_BITS;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
-        const uint32_t key = keys[i];
+        const uint32_t key = keys[i], top = key >> SH;
         uint32_t lo = i;
         int steps = 0;
-        while (lo > 0 && steps < 4 && keys[lo - 1] == key) { --lo; ++steps; }
-        if (lo > 0 && keys[lo - 1] == key) {  // a long run
+        while (lo > 0 && steps < 4 && (keys[lo - 1] >> SH) == top) { --lo; ++steps; }
+        if (lo > 0 && (keys[lo - 1] >> SH) == top) {  // a long run
             uint32_t a = 0, b = lo;
             while (a < b) {
                 const uint32_t mid = (a + b) >> 1;
-                if (keys[mid] < key) a = mid + 1; else b = mid;
+                if ((keys[mid] >> SH) < top) a = mid + 1; else b = mid;
             }
             lo = a;
         }
-        uint32_t e = vals[i];
-        uint32_t sz = usize[e];
-        const uint32_t *pe = tmp + off[e];
+        const uint32_t e = vals[i];
         uint32_t r = e;
-        for (uint32_t j = lo; j < i; ++j) {
-            uint32_t f = vals[j];
-            if (usize[f] != sz) continue;
-            const uint32_t *pf = tmp + off[f];
-            bool same = true;
-            for (uint32_t q = 0; q < sz && same; ++q) same = pe[q] == pf[q];
-            if (same) { r = f; break; }
+        if (lo < i) {
+            const uint32_t sz = usize[e];
+            const uint32_t *pe = tmp + off[e];
+            for (uint32_t j = lo; j < i; ++j) {
+                if (keys[j] != key) continue;
+                const uint32_t f = vals[j];
+                if (usize[f] != sz) continue;
+                const uint32_t *pf = tmp + off[f];
+                bool same = true;
+                for (uint32_t q = 0; q < sz && same; ++q) same = pe[q] == pf[q];
+                if (same) { r = f; break; }
+            }
+            if (r != e) atomicAdd(&wsum[r], nwgt[e]);
         }
         repnet[e] = r;
-        atomicAdd(&wsum[r], nwgt[e]);
     }
 }
 
@@ -148,14 +156,14 @@ struct KeptPack {
 struct StoreKept {
     uint32_t *newid, *newoff, *cpin_off;
     int32_t *cnwgt;
-    const int32_t *wsum;
+    const int32_t *nwgt, *wsum;
     __device__ void operator()(size_t e, uint64_t excl, uint64_t v) const {
         if (v) {
             uint32_t id = (uint32_t)(excl >> 32);
             newid[e] = id;
             newoff[e] = (uint32_t)excl;
             cpin_off[id] = (uint32_t)excl;
-            cnwgt[id] = wsum[e];
+            cnwgt[id] = nwgt[e] + wsum[e];
         } else {
             newid[e] = NONE;
         }
@@ -303,7 +311,7 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
     stream_sync(st);
     uint32_t *kk = (uint32_t *)B.keys;  // 32-bit hash keys in the 64-bit buffers
     uint32_t *vv = B.vals;
-    radix_sort_pairs<uint32_t>(A, &kk, &vv, (uint32_t *)B.keys_alt, B.vals_alt, nv, 0, 32, st);
+    radix_sort_pairs<uint32_t>(A, &kk, &vv, (uint32_t *)B.keys_alt, B.vals_alt, nv, 32 - HASH_SORT_BITS, 32, st);
     if (m) HGP_CHECK_HIP(hipMemsetAsync(B.wsum, 0, sizeof(int32_t) * m, st));
     if (nv) {
         k_identical<<<grid_for(nv, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, nv, h.pin_off, B.tmp, B.usize, h.nwgt,
@@ -313,7 +321,7 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
 
     // 4. number the kept nets, copy pins, count coarse degrees
     scan_apply<uint64_t>(A, m, KeptPack{B.valid, B.repnet, B.usize},
-                         StoreKept{B.newid, B.newoff, out.pin_off, out.nwgt, B.wsum}, d_tot, st);
+                         StoreKept{B.newid, B.newoff, out.pin_off, out.nwgt, h.nwgt, B.wsum}, d_tot, st);
     uint64_t tot = 0;
     HGP_CHECK_HIP(hipMemcpyAsync(&tot, d_tot, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     stream_sync(st);

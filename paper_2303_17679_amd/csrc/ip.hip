@@ -68,8 +68,15 @@ __global__ __launch_bounds__(BLOCK) void k_exoff(const uint32_t *pin_off, const 
 // smallest unvisited vertex with incident nets in [from, n) -> *out (preset n)
 __global__ void k_find_start(const uint32_t *inc_off, const uint32_t *visited, uint32_t from, uint32_t n,
                              uint32_t *out) {
+    uint32_t best = n;
     for (uint32_t v = from + blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        if (!visited[v] && inc_off[v + 1] > inc_off[v]) atomicMin(out, v);
+        if (!visited[v] && inc_off[v + 1] > inc_off[v]) { best = v; break; }  // ascending per thread
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_xor(best, o, 64);
+        best = y < best ? y : best;
+    }
+    if (__lane_id() == 0 && best < n) atomicMin(out, best);  // one atomic per wave
 }
 
 struct Unvisited {

@@ -1295,7 +1295,7 @@ static void build_conn(const hgp_hg &h, const uint32_t *part, RefineBufs &B, hip
 static void block_weights(const uint32_t *part, const int32_t *vwgt, uint32_t n, uint32_t k, int64_t *bw,
                           hipStream_t st) {
     HGP_CHECK_HIP(hipMemsetAsync(bw, 0, sizeof(int64_t) * k, st));
-    k_block_weights<<<grid_for(n, BLOCK * 8, 1024), BLOCK, 0, st>>>(part, vwgt, n, k, bw);
+    k_block_weights<<<grid_for(n, BLOCK * 8, REDUCE_BLOCKS), BLOCK, 0, st>>>(part, vwgt, n, k, bw);
     HGP_LAUNCH_CHECK();
 }
 
@@ -1350,7 +1350,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     HGP_LAUNCH_CHECK();
     // degree classes of the nodes (lanes per node 1 / 8 / 64)
     HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * NDEG, st));
-    k_deg_classify<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt);
+    k_deg_classify<<<grid_for(n, BLOCK, REDUCE_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt);
     HGP_LAUNCH_CHECK();
     uint32_t dc[NDEG], hs[16];
     HGP_CHECK_HIP(hipMemcpyAsync(hs, B.scal, sizeof(hs), hipMemcpyDeviceToHost, st));

@@ -48,7 +48,7 @@ static SumMax sum_max(const int32_t *w, uint32_t n, Arena &A, hipStream_t st) {
     if (A.measure) { A.release(mk); return r; }
     HGP_CHECK_HIP(hipMemsetAsync(buf, 0, 64, st));
     if (n) {
-        k_sum_max<<<grid_for(n, BLOCK * 8, 1024), BLOCK, 0, st>>>(w, n, (int64_t *)buf, (int32_t *)(buf + 8),
+        k_sum_max<<<grid_for(n, BLOCK * 8, REDUCE_BLOCKS), BLOCK, 0, st>>>(w, n, (int64_t *)buf, (int32_t *)(buf + 8),
                                                                   (uint32_t *)(buf + 12));
         HGP_LAUNCH_CHECK();
     }
