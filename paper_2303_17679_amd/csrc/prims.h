@@ -168,70 +168,113 @@ void exclusive_scan(Arena &A, const T *a, T *out, size_t n, T *total_dev, hipStr
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = BLOCK * RS_ITEMS;
 
+// Digit of every valid lane; `match` gets the lanes of the wave holding the
+// same digit (eight ballots).
+__device__ inline uint64_t digit_match(bool valid, uint32_t d) {
+    uint64_t match = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t vote = __ballot(bit);
+        match &= bit ? vote : ~vote;
+    }
+    return match;
+}
+
+// Per-tile digit histogram; all RS_ITEMS keys of a thread are loaded first.
 template <class K>
 __global__ __launch_bounds__(BLOCK) void k_rs_hist(const K *keys, size_t n, int shift, uint32_t ntiles,
                                                    uint32_t *counts) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
-    __syncthreads();
-    size_t base = (size_t)blockIdx.x * RS_TILE;
-    for (int r = 0; r < RS_ITEMS; ++r) {
-        size_t i = base + (size_t)r * BLOCK + threadIdx.x;
-        bool valid = i < n;
-        uint32_t d = valid ? ((uint32_t)(keys[i] >> shift) & 0xFFu) : 0u;
-        // one LDS atomic per distinct digit of the wave
-        uint64_t match = __ballot(valid);
+    const size_t base = (size_t)blockIdx.x * RS_TILE;
+    uint32_t dg[RS_ITEMS];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t vote = __ballot(bit);
-            match &= bit ? vote : ~vote;
-        }
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const size_t i = base + (size_t)r * BLOCK + threadIdx.x;
+        dg[r] = i < n ? ((uint32_t)(keys[i] >> shift) & 0xFFu) : 256u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const bool valid = dg[r] < 256u;
+        const uint32_t d = dg[r] & 0xFFu;
+        const uint64_t match = digit_match(valid, d);  // one LDS atomic per distinct digit of the wave
         if (valid && (match & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(match));
     }
     __syncthreads();
     counts[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Stable scatter of one tile: the tile is first ordered by digit in LDS
+// (rank within the digit = earlier rounds, earlier waves, earlier lanes),
+// then written out position by position, so the elements of a digit bucket
+// leave as one contiguous run instead of single scattered words.
 template <class K>
 __global__ __launch_bounds__(BLOCK) void k_rs_scatter(const K *keys, const uint32_t *vals, K *keys_out,
                                                       uint32_t *vals_out, size_t n, int shift,
                                                       uint32_t ntiles, const uint32_t *offsets) {
-    __shared__ uint32_t base_off[256];
+    __shared__ K skey[RS_TILE];
+    __shared__ uint32_t sval[RS_TILE];
     __shared__ uint32_t wcnt[BLOCK / WAVE][256];
-    const unsigned tid = threadIdx.x, w = tid / WAVE, l = __lane_id();
-    base_off[tid] = offsets[(size_t)tid * ntiles + blockIdx.x];
-    size_t tbase = (size_t)blockIdx.x * RS_TILE;
+    __shared__ uint32_t run[256];   // elements of each digit in the rounds so far
+    __shared__ uint32_t tpre[256];  // exclusive prefix of the tile's digit counts
+    __shared__ uint32_t gout[256];  // where the tile's bucket of each digit starts in the output
+    __shared__ uint32_t wsum[BLOCK / WAVE];
+    const unsigned tid = threadIdx.x, w = tid / WAVE;
+    gout[tid] = offsets[(size_t)tid * ntiles + blockIdx.x];
+    run[tid] = 0;
+    const size_t tbase = (size_t)blockIdx.x * RS_TILE;
+    K kr[RS_ITEMS];
+    uint32_t vr[RS_ITEMS], rk[RS_ITEMS];
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const size_t i = tbase + (size_t)r * BLOCK + tid;
+        kr[r] = i < n ? keys[i] : K(0);
+        vr[r] = i < n ? vals[i] : 0u;
+    }
+#pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
 #pragma unroll
         for (int q = 0; q < BLOCK / WAVE; ++q) wcnt[q][tid] = 0;
         __syncthreads();
-        size_t i = tbase + (size_t)r * BLOCK + tid;
-        bool valid = i < n;
-        K key = valid ? keys[i] : K(0);
-        uint32_t val = valid ? vals[i] : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
-        uint64_t match = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t vote = __ballot(bit);
-            match &= bit ? vote : ~vote;
-        }
-        uint32_t rank = (uint32_t)__popcll(match & lanemask_lt());
+        const bool valid = tbase + (size_t)r * BLOCK + tid < n;
+        const uint32_t d = (uint32_t)(kr[r] >> shift) & 0xFFu;
+        const uint64_t match = digit_match(valid, d);
+        const uint32_t rank = (uint32_t)__popcll(match & lanemask_lt());
         if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
         __syncthreads();
-        if (valid) {
-            uint32_t pos = base_off[d] + rank;
-            for (unsigned q = 0; q < w; ++q) pos += wcnt[q][d];
-            keys_out[pos] = key;
-            vals_out[pos] = val;
-        }
+        uint32_t pos = run[d] + rank;
+        for (unsigned q = 0; q < w; ++q) pos += wcnt[q][d];
+        rk[r] = pos;
         __syncthreads();
         uint32_t add = 0;
 #pragma unroll
         for (int q = 0; q < BLOCK / WAVE; ++q) add += wcnt[q][tid];
-        base_off[tid] += add;
+        run[tid] += add;
+    }
+    __syncthreads();
+    const uint32_t c = run[tid];
+    uint32_t tot;
+    const uint32_t incl = block_incl_scan<uint32_t>(c, wsum, &tot);
+    tpre[tid] = incl - c;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        if (tbase + (size_t)r * BLOCK + tid < n) {
+            const uint32_t p = tpre[(uint32_t)(kr[r] >> shift) & 0xFFu] + rk[r];
+            skey[p] = kr[r];
+            sval[p] = vr[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t cnt = (uint32_t)(n - tbase < (size_t)RS_TILE ? n - tbase : (size_t)RS_TILE);
+    for (uint32_t p = tid; p < cnt; p += BLOCK) {
+        const K key = skey[p];
+        const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+        const size_t o = (size_t)gout[d] + (p - tpre[d]);
+        keys_out[o] = key;
+        vals_out[o] = sval[p];
     }
 }
 
