@@ -717,6 +717,29 @@ __global__ void k_lp_select(const uint64_t *keys, uint32_t np, KeyLayout L, uint
     }
 }
 
+// Proposals of the pairs flagged for the device-wide path, from the
+// proposal lists (movers of the sub-round are in other pairs).
+__global__ __launch_bounds__(BLOCK) void k_collect_slow(const uint32_t *plist, const uint32_t *pcnt,
+                                                        uint32_t slot_cap, const uint32_t *part,
+                                                        const uint32_t *prop_t, uint32_t k, const uint8_t *slowpair,
+                                                        uint32_t *slow, uint32_t *nslow) {
+    const uint32_t sl = blockIdx.x % NSLOT, bj = blockIdx.x / NSLOT, nbj = gridDim.x / NSLOT;
+    const uint32_t np = pcnt[sl * SPREAD_U32];
+    const uint32_t *pl = plist + (size_t)sl * slot_cap;
+    for (uint32_t base = bj * BLOCK; base < np; base += nbj * BLOCK) {
+        const uint32_t i = base + threadIdx.x;
+        bool take = false;
+        uint32_t u = 0;
+        if (i < np) {
+            u = pl[i];
+            const uint32_t s = part[u], t = prop_t[u];
+            if (s != t) take = slowpair[(s < t ? s : t) * k + (s < t ? t : s)] != 0;
+        }
+        const uint32_t pos = warp_agg_append(nslow, take);
+        if (take) slow[pos] = u;
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_lp_apply(const uint64_t *keys, const uint32_t *vals, uint32_t np,
                                                     KeyLayout L, uint32_t k, const uint32_t *seg_start,
                                                     const unsigned long long *best, const int32_t *vwgt,
@@ -763,14 +786,20 @@ __global__ __launch_bounds__(BLOCK) void k_lp_apply(const uint64_t *keys, const 
 // Block-weight changes go to dbw_g so that the sorted walk still reads the
 // snapshot block weights.  Movers are not listed: a proposer has moved iff
 // its block is now its proposed target.  The proposals of the other pairs go
-// to their pair's segment of `seg` (k_pair_plan has laid the segments out).
+// to their pair's segment of `seg`: every unordered pair {x < y} owns
+// seg_cap slots (a pair of more proposals goes to the device-wide path,
+// which collects them again from the proposal lists).
 // Workgroup b reads proposal list b % NSLOT (the grid is a multiple of NSLOT).
 // ---------------------------------------------------------------------------
+__device__ inline size_t pair_segment(uint32_t x, uint32_t y, uint32_t k, uint32_t seg_cap) {
+    return ((size_t)x * (2 * k - x - 1) / 2 + (y - x - 1)) * seg_cap;  // triangular index of {x < y}
+}
+
 __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const uint32_t *pcnt, uint32_t slot_cap,
                                                    const uint32_t *prop_t, const uint32_t *pw, uint32_t k,
                                                    const int32_t *vwgt, uint32_t *part, const int64_t *bw,
-                                                   int64_t lmax, int64_t *dbw_g, const uint32_t *pbase,
-                                                   uint32_t *pcur, uint32_t *seg, const uint32_t *abort) {
+                                                   int64_t lmax, int64_t *dbw_g, uint32_t *pcur, uint32_t *seg,
+                                                   uint32_t seg_cap, const uint32_t *abort) {
     if (*abort) return;
     __shared__ int64_t dbw[256];
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
@@ -793,8 +822,8 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
                 atomicAdd((unsigned long long *)&dbw[s], (unsigned long long)(-c));
                 atomicAdd((unsigned long long *)&dbw[t], (unsigned long long)c);
             } else {
-                const uint32_t pi = x * k + y;
-                seg[pbase[pi] + atomicAdd(&pcur[pi], 1u)] = u;
+                const uint32_t at = atomicAdd(&pcur[x * k + y], 1u);
+                if (at < seg_cap) seg[pair_segment(x, y, k, seg_cap) + at] = u;
             }
         }
     }
@@ -838,84 +867,22 @@ __global__ __launch_bounds__(BLOCK) void k_gain_max(const uint32_t *list, uint32
 
 // ---------------------------------------------------------------------------
 // Pairs whose whole move sets do not fit: one workgroup per block pair.
-//   k_pair_plan  (one workgroup) applies the whole-pair test of k_lp_fast to
-//                every unordered pair {x < y} with proposals and gives each
-//                pair that fails it a segment of `seg` (exclusive prefix of
-//                the failing pairs' proposal counts) and a slot in the pair
-//                list.
-//   k_lp_fast    scatters those pairs' proposals into their segments, in no
-//                particular order.
-//   k_lp_pairs   sorts each segment in LDS by (direction, gain desc, u asc) --
-//                a total order, so the arbitrary segment order does not
-//                matter -- walks the merge path of the pair and applies the
-//                approved prefixes.  A pair of more than PAIR_MAX proposals is
-//                handed to the device-wide path: its proposals go to the slow
-//                list and the abort word records the sub-round, after which
-//                the host finishes the sub-round and replays the rest of the
-//                round.
+//   k_lp_fast    puts the proposals of every pair that fails the whole-pair
+//                test into the pair's segment, in no particular order.
+//   k_lp_pairs   finds those pairs by the same test, sorts each segment in
+//                LDS by (direction, gain desc, u asc) -- a total order, so the
+//                arbitrary segment order does not matter -- walks the merge
+//                path of the pair and applies the approved prefixes.  A pair
+//                of more than PAIR_MAX proposals is handed to the device-wide
+//                path: it is flagged and the abort word records the
+//                sub-round, after which the host collects the flagged pairs'
+//                proposals, finishes the sub-round and replays the rest of
+//                the round.
 // Block-weight changes go to dbw_g; every test of the sub-round reads the
 // snapshot block weights.
 // ---------------------------------------------------------------------------
-constexpr int PLAN_THREADS = 1024;
 constexpr int PAIR_THREADS = 512;
 constexpr uint32_t PAIR_MAX = 4096;
-
-// Pair entries i = x * k + y, PLAN_PER consecutive entries per thread and
-// round (one block scan per round); every load of a round is issued before
-// any is used.
-constexpr uint32_t PLAN_PER = 4;
-__global__ __launch_bounds__(PLAN_THREADS) void k_pair_plan(const uint32_t *pw, const uint32_t *pc, uint32_t k,
-                                                            const int64_t *bw, int64_t lmax, uint32_t *pbase,
-                                                            uint32_t *pcur, uint32_t *spairs, uint32_t *nsp,
-                                                            const uint32_t *abort) {
-    __shared__ uint64_t wsum[PLAN_THREADS / WAVE];
-    __shared__ int64_t sbeta[256];
-    if (*abort) return;
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t b = tid; b < k; b += PLAN_THREADS) sbeta[b] = floor_div_i64(lmax - bw[b], (int64_t)k - 1);
-    __syncthreads();
-    const uint32_t kk = k * k;
-    uint64_t carry = 0;  // (failing pairs << 32) | their proposals
-    for (uint32_t c0 = 0; c0 < kk; c0 += PLAN_THREADS * PLAN_PER) {
-        const uint32_t i0 = c0 + tid * PLAN_PER;
-        uint32_t x[PLAN_PER], y[PLAN_PER], ca[PLAN_PER], cb[PLAN_PER], wa[PLAN_PER], wb[PLAN_PER];
-#pragma unroll
-        for (uint32_t q = 0; q < PLAN_PER; ++q) {
-            const uint32_t i = i0 + q < kk ? i0 + q : 0u;
-            x[q] = i / k;
-            y[q] = i - x[q] * k;
-            const uint32_t it = y[q] * k + x[q];
-            ca[q] = pc[i];
-            cb[q] = pc[it];
-            wa[q] = pw[i];
-            wb[q] = pw[it];
-        }
-        uint32_t cnt[PLAN_PER];
-        uint64_t mine = 0;
-#pragma unroll
-        for (uint32_t q = 0; q < PLAN_PER; ++q) {
-            const uint32_t c = ca[q] + cb[q];
-            const int64_t xf = (int64_t)wa[q] - (int64_t)wb[q];
-            const bool fail = i0 + q < kk && x[q] < y[q] && c && !(-sbeta[x[q]] <= xf && xf <= sbeta[y[q]]);
-            cnt[q] = fail ? c : 0u;
-            if (fail) mine += (1ull << 32) | c;
-        }
-        uint64_t tot;
-        const uint64_t incl = block_incl_scan_n<uint64_t, PLAN_THREADS>(mine, wsum, &tot);
-        uint64_t ex = carry + incl - mine;
-#pragma unroll
-        for (uint32_t q = 0; q < PLAN_PER; ++q) {
-            if (!cnt[q]) continue;
-            const uint32_t i = i0 + q;
-            pbase[i] = (uint32_t)ex;
-            pcur[i] = 0;
-            spairs[(uint32_t)(ex >> 32)] = i;
-            ex += (1ull << 32) | cnt[q];
-        }
-        carry += tot;
-    }
-    if (tid == 0) *nsp = (uint32_t)(carry >> 32);
-}
 
 // Merge-path view of one direction of a pair: element i of the direction is
 // sorted position start + i; excl(i) is the weight of its first i elements.
@@ -937,12 +904,12 @@ __device__ inline uint32_t lcount_below(const LSeg &v, uint32_t x, bool strict) 
     return lo;
 }
 
-__global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *spairs, const uint32_t *nsp_dev,
-                                                           const uint32_t *pbase, const uint32_t *pc,
-                                                           const uint32_t *seg, uint32_t k, const uint32_t *prop_g,
-                                                           const int32_t *vwgt, uint32_t *part, const int64_t *bw,
-                                                           int64_t lmax, int64_t *dbw_g, uint32_t *slow,
-                                                           uint32_t *nslow, uint32_t *abort, uint32_t sub_id) {
+__global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *pw, const uint32_t *pc,
+                                                           const uint32_t *seg, uint32_t seg_cap, uint32_t k,
+                                                           const uint32_t *prop_g, const int32_t *vwgt,
+                                                           uint32_t *part, const int64_t *bw, int64_t lmax,
+                                                           int64_t *dbw_g, uint8_t *slowpair, uint32_t *abort,
+                                                           uint32_t sub_id) {
     __shared__ uint64_t skey[PAIR_MAX];
     __shared__ uint32_t sincl[PAIR_MAX];
     __shared__ uint32_t wsum[PAIR_THREADS / WAVE];
@@ -952,28 +919,32 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *spair
     const uint32_t aw = *abort;
     if (aw && aw != sub_id + 1) return;
     const uint32_t tid = threadIdx.x;
-    const uint32_t ns = *nsp_dev;
-    for (uint32_t q = blockIdx.x; q < ns; q += gridDim.x) {
-        const uint32_t pi = spairs[q];
+    for (uint32_t pi = blockIdx.x; pi < k * k; pi += gridDim.x) {
         const uint32_t x = pi / k, y = pi % k;
+        if (x >= y) continue;
         const uint32_t nA = pc[pi], L = nA + pc[y * k + x];
-        const uint32_t base = pbase[pi];
-        if (L > PAIR_MAX) {  // uniform per block
-            for (uint32_t c0 = 0; c0 < L; c0 += PAIR_THREADS) {
-                const uint32_t i = c0 + tid;
-                const uint32_t pos = warp_agg_append(nslow, i < L);
-                if (i < L) slow[pos] = seg[base + i];
+        if (L == 0) continue;
+        {  // the whole-pair test of k_lp_fast: such pairs are done
+            const int64_t xf = (int64_t)pw[pi] - (int64_t)pw[y * k + x];
+            const int64_t bx = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
+            const int64_t by = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
+            if (-bx <= xf && xf <= by) continue;
+        }
+        if (L > PAIR_MAX || L > seg_cap) {  // uniform per block
+            if (tid == 0) {
+                slowpair[pi] = 1;
+                atomicExch(abort, sub_id + 1);
             }
-            if (tid == 0) atomicExch(abort, sub_id + 1);
             continue;
         }
+        const uint32_t *sg = seg + pair_segment(x, y, k, seg_cap);
         uint32_t n2 = 1;
         while (n2 < L) n2 <<= 1;
         // key: direction (0: x -> y), then gain descending, then u (< 2^31)
         for (uint32_t i = tid; i < n2; i += PAIR_THREADS) {
             uint64_t key = ~0ull;
             if (i < L) {
-                const uint32_t u = seg[base + i];
+                const uint32_t u = sg[i];
                 const uint64_t dir = part[u] == x ? 0ull : 1ull;
                 key = (dir << 63) | ((uint64_t)(0xFFFFFFFFu - prop_g[u]) << 31) | (uint64_t)u;
             }
@@ -1152,7 +1123,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_heavy(const uint32_t *pin_o
 // The proposal-list lengths come in two sets used by alternate sub-rounds:
 // the update reads its own sub-round's set and clears the other one.
 struct NextSub {
-    uint32_t *scal, *pw, *pc;
+    uint32_t *scal, *pw, *pc, *pcur;
     uint32_t kk, k;
     int64_t *bw, *dbw_g;
     uint32_t *pcnt_next;
@@ -1161,7 +1132,7 @@ __device__ inline void next_subround(const NextSub &z) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
     if (tid == 0) z.scal[26] = 0;  // hub candidates
     if (tid < NSLOT) z.pcnt_next[tid * SPREAD_U32] = 0;
-    for (uint32_t i = tid; i < z.kk; i += nt) { z.pw[i] = 0; z.pc[i] = 0; }
+    for (uint32_t i = tid; i < z.kk; i += nt) { z.pw[i] = 0; z.pc[i] = 0; z.pcur[i] = 0; }
     if (blockIdx.x == 0)
         for (uint32_t b = threadIdx.x; b < z.k; b += blockDim.x) {
             const int64_t d = z.dbw_g[b];
@@ -1229,12 +1200,16 @@ struct RefineBufs {
     uint32_t *longl, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow;
     uint32_t *pcnt;  // [2][NSLOT * SPREAD_U32] proposal-list lengths, alternate sub-rounds
     uint32_t *dlists;  // hub candidates of the sub-round
-    uint32_t *pc, *pbase, *pcur, *spairs, *seg;  // per-pair proposal counts, segments of over-budget pairs
+    uint32_t *pc, *pcur, *seg;  // per-pair proposal counts, appends and segments of over-budget pairs
+    uint8_t *slowpair;          // [k*k] pairs handed to the device-wide path
     int64_t *dbw_g;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt, *seg_start, *seg_end;
     unsigned long long *best;
 };
+
+// Slots per unordered block pair for the sorted walk's proposals.
+static uint32_t pair_seg_cap(uint32_t n) { return n < PAIR_MAX ? n : PAIR_MAX; }
 
 static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     int KW = (int)((k + 63) / 64);
@@ -1260,10 +1235,9 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.best = A.alloc<unsigned long long>((size_t)k * k);
     B.pw = A.alloc<uint32_t>((size_t)k * k);
     B.pc = A.alloc<uint32_t>((size_t)k * k);
-    B.pbase = A.alloc<uint32_t>((size_t)k * k);
     B.pcur = A.alloc<uint32_t>((size_t)k * k);
-    B.spairs = A.alloc<uint32_t>((size_t)k * k);
-    B.seg = A.alloc<uint32_t>(n);
+    B.slowpair = A.alloc<uint8_t>((size_t)k * k);
+    B.seg = A.alloc<uint32_t>((size_t)k * (k - 1) / 2 * pair_seg_cap(n));
     B.slow = A.alloc<uint32_t>(n);
     B.heavy = A.alloc<uint32_t>(n);
     B.dbw_g = A.alloc<int64_t>(k);
@@ -1384,13 +1358,15 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     // abort word: 1 + the sub-round whose selection handed a pair to the
     // device-wide path (0: none); later kernels of the round skip their work
     uint32_t *abort = B.scal + 15;
-    uint32_t *nsp = B.scal + 25;  // over-budget pairs of the sub-round
     // all per-sub-round state starts at zero (afterwards the kernels of each
     // sub-round clear it for the next: the gains kernel what only later
     // kernels use, the update kernel the rest)
     HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 32, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.pw, 0, sizeof(uint32_t) * k * k, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.pc, 0, sizeof(uint32_t) * k * k, st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.pcur, 0, sizeof(uint32_t) * k * k, st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.slowpair, 0, (size_t)k * k, st));
+    const uint32_t seg_cap = pair_seg_cap(n);
     HGP_CHECK_HIP(hipMemsetAsync(B.dbw_g, 0, sizeof(int64_t) * k, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.pcnt, 0, sizeof(uint32_t) * 2 * NSLOT * SPREAD_U32, st));
     // proposal-list lengths of sub-round `stamp` (stamps are consecutive)
@@ -1400,7 +1376,16 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     // Device-wide selection of the pairs that sub-round (r, s) handed over
     // (more than PAIR_MAX proposals in one pair).  The counts are read back
     // here (the host has synchronised).
-    auto slow_path = [&](uint32_t ns) {
+    auto slow_path = [&](uint32_t stamp) {
+        // proposals of the flagged pairs
+        uint32_t ns = 0;
+        HGP_CHECK_HIP(hipMemsetAsync(nslow, 0, sizeof(uint32_t), st));
+        k_collect_slow<<<fast_blocks, BLOCK, 0, st>>>(B.plist, pcnt_of(stamp), slot_cap, part, B.prop_t, k,
+                                                      B.slowpair, B.slow, nslow);
+        HGP_LAUNCH_CHECK();
+        HGP_CHECK_HIP(hipMemcpyAsync(&ns, nslow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        stream_sync(st);
+        HGP_CHECK_HIP(hipMemsetAsync(B.slowpair, 0, (size_t)k * k, st));
         uint32_t G = 0;  // largest gain of the handed-over proposals
         if (ns) {
             HGP_CHECK_HIP(hipMemsetAsync(gmax, 0, sizeof(uint32_t), st));
@@ -1468,7 +1453,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         }
         {
             TimedLaunch tl(KID_LP_UPDATE, st);
-            const NextSub zn{B.scal, B.pw, B.pc, k * k, k, B.bw, B.dbw_g, pcnt_of(stamp + 1)};
+            const NextSub zn{B.scal, B.pw, B.pc, B.pcur, k * k, k, B.bw, B.dbw_g, pcnt_of(stamp + 1)};
             auto launch = [&](auto kern, uint32_t blocks) {
                 kern<<<blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.plist, pcnt_of(stamp), slot_cap,
                                                B.prop_t, part, (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl,
@@ -1513,19 +1498,16 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             k_gains_hub<KW><<<hub_blocks, HUB_THREADS, 0, st>>>(ga, B.dlists, nhub);
             HGP_LAUNCH_CHECK();
         }
-        k_pair_plan<<<1, PLAN_THREADS, 0, st>>>(B.pw, B.pc, k, B.bw, lmax, B.pbase, B.pcur, B.spairs, nsp, abort);
-        HGP_LAUNCH_CHECK();
         {  // pairs whose whole move sets are feasible: applied directly
             TimedLaunch tl(KID_LP_FAST, st);
             k_lp_fast<<<fast_blocks, BLOCK, 0, st>>>(B.plist, pcnt_of(stamp), slot_cap, B.prop_t, B.pw, k, h.vwgt,
-                                                     part, B.bw, lmax, B.dbw_g, B.pbase, B.pcur, B.seg, abort);
+                                                     part, B.bw, lmax, B.dbw_g, B.pcur, B.seg, seg_cap, abort);
             HGP_LAUNCH_CHECK();
         }
         {  // the other pairs: sorted two-pointer walk, a workgroup per pair
             TimedLaunch tl(KID_LP_PAIRS, st);
-            k_lp_pairs<<<pair_blocks, PAIR_THREADS, 0, st>>>(B.spairs, nsp, B.pbase, B.pc, B.seg, k, B.prop_g, h.vwgt,
-                                                             part, B.bw, lmax, B.dbw_g, B.slow, nslow,
-                                                             abort, s);
+            k_lp_pairs<<<pair_blocks, PAIR_THREADS, 0, st>>>(B.pw, B.pc, B.seg, seg_cap, k, B.prop_g, h.vwgt, part,
+                                                             B.bw, lmax, B.dbw_g, B.slowpair, abort, s);
             HGP_LAUNCH_CHECK();
         }
         update(stamp);
@@ -1543,7 +1525,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             // it there, then replay the remaining sub-rounds of the round
             const uint32_t s0 = hv[15] - 1;
             HGP_CHECK_HIP(hipMemsetAsync(abort, 0, sizeof(uint32_t), st));
-            slow_path(hv[13]);
+            slow_path(1 + r * S + s0);
             update(1 + r * S + s0);
             for (uint32_t s = s0 + 1; s < S; ++s) subround(r, s);
         }
