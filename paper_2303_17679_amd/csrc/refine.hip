@@ -88,6 +88,18 @@ __device__ inline int popc_bits(const uint64_t *x) {
     return c;
 }
 
+// Control words of an LP level.  Every kernel of sub-round `stamp` (stamps
+// 1 + r * S + s are consecutive over the level's rounds) does nothing once
+// an earlier sub-round was handed to the device-wide path (abort holds its
+// stamp) or when the previous round moved no node (prev -> its moves flag),
+// so whole rounds are queued without a host round trip.
+struct LpCtl {
+    uint32_t *abort;
+    const uint32_t *prev;  // nullptr in the first round
+    uint32_t stamp;
+};
+__device__ inline bool lp_skip(const LpCtl &c) { return *c.abort != 0 || (c.prev && *c.prev == 0); }
+
 // Thread per net for nets of at most 64 pins; longer nets go to a list.
 template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_conn_small(const uint32_t *pin_off, const uint32_t *pins, uint32_t m,
@@ -130,8 +142,8 @@ template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_conn_long(const uint32_t *pin_off, const uint32_t *pins,
                                                      const uint32_t *list, const uint32_t *count_dev,
                                                      const int32_t *nwgt, const uint32_t *part, NetRec<KW> *nr,
-                                                     int64_t *f, bool delta, uint32_t *bcnt, const uint32_t *abort) {
-    if (abort && *abort) return;
+                                                     int64_t *f, bool delta, uint32_t *bcnt, LpCtl ctl) {
+    if (ctl.abort && lp_skip(ctl)) return;  // (no control words when building the records)
     const uint32_t count = *count_dev;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nw = gridDim.x * blockDim.x / WAVE;
@@ -217,7 +229,7 @@ struct GainArgs {
     uint32_t *pw;  // [k*k] total weight proposed per ordered block pair
     uint32_t *pc;  // [k*k] number of proposals per ordered block pair
     uint32_t k;
-    const uint32_t *abort;  // set when the round must be resumed by the host
+    LpCtl ctl;
 };
 
 // Proposal lists: NSLOT lists by vertex chunk (see GainArgs).  A list holds
@@ -396,7 +408,7 @@ __global__ __launch_bounds__(BLOCK) void k_gains(GainArgs<KW> a, uint32_t ch, ui
                                                  uint32_t *nhub, uint32_t *scal) {
     __shared__ uint32_t lst[3][GAIN_CH];
     __shared__ uint32_t lcnt[3];
-    if (*a.abort) return;
+    if (lp_skip(a.ctl)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         scal[2] = 0; scal[3] = 0;     // ntouched, nlong
         scal[13] = 0; scal[14] = 0;   // oversized-pair proposals, movers
@@ -432,7 +444,7 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
     __shared__ unsigned long long Us[KW];
     __shared__ int64_t rbu[NW], rwi[NW];
     __shared__ uint32_t rg[NW], rt[NW];
-    if (*a.abort) return;
+    if (lp_skip(a.ctl)) return;
     const uint32_t cnt = *count_dev, tid = threadIdx.x, w = tid / WAVE;
     for (uint32_t idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
         const uint32_t u = list[idx];
@@ -560,6 +572,7 @@ template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs<KW> a, uint32_t *nmark, uint32_t stamp,
                                                          unsigned long long *acc) {
     __shared__ unsigned long long red[BLOCK / WAVE];
+    if (lp_skip(a.ctl)) return;  // the sub-round does nothing
     unsigned long long bytes = 0;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
         bytes += 4;  // boundary count
@@ -721,7 +734,7 @@ __global__ void k_lp_select(const uint64_t *keys, uint32_t np, KeyLayout L, uint
 // proposal lists (movers of the sub-round are in other pairs).
 __global__ __launch_bounds__(BLOCK) void k_collect_slow(const uint32_t *plist, const uint32_t *pcnt,
                                                         uint32_t slot_cap, const uint32_t *part,
-                                                        const uint32_t *prop_t, uint32_t k, const uint8_t *slowpair,
+                                                        const uint32_t *prop_t, uint32_t k, const uint32_t *slowpair,
                                                         uint32_t *slow, uint32_t *nslow) {
     const uint32_t sl = blockIdx.x % NSLOT, bj = blockIdx.x / NSLOT, nbj = gridDim.x / NSLOT;
     const uint32_t np = pcnt[sl * SPREAD_U32];
@@ -799,8 +812,8 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
                                                    const uint32_t *prop_t, const uint32_t *pw, uint32_t k,
                                                    const int32_t *vwgt, uint32_t *part, const int64_t *bw,
                                                    int64_t lmax, int64_t *dbw_g, uint32_t *pcur, uint32_t *seg,
-                                                   uint32_t seg_cap, const uint32_t *abort) {
-    if (*abort) return;
+                                                   uint32_t seg_cap, LpCtl ctl) {
+    if (lp_skip(ctl)) return;
     __shared__ int64_t dbw[256];
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
     __syncthreads();
@@ -830,6 +843,23 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK)
         if (dbw[b]) atomic_add_i64(&dbw_g[b], dbw[b]);
+}
+
+// Clears up to ZERO_MAX word ranges in one launch.
+constexpr int ZERO_MAX = 12;
+struct ZeroSet {
+    uint32_t *p[ZERO_MAX];
+    size_t len[ZERO_MAX];
+    int n;
+    void add(void *q, size_t words) {
+        if (words) { p[n] = (uint32_t *)q; len[n] = words; ++n; }
+    }
+};
+__global__ void k_zero_words(ZeroSet z) {
+    for (int a = 0; a < z.n; ++a)
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.len[a];
+             i += (size_t)gridDim.x * blockDim.x)
+            z.p[a][i] = 0;
 }
 
 __global__ void k_add_dbw(int64_t *bw, int64_t *dbw_g, uint32_t k) {
@@ -908,16 +938,15 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *pw, c
                                                            const uint32_t *seg, uint32_t seg_cap, uint32_t k,
                                                            const uint32_t *prop_g, const int32_t *vwgt,
                                                            uint32_t *part, const int64_t *bw, int64_t lmax,
-                                                           int64_t *dbw_g, uint8_t *slowpair, uint32_t *abort,
-                                                           uint32_t sub_id) {
+                                                           int64_t *dbw_g, uint32_t *slowpair, LpCtl ctl) {
     __shared__ uint64_t skey[PAIR_MAX];
     __shared__ uint32_t sincl[PAIR_MAX];
     __shared__ uint32_t wsum[PAIR_THREADS / WAVE];
     __shared__ unsigned long long sbest;
     // an earlier sub-round was cut short (a block of this launch may raise
     // the word for this sub-round: that does not stop the others)
-    const uint32_t aw = *abort;
-    if (aw && aw != sub_id + 1) return;
+    const uint32_t aw = *ctl.abort;
+    if ((aw && aw != ctl.stamp) || (ctl.prev && *ctl.prev == 0)) return;
     const uint32_t tid = threadIdx.x;
     for (uint32_t pi = blockIdx.x; pi < k * k; pi += gridDim.x) {
         const uint32_t x = pi / k, y = pi % k;
@@ -933,7 +962,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *pw, c
         if (L > PAIR_MAX || L > seg_cap) {  // uniform per block
             if (tid == 0) {
                 slowpair[pi] = 1;
-                atomicExch(abort, sub_id + 1);
+                atomicExch(ctl.abort, ctl.stamp);
             }
             continue;
         }
@@ -1022,8 +1051,10 @@ __global__ __launch_bounds__(BLOCK) void k_account_update(const uint32_t *pin_of
                                                           const uint32_t *inc, const uint32_t *plist,
                                                           const uint32_t *pcnt, uint32_t slot_cap,
                                                           const uint32_t *part, const uint32_t *prop_t,
-                                                          uint32_t *nmark, uint32_t stamp, unsigned long long *acc) {
+                                                          uint32_t *nmark, uint32_t stamp, unsigned long long *acc,
+                                                          LpCtl ctl) {
     __shared__ unsigned long long red[BLOCK / WAVE];
+    if (lp_skip(ctl)) return;  // the sub-round does nothing
     unsigned long long bytes = 0;
     const uint32_t sl = blockIdx.x % NSLOT, bj = blockIdx.x / NSLOT, nbj = gridDim.x / NSLOT;
     const uint32_t cnt = pcnt[sl * SPREAD_U32];
@@ -1090,8 +1121,8 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_heavy(const uint32_t *pin_o
                                                            const uint32_t *heavy, const uint32_t *nheavy,
                                                            const uint32_t *part, NetRec<KW> *nr, uint32_t *tstamp,
                                                            uint32_t stamp, int64_t *f, uint32_t *longl,
-                                                           uint32_t *nlong, uint32_t *bcnt, const uint32_t *abort) {
-    if (*abort) return;
+                                                           uint32_t *nlong, uint32_t *bcnt, LpCtl ctl) {
+    if (lp_skip(ctl)) return;
     __shared__ int64_t red[BLOCK / WAVE];
     const uint32_t cnt = *nheavy;
     int64_t acc = 0;
@@ -1152,8 +1183,8 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
                                                             uint32_t stamp, int64_t *f, uint32_t *longl,
                                                             uint32_t *nlong, uint32_t *moves, uint32_t *bcnt,
                                                             uint32_t *heavy, uint32_t *nheavy, NextSub z,
-                                                            const uint32_t *abort) {
-    if (*abort) return;
+                                                            LpCtl ctl) {
+    if (lp_skip(ctl)) return;
     next_subround(z);
     __shared__ int64_t red[BLOCK / WAVE];
     __shared__ uint32_t moved_any;
@@ -1201,12 +1232,16 @@ struct RefineBufs {
     uint32_t *pcnt;  // [2][NSLOT * SPREAD_U32] proposal-list lengths, alternate sub-rounds
     uint32_t *dlists;  // hub candidates of the sub-round
     uint32_t *pc, *pcur, *seg;  // per-pair proposal counts, appends and segments of over-budget pairs
-    uint8_t *slowpair;          // [k*k] pairs handed to the device-wide path
+    uint32_t *slowpair;         // [k*k] pairs handed to the device-wide path
+    uint32_t *rmoves;           // [LP_MAX_ROUNDS] moves flag of every round
     int64_t *dbw_g;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt, *seg_start, *seg_end;
     unsigned long long *best;
 };
+
+constexpr uint32_t LP_MAX_ROUNDS = 65536;  // above the largest accepted R_lp
+constexpr uint32_t LP_ROUND_BATCH = 8;      // rounds queued per host read-back
 
 // Slots per unordered block pair for the sorted walk's proposals.
 static uint32_t pair_seg_cap(uint32_t n) { return n < PAIR_MAX ? n : PAIR_MAX; }
@@ -1236,7 +1271,8 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.pw = A.alloc<uint32_t>((size_t)k * k);
     B.pc = A.alloc<uint32_t>((size_t)k * k);
     B.pcur = A.alloc<uint32_t>((size_t)k * k);
-    B.slowpair = A.alloc<uint8_t>((size_t)k * k);
+    B.slowpair = A.alloc<uint32_t>((size_t)k * k);
+    B.rmoves = A.alloc<uint32_t>(LP_MAX_ROUNDS);
     B.seg = A.alloc<uint32_t>((size_t)k * (k - 1) / 2 * pair_seg_cap(n));
     B.slow = A.alloc<uint32_t>(n);
     B.heavy = A.alloc<uint32_t>(n);
@@ -1252,16 +1288,21 @@ size_t refine_workspace(uint32_t n, uint32_t m, uint32_t k) {
     return A.peak;
 }
 
+// Net records and objective of `part`; the objective slots and the long-net
+// count start at zero (cleared here unless the caller has).
 template <int KW>
-static void build_conn(const hgp_hg &h, const uint32_t *part, RefineBufs &B, hipStream_t st) {
-    HGP_CHECK_HIP(hipMemsetAsync(B.f, 0, sizeof(int64_t) * SPREAD * SPREAD_I64, st));
-    HGP_CHECK_HIP(hipMemsetAsync(B.scal + 12, 0, sizeof(uint32_t), st));
+static void build_conn(const hgp_hg &h, const uint32_t *part, RefineBufs &B, hipStream_t st, bool zeroed = false) {
+    if (!zeroed) {
+        HGP_CHECK_HIP(hipMemsetAsync(B.f, 0, sizeof(int64_t) * SPREAD * SPREAD_I64, st));
+        HGP_CHECK_HIP(hipMemsetAsync(B.scal + 12, 0, sizeof(uint32_t), st));
+    }
     if (h.m) {
         k_conn_small<KW><<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
             h.pin_off, h.pins, h.m, h.nwgt, part, (NetRec<KW> *)B.nr, B.f, B.longl, B.scal + 12);
         HGP_LAUNCH_CHECK();
         k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, B.scal + 12, h.nwgt, part,
-                                                           (NetRec<KW> *)B.nr, B.f, false, nullptr, nullptr);
+                                                           (NetRec<KW> *)B.nr, B.f, false, nullptr,
+                                                           LpCtl{nullptr, nullptr, 0});
         HGP_LAUNCH_CHECK();
     }
 }
@@ -1309,12 +1350,28 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const uint64_t mseed = mix64(prm.seed);
     // device scalars: ntouched and nlong are adjacent so one memset clears both
     uint32_t *gmax = B.scal + 1, *ntouched = B.scal + 2, *nlong = B.scal + 3,
-             *moves = B.scal + 4, *dcnt = B.scal + 5 /* [NDEG] */, *nheavy = B.scal + 24,
+             *dcnt = B.scal + 5 /* [NDEG] */, *nheavy = B.scal + 24,
              *nslow = B.scal + 13;
 
-    build_conn<KW>(h, part, B, st);
-    block_weights(part, h.vwgt, n, k, B.bw, st);
-    if (m) HGP_CHECK_HIP(hipMemsetAsync(B.tstamp, 0, sizeof(uint32_t) * m, st));
+    {  // every counter, flag, stamp and accumulator of the level starts at zero
+        ZeroSet z{};
+        z.add(B.scal, 32);
+        z.add(B.pw, (size_t)k * k);
+        z.add(B.pc, (size_t)k * k);
+        z.add(B.pcur, (size_t)k * k);
+        z.add(B.slowpair, (size_t)k * k);
+        z.add(B.dbw_g, 2 * (size_t)k);
+        z.add(B.bw, 2 * (size_t)k);
+        z.add(B.pcnt, 2 * NSLOT * SPREAD_U32);
+        z.add(B.rmoves, std::min<uint32_t>(prm.lp_rounds, LP_MAX_ROUNDS));
+        z.add(B.f, 2 * SPREAD * SPREAD_I64);
+        z.add(B.tstamp, m);
+        k_zero_words<<<grid_for(std::max<size_t>(m, (size_t)k * k), BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(z);
+        HGP_LAUNCH_CHECK();
+    }
+    build_conn<KW>(h, part, B, st, true);
+    k_block_weights<<<grid_for(n, BLOCK * 8, REDUCE_BLOCKS), BLOCK, 0, st>>>(part, h.vwgt, n, k, B.bw);
+    HGP_LAUNCH_CHECK();
     if ((uint64_t)h.p >= (uint64_t)16 * n)  // average degree of at least 16: a wave per node
         k_init_bcnt_wave<KW><<<grid_for((size_t)n * WAVE, BLOCK, 4 * FILL_BLOCKS), BLOCK, 0, st>>>(
             h.inc_off, h.inc, n, (const NetRec<KW> *)B.nr, B.bcnt);
@@ -1323,7 +1380,6 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
                                                                            (const NetRec<KW> *)B.nr, B.bcnt);
     HGP_LAUNCH_CHECK();
     // degree classes of the nodes (lanes per node 1 / 8 / 64)
-    HGP_CHECK_HIP(hipMemsetAsync(dcnt, 0, sizeof(uint32_t) * NDEG, st));
     k_deg_classify<<<grid_for(n, BLOCK, REDUCE_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt);
     HGP_LAUNCH_CHECK();
     uint32_t dc[NDEG], hs[16];
@@ -1358,17 +1414,10 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     // abort word: 1 + the sub-round whose selection handed a pair to the
     // device-wide path (0: none); later kernels of the round skip their work
     uint32_t *abort = B.scal + 15;
-    // all per-sub-round state starts at zero (afterwards the kernels of each
+    // all per-sub-round state started at zero (afterwards the kernels of each
     // sub-round clear it for the next: the gains kernel what only later
     // kernels use, the update kernel the rest)
-    HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 32, st));
-    HGP_CHECK_HIP(hipMemsetAsync(B.pw, 0, sizeof(uint32_t) * k * k, st));
-    HGP_CHECK_HIP(hipMemsetAsync(B.pc, 0, sizeof(uint32_t) * k * k, st));
-    HGP_CHECK_HIP(hipMemsetAsync(B.pcur, 0, sizeof(uint32_t) * k * k, st));
-    HGP_CHECK_HIP(hipMemsetAsync(B.slowpair, 0, (size_t)k * k, st));
     const uint32_t seg_cap = pair_seg_cap(n);
-    HGP_CHECK_HIP(hipMemsetAsync(B.dbw_g, 0, sizeof(int64_t) * k, st));
-    HGP_CHECK_HIP(hipMemsetAsync(B.pcnt, 0, sizeof(uint32_t) * 2 * NSLOT * SPREAD_U32, st));
     // proposal-list lengths of sub-round `stamp` (stamps are consecutive)
     auto pcnt_of = [&](uint32_t stamp) { return B.pcnt + (stamp & 1u) * NSLOT * SPREAD_U32; };
     const uint32_t pair_blocks = std::min<uint32_t>(k * (k - 1) / 2, 1024u);
@@ -1385,7 +1434,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         HGP_LAUNCH_CHECK();
         HGP_CHECK_HIP(hipMemcpyAsync(&ns, nslow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         stream_sync(st);
-        HGP_CHECK_HIP(hipMemsetAsync(B.slowpair, 0, (size_t)k * k, st));
+        HGP_CHECK_HIP(hipMemsetAsync(B.slowpair, 0, sizeof(uint32_t) * k * k, st));
         uint32_t G = 0;  // largest gain of the handed-over proposals
         if (ns) {
             HGP_CHECK_HIP(hipMemsetAsync(gmax, 0, sizeof(uint32_t), st));
@@ -1440,7 +1489,13 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         HGP_LAUNCH_CHECK();
     };
     // Update of the nets touched by the sub-round's moves.
+    auto ctl_of = [&](uint32_t stamp) {
+        const uint32_t r = (stamp - 1) / S;
+        return LpCtl{abort, r ? B.rmoves + r - 1 : nullptr, stamp};
+    };
     auto update = [&](uint32_t stamp) {
+        const LpCtl ctl = ctl_of(stamp);
+        uint32_t *moved = B.rmoves + (stamp - 1) / S;
         if (accounting(KID_LP_UPDATE)) {
             Timing &T = timing();
             ++T.stamp;
@@ -1448,7 +1503,8 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             k_account_update<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, B.plist,
                                                                     pcnt_of(stamp), slot_cap, part, B.prop_t,
                                                                     T.marks, T.stamp,
-                                                                    (unsigned long long *)T.acc_dev + KID_LP_UPDATE);
+                                                                    (unsigned long long *)T.acc_dev + KID_LP_UPDATE,
+                                                                    ctl);
             HGP_LAUNCH_CHECK();
         }
         {
@@ -1457,7 +1513,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             auto launch = [&](auto kern, uint32_t blocks) {
                 kern<<<blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.plist, pcnt_of(stamp), slot_cap,
                                                B.prop_t, part, (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl,
-                                               nlong, moves, B.bcnt, B.heavy, nheavy, zn, abort);
+                                               nlong, moved, B.bcnt, B.heavy, nheavy, zn, ctl);
             };
             if (upd_g == 8) launch(k_lp_update_movers<KW, 8>, upd_blocks);
             else if (upd_g == 16) launch(k_lp_update_movers<KW, 16>, upd_blocks);
@@ -1467,21 +1523,22 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         if (dc[3]) {  // the level has nodes of more than HUB_DEG nets
             k_lp_update_heavy<KW><<<512, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.heavy, nheavy, part,
                                                          (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl, nlong,
-                                                         B.bcnt, abort);
+                                                         B.bcnt, ctl);
             HGP_LAUNCH_CHECK();
         }
         if (long_nets) {
             k_conn_long<KW><<<long_blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, h.nwgt, part,
-                                                           (NetRec<KW> *)B.nr, B.f, true, B.bcnt, abort);
+                                                           (NetRec<KW> *)B.nr, B.f, true, B.bcnt, ctl);
             HGP_LAUNCH_CHECK();
         }
     };
     // One sub-round, entirely on the device (no host round trip).
     auto subround = [&](uint32_t r, uint32_t s) {
         const uint32_t stamp = 1 + r * S + s;
+        const LpCtl ctl = ctl_of(stamp);
         const GainArgs<KW> ga{h.inc_off, h.inc, h.vwgt, (const NetRec<KW> *)B.nr, part, B.bw, B.bcnt, lmax, mseed,
                               level, r, s, S, n, B.prop_t, B.prop_g, B.plist, pcnt_of(stamp), gch, slot_cap,
-                              B.pw, B.pc, k, abort};
+                              B.pw, B.pc, k, ctl};
         if (accounting(KID_GAINS)) {
             Timing &T = timing();
             ++T.stamp;
@@ -1501,35 +1558,47 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         {  // pairs whose whole move sets are feasible: applied directly
             TimedLaunch tl(KID_LP_FAST, st);
             k_lp_fast<<<fast_blocks, BLOCK, 0, st>>>(B.plist, pcnt_of(stamp), slot_cap, B.prop_t, B.pw, k, h.vwgt,
-                                                     part, B.bw, lmax, B.dbw_g, B.pcur, B.seg, seg_cap, abort);
+                                                     part, B.bw, lmax, B.dbw_g, B.pcur, B.seg, seg_cap, ctl);
             HGP_LAUNCH_CHECK();
         }
         {  // the other pairs: sorted two-pointer walk, a workgroup per pair
             TimedLaunch tl(KID_LP_PAIRS, st);
             k_lp_pairs<<<pair_blocks, PAIR_THREADS, 0, st>>>(B.pw, B.pc, B.seg, seg_cap, k, B.prop_g, h.vwgt, part,
-                                                             B.bw, lmax, B.dbw_g, B.slowpair, abort, s);
+                                                             B.bw, lmax, B.dbw_g, B.slowpair, ctl);
             HGP_LAUNCH_CHECK();
         }
         update(stamp);
     };
 
-    for (uint32_t r = 0; r < prm.lp_rounds; ++r) {
-        HGP_CHECK_HIP(hipMemsetAsync(moves, 0, sizeof(uint32_t), st));
-        for (uint32_t s = 0; s < S; ++s) subround(r, s);
-        uint32_t hv[17];
-        for (;;) {
-            HGP_CHECK_HIP(hipMemcpyAsync(hv, B.scal, sizeof(hv), hipMemcpyDeviceToHost, st));
-            stream_sync(st);
-            if (!hv[15]) break;
-            // sub-round hv[15] - 1 handed pairs to the device-wide path: finish
-            // it there, then replay the remaining sub-rounds of the round
-            const uint32_t s0 = hv[15] - 1;
+    // Rounds are queued LP_ROUND_BATCH at a time with one read-back per
+    // batch: a round after one without moves does nothing on the device, and
+    // a sub-round handed to the device-wide path stops every later one until
+    // the host has finished it; the rest is then queued again.
+    const uint32_t R = std::min<uint32_t>(prm.lp_rounds, LP_MAX_ROUNDS);
+    uint32_t r0 = 0, s0 = 0;  // next sub-round to queue
+    while (r0 < R) {
+        const uint32_t r1 = std::min<uint32_t>(R, r0 + LP_ROUND_BATCH);
+        for (uint32_t r = r0; r < r1; ++r)
+            for (uint32_t s = (r == r0 ? s0 : 0); s < S; ++s) subround(r, s);
+        uint32_t hv[2];
+        HGP_CHECK_HIP(hipMemcpyAsync(&hv[0], abort, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HGP_CHECK_HIP(hipMemcpyAsync(&hv[1], B.rmoves + r1 - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        stream_sync(st);
+        if (hv[0]) {
+            // sub-round hv[0] handed pairs to the device-wide path: finish it
+            // there, then queue the sub-rounds after it again
+            const uint32_t stamp = hv[0];
             HGP_CHECK_HIP(hipMemsetAsync(abort, 0, sizeof(uint32_t), st));
-            slow_path(1 + r * S + s0);
-            update(1 + r * S + s0);
-            for (uint32_t s = s0 + 1; s < S; ++s) subround(r, s);
+            slow_path(stamp);
+            update(stamp);
+            r0 = (stamp - 1) / S;
+            s0 = (stamp - 1) % S + 1;
+            if (s0 == S) { ++r0; s0 = 0; }
+            continue;
         }
-        if (hv[4] == 0) break;  // no move in the whole round
+        if (hv[1] == 0) break;  // the batch ended with a round without moves
+        r0 = r1;
+        s0 = 0;
     }
     // the last sub-round's block-weight changes
     k_add_dbw<<<1, 256, 0, st>>>(B.bw, B.dbw_g, k);
