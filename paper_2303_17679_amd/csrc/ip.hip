@@ -93,6 +93,11 @@ struct AppendOrder {
     }
 };
 
+// State of a BFS layer in device memory (two copies, by layer parity): the
+// frontier order[fs, fs + F), the next free order position, and the layer's
+// expansion size T and winner count W once known.
+enum BfsWord { BFS_FS = 0, BFS_POS = 1, BFS_F = 2, BFS_T = 3, BFS_W = 4, BFS_WORDS = 8 };
+
 __global__ void k_mark_range(const uint32_t *order, uint32_t a, uint32_t b, uint32_t *visited,
                              unsigned long long *key) {
     for (uint32_t i = a + blockIdx.x * blockDim.x + threadIdx.x; i < b; i += gridDim.x * blockDim.x) {
@@ -102,19 +107,40 @@ __global__ void k_mark_range(const uint32_t *order, uint32_t a, uint32_t b, uint
     }
 }
 
-__global__ void k_put_start(uint32_t *order, uint32_t pos, const uint32_t *start, uint32_t *visited) {
+// The start vertex opens a BFS: order[pos] = s, the first layer state.
+__global__ void k_put_start(uint32_t *order, uint32_t pos, const uint32_t *start, uint32_t *visited, uint32_t *bst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         uint32_t s = *start;
         order[pos] = s;
         visited[s] = 1;
+        bst[BFS_FS] = pos;
+        bst[BFS_POS] = pos + 1;
+        bst[BFS_F] = 1;
+    }
+}
+
+// Layer winners [pos, pos + W) become visited; the next layer's state (the
+// other copy) has them as its frontier.
+__global__ void k_bfs_mark(const uint32_t *order, const uint32_t *cur, uint32_t *nxt, uint32_t *visited,
+                           unsigned long long *key) {
+    const uint32_t a = cur[BFS_POS], W = cur[BFS_W];
+    for (uint32_t i = a + blockIdx.x * blockDim.x + threadIdx.x; i < a + W; i += gridDim.x * blockDim.x) {
+        uint32_t w = order[i];
+        visited[w] = 1;
+        key[w] = ~0ull;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        nxt[BFS_FS] = a;
+        nxt[BFS_POS] = a + W;
+        nxt[BFS_F] = W;
     }
 }
 
 struct FrontierDeg {
     const uint32_t *order, *inc_off;
-    uint32_t fs;
+    const uint32_t *fs;
     __device__ uint32_t operator()(size_t i) const {
-        uint32_t v = order[fs + i];
+        uint32_t v = order[*fs + i];
         return inc_off[v + 1] - inc_off[v];
     }
 };
@@ -131,11 +157,10 @@ __device__ inline void pair_of(const uint32_t *D, uint32_t F, uint32_t t, const 
     jj = inc_off[order[fs + fi]] + (t - D[fi]);
 }
 
-__global__ void k_bfs_keys(const uint32_t *D, uint32_t F, const uint32_t *Tdev, const uint32_t *order, uint32_t fs,
-                           const uint32_t *inc_off, const uint32_t *inc, const uint32_t *pin_off,
-                           const uint32_t *pins, const uint32_t *exoff, const uint32_t *visited,
-                           unsigned long long *key) {
-    const uint32_t T = *Tdev;
+__global__ void k_bfs_keys(const uint32_t *D, const uint32_t *bst, const uint32_t *order, const uint32_t *inc_off,
+                           const uint32_t *inc, const uint32_t *pin_off, const uint32_t *pins,
+                           const uint32_t *exoff, const uint32_t *visited, unsigned long long *key) {
+    const uint32_t F = bst[BFS_F], T = bst[BFS_T], fs = bst[BFS_FS];
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
         uint32_t fi, jj;
         pair_of(D, F, t, order, fs, inc_off, fi, jj);
@@ -150,12 +175,11 @@ __global__ void k_bfs_keys(const uint32_t *D, uint32_t F, const uint32_t *Tdev, 
 }
 
 // winners of pair t: count (write=false) or append in key order (write=true)
-__global__ void k_bfs_winners(const uint32_t *D, uint32_t F, const uint32_t *Tdev, const uint32_t *order,
-                              uint32_t fs, const uint32_t *inc_off, const uint32_t *inc, const uint32_t *pin_off,
+__global__ void k_bfs_winners(const uint32_t *D, const uint32_t *bst, const uint32_t *order,
+                              const uint32_t *inc_off, const uint32_t *inc, const uint32_t *pin_off,
                               const uint32_t *pins, const uint32_t *exoff, const uint32_t *visited,
-                              const unsigned long long *key, uint32_t *cnt, uint32_t *order_out, uint32_t pos,
-                              bool write) {
-    const uint32_t T = *Tdev;
+                              const unsigned long long *key, uint32_t *cnt, uint32_t *order_out, bool write) {
+    const uint32_t F = bst[BFS_F], T = bst[BFS_T], fs = bst[BFS_FS], pos = bst[BFS_POS];
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
         uint32_t fi, jj;
         pair_of(D, F, t, order, fs, inc_off, fi, jj);
@@ -460,6 +484,7 @@ __global__ __launch_bounds__(IPS_THREADS) void k_ip_small(const uint32_t *pin_of
 
 struct IpBufs {
     uint32_t *order, *visited, *J, *S, *exoff, *D, *cnt, *scal;
+    uint32_t *bst;  // [2][BFS_WORDS] BFS layer states
     unsigned long long *key;
     uint64_t *P, *E;
 };
@@ -476,6 +501,7 @@ static void plan(Arena &A, uint32_t n, uint32_t p, uint32_t k, IpBufs &B) {
     B.cnt = A.alloc<uint32_t>((size_t)p + 1);
     B.E = A.alloc<uint64_t>(std::min<size_t>(p, IPS_MAX_P) + 1);
     B.scal = A.alloc<uint32_t>(8);
+    B.bst = A.alloc<uint32_t>(2 * BFS_WORDS);
     scan_reserve<uint64_t>(A, n);
     scan_reserve<uint32_t>(A, (size_t)p + 1);
 }
@@ -486,6 +512,8 @@ size_t ip_workspace(uint32_t n, uint32_t p, uint32_t k) {
     plan(A, n, p, k, B);
     return A.peak;
 }
+
+constexpr uint32_t BFS_BATCH = 8;  // BFS layers queued per host read-back
 
 static uint32_t read_u32(const uint32_t *d, hipStream_t st) {
     uint32_t h = 0;
@@ -522,7 +550,7 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
         A.release(mk);
         return;
     }
-    uint32_t *d_start = B.scal + 0, *d_cnt = B.scal + 1, *d_T = B.scal + 2, *d_W = B.scal + 3;
+    uint32_t *d_start = B.scal + 0, *d_cnt = B.scal + 1;
     HGP_CHECK_HIP(hipMemsetAsync(B.visited, 0, sizeof(uint32_t) * n, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.key, 0xFF, sizeof(unsigned long long) * n, st));
     k_exoff<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, B.exoff);
@@ -544,36 +572,40 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
             pos += c;
         }
         if (s >= n) break;
-        k_put_start<<<1, 64, 0, st>>>(B.order, pos, d_start, B.visited);
+        k_put_start<<<1, 64, 0, st>>>(B.order, pos, d_start, B.visited, B.bst);
         HGP_LAUNCH_CHECK();
-        uint32_t fs = pos, fe = pos + 1;
-        pos += 1;
         next = s + 1;
-        while (fs < fe) {
-            const uint32_t F = fe - fs;
-            scan_apply<uint32_t>(A, F, FrontierDeg{B.order, h.inc_off, fs}, StoreExcl<uint32_t>{B.D}, d_T, st);
-            const uint32_t Tn = read_u32(d_T, st);
-            if (Tn == 0) break;
-            const unsigned g = grid_for(Tn, BLOCK, FILL_BLOCKS);
-            k_bfs_keys<<<g, BLOCK, 0, st>>>(B.D, F, d_T, B.order, fs, h.inc_off, h.inc, h.pin_off, h.pins, B.exoff,
-                                            B.visited, B.key);
-            HGP_LAUNCH_CHECK();
-            k_bfs_winners<<<g, BLOCK, 0, st>>>(B.D, F, d_T, B.order, fs, h.inc_off, h.inc, h.pin_off, h.pins,
-                                               B.exoff, B.visited, B.key, B.cnt, B.order, pos, false);
-            HGP_LAUNCH_CHECK();
-            exclusive_scan<uint32_t>(A, B.cnt, B.cnt, Tn, d_W, st);
-            k_bfs_winners<<<g, BLOCK, 0, st>>>(B.D, F, d_T, B.order, fs, h.inc_off, h.inc, h.pin_off, h.pins,
-                                               B.exoff, B.visited, B.key, B.cnt, B.order, pos, true);
-            HGP_LAUNCH_CHECK();
-            const uint32_t Wn = read_u32(d_W, st);
-            if (Wn) {
-                k_mark_range<<<grid_for(Wn, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.order, pos, pos + Wn, B.visited,
-                                                                                B.key);
+        // BFS layers, BFS_BATCH at a time with the state in device memory
+        // (sizes are bounded by n and p, layers after the last do nothing);
+        // one read-back per batch tells whether the frontier has emptied
+        const unsigned gT = grid_for(h.p, BLOCK, FILL_BLOCKS), gW = grid_for(n, BLOCK, FILL_BLOCKS);
+        for (uint32_t layer = 0;;) {
+            for (uint32_t b = 0; b < BFS_BATCH; ++b, ++layer) {
+                uint32_t *cur = B.bst + (layer & 1u) * BFS_WORDS, *nxt = B.bst + ((layer + 1) & 1u) * BFS_WORDS;
+                scan_apply_dn<uint32_t>(A, n, cur + BFS_F, FrontierDeg{B.order, h.inc_off, cur + BFS_FS},
+                                        StoreExcl<uint32_t>{B.D}, cur + BFS_T, st);
+                k_bfs_keys<<<gT, BLOCK, 0, st>>>(B.D, cur, B.order, h.inc_off, h.inc, h.pin_off, h.pins, B.exoff,
+                                                 B.visited, B.key);
+                HGP_LAUNCH_CHECK();
+                k_bfs_winners<<<gT, BLOCK, 0, st>>>(B.D, cur, B.order, h.inc_off, h.inc, h.pin_off, h.pins,
+                                                    B.exoff, B.visited, B.key, B.cnt, B.order, false);
+                HGP_LAUNCH_CHECK();
+                scan_apply_dn<uint32_t>(A, h.p, cur + BFS_T, LoadArr<uint32_t>{B.cnt}, StoreExcl<uint32_t>{B.cnt},
+                                        cur + BFS_W, st);
+                k_bfs_winners<<<gT, BLOCK, 0, st>>>(B.D, cur, B.order, h.inc_off, h.inc, h.pin_off, h.pins,
+                                                    B.exoff, B.visited, B.key, B.cnt, B.order, true);
+                HGP_LAUNCH_CHECK();
+                k_bfs_mark<<<gW, BLOCK, 0, st>>>(B.order, cur, nxt, B.visited, B.key);
                 HGP_LAUNCH_CHECK();
             }
-            fs = pos;
-            fe = pos + Wn;
-            pos += Wn;
+            uint32_t hs[BFS_WORDS];
+            HGP_CHECK_HIP(hipMemcpyAsync(hs, B.bst + (layer & 1u) * BFS_WORDS, sizeof(hs), hipMemcpyDeviceToHost,
+                                         st));
+            stream_sync(st);
+            if (hs[BFS_F] == 0) {
+                pos = hs[BFS_POS];
+                break;
+            }
         }
     }
     scan_apply<uint64_t>(A, n, OrderWeight{B.order, h.vwgt}, StoreInclP{B.P}, (uint64_t *)nullptr, st);

@@ -135,6 +135,98 @@ void scan_apply(Arena &A, size_t n, In in, Out out, T *total_dev, hipStream_t st
     A.release(mk);
 }
 
+// The same scan with the element count in device memory (at most nmax):
+// the grid is sized for nmax and tiles past the count do nothing, so no host
+// round trip is needed to learn the count.
+template <class T, class In>
+__global__ __launch_bounds__(BLOCK) void k_tile_reduce_dn(const uint32_t *n_dev, In in, T *tile_sum) {
+    __shared__ T lds[BLOCK / WAVE];
+    const size_t n = *n_dev;
+    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+        if (base + i < n) s += in(base + i);
+    s = wave_sum(s);
+    if (__lane_id() == 0) lds[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T t = 0;
+        for (int i = 0; i < BLOCK / WAVE; ++i) t += lds[i];
+        tile_sum[blockIdx.x] = t;  // zero past the count
+    }
+}
+
+template <class T, class In, class Out>
+__global__ __launch_bounds__(BLOCK) void k_tile_scan_dn(const uint32_t *n_dev, In in, Out out, const T *tile_off) {
+    __shared__ T lds[BLOCK / WAVE];
+    const size_t n = *n_dev;
+    if ((size_t)blockIdx.x * SCAN_TILE >= n) return;  // uniform per block
+    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    T v[SCAN_ITEMS];
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = (base + i < n) ? in(base + i) : T(0);
+        s += v[i];
+    }
+    T incl = block_incl_scan<T>(s, lds, nullptr);
+    T run = tile_off[blockIdx.x] + incl - s;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < n) out(base + i, run, v[i]);
+        run += v[i];
+    }
+}
+
+template <class T, class In, class Out>
+__global__ __launch_bounds__(BLOCK) void k_scan_small_dn(const uint32_t *n_dev, In in, Out out, T *total) {
+    __shared__ T lds[BLOCK / WAVE];
+    const size_t n = *n_dev;
+    T carry = 0;
+    for (size_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
+        const size_t base = t0 + (size_t)threadIdx.x * SCAN_ITEMS;
+        T v[SCAN_ITEMS];
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            v[i] = (base + i < n) ? in(base + i) : T(0);
+            s += v[i];
+        }
+        T tot;
+        const T incl = block_incl_scan<T>(s, lds, &tot);
+        T run = carry + incl - s;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            if (base + i < n) out(base + i, run, v[i]);
+            run += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <class T, class In, class Out>
+void scan_apply_dn(Arena &A, size_t nmax, const uint32_t *n_dev, In in, Out out, T *total_dev, hipStream_t st) {
+    const size_t ntiles = (nmax + SCAN_TILE - 1) / SCAN_TILE;
+    size_t mk = A.mark();
+    T *tiles = A.alloc<T>(ntiles ? ntiles : 1);
+    if (A.measure) { A.release(mk); return; }
+    if (ntiles <= SCAN_SMALL_TILES) {
+        k_scan_small_dn<T, In, Out><<<1, BLOCK, 0, st>>>(n_dev, in, out, total_dev);
+        HGP_LAUNCH_CHECK();
+        A.release(mk);
+        return;
+    }
+    k_tile_reduce_dn<T, In><<<(unsigned)ntiles, BLOCK, 0, st>>>(n_dev, in, tiles);
+    HGP_LAUNCH_CHECK();
+    k_scan_tiles<T><<<1, BLOCK, 0, st>>>(ntiles, tiles, total_dev);
+    HGP_LAUNCH_CHECK();
+    k_tile_scan_dn<T, In, Out><<<(unsigned)ntiles, BLOCK, 0, st>>>(n_dev, in, out, tiles);
+    HGP_LAUNCH_CHECK();
+    A.release(mk);
+}
+
 // Size-only reservation of scan_apply's temporaries (never launches).
 template <class T>
 inline void scan_reserve(Arena &A, size_t n) {
