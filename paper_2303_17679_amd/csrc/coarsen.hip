@@ -45,6 +45,7 @@ struct RateArgs {
     bool dedup;  // false in the first sub-round: every cluster is a singleton
     const uint32_t *ncl;  // clusters after the previous sub-round
     uint32_t n_cur;       // vertices of the level
+    const uint32_t *ovf;  // set: an earlier sub-round awaits the host (nullptr: none can)
 };
 
 // The pass stops once the clustering has shrunk the level below n / 2.5
@@ -54,6 +55,15 @@ __device__ inline bool pass_cut(const uint32_t *ncl, uint32_t n) {
     return (uint64_t)5 * *ncl < (uint64_t)2 * n;
 }
 
+// A pass whose sub-rounds are all queued at once: the sorted approval of a
+// sub-round runs in one workgroup, and one too large for it sets ovf to
+// 1 + the sub-round, after which every later kernel of the pass does
+// nothing until the host has finished that sub-round.  cut[r] keeps the
+// pass-cut decision of sub-round r, taken before its joins change the
+// cluster count.
+__device__ inline bool ovf_set(const uint32_t *ovf) { return ovf && *ovf != 0; }
+__device__ inline bool rate_skip(const RateArgs &a) { return ovf_set(a.ovf) || pass_cut(a.ncl, a.n_cur); }
+
 // Larger than any cluster weight (< 2^31) while cap_mult * (c(u) + TINFO_BAD)
 // stays far from overflow (cap_mult = limit_factor * k < 2^26).
 constexpr int64_t TINFO_BAD = (int64_t)1 << 34;
@@ -61,10 +71,18 @@ constexpr int64_t TINFO_BAD = (int64_t)1 << 34;
 // tinfo[C]: cw[C] if C may be joined in sub-round r, TINFO_BAD if C is itself
 // a candidate singleton of the sub-round (no chains within a sub-round).
 // Every vertex of the sub-round starts with no target.
+// Block 0 also clears the slow-join count and records the pass-cut decision.
 __global__ void k_target_info(const uint32_t *rep, const int64_t *cw, const int32_t *vwgt, uint32_t n,
                               uint64_t mseed, uint32_t level, uint32_t S, uint32_t r, int64_t *tinfo,
-                              uint32_t *ptarget, const uint32_t *ncl) {
-    if (pass_cut(ncl, n)) return;
+                              uint32_t *ptarget, const uint32_t *ncl, uint32_t *nslow, uint32_t *cut,
+                              const uint32_t *ovf) {
+    if (ovf_set(ovf)) return;
+    const bool c = pass_cut(ncl, n);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *nslow = 0;
+        cut[r] = c ? 1u : 0u;
+    }
+    if (c) return;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         int64_t c = cw[v];
         const bool mine = tag_hash(mseed, 1, level, 0, v) % S == r;
@@ -136,7 +154,7 @@ __device__ inline void rate_small_net(const RateArgs &a, uint32_t u, uint32_t b,
 template <int G, int CAP, int LOG2CAP>
 __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t *list, uint32_t count) {
     constexpr int GPB = BLOCK / G;
-    if (pass_cut(a.ncl, a.n_cur)) return;
+    if (rate_skip(a)) return;
     __shared__ uint32_t keys[GPB][CAP];
     __shared__ uint32_t stamp[GPB][CAP];
     __shared__ uint64_t R[GPB][CAP];
@@ -254,7 +272,7 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t *list, uint32_t count) {
     constexpr int LCAP = 4096, LLOG = 12;
-    if (pass_cut(a.ncl, a.n_cur)) return;
+    if (rate_skip(a)) return;
     __shared__ uint32_t keys[LCAP];
     __shared__ uint32_t stamp[LCAP];
     __shared__ uint64_t R[LCAP];
@@ -377,7 +395,7 @@ __global__ __launch_bounds__(BLOCK) void k_hub_info(RateArgs a, const uint32_t *
                                                     const uint32_t *bound, uint32_t n_cur, uint4 *info) {
     for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
         const uint32_t u = list[i];
-        const bool active = a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u] && !pass_cut(a.ncl, a.n_cur);
+        const bool active = a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u] && !rate_skip(a);
         const uint32_t D = bound[u] < n_cur - 1 ? bound[u] : n_cur - 1;
         info[i] = make_uint4(u, a.inc_off[u], a.inc_off[u + 1], active ? D : NONE);
     }
@@ -759,7 +777,7 @@ __global__ __launch_bounds__(BLOCK) void k_account_rate(RateArgs a, const uint32
                                                         uint32_t *nmark, uint32_t *vmark, uint32_t *cmark,
                                                         uint32_t stamp, unsigned long long *acc) {
     __shared__ unsigned long long red[BLOCK / WAVE];
-    if (pass_cut(a.ncl, a.n_cur)) return;
+    if (rate_skip(a)) return;
     unsigned long long bytes = 0;
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
         const uint32_t u = list[idx];
@@ -904,7 +922,7 @@ constexpr int MAX_KEYS = 256 * NCLASS;
 constexpr unsigned CLASSIFY_BLOCKS = 512;
 // The class of a candidate follows D = min(B(u), n - 1), a bound on the
 // distinct clusters it rates; counts[S * NCLASS] receives the largest D of
-// the global-table class.
+// the global-table class and counts[S * NCLASS + 2] the largest vertex weight.
 __device__ inline int classify_key(const uint32_t *bound, uint32_t n, uint64_t mseed, uint32_t level, uint32_t S,
                                    uint32_t u, uint32_t *D) {
     *D = bound[u] < n - 1 ? bound[u] : n - 1;
@@ -919,27 +937,39 @@ __global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *bound, uint3
                                                     uint32_t *lists, bool fill) {
     __shared__ uint32_t lcnt[MAX_KEYS];
     __shared__ uint32_t lbase[MAX_KEYS];
-    __shared__ uint32_t lmaxd;
+    __shared__ uint32_t lmaxd, lmaxw;
     const uint32_t nkeys = S * NCLASS;
     for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) lcnt[i] = 0;
-    if (threadIdx.x == 0) lmaxd = 0;
+    if (threadIdx.x == 0) { lmaxd = 0; lmaxw = 0; }
     __syncthreads();
+    uint32_t mw = 0;  // largest vertex weight seen by the thread
     for (uint32_t u = blockIdx.x * BLOCK + threadIdx.x; u < n; u += gridDim.x * BLOCK) {
         uint32_t D;
         const int key = classify_key(bound, n, mseed, level, S, u, &D);
         if (!fill) {
+            const int32_t w = vwgt[u];
             rep[u] = u;
-            cw[u] = vwgt[u];
+            cw[u] = w;
             tsum[u] = 0;
+            mw = (uint32_t)w > mw ? (uint32_t)w : mw;
             if (key >= 0 && (uint32_t)key % NCLASS == NCLASS - 1) atomicMax(&lmaxd, D);
         }
         if (key >= 0) atomicAdd(&lcnt[key], 1u);
+    }
+    if (!fill) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t y = __shfl_xor(mw, o, 64);
+            mw = y > mw ? y : mw;
+        }
+        if (__lane_id() == 0 && mw) atomicMax(&lmaxw, mw);
     }
     __syncthreads();
     if (!fill) {
         for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK)
             if (lcnt[i]) atomicAdd(&counts[i], lcnt[i]);
         if (threadIdx.x == 0 && lmaxd) atomicMax(&counts[nkeys], lmaxd);
+        if (threadIdx.x == 0 && lmaxw) atomicMax(&counts[nkeys + 2], lmaxw);
         return;
     }
     for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) {
@@ -961,8 +991,8 @@ __global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *bound, uint3
 // Proposers are the candidates of the sub-round's list whose target is set.
 __global__ void k_approve_fast(const uint32_t *cands, uint32_t nc, const uint32_t *ptarget, const int64_t *cw,
                                const int64_t *tsum, int64_t cap_mult, int64_t W, uint8_t *ok, uint32_t *slow,
-                               uint32_t *nslow, const uint32_t *ncl, uint32_t n) {
-    if (pass_cut(ncl, n)) return;  // nothing was rated
+                               uint32_t *nslow, const uint32_t *ncl, uint32_t n, const uint32_t *ovf) {
+    if (ovf_set(ovf) || pass_cut(ncl, n)) return;  // nothing was rated
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ((nc + 63) / 64) * 64;
          i += gridDim.x * blockDim.x) {
         const uint32_t u = i < nc ? cands[i] : 0;
@@ -1031,13 +1061,26 @@ __global__ void k_slow_decide(const uint32_t *vals, uint32_t ns, const uint32_t 
 // decision as k_slow_decide.  Needs the key to fit 64 bits.
 constexpr uint32_t SLOW_SMALL = 4096;
 constexpr int SLOW_THREADS = 1024;
+// With ns_dev the count is read on the device (queued passes): nothing to do
+// when the sub-round found the pass cut or an earlier one awaits the host,
+// and more than SLOW_SMALL joins hand the sub-round to the host (ovf).
 __global__ __launch_bounds__(SLOW_THREADS) void k_slow_small(const uint32_t *slow, uint32_t ns,
                                                              const uint32_t *ptarget, const int32_t *vwgt,
                                                              const int64_t *cw, int64_t cap_mult, int64_t W,
-                                                             uint8_t *ok, int wb, int ub) {
+                                                             uint8_t *ok, int wb, int ub, const uint32_t *ns_dev,
+                                                             const uint32_t *cut_r, uint32_t *ovf, uint32_t r) {
     __shared__ uint64_t key[SLOW_SMALL];
     __shared__ uint64_t incl[SLOW_SMALL];
     __shared__ uint64_t wsum[SLOW_THREADS / WAVE];
+    if (ns_dev) {
+        if (*cut_r || *ovf) return;
+        ns = *ns_dev;
+        if (ns > SLOW_SMALL) {
+            if (threadIdx.x == 0) *ovf = r + 1;
+            return;
+        }
+    }
+    if (ns == 0) return;
     const uint32_t tid = threadIdx.x;
     const int cs = wb + ub;
     const uint64_t umask = (1ull << ub) - 1ull, wmask = (1ull << wb) - 1ull;
@@ -1092,8 +1135,10 @@ __global__ __launch_bounds__(SLOW_THREADS) void k_slow_small(const uint32_t *slo
 constexpr unsigned APPLY_BLOCKS = 512;
 __global__ __launch_bounds__(BLOCK) void k_apply_joins(const uint32_t *cands, uint32_t nc, const uint32_t *ptarget,
                                                        const uint8_t *ok, const int32_t *vwgt, uint32_t *rep,
-                                                       int64_t *cw, int64_t *tsum, uint32_t *n_clusters) {
+                                                       int64_t *cw, int64_t *tsum, uint32_t *n_clusters,
+                                                       const uint32_t *cut_r, const uint32_t *ovf) {
     __shared__ uint32_t red[BLOCK / WAVE];
+    if (*cut_r || ovf_set(ovf)) return;  // nothing was rated, or the host finishes the sub-round
     uint32_t joins = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
         const uint32_t u = cands[i];
@@ -1152,10 +1197,10 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, uint32_t S, Coars
     B.ptarget = A.alloc<uint32_t>(n);
     B.slow = A.alloc<uint32_t>(n);
     B.lists = A.alloc<uint32_t>(n);
-    B.counts = A.alloc<uint32_t>((size_t)S * NCLASS + 2);  // + largest D, largest net
+    B.counts = A.alloc<uint32_t>((size_t)S * NCLASS + 3);  // + largest D, largest net, largest vertex weight
     B.bound = A.alloc<uint32_t>(n);
     B.cursor = A.alloc<uint32_t>((size_t)S * NCLASS);
-    B.scal = A.alloc<uint32_t>(8);
+    B.scal = A.alloc<uint32_t>(8 + 256);  // counters, then the cut decision of every sub-round
     B.ok = A.alloc<uint8_t>(n);
     B.keys = A.alloc<uint64_t>(n);
     B.keys_alt = A.alloc<uint64_t>(n);
@@ -1219,7 +1264,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
 
     k_net_score<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.nwgt, m, B.nscore);
     HGP_LAUNCH_CHECK();
-    HGP_CHECK_HIP(hipMemsetAsync(B.counts, 0, sizeof(uint32_t) * (S * NCLASS + 2), st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.counts, 0, sizeof(uint32_t) * (S * NCLASS + 3), st));
     if ((uint64_t)h.p >= (uint64_t)16 * n)  // average degree of at least 16: a wave per vertex
         k_vertex_b_wave<<<grid_for((size_t)std::max(n, m) * WAVE, BLOCK, 4 * FILL_BLOCKS), BLOCK, 0, st>>>(
             h.pin_off, h.inc_off, h.inc, n, m, B.bound, B.counts + S * NCLASS + 1);
@@ -1230,8 +1275,8 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     k_classify<<<grid_for(n, BLOCK, CLASSIFY_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
                                                                  B.tsum, B.counts, B.cursor, B.lists, false);
     HGP_LAUNCH_CHECK();
-    std::vector<uint32_t> counts(S * NCLASS + 2), offs(S * NCLASS + 1);
-    HGP_CHECK_HIP(hipMemcpyAsync(counts.data(), B.counts, sizeof(uint32_t) * (S * NCLASS + 2), hipMemcpyDeviceToHost,
+    std::vector<uint32_t> counts(S * NCLASS + 3), offs(S * NCLASS + 1);
+    HGP_CHECK_HIP(hipMemcpyAsync(counts.data(), B.counts, sizeof(uint32_t) * (S * NCLASS + 3), hipMemcpyDeviceToHost,
                                  st));
     const bool huge_nets = counts[S * NCLASS + 1] > HUB_BIG;
     stream_sync(st);
@@ -1393,19 +1438,22 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     HGP_LAUNCH_CHECK();
 
     uint32_t cnt = n;
-    int wb = -1;  // bits of the largest vertex weight (read when the sorted approval first runs)
-    uint32_t *nslow = B.scal + 1, *ncl = B.scal + 2;
+    uint32_t *nslow = B.scal + 1, *ncl = B.scal + 2, *ovf = B.scal + 3, *cut = B.scal + 8;  // cut: [S] words
+    const int ub = bits_for(n ? n - 1 : 0), cb = ub;
+    const int wb = bits_for((uint64_t)counts[S * NCLASS + 2]);  // bits of the largest vertex weight
+    // Queued pass: every sub-round goes to the device at once when the
+    // approval keys fit one word and no hub candidate needs host planning;
+    // otherwise the host reads the slow-join count back after every sub-round.
+    const bool queued = cb + wb + ub <= 64 && !any_hub;
     HGP_CHECK_HIP(hipMemcpyAsync(ncl, &cnt, sizeof(uint32_t), hipMemcpyHostToDevice, st));
-    for (uint32_t r = 0; r < S; ++r) {
-        HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 2, st));
+    if (queued) HGP_CHECK_HIP(hipMemsetAsync(ovf, 0, sizeof(uint32_t), st));
+    auto rate_subround = [&](uint32_t r) {
         k_target_info<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(rep, B.cw, h.vwgt, n, mseed, level, S, r,
-                                                                        B.tinfo, B.ptarget, ncl);
+                                                                        B.tinfo, B.ptarget, ncl, nslow, cut,
+                                                                        queued ? ovf : nullptr);
         HGP_LAUNCH_CHECK();
         RateArgs a{h.pin_off, h.pins, h.inc_off, h.inc, h.vwgt, B.nscore, rep, B.cw, B.tinfo, B.ptarget, B.tsum,
-                   mseed, level, r, S, cap_mult, W, r > 0, ncl, n};
-        const uint32_t *cands = B.lists + offs[r * NCLASS];  // the sub-round's candidates, all classes
-        uint32_t cand = 0;  // candidates listed for the sub-round: a bound on its proposals
-        for (int c = 0; c < NCLASS; ++c) cand += counts[r * NCLASS + c];
+                   mseed, level, r, S, cap_mult, W, r > 0, ncl, n, queued ? ovf : nullptr};
         for (int c = 0; c < NCLASS; ++c) {
             uint32_t cntc = counts[r * NCLASS + c];
             if (!cntc) continue;
@@ -1440,11 +1488,96 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             }
             HGP_LAUNCH_CHECK();
         }
-        if (cand) {
-            k_approve_fast<<<grid_for(cand, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(cands, cand, B.ptarget, B.cw,
-                                                                                B.tsum, cap_mult, W, B.ok, B.slow,
-                                                                                nslow, ncl, n);
+    };
+    auto cands_of = [&](uint32_t r) { return B.lists + offs[r * NCLASS]; };  // the sub-round's candidates
+    auto cand_of = [&](uint32_t r) {  // candidates listed for the sub-round: a bound on its proposals
+        uint32_t c = 0;
+        for (int q = 0; q < NCLASS; ++q) c += counts[r * NCLASS + q];
+        return c;
+    };
+    auto approve = [&](uint32_t r) {
+        k_approve_fast<<<grid_for(cand_of(r), BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+            cands_of(r), cand_of(r), B.ptarget, B.cw, B.tsum, cap_mult, W, B.ok, B.slow, nslow, ncl, n,
+            queued ? ovf : nullptr);
+        HGP_LAUNCH_CHECK();
+    };
+    auto apply = [&](uint32_t r, const uint32_t *ovf_or_null) {
+        k_apply_joins<<<grid_for(cand_of(r), BLOCK, APPLY_BLOCKS), BLOCK, 0, st>>>(
+            cands_of(r), cand_of(r), B.ptarget, B.ok, h.vwgt, rep, B.cw, B.tsum, ncl, cut + r, ovf_or_null);
+        HGP_LAUNCH_CHECK();
+    };
+    // sorted approval of ns slow joins on the host-driven path
+    auto host_slow = [&](uint32_t ns) {
+        uint64_t *kk = B.keys;
+        uint32_t *vv = B.vals;
+        if (ns <= SLOW_SMALL && cb + wb + ub <= 64) {
+            k_slow_small<<<1, SLOW_THREADS, 0, st>>>(B.slow, ns, B.ptarget, h.vwgt, B.cw, cap_mult, W, B.ok, wb, ub,
+                                                     nullptr, nullptr, nullptr, 0);
             HGP_LAUNCH_CHECK();
+            return;
+        }
+        if (cb + wb + ub <= 64) {
+            k_slow_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.slow, ns, B.ptarget, h.vwgt, wb, ub, kk,
+                                                                           vv, true);
+            HGP_LAUNCH_CHECK();
+            radix_sort_pairs<uint64_t>(A, &kk, &vv, kk == B.keys ? B.keys_alt : B.keys,
+                                       vv == B.vals ? B.vals_alt : B.vals, ns, 0, cb + wb + ub, st);
+        } else {
+            // stable two-stage: by u, then by (C, c(u))
+            k_u_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.slow, ns, kk, vv);
+            HGP_LAUNCH_CHECK();
+            radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, ub, st);
+            uint64_t *k2 = (kk == B.keys) ? B.keys_alt : B.keys;
+            uint32_t *v2 = (vv == B.vals) ? B.vals_alt : B.vals;
+            k_slow_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(vv, ns, B.ptarget, h.vwgt, wb, 0, kk, v2,
+                                                                           false);
+            HGP_LAUNCH_CHECK();
+            // kk holds keys aligned with v2 (= copy of vv)
+            uint32_t *vcur = v2;
+            radix_sort_pairs<uint64_t>(A, &kk, &vcur, k2, vv, ns, 0, cb + wb, st);
+            vv = vcur;
+        }
+        scan_apply<uint64_t>(A, ns, WeightOfSorted{vv, h.vwgt}, StoreInclU64{B.incl}, (uint64_t *)nullptr, st);
+        k_slow_decide<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(vv, ns, B.ptarget, B.incl, h.vwgt, B.cw,
+                                                                         cap_mult, W, B.ok);
+        HGP_LAUNCH_CHECK();
+    };
+    if (queued) {
+        // one read-back per pass (more when a sub-round is handed back)
+        uint32_t r0 = 0;
+        for (;;) {
+            for (uint32_t r = r0; r < S; ++r) {
+                rate_subround(r);
+                if (!cand_of(r)) {  // nothing listed: the sub-round only records its cut decision
+                    continue;
+                }
+                approve(r);
+                k_slow_small<<<1, SLOW_THREADS, 0, st>>>(B.slow, 0, B.ptarget, h.vwgt, B.cw, cap_mult, W, B.ok, wb,
+                                                         ub, nslow, cut + r, ovf, r);
+                HGP_LAUNCH_CHECK();
+                apply(r, ovf);
+            }
+            uint32_t hv[2];  // cluster count, handed-back sub-round
+            HGP_CHECK_HIP(hipMemcpyAsync(hv, ncl, sizeof(hv), hipMemcpyDeviceToHost, st));
+            stream_sync(st);
+            cnt = hv[0];
+            if (!hv[1]) break;
+            // sub-round hv[1] - 1 had more slow joins than one workgroup
+            // sorts: approve them on the host-driven path, apply, go on
+            const uint32_t r = hv[1] - 1;
+            uint32_t ns = 0;
+            HGP_CHECK_HIP(hipMemcpyAsync(&ns, nslow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            HGP_CHECK_HIP(hipMemsetAsync(ovf, 0, sizeof(uint32_t), st));
+            stream_sync(st);
+            host_slow(ns);
+            apply(r, nullptr);
+            r0 = r + 1;
+        }
+    } else {
+        for (uint32_t r = 0; r < S; ++r) {
+            rate_subround(r);
+            if (!cand_of(r)) continue;
+            approve(r);
             // one read-back per sub-round: the joins that need the sorted
             // approval, and the cluster count after the previous sub-round
             uint32_t hv[3];
@@ -1453,52 +1586,12 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             const uint32_t ns = hv[1];
             cnt = hv[2];
             if ((uint64_t)5 * cnt < (uint64_t)2 * n) break;  // the pass was cut: nothing was proposed
-            if (ns) {
-                int ub = bits_for(n ? n - 1 : 0);
-                int cb = bits_for(n ? n - 1 : 0);
-                if (wb < 0) wb = bits_for((uint64_t)max_vertex_weight(h.vwgt, n, A, st));  // once per pass
-                uint64_t *kk = B.keys;
-                uint32_t *vv = B.vals;
-                if (ns <= SLOW_SMALL && cb + wb + ub <= 64) {
-                    k_slow_small<<<1, SLOW_THREADS, 0, st>>>(B.slow, ns, B.ptarget, h.vwgt, B.cw, cap_mult, W, B.ok,
-                                                             wb, ub);
-                    HGP_LAUNCH_CHECK();
-                } else {
-                    if (cb + wb + ub <= 64) {
-                        k_slow_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.slow, ns, B.ptarget,
-                                                                                       h.vwgt, wb, ub, kk, vv, true);
-                        HGP_LAUNCH_CHECK();
-                        radix_sort_pairs<uint64_t>(A, &kk, &vv, kk == B.keys ? B.keys_alt : B.keys,
-                                                   vv == B.vals ? B.vals_alt : B.vals, ns, 0, cb + wb + ub, st);
-                    } else {
-                        // stable two-stage: by u, then by (C, c(u))
-                        k_u_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(B.slow, ns, kk, vv);
-                        HGP_LAUNCH_CHECK();
-                        radix_sort_pairs<uint64_t>(A, &kk, &vv, B.keys_alt, B.vals_alt, ns, 0, ub, st);
-                        uint64_t *k2 = (kk == B.keys) ? B.keys_alt : B.keys;
-                        uint32_t *v2 = (vv == B.vals) ? B.vals_alt : B.vals;
-                        k_slow_keys<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(vv, ns, B.ptarget, h.vwgt,
-                                                                                       wb, 0, kk, v2, false);
-                        HGP_LAUNCH_CHECK();
-                        // kk holds keys aligned with v2 (= copy of vv)
-                        uint32_t *vcur = v2;
-                        radix_sort_pairs<uint64_t>(A, &kk, &vcur, k2, vv, ns, 0, cb + wb, st);
-                        vv = vcur;
-                    }
-                    scan_apply<uint64_t>(A, ns, WeightOfSorted{vv, h.vwgt}, StoreInclU64{B.incl},
-                                         (uint64_t *)nullptr, st);
-                    k_slow_decide<<<grid_for(ns, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(vv, ns, B.ptarget, B.incl,
-                                                                                     h.vwgt, B.cw, cap_mult, W, B.ok);
-                    HGP_LAUNCH_CHECK();
-                }
-            }
-            k_apply_joins<<<grid_for(cand, BLOCK, APPLY_BLOCKS), BLOCK, 0, st>>>(cands, cand, B.ptarget, B.ok,
-                                                                                h.vwgt, rep, B.cw, B.tsum, ncl);
-            HGP_LAUNCH_CHECK();
+            if (ns) host_slow(ns);
+            apply(r, nullptr);
         }
+        HGP_CHECK_HIP(hipMemcpyAsync(&cnt, ncl, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        stream_sync(st);
     }
-    HGP_CHECK_HIP(hipMemcpyAsync(&cnt, ncl, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    stream_sync(st);
     if (n_clusters_dev)
         HGP_CHECK_HIP(hipMemcpyAsync(n_clusters_dev, ncl, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
     if (n_clusters_host) *n_clusters_host = cnt;

@@ -56,6 +56,7 @@ CASES = [
     ("random120k", 256, 6),   # four words per net
     ("random120k", 2, 5),     # one block pair of more than 4096 proposals: device-wide selection and replay
     ("hugenets", 4, 9),       # hub ratings with nets of more than 2048 pins
+    ("stars", 2, 1),          # sub-rounds of more than 4096 slow joins: a queued pass hands them back to the host
 ]
 
 
@@ -70,6 +71,12 @@ def make(name):
         return W.from_nets(n, nets, nwgt=rs.randint(1, 4, size=len(nets)))
     if name == "random120k":
         return W.random_uniform(120000, 120000, 2, 8, seed=4, name=name)
+    if name == "stars":
+        # 100 stars of 600 leaves (2-pin nets leaf-center): the leaves of a
+        # sub-round all propose to their center, far beyond the cluster cap,
+        # so the sorted approval takes 13227, then 6537 joins (oracle counts)
+        nets = [[c * 601, c * 601 + i] for c in range(100) for i in range(1, 601)]
+        return W.from_nets(100 * 601, nets)
     return W.workload(name)[0]
 
 
