@@ -812,7 +812,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
                                                    const uint32_t *prop_t, const uint32_t *pw, uint32_t k,
                                                    const int32_t *vwgt, uint32_t *part, const int64_t *bw,
                                                    int64_t lmax, int64_t *dbw_g, uint32_t *pcur, uint32_t *seg,
-                                                   uint32_t seg_cap, LpCtl ctl) {
+                                                   uint32_t seg_cap, uint32_t *spairs, uint32_t *nsp, LpCtl ctl) {
     if (lp_skip(ctl)) return;
     __shared__ int64_t dbw[256];
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
@@ -837,6 +837,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const 
             } else {
                 const uint32_t at = atomicAdd(&pcur[x * k + y], 1u);
                 if (at < seg_cap) seg[pair_segment(x, y, k, seg_cap) + at] = u;
+                if (at == 0) spairs[atomicAdd(nsp, 1u)] = x * k + y;  // the pair's first proposal lists it
             }
         }
     }
@@ -898,8 +899,9 @@ __global__ __launch_bounds__(BLOCK) void k_gain_max(const uint32_t *list, uint32
 // ---------------------------------------------------------------------------
 // Pairs whose whole move sets do not fit: one workgroup per block pair.
 //   k_lp_fast    puts the proposals of every pair that fails the whole-pair
-//                test into the pair's segment, in no particular order.
-//   k_lp_pairs   finds those pairs by the same test, sorts each segment in
+//                test into the pair's segment, in no particular order, and
+//                lists the pair.
+//   k_lp_pairs   takes the listed pairs, sorts each segment in
 //                LDS by (direction, gain desc, u asc) -- a total order, so the
 //                arbitrary segment order does not matter -- walks the merge
 //                path of the pair and applies the approved prefixes.  A pair
@@ -934,8 +936,9 @@ __device__ inline uint32_t lcount_below(const LSeg &v, uint32_t x, bool strict) 
     return lo;
 }
 
-__global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *pw, const uint32_t *pc,
-                                                           const uint32_t *seg, uint32_t seg_cap, uint32_t k,
+__global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *spairs, const uint32_t *nsp,
+                                                           const uint32_t *pc, const uint32_t *seg, uint32_t seg_cap,
+                                                           uint32_t k,
                                                            const uint32_t *prop_g, const int32_t *vwgt,
                                                            uint32_t *part, const int64_t *bw, int64_t lmax,
                                                            int64_t *dbw_g, uint32_t *slowpair, LpCtl ctl) {
@@ -948,17 +951,11 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *pw, c
     const uint32_t aw = *ctl.abort;
     if ((aw && aw != ctl.stamp) || (ctl.prev && *ctl.prev == 0)) return;
     const uint32_t tid = threadIdx.x;
-    for (uint32_t pi = blockIdx.x; pi < k * k; pi += gridDim.x) {
-        const uint32_t x = pi / k, y = pi % k;
-        if (x >= y) continue;
+    const uint32_t np = *nsp;
+    for (uint32_t q = blockIdx.x; q < np; q += gridDim.x) {
+        const uint32_t pi = spairs[q];
+        const uint32_t x = pi / k, y = pi % k;  // x < y
         const uint32_t nA = pc[pi], L = nA + pc[y * k + x];
-        if (L == 0) continue;
-        {  // the whole-pair test of k_lp_fast: such pairs are done
-            const int64_t xf = (int64_t)pw[pi] - (int64_t)pw[y * k + x];
-            const int64_t bx = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
-            const int64_t by = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
-            if (-bx <= xf && xf <= by) continue;
-        }
         if (L > PAIR_MAX || L > seg_cap) {  // uniform per block
             if (tid == 0) {
                 slowpair[pi] = 1;
@@ -1161,7 +1158,7 @@ struct NextSub {
 };
 __device__ inline void next_subround(const NextSub &z) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
-    if (tid == 0) z.scal[26] = 0;  // hub candidates
+    if (tid == 0) { z.scal[25] = 0; z.scal[26] = 0; }  // listed pairs, hub candidates
     if (tid < NSLOT) z.pcnt_next[tid * SPREAD_U32] = 0;
     for (uint32_t i = tid; i < z.kk; i += nt) { z.pw[i] = 0; z.pc[i] = 0; z.pcur[i] = 0; }
     if (blockIdx.x == 0)
@@ -1232,6 +1229,7 @@ struct RefineBufs {
     uint32_t *pcnt;  // [2][NSLOT * SPREAD_U32] proposal-list lengths, alternate sub-rounds
     uint32_t *dlists;  // hub candidates of the sub-round
     uint32_t *pc, *pcur, *seg;  // per-pair proposal counts, appends and segments of over-budget pairs
+    uint32_t *spairs;           // the sub-round's over-budget pairs
     uint32_t *slowpair;         // [k*k] pairs handed to the device-wide path
     uint32_t *rmoves;           // [LP_MAX_ROUNDS] moves flag of every round
     int64_t *dbw_g;
@@ -1272,6 +1270,7 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.pc = A.alloc<uint32_t>((size_t)k * k);
     B.pcur = A.alloc<uint32_t>((size_t)k * k);
     B.slowpair = A.alloc<uint32_t>((size_t)k * k);
+    B.spairs = A.alloc<uint32_t>((size_t)k * k);
     B.rmoves = A.alloc<uint32_t>(LP_MAX_ROUNDS);
     B.seg = A.alloc<uint32_t>((size_t)k * (k - 1) / 2 * pair_seg_cap(n));
     B.slow = A.alloc<uint32_t>(n);
@@ -1420,7 +1419,8 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const uint32_t seg_cap = pair_seg_cap(n);
     // proposal-list lengths of sub-round `stamp` (stamps are consecutive)
     auto pcnt_of = [&](uint32_t stamp) { return B.pcnt + (stamp & 1u) * NSLOT * SPREAD_U32; };
-    const uint32_t pair_blocks = std::min<uint32_t>(k * (k - 1) / 2, 1024u);
+    const uint32_t pair_blocks = std::min<uint32_t>(k * (k - 1) / 2, 256u);
+    uint32_t *nsp = B.scal + 25;  // over-budget pairs of the sub-round (list in spairs)
 
     // Device-wide selection of the pairs that sub-round (r, s) handed over
     // (more than PAIR_MAX proposals in one pair).  The counts are read back
@@ -1558,13 +1558,14 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         {  // pairs whose whole move sets are feasible: applied directly
             TimedLaunch tl(KID_LP_FAST, st);
             k_lp_fast<<<fast_blocks, BLOCK, 0, st>>>(B.plist, pcnt_of(stamp), slot_cap, B.prop_t, B.pw, k, h.vwgt,
-                                                     part, B.bw, lmax, B.dbw_g, B.pcur, B.seg, seg_cap, ctl);
+                                                     part, B.bw, lmax, B.dbw_g, B.pcur, B.seg, seg_cap, B.spairs,
+                                                     nsp, ctl);
             HGP_LAUNCH_CHECK();
         }
         {  // the other pairs: sorted two-pointer walk, a workgroup per pair
             TimedLaunch tl(KID_LP_PAIRS, st);
-            k_lp_pairs<<<pair_blocks, PAIR_THREADS, 0, st>>>(B.pw, B.pc, B.seg, seg_cap, k, B.prop_g, h.vwgt, part,
-                                                             B.bw, lmax, B.dbw_g, B.slowpair, ctl);
+            k_lp_pairs<<<pair_blocks, PAIR_THREADS, 0, st>>>(B.spairs, nsp, B.pc, B.seg, seg_cap, k, B.prop_g,
+                                                             h.vwgt, part, B.bw, lmax, B.dbw_g, B.slowpair, ctl);
             HGP_LAUNCH_CHECK();
         }
         update(stamp);
