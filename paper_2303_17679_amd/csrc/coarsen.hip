@@ -137,7 +137,8 @@ __device__ inline void rate_small_net(const RateArgs &a, uint32_t u, uint32_t b,
 #pragma unroll
     for (uint32_t q = 0; q < LANE_NET; ++q) C[q] = q < sz ? a.pins[b + q] : NONE;
 #pragma unroll
-    for (uint32_t q = 0; q < LANE_NET; ++q) C[q] = (C[q] != NONE && C[q] != u) ? a.rep[C[q]] : NONE;
+    for (uint32_t q = 0; q < LANE_NET; ++q)  // (first sub-round: every vertex is its own cluster)
+        C[q] = (C[q] != NONE && C[q] != u) ? (a.dedup ? a.rep[C[q]] : C[q]) : NONE;
 #pragma unroll
     for (uint32_t q = 0; q < LANE_NET; ++q) {
         bool fresh = C[q] != NONE;
@@ -150,18 +151,22 @@ __device__ inline void rate_small_net(const RateArgs &a, uint32_t u, uint32_t b,
 // ---------------------------------------------------------------------------
 // Groups of G lanes (G <= 64), one candidate per group, LDS table of CAP.
 // Occupied slots are listed so that argmax and clearing touch only them.
+// A large net adds its score once per cluster: a bit per slot marks the
+// clusters it has reached (cleared before each large net).
 // ---------------------------------------------------------------------------
 template <int G, int CAP, int LOG2CAP>
 __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t *list, uint32_t count) {
     constexpr int GPB = BLOCK / G;
+    constexpr int MW = CAP / 64;  // mask words per group
     if (rate_skip(a)) return;
     __shared__ uint32_t keys[GPB][CAP];
-    __shared__ uint32_t stamp[GPB][CAP];
+    __shared__ unsigned long long seen[GPB][MW];
     __shared__ uint64_t R[GPB][CAP];
-    __shared__ uint16_t occ[GPB][CAP];
+    using OccT = typename std::conditional<(CAP <= 256), uint8_t, uint16_t>::type;  // slot indices
+    __shared__ OccT occ[GPB][CAP];
     __shared__ uint32_t nocc[GPB];
     const int g = threadIdx.x / G, l = threadIdx.x % G;
-    for (int s = l; s < CAP; s += G) { keys[g][s] = NONE; stamp[g][s] = NONE; R[g][s] = 0; }
+    for (int s = l; s < CAP; s += G) { keys[g][s] = NONE; R[g][s] = 0; }
     if (l == 0) nocc[g] = 0;
     wave_sync();
     // groups never synchronise with each other (each lives inside one wave),
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
                 if (k == NONE) {
                     uint32_t old = atomicCAS(&keys[g][slot], NONE, C);
                     if (old == NONE) {
-                        occ[g][atomicAdd(&nocc[g], 1u)] = (uint16_t)slot;
+                        occ[g][atomicAdd(&nocc[g], 1u)] = (OccT)slot;
                         break;
                     }
                     if (old == C) break;
@@ -210,12 +215,20 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
                 uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
                 if (sz <= LANE_NET) continue;
                 uint64_t sc = a.nscore[e];
+                if (a.dedup) {
+                    for (int w = l; w < MW; w += G) seen[g][w] = 0ull;
+                    wave_sync();
+                }
                 for (uint32_t q = l; q < sz; q += G) {
                     uint32_t v = a.pins[b + q];
                     if (v == u) continue;
-                    uint32_t slot = insert(a.rep[v], sc);
-                    if (!a.dedup || atomicExch(&stamp[g][slot], e) != e)
-                        atomicAdd((unsigned long long *)&R[g][slot], (unsigned long long)sc);
+                    const uint32_t slot = insert(a.dedup ? a.rep[v] : v, sc);
+                    bool first = true;
+                    if (a.dedup) {
+                        const unsigned long long bit = 1ull << (slot & 63);
+                        first = (atomicOr(&seen[g][slot >> 6], bit) & bit) == 0ull;
+                    }
+                    if (first) atomicAdd((unsigned long long *)&R[g][slot], (unsigned long long)sc);
                 }
                 wave_sync();
             }
@@ -240,7 +253,6 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
                     Cs[k4] = keys[g][slot];
                     Rs[k4] = R[g][slot];
                     keys[g][slot] = NONE;  // leave the table clean for the next candidate
-                    stamp[g][slot] = NONE;
                     R[g][slot] = 0;
                 }
             }
