@@ -404,7 +404,7 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
 // sub-round use.
 constexpr uint32_t GAIN_CH = 2048;  // largest chunk
 template <int KW>
-__global__ __launch_bounds__(BLOCK) void k_gains(GainArgs<KW> a, uint32_t ch, uint32_t nchunks, uint32_t *hubl,
+__global__ __launch_bounds__(BLOCK, 6) void k_gains(GainArgs<KW> a, uint32_t ch, uint32_t nchunks, uint32_t *hubl,
                                                  uint32_t *nhub, uint32_t *scal) {
     __shared__ uint32_t lst[3][GAIN_CH];
     __shared__ uint32_t lcnt[3];
