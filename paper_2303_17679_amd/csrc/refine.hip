@@ -402,7 +402,7 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
 // wave up to HUB_DEG; larger nodes go to the hub list for k_gains_hub.
 // Block 0 also clears the counters that only the later kernels of the
 // sub-round use.
-constexpr uint32_t GAIN_CH = 2048;  // largest chunk
+constexpr uint32_t GAIN_CH = 1024;  // largest chunk
 template <int KW>
 __global__ __launch_bounds__(BLOCK, 6) void k_gains(GainArgs<KW> a, uint32_t ch, uint32_t nchunks, uint32_t *hubl,
                                                  uint32_t *nhub, uint32_t *scal) {
@@ -419,9 +419,30 @@ __global__ __launch_bounds__(BLOCK, 6) void k_gains(GainArgs<KW> a, uint32_t ch,
         const uint32_t lo = c * ch, hi = lo + ch < a.n ? lo + ch : a.n;
         if (threadIdx.x < 3) lcnt[threadIdx.x] = 0;
         __syncthreads();
-        for (uint32_t v = lo + threadIdx.x; v < hi; v += BLOCK) {
-            if (a.bcnt[v] == 0 || tag_hash(a.mseed, 3, a.level, a.round, v) % a.S != a.sub) continue;
-            const int cls = deg_class(a.inc_off[v + 1] - a.inc_off[v]);
+        // a thread's vertices lo + q * BLOCK: every load of a step is issued
+        // before any is used (boundary counts, then the candidates' degrees)
+        constexpr int PER = GAIN_CH / BLOCK;
+        uint32_t bc[PER], d[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t v = lo + q * BLOCK + threadIdx.x;
+            bc[q] = v < hi ? a.bcnt[v] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t v = lo + q * BLOCK + threadIdx.x;
+            if (bc[q] && tag_hash(a.mseed, 3, a.level, a.round, v) % a.S != a.sub) bc[q] = 0;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t v = lo + q * BLOCK + threadIdx.x;
+            d[q] = bc[q] ? a.inc_off[v + 1] - a.inc_off[v] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (!bc[q]) continue;
+            const uint32_t v = lo + q * BLOCK + threadIdx.x;
+            const int cls = deg_class(d[q]);
             if (cls == 3) hubl[atomicAdd(nhub, 1u)] = v;
             else lst[cls][atomicAdd(&lcnt[cls], 1u)] = v;
         }
