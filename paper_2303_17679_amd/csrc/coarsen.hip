@@ -881,11 +881,17 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, con
         if (u < n) { j0 = inc_off[u]; j1 = inc_off[u + 1]; }
         const bool heavy = j1 - j0 > 32;
         uint64_t b = 0;
-        if (!heavy)
-            for (uint32_t j = j0; j < j1; ++j) {
-                const uint32_t e = inc[j];
-                const uint32_t sz = pin_off[e + 1] - pin_off[e];
-                if (sz >= 2) b += sz - 1;
+        if (!heavy)  // eight nets at a time: all incidence loads, then all offset loads
+            for (uint32_t j = j0; j < j1; j += 8) {
+                uint32_t e[8];
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) e[q] = j + q < j1 ? inc[j + q] : NONE;
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) {
+                    if (e[q] == NONE) continue;
+                    const uint32_t sz = pin_off[e[q] + 1] - pin_off[e[q]];
+                    if (sz >= 2) b += sz - 1;
+                }
             }
         uint64_t hm = __ballot(heavy);
         while (hm) {  // the wave sums each heavy vertex together

@@ -567,8 +567,14 @@ __global__ __launch_bounds__(BLOCK) void k_init_bcnt(const uint32_t *inc_off, co
         if (u < n) { j0 = inc_off[u]; j1 = inc_off[u + 1]; }
         const bool heavy = j1 - j0 > 32;
         uint32_t c = 0;
-        if (!heavy)
-            for (uint32_t j = j0; j < j1; ++j) c += popc_bits<KW>(nr[inc[j]].lam) > 1;
+        if (!heavy)  // eight nets at a time: all incidence loads, then all record loads
+            for (uint32_t j = j0; j < j1; j += 8) {
+                uint32_t e[8];
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) e[q] = j + q < j1 ? inc[j + q] : NONE;
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) c += e[q] != NONE && popc_bits<KW>(nr[e[q]].lam) > 1;
+            }
         uint64_t hm = __ballot(heavy);
         while (hm) {
             const int h = __ffsll((long long)hm) - 1;
