@@ -104,7 +104,8 @@ __device__ inline bool lp_skip(const LpCtl &c) { return *c.abort != 0 || (c.prev
 template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_conn_small(const uint32_t *pin_off, const uint32_t *pins, uint32_t m,
                                                       const int32_t *nwgt, const uint32_t *part, NetRec<KW> *nr,
-                                                      int64_t *f, uint32_t *longl, uint32_t *nlong) {
+                                                      int64_t *f, uint32_t *longl, uint32_t *nlong,
+                                                      uint64_t *cutbits) {
     __shared__ int64_t red[BLOCK / WAVE];
     int64_t acc = 0;
     for (uint32_t e0 = blockIdx.x * blockDim.x; e0 < m; e0 += gridDim.x * blockDim.x) {
@@ -114,18 +115,26 @@ __global__ __launch_bounds__(BLOCK) void k_conn_small(const uint32_t *pin_off, c
         bool lng = act && len > 64;
         uint32_t pos = warp_agg_append(nlong, lng);
         if (lng) longl[pos] = e;
-        if (!act || lng) continue;
-        uint64_t once[KW], twice[KW];
-        net_bits<KW>(pins, b, len, part, once, twice);
-        NetRec<KW> R;
+        bool cut = false;
+        if (act && !lng) {
+            uint64_t once[KW], twice[KW];
+            net_bits<KW>(pins, b, len, part, once, twice);
+            NetRec<KW> R;
 #pragma unroll
-        for (int q = 0; q < KW; ++q) {
-            R.lam[q] = once[q];
-            R.lam1[q] = once[q] & ~twice[q];
+            for (int q = 0; q < KW; ++q) {
+                R.lam[q] = once[q];
+                R.lam1[q] = once[q] & ~twice[q];
+            }
+            R.w = nwgt[e];
+            nr[e] = R;
+            const int lam = popc_bits<KW>(once);
+            acc += lam_cost(lam) * R.w;
+            cut = lam > 1;
         }
-        R.w = nwgt[e];
-        nr[e] = R;
-        acc += lam_cost(popc_bits<KW>(once)) * R.w;
+        // one bit per net: cut or not (long nets are added by k_conn_long)
+        const uint64_t word = __ballot(cut);
+        const uint32_t ebase = e0 + (threadIdx.x & ~(WAVE - 1));
+        if (__lane_id() == 0 && ebase < m) cutbits[ebase / WAVE] = word;
     }
     acc = wave_sum(acc);
     if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
@@ -142,7 +151,8 @@ template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_conn_long(const uint32_t *pin_off, const uint32_t *pins,
                                                      const uint32_t *list, const uint32_t *count_dev,
                                                      const int32_t *nwgt, const uint32_t *part, NetRec<KW> *nr,
-                                                     int64_t *f, bool delta, uint32_t *bcnt, LpCtl ctl) {
+                                                     int64_t *f, bool delta, uint32_t *bcnt, LpCtl ctl,
+                                                     uint32_t *cutbits = nullptr) {
     if (ctl.abort && lp_skip(ctl)) return;  // (no control words when building the records)
     const uint32_t count = *count_dev;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -186,6 +196,7 @@ __global__ __launch_bounds__(BLOCK) void k_conn_long(const uint32_t *pin_off, co
             R.w = nwgt[e];
             nr[e] = R;
             if (d) spread_add_i64(f, d * R.w);
+            if (cutbits && lnew > 1) atomicOr(&cutbits[e >> 5], 1u << (e & 31));
         }
         if (delta && bcnt && (lnew > 1) != (lold > 1)) {
             const uint32_t dl = lnew > 1 ? 1u : 0xFFFFFFFFu;
@@ -545,22 +556,26 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
 // high (coarse levels).
 template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_init_bcnt_wave(const uint32_t *inc_off, const uint32_t *inc, uint32_t n,
-                                                          const NetRec<KW> *nr, uint32_t *bcnt) {
+                                                          const uint32_t *cut, uint32_t *bcnt) {
     const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nw = gridDim.x * BLOCK / WAVE;
     for (uint32_t u = wid; u < n; u += nw) {
         const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
         uint32_t t = 0;
-        for (uint32_t j = j0 + __lane_id(); j < j1; j += WAVE) t += popc_bits<KW>(nr[inc[j]].lam) > 1;
+        for (uint32_t j = j0 + __lane_id(); j < j1; j += WAVE) {
+            const uint32_t e = inc[j];
+            t += (cut[e >> 5] >> (e & 31)) & 1u;
+        }
         t = wave_sum(t);
         if (__lane_id() == 0) bcnt[u] = t;
     }
 }
 
-// Boundary count of every node from scratch (once per level); a node of more
-// than 32 nets is counted by its whole wave.
+// Boundary count of every node from scratch (once per level), from the bit
+// per net that the connectivity kernels leave (the bitmap is small enough to
+// stay in L2); a node of more than 32 nets is counted by its whole wave.
 template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_init_bcnt(const uint32_t *inc_off, const uint32_t *inc, uint32_t n,
-                                                     const NetRec<KW> *nr, uint32_t *bcnt) {
+                                                     const uint32_t *cut, uint32_t *bcnt) {
     for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
         const uint32_t u = u0 + threadIdx.x;
         uint32_t j0 = 0, j1 = 0;
@@ -573,7 +588,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_bcnt(const uint32_t *inc_off, co
 #pragma unroll
                 for (uint32_t q = 0; q < 8; ++q) e[q] = j + q < j1 ? inc[j + q] : NONE;
 #pragma unroll
-                for (uint32_t q = 0; q < 8; ++q) c += e[q] != NONE && popc_bits<KW>(nr[e[q]].lam) > 1;
+                for (uint32_t q = 0; q < 8; ++q) c += e[q] != NONE ? (cut[e[q] >> 5] >> (e[q] & 31)) & 1u : 0u;
             }
         uint64_t hm = __ballot(heavy);
         while (hm) {
@@ -581,7 +596,10 @@ __global__ __launch_bounds__(BLOCK) void k_init_bcnt(const uint32_t *inc_off, co
             hm &= hm - 1;
             const uint32_t hj0 = __shfl(j0, h, 64), hj1 = __shfl(j1, h, 64);
             uint32_t t = 0;
-            for (uint32_t j = hj0 + __lane_id(); j < hj1; j += WAVE) t += popc_bits<KW>(nr[inc[j]].lam) > 1;
+            for (uint32_t j = hj0 + __lane_id(); j < hj1; j += WAVE) {
+                const uint32_t e = inc[j];
+                t += (cut[e >> 5] >> (e & 31)) & 1u;
+            }
             t = wave_sum(t);
             if ((int)__lane_id() == h) c = t;
         }
@@ -1259,6 +1277,7 @@ struct RefineBufs {
     uint32_t *spairs;           // the sub-round's over-budget pairs
     uint32_t *slowpair;         // [k*k] pairs handed to the device-wide path
     uint32_t *rmoves;           // [LP_MAX_ROUNDS] moves flag of every round
+    uint64_t *cut;              // [ceil(m / 64)] cut bit of every net, for the boundary counts
     int64_t *dbw_g;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt, *seg_start, *seg_end;
@@ -1299,6 +1318,7 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.slowpair = A.alloc<uint32_t>((size_t)k * k);
     B.spairs = A.alloc<uint32_t>((size_t)k * k);
     B.rmoves = A.alloc<uint32_t>(LP_MAX_ROUNDS);
+    B.cut = A.alloc<uint64_t>(((size_t)m + WAVE - 1) / WAVE);
     B.seg = A.alloc<uint32_t>((size_t)k * (k - 1) / 2 * pair_seg_cap(n));
     B.slow = A.alloc<uint32_t>(n);
     B.heavy = A.alloc<uint32_t>(n);
@@ -1324,11 +1344,11 @@ static void build_conn(const hgp_hg &h, const uint32_t *part, RefineBufs &B, hip
     }
     if (h.m) {
         k_conn_small<KW><<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
-            h.pin_off, h.pins, h.m, h.nwgt, part, (NetRec<KW> *)B.nr, B.f, B.longl, B.scal + 12);
+            h.pin_off, h.pins, h.m, h.nwgt, part, (NetRec<KW> *)B.nr, B.f, B.longl, B.scal + 12, B.cut);
         HGP_LAUNCH_CHECK();
         k_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, B.scal + 12, h.nwgt, part,
                                                            (NetRec<KW> *)B.nr, B.f, false, nullptr,
-                                                           LpCtl{nullptr, nullptr, 0});
+                                                           LpCtl{nullptr, nullptr, 0}, (uint32_t *)B.cut);
         HGP_LAUNCH_CHECK();
     }
 }
@@ -1400,10 +1420,10 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     HGP_LAUNCH_CHECK();
     if ((uint64_t)h.p >= (uint64_t)16 * n)  // average degree of at least 16: a wave per node
         k_init_bcnt_wave<KW><<<grid_for((size_t)n * WAVE, BLOCK, 4 * FILL_BLOCKS), BLOCK, 0, st>>>(
-            h.inc_off, h.inc, n, (const NetRec<KW> *)B.nr, B.bcnt);
+            h.inc_off, h.inc, n, (const uint32_t *)B.cut, B.bcnt);
     else
         k_init_bcnt<KW><<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n,
-                                                                           (const NetRec<KW> *)B.nr, B.bcnt);
+                                                                           (const uint32_t *)B.cut, B.bcnt);
     HGP_LAUNCH_CHECK();
     // degree classes of the nodes (lanes per node 1 / 8 / 64)
     k_deg_classify<<<grid_for(n, BLOCK, REDUCE_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt);
