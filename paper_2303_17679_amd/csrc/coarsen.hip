@@ -130,17 +130,20 @@ __device__ inline void publish(const RateArgs &a, uint32_t u, uint32_t C) {
 // whole group, one net at a time, with a per-slot "last net" stamp.
 constexpr uint32_t LANE_NET = 16;
 
-template <class Insert>
+// LN (at most LANE_NET) bounds the net size of the lane path; a level whose
+// nets have at most 8 pins uses LN = 8, so a lane carries half the registers
+// and comparisons.
+template <uint32_t LN = LANE_NET, class Insert>
 __device__ inline void rate_small_net(const RateArgs &a, uint32_t u, uint32_t b, uint32_t sz, uint64_t sc,
                                       Insert &&insert) {
-    uint32_t C[LANE_NET];
+    uint32_t C[LN];
 #pragma unroll
-    for (uint32_t q = 0; q < LANE_NET; ++q) C[q] = q < sz ? a.pins[b + q] : NONE;
+    for (uint32_t q = 0; q < LN; ++q) C[q] = q < sz ? a.pins[b + q] : NONE;
 #pragma unroll
-    for (uint32_t q = 0; q < LANE_NET; ++q)  // (first sub-round: every vertex is its own cluster)
+    for (uint32_t q = 0; q < LN; ++q)  // (first sub-round: every vertex is its own cluster)
         C[q] = (C[q] != NONE && C[q] != u) ? (a.dedup ? a.rep[C[q]] : C[q]) : NONE;
 #pragma unroll
-    for (uint32_t q = 0; q < LANE_NET; ++q) {
+    for (uint32_t q = 0; q < LN; ++q) {
         bool fresh = C[q] != NONE;
 #pragma unroll
         for (uint32_t r = 0; r < q; ++r) fresh = fresh && C[r] != C[q];
@@ -154,7 +157,7 @@ __device__ inline void rate_small_net(const RateArgs &a, uint32_t u, uint32_t b,
 // A large net adds its score once per cluster: a bit per slot marks the
 // clusters it has reached (cleared before each large net).
 // ---------------------------------------------------------------------------
-template <int G, int CAP, int LOG2CAP>
+template <int G, int CAP, int LOG2CAP, uint32_t LN>
 __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t *list, uint32_t count) {
     constexpr int GPB = BLOCK / G;
     constexpr int MW = CAP / 64;  // mask words per group
@@ -198,9 +201,9 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
         for (uint32_t j = j0 + l; j < j1; j += G) {
             uint32_t e = a.inc[j];
             uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
-            if (sz > LANE_NET) { big = true; continue; }
+            if (sz > LN) { big = true; continue; }
             if (sz < 2) continue;
-            rate_small_net(a, u, b, sz, a.nscore[e], [&](uint32_t C, uint64_t sc) {
+            rate_small_net<LN>(a, u, b, sz, a.nscore[e], [&](uint32_t C, uint64_t sc) {
                 uint32_t slot = insert(C, sc);
                 atomicAdd((unsigned long long *)&R[g][slot], (unsigned long long)sc);
             });
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
             for (uint32_t j = j0; j < j1; ++j) {
                 uint32_t e = a.inc[j];
                 uint32_t b = a.pin_off[e], sz = a.pin_off[e + 1] - b;
-                if (sz <= LANE_NET) continue;
+                if (sz <= LN) continue;
                 uint64_t sc = a.nscore[e];
                 if (a.dedup) {
                     for (int w = l; w < MW; w += G) seen[g][w] = 0ull;
@@ -1297,6 +1300,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     HGP_CHECK_HIP(hipMemcpyAsync(counts.data(), B.counts, sizeof(uint32_t) * (S * NCLASS + 3), hipMemcpyDeviceToHost,
                                  st));
     const bool huge_nets = counts[S * NCLASS + 1] > HUB_BIG;
+    const bool small_nets = counts[S * NCLASS + 1] <= 8;  // every net fits the 8-pin lane path
     stream_sync(st);
     // hub tables: the whole region, cleared once; every job leaves its slots clean
     const size_t E = B.greg_bytes / GENTRY_BYTES;
@@ -1492,13 +1496,26 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             TimedLaunch tl(kid, st);
             switch (c) {
                 case 0:
-                    k_rate_group<8, 64, 6><<<grid_for(cntc, BLOCK / 8, 8192), BLOCK, 0, st>>>(a, lst, cntc);
+                    if (small_nets)
+                        k_rate_group<8, 64, 6, 8><<<grid_for(cntc, BLOCK / 8, 8192), BLOCK, 0, st>>>(a, lst, cntc);
+                    else
+                        k_rate_group<8, 64, 6, LANE_NET><<<grid_for(cntc, BLOCK / 8, 8192), BLOCK, 0, st>>>(a, lst,
+                                                                                                      cntc);
                     break;
                 case 1:
-                    k_rate_group<16, 256, 8><<<grid_for(cntc, BLOCK / 16, 8192), BLOCK, 0, st>>>(a, lst, cntc);
+                    if (small_nets)
+                        k_rate_group<16, 256, 8, 8><<<grid_for(cntc, BLOCK / 16, 8192), BLOCK, 0, st>>>(a, lst, cntc);
+                    else
+                        k_rate_group<16, 256, 8, LANE_NET><<<grid_for(cntc, BLOCK / 16, 8192), BLOCK, 0, st>>>(
+                            a, lst, cntc);
                     break;
                 case 2:
-                    k_rate_group<64, 1024, 10><<<grid_for(cntc, BLOCK / 64, 8192), BLOCK, 0, st>>>(a, lst, cntc);
+                    if (small_nets)
+                        k_rate_group<64, 1024, 10, 8><<<grid_for(cntc, BLOCK / 64, 8192), BLOCK, 0, st>>>(a, lst,
+                                                                                                        cntc);
+                    else
+                        k_rate_group<64, 1024, 10, LANE_NET><<<grid_for(cntc, BLOCK / 64, 8192), BLOCK, 0, st>>>(
+                            a, lst, cntc);
                     break;
                 default:
                     k_rate_block<<<grid_for(cntc, 1, 8192), BLOCK, 0, st>>>(a, lst, cntc);
