@@ -132,9 +132,37 @@ __global__ __launch_bounds__(BLOCK) void k_check_transpose(const uint32_t *pin_o
             }
             return lo < end && inc[lo] == net;
         };
-        if (!heavy)
-            for (uint32_t j = j0; j < j1; ++j)
-                if (!found(e, pins[j])) { atomicOr(err, 4u); break; }
+        if (!heavy) {  // eight pins at a time, their binary searches in lock step
+            bool ok = true;
+            for (uint32_t j = j0; j < j1 && ok; j += 8) {
+                uint32_t v[8], lo[8], hi[8], end[8];
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) v[q] = j + q < j1 ? pins[j + q] : NONE;
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) {
+                    lo[q] = v[q] != NONE ? inc_off[v[q]] : 0u;
+                    hi[q] = v[q] != NONE ? inc_off[v[q] + 1] : 0u;
+                    end[q] = hi[q];
+                }
+                for (bool any = true; any;) {
+                    any = false;
+                    uint32_t x[8];
+#pragma unroll
+                    for (uint32_t q = 0; q < 8; ++q) x[q] = lo[q] < hi[q] ? inc[(lo[q] + hi[q]) >> 1] : 0u;
+#pragma unroll
+                    for (uint32_t q = 0; q < 8; ++q) {
+                        if (lo[q] >= hi[q]) continue;
+                        const uint32_t mid = (lo[q] + hi[q]) >> 1;
+                        if (x[q] < e) lo[q] = mid + 1; else hi[q] = mid;
+                        any = true;
+                    }
+                }
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q)
+                    if (v[q] != NONE) ok = ok && lo[q] < end[q] && inc[lo[q]] == e;
+            }
+            if (!ok) atomicOr(err, 4u);
+        }
         uint64_t hm = __ballot(heavy);
         while (hm) {
             const int h = __ffsll((long long)hm) - 1;

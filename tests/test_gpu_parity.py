@@ -204,6 +204,19 @@ def test_invalid_inputs_rejected(hgp):
     bad = H.Hypergraph.from_host(h)
     bad.pins[0], bad.pins[1] = 1, 0  # not ascending
     assert H.validate(bad) == -1
+    bad = H.Hypergraph.from_host(h)
+    bad.inc[0] = 1  # well-formed lists that are not the transpose of the pins
+    assert H.validate(bad) == -1
+    # the same for a net of 20 pins (checked eight pins at a time) and one of
+    # 40 pins (checked by a whole wave): vertex v lists net 2 instead
+    h2 = W.from_nets(60, [list(range(20)), list(range(10, 50)), [50, 51]])
+    assert H.validate(H.Hypergraph.from_host(h2)) == 0
+    for v, net in ((5, 0), (45, 1)):
+        bad = H.Hypergraph.from_host(h2)
+        j = int(h2.inc_off[v])
+        assert int(h2.inc[j]) == net and int(h2.inc_off[v + 1]) == j + 1
+        bad.inc[j] = 2
+        assert H.validate(bad) == -1
     with pytest.raises(H.HGPError):
         H.partition(G, H.params(300))
     with pytest.raises(H.HGPError):
