@@ -404,27 +404,29 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
     }
 }
 
-// Candidates and gains of LP sub-round (r, s) in one launch.  The
-// candidates are the boundary vertices (an incident net with lambda > 1 --
-// no other vertex can have a positive gain) whose sub-round hash selects s.
-// Each workgroup takes chunks of `ch` consecutive vertices (the chunks of
-// one XCD are contiguous), lists the chunk's candidates in LDS by degree
-// class and rates them: 1 lane per node up to 8 nets, 8 lanes up to 64, a
-// wave up to HUB_DEG; larger nodes go to the hub list for k_gains_hub.
-// Block 0 also clears the counters that only the later kernels of the
-// sub-round use.
+// Candidates of LP sub-round (r, s): the boundary vertices (an incident net
+// with lambda > 1 -- no other vertex can have a positive gain) whose
+// sub-round hash selects s.  Each workgroup takes chunks of `ch` consecutive
+// vertices (the chunks of one XCD are contiguous), gathers the chunk's
+// candidates in LDS by degree class (1 lane per node up to 8 nets, 8 lanes up
+// to 64, a wave up to HUB_DEG; larger nodes go to the hub list for
+// k_gains_hub) and appends them to the class list of the chunk's slot
+// c mod NSLOT (cl[class][slot], capacity slot_cap each, lengths in ccnt), one
+// atomic per class and chunk.  Block 0 also clears the counters that only
+// the later kernels of the sub-round use.
 constexpr uint32_t GAIN_CH = 1024;  // largest chunk
 template <int KW>
-__global__ __launch_bounds__(BLOCK, 6) void k_gains(GainArgs<KW> a, uint32_t ch, uint32_t nchunks, uint32_t *hubl,
-                                                 uint32_t *nhub, uint32_t *scal) {
+__global__ __launch_bounds__(BLOCK) void k_gain_scan(GainArgs<KW> a, uint32_t ch, uint32_t nchunks, uint32_t *cl,
+                                                     uint32_t *ccnt, uint32_t *hubl, uint32_t *nhub, uint32_t *scal) {
     __shared__ uint32_t lst[3][GAIN_CH];
-    __shared__ uint32_t lcnt[3];
+    __shared__ uint32_t lcnt[3], lbase[3];
     if (lp_skip(a.ctl)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         scal[2] = 0; scal[3] = 0;     // ntouched, nlong
         scal[13] = 0; scal[14] = 0;   // oversized-pair proposals, movers
         scal[24] = 0;                 // movers of more than HUB_DEG nets
     }
+    const size_t cstride = (size_t)NSLOT * a.slot_cap;  // one class's lists
     const XcdSlice xs = xcd_slice(blockIdx.x, gridDim.x, nchunks);
     for (uint32_t c = xs.lo + xs.wi; c < xs.hi; c += xs.nw) {
         const uint32_t lo = c * ch, hi = lo + ch < a.n ? lo + ch : a.n;
@@ -458,11 +460,32 @@ __global__ __launch_bounds__(BLOCK, 6) void k_gains(GainArgs<KW> a, uint32_t ch,
             else lst[cls][atomicAdd(&lcnt[cls], 1u)] = v;
         }
         __syncthreads();
-        gains_body<KW, 1>(a, lst[0], lcnt[0], 0, 1, c % NSLOT);
-        gains_body<KW, 8>(a, lst[1], lcnt[1], 0, 1, c % NSLOT);
-        gains_body<KW, 64>(a, lst[2], lcnt[2], 0, 1, c % NSLOT);
+        const uint32_t slot = c % NSLOT;
+        if (threadIdx.x < 3)
+            lbase[threadIdx.x] =
+                lcnt[threadIdx.x] ? atomicAdd(&ccnt[(threadIdx.x * NSLOT + slot) * SPREAD_U32], lcnt[threadIdx.x]) : 0u;
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            uint32_t *dst = cl + t * cstride + (size_t)slot * a.slot_cap + lbase[t];
+            for (uint32_t i = threadIdx.x; i < lcnt[t]; i += BLOCK) dst[i] = lst[t][i];
+        }
         __syncthreads();  // the lists are rewritten by the next chunk
     }
+}
+
+// Gains of the listed candidates: workgroup b rates part of slot b mod
+// NSLOT's class lists (the grid is a multiple of NSLOT), so every candidate
+// of the sub-round is in flight at once, not a chunk's worth per workgroup.
+template <int KW>
+__global__ __launch_bounds__(BLOCK, 6) void k_gains(GainArgs<KW> a, const uint32_t *cl, const uint32_t *ccnt) {
+    if (lp_skip(a.ctl)) return;
+    const uint32_t sl = blockIdx.x % NSLOT, bj = blockIdx.x / NSLOT, nbj = gridDim.x / NSLOT;
+    const size_t cstride = (size_t)NSLOT * a.slot_cap;
+    const size_t off = (size_t)sl * a.slot_cap;
+    gains_body<KW, 1>(a, cl + off, ccnt[(0 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
+    gains_body<KW, 8>(a, cl + cstride + off, ccnt[(1 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
+    gains_body<KW, 64>(a, cl + 2 * cstride + off, ccnt[(2 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
 }
 
 // Candidates of more than HUB_DEG nets: one 1024-thread workgroup each, the
@@ -620,12 +643,12 @@ __global__ __launch_bounds__(BLOCK) void k_account_gains(GainArgs<KW> a, uint32_
     if (lp_skip(a.ctl)) return;  // the sub-round does nothing
     unsigned long long bytes = 0;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
-        bytes += 4;  // boundary count
+        // the candidates of k_gains (k_gain_scan's boundary counts and the
+        // hub candidates are not its bytes)
         if (a.bcnt[v] == 0 || tag_hash(a.mseed, 3, a.level, a.round, v) % a.S != a.sub) continue;
         const uint32_t j0 = a.inc_off[v], j1 = a.inc_off[v + 1];
-        bytes += 8;
-        if (deg_class(j1 - j0) == 3) { bytes += 4; continue; }
-        bytes += 4 + 4 + 4ull * (j1 - j0);  // block, weight, incidence list
+        if (deg_class(j1 - j0) == 3) continue;
+        bytes += 4 + 8 + 4 + 4 + 4ull * (j1 - j0);  // list entry, offsets, block, weight, incidence list
         for (uint32_t j = j0; j < j1; ++j)
             if (atomicExch(&nmark[a.inc[j]], stamp) != stamp) bytes += 4 + 8ull * KW + 8;
     }
@@ -1196,7 +1219,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_heavy(const uint32_t *pin_o
 // The proposal-list lengths come in two sets used by alternate sub-rounds:
 // the update reads its own sub-round's set and clears the other one.
 struct NextSub {
-    uint32_t *scal, *pw, *pc, *pcur;
+    uint32_t *scal, *pw, *pc, *pcur, *ccnt;
     uint32_t kk, k;
     int64_t *bw, *dbw_g;
     uint32_t *pcnt_next;
@@ -1205,6 +1228,7 @@ __device__ inline void next_subround(const NextSub &z) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
     if (tid == 0) { z.scal[25] = 0; z.scal[26] = 0; }  // listed pairs, hub candidates
     if (tid < NSLOT) z.pcnt_next[tid * SPREAD_U32] = 0;
+    if (tid < 3 * NSLOT) z.ccnt[tid * SPREAD_U32] = 0;  // candidate lists (read by this sub-round's gains only)
     for (uint32_t i = tid; i < z.kk; i += nt) { z.pw[i] = 0; z.pc[i] = 0; z.pcur[i] = 0; }
     if (blockIdx.x == 0)
         for (uint32_t b = threadIdx.x; b < z.k; b += blockDim.x) {
@@ -1272,6 +1296,8 @@ struct RefineBufs {
     int64_t *bw;
     uint32_t *longl, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow;
     uint32_t *pcnt;  // [2][NSLOT * SPREAD_U32] proposal-list lengths, alternate sub-rounds
+    uint32_t *cl;    // [3][NSLOT] candidate lists by degree class and slot
+    uint32_t *ccnt;  // [3 * NSLOT * SPREAD_U32] their lengths
     uint32_t *dlists;  // hub candidates of the sub-round
     uint32_t *pc, *pcur, *seg;  // per-pair proposal counts, appends and segments of over-budget pairs
     uint32_t *spairs;           // the sub-round's over-budget pairs
@@ -1295,6 +1321,8 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.nr = A.alloc<char>((size_t)m * netrec_bytes(KW));
     B.f = A.alloc<int64_t>((size_t)SPREAD * SPREAD_I64);
     B.pcnt = A.alloc<uint32_t>((size_t)2 * NSLOT * SPREAD_U32);
+    B.cl = A.alloc<uint32_t>(3 * ((size_t)n + (size_t)(NSLOT + 1) * GAIN_CH));
+    B.ccnt = A.alloc<uint32_t>((size_t)3 * NSLOT * SPREAD_U32);
     B.bw = A.alloc<int64_t>(k);
     B.longl = A.alloc<uint32_t>(m);
     B.dlists = A.alloc<uint32_t>(n);
@@ -1412,6 +1440,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         z.add(B.rmoves, std::min<uint32_t>(prm.lp_rounds, LP_MAX_ROUNDS));
         z.add(B.f, 2 * SPREAD * SPREAD_I64);
         z.add(B.tstamp, m);
+        z.add(B.ccnt, 3 * NSLOT * SPREAD_U32);
         k_zero_words<<<grid_for(std::max<size_t>(m, (size_t)k * k), BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(z);
         HGP_LAUNCH_CHECK();
     }
@@ -1439,7 +1468,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     uint32_t gch = 64;
     while (gch < GAIN_CH && (size_t)gch * 2048 <= n) gch <<= 1;
     const uint32_t gchunks = (uint32_t)(((size_t)n + gch - 1) / gch);
-    const uint32_t gain_blocks = std::min<uint32_t>(gchunks, 4096u);
+    const uint32_t gain_blocks = std::min<uint32_t>(gchunks, 2048u);  // about one round of the scan
     // capacity of one proposal list: the vertices of its chunks
     const uint32_t slot_cap = (gchunks + NSLOT - 1) / NSLOT * gch;
     const uint32_t hub_blocks = dc[3] ? grid_for((dc[3] + S - 1) / S, 1, 256) : 0u;
@@ -1450,6 +1479,10 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     // (the kernels that read the proposal lists take a multiple of NSLOT)
     auto slot_grid = [](uint32_t g) { return (g + NSLOT - 1) / NSLOT * NSLOT; };
     const uint32_t fast_blocks = slot_grid(grid_for(per_sub, BLOCK, FILL_BLOCKS / 4));
+    // gains of the listed candidates: one round of resident workgroups (six
+    // per CU at 80 registers), so that every candidate's chain of dependent
+    // gathers is in flight at once instead of in successive rounds
+    const uint32_t list_blocks = slot_grid(6 * 256);
     // lanes per mover by the level's average degree (a lane per incident net)
     const uint64_t avg_deg = n ? ((uint64_t)h.p + n - 1) / n : 1;
     const uint32_t upd_g = avg_deg <= 8 ? 8u : (avg_deg <= 24 ? 16u : 64u);
@@ -1556,7 +1589,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         }
         {
             TimedLaunch tl(KID_LP_UPDATE, st);
-            const NextSub zn{B.scal, B.pw, B.pc, B.pcur, k * k, k, B.bw, B.dbw_g, pcnt_of(stamp + 1)};
+            const NextSub zn{B.scal, B.pw, B.pc, B.pcur, B.ccnt, k * k, k, B.bw, B.dbw_g, pcnt_of(stamp + 1)};
             auto launch = [&](auto kern, uint32_t blocks) {
                 kern<<<blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.plist, pcnt_of(stamp), slot_cap,
                                                B.prop_t, part, (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl,
@@ -1594,8 +1627,10 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             HGP_LAUNCH_CHECK();
         }
         if (n) {
+            k_gain_scan<KW><<<gain_blocks, BLOCK, 0, st>>>(ga, gch, gchunks, B.cl, B.ccnt, B.dlists, nhub, B.scal);
+            HGP_LAUNCH_CHECK();
             TimedLaunch tl(KID_GAINS, st);
-            k_gains<KW><<<gain_blocks, BLOCK, 0, st>>>(ga, gch, gchunks, B.dlists, nhub, B.scal);
+            k_gains<KW><<<list_blocks, BLOCK, 0, st>>>(ga, B.cl, B.ccnt);
             HGP_LAUNCH_CHECK();
         }
         if (hub_blocks) {
@@ -1622,10 +1657,14 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     // batch: a round after one without moves does nothing on the device, and
     // a sub-round handed to the device-wide path stops every later one until
     // the host has finished it; the rest is then queued again.
+    // After a hand-over the level queues one round at a time (levels that
+    // need the device-wide path tend to need it again: a batch would be
+    // queued, skipped and queued again).
     const uint32_t R = std::min<uint32_t>(prm.lp_rounds, LP_MAX_ROUNDS);
     uint32_t r0 = 0, s0 = 0;  // next sub-round to queue
+    uint32_t batch = LP_ROUND_BATCH;
     while (r0 < R) {
-        const uint32_t r1 = std::min<uint32_t>(R, r0 + LP_ROUND_BATCH);
+        const uint32_t r1 = std::min<uint32_t>(R, r0 + batch);
         for (uint32_t r = r0; r < r1; ++r)
             for (uint32_t s = (r == r0 ? s0 : 0); s < S; ++s) subround(r, s);
         uint32_t hv[2];
@@ -1642,6 +1681,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             r0 = (stamp - 1) / S;
             s0 = (stamp - 1) % S + 1;
             if (s0 == S) { ++r0; s0 = 0; }
+            batch = 1;
             continue;
         }
         if (hv[1] == 0) break;  // the batch ended with a round without moves
