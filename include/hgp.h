@@ -99,10 +99,12 @@ hgp_status hgp_default_params(uint32_t k, hgp_params *out);
 
 /* Host.  Workspace bytes needed by operation `op` on a level of n vertices,
  * m nets and p pins.  For HGP_OP_PARTITION the figure includes room for the
- * coarse hierarchy: six times the arrays of the input level (coarse levels
- * are stored compactly; the figure holds whenever they sum to at most six
- * input levels, as for every input tested); a deeper hierarchy makes
- * hgp_partition return HGP_E_WORKSPACE. */
+ * coarse hierarchy: eight times the arrays of the input level (each coarse
+ * level keeps the array capacities of its parent, so the hierarchy holds the
+ * input and every level but the coarsest; the figure holds whenever those
+ * levels below the input sum to at most seven input levels, as for every
+ * input tested); a deeper hierarchy makes hgp_partition return
+ * HGP_E_WORKSPACE. */
 hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p,
                                const hgp_params *prm, size_t *out);
 

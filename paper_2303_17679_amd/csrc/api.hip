@@ -86,10 +86,11 @@ hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p, const
             case HGP_OP_PARTITION: {
                 size_t temp = std::max({coarsen_workspace(n, m, p, dp), contract_workspace(n, m, p),
                                         refine_workspace(n, m, k), ip_workspace(n, p, k), util_workspace(n, m)});
-                // hierarchy: compact coarse levels and their maps, budgeted at
-                // six input levels; on top, the level being built with the
-                // capacities of its parent, rep, and the compaction staging
-                size_t hier = 6 * level_bytes(n, m, p) + 2 * level_bytes(n, m, p) + 4ull * n + 4096;
+                // hierarchy: every coarse level with the capacities of its
+                // parent, and the maps, budgeted at eight input levels (the
+                // input and levels whose sizes sum to at most seven times it
+                // fit); on top, rep
+                size_t hier = 8 * level_bytes(n, m, p) + 4ull * n + 4096;
                 need = temp + hier;
                 break;
             }
@@ -208,9 +209,7 @@ hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
         if (!((uint64_t)cur.n > limit)) break;
         size_t mk = A.mark();
         uint32_t *cid = A.alloc<uint32_t>(cur.n);
-        // the would-be coarse level, with the capacities of this level; once
-        // its sizes are known it is compacted to exactly those sizes at M
-        const size_t M = A.mark();
+        // the would-be coarse level, with the capacities of this level
         hgp_hg_out out;
         out.cap_n = cur.n; out.cap_m = cur.m; out.cap_p = cur.p;
         out.pin_off = A.alloc<uint32_t>((size_t)cur.m + 1);
@@ -231,25 +230,12 @@ hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
         uint32_t dims[3];
         contract(cur, rep, cid, out, dims, A, st);
         A.release(mk_rep);
+        // the coarse level keeps the arrays of its parent's capacities: only
+        // their used prefix is read, and no copy is spent on compacting them
         hgp_hg nh;
         nh.n = dims[0]; nh.m = dims[1]; nh.p = dims[2];
-        {
-            // stage the used part of every array above, then move it to M
-            const uint64_t len[6] = {(uint64_t)nh.m + 1, nh.p, (uint64_t)nh.n + 1, nh.p, nh.n, nh.m};
-            uint32_t *from[6] = {out.pin_off, out.pins, out.inc_off, out.inc, (uint32_t *)out.vwgt,
-                                 (uint32_t *)out.nwgt};
-            uint32_t *stage[6], *dst[6];
-            for (int a = 0; a < 6; ++a) stage[a] = A.alloc<uint32_t>(len[a]);
-            CopySet c1, c2;
-            for (int a = 0; a < 6; ++a) { c1.src[a] = from[a]; c1.dst[a] = stage[a]; c1.len[a] = len[a]; }
-            copy_arrays(c1, st);
-            A.release(M);  // the staging area lies above M + (compact size): no overlap
-            for (int a = 0; a < 6; ++a) dst[a] = A.alloc<uint32_t>(len[a]);
-            for (int a = 0; a < 6; ++a) { c2.src[a] = stage[a]; c2.dst[a] = dst[a]; c2.len[a] = len[a]; }
-            copy_arrays(c2, st);
-            nh.pin_off = dst[0]; nh.pins = dst[1]; nh.inc_off = dst[2]; nh.inc = dst[3];
-            nh.vwgt = (const int32_t *)dst[4]; nh.nwgt = (const int32_t *)dst[5];
-        }
+        nh.pin_off = out.pin_off; nh.pins = out.pins; nh.inc_off = out.inc_off; nh.inc = out.inc;
+        nh.vwgt = out.vwgt; nh.nwgt = out.nwgt;
         L.back().cid = cid;
         L.push_back({nh, nullptr});
         if (L.size() > 4096) break;

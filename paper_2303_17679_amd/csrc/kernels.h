@@ -10,14 +10,6 @@ int64_t total_weight(const int32_t *w, uint32_t n, Arena &A, hipStream_t st);
 int32_t max_vertex_weight(const int32_t *w, uint32_t n, Arena &A, hipStream_t st);
 size_t util_workspace(uint32_t n, uint32_t m);
 hgp_status validate(const hgp_hg &h, Arena &A, hipStream_t st);
-// Copies up to 6 arrays of 32-bit words (src[i] -> dst[i], len[i] words) in
-// one launch; source and destination ranges must not overlap.
-struct CopySet {
-    const uint32_t *src[6];
-    uint32_t *dst[6];
-    uint64_t len[6];
-};
-void copy_arrays(const CopySet &c, hipStream_t st);
 
 // coarsen.hip
 size_t coarsen_workspace(uint32_t n, uint32_t m, uint32_t p, const hgp_params &prm);

@@ -235,24 +235,4 @@ void stream_sync(hipStream_t st) {
     HGP_CHECK_HIP(hipEventSynchronize(w.ev));
 }
 
-__global__ __launch_bounds__(BLOCK) void k_copy_arrays(CopySet c) {
-    uint64_t total = 0;
-#pragma unroll
-    for (int a = 0; a < 6; ++a) total += c.len[a];
-    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < total; i += (uint64_t)gridDim.x * BLOCK) {
-        uint64_t x = i;
-        int a = 0;
-        while (x >= c.len[a]) x -= c.len[a++];
-        c.dst[a][x] = c.src[a][x];
-    }
-}
-
-void copy_arrays(const CopySet &c, hipStream_t st) {
-    uint64_t total = 0;
-    for (int a = 0; a < 6; ++a) total += c.len[a];
-    if (!total) return;
-    k_copy_arrays<<<grid_for(total, BLOCK * 4, FILL_BLOCKS), BLOCK, 0, st>>>(c);
-    HGP_LAUNCH_CHECK();
-}
-
 }  // namespace hgp
