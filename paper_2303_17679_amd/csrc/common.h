@@ -32,6 +32,12 @@ struct Error {
 inline thread_local bool blocking_waits = false;
 void stream_sync(hipStream_t st);
 
+// Pinned host words of the calling thread (MAILBOX_WORDS of them): a counter
+// copied there with hipMemcpyAsync is valid after the next stream_sync of
+// that stream, so a read-back can wait for a sync the caller needs anyway.
+constexpr int MAILBOX_WORDS = 16;
+uint32_t *host_mailbox();
+
 #define HGP_LAUNCH_CHECK() HGP_CHECK_HIP(hipGetLastError())
 
 #define HGP_REQUIRE(cond, code)                 \

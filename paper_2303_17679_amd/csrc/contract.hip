@@ -30,12 +30,14 @@ struct StoreRank {
     __device__ void operator()(size_t i, uint32_t excl, uint32_t) const { rank[i] = excl; }
 };
 
+// Coarse IDs and weights; the weights only below cap (the host rejects a
+// coarse level above the caller's capacity once the count is read back).
 __global__ void k_cid(const uint32_t *rep, const uint32_t *rank, uint32_t n, const int32_t *vwgt, uint32_t *cid,
-                      int32_t *cvwgt) {
+                      int32_t *cvwgt, uint32_t cap) {
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         uint32_t c = rank[rep[v]];
         cid[v] = c;
-        atomicAdd(&cvwgt[c], vwgt[v]);
+        if (c < cap) atomicAdd(&cvwgt[c], vwgt[v]);
     }
 }
 
@@ -108,10 +110,11 @@ struct GatherValid {
 // back over a few neighbours (runs are short), else by binary search.
 // wsum[r] receives the weights of the nets r represents besides itself.
 constexpr int HASH_SORT_BITS = 24;
-__global__ void k_identical(const uint32_t *keys, const uint32_t *vals, uint32_t nv, const uint32_t *off,
+__global__ void k_identical(const uint32_t *keys, const uint32_t *vals, const uint32_t *nv_dev, const uint32_t *off,
                             const uint32_t *tmp, const uint32_t *usize, const int32_t *nwgt, uint32_t *repnet,
                             int32_t *wsum) {
     constexpr int SH = 32 - HASH_SORT_BITS;
+    const uint32_t nv = *nv_dev;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
         const uint32_t key = keys[i], top = key >> SH;
         uint32_t lo = i;
@@ -157,13 +160,16 @@ struct StoreKept {
     uint32_t *newid, *newoff, *cpin_off;
     int32_t *cnwgt;
     const int32_t *nwgt, *wsum;
+    uint32_t cap_m;  // coarse arrays written below it only (the host checks mc <= cap_m)
     __device__ void operator()(size_t e, uint64_t excl, uint64_t v) const {
         if (v) {
             uint32_t id = (uint32_t)(excl >> 32);
             newid[e] = id;
             newoff[e] = (uint32_t)excl;
-            cpin_off[id] = (uint32_t)excl;
-            cnwgt[id] = nwgt[e] + wsum[e];
+            if (id < cap_m) {
+                cpin_off[id] = (uint32_t)excl;
+                cnwgt[id] = nwgt[e] + wsum[e];
+            }
         } else {
             newid[e] = NONE;
         }
@@ -269,25 +275,27 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
     uint64_t *d_tot = (uint64_t *)(B.scal + 2);
     uint32_t *d_nv = B.scal + 4;
 
-    // 1. coarse vertex IDs and weights
+    // 1. coarse vertex IDs and weights; the cluster count is read back at
+    // the segmented sort's sync
     scan_apply<uint32_t>(A, n, IsRep{rep}, StoreRank{B.rank}, d_nc, st);
-    uint32_t nc = 0;
-    HGP_CHECK_HIP(hipMemcpyAsync(&nc, d_nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    stream_sync(st);
-    HGP_REQUIRE(nc <= out.cap_n, HGP_E_INVALID);
-    HGP_CHECK_HIP(hipMemsetAsync(out.vwgt, 0, sizeof(int32_t) * (nc ? nc : 1), st));
-    k_cid<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(rep, B.rank, n, h.vwgt, cid, out.vwgt);
-    HGP_LAUNCH_CHECK();
+    uint32_t *mb = host_mailbox();
+    HGP_CHECK_HIP(hipMemcpyAsync(mb, d_nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    const uint32_t vcap = std::min(out.cap_n, n);  // nc <= n
+    if (vcap) HGP_CHECK_HIP(hipMemsetAsync(out.vwgt, 0, sizeof(int32_t) * vcap, st));
+    if (n) {
+        k_cid<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(rep, B.rank, n, h.vwgt, cid, out.vwgt, vcap);
+        HGP_LAUNCH_CHECK();
+    }
 
     // 2. remap pins, sort + de-duplicate every net
     if (p) {
         k_map_pins<<<grid_for(p, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pins, p, cid, B.tmp);
         HGP_LAUNCH_CHECK();
     }
-    segmented_sort(A, B.ss_net, h.pin_off, m, B.tmp, true, B.usize, st);
     uint32_t cnt_ml[2];
-    HGP_CHECK_HIP(hipMemcpyAsync(cnt_ml, B.ss_net.scal, sizeof(cnt_ml), hipMemcpyDeviceToHost, st));
-    stream_sync(st);
+    segmented_sort(A, B.ss_net, h.pin_off, m, B.tmp, true, B.usize, cnt_ml, st);  // syncs
+    const uint32_t nc = mb[0];
+    HGP_REQUIRE(nc <= out.cap_n, HGP_E_INVALID);
 
     // 3. hashes, drop single-pin nets, identical-net detection
     if (m) {
@@ -305,23 +313,23 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
                                                                          B.usize, B.hkey, B.valid);
         HGP_LAUNCH_CHECK();
     }
+    // the nv kept nets' (hash, net) pairs: their count stays on the device,
+    // the launches are sized for m
     scan_apply<uint32_t>(A, m, IsValid{B.valid}, GatherValid{B.valid, B.hkey, (uint32_t *)B.keys, B.vals}, d_nv, st);
-    uint32_t nv = 0;
-    HGP_CHECK_HIP(hipMemcpyAsync(&nv, d_nv, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    stream_sync(st);
     uint32_t *kk = (uint32_t *)B.keys;  // 32-bit hash keys in the 64-bit buffers
     uint32_t *vv = B.vals;
-    radix_sort_pairs<uint32_t>(A, &kk, &vv, (uint32_t *)B.keys_alt, B.vals_alt, nv, 32 - HASH_SORT_BITS, 32, st);
-    if (m) HGP_CHECK_HIP(hipMemsetAsync(B.wsum, 0, sizeof(int32_t) * m, st));
-    if (nv) {
-        k_identical<<<grid_for(nv, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, nv, h.pin_off, B.tmp, B.usize, h.nwgt,
-                                                                       B.repnet, B.wsum);
+    radix_sort_pairs<uint32_t>(A, &kk, &vv, (uint32_t *)B.keys_alt, B.vals_alt, m, 32 - HASH_SORT_BITS, 32, st,
+                               d_nv);
+    if (m) {
+        HGP_CHECK_HIP(hipMemsetAsync(B.wsum, 0, sizeof(int32_t) * m, st));
+        k_identical<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, d_nv, h.pin_off, B.tmp, B.usize,
+                                                                      h.nwgt, B.repnet, B.wsum);
         HGP_LAUNCH_CHECK();
     }
 
     // 4. number the kept nets, copy pins, count coarse degrees
     scan_apply<uint64_t>(A, m, KeptPack{B.valid, B.repnet, B.usize},
-                         StoreKept{B.newid, B.newoff, out.pin_off, out.nwgt, h.nwgt, B.wsum}, d_tot, st);
+                         StoreKept{B.newid, B.newoff, out.pin_off, out.nwgt, h.nwgt, B.wsum, out.cap_m}, d_tot, st);
     uint64_t tot = 0;
     HGP_CHECK_HIP(hipMemcpyAsync(&tot, d_tot, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     stream_sync(st);

@@ -275,9 +275,10 @@ __device__ inline uint64_t digit_match(bool valid, uint32_t d) {
 
 // Per-tile digit histogram; all RS_ITEMS keys of a thread are loaded first.
 template <class K>
-__global__ __launch_bounds__(BLOCK) void k_rs_hist(const K *keys, size_t n, int shift, uint32_t ntiles,
-                                                   uint32_t *counts) {
+__global__ __launch_bounds__(BLOCK) void k_rs_hist(const K *keys, size_t n, const uint32_t *n_dev, int shift,
+                                                   uint32_t ntiles, uint32_t *counts) {
     __shared__ uint32_t h[256];
+    if (n_dev && (size_t)*n_dev < n) n = *n_dev;
     h[threadIdx.x] = 0;
     const size_t base = (size_t)blockIdx.x * RS_TILE;
     uint32_t dg[RS_ITEMS];
@@ -304,8 +305,8 @@ __global__ __launch_bounds__(BLOCK) void k_rs_hist(const K *keys, size_t n, int 
 // leave as one contiguous run instead of single scattered words.
 template <class K>
 __global__ __launch_bounds__(BLOCK) void k_rs_scatter(const K *keys, const uint32_t *vals, K *keys_out,
-                                                      uint32_t *vals_out, size_t n, int shift,
-                                                      uint32_t ntiles, const uint32_t *offsets) {
+                                                      uint32_t *vals_out, size_t n, const uint32_t *n_dev,
+                                                      int shift, uint32_t ntiles, const uint32_t *offsets) {
     __shared__ K skey[RS_TILE];
     __shared__ uint32_t sval[RS_TILE];
     __shared__ uint32_t wcnt[BLOCK / WAVE][256];
@@ -314,6 +315,7 @@ __global__ __launch_bounds__(BLOCK) void k_rs_scatter(const K *keys, const uint3
     __shared__ uint32_t gout[256];  // where the tile's bucket of each digit starts in the output
     __shared__ uint32_t wsum[BLOCK / WAVE];
     const unsigned tid = threadIdx.x, w = tid / WAVE;
+    if (n_dev && (size_t)*n_dev < n) n = *n_dev;
     gout[tid] = offsets[(size_t)tid * ntiles + blockIdx.x];
     run[tid] = 0;
     const size_t tbase = (size_t)blockIdx.x * RS_TILE;
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(BLOCK) void k_rs_scatter(const K *keys, const uint3
         }
     }
     __syncthreads();
-    const uint32_t cnt = (uint32_t)(n - tbase < (size_t)RS_TILE ? n - tbase : (size_t)RS_TILE);
+    const uint32_t cnt = tbase >= n ? 0u : (uint32_t)(n - tbase < (size_t)RS_TILE ? n - tbase : (size_t)RS_TILE);
     for (uint32_t p = tid; p < cnt; p += BLOCK) {
         const K key = skey[p];
         const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
@@ -372,10 +374,11 @@ __global__ __launch_bounds__(BLOCK) void k_rs_scatter(const K *keys, const uint3
 
 // Sorts n pairs by bits [begin_bit, end_bit) of the key, stably.  The sorted
 // data ends in (*keys_io, *vals_io), which may be swapped with the alternate
-// buffers given.
+// buffers given.  With n_dev, the pairs sorted are the first min(n, *n_dev)
+// (a count the stream produces): n only sizes the launches.
 template <class K>
 void radix_sort_pairs(Arena &A, K **keys_io, uint32_t **vals_io, K *keys_alt, uint32_t *vals_alt,
-                      size_t n, int begin_bit, int end_bit, hipStream_t st) {
+                      size_t n, int begin_bit, int end_bit, hipStream_t st, const uint32_t *n_dev = nullptr) {
     uint32_t ntiles = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
     size_t mk = A.mark();
     uint32_t *counts = A.alloc<uint32_t>((size_t)256 * (ntiles ? ntiles : 1));
@@ -384,10 +387,10 @@ void radix_sort_pairs(Arena &A, K **keys_io, uint32_t **vals_io, K *keys_alt, ui
     K *kin = *keys_io, *kout = keys_alt;
     uint32_t *vin = *vals_io, *vout = vals_alt;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        k_rs_hist<K><<<ntiles, BLOCK, 0, st>>>(kin, n, shift, ntiles, counts);
+        k_rs_hist<K><<<ntiles, BLOCK, 0, st>>>(kin, n, n_dev, shift, ntiles, counts);
         HGP_LAUNCH_CHECK();
         exclusive_scan<uint32_t>(A, counts, counts, (size_t)256 * ntiles, nullptr, st);
-        k_rs_scatter<K><<<ntiles, BLOCK, 0, st>>>(kin, vin, kout, vout, n, shift, ntiles, counts);
+        k_rs_scatter<K><<<ntiles, BLOCK, 0, st>>>(kin, vin, kout, vout, n, n_dev, shift, ntiles, counts);
         HGP_LAUNCH_CHECK();
         K *tk = kin; kin = kout; kout = tk;
         uint32_t *tv = vin; vin = vout; vout = tv;

@@ -232,16 +232,24 @@ inline void segsort_plan(Arena &A, uint32_t nseg, size_t total, SegSortBufs &B) 
 }
 
 // Sorts (and with uniq, de-duplicates) every segment.  Syncs the stream.
+// tiers[0], tiers[1] (host) receive the numbers of segments of the block and
+// device-wide tiers (B.med and B.large list them).
 inline void segmented_sort(Arena &A, const SegSortBufs &B, const uint32_t *off, uint32_t nseg, uint32_t *data,
-                           bool uniq, uint32_t *usize, hipStream_t st) {
-    HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 6, st));  // callers read the counts
-    if (nseg == 0) return;
+                           bool uniq, uint32_t *usize, uint32_t *tiers, hipStream_t st) {
+    tiers[0] = tiers[1] = 0;
+    if (nseg == 0) {
+        stream_sync(st);
+        return;
+    }
+    HGP_CHECK_HIP(hipMemsetAsync(B.scal, 0, sizeof(uint32_t) * 6, st));
     k_seg_small<<<grid_for(nseg, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(off, nseg, data, uniq, usize, B.med, B.scal,
                                                                      B.large, B.scal + 1, B.scal + 4);
     HGP_LAUNCH_CHECK();
     uint32_t cnt[5];
     HGP_CHECK_HIP(hipMemcpyAsync(cnt, B.scal, sizeof(cnt), hipMemcpyDeviceToHost, st));
     stream_sync(st);
+    tiers[0] = cnt[0];
+    tiers[1] = cnt[1];
     if (cnt[4]) {  // some segment of the wave tier
         k_seg_wave<<<grid_for(nseg, BLOCK, 8192), BLOCK, 0, st>>>(off, nseg, data, uniq, usize);
         HGP_LAUNCH_CHECK();

@@ -224,6 +224,21 @@ struct WaitEvent {
 };
 }  // namespace
 
+namespace {
+struct PinnedWords {
+    uint32_t *p = nullptr;
+    ~PinnedWords() {
+        if (p) hipHostFree(p);
+    }
+};
+}  // namespace
+
+uint32_t *host_mailbox() {
+    thread_local PinnedWords w;
+    if (!w.p) HGP_CHECK_HIP(hipHostMalloc((void **)&w.p, sizeof(uint32_t) * MAILBOX_WORDS, hipHostMallocDefault));
+    return w.p;
+}
+
 void stream_sync(hipStream_t st) {
     if (!blocking_waits) {
         HGP_CHECK_HIP(hipStreamSynchronize(st));
