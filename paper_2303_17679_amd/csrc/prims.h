@@ -107,6 +107,45 @@ __global__ __launch_bounds__(BLOCK) void k_scan_small(size_t n, In in, Out out, 
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// Medium inputs (at most SCAN_FOLD_TILES tiles): no launch for the tile
+// offsets.  Every block of the scan adds up the tile sums before its own
+// (L2-resident words, a few per thread); block 0 adds up all of them for
+// the total.  Two launches instead of three.
+constexpr size_t SCAN_FOLD_TILES = 1024;
+template <class T>
+__device__ inline T tile_offset(const T *tile_sum, size_t ntiles, T *total, T *lds) {
+    const size_t lim = blockIdx.x == 0 ? ntiles : (size_t)blockIdx.x;
+    T s = 0;
+    for (size_t t = threadIdx.x; t < lim; t += BLOCK) s += tile_sum[t];
+    T tot;
+    block_incl_scan<T>(s, lds, &tot);
+    if (blockIdx.x != 0) return tot;
+    if (threadIdx.x == 0 && total) *total = tot;
+    return 0;
+}
+
+template <class T, class In, class Out>
+__global__ __launch_bounds__(BLOCK) void k_tile_scan_fold(size_t n, In in, Out out, const T *tile_sum,
+                                                          size_t ntiles, T *total) {
+    __shared__ T lds[BLOCK / WAVE];
+    const T off = tile_offset<T>(tile_sum, ntiles, total, lds);
+    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    T v[SCAN_ITEMS];
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = (base + i < n) ? in(base + i) : T(0);
+        s += v[i];
+    }
+    T incl = block_incl_scan<T>(s, lds, nullptr);
+    T run = off + incl - s;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < n) out(base + i, run, v[i]);
+        run += v[i];
+    }
+}
+
 // out(i, exclusive_prefix, value) is called for every i < n; *total_dev gets
 // the sum (may be nullptr).  Temporaries come from the arena and are released.
 template <class T, class In, class Out>
@@ -128,6 +167,12 @@ void scan_apply(Arena &A, size_t n, In in, Out out, T *total_dev, hipStream_t st
     }
     k_tile_reduce<T, In><<<(unsigned)ntiles, BLOCK, 0, st>>>(n, in, tiles);
     HGP_LAUNCH_CHECK();
+    if (ntiles <= SCAN_FOLD_TILES) {
+        k_tile_scan_fold<T, In, Out><<<(unsigned)ntiles, BLOCK, 0, st>>>(n, in, out, tiles, ntiles, total_dev);
+        HGP_LAUNCH_CHECK();
+        A.release(mk);
+        return;
+    }
     k_scan_tiles<T><<<1, BLOCK, 0, st>>>(ntiles, tiles, total_dev);
     HGP_LAUNCH_CHECK();
     k_tile_scan<T, In, Out><<<(unsigned)ntiles, BLOCK, 0, st>>>(n, in, out, tiles);
@@ -180,6 +225,30 @@ __global__ __launch_bounds__(BLOCK) void k_tile_scan_dn(const uint32_t *n_dev, I
 }
 
 template <class T, class In, class Out>
+__global__ __launch_bounds__(BLOCK) void k_tile_scan_fold_dn(const uint32_t *n_dev, In in, Out out,
+                                                             const T *tile_sum, size_t ntiles, T *total) {
+    __shared__ T lds[BLOCK / WAVE];
+    const T off = tile_offset<T>(tile_sum, ntiles, total, lds);  // block 0 writes the total
+    const size_t n = *n_dev;
+    if ((size_t)blockIdx.x * SCAN_TILE >= n) return;  // uniform per block
+    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    T v[SCAN_ITEMS];
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = (base + i < n) ? in(base + i) : T(0);
+        s += v[i];
+    }
+    T incl = block_incl_scan<T>(s, lds, nullptr);
+    T run = off + incl - s;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < n) out(base + i, run, v[i]);
+        run += v[i];
+    }
+}
+
+template <class T, class In, class Out>
 __global__ __launch_bounds__(BLOCK) void k_scan_small_dn(const uint32_t *n_dev, In in, Out out, T *total) {
     __shared__ T lds[BLOCK / WAVE];
     const size_t n = *n_dev;
@@ -220,6 +289,13 @@ void scan_apply_dn(Arena &A, size_t nmax, const uint32_t *n_dev, In in, Out out,
     }
     k_tile_reduce_dn<T, In><<<(unsigned)ntiles, BLOCK, 0, st>>>(n_dev, in, tiles);
     HGP_LAUNCH_CHECK();
+    if (ntiles <= SCAN_FOLD_TILES) {
+        k_tile_scan_fold_dn<T, In, Out><<<(unsigned)ntiles, BLOCK, 0, st>>>(n_dev, in, out, tiles, ntiles,
+                                                                           total_dev);
+        HGP_LAUNCH_CHECK();
+        A.release(mk);
+        return;
+    }
     k_scan_tiles<T><<<1, BLOCK, 0, st>>>(ntiles, tiles, total_dev);
     HGP_LAUNCH_CHECK();
     k_tile_scan_dn<T, In, Out><<<(unsigned)ntiles, BLOCK, 0, st>>>(n_dev, in, out, tiles);
