@@ -8,27 +8,98 @@
 namespace hgp {
 
 // ---------------------------------------------------------------------------
-// Exclusive scan: tile = BLOCK threads x SCAN_ITEMS consecutive values each.
+// Exclusive scan.  A tile is BLOCK x SCAN_ITEMS values: wave w holds the run
+// [w * WAVE * SCAN_ITEMS, (w + 1) * WAVE * SCAN_ITEMS) of the tile as
+// SCAN_ITEMS rows of WAVE consecutive values, so every load and store of a
+// wave covers 64 consecutive elements.  Element types are integers: the
+// order of the additions does not change a result.
 // ---------------------------------------------------------------------------
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
 
+// Index of the value that the calling lane holds in row r of the tile at base.
+__device__ inline size_t scan_elem(size_t base, int r) {
+    return base + (size_t)(threadIdx.x / WAVE) * (WAVE * SCAN_ITEMS) + (size_t)r * WAVE + __lane_id();
+}
+
+// Sum of in(i) over the tile's elements below n (every thread gets it).
+// Functors -------------------------------------------------------------------
+template <class T>
+struct LoadArr {
+    const T *a;
+    __device__ T operator()(size_t i) const { return a[i]; }
+};
+template <class T>
+struct StoreExcl {
+    T *out;
+    __device__ void operator()(size_t i, T excl, T) const { out[i] = excl; }
+};
+
 template <class T, class In>
-__global__ __launch_bounds__(BLOCK) void k_tile_reduce(size_t n, In in, T *tile_sum) {
-    __shared__ T lds[BLOCK / WAVE];
-    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+__device__ inline T reduce_tile(size_t base, size_t n, In in, T *lds) {
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i)
-        if (base + i < n) s += in(base + i);
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        const size_t i = scan_elem(base, r);
+        if (i < n) s += in(i);
+    }
     s = wave_sum(s);
     if (__lane_id() == 0) lds[threadIdx.x / WAVE] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        T t = 0;
-        for (int i = 0; i < BLOCK / WAVE; ++i) t += lds[i];
-        tile_sum[blockIdx.x] = t;
+    T t = 0;
+#pragma unroll
+    for (int q = 0; q < BLOCK / WAVE; ++q) t += lds[q];
+    __syncthreads();  // lds is reused by the caller
+    return t;
+}
+
+// Calls out(i, off + exclusive prefix within the tile, in(i)) for the tile's
+// elements below n; returns the tile's sum (every thread gets it).
+template <class T, class In, class Out>
+__device__ inline T scan_tile(size_t base, size_t n, In in, Out out, T off, T *lds) {
+    const unsigned lane = __lane_id(), w = threadIdx.x / WAVE;
+    T v[SCAN_ITEMS], ex[SCAN_ITEMS];
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        const size_t i = scan_elem(base, r);
+        v[r] = i < n ? in(i) : T(0);
     }
+    T carry = 0;  // the wave's sum of the rows before
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        T x = v[r];
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const T t = __shfl_up(x, o, WAVE);
+            if (lane >= (unsigned)o) x += t;
+        }
+        ex[r] = carry + x - v[r];
+        carry += __shfl(x, WAVE - 1, WAVE);
+    }
+    if (lane == 0) lds[w] = carry;
+    __syncthreads();
+    T before = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < BLOCK / WAVE; ++q) {
+        const T c = lds[q];
+        if (q < (int)w) before += c;
+        tot += c;
+    }
+    __syncthreads();  // lds is reused by the caller
+    off += before;
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        const size_t i = scan_elem(base, r);
+        if (i < n) out(i, off + ex[r], v[r]);
+    }
+    return tot;
+}
+
+template <class T, class In>
+__global__ __launch_bounds__(BLOCK) void k_tile_reduce(size_t n, In in, T *tile_sum) {
+    __shared__ T lds[BLOCK / WAVE];
+    const T t = reduce_tile<T, In>((size_t)blockIdx.x * SCAN_TILE, n, in, lds);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = t;
 }
 
 // Single block: exclusive scan of tile sums in place; *total <- sum.
@@ -36,46 +107,15 @@ template <class T>
 __global__ __launch_bounds__(BLOCK) void k_scan_tiles(size_t ntiles, T *tile_sum, T *total) {
     __shared__ T lds[BLOCK / WAVE];
     T carry = 0;
-    for (size_t base = 0; base < ntiles; base += (size_t)BLOCK * SCAN_ITEMS) {
-        T v[SCAN_ITEMS];
-        T s = 0;
-        size_t my = base + (size_t)threadIdx.x * SCAN_ITEMS;
-#pragma unroll
-        for (int i = 0; i < SCAN_ITEMS; ++i) {
-            v[i] = (my + i < ntiles) ? tile_sum[my + i] : T(0);
-            s += v[i];
-        }
-        T tot;
-        T incl = block_incl_scan<T>(s, lds, &tot);
-        T run = carry + incl - s;
-#pragma unroll
-        for (int i = 0; i < SCAN_ITEMS; ++i) {
-            if (my + i < ntiles) tile_sum[my + i] = run;
-            run += v[i];
-        }
-        carry += tot;
-    }
+    for (size_t base = 0; base < ntiles; base += SCAN_TILE)
+        carry += scan_tile<T>(base, ntiles, LoadArr<T>{tile_sum}, StoreExcl<T>{tile_sum}, carry, lds);
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
 template <class T, class In, class Out>
 __global__ __launch_bounds__(BLOCK) void k_tile_scan(size_t n, In in, Out out, const T *tile_off) {
     __shared__ T lds[BLOCK / WAVE];
-    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
-    T v[SCAN_ITEMS];
-    T s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        v[i] = (base + i < n) ? in(base + i) : T(0);
-        s += v[i];
-    }
-    T incl = block_incl_scan<T>(s, lds, nullptr);
-    T run = tile_off[blockIdx.x] + incl - s;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        if (base + i < n) out(base + i, run, v[i]);
-        run += v[i];
-    }
+    scan_tile<T, In, Out>((size_t)blockIdx.x * SCAN_TILE, n, in, out, tile_off[blockIdx.x], lds);
 }
 
 // Short inputs (at most SCAN_SMALL_TILES tiles): one block walks the tiles in
@@ -85,25 +125,7 @@ template <class T, class In, class Out>
 __global__ __launch_bounds__(BLOCK) void k_scan_small(size_t n, In in, Out out, T *total) {
     __shared__ T lds[BLOCK / WAVE];
     T carry = 0;
-    for (size_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
-        const size_t base = t0 + (size_t)threadIdx.x * SCAN_ITEMS;
-        T v[SCAN_ITEMS];
-        T s = 0;
-#pragma unroll
-        for (int i = 0; i < SCAN_ITEMS; ++i) {
-            v[i] = (base + i < n) ? in(base + i) : T(0);
-            s += v[i];
-        }
-        T tot;
-        const T incl = block_incl_scan<T>(s, lds, &tot);
-        T run = carry + incl - s;
-#pragma unroll
-        for (int i = 0; i < SCAN_ITEMS; ++i) {
-            if (base + i < n) out(base + i, run, v[i]);
-            run += v[i];
-        }
-        carry += tot;
-    }
+    for (size_t t0 = 0; t0 < n; t0 += SCAN_TILE) carry += scan_tile<T, In, Out>(t0, n, in, out, carry, lds);
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
@@ -129,21 +151,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_scan_fold(size_t n, In in, Out o
                                                           size_t ntiles, T *total) {
     __shared__ T lds[BLOCK / WAVE];
     const T off = tile_offset<T>(tile_sum, ntiles, total, lds);
-    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
-    T v[SCAN_ITEMS];
-    T s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        v[i] = (base + i < n) ? in(base + i) : T(0);
-        s += v[i];
-    }
-    T incl = block_incl_scan<T>(s, lds, nullptr);
-    T run = off + incl - s;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        if (base + i < n) out(base + i, run, v[i]);
-        run += v[i];
-    }
+    scan_tile<T, In, Out>((size_t)blockIdx.x * SCAN_TILE, n, in, out, off, lds);
 }
 
 // out(i, exclusive_prefix, value) is called for every i < n; *total_dev gets
@@ -186,20 +194,8 @@ void scan_apply(Arena &A, size_t n, In in, Out out, T *total_dev, hipStream_t st
 template <class T, class In>
 __global__ __launch_bounds__(BLOCK) void k_tile_reduce_dn(const uint32_t *n_dev, In in, T *tile_sum) {
     __shared__ T lds[BLOCK / WAVE];
-    const size_t n = *n_dev;
-    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
-    T s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i)
-        if (base + i < n) s += in(base + i);
-    s = wave_sum(s);
-    if (__lane_id() == 0) lds[threadIdx.x / WAVE] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        T t = 0;
-        for (int i = 0; i < BLOCK / WAVE; ++i) t += lds[i];
-        tile_sum[blockIdx.x] = t;  // zero past the count
-    }
+    const T t = reduce_tile<T, In>((size_t)blockIdx.x * SCAN_TILE, *n_dev, in, lds);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = t;  // zero past the count
 }
 
 template <class T, class In, class Out>
@@ -207,21 +203,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_scan_dn(const uint32_t *n_dev, I
     __shared__ T lds[BLOCK / WAVE];
     const size_t n = *n_dev;
     if ((size_t)blockIdx.x * SCAN_TILE >= n) return;  // uniform per block
-    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
-    T v[SCAN_ITEMS];
-    T s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        v[i] = (base + i < n) ? in(base + i) : T(0);
-        s += v[i];
-    }
-    T incl = block_incl_scan<T>(s, lds, nullptr);
-    T run = tile_off[blockIdx.x] + incl - s;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        if (base + i < n) out(base + i, run, v[i]);
-        run += v[i];
-    }
+    scan_tile<T, In, Out>((size_t)blockIdx.x * SCAN_TILE, n, in, out, tile_off[blockIdx.x], lds);
 }
 
 template <class T, class In, class Out>
@@ -231,21 +213,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_scan_fold_dn(const uint32_t *n_d
     const T off = tile_offset<T>(tile_sum, ntiles, total, lds);  // block 0 writes the total
     const size_t n = *n_dev;
     if ((size_t)blockIdx.x * SCAN_TILE >= n) return;  // uniform per block
-    size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
-    T v[SCAN_ITEMS];
-    T s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        v[i] = (base + i < n) ? in(base + i) : T(0);
-        s += v[i];
-    }
-    T incl = block_incl_scan<T>(s, lds, nullptr);
-    T run = off + incl - s;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        if (base + i < n) out(base + i, run, v[i]);
-        run += v[i];
-    }
+    scan_tile<T, In, Out>((size_t)blockIdx.x * SCAN_TILE, n, in, out, off, lds);
 }
 
 template <class T, class In, class Out>
@@ -253,25 +221,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_small_dn(const uint32_t *n_dev, 
     __shared__ T lds[BLOCK / WAVE];
     const size_t n = *n_dev;
     T carry = 0;
-    for (size_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
-        const size_t base = t0 + (size_t)threadIdx.x * SCAN_ITEMS;
-        T v[SCAN_ITEMS];
-        T s = 0;
-#pragma unroll
-        for (int i = 0; i < SCAN_ITEMS; ++i) {
-            v[i] = (base + i < n) ? in(base + i) : T(0);
-            s += v[i];
-        }
-        T tot;
-        const T incl = block_incl_scan<T>(s, lds, &tot);
-        T run = carry + incl - s;
-#pragma unroll
-        for (int i = 0; i < SCAN_ITEMS; ++i) {
-            if (base + i < n) out(base + i, run, v[i]);
-            run += v[i];
-        }
-        carry += tot;
-    }
+    for (size_t t0 = 0; t0 < n; t0 += SCAN_TILE) carry += scan_tile<T, In, Out>(t0, n, in, out, carry, lds);
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
@@ -312,17 +262,6 @@ inline void scan_reserve(Arena &A, size_t n) {
     A.release(mk);
 }
 
-// Functors -------------------------------------------------------------------
-template <class T>
-struct LoadArr {
-    const T *a;
-    __device__ T operator()(size_t i) const { return a[i]; }
-};
-template <class T>
-struct StoreExcl {
-    T *out;
-    __device__ void operator()(size_t i, T excl, T) const { out[i] = excl; }
-};
 
 // Exclusive scan of an array into another (may alias): out[i] = sum a[0:i].
 template <class T>
