@@ -109,6 +109,8 @@ struct GatherValid {
 // among identical nets.  The run of equal sorted bits is found by stepping
 // back over a few neighbours (runs are short), else by binary search.
 // wsum[r] receives the weights of the nets r represents besides itself.
+// repnet (NONE on entry) is written only for the nets that are merged into
+// another one, so a net with no copy costs no scattered store.
 constexpr int HASH_SORT_BITS = 24;
 __global__ void k_identical(const uint32_t *keys, const uint32_t *vals, const uint32_t *nv_dev, const uint32_t *off,
                             const uint32_t *tmp, const uint32_t *usize, const int32_t *nwgt, uint32_t *repnet,
@@ -142,9 +144,11 @@ __global__ void k_identical(const uint32_t *keys, const uint32_t *vals, const ui
                 for (uint32_t q = 0; q < sz && same; ++q) same = pe[q] == pf[q];
                 if (same) { r = f; break; }
             }
-            if (r != e) atomicAdd(&wsum[r], nwgt[e]);
+            if (r != e) {
+                atomicAdd(&wsum[r], nwgt[e]);
+                repnet[e] = r;
+            }
         }
-        repnet[e] = r;
     }
 }
 
@@ -153,7 +157,7 @@ struct KeptPack {
     const uint8_t *valid;
     const uint32_t *repnet, *usize;
     __device__ uint64_t operator()(size_t e) const {
-        return (valid[e] && repnet[e] == (uint32_t)e) ? ((1ull << 32) | usize[e]) : 0ull;
+        return (valid[e] && repnet[e] == NONE) ? ((1ull << 32) | usize[e]) : 0ull;
     }
 };
 struct StoreKept {
@@ -179,20 +183,52 @@ struct StoreKept {
 // Pins of the kept nets into the coarse pin array, and (pin, net) pairs in
 // net order for the transpose: sorting them stably by pin gives every coarse
 // vertex its incident nets in increasing order.
+// A wave takes WAVE consecutive nets (a net per lane) and copies their kept
+// pins together, WAVE pins per step: a wave prefix of the sizes numbers the
+// pins, and each lane finds the net of its pin by a binary search over the
+// lanes' prefixes.  Consecutive nets have consecutive pin ranges on both
+// sides, so the loads and stores of a step are nearly contiguous.
 __global__ void k_copy_pins_small(const uint32_t *off, uint32_t m, const uint32_t *tmp, const uint32_t *usize,
                                   const uint32_t *newid, const uint32_t *newoff, uint32_t *cpins, uint32_t *tkey,
                                   uint32_t *tnet) {
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
-        const uint32_t id = newid[e];
-        if (id == NONE) continue;
-        uint32_t b = off[e], len = off[e + 1] - b;
-        if (len > SEG_WAVE) continue;  // done by the block kernel
-        uint32_t sz = usize[e], o = newoff[e];
-        for (uint32_t i = 0; i < sz; ++i) {
-            uint32_t v = tmp[b + i];
-            cpins[o + i] = v;
-            tkey[o + i] = v;
-            tnet[o + i] = id;
+    const uint32_t lane = __lane_id();
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, nw = gridDim.x * blockDim.x / WAVE;
+    for (uint32_t run = wid * WAVE; run < m; run += nw * WAVE) {  // uniform per wave
+        const uint32_t e = run + lane;
+        uint32_t id = NONE, b = 0, sz = 0, o = 0;
+        if (e < m) {
+            id = newid[e];
+            if (id != NONE) {
+                b = off[e];
+                if (off[e + 1] - b <= SEG_WAVE) {  // longer nets: the block kernel
+                    sz = usize[e];
+                    o = newoff[e];
+                }
+            }
+        }
+        uint32_t x = sz;  // inclusive prefix over the lanes
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const uint32_t t = __shfl_up(x, d, WAVE);
+            if (lane >= (uint32_t)d) x += t;
+        }
+        const uint32_t total = __shfl(x, WAVE - 1, WAVE), excl = x - sz;
+        for (uint32_t q0 = 0; q0 < total; q0 += WAVE) {
+            const uint32_t q = q0 + lane;
+            uint32_t j = 0;  // the last lane whose prefix is <= q: its net holds pin q
+#pragma unroll
+            for (int step = WAVE / 2; step >= 1; step >>= 1) {
+                const uint32_t c = j + (uint32_t)step;
+                if (__shfl(excl, (int)c, WAVE) <= q) j = c;
+            }
+            const uint32_t bj = __shfl(b, (int)j, WAVE), oj = __shfl(o, (int)j, WAVE);
+            const uint32_t idj = __shfl(id, (int)j, WAVE), ej = __shfl(excl, (int)j, WAVE);
+            if (q < total) {
+                const uint32_t i = q - ej, v = tmp[bj + i];
+                cpins[oj + i] = v;
+                tkey[oj + i] = v;
+                tnet[oj + i] = idj;
+            }
         }
     }
 }
@@ -322,6 +358,7 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
                                d_nv);
     if (m) {
         HGP_CHECK_HIP(hipMemsetAsync(B.wsum, 0, sizeof(int32_t) * m, st));
+        HGP_CHECK_HIP(hipMemsetAsync(B.repnet, 0xFF, sizeof(uint32_t) * m, st));
         k_identical<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, d_nv, h.pin_off, B.tmp, B.usize,
                                                                       h.nwgt, B.repnet, B.wsum);
         HGP_LAUNCH_CHECK();
