@@ -173,12 +173,36 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
     if (l == 0) nocc[g] = 0;
     wave_sync();
     // groups never synchronise with each other (each lives inside one wave),
-    // so every group simply strides over the list
-    for (uint32_t idx = blockIdx.x * GPB + g; idx < count; idx += gridDim.x * GPB) {
-        const uint32_t u = list[idx];
-        const bool active = a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u];  // not joined earlier
+    // so every group simply strides over the list.  The candidates' records
+    // are fetched ahead (this kernel writes none of them): the ID two
+    // candidates ahead, and the cluster state and incidence range of the
+    // next, so those loads overlap the current candidate's gathers.
+    const uint32_t stride = gridDim.x * GPB;
+    uint32_t idx = blockIdx.x * GPB + g;
+    uint32_t pu = NONE, pj0 = 0, pj1 = 0;  // the next candidate's record
+    int64_t pcw = 0;
+    int32_t pvw = 0;
+    uint32_t prep = NONE;
+    auto fetch = [&](uint32_t v) {
+        pu = v;
+        if (v != NONE) {
+            prep = a.rep[v];
+            pcw = a.cw[v];
+            pvw = a.vwgt[v];
+            pj0 = a.inc_off[v];
+            pj1 = a.inc_off[v + 1];
+        }
+    };
+    fetch(idx < count ? list[idx] : NONE);
+    uint32_t nid = idx + stride < count ? list[idx + stride] : NONE;  // the ID after that
+    for (; idx < count; idx += stride) {
+        const uint32_t u = pu, j0 = pj0, j1 = pj1;
+        const int64_t cu = pvw;
+        const bool active = prep == u && pcw == cu;  // not joined earlier
+        const uint32_t after = nid;
+        nid = idx + 2 * stride < count ? list[idx + 2 * stride] : NONE;
+        fetch(after);
         if (!active) continue;  // uniform within the group
-        const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
         auto insert = [&](uint32_t C, uint64_t sc) -> uint32_t {
             uint32_t slot = slot_hash(C, LOG2CAP);
             for (;;) {
@@ -238,7 +262,6 @@ __global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t
         }
         wave_sync();
         const uint32_t no = nocc[g];
-        const int64_t cu = a.vwgt[u];
         uint64_t bR = 0;
         uint32_t bC = NONE;
         // four slots per lane at a time so that their tinfo loads overlap
