@@ -225,13 +225,16 @@ __global__ __launch_bounds__(BLOCK) void k_scan_small_dn(const uint32_t *n_dev, 
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// With the count on the device the single-block walk covers only the tiles
+// the count reaches, so it is taken up to twice as many tiles of the bound.
+constexpr size_t SCAN_SMALL_TILES_DN = 2 * SCAN_SMALL_TILES;
 template <class T, class In, class Out>
 void scan_apply_dn(Arena &A, size_t nmax, const uint32_t *n_dev, In in, Out out, T *total_dev, hipStream_t st) {
     const size_t ntiles = (nmax + SCAN_TILE - 1) / SCAN_TILE;
     size_t mk = A.mark();
     T *tiles = A.alloc<T>(ntiles ? ntiles : 1);
     if (A.measure) { A.release(mk); return; }
-    if (ntiles <= SCAN_SMALL_TILES) {
+    if (ntiles <= SCAN_SMALL_TILES_DN) {
         k_scan_small_dn<T, In, Out><<<1, BLOCK, 0, st>>>(n_dev, in, out, total_dev);
         HGP_LAUNCH_CHECK();
         A.release(mk);
