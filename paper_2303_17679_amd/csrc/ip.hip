@@ -25,18 +25,27 @@ namespace hgp {
 __global__ __launch_bounds__(BLOCK) void k_exoff(const uint32_t *pin_off, const uint32_t *inc_off,
                                                  const uint32_t *inc, uint32_t n, uint32_t *exoff) {
     // exclusive prefix of the sizes of each vertex's nets; a vertex of more
-    // than 32 nets is scanned by its whole wave, 64 entries at a time
+    // than 128 nets is scanned by its whole wave, 64 entries at a time (a
+    // wave takes its heavy vertices one after another, so the threshold is
+    // above the degrees of coarse levels, which run to a few dozen)
     for (uint32_t v0 = blockIdx.x * BLOCK; v0 < n; v0 += gridDim.x * BLOCK) {
         const uint32_t v = v0 + threadIdx.x;
         uint32_t j0 = 0, j1 = 0;
         if (v < n) { j0 = inc_off[v]; j1 = inc_off[v + 1]; }
-        const bool heavy = j1 - j0 > 32;
-        if (!heavy) {
+        const bool heavy = j1 - j0 > 128;
+        if (!heavy) {  // eight nets at a time: their IDs, then their sizes, then the prefix
             uint32_t acc = 0;
-            for (uint32_t j = j0; j < j1; ++j) {
-                exoff[j] = acc;
-                const uint32_t e = inc[j];
-                acc += pin_off[e + 1] - pin_off[e];
+            for (uint32_t j = j0; j < j1; j += 8) {
+                uint32_t ev[8], sz[8];
+#pragma unroll
+                for (uint32_t c = 0; c < 8; ++c) ev[c] = j + c < j1 ? inc[j + c] : NONE;
+#pragma unroll
+                for (uint32_t c = 0; c < 8; ++c) sz[c] = ev[c] != NONE ? pin_off[ev[c] + 1] - pin_off[ev[c]] : 0u;
+#pragma unroll
+                for (uint32_t c = 0; c < 8; ++c) {
+                    if (j + c < j1) exoff[j + c] = acc;
+                    acc += sz[c];
+                }
             }
         }
         uint64_t hm = __ballot(heavy);
