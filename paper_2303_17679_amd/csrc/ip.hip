@@ -175,10 +175,16 @@ __global__ void k_bfs_keys(const uint32_t *D, const uint32_t *bst, const uint32_
         pair_of(D, F, t, order, fs, inc_off, fi, jj);
         uint32_t e = inc[jj];
         uint64_t base = ((uint64_t)fi << 32) | exoff[jj];
-        uint32_t b = pin_off[e];
-        for (uint32_t q = b; q < pin_off[e + 1]; ++q) {
-            uint32_t w = pins[q];
-            if (!visited[w]) atomicMin(&key[w], (unsigned long long)(base + (q - b)));
+        const uint32_t b = pin_off[e], b1 = pin_off[e + 1];
+        for (uint32_t q0 = b; q0 < b1; q0 += 8) {  // eight pins at a time: pins, then their flags
+            uint32_t w[8], vis[8];
+#pragma unroll
+            for (uint32_t c = 0; c < 8; ++c) w[c] = q0 + c < b1 ? pins[q0 + c] : NONE;
+#pragma unroll
+            for (uint32_t c = 0; c < 8; ++c) vis[c] = w[c] != NONE ? visited[w[c]] : 1u;
+#pragma unroll
+            for (uint32_t c = 0; c < 8; ++c)
+                if (!vis[c]) atomicMin(&key[w[c]], (unsigned long long)(base + (q0 + c - b)));
         }
     }
 }
@@ -194,13 +200,24 @@ __global__ void k_bfs_winners(const uint32_t *D, const uint32_t *bst, const uint
         pair_of(D, F, t, order, fs, inc_off, fi, jj);
         uint32_t e = inc[jj];
         uint64_t base = ((uint64_t)fi << 32) | exoff[jj];
-        uint32_t b = pin_off[e];
+        const uint32_t b = pin_off[e], b1 = pin_off[e + 1];
         uint32_t c = 0, wp = write ? pos + cnt[t] : 0;
-        for (uint32_t q = b; q < pin_off[e + 1]; ++q) {
-            uint32_t w = pins[q];
-            if (!visited[w] && key[w] == base + (q - b)) {
-                if (write) order_out[wp + c] = w;
-                ++c;
+        for (uint32_t q0 = b; q0 < b1; q0 += 8) {  // eight pins at a time, decided in pin order
+            uint32_t w[8], vis[8];
+            unsigned long long kw[8];
+#pragma unroll
+            for (uint32_t i = 0; i < 8; ++i) w[i] = q0 + i < b1 ? pins[q0 + i] : NONE;
+#pragma unroll
+            for (uint32_t i = 0; i < 8; ++i) {
+                vis[i] = w[i] != NONE ? visited[w[i]] : 1u;
+                kw[i] = w[i] != NONE ? key[w[i]] : 0ull;
+            }
+#pragma unroll
+            for (uint32_t i = 0; i < 8; ++i) {
+                if (!vis[i] && kw[i] == base + (q0 + i - b)) {
+                    if (write) order_out[wp + c] = w[i];
+                    ++c;
+                }
             }
         }
         if (!write) cnt[t] = c;
