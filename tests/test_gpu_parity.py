@@ -221,3 +221,38 @@ def test_invalid_inputs_rejected(hgp):
         H.partition(G, H.params(300))
     with pytest.raises(H.HGPError):
         H.partition(G, H.params(1))
+
+
+def test_contract_capacity_guard(hgp):
+    """A coarse level above the caller's capacities is rejected, and nothing
+    is written past them: the kernels that run before the coarse sizes are
+    read back write only below the capacities."""
+    import ctypes
+    import torch
+    H = hgp
+    h = make("random2k")
+    G = H.Hypergraph.from_host(h)
+    rep, _ = H.coarsen(G, H.params(2))
+    _, C = H.contract(G, rep)
+    nc, mc, pc = C.n, C.m, C.p
+    assert min(nc, mc, pc) > 1
+    SENT, PAD = -123456789, 4096  # the padding also keeps any stray write inside the tensor
+    for cn, cm, cp in ((nc - 1, mc, pc), (nc, mc - 1, pc), (nc, mc, pc - 1)):
+        say("contract capacities", cn, cm, cp, "for", nc, mc, pc)
+        sizes = dict(pin_off=cm + 1, pins=cp, inc_off=cn + 1, inc=cp, vwgt=cn, nwgt=cm)
+        bufs = {k: torch.full((v + PAD,), SENT, dtype=torch.int32, device="cuda") for k, v in sizes.items()}
+        dims = torch.zeros(3, dtype=torch.int32, device="cuda")
+        out = H._HGOut(cn, cm, cp, *[H._ptr(bufs[k]) for k in ("pin_off", "pins", "inc_off", "inc", "vwgt", "nwgt")],
+                       H._ptr(dims))
+        ws = H._ws(H.OP_CONTRACT, G)
+        cid = torch.empty(G.n, dtype=torch.int32, device="cuda")
+        s = G.struct()
+        st = H.lib().hgp_contract(ctypes.byref(s), H._ptr(rep), H._ptr(cid), ctypes.byref(out), H._ptr(ws),
+                                  ws.numel(), H._stream())
+        torch.cuda.synchronize()
+        assert st == -1, (cn, cm, cp)
+        for k, v in sizes.items():
+            assert bool((bufs[k][v:] == SENT).all()), (cn, cm, cp, k)
+    # a contraction with room still gives the same level afterwards
+    _, C2 = H.contract(G, rep)
+    same_hg(C2, C.to_host())
