@@ -157,9 +157,13 @@ __device__ inline void rate_small_net(const RateArgs &a, uint32_t u, uint32_t b,
 // A large net adds its score once per cluster: a bit per slot marks the
 // clusters it has reached (cleared before each large net).
 // ---------------------------------------------------------------------------
-template <int G, int CAP, int LOG2CAP, uint32_t LN>
-__global__ __launch_bounds__(BLOCK) void k_rate_group(RateArgs a, const uint32_t *list, uint32_t count) {
-    constexpr int GPB = BLOCK / G;
+// Workgroup size of the 16- and 64-lane classes: their tables take about
+// 54-58 KB of LDS per 256 threads, so halving the workgroup lets five of them
+// share a CU instead of two (10 waves instead of 8).
+constexpr int RATE_NT = 128;
+template <int G, int CAP, int LOG2CAP, uint32_t LN, int NT = BLOCK>
+__global__ __launch_bounds__(NT) void k_rate_group(RateArgs a, const uint32_t *list, uint32_t count) {
+    constexpr int GPB = NT / G;
     constexpr int MW = CAP / 64;  // mask words per group
     if (rate_skip(a)) return;
     __shared__ uint32_t keys[GPB][CAP];
@@ -1525,21 +1529,22 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                         k_rate_group<8, 64, 6, LANE_NET><<<grid_for(cntc, BLOCK / 8, 8192), BLOCK, 0, st>>>(a, lst,
                                                                                                       cntc);
                     break;
-                case 1:
+                case 1: {
+                    const unsigned gb = grid_for(cntc, RATE_NT / 16, 8192);
                     if (small_nets)
-                        k_rate_group<16, 256, 8, 8><<<grid_for(cntc, BLOCK / 16, 8192), BLOCK, 0, st>>>(a, lst, cntc);
+                        k_rate_group<16, 256, 8, 8, RATE_NT><<<gb, RATE_NT, 0, st>>>(a, lst, cntc);
                     else
-                        k_rate_group<16, 256, 8, LANE_NET><<<grid_for(cntc, BLOCK / 16, 8192), BLOCK, 0, st>>>(
-                            a, lst, cntc);
+                        k_rate_group<16, 256, 8, LANE_NET, RATE_NT><<<gb, RATE_NT, 0, st>>>(a, lst, cntc);
                     break;
-                case 2:
+                }
+                case 2: {
+                    const unsigned gb = grid_for(cntc, RATE_NT / 64, 8192);
                     if (small_nets)
-                        k_rate_group<64, 1024, 10, 8><<<grid_for(cntc, BLOCK / 64, 8192), BLOCK, 0, st>>>(a, lst,
-                                                                                                        cntc);
+                        k_rate_group<64, 1024, 10, 8, RATE_NT><<<gb, RATE_NT, 0, st>>>(a, lst, cntc);
                     else
-                        k_rate_group<64, 1024, 10, LANE_NET><<<grid_for(cntc, BLOCK / 64, 8192), BLOCK, 0, st>>>(
-                            a, lst, cntc);
+                        k_rate_group<64, 1024, 10, LANE_NET, RATE_NT><<<gb, RATE_NT, 0, st>>>(a, lst, cntc);
                     break;
+                }
                 default:
                     k_rate_block<<<grid_for(cntc, 1, 8192), BLOCK, 0, st>>>(a, lst, cntc);
                     break;
