@@ -157,10 +157,10 @@ __device__ inline void rate_small_net(const RateArgs &a, uint32_t u, uint32_t b,
 // A large net adds its score once per cluster: a bit per slot marks the
 // clusters it has reached (cleared before each large net).
 // ---------------------------------------------------------------------------
-// Workgroup size of the 16- and 64-lane classes: their tables take about
-// 54-58 KB of LDS per 256 threads, so halving the workgroup lets five of them
-// share a CU instead of two (10 waves instead of 8).
-constexpr int RATE_NT = 128;
+// Workgroup sizes of the rating classes: the tables take about 27 KB (8
+// lanes) and 54-58 KB (16, 64 lanes) of LDS per 256 threads, so smaller
+// workgroups let more waves share a CU's LDS.
+constexpr int RATE_NT8 = 128, RATE_NT = 64;
 template <int G, int CAP, int LOG2CAP, uint32_t LN, int NT = BLOCK>
 __global__ __launch_bounds__(NT) void k_rate_group(RateArgs a, const uint32_t *list, uint32_t count) {
     constexpr int GPB = NT / G;
@@ -1522,13 +1522,14 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             }
             TimedLaunch tl(kid, st);
             switch (c) {
-                case 0:
+                case 0: {
+                    const unsigned gb = grid_for(cntc, RATE_NT8 / 8, 8192);
                     if (small_nets)
-                        k_rate_group<8, 64, 6, 8><<<grid_for(cntc, BLOCK / 8, 8192), BLOCK, 0, st>>>(a, lst, cntc);
+                        k_rate_group<8, 64, 6, 8, RATE_NT8><<<gb, RATE_NT8, 0, st>>>(a, lst, cntc);
                     else
-                        k_rate_group<8, 64, 6, LANE_NET><<<grid_for(cntc, BLOCK / 8, 8192), BLOCK, 0, st>>>(a, lst,
-                                                                                                      cntc);
+                        k_rate_group<8, 64, 6, LANE_NET, RATE_NT8><<<gb, RATE_NT8, 0, st>>>(a, lst, cntc);
                     break;
+                }
                 case 1: {
                     const unsigned gb = grid_for(cntc, RATE_NT / 16, 8192);
                     if (small_nets)
