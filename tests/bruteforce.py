@@ -82,3 +82,29 @@ def merge_path_states(ca, cb):
             j += 1
         states.append((i, j))
     return states
+
+
+# ---------------------------------------------------------------------------
+# Seeded hash from its definition, independent of the oracle's C code.
+# mix64 is the SplitMix64 finalizer (Steele, Lea, Flood 2014); the tests pin
+# it to the published outputs of that generator.  The tag layout is the one
+# fixed for this method's determinism: H(seed, purpose, level, it, x) =
+# mix64(mix64(seed) XOR ((purpose | level << 8 | it << 16) << 32 | x)), with
+# purpose 1 = coarsening sub-round, 2 = rating tie, 3 = LP sub-round.
+# ---------------------------------------------------------------------------
+M64 = (1 << 64) - 1
+
+
+def mix64(z):
+    z &= M64
+    z ^= z >> 30
+    z = (z * 0xBF58476D1CE4E5B9) & M64
+    z ^= z >> 27
+    z = (z * 0x94D049BB133111EB) & M64
+    z ^= z >> 31
+    return z
+
+
+def H(seed, purpose, level, it, x):
+    tag = (purpose & 0xFF) | ((level & 0xFF) << 8) | ((it & 0xFFFF) << 16)
+    return mix64(mix64(seed) ^ ((tag << 32) | (x & 0xFFFFFFFF)))

@@ -156,7 +156,7 @@ def test_rating_and_target_bruteforce(orc, seed):
         for r in range(2):
             target, nc = orc.rate_subround(h, P, 0, r, rep, cw, cs)
             cand = [u for u in range(h.n) if rep[u] == u and cs[u] == 1
-                    and orc.hash_(seed, 1, 0, 0, u) % 2 == r]
+                    and bf.H(seed, 1, 0, 0, u) % 2 == r]
             assert nc == len(cand)
             for u in range(h.n):
                 if u not in cand:
@@ -167,7 +167,7 @@ def test_rating_and_target_bruteforce(orc, seed):
                 if not ok:
                     assert target[u] == orc.NONE
                     continue
-                best = min(ok, key=lambda C: (-R[C], orc.hash_(seed, 2, 0, 0, C), C))
+                best = min(ok, key=lambda C: (-R[C], bf.H(seed, 2, 0, 0, C), C))
                 assert target[u] == best, (u, R, ok)
 
 
@@ -355,7 +355,8 @@ def test_cluster_pass_cap_and_invariants(orc):
     cw = np.bincount(rep, weights=h.vwgt, minlength=h.n)
     Wt = int(h.vwgt.sum())
     assert all(160 * 4 * cw[c] <= Wt or cw[c] == h.vwgt[c] for c in range(h.n) if rep[c] == c)
-    # pass cut: stops after the first sub-round that leaves fewer than n/2.5 clusters
+    # a pass that ended early left fewer than n/2.5 clusters (the rule itself
+    # is replayed sub-round by sub-round in test_oracle_rules)
     assert run == 3 or 5 * cnt < 2 * h.n
 
 
@@ -417,7 +418,7 @@ def test_lp_proposals_bruteforce(orc, seed):
         for s in range(2):
             t, g = orc.lp_proposals(h, P, 0, 1, s, part)
             for u in range(h.n):
-                if orc.hash_(seed, 3, 0, 1, u) % 2 != s:
+                if bf.H(seed, 3, 0, 1, u) % 2 != s:
                     assert t[u] == orc.NONE
                     continue
                 best = None
