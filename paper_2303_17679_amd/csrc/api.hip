@@ -30,8 +30,27 @@ hgp_status check_hg(const hgp_hg *h) {
     return HGP_OK;
 }
 
+// Runs f, turning exceptions into status codes.  A call that fails after it
+// has enqueued work (a workspace or capacity check partway through, a launch
+// error) waits for `st` before returning, so that on every error return no
+// work of the call is still running and the caller may reuse its buffers.
 template <class F>
-hgp_status guarded(F &&f) {
+hgp_status guarded(hipStream_t st, F &&f) {
+    hgp_status s;
+    try {
+        s = f();
+    } catch (const Error &e) {
+        s = e.code;
+    } catch (...) {
+        s = HGP_E_DEVICE;
+    }
+    if (s != HGP_OK) (void)hipStreamSynchronize(st);
+    return s;
+}
+
+// Host-only computations (no stream involved).
+template <class F>
+hgp_status guarded_host(F &&f) {
     try {
         return f();
     } catch (const Error &e) {
@@ -75,7 +94,7 @@ hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p, const
     } else {
         hgp_default_params(2, &dp);
     }
-    return guarded([&]() -> hgp_status {
+    return guarded_host([&]() -> hgp_status {
         size_t need = 0;
         switch (op) {
             case HGP_OP_COARSEN: need = coarsen_workspace(n, m, p, dp); break;
@@ -105,7 +124,7 @@ hgp_status hgp_validate(const hgp_hg *h, void *ws, size_t ws_bytes, void *stream
     hgp_status s = check_hg(h);
     if (s != HGP_OK) return s;
     if (!ws) return HGP_E_WORKSPACE;
-    return guarded([&]() {
+    return guarded(S(stream), [&]() {
         Arena A(ws, ws_bytes);
         return validate(*h, A, S(stream));
     });
@@ -117,7 +136,7 @@ hgp_status hgp_coarsen(const hgp_hg *h, const hgp_params *prm, uint32_t level, u
     if (s == HGP_OK) s = check_params(prm);
     if (s != HGP_OK) return s;
     if (!rep || !ws) return HGP_E_INVALID;
-    return guarded([&]() {
+    return guarded(S(stream), [&]() {
         Arena A(ws, ws_bytes);
         coarsen_pass(*h, *prm, level, rep, n_clusters, nullptr, A, S(stream));
         return HGP_OK;
@@ -130,7 +149,7 @@ hgp_status hgp_contract(const hgp_hg *fine, const uint32_t *rep, uint32_t *cid, 
     if (s != HGP_OK) return s;
     if (!rep || !cid || !out || !ws || !out->pin_off || !out->inc_off || !out->vwgt) return HGP_E_INVALID;
     if (out->cap_n < 1 || (fine->m && !out->nwgt) || (fine->p && (!out->pins || !out->inc))) return HGP_E_INVALID;
-    return guarded([&]() {
+    return guarded(S(stream), [&]() {
         Arena A(ws, ws_bytes);
         contract(*fine, rep, cid, *out, nullptr, A, S(stream));
         return HGP_OK;
@@ -139,7 +158,7 @@ hgp_status hgp_contract(const hgp_hg *fine, const uint32_t *rep, uint32_t *cid, 
 
 hgp_status hgp_project(uint32_t n, const uint32_t *cid, const uint32_t *coarse_part, uint32_t *part, void *stream) {
     if (n && (!cid || !coarse_part || !part)) return HGP_E_INVALID;
-    return guarded([&]() {
+    return guarded(S(stream), [&]() {
         project(n, cid, coarse_part, part, S(stream));
         return HGP_OK;
     });
@@ -152,7 +171,7 @@ hgp_status hgp_objective(const hgp_hg *h, uint32_t k, const uint32_t *part, int6
     if (k < 2) return HGP_E_INVALID;
     if (k > 256) return HGP_E_UNSUPPORTED;
     if (!part || !objective || !ws) return HGP_E_INVALID;
-    return guarded([&]() {
+    return guarded(S(stream), [&]() {
         Arena A(ws, ws_bytes);
         hgp::objective(*h, k, part, objective, block_wgt, A, S(stream));
         return HGP_OK;
@@ -165,7 +184,7 @@ hgp_status hgp_refine_lp(const hgp_hg *h, const hgp_params *prm, uint32_t level,
     if (s == HGP_OK) s = check_params(prm);
     if (s != HGP_OK) return s;
     if (!part || !ws) return HGP_E_INVALID;
-    return guarded([&]() {
+    return guarded(S(stream), [&]() {
         Arena A(ws, ws_bytes);
         refine_lp(*h, *prm, level, part, objective, block_wgt, A, S(stream));
         return HGP_OK;
@@ -179,7 +198,7 @@ hgp_status hgp_initial_partition(const hgp_hg *h, uint32_t k, uint32_t *part, vo
     if (k < 2) return HGP_E_INVALID;
     if (k > 256) return HGP_E_UNSUPPORTED;
     if (!part || !ws) return HGP_E_INVALID;
-    return guarded([&]() {
+    return guarded(S(stream), [&]() {
         Arena A(ws, ws_bytes);
         initial_partition(*h, k, part, A, S(stream));
         return HGP_OK;
@@ -268,7 +287,7 @@ hgp_status hgp_partition(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
     if (s != HGP_OK) return s;
     if (!part || !objective || !ws) return HGP_E_INVALID;
     hipStream_t st = S(stream);
-    return guarded([&]() -> hgp_status {
+    return guarded(st, [&]() -> hgp_status {
         Arena A(ws, ws_bytes);
         return partition_one(h0, prm, part, objective, levels_out, A, st);
     });

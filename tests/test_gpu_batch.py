@@ -114,3 +114,49 @@ def test_server_rejects_request_larger_than_pool(hgp):
             S.submit(g, prm)
     finally:
         S.close()
+
+
+def test_server_failed_requests_leave_the_others_intact(hgp):
+    # malformed requests (pins out of order, so the device-side validation
+    # fails after launching its kernels) mixed with good ones: every failed
+    # request returns its error after its own work has drained, the pool
+    # memory it held goes to later requests, and every good request equals
+    # its result alone
+    import dataclasses
+    import torch
+    H = hgp
+    good = [(W.workload("stencil16")[0], 4, 4), (W.random_uniform(5000, 5000, 2, 8, seed=5), 2, 3)]
+    good += [(h, k, 10 + i) for (h, k, i) in small_vlsi(4)]
+    bad_h = W.random_uniform(20000, 20000, 2, 8, seed=7)
+    pins = bad_h.pins.copy()
+    a, b = int(bad_h.pin_off[10]), int(bad_h.pin_off[10]) + 1
+    pins[a], pins[b] = pins[b], pins[a]
+    bad_h = dataclasses.replace(bad_h, pins=pins)
+    hs = [H.Hypergraph.from_host(h) for h, _, _ in good]
+    prms = [H.params(k, seed=sd) for (_, k, sd) in good]
+    alone = [H.partition(g, p) for g, p in zip(hs, prms)]
+    bad = H.Hypergraph.from_host(bad_h)
+    with pytest.raises(H.HGPError):
+        H.partition(bad, H.params(8))
+    need = [H.workspace_bytes(H.OP_PARTITION, g.n, g.m, g.p, p) for g, p in zip(hs, prms)]
+    need_bad = H.workspace_bytes(H.OP_PARTITION, bad.n, bad.m, bad.p, H.params(8))
+    pool = max(need + [need_bad]) * 2 + 4096
+    S = H.Server(lanes=3, pool_bytes=pool)
+    try:
+        order = []
+        for i, (g, p) in enumerate(zip(hs, prms)):
+            order.append(("bad", S.submit(bad, H.params(8))))
+            order.append((i, S.submit(g, p)))
+        for what, (t, part, obj) in order:
+            if what == "bad":
+                with pytest.raises(H.HGPError) as ei:
+                    S.wait(t)
+                assert ei.value.status == -1  # HGP_E_INVALID
+                continue
+            lv, lat, qm = S.wait(t)
+            torch.cuda.synchronize()
+            p_ref, f_ref, l_ref = alone[what]
+            assert lv == l_ref and int(obj.item()) == f_ref
+            assert np.array_equal(host(part), host(p_ref))
+    finally:
+        S.close()
