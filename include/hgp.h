@@ -8,8 +8,9 @@
  * Conventions for every entry point
  *  - Array arguments are DEVICE pointers (HIP device memory on the current
  *    device) unless a comment says "host".  The caller owns every buffer,
- *    including the workspace; the library never allocates device memory,
- *    never frees, and keeps no pointer past the end of the call.
+ *    including the workspace; the library never allocates device memory
+ *    (beyond the one fixed array that hgp_refine_lp_static uses), never
+ *    frees, and keeps no pointer past the end of the call.
  *  - IDs and offsets are uint32, vertex and net weights int32 (>= 1).
  *  - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).
  *    Entry points marked "syncs" wait for `stream` before returning
@@ -185,6 +186,20 @@ hgp_status hgp_initial_partition(const hgp_hg *h, uint32_t k, uint32_t *part,
 hgp_status hgp_partition(const hgp_hg *h, const hgp_params *prm, uint32_t *part,
                          int64_t *objective, uint32_t *levels_out,
                          void *ws, size_t ws_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * refinement as hgp_refine_lp, with its scratch memory in a device array of
+ * HGP_STATIC_SCRATCH_BYTES that the library holds on every device it runs on
+ * until the process ends, instead of a caller workspace.  The call allocates
+ * nothing.  A level whose hgp_workspace_bytes(HGP_OP_REFINE, n, m, p, prm)
+ * exceeds HGP_STATIC_SCRATCH_BYTES is rejected with HGP_E_WORKSPACE before
+ * anything is enqueued.  Every call on one device shares that device's array:
+ * calls that overlap on one device (from several host threads, or on streams
+ * not ordered with each other) race and give undefined results.  Syncs. */
+#define HGP_STATIC_SCRATCH_BYTES (64u << 20)
+hgp_status hgp_refine_lp_static(const hgp_hg *h, const hgp_params *prm, uint32_t level, uint32_t *part,
+                                int64_t *objective, int64_t *block_wgt, void *stream);
 
 /* ------------------------------------------------------------------------
  * Many hypergraphs at once.  Each request runs exactly the driver of

@@ -26,7 +26,7 @@ EXPORTS = ["hgp_default_params", "hgp_workspace_bytes", "hgp_validate", "hgp_coa
            "hgp_project", "hgp_objective", "hgp_refine_lp", "hgp_initial_partition", "hgp_partition",
            "hgp_timing_scratch_bytes", "hgp_timing_begin", "hgp_timing_end", "hgp_status_str",
            "hgp_server_create", "hgp_server_submit", "hgp_server_wait", "hgp_server_destroy",
-           "hgp_batch_workspace_bytes", "hgp_partition_batch"]
+           "hgp_batch_workspace_bytes", "hgp_partition_batch", "hgp_refine_lp_static"]
 
 # kernel ids of the measurement calls, with the kernel symbol each one names
 KERNELS = ["k_rate_group<8, 64, 6>", "k_rate_group<16, 256, 8>", "k_rate_group<64, 1024, 10>", "k_rate_block",
@@ -86,6 +86,7 @@ def lib():
         L.hgp_project.restype = i32; L.hgp_project.argtypes = [u32, P, P, P, P]
         L.hgp_objective.restype = i32; L.hgp_objective.argtypes = [P, u32, P, P, P, P, ctypes.c_size_t, P]
         L.hgp_refine_lp.restype = i32; L.hgp_refine_lp.argtypes = [P, P, u32, P, P, P, P, ctypes.c_size_t, P]
+        L.hgp_refine_lp_static.restype = i32; L.hgp_refine_lp_static.argtypes = [P, P, u32, P, P, P, P]
         L.hgp_initial_partition.restype = i32
         L.hgp_initial_partition.argtypes = [P, u32, P, P, ctypes.c_size_t, P]
         L.hgp_partition.restype = i32
@@ -261,6 +262,21 @@ def refine_lp(h: Hypergraph, prm: Params, level: int, part):
     s = h.struct()
     _check(lib().hgp_refine_lp(ctypes.byref(s), ctypes.byref(prm), level, _ptr(part), _ptr(f), _ptr(bw),
                                _ptr(ws), ws.numel(), _stream()), "hgp_refine_lp")
+    return int(f.item()), bw
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # HGP_STATIC_SCRATCH_BYTES
+
+
+def refine_lp_static(h: Hypergraph, prm: Params, level: int, part):
+    """hgp_refine_lp_static: the same refinement with the library's fixed
+    device scratch array (no workspace); returns (objective, block weights)."""
+    torch = _torch()
+    f = torch.zeros(1, dtype=torch.int64, device=h.device)
+    bw = torch.zeros(prm.k, dtype=torch.int64, device=h.device)
+    s = h.struct()
+    _check(lib().hgp_refine_lp_static(ctypes.byref(s), ctypes.byref(prm), level, _ptr(part), _ptr(f), _ptr(bw),
+                                      _stream()), "hgp_refine_lp_static")
     return int(f.item()), bw
 
 

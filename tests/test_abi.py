@@ -27,7 +27,7 @@ def H():
 
 def test_header_symbols_exported(H):
     names = declared()
-    assert len(names) == 20
+    assert len(names) == 21
     assert names == sorted(H.EXPORTS)
     L = ctypes.CDLL(H.LIB_PATH)
     for n in names:
@@ -72,3 +72,17 @@ def test_bad_parameters_rejected_on_host(H):
     # null hypergraph / workspace pointers are refused before any device work
     assert L.hgp_partition(None, ctypes.byref(H.params(4)), None, None, None, None, 0, None) == -1
     assert L.hgp_coarsen(None, None, 0, None, None, None, 0, None) == -1
+
+
+def test_static_refine_rejects_levels_beyond_its_scratch(H):
+    # rejected on the host from the sizes alone, before any device work
+    import ctypes
+    L = H.lib()
+    s = H._HG(1 << 24, 1 << 24, 1 << 26, None, None, None, None, None, None)
+    prm = H.params(64)
+    part = ctypes.c_uint32(0)
+    st = L.hgp_refine_lp_static(ctypes.byref(s), ctypes.byref(prm), 0, ctypes.addressof(part), None, None, None)
+    assert st == -3  # HGP_E_WORKSPACE
+    need = ctypes.c_size_t(0)
+    assert L.hgp_workspace_bytes(3, 1 << 24, 1 << 24, 1 << 26, ctypes.byref(prm), ctypes.byref(need)) == 0
+    assert need.value > H.STATIC_SCRATCH_BYTES
