@@ -74,6 +74,10 @@ def lib():
         L.or_refine_lp.argtypes = [P, P, u32, P, P, P, P, P]
         L.or_partition.restype = ctypes.c_int; L.or_partition.argtypes = [P, P, P, P, P]
         L.or_lp_proposals.restype = u32; L.or_lp_proposals.argtypes = [P, P, u32, u32, u32, P, P, P]
+        L.or_gain_table.restype = ctypes.c_int; L.or_gain_table.argtypes = [P, u32, P, P, P]
+        L.or_gain_table_moves.restype = ctypes.c_int
+        L.or_gain_table_moves.argtypes = [P, u32, P, P, P, u32, P, P]
+        L.or_gain_recalc.restype = ctypes.c_int; L.or_gain_recalc.argtypes = [P, u32, P, P, P, u32, P]
         _lib = L
     return _lib
 
@@ -211,6 +215,41 @@ def lp_proposals(h, P: Params, level: int, r: int, s: int, part):
     g = np.empty(h.n, np.int64)
     lib().or_lp_proposals(v.ref, ctypes.byref(P), level, r, s, _ptr(part), _ptr(t), _ptr(g))
     return t, g
+
+
+def gain_table(h, k: int, part):
+    """(benefit[n], penalty[n, k]) of the gain table (int64)."""
+    v = _View(h)
+    part = np.ascontiguousarray(part, np.uint32)
+    ben = np.zeros(max(h.n, 1), np.int64)
+    pen = np.zeros((max(h.n, 1), k), np.int64)
+    assert lib().or_gain_table(v.ref, k, _ptr(part), _ptr(ben), _ptr(pen)) == 0
+    return ben[:h.n], pen[:h.n]
+
+
+def gain_table_moves(h, k: int, part, mu, mt, ben, pen):
+    """Applies the moves with the gain-table update rules; returns the new
+    (part, benefit, penalty)."""
+    v = _View(h)
+    part = np.array(part, dtype=np.uint32, copy=True)
+    ben = np.array(ben, dtype=np.int64, copy=True)
+    pen = np.ascontiguousarray(np.array(pen, dtype=np.int64, copy=True))
+    mu = np.ascontiguousarray(mu, np.uint32)
+    mt = np.ascontiguousarray(mt, np.uint32)
+    assert lib().or_gain_table_moves(v.ref, k, _ptr(part), _ptr(mu), _ptr(mt), mu.shape[0], _ptr(ben),
+                                     _ptr(pen)) == 0
+    return part, ben, pen
+
+
+def gain_recalc(h, k: int, part, mu, mt):
+    """Gain of every move of the sequence when performed in order (int64)."""
+    v = _View(h)
+    part = np.ascontiguousarray(part, np.uint32)
+    mu = np.ascontiguousarray(mu, np.uint32)
+    mt = np.ascontiguousarray(mt, np.uint32)
+    g = np.zeros(max(mu.shape[0], 1), np.int64)
+    assert lib().or_gain_recalc(v.ref, k, _ptr(part), _ptr(mu), _ptr(mt), mu.shape[0], _ptr(g)) == 0
+    return g[:mu.shape[0]]
 
 
 def partition(h, P: Params):

@@ -729,3 +729,109 @@ int or_partition(const or_hg *h0, const or_params *P, uint32_t *part, int64_t *f
     free(L); free(rep); free(cp);
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Gain table (Sec. 6.2): benefit b(u) = w({e in I(u): Phi(e, Pi[u]) = 1})  */
+/* and penalty p(u, V_t) = w({e in I(u): Phi(e, V_t) = 0}), so that         */
+/* g_u(t) = b(u) - p(u, V_t).  pen is row major, n rows of k entries.       */
+/* ------------------------------------------------------------------------ */
+int or_gain_table(const or_hg *h, uint32_t k, const uint32_t *part, int64_t *ben, int64_t *pen)
+{
+    uint32_t *cnt = (uint32_t *)calloc(k, sizeof(uint32_t));
+    if (!cnt) return OR_E_NOMEM;
+    for (uint32_t u = 0; u < h->n; ++u) {
+        ben[u] = 0;
+        for (uint32_t t = 0; t < k; ++t) pen[(size_t)u * k + t] = 0;
+        for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+            uint32_t e = h->inc[j];
+            for (uint32_t t = 0; t < k; ++t) cnt[t] = 0;
+            for (uint32_t q = h->pin_off[e]; q < h->pin_off[e + 1]; ++q) cnt[part[h->pins[q]]]++;
+            if (cnt[part[u]] == 1) ben[u] += h->nwgt[e];
+            for (uint32_t t = 0; t < k; ++t)
+                if (cnt[t] == 0) pen[(size_t)u * k + t] += h->nwgt[e];
+        }
+    }
+    free(cnt);
+    return OR_OK;
+}
+
+/* Moves u_i -> t_i (i = 0..l-1, every node at most once) applied one after
+ * the other to part, with the update rules of Sec. 6.2 on the gain table
+ * after each move: with Phi updated for the move (Phi(e, s) - 1 and
+ * Phi(e, t) + 1 for every e in I(u)), a penalty for s is added for every pin
+ * of e when Phi(e, s) reaches 0, a benefit is added to the pin left alone in
+ * s when Phi(e, s) reaches 1, the penalty for t is taken back from every pin
+ * when Phi(e, t) reaches 1, and the benefit of the pin that was alone in t is
+ * taken back when Phi(e, t) reaches 2.  As in the paper, the benefits of the
+ * moved nodes are recomputed afterwards (their block changed).  part, ben and
+ * pen are updated in place. */
+int or_gain_table_moves(const or_hg *h, uint32_t k, uint32_t *part, const uint32_t *mu, const uint32_t *mt,
+                        uint32_t l, int64_t *ben, int64_t *pen)
+{
+    const uint32_t m = h->m;
+    uint32_t *phi = (uint32_t *)calloc((size_t)(m ? m : 1) * k, sizeof(uint32_t));
+    uint8_t *moved = (uint8_t *)calloc(h->n ? h->n : 1, 1);
+    if (!phi || !moved) return OR_E_NOMEM;
+    for (uint32_t e = 0; e < m; ++e)
+        for (uint32_t q = h->pin_off[e]; q < h->pin_off[e + 1]; ++q) phi[(size_t)e * k + part[h->pins[q]]]++;
+    for (uint32_t i = 0; i < l; ++i) {
+        const uint32_t u = mu[i], s = part[u], t = mt[i];
+        if (s == t) continue;
+        part[u] = t;
+        moved[u] = 1;
+        for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+            const uint32_t e = h->inc[j];
+            const int64_t w = h->nwgt[e];
+            const uint32_t ps = --phi[(size_t)e * k + s];
+            const uint32_t pt = ++phi[(size_t)e * k + t];
+            for (uint32_t q = h->pin_off[e]; q < h->pin_off[e + 1]; ++q) {
+                const uint32_t v = h->pins[q];
+                if (ps == 0) pen[(size_t)v * k + s] += w;
+                if (ps == 1 && part[v] == s) ben[v] += w;
+                if (pt == 1) pen[(size_t)v * k + t] -= w;
+                if (pt == 2 && part[v] == t) ben[v] -= w;
+            }
+        }
+    }
+    for (uint32_t u = 0; u < h->n; ++u) {
+        if (!moved[u]) continue;
+        ben[u] = 0;
+        for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+            const uint32_t e = h->inc[j];
+            if (phi[(size_t)e * k + part[u]] == 1) ben[u] += h->nwgt[e];
+        }
+    }
+    free(phi); free(moved);
+    return OR_OK;
+}
+
+/* Gains of a move sequence (Sec. 6.3): g_i = f(Pi_{i-1}) - f(Pi_i), the
+ * change of the connectivity objective made by move i when the moves are
+ * performed in the order given, starting from part (unchanged here).  Each
+ * move u_i -> t_i, every node moved at most once.  Computed by performing
+ * the moves one after the other: a net leaves block s when its last pin in s
+ * moves out (+w), and enters block t when its first pin arrives (-w). */
+int or_gain_recalc(const or_hg *h, uint32_t k, const uint32_t *part, const uint32_t *mu, const uint32_t *mt,
+                   uint32_t l, int64_t *g)
+{
+    const uint32_t m = h->m;
+    uint32_t *phi = (uint32_t *)calloc((size_t)(m ? m : 1) * k, sizeof(uint32_t));
+    uint32_t *cur = (uint32_t *)malloc(sizeof(uint32_t) * (h->n ? h->n : 1));
+    if (!phi || !cur) return OR_E_NOMEM;
+    memcpy(cur, part, sizeof(uint32_t) * h->n);
+    for (uint32_t e = 0; e < m; ++e)
+        for (uint32_t q = h->pin_off[e]; q < h->pin_off[e + 1]; ++q) phi[(size_t)e * k + cur[h->pins[q]]]++;
+    for (uint32_t i = 0; i < l; ++i) {
+        const uint32_t u = mu[i], s = cur[u], t = mt[i];
+        g[i] = 0;
+        if (s == t) continue;
+        cur[u] = t;
+        for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+            const uint32_t e = h->inc[j];
+            if (--phi[(size_t)e * k + s] == 0) g[i] += h->nwgt[e];
+            if (++phi[(size_t)e * k + t] == 1) g[i] -= h->nwgt[e];
+        }
+    }
+    free(phi); free(cur);
+    return OR_OK;
+}

@@ -108,3 +108,72 @@ def mix64(z):
 def H(seed, purpose, level, it, x):
     tag = (purpose & 0xFF) | ((level & 0xFF) << 8) | ((it & 0xFFFF) << 16)
     return mix64(mix64(seed) ^ ((tag << 32) | (x & 0xFFFFFFFF)))
+
+
+# ---------------------------------------------------------------------------
+# Gain table and move-sequence gains (Sec. 6.2, 6.3) from the definitions
+# ---------------------------------------------------------------------------
+def phi(h, part, e, b):
+    return sum(1 for v in nets_of(h)[e] if int(part[v]) == b)
+
+
+def gain_table(h, k, part):
+    """benefit b(u) = w(nets of u where u is the only pin of its block) and
+    penalty p(u, t) = w(nets of u with no pin in block t)."""
+    nets = nets_of(h)
+    ben = [0] * h.n
+    pen = [[0] * k for _ in range(h.n)]
+    for e, pins in enumerate(nets):
+        w = int(h.nwgt[e])
+        blocks = [int(part[v]) for v in pins]
+        for v in pins:
+            if blocks.count(int(part[v])) == 1:
+                ben[v] += w
+            for t in range(k):
+                if t not in blocks:
+                    pen[v][t] += w
+    return ben, pen
+
+
+def sequence_gains(h, part, moves):
+    """Objective decrease of each move when the moves are performed in order."""
+    q = [int(x) for x in part]
+    out = []
+    for u, t in moves:
+        before = objective(h, q)
+        q[u] = t
+        out.append(before - objective(h, q))
+    return out
+
+
+def alg4_gains(h, part, moves):
+    """The paper's parallel gain recalculation (Sec. 6.3), one net at a time:
+    for every block, the index of the first move into it and of the last move
+    out of it among the net's pins, and the number of unmoved pins in it; a
+    move gains w(e) when it is the last to leave a block that ends empty of
+    unmoved pins before any pin arrives, and loses w(e) when it is the first to
+    arrive in a block left empty in that way earlier."""
+    idx = {u: i for i, (u, t) in enumerate(moves)}
+    g = [0] * len(moves)
+    for e, pins in enumerate(nets_of(h)):
+        w = int(h.nwgt[e])
+        first_in, last_out, unmoved = {}, {}, {}
+        for v in pins:
+            if v in idx:
+                i = idx[v]
+                s, t = int(part[v]), moves[i][1]
+                last_out[s] = max(i, last_out.get(s, -1))
+                first_in[t] = min(i, first_in.get(t, len(moves)))
+            else:
+                b = int(part[v])
+                unmoved[b] = unmoved.get(b, 0) + 1
+        for v in pins:
+            if v not in idx:
+                continue
+            i = idx[v]
+            s, t = int(part[v]), moves[i][1]
+            if last_out.get(s) == i and i < first_in.get(s, len(moves)) and unmoved.get(s, 0) == 0:
+                g[i] += w
+            if first_in.get(t) == i and i > last_out.get(t, -1) and unmoved.get(t, 0) == 0:
+                g[i] -= w
+    return g
