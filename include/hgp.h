@@ -74,9 +74,9 @@ typedef struct {
     uint32_t *dims;    /* device [3] <- n', m', p' */
 } hgp_hg_out;
 
-/* Parameters.  Every field changes results, so tests pass the same values
- * to the reference implementation.  hgp_default_params() fills the
- * defaults given in brackets. */
+/* Parameters.  Every field but flags changes results, so tests pass the
+ * same values to the reference implementation.  hgp_default_params() fills
+ * the defaults given in brackets. */
 typedef struct {
     uint32_t k;                 /* number of blocks, 2..256                          */
     uint32_t eps_num, eps_den;  /* imbalance eps = num/den exactly [3/100]; den <= 2^20 */
@@ -85,7 +85,14 @@ typedef struct {
     uint32_t coarsen_subrounds; /* S_c, sub-rounds of a clustering pass [3] (Sec. 11)  */
     uint32_t lp_subrounds;      /* S_lp, sub-rounds of an LP round [5] (Sec. 11)       */
     uint32_t lp_rounds;         /* R_lp, maximum LP rounds per level [5]               */
+    uint32_t flags;             /* HGP_TRUSTED_INPUT or 0 [0]; results do not depend on it */
 } hgp_params;
+
+/* hgp_params.flags: the caller vouches that the hypergraph meets every
+ * precondition of hgp_hg (e.g. hgp_validate returned HGP_OK for it before),
+ * so hgp_partition skips its own device-side check of the input.  Results
+ * for valid input are the same; invalid input is then undefined behaviour. */
+#define HGP_TRUSTED_INPUT 1u
 
 /* Workspace-size queries. */
 #define HGP_OP_COARSEN 1
@@ -94,6 +101,7 @@ typedef struct {
 #define HGP_OP_PARTITION 4
 #define HGP_OP_VALIDATE 5
 #define HGP_OP_INITIAL 6
+#define HGP_OP_GAINS 7     /* hgp_gain_table, hgp_gain_table_update, hgp_gain_recalc */
 
 /* Host.  Fills *out with the defaults listed in hgp_params for k blocks. */
 hgp_status hgp_default_params(uint32_t k, hgp_params *out);
@@ -200,6 +208,51 @@ hgp_status hgp_partition(const hgp_hg *h, const hgp_params *prm, uint32_t *part,
 #define HGP_STATIC_SCRATCH_BYTES (64u << 20)
 hgp_status hgp_refine_lp_static(const hgp_hg *h, const hgp_params *prm, uint32_t level, uint32_t *part,
                                 int64_t *objective, int64_t *block_wgt, void *stream);
+
+/* Gain table of a partition (paper Sec. 6.2): benefit[u] (device int32 [n])
+ * = the weight of u's nets in which u is the only pin of its block, and
+ * penalty[u * k + t] (device int32 [n * k], row u = the k penalties of u) =
+ * the weight of u's nets without a pin in block t.  Moving u to t changes
+ * the connectivity objective by penalty[u*k+t] - benefit[u] (so the gain is
+ * benefit - penalty).  part[n] holds blocks < k. */
+hgp_status hgp_gain_table(const hgp_hg *h, uint32_t k, const uint32_t *part, int32_t *benefit, int32_t *penalty,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* Applies the moves node[i] -> target[i] (device uint32 [count]; every node
+ * at most once, targets < k; a move to the node's own block does nothing) to
+ * part and brings a gain table of part up to date (paper Sec. 6.2 update
+ * rules, net by net; the moved nodes' benefits are recomputed in their new
+ * blocks).  Afterwards benefit and penalty equal hgp_gain_table of the new
+ * partition.  A node listed twice or an index out of range returns
+ * HGP_E_INVALID with part and the table unchanged.  Syncs. */
+hgp_status hgp_gain_table_update(const hgp_hg *h, uint32_t k, uint32_t *part, const uint32_t *node,
+                                 const uint32_t *target, uint32_t count, int32_t *benefit, int32_t *penalty,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/* Gains of a move sequence (paper Sec. 6.3, parallel gain recalculation):
+ * gain[i] (device int64 [count]) = the decrease of the connectivity
+ * objective caused by move i when the moves node[i] -> target[i] are made
+ * one after the other in index order, starting from part (left unchanged).
+ * Computed per net touched by a move from the first move into and the last
+ * move out of every block among its pins.  Same move rules and errors as
+ * hgp_gain_table_update.  Syncs. */
+hgp_status hgp_gain_recalc(const hgp_hg *h, uint32_t k, const uint32_t *part, const uint32_t *node,
+                           const uint32_t *target, uint32_t count, int64_t *gain, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* Per-level record of one multilevel partition, in host arrays the caller
+ * owns: level l = 0 is the input, l = levels the coarsest level. */
+typedef struct {
+    uint32_t cap;        /* entries of each array below (levels + 1 are needed) */
+    uint32_t levels;     /* out: number of contractions                         */
+    uint32_t *n, *m, *p; /* out [cap] (each may be NULL): sizes of level l      */
+    uint32_t *lp_rounds; /* out [cap] (may be NULL): LP rounds run on level l   */
+} hgp_trace;
+
+/* hgp_partition that also fills *trace (levels beyond trace->cap are run but
+ * not recorded).  Used to price a run's algorithmic bytes by level.  Syncs. */
+hgp_status hgp_partition_traced(const hgp_hg *h, const hgp_params *prm, uint32_t *part, int64_t *objective,
+                                hgp_trace *trace, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Many hypergraphs at once.  Each request runs exactly the driver of

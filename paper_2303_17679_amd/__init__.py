@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhgp.so")
 
-OP_COARSEN, OP_CONTRACT, OP_REFINE, OP_PARTITION, OP_VALIDATE, OP_INITIAL = 1, 2, 3, 4, 5, 6
+OP_COARSEN, OP_CONTRACT, OP_REFINE, OP_PARTITION, OP_VALIDATE, OP_INITIAL, OP_GAINS = 1, 2, 3, 4, 5, 6, 7
 STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_OVERFLOW", -3: "HGP_E_WORKSPACE",
           -4: "HGP_E_DEVICE", -5: "HGP_E_UNSUPPORTED"}
 
@@ -26,7 +26,8 @@ EXPORTS = ["hgp_default_params", "hgp_workspace_bytes", "hgp_validate", "hgp_coa
            "hgp_project", "hgp_objective", "hgp_refine_lp", "hgp_initial_partition", "hgp_partition",
            "hgp_timing_scratch_bytes", "hgp_timing_begin", "hgp_timing_end", "hgp_status_str",
            "hgp_server_create", "hgp_server_submit", "hgp_server_wait", "hgp_server_destroy",
-           "hgp_batch_workspace_bytes", "hgp_partition_batch", "hgp_refine_lp_static"]
+           "hgp_batch_workspace_bytes", "hgp_partition_batch", "hgp_refine_lp_static",
+           "hgp_partition_traced", "hgp_gain_table", "hgp_gain_table_update", "hgp_gain_recalc"]
 
 # kernel ids of the measurement calls, with the kernel symbol each one names
 KERNELS = ["k_rate_group<8, 64, 6>", "k_rate_group<16, 256, 8>", "k_rate_group<64, 1024, 10>", "k_rate_block",
@@ -53,17 +54,26 @@ class _HGOut(ctypes.Structure):
                 ("vwgt", ctypes.c_void_p), ("nwgt", ctypes.c_void_p), ("dims", ctypes.c_void_p)]
 
 
+class _Trace(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_uint32), ("levels", ctypes.c_uint32),
+                ("n", ctypes.c_void_p), ("m", ctypes.c_void_p), ("p", ctypes.c_void_p),
+                ("lp_rounds", ctypes.c_void_p)]
+
+
 class Params(ctypes.Structure):
     """Mirror of hgp_params (every field changes results)."""
     _fields_ = [("k", ctypes.c_uint32), ("eps_num", ctypes.c_uint32), ("eps_den", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("limit_factor", ctypes.c_uint32),
                 ("coarsen_subrounds", ctypes.c_uint32), ("lp_subrounds", ctypes.c_uint32),
-                ("lp_rounds", ctypes.c_uint32)]
+                ("lp_rounds", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 def params(k: int, eps=(3, 100), seed: int = 0, limit_factor: int = 160, coarsen_subrounds: int = 3,
-           lp_subrounds: int = 5, lp_rounds: int = 5) -> Params:
-    return Params(k, eps[0], eps[1], seed, limit_factor, coarsen_subrounds, lp_subrounds, lp_rounds)
+           lp_subrounds: int = 5, lp_rounds: int = 5, trusted: bool = False) -> Params:
+    """trusted: the input was validated before (hgp_validate), so
+    hgp_partition skips its own input check (HGP_TRUSTED_INPUT)."""
+    return Params(k, eps[0], eps[1], seed, limit_factor, coarsen_subrounds, lp_subrounds, lp_rounds,
+                  1 if trusted else 0)
 
 
 _lib = None
@@ -91,6 +101,13 @@ def lib():
         L.hgp_initial_partition.argtypes = [P, u32, P, P, ctypes.c_size_t, P]
         L.hgp_partition.restype = i32
         L.hgp_partition.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_uint32), P, ctypes.c_size_t, P]
+        L.hgp_gain_table.restype = i32; L.hgp_gain_table.argtypes = [P, u32, P, P, P, P, ctypes.c_size_t, P]
+        L.hgp_gain_table_update.restype = i32
+        L.hgp_gain_table_update.argtypes = [P, u32, P, P, P, u32, P, P, P, ctypes.c_size_t, P]
+        L.hgp_gain_recalc.restype = i32
+        L.hgp_gain_recalc.argtypes = [P, u32, P, P, P, u32, P, P, ctypes.c_size_t, P]
+        L.hgp_partition_traced.restype = i32
+        L.hgp_partition_traced.argtypes = [P, P, P, P, P, P, ctypes.c_size_t, P]
         L.hgp_status_str.restype = ctypes.c_char_p; L.hgp_status_str.argtypes = [i32]
         L.hgp_timing_scratch_bytes.restype = i32
         L.hgp_timing_scratch_bytes.argtypes = [u32, u32, ctypes.POINTER(ctypes.c_size_t)]
@@ -265,6 +282,39 @@ def refine_lp(h: Hypergraph, prm: Params, level: int, part):
     return int(f.item()), bw
 
 
+def gain_table(h: Hypergraph, k: int, part, ws=None):
+    """hgp_gain_table: (benefit int32 [n], penalty int32 [n, k])."""
+    torch = _torch()
+    ben = torch.empty(h.n, dtype=torch.int32, device=h.device)
+    pen = torch.empty((h.n, k), dtype=torch.int32, device=h.device)
+    ws = _ws(OP_GAINS, h, params(k)) if ws is None else ws
+    s = h.struct()
+    _check(lib().hgp_gain_table(ctypes.byref(s), k, _ptr(part), _ptr(ben), _ptr(pen), _ptr(ws), ws.numel(),
+                                _stream()), "hgp_gain_table")
+    return ben, pen
+
+
+def gain_table_update(h: Hypergraph, k: int, part, node, target, ben, pen, ws=None):
+    """hgp_gain_table_update: applies the moves to part and updates the
+    table in place."""
+    ws = _ws(OP_GAINS, h, params(k)) if ws is None else ws
+    s = h.struct()
+    _check(lib().hgp_gain_table_update(ctypes.byref(s), k, _ptr(part), _ptr(node), _ptr(target), node.numel(),
+                                       _ptr(ben), _ptr(pen), _ptr(ws), ws.numel(), _stream()),
+           "hgp_gain_table_update")
+
+
+def gain_recalc(h: Hypergraph, k: int, part, node, target, ws=None):
+    """hgp_gain_recalc: int64 gain of every move of the sequence."""
+    torch = _torch()
+    g = torch.empty(max(node.numel(), 1), dtype=torch.int64, device=h.device)
+    ws = _ws(OP_GAINS, h, params(k)) if ws is None else ws
+    s = h.struct()
+    _check(lib().hgp_gain_recalc(ctypes.byref(s), k, _ptr(part), _ptr(node), _ptr(target), node.numel(), _ptr(g),
+                                 _ptr(ws), ws.numel(), _stream()), "hgp_gain_recalc")
+    return g[:node.numel()]
+
+
 STATIC_SCRATCH_BYTES = 64 << 20  # HGP_STATIC_SCRATCH_BYTES
 
 
@@ -293,10 +343,10 @@ def initial_partition(h: Hypergraph, k: int):
 class Partitioner:
     """Reusable partitioner: the workspace is allocated once per size."""
 
-    def __init__(self, h: Hypergraph, prm: Params):
+    def __init__(self, h: Hypergraph, prm: Params, ws=None):
         torch = _torch()
         self.h, self.prm = h, prm
-        self.ws = _ws(OP_PARTITION, h, prm)
+        self.ws = _ws(OP_PARTITION, h, prm) if ws is None else ws
         self.part = torch.empty(h.n, dtype=torch.int32, device=h.device)
         self.f = torch.zeros(1, dtype=torch.int64, device=h.device)
         self._s = h.struct()
@@ -306,6 +356,18 @@ class Partitioner:
         _check(lib().hgp_partition(ctypes.byref(self._s), ctypes.byref(self.prm), _ptr(self.part), _ptr(self.f),
                                    ctypes.byref(lv), _ptr(self.ws), self.ws.numel(), _stream()), "hgp_partition")
         return int(lv.value)
+
+
+    def run_traced(self, cap: int = 256):
+        """One run through hgp_partition_traced; returns a list of per-level
+        dicts (n, m, p, lp_rounds), level 0 first."""
+        arr = {f: np.zeros(cap, np.uint32) for f in ("n", "m", "p", "lp_rounds")}
+        tr = _Trace(cap, 0, *[arr[f].ctypes.data for f in ("n", "m", "p", "lp_rounds")])
+        _check(lib().hgp_partition_traced(ctypes.byref(self._s), ctypes.byref(self.prm), _ptr(self.part),
+                                          _ptr(self.f), ctypes.byref(tr), _ptr(self.ws), self.ws.numel(),
+                                          _stream()), "hgp_partition_traced")
+        L = min(int(tr.levels) + 1, cap)
+        return [{f: int(arr[f][l]) for f in arr} for l in range(L)]
 
 
 def partition(h: Hypergraph, prm: Params):
@@ -382,7 +444,7 @@ class Server:
         obj = torch.zeros(1, dtype=torch.int64, device=h.device)
         s = h.struct()
         p = Params(prm.k, prm.eps_num, prm.eps_den, prm.seed, prm.limit_factor, prm.coarsen_subrounds,
-                   prm.lp_subrounds, prm.lp_rounds)
+                   prm.lp_subrounds, prm.lp_rounds, prm.flags)
         t = ctypes.c_uint64(0)
         _check(lib().hgp_server_submit(self._h, ctypes.byref(s), ctypes.byref(p), _ptr(part), _ptr(obj), _stream(),
                                        ctypes.byref(t)), "hgp_server_submit")

@@ -18,6 +18,7 @@ hgp_status check_params(const hgp_params *p) {
     if (p->limit_factor == 0 || p->limit_factor > (1u << 20)) return HGP_E_INVALID;
     if (p->coarsen_subrounds == 0 || p->lp_subrounds == 0) return HGP_E_INVALID;
     if (p->coarsen_subrounds > 256 || p->lp_subrounds > 256 || p->lp_rounds > 65535) return HGP_E_INVALID;
+    if (p->flags & ~HGP_TRUSTED_INPUT) return HGP_E_INVALID;
     return HGP_OK;
 }
 
@@ -79,6 +80,7 @@ hgp_status hgp_default_params(uint32_t k, hgp_params *out) {
     out->coarsen_subrounds = 3;
     out->lp_subrounds = 5;
     out->lp_rounds = 5;
+    out->flags = 0;
     return HGP_OK;
 }
 
@@ -102,6 +104,7 @@ hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p, const
             case HGP_OP_REFINE: need = refine_workspace(n, m, k); break;
             case HGP_OP_VALIDATE: need = util_workspace(n, m); break;
             case HGP_OP_INITIAL: need = ip_workspace(n, p, k); break;
+            case HGP_OP_GAINS: need = gaintable_workspace(n, m, k, n); break;
             case HGP_OP_PARTITION: {
                 size_t temp = std::max({coarsen_workspace(n, m, p, dp), contract_workspace(n, m, p),
                                         refine_workspace(n, m, k), ip_workspace(n, p, k), util_workspace(n, m)});
@@ -212,9 +215,11 @@ namespace {
 // FM / flows) on one hypergraph, scratch from A, work on st.  Syncs.  Throws
 // Error on workspace or device failures.
 hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part, int64_t *objective,
-                         uint32_t *levels_out, Arena &A, hipStream_t st) {
-    hgp_status v = validate(*h0, A, st);
-    if (v != HGP_OK) return v;
+                         uint32_t *levels_out, Arena &A, hipStream_t st, hgp_trace *trace = nullptr) {
+    if (!(prm->flags & HGP_TRUSTED_INPUT)) {
+        const hgp_status v = validate(*h0, A, st);
+        if (v != HGP_OK) return v;
+    }
     const int64_t W = total_weight(h0->vwgt, h0->n, A, st);  // c(V): the same on every level
     struct Level {
         hgp_hg h;
@@ -263,17 +268,29 @@ hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
     // initial partition and LP on the coarsest level
     hgp_hg cs = L.back().h;
     uint32_t *cpart = (nl == 0) ? part : A.alloc<uint32_t>(cs.n);
+    // per-level record: sizes, and the LP rounds run (host, caller's arrays)
+    auto rounds_of = [&](uint32_t l) -> uint32_t * {
+        return (trace && trace->lp_rounds && l < trace->cap) ? trace->lp_rounds + l : nullptr;
+    };
     initial_partition(cs, prm->k, cpart, A, st, W);
-    refine_lp(cs, *prm, nl, cpart, objective, nullptr, A, st, W);
+    refine_lp(cs, *prm, nl, cpart, objective, nullptr, A, st, W, rounds_of(nl));
     for (int l = (int)nl - 1; l >= 0; --l) {
         hgp_hg fh = L[l].h;
         uint32_t *fpart = (l == 0) ? part : A.alloc<uint32_t>(fh.n);
         project(fh.n, L[l].cid, cpart, fpart, st);
-        refine_lp(fh, *prm, (uint32_t)l, fpart, objective, nullptr, A, st, W);
+        refine_lp(fh, *prm, (uint32_t)l, fpart, objective, nullptr, A, st, W, rounds_of((uint32_t)l));
         cpart = fpart;
     }
     stream_sync(st);
     if (levels_out) *levels_out = nl;
+    if (trace) {
+        trace->levels = nl;
+        for (uint32_t l = 0; l <= nl && l < trace->cap; ++l) {
+            if (trace->n) trace->n[l] = L[l].h.n;
+            if (trace->m) trace->m[l] = L[l].h.m;
+            if (trace->p) trace->p[l] = L[l].h.p;
+        }
+    }
     return HGP_OK;
 }
 }  // namespace
@@ -290,6 +307,61 @@ hgp_status hgp_partition(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
     return guarded(st, [&]() -> hgp_status {
         Arena A(ws, ws_bytes);
         return partition_one(h0, prm, part, objective, levels_out, A, st);
+    });
+}
+
+hgp_status hgp_gain_table(const hgp_hg *h, uint32_t k, const uint32_t *part, int32_t *benefit, int32_t *penalty,
+                          void *ws, size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h);
+    if (s != HGP_OK) return s;
+    if (k < 2) return HGP_E_INVALID;
+    if (k > 256) return HGP_E_UNSUPPORTED;
+    if (!part || !benefit || !penalty || !ws) return HGP_E_INVALID;
+    return guarded(S(stream), [&]() {
+        Arena A(ws, ws_bytes);
+        gain_table(*h, k, part, benefit, penalty, A, S(stream));
+        return HGP_OK;
+    });
+}
+
+hgp_status hgp_gain_table_update(const hgp_hg *h, uint32_t k, uint32_t *part, const uint32_t *node,
+                                 const uint32_t *target, uint32_t count, int32_t *benefit, int32_t *penalty,
+                                 void *ws, size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h);
+    if (s != HGP_OK) return s;
+    if (k < 2) return HGP_E_INVALID;
+    if (k > 256) return HGP_E_UNSUPPORTED;
+    if (!part || !benefit || !penalty || !ws || (count && (!node || !target)) || count > h->n) return HGP_E_INVALID;
+    return guarded(S(stream), [&]() {
+        Arena A(ws, ws_bytes);
+        return gain_table_update(*h, k, part, node, target, count, benefit, penalty, A, S(stream));
+    });
+}
+
+hgp_status hgp_gain_recalc(const hgp_hg *h, uint32_t k, const uint32_t *part, const uint32_t *node,
+                           const uint32_t *target, uint32_t count, int64_t *gain, void *ws, size_t ws_bytes,
+                           void *stream) {
+    hgp_status s = check_hg(h);
+    if (s != HGP_OK) return s;
+    if (k < 2) return HGP_E_INVALID;
+    if (k > 256) return HGP_E_UNSUPPORTED;
+    if (!part || !ws || (count && (!node || !target || !gain)) || count > h->n) return HGP_E_INVALID;
+    return guarded(S(stream), [&]() {
+        Arena A(ws, ws_bytes);
+        return gain_recalc(*h, k, part, node, target, count, gain, A, S(stream));
+    });
+}
+
+hgp_status hgp_partition_traced(const hgp_hg *h0, const hgp_params *prm, uint32_t *part, int64_t *objective,
+                                hgp_trace *trace, void *ws, size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h0);
+    if (s == HGP_OK) s = check_params(prm);
+    if (s != HGP_OK) return s;
+    if (!part || !objective || !ws || !trace) return HGP_E_INVALID;
+    hipStream_t st = S(stream);
+    return guarded(st, [&]() -> hgp_status {
+        Arena A(ws, ws_bytes);
+        return partition_one(h0, prm, part, objective, nullptr, A, st, trace);
     });
 }
 

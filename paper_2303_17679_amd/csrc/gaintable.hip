@@ -1,0 +1,558 @@
+// Gain table of a partition (paper Sec. 6.2) and the gains of a move
+// sequence (Sec. 6.3, the parallel gain recalculation).
+//
+//  - benefit b(u) = w({e in I(u): Phi(e, Pi[u]) = 1}), penalty p(u, t) =
+//    w({e in I(u): Phi(e, t) = 0}); the gain of moving u to t is b(u) - p(u, t).
+//    Stored as int32 (every weight sum is below 2^31): benefit[n] and
+//    penalty[n * k], row u holding the k penalties of u.
+//  - The table is built from the connectivity sets of the nets: Lambda(e)
+//    (blocks with a pin of e) and Lambda1(e) (blocks with exactly one pin),
+//    k-bit sets computed once per call.  A group of V lanes takes a vertex
+//    (V = k rounded up to a power of two, at most a wave): the lanes load V
+//    incident nets at a time, and every lane adds the weights of the nets
+//    whose Lambda misses its block, so a row of penalties leaves as one
+//    coalesced store.
+//  - A batch of moves is applied net by net: the first mover to reach a net
+//    claims it (a per-net stamp) and compares Phi(e, .) before and after the
+//    batch; a block whose count crosses zero changes the penalty of every pin
+//    of e, a block whose count crosses one changes the benefit of its
+//    unmoved pins.  Integer atomics make the result independent of the order
+//    (it is the table of the new partition); the movers' benefits are
+//    recomputed afterwards, as in the paper.
+//  - The sequence gains follow the recalculation of Sec. 6.3 per claimed net:
+//    for each block, the first move into it and the last move out of it among
+//    the net's pins and the number of unmoved pins in it decide which moves
+//    remove the net from a block (+w) or add it to one (-w).
+//  Nets of up to SMALL_NET pins are handled by the claiming lane with
+//  quadratic loops over the pins; longer nets are listed and handled by a
+//  wave each with per-block counters in LDS.
+#include "kernels.h"
+#include "prims.h"
+
+namespace hgp {
+
+namespace {
+
+constexpr uint32_t SMALL_NET = 32;
+
+// Lambda and Lambda1 words of a net, from the blocks of its pins.
+template <int KW>
+__device__ inline void fold_block(uint32_t b, uint64_t *once, uint64_t *twice) {
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+        const uint64_t bit = ((uint32_t)q == (b >> 6)) ? (1ull << (b & 63)) : 0ull;
+        twice[q] |= once[q] & bit;
+        once[q] |= bit;
+    }
+}
+
+// Thread per net up to SMALL_NET pins; longer nets are listed for a wave each.
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_gt_conn(const uint32_t *pin_off, const uint32_t *pins, uint32_t m,
+                                                   const uint32_t *part, uint64_t *lam, uint64_t *lam1,
+                                                   uint32_t *longl, uint32_t *nlong) {
+    for (uint32_t e = blockIdx.x * BLOCK + threadIdx.x; e < m; e += gridDim.x * BLOCK) {
+        const uint32_t b = pin_off[e], len = pin_off[e + 1] - b;
+        if (len > SMALL_NET) {
+            longl[atomicAdd(nlong, 1u)] = e;
+            continue;
+        }
+        uint64_t once[KW], twice[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) { once[q] = 0; twice[q] = 0; }
+        for (uint32_t j = 0; j < len; ++j) fold_block<KW>(part[pins[b + j]], once, twice);
+#pragma unroll
+        for (int q = 0; q < KW; ++q) {
+            lam[(size_t)e * KW + q] = once[q];
+            lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
+        }
+    }
+}
+
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_gt_conn_long(const uint32_t *pin_off, const uint32_t *pins,
+                                                        const uint32_t *longl, const uint32_t *nlong,
+                                                        const uint32_t *part, uint64_t *lam, uint64_t *lam1) {
+    const uint32_t nl = *nlong, lane = __lane_id();
+    const uint32_t w0 = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE, nw = gridDim.x * (BLOCK / WAVE);
+    for (uint32_t i = w0; i < nl; i += nw) {
+        const uint32_t e = longl[i], b = pin_off[e], len = pin_off[e + 1] - b;
+        uint64_t once[KW], twice[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) { once[q] = 0; twice[q] = 0; }
+        for (uint32_t j = lane; j < len; j += WAVE) fold_block<KW>(part[pins[b + j]], once, twice);
+        // (once, twice) pairs combine as once = o1 | o2, twice = t1 | t2 | (o1 & o2)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                const uint64_t oo = __shfl_xor(once[q], o, WAVE), ot = __shfl_xor(twice[q], o, WAVE);
+                twice[q] |= ot | (once[q] & oo);
+                once[q] |= oo;
+            }
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                lam[(size_t)e * KW + q] = once[q];
+                lam1[(size_t)e * KW + q] = once[q] & ~twice[q];
+            }
+    }
+}
+
+// Groups of V lanes per vertex (V a power of two, V >= k when k <= 64, else
+// 64); lane l of a group owns blocks q * 64 + l (V = 64) or block l.
+template <int KW, int V>
+__global__ __launch_bounds__(BLOCK) void k_gt_rows(const uint32_t *inc_off, const uint32_t *inc, const int32_t *nwgt,
+                                                   const uint32_t *part, const uint64_t *lam, const uint64_t *lam1,
+                                                   uint32_t n, uint32_t k, int32_t *ben, int32_t *pen) {
+    constexpr uint32_t GPB = BLOCK / V;
+    const uint32_t l = threadIdx.x % V, gi = threadIdx.x / V, base = (threadIdx.x % WAVE) - l;
+    for (uint32_t u0 = blockIdx.x * GPB; u0 < n; u0 += gridDim.x * GPB) {
+        const uint32_t u = u0 + gi;
+        const bool act = u < n;  // uniform within the group
+        uint32_t j0 = 0, j1 = 0, s = 0;
+        if (act) { j0 = inc_off[u]; j1 = inc_off[u + 1]; s = part[u]; }
+        int64_t acc[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) acc[q] = 0;
+        int64_t bsum = 0, wsum = 0;
+        // groups of a wave run the same number of steps (the longest list)
+        uint32_t steps = (j1 - j0 + V - 1) / V;
+#pragma unroll
+        for (int o = V; o < WAVE; o <<= 1) {
+            const uint32_t x = __shfl_xor(steps, o, WAVE);
+            steps = x > steps ? x : steps;
+        }
+        for (uint32_t it = 0; it < steps; ++it) {
+            const uint32_t j = j0 + it * V + l;
+            // nets of this step in the fullest group of the wave
+            const uint32_t left = j1 - j0 > it * V ? j1 - j0 - it * V : 0u;
+            uint32_t lim = left < V ? left : V;
+#pragma unroll
+            for (int o = V; o < WAVE; o <<= 1) {
+                const uint32_t y = __shfl_xor(lim, o, WAVE);
+                lim = y > lim ? y : lim;
+            }
+            int32_t w = 0;
+            uint64_t x[KW];
+#pragma unroll
+            for (int q = 0; q < KW; ++q) x[q] = 0;
+            if (j < j1) {
+                const uint32_t e = inc[j];
+                w = nwgt[e];
+#pragma unroll
+                for (int q = 0; q < KW; ++q) x[q] = lam[(size_t)e * KW + q];
+                if ((s >> 6) < (uint32_t)KW && ((lam1[(size_t)e * KW + (s >> 6)] >> (s & 63)) & 1ull)) bsum += w;
+                wsum += w;
+            }
+            // every lane adds the nets whose Lambda holds its block
+            for (uint32_t c = 0; c < lim; ++c) {
+                const int32_t wc = __shfl(w, (int)(base + c), WAVE);
+#pragma unroll
+                for (int q = 0; q < KW; ++q) {
+                    const uint64_t xc = __shfl(x[q], (int)(base + c), WAVE);
+                    if ((xc >> (V == WAVE ? l : l & 63)) & 1ull) acc[q] += wc;
+                }
+            }
+        }
+#pragma unroll
+        for (int o = V / 2; o > 0; o >>= 1) {
+            bsum += __shfl_xor(bsum, o, WAVE);
+            wsum += __shfl_xor(wsum, o, WAVE);
+        }
+        if (act) {
+            if (l == 0) ben[u] = (int32_t)bsum;
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                const uint32_t t = (V == WAVE ? (uint32_t)q * 64 : 0u) + l;
+                if (t < k) pen[(size_t)u * k + t] = (int32_t)(wsum - acc[q]);
+            }
+        }
+    }
+}
+
+// Moves: idx[u] <- i for every node moved by move i (to a block other than
+// its own); err[0] <- 1 on a node out of range, a target out of range or a
+// node moved twice.  from[i] <- the node's block before the moves.
+__global__ __launch_bounds__(BLOCK) void k_gt_mark(const uint32_t *node, const uint32_t *target, uint32_t count,
+                                                   uint32_t n, uint32_t k, const uint32_t *part, uint32_t *idx,
+                                                   uint32_t *from, uint32_t *err) {
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+        const uint32_t u = node[i], t = target[i];
+        if (u >= n || t >= k || part[u] >= k) { atomicOr(err, 1u); from[i] = NONE; continue; }
+        const uint32_t prev = atomicCAS(&idx[u], NONE, i);
+        if (prev != NONE) { atomicOr(err, 1u); from[i] = NONE; continue; }
+        from[i] = part[u];
+    }
+}
+
+struct MoveView {
+    const uint32_t *idx;     // [n] move of the node or NONE
+    const uint32_t *target;  // [count]
+    const uint32_t *from;    // [count] block before the moves
+    const uint32_t *part;    // [n] blocks before the moves
+    // (moved, index) of v: a move to the node's own block is no move
+    __device__ bool moved(uint32_t v, uint32_t *i) const {
+        const uint32_t x = idx[v];
+        if (x == NONE || target[x] == from[x]) return false;
+        *i = x;
+        return true;
+    }
+    __device__ uint32_t old_block(uint32_t v) const { return part[v]; }
+    __device__ uint32_t new_block(uint32_t v) const {
+        uint32_t i;
+        return moved(v, &i) ? target[i] : part[v];
+    }
+};
+
+// Claims net e for the calling lane (first mover to reach it this call).
+__device__ inline bool claim(uint32_t *stamp, uint32_t e, uint32_t call) {
+    return atomicCAS(&stamp[e], 0u, call) == 0u;
+}
+
+// Table update of one claimed net of at most SMALL_NET pins.
+__device__ inline void update_small_net(const MoveView &M, const uint32_t *pins, uint32_t b, uint32_t len, int32_t w,
+                                        uint32_t k, int32_t *ben, int32_t *pen) {
+    for (uint32_t x = 0; x < len; ++x) {
+        const uint32_t vx = pins[b + x];
+        // the blocks that change: the old and the new block of a moved pin,
+        // each judged once (at its first occurrence among the pins)
+        uint32_t ix;
+        if (!M.moved(vx, &ix)) continue;
+        const uint32_t cand[2] = {M.from[ix], M.target[ix]};
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t blk = cand[c];
+            bool first = true;
+            uint32_t co = 0, cn = 0;
+            for (uint32_t y = 0; y < len; ++y) {
+                const uint32_t vy = pins[b + y];
+                uint32_t iy;
+                const bool my = M.moved(vy, &iy);
+                if (my && y < x && (M.from[iy] == blk || M.target[iy] == blk)) first = false;
+                if (my && y == x && c == 1 && M.from[iy] == blk) first = false;
+                co += M.old_block(vy) == blk;
+                cn += (my ? M.target[iy] : M.old_block(vy)) == blk;
+            }
+            if (!first) continue;
+            if ((co == 0) != (cn == 0)) {
+                const int32_t d = cn == 0 ? w : -w;
+                for (uint32_t y = 0; y < len; ++y) atomicAdd(&pen[(size_t)pins[b + y] * k + blk], d);
+            }
+            if ((co == 1) != (cn == 1)) {
+                const int32_t d = cn == 1 ? w : -w;
+                for (uint32_t y = 0; y < len; ++y) {
+                    const uint32_t vy = pins[b + y];
+                    uint32_t iy;
+                    if (!M.moved(vy, &iy) && M.old_block(vy) == blk) atomicAdd(&ben[vy], d);
+                }
+            }
+        }
+    }
+}
+
+// Gains of the moves among the pins of one claimed net of at most SMALL_NET
+// pins (the recalculation of Sec. 6.3 for this net).
+__device__ inline void recalc_small_net(const MoveView &M, const uint32_t *pins, uint32_t b, uint32_t len, int64_t w,
+                                        unsigned long long *gain) {
+    for (uint32_t x = 0; x < len; ++x) {
+        uint32_t i;
+        if (!M.moved(pins[b + x], &i)) continue;
+        const uint32_t s = M.from[i], t = M.target[i];
+        // over the net's pins: last move out of s and of t, first move into
+        // s and into t, unmoved pins in s and in t
+        int64_t last_out_s = -1, last_out_t = -1;
+        uint32_t first_in_s = NONE, first_in_t = NONE, un_s = 0, un_t = 0;
+        for (uint32_t y = 0; y < len; ++y) {
+            const uint32_t vy = pins[b + y];
+            uint32_t iy;
+            if (M.moved(vy, &iy)) {
+                const uint32_t fy = M.from[iy], ty = M.target[iy];
+                if (fy == s && (int64_t)iy > last_out_s) last_out_s = iy;
+                if (fy == t && (int64_t)iy > last_out_t) last_out_t = iy;
+                if (ty == s && iy < first_in_s) first_in_s = iy;
+                if (ty == t && iy < first_in_t) first_in_t = iy;
+            } else {
+                const uint32_t by = M.old_block(vy);
+                un_s += by == s;
+                un_t += by == t;
+            }
+        }
+        int64_t d = 0;
+        if (last_out_s == (int64_t)i && i < first_in_s && un_s == 0) d += w;
+        if (first_in_t == i && (int64_t)i > last_out_t && un_t == 0) d -= w;
+        if (d) atomicAdd(&gain[i], (unsigned long long)d);
+    }
+}
+
+// What a pass over the movers' nets does with each claimed net.
+enum NetOp : int { OP_UPDATE = 0, OP_RECALC = 1 };
+
+// Lane per move: the lane walks its node's nets and handles every net it
+// claims (small nets at once, long nets listed).
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_gt_nets(MoveView M, const uint32_t *node, uint32_t count,
+                                                   const uint32_t *inc_off, const uint32_t *inc,
+                                                   const uint32_t *pin_off, const uint32_t *pins,
+                                                   const int32_t *nwgt, uint32_t k, uint32_t *stamp, uint32_t call,
+                                                   uint32_t *longl, uint32_t *nlong, int32_t *ben, int32_t *pen,
+                                                   unsigned long long *gain) {
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+        const uint32_t u = node[i];
+        uint32_t iu;
+        if (M.from[i] == NONE || !M.moved(u, &iu)) continue;
+        for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) {
+            const uint32_t e = inc[j];
+            if (!claim(stamp, e, call)) continue;
+            const uint32_t b = pin_off[e], len = pin_off[e + 1] - b;
+            if (len > SMALL_NET) {
+                longl[atomicAdd(nlong, 1u)] = e;
+                continue;
+            }
+            if (OP == OP_UPDATE) update_small_net(M, pins, b, len, nwgt[e], k, ben, pen);
+            else recalc_small_net(M, pins, b, len, nwgt[e], gain);
+        }
+    }
+}
+
+// Wave per listed long net, per-block counters in LDS.
+constexpr int LW = BLOCK / WAVE;
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_gt_long(MoveView M, const uint32_t *longl, const uint32_t *nlong,
+                                                   const uint32_t *pin_off, const uint32_t *pins,
+                                                   const int32_t *nwgt, uint32_t k, int32_t *ben, int32_t *pen,
+                                                   unsigned long long *gain) {
+    // per wave: old and new pin counts (update) or first-in, last-out and
+    // unmoved counts (recalculation) of every block
+    __shared__ uint32_t A0[LW][256], A1[LW][256], A2[LW][256];
+    const uint32_t wv = threadIdx.x / WAVE, lane = __lane_id();
+    const uint32_t nl = *nlong;
+    for (uint32_t li = blockIdx.x * LW + wv; li < nl; li += gridDim.x * LW) {
+        const uint32_t e = longl[li], b = pin_off[e], len = pin_off[e + 1] - b;
+        const int32_t w = nwgt[e];
+        for (uint32_t t = lane; t < k; t += WAVE) {
+            A0[wv][t] = OP == OP_UPDATE ? 0u : NONE;  // first in
+            A1[wv][t] = 0u;                           // last out + 1
+            A2[wv][t] = 0u;
+        }
+        wave_sync();
+        for (uint32_t y = lane; y < len; y += WAVE) {
+            const uint32_t v = pins[b + y];
+            uint32_t i;
+            const bool mv = M.moved(v, &i);
+            const uint32_t ob = M.old_block(v);
+            if (ob >= k) continue;  // blocks are < k (precondition)
+            if (OP == OP_UPDATE) {
+                atomicAdd(&A0[wv][ob], 1u);
+                atomicAdd(&A1[wv][mv ? M.target[i] : ob], 1u);
+            } else if (mv) {
+                atomicMin(&A0[wv][M.target[i]], i);
+                atomicMax(&A1[wv][M.from[i]], i + 1);
+            } else {
+                atomicAdd(&A2[wv][ob], 1u);
+            }
+        }
+        wave_sync();
+        if (OP == OP_UPDATE) {
+            // penalties: blocks whose count crosses zero, for every pin
+            for (uint32_t t = 0; t < k; ++t) {
+                const uint32_t co = A0[wv][t], cn = A1[wv][t];
+                if ((co == 0) != (cn == 0)) {
+                    const int32_t d = cn == 0 ? w : -w;
+                    for (uint32_t y = lane; y < len; y += WAVE) atomicAdd(&pen[(size_t)pins[b + y] * k + t], d);
+                }
+            }
+            // benefits of unmoved pins whose block's count crosses one
+            for (uint32_t y = lane; y < len; y += WAVE) {
+                const uint32_t v = pins[b + y];
+                uint32_t i;
+                if (M.moved(v, &i)) continue;
+                const uint32_t c = M.old_block(v);
+                if (c >= k) continue;
+                const uint32_t co = A0[wv][c], cn = A1[wv][c];
+                if ((co == 1) != (cn == 1)) atomicAdd(&ben[v], cn == 1 ? w : -w);
+            }
+        } else {
+            for (uint32_t y = lane; y < len; y += WAVE) {
+                uint32_t i;
+                if (!M.moved(pins[b + y], &i)) continue;
+                const uint32_t s = M.from[i], t = M.target[i];
+                int64_t d = 0;
+                if (A1[wv][s] == i + 1 && i < A0[wv][s] && A2[wv][s] == 0) d += w;
+                if (A0[wv][t] == i && (A1[wv][t] == 0 || i + 1 > A1[wv][t]) && A2[wv][t] == 0) d -= w;
+                if (d) atomicAdd(&gain[i], (unsigned long long)d);
+            }
+        }
+        wave_sync();  // the counters are cleared for the next net
+    }
+}
+
+// Benefit of every mover in its new block, from the new pin counts of its nets.
+__global__ __launch_bounds__(BLOCK) void k_gt_mover_benefit(MoveView M, const uint32_t *node, uint32_t count,
+                                                            const uint32_t *inc_off, const uint32_t *inc,
+                                                            const uint32_t *pin_off, const uint32_t *pins,
+                                                            const int32_t *nwgt, int32_t *ben) {
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+        const uint32_t u = node[i];
+        uint32_t iu;
+        if (M.from[i] == NONE || !M.moved(u, &iu)) continue;
+        const uint32_t t = M.target[i];
+        int64_t bsum = 0;
+        for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) {
+            const uint32_t e = inc[j];
+            uint32_t c = 0;
+            for (uint32_t q = pin_off[e]; q < pin_off[e + 1] && c < 2; ++q) c += M.new_block(pins[q]) == t;
+            if (c == 1) bsum += nwgt[e];
+        }
+        ben[u] = (int32_t)bsum;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gt_apply(MoveView M, const uint32_t *node, uint32_t count,
+                                                    uint32_t *part) {
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+        uint32_t iu;
+        if (M.from[i] != NONE && M.moved(node[i], &iu)) part[node[i]] = M.target[i];
+    }
+}
+
+struct GtBufs {
+    uint64_t *lam, *lam1;
+    uint32_t *idx, *from, *stamp, *longl, *scal;
+};
+
+void plan_table(Arena &A, uint32_t m, uint32_t k, GtBufs &B) {
+    const size_t kw = (k + 63) / 64;
+    B.lam = A.alloc<uint64_t>((size_t)m * kw);
+    B.lam1 = A.alloc<uint64_t>((size_t)m * kw);
+    B.longl = A.alloc<uint32_t>(m);
+    B.scal = A.alloc<uint32_t>(64);
+}
+
+void plan_moves(Arena &A, uint32_t n, uint32_t m, uint32_t count, GtBufs &B) {
+    B.idx = A.alloc<uint32_t>(n);
+    B.from = A.alloc<uint32_t>(count);
+    B.stamp = A.alloc<uint32_t>(m);
+    B.longl = A.alloc<uint32_t>(m);
+    B.scal = A.alloc<uint32_t>(64);
+}
+
+template <int KW, int V>
+void launch_rows(const hgp_hg &h, uint32_t k, const uint32_t *part, const GtBufs &B, int32_t *ben, int32_t *pen,
+                 hipStream_t st) {
+    k_gt_rows<KW, V><<<grid_for(h.n, BLOCK / V, 8 * FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, h.nwgt, part,
+                                                                                  B.lam, B.lam1, h.n, k, ben, pen);
+    HGP_LAUNCH_CHECK();
+}
+
+template <int KW>
+void table_t(const hgp_hg &h, uint32_t k, const uint32_t *part, int32_t *ben, int32_t *pen, Arena &A,
+             hipStream_t st) {
+    size_t mk = A.mark();
+    GtBufs B{};
+    plan_table(A, h.m, k, B);
+    if (A.measure) { A.release(mk); return; }
+    uint32_t *nlong = B.scal;
+    fill<uint32_t>(B.scal, 64, 0u, st);
+    if (h.m) {
+        k_gt_conn<KW><<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.pins, h.m, part, B.lam,
+                                                                           B.lam1, B.longl, nlong);
+        HGP_LAUNCH_CHECK();
+        k_gt_conn_long<KW><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(h.pin_off, h.pins, B.longl, nlong, part, B.lam,
+                                                              B.lam1);
+        HGP_LAUNCH_CHECK();
+    }
+    if (KW > 1 || k > 32) launch_rows<KW, 64>(h, k, part, B, ben, pen, st);
+    else if (k > 16) launch_rows<1, 32>(h, k, part, B, ben, pen, st);
+    else if (k > 8) launch_rows<1, 16>(h, k, part, B, ben, pen, st);
+    else if (k > 4) launch_rows<1, 8>(h, k, part, B, ben, pen, st);
+    else launch_rows<1, 4>(h, k, part, B, ben, pen, st);
+    A.release(mk);
+}
+
+// Marks the moves and checks them; returns false on invalid moves.  Syncs.
+bool mark_moves(const hgp_hg &h, uint32_t k, const uint32_t *part, const uint32_t *node, const uint32_t *target,
+                uint32_t count, const GtBufs &B, hipStream_t st) {
+    fill<uint32_t>(B.idx, h.n, NONE, st);
+    fill<uint32_t>(B.stamp, h.m, 0u, st);
+    fill<uint32_t>(B.scal, 64, 0u, st);
+    k_gt_mark<<<grid_for(count, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(node, target, count, h.n, k, part, B.idx,
+                                                                     B.from, B.scal + 1);
+    HGP_LAUNCH_CHECK();
+    uint32_t err = 0;
+    HGP_CHECK_HIP(hipMemcpyAsync(&err, B.scal + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    stream_sync(st);
+    return err == 0;
+}
+
+}  // namespace
+
+size_t gaintable_workspace(uint32_t n, uint32_t m, uint32_t k, uint32_t count) {
+    Arena A(nullptr, 0);
+    GtBufs B{};
+    plan_table(A, m, k, B);
+    size_t a = A.peak;
+    Arena C(nullptr, 0);
+    plan_moves(C, n, m, count, B);
+    return a > C.peak ? a : C.peak;
+}
+
+void gain_table(const hgp_hg &h, uint32_t k, const uint32_t *part, int32_t *ben, int32_t *pen, Arena &A,
+                hipStream_t st) {
+    switch ((k + 63) / 64) {
+        case 1: table_t<1>(h, k, part, ben, pen, A, st); break;
+        case 2: table_t<2>(h, k, part, ben, pen, A, st); break;
+        case 3: table_t<3>(h, k, part, ben, pen, A, st); break;
+        default: table_t<4>(h, k, part, ben, pen, A, st); break;
+    }
+}
+
+hgp_status gain_table_update(const hgp_hg &h, uint32_t k, uint32_t *part, const uint32_t *node,
+                             const uint32_t *target, uint32_t count, int32_t *ben, int32_t *pen, Arena &A,
+                             hipStream_t st) {
+    size_t mk = A.mark();
+    GtBufs B{};
+    plan_moves(A, h.n, h.m, count, B);
+    if (A.measure || count == 0) { A.release(mk); return HGP_OK; }
+    if (!mark_moves(h, k, part, node, target, count, B, st)) { A.release(mk); return HGP_E_INVALID; }
+    const MoveView M{B.idx, target, B.from, part};
+    uint32_t *nlong = B.scal;
+    const unsigned g = grid_for(count, BLOCK, FILL_BLOCKS);
+    k_gt_nets<OP_UPDATE><<<g, BLOCK, 0, st>>>(M, node, count, h.inc_off, h.inc, h.pin_off, h.pins, h.nwgt, k,
+                                              B.stamp, 1u, B.longl, nlong, ben, pen, nullptr);
+    HGP_LAUNCH_CHECK();
+    k_gt_long<OP_UPDATE><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(M, B.longl, nlong, h.pin_off, h.pins, h.nwgt, k, ben,
+                                                            pen, nullptr);
+    HGP_LAUNCH_CHECK();
+    k_gt_mover_benefit<<<g, BLOCK, 0, st>>>(M, node, count, h.inc_off, h.inc, h.pin_off, h.pins, h.nwgt, ben);
+    HGP_LAUNCH_CHECK();
+    k_gt_apply<<<g, BLOCK, 0, st>>>(M, node, count, part);
+    HGP_LAUNCH_CHECK();
+    stream_sync(st);
+    A.release(mk);
+    return HGP_OK;
+}
+
+hgp_status gain_recalc(const hgp_hg &h, uint32_t k, const uint32_t *part, const uint32_t *node,
+                       const uint32_t *target, uint32_t count, int64_t *gain, Arena &A, hipStream_t st) {
+    size_t mk = A.mark();
+    GtBufs B{};
+    plan_moves(A, h.n, h.m, count, B);
+    if (A.measure || count == 0) { A.release(mk); return HGP_OK; }
+    if (!mark_moves(h, k, part, node, target, count, B, st)) { A.release(mk); return HGP_E_INVALID; }
+    const MoveView M{B.idx, target, B.from, part};
+    uint32_t *nlong = B.scal;
+    HGP_CHECK_HIP(hipMemsetAsync(gain, 0, sizeof(int64_t) * count, st));
+    const unsigned g = grid_for(count, BLOCK, FILL_BLOCKS);
+    k_gt_nets<OP_RECALC><<<g, BLOCK, 0, st>>>(M, node, count, h.inc_off, h.inc, h.pin_off, h.pins, h.nwgt, k,
+                                              B.stamp, 1u, B.longl, nlong, nullptr, nullptr,
+                                              (unsigned long long *)gain);
+    HGP_LAUNCH_CHECK();
+    k_gt_long<OP_RECALC><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(M, B.longl, nlong, h.pin_off, h.pins, h.nwgt, k,
+                                                            nullptr, nullptr, (unsigned long long *)gain);
+    HGP_LAUNCH_CHECK();
+    stream_sync(st);
+    A.release(mk);
+    return HGP_OK;
+}
+
+}  // namespace hgp

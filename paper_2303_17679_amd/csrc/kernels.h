@@ -27,12 +27,23 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
 size_t refine_workspace(uint32_t n, uint32_t m, uint32_t k);
 void objective(const hgp_hg &h, uint32_t k, const uint32_t *part, int64_t *obj, int64_t *bw, Arena &A,
                hipStream_t st);
+// rounds_out (host, may be null): LP rounds run on the level.
 void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj, int64_t *bw,
-               Arena &A, hipStream_t st, int64_t W_known = -1);
+               Arena &A, hipStream_t st, int64_t W_known = -1, uint32_t *rounds_out = nullptr);
 
 // ip.hip
 size_t ip_workspace(uint32_t n, uint32_t p, uint32_t k);
 void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st, int64_t W_known = -1);
 void project(uint32_t n, const uint32_t *cid, const uint32_t *cpart, uint32_t *part, hipStream_t st);
+
+// gaintable.hip
+size_t gaintable_workspace(uint32_t n, uint32_t m, uint32_t k, uint32_t count);
+void gain_table(const hgp_hg &h, uint32_t k, const uint32_t *part, int32_t *ben, int32_t *pen, Arena &A,
+                hipStream_t st);
+hgp_status gain_table_update(const hgp_hg &h, uint32_t k, uint32_t *part, const uint32_t *node,
+                             const uint32_t *target, uint32_t count, int32_t *ben, int32_t *pen, Arena &A,
+                             hipStream_t st);
+hgp_status gain_recalc(const hgp_hg &h, uint32_t k, const uint32_t *part, const uint32_t *node,
+                       const uint32_t *target, uint32_t count, int64_t *gain, Arena &A, hipStream_t st);
 
 }  // namespace hgp

@@ -1414,7 +1414,7 @@ void objective(const hgp_hg &h, uint32_t k, const uint32_t *part, int64_t *obj, 
 
 template <int KW>
 static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj,
-                     int64_t *bw_out, Arena &A, hipStream_t st, int64_t W_known) {
+                     int64_t *bw_out, Arena &A, hipStream_t st, int64_t W_known, uint32_t *rounds_out) {
     const uint32_t n = h.n, m = h.m, k = prm.k;
     size_t mk = A.mark();
     RefineBufs B;
@@ -1663,13 +1663,15 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const uint32_t R = std::min<uint32_t>(prm.lp_rounds, LP_MAX_ROUNDS);
     uint32_t r0 = 0, s0 = 0;  // next sub-round to queue
     uint32_t batch = LP_ROUND_BATCH;
+    uint32_t rounds_run = 0;
     while (r0 < R) {
         const uint32_t r1 = std::min<uint32_t>(R, r0 + batch);
         for (uint32_t r = r0; r < r1; ++r)
             for (uint32_t s = (r == r0 ? s0 : 0); s < S; ++s) subround(r, s);
-        uint32_t hv[2];
+        uint32_t hv[1 + LP_ROUND_BATCH];
         HGP_CHECK_HIP(hipMemcpyAsync(&hv[0], abort, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        HGP_CHECK_HIP(hipMemcpyAsync(&hv[1], B.rmoves + r1 - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HGP_CHECK_HIP(hipMemcpyAsync(&hv[1], B.rmoves + r0, sizeof(uint32_t) * (r1 - r0), hipMemcpyDeviceToHost,
+                                     st));
         stream_sync(st);
         if (hv[0]) {
             // sub-round hv[0] handed pairs to the device-wide path: finish it
@@ -1684,10 +1686,17 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             batch = 1;
             continue;
         }
-        if (hv[1] == 0) break;  // the batch ended with a round without moves
+        // a round without moves ends LP (the rounds after it did nothing)
+        bool stop = false;
+        for (uint32_t r = r0; r < r1 && !stop; ++r) {
+            rounds_run = r + 1;
+            stop = hv[1 + (r - r0)] == 0;
+        }
+        if (stop) break;
         r0 = r1;
         s0 = 0;
     }
+    if (rounds_out) *rounds_out = rounds_run;
     // the last sub-round's block-weight changes
     k_add_dbw<<<1, 256, 0, st>>>(B.bw, B.dbw_g, k);
     HGP_LAUNCH_CHECK();
@@ -1701,12 +1710,12 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
 }
 
 void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj, int64_t *bw,
-               Arena &A, hipStream_t st, int64_t W_known) {
+               Arena &A, hipStream_t st, int64_t W_known, uint32_t *rounds_out) {
     switch ((prm.k + 63) / 64) {
-        case 1: refine_t<1>(h, prm, level, part, obj, bw, A, st, W_known); break;
-        case 2: refine_t<2>(h, prm, level, part, obj, bw, A, st, W_known); break;
-        case 3: refine_t<3>(h, prm, level, part, obj, bw, A, st, W_known); break;
-        default: refine_t<4>(h, prm, level, part, obj, bw, A, st, W_known); break;
+        case 1: refine_t<1>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out); break;
+        case 2: refine_t<2>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out); break;
+        case 3: refine_t<3>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out); break;
+        default: refine_t<4>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out); break;
     }
 }
 

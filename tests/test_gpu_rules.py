@@ -68,3 +68,39 @@ def test_pass_cut_boundary_cases(hgp, orc):
         rep, cnt = hgp.coarsen(G, hgp.params(2, seed=seed, limit_factor=1, coarsen_subrounds=sc), 0)
         assert cnt == cnt_o
         assert np.array_equal(rep.cpu().numpy().view(np.uint32), rep_o)
+
+
+def test_trusted_input_flag_gives_the_same_result(hgp, orc):
+    h = W.random_uniform(4000, 4000, 2, 8, seed=12)
+    G = hgp.Hypergraph.from_host(h)
+    assert hgp.validate(G) == 0
+    a = hgp.partition(G, hgp.params(4, seed=3))
+    b = hgp.partition(G, hgp.params(4, seed=3, trusted=True))
+    part_o, f_o, L_o = orc.partition(h, orc.params(4, seed=3))
+    for part, f, L in (a, b):
+        assert (f, L) == (f_o, L_o)
+        assert np.array_equal(part.cpu().numpy().view(np.uint32), part_o)
+
+
+def test_partition_workspace_too_small_for_the_hierarchy(hgp, orc):
+    # a workspace smaller than one stored level: hgp_partition returns
+    # HGP_E_WORKSPACE with its work drained, and the same output buffers then
+    # give the oracle's result with a workspace of the documented size
+    import torch
+    H = hgp
+    h = W.workload("stencil24")[0]
+    k = 8
+    G = H.Hypergraph.from_host(h)
+    prm = H.params(k, seed=2)
+    part_o, f_o, L_o = orc.partition(h, orc.params(k, seed=2))
+    assert L_o >= 3
+    level = 4 * (2 * G.m + 2 * G.p + 4 * G.n + 2)
+    small = torch.empty(level // 2, dtype=torch.uint8, device="cuda")
+    P = H.Partitioner(G, prm, ws=small)
+    with pytest.raises(H.HGPError) as ei:
+        P.run()
+    assert ei.value.status == -3  # HGP_E_WORKSPACE
+    P.ws = torch.empty(H.workspace_bytes(H.OP_PARTITION, G.n, G.m, G.p, prm), dtype=torch.uint8, device="cuda")
+    L = P.run()
+    assert (L, int(P.f.item())) == (L_o, f_o)
+    assert np.array_equal(P.part.cpu().numpy().view(np.uint32), part_o)
