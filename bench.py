@@ -34,6 +34,9 @@ WORKLOADS = {
     "batch": "4096 VLSI-like hypergraphs, seed 4: n log-uniform in [1e3, 2e5], m = 1.1 n, net size "
              "2+Geometric(0.4) capped at 50, 90% of pins within a 256-ID window around the net's anchor, vertex "
              "weights in [1,10], k uniform in {2,4,8}, eps=0.03; all partitioned by one hgp_partition_batch call",
+    "gaintable": "gain table of the 160^3 row-net stencil (k=64) for its multilevel partition: build "
+                 "benefit and penalty rows (n x k), gains of a sequence of moves of 1% of the vertices "
+                 "(seeded random nodes and targets), and the table update for those moves",
     "serve": "Poisson stream of partition requests, seed 5: sizes log-uniform in [1e4, 1e7] pins, family uniform "
              "over {random, power-law, stencil, R-MAT}, k uniform in {2..64}, eps=0.03, admitted by workspace "
              "footprint into a continuous-admission server; arrival rate 0.8 x the measured saturation rate",
@@ -198,6 +201,95 @@ def run_serve(args):
     }
 
 
+def run_gaintable(args):
+    """Gain table (Sec. 6.2) and move-sequence gains (Sec. 6.3) on the
+    stencil's own multilevel partition.  One step = build the table, compute
+    the gains of a sequence of moves of 1% of the vertices, and apply the
+    moves with the table update; steps alternate between the moves and
+    their reversal, so every step does the same work."""
+    import numpy as np
+    import torch
+    import paper_2303_17679_amd as H
+    h, k = W.workload("stencil160")
+    G = H.Hypergraph.from_host(h)
+    if H.validate(G) != 0:
+        raise SystemExit("stencil160: input failed hgp_validate")
+    P = H.Partitioner(G, H.params(k, seed=args.seed, trusted=True))
+    P.run()
+    part0 = P.part.cpu().numpy().view(np.uint32).copy()
+    count = h.n // 100
+    us, ts = W.move_sequence(h.n, k, part0, count, seed=6)
+    back = part0[us].copy()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).cuda()
+    node, fwd, rev = dev(us), dev(ts), dev(back)
+    ws = torch.empty(H.workspace_bytes(H.OP_GAINS, G.n, G.m, G.p, H.params(k)), dtype=torch.uint8, device="cuda")
+    t = dev(part0)
+    del P
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    spent = [0.0, 0.0, 0.0]
+
+    def step(i, timed):
+        tgt = fwd if i % 2 == 0 else rev
+        ev[0].record()
+        ben, pen = H.gain_table(G, k, t, ws=ws)
+        ev[1].record()
+        g = H.gain_recalc(G, k, t, node, tgt, ws=ws)
+        ev[2].record()
+        H.gain_table_update(G, k, t, node, tgt, ben, pen, ws=ws)
+        ev[3].record()
+        if timed:
+            torch.cuda.synchronize()
+            for j in range(3):
+                spent[j] += ev[j].elapsed_time(ev[j + 1])
+        return ben, pen, g
+
+    for i in range(args.warmup + (args.warmup % 2)):  # an even count: back at the partition
+        step(i, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = args.steps + (args.steps % 2)
+    for i in range(steps):
+        ben, pen, g = step(i, True)
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / steps
+    # compulsory bytes of one table build: offsets, incidence lists, each
+    # net's weight and two k-bit sets, the blocks, and the benefit and
+    # penalty rows written
+    kw = (k + 63) // 64
+    table_bytes = 4 * (h.n + 1) + 4 * h.p + h.m * (4 + 16 * kw) + 4 * h.n + 4 * h.n + 4 * h.n * k
+    t_table = spent[0] / 1e3 / steps
+    achieved = table_bytes / t_table / 1e9
+    cpu = None
+    match = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        t1 = time.perf_counter()
+        b_o, p_o = oracle.gain_table(h, k, part0)
+        g_o = oracle.gain_recalc(h, k, part0, us, ts)
+        To = time.perf_counter() - t1
+        # after an even number of steps the table is that of part0 again
+        match = bool(np.array_equal(ben.cpu().numpy(), b_o) and np.array_equal(pen.cpu().numpy(), p_o))
+        model, ncpu = cpu_info()
+        cpu = {"value": h.p / To, "unit": "pins/s", "cores": 1, "kind": "oracle",
+               "sample": f"gain table of the whole stencil160 partition plus the gains of the {count} moves, "
+                         f"one run, single thread, {To:.1f} s (the table update is not timed on the CPU)",
+               "host_cpu": model, "host_threads": ncpu}
+    return {
+        "metric": "pins/s for gain table build + move-sequence gains + table update",
+        "value": h.p / T, "unit": "pins/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * T, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32/int64 (integer only)", "data": "synthetic",
+        "config": {"workload": "gaintable", "description": WORKLOADS["gaintable"], "k": k, "n": h.n, "m": h.m,
+                   "pins": h.p, "moves": count, "parallelism": "single GPU"},
+        "phase_ms": {"table": spent[0] / steps, "sequence_gains": spent[1] / steps, "update": spent[2] / steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                     "traffic": None, "kernel": "hgp_gain_table (k_gt_conn + k_gt_rows)",
+                     "alg_bytes_per_launch": table_bytes, "avg_launch_us": t_table * 1e6},
+        "cpu_baseline": cpu, "oracle_match": match,
+    }
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC runs
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
@@ -275,6 +367,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "gaintable":
+        print(json.dumps(run_gaintable(args)), flush=True)
+        return
     if args.workload in ("batch", "serve"):
         if args.count is None:
             args.count = 4096 if args.workload == "batch" else 200

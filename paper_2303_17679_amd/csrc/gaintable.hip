@@ -7,11 +7,10 @@
 //    penalty[n * k], row u holding the k penalties of u.
 //  - The table is built from the connectivity sets of the nets: Lambda(e)
 //    (blocks with a pin of e) and Lambda1(e) (blocks with exactly one pin),
-//    k-bit sets computed once per call.  A group of V lanes takes a vertex
-//    (V = k rounded up to a power of two, at most a wave): the lanes load V
-//    incident nets at a time, and every lane adds the weights of the nets
-//    whose Lambda misses its block, so a row of penalties leaves as one
-//    coalesced store.
+//    k-bit sets computed once per call.  A wave takes batches of consecutive
+//    vertices whose nets fill its 64 lanes (all loads of a batch at once),
+//    and every lane adds the weights of a vertex's nets whose Lambda holds
+//    its block, so a row of penalties leaves as one coalesced store.
 //  - A batch of moves is applied net by net: the first mover to reach a net
 //    claims it (a per-net stamp) and compares Phi(e, .) before and after the
 //    batch; a block whose count crosses zero changes the penalty of every pin
@@ -28,6 +27,8 @@
 //  wave each with per-block counters in LDS.
 #include "kernels.h"
 #include "prims.h"
+
+#include <algorithm>
 
 namespace hgp {
 
@@ -99,75 +100,143 @@ __global__ __launch_bounds__(BLOCK) void k_gt_conn_long(const uint32_t *pin_off,
     }
 }
 
-// Groups of V lanes per vertex (V a power of two, V >= k when k <= 64, else
-// 64); lane l of a group owns blocks q * 64 + l (V = 64) or block l.
-template <int KW, int V>
+// Wave-uniform reads of lane c's registers (c uniform): no LDS traffic.
+__device__ inline int32_t lane_i32(int32_t v, uint32_t c) { return __builtin_amdgcn_readlane(v, (int)c); }
+__device__ inline uint64_t lane_u64(uint64_t v, uint32_t c) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)c);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)c);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// A wave per contiguous range of vertices.  Each step takes the next batch
+// of consecutive vertices whose incident nets fit the 64 lanes (one net per
+// lane: its weight, its Lambda words and the Lambda1 bit of its vertex's
+// block, all loaded at once), then writes the batch's rows one vertex after
+// the other: lane l owns blocks q * 64 + l and adds the weights of the
+// vertex's nets whose Lambda holds its block (wave-uniform register reads),
+// so every row leaves as one coalesced store.  A vertex of more than 64 nets
+// is a batch of its own, walked 64 nets at a time.
+template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_gt_rows(const uint32_t *inc_off, const uint32_t *inc, const int32_t *nwgt,
                                                    const uint32_t *part, const uint64_t *lam, const uint64_t *lam1,
                                                    uint32_t n, uint32_t k, int32_t *ben, int32_t *pen) {
-    constexpr uint32_t GPB = BLOCK / V;
-    const uint32_t l = threadIdx.x % V, gi = threadIdx.x / V, base = (threadIdx.x % WAVE) - l;
-    for (uint32_t u0 = blockIdx.x * GPB; u0 < n; u0 += gridDim.x * GPB) {
-        const uint32_t u = u0 + gi;
-        const bool act = u < n;  // uniform within the group
-        uint32_t j0 = 0, j1 = 0, s = 0;
-        if (act) { j0 = inc_off[u]; j1 = inc_off[u + 1]; s = part[u]; }
-        int64_t acc[KW];
-#pragma unroll
-        for (int q = 0; q < KW; ++q) acc[q] = 0;
-        int64_t bsum = 0, wsum = 0;
-        // groups of a wave run the same number of steps (the longest list)
-        uint32_t steps = (j1 - j0 + V - 1) / V;
-#pragma unroll
-        for (int o = V; o < WAVE; o <<= 1) {
-            const uint32_t x = __shfl_xor(steps, o, WAVE);
-            steps = x > steps ? x : steps;
+    const uint32_t lane = __lane_id();
+    const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nwv = gridDim.x * (BLOCK / WAVE);
+    const uint32_t per = (uint32_t)(((uint64_t)n + nwv - 1) / nwv);
+    uint32_t u = (uint32_t)min((uint64_t)wid * per, (uint64_t)n);
+    const uint32_t uend = (uint32_t)min((uint64_t)u + per, (uint64_t)n);
+    while (u < uend) {  // uniform per wave
+        // degrees of the next 64 vertices and their inclusive prefix
+        const uint32_t cand = u + lane;
+        uint32_t o = 0, d = 0, blk = 0;
+        if (cand < uend) {
+            o = inc_off[cand];
+            d = inc_off[cand + 1] - o;
+            blk = part[cand];
         }
-        for (uint32_t it = 0; it < steps; ++it) {
-            const uint32_t j = j0 + it * V + l;
-            // nets of this step in the fullest group of the wave
-            const uint32_t left = j1 - j0 > it * V ? j1 - j0 - it * V : 0u;
-            uint32_t lim = left < V ? left : V;
+        uint32_t pre = d;
 #pragma unroll
-            for (int o = V; o < WAVE; o <<= 1) {
-                const uint32_t y = __shfl_xor(lim, o, WAVE);
-                lim = y > lim ? y : lim;
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const uint32_t t = __shfl_up(pre, off, WAVE);
+            if (lane >= (uint32_t)off) pre += t;
+        }
+        const uint64_t fit = __ballot(cand < uend && pre <= WAVE);  // a prefix of the lanes
+        const uint32_t nb = (uint32_t)__popcll(fit);
+        if (nb == 0) {
+            // one vertex of more than 64 nets
+            const uint32_t j0 = lane_i32((int32_t)o, 0), j1 = j0 + lane_i32((int32_t)d, 0);
+            const uint32_t s = (uint32_t)lane_i32((int32_t)blk, 0);
+            int64_t acc[KW];
+#pragma unroll
+            for (int q = 0; q < KW; ++q) acc[q] = 0;
+            int64_t bsum = 0, wsum = 0;
+            for (uint32_t c0 = j0; c0 < j1; c0 += WAVE) {
+                const uint32_t j = c0 + lane;
+                int32_t w = 0, bw = 0;
+                uint64_t x[KW];
+#pragma unroll
+                for (int q = 0; q < KW; ++q) x[q] = 0;
+                if (j < j1) {
+                    const uint32_t e = inc[j];
+                    w = nwgt[e];
+#pragma unroll
+                    for (int q = 0; q < KW; ++q) x[q] = lam[(size_t)e * KW + q];
+                    if ((s >> 6) < (uint32_t)KW && ((lam1[(size_t)e * KW + (s >> 6)] >> (s & 63)) & 1ull)) bw = w;
+                }
+                const uint32_t cn = j1 - c0 < WAVE ? j1 - c0 : WAVE;
+                for (uint32_t c = 0; c < cn; ++c) {
+                    const int32_t wc = lane_i32(w, c);
+                    wsum += wc;
+                    bsum += lane_i32(bw, c);
+#pragma unroll
+                    for (int q = 0; q < KW; ++q)
+                        if ((lane_u64(x[q], c) >> lane) & 1ull) acc[q] += wc;
+                }
             }
-            int32_t w = 0;
-            uint64_t x[KW];
 #pragma unroll
-            for (int q = 0; q < KW; ++q) x[q] = 0;
-            if (j < j1) {
-                const uint32_t e = inc[j];
+            for (int q = 0; q < KW; ++q) {
+                const uint32_t t = (uint32_t)q * 64 + lane;
+                if (t < k) pen[(size_t)u * k + t] = (int32_t)(wsum - acc[q]);
+            }
+            if (lane == 0) ben[u] = (int32_t)bsum;
+            u += 1;
+            continue;
+        }
+        // slot lane j of the batch: net (j - excl) of vertex `own`, where own
+        // is the first batch vertex whose inclusive prefix exceeds j
+        const uint32_t total = (uint32_t)lane_i32((int32_t)pre, nb - 1);
+        int32_t w = 0, bw = 0;
+        uint64_t x[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) x[q] = 0;
+        {
+            uint32_t lo = 0, hi = nb - 1;  // first i in [0, nb) with pre_i > lane
+#pragma unroll
+            for (int it = 0; it < 6; ++it) {
+                const uint32_t mid = (lo + hi) >> 1;
+                const uint32_t pm = (uint32_t)__shfl((int)pre, (int)mid, WAVE);
+                if (lo < hi) {
+                    if (pm > lane) hi = mid; else lo = mid + 1;
+                }
+            }
+            const uint32_t own = lo;
+            const uint32_t po = (uint32_t)__shfl((int)pre, (int)own, WAVE);
+            const uint32_t dd = (uint32_t)__shfl((int)d, (int)own, WAVE);
+            const uint32_t oo = (uint32_t)__shfl((int)o, (int)own, WAVE);
+            const uint32_t s = (uint32_t)__shfl((int)blk, (int)own, WAVE);
+            if (lane < total) {
+                const uint32_t e = inc[oo + (lane - (po - dd))];
                 w = nwgt[e];
 #pragma unroll
                 for (int q = 0; q < KW; ++q) x[q] = lam[(size_t)e * KW + q];
-                if ((s >> 6) < (uint32_t)KW && ((lam1[(size_t)e * KW + (s >> 6)] >> (s & 63)) & 1ull)) bsum += w;
-                wsum += w;
-            }
-            // every lane adds the nets whose Lambda holds its block
-            for (uint32_t c = 0; c < lim; ++c) {
-                const int32_t wc = __shfl(w, (int)(base + c), WAVE);
-#pragma unroll
-                for (int q = 0; q < KW; ++q) {
-                    const uint64_t xc = __shfl(x[q], (int)(base + c), WAVE);
-                    if ((xc >> (V == WAVE ? l : l & 63)) & 1ull) acc[q] += wc;
-                }
+                if ((s >> 6) < (uint32_t)KW && ((lam1[(size_t)e * KW + (s >> 6)] >> (s & 63)) & 1ull)) bw = w;
             }
         }
+        // rows of the batch, one vertex at a time
+        uint32_t c = 0;
+        for (uint32_t i = 0; i < nb; ++i) {
+            const uint32_t ci = c + (uint32_t)lane_i32((int32_t)d, i);
+            int64_t acc[KW];
 #pragma unroll
-        for (int o = V / 2; o > 0; o >>= 1) {
-            bsum += __shfl_xor(bsum, o, WAVE);
-            wsum += __shfl_xor(wsum, o, WAVE);
-        }
-        if (act) {
-            if (l == 0) ben[u] = (int32_t)bsum;
+            for (int q = 0; q < KW; ++q) acc[q] = 0;
+            int64_t bsum = 0, wsum = 0;
+            for (; c < ci; ++c) {
+                const int32_t wc = lane_i32(w, c);
+                wsum += wc;
+                bsum += lane_i32(bw, c);
+#pragma unroll
+                for (int q = 0; q < KW; ++q)
+                    if ((lane_u64(x[q], c) >> lane) & 1ull) acc[q] += wc;
+            }
+            const uint32_t v = u + i;
 #pragma unroll
             for (int q = 0; q < KW; ++q) {
-                const uint32_t t = (V == WAVE ? (uint32_t)q * 64 : 0u) + l;
-                if (t < k) pen[(size_t)u * k + t] = (int32_t)(wsum - acc[q]);
+                const uint32_t t = (uint32_t)q * 64 + lane;
+                if (t < k) pen[(size_t)v * k + t] = (int32_t)(wsum - acc[q]);
             }
+            if (lane == 0) ben[v] = (int32_t)bsum;
         }
+        u += nb;
     }
 }
 
@@ -208,6 +277,96 @@ struct MoveView {
 // Claims net e for the calling lane (first mover to reach it this call).
 __device__ inline bool claim(uint32_t *stamp, uint32_t e, uint32_t call) {
     return atomicCAS(&stamp[e], 0u, call) == 0u;
+}
+
+// Nets of at most TINY_NET pins: the pins' old and new blocks and move
+// indices are loaded once into registers (three batches of independent
+// loads), and both passes below work on the registers.
+constexpr uint32_t TINY_NET = 8;
+struct TinyNet {
+    uint32_t v[TINY_NET], ob[TINY_NET], nb[TINY_NET], mi[TINY_NET];  // mi: move index or NONE (not moved)
+};
+__device__ inline void load_tiny(const MoveView &M, const uint32_t *pins, uint32_t b, uint32_t len, TinyNet &T) {
+    uint32_t x[TINY_NET];
+#pragma unroll
+    for (uint32_t y = 0; y < TINY_NET; ++y) T.v[y] = y < len ? pins[b + y] : NONE;
+#pragma unroll
+    for (uint32_t y = 0; y < TINY_NET; ++y) {
+        x[y] = T.v[y] != NONE ? M.idx[T.v[y]] : NONE;
+        T.ob[y] = T.v[y] != NONE ? M.part[T.v[y]] : NONE;
+    }
+#pragma unroll
+    for (uint32_t y = 0; y < TINY_NET; ++y) {
+        T.nb[y] = T.ob[y];
+        T.mi[y] = NONE;
+        if (x[y] != NONE) {
+            const uint32_t t = M.target[x[y]];
+            if (t != M.from[x[y]]) { T.nb[y] = t; T.mi[y] = x[y]; }
+        }
+    }
+}
+
+__device__ inline void update_tiny_net(const TinyNet &T, uint32_t len, int32_t w, uint32_t k, int32_t *ben,
+                                       int32_t *pen) {
+#pragma unroll
+    for (uint32_t x = 0; x < TINY_NET; ++x) {
+        if (x >= len || T.mi[x] == NONE) continue;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t blk = c == 0 ? T.ob[x] : T.nb[x];
+            // judged once: at the first moved pin naming the block
+            bool first = true;
+            uint32_t co = 0, cn = 0;
+#pragma unroll
+            for (uint32_t y = 0; y < TINY_NET; ++y) {
+                if (y >= len) continue;
+                if (y < x && T.mi[y] != NONE && (T.ob[y] == blk || T.nb[y] == blk)) first = false;
+                co += T.ob[y] == blk;
+                cn += T.nb[y] == blk;
+            }
+            if (!first) continue;
+            if ((co == 0) != (cn == 0)) {
+                const int32_t d = cn == 0 ? w : -w;
+#pragma unroll
+                for (uint32_t y = 0; y < TINY_NET; ++y)
+                    if (y < len) atomicAdd(&pen[(size_t)T.v[y] * k + blk], d);
+            }
+            if ((co == 1) != (cn == 1)) {
+                const int32_t d = cn == 1 ? w : -w;
+#pragma unroll
+                for (uint32_t y = 0; y < TINY_NET; ++y)
+                    if (y < len && T.mi[y] == NONE && T.ob[y] == blk) atomicAdd(&ben[T.v[y]], d);
+            }
+        }
+    }
+}
+
+__device__ inline void recalc_tiny_net(const TinyNet &T, uint32_t len, int64_t w, unsigned long long *gain) {
+#pragma unroll
+    for (uint32_t x = 0; x < TINY_NET; ++x) {
+        if (x >= len || T.mi[x] == NONE) continue;
+        const uint32_t i = T.mi[x], s = T.ob[x], t = T.nb[x];
+        int64_t last_out_s = -1, last_out_t = -1;
+        uint32_t first_in_s = NONE, first_in_t = NONE, un_s = 0, un_t = 0;
+#pragma unroll
+        for (uint32_t y = 0; y < TINY_NET; ++y) {
+            if (y >= len) continue;
+            const uint32_t iy = T.mi[y];
+            if (iy != NONE) {
+                if (T.ob[y] == s && (int64_t)iy > last_out_s) last_out_s = iy;
+                if (T.ob[y] == t && (int64_t)iy > last_out_t) last_out_t = iy;
+                if (T.nb[y] == s && iy < first_in_s) first_in_s = iy;
+                if (T.nb[y] == t && iy < first_in_t) first_in_t = iy;
+            } else {
+                un_s += T.ob[y] == s;
+                un_t += T.ob[y] == t;
+            }
+        }
+        int64_t d = 0;
+        if (last_out_s == (int64_t)i && i < first_in_s && un_s == 0) d += w;
+        if (first_in_t == i && (int64_t)i > last_out_t && un_t == 0) d -= w;
+        if (d) atomicAdd(&gain[i], (unsigned long long)d);
+    }
 }
 
 // Table update of one claimed net of at most SMALL_NET pins.
@@ -308,8 +467,16 @@ __global__ __launch_bounds__(BLOCK) void k_gt_nets(MoveView M, const uint32_t *n
                 longl[atomicAdd(nlong, 1u)] = e;
                 continue;
             }
-            if (OP == OP_UPDATE) update_small_net(M, pins, b, len, nwgt[e], k, ben, pen);
-            else recalc_small_net(M, pins, b, len, nwgt[e], gain);
+            if (len <= TINY_NET) {
+                TinyNet T;
+                load_tiny(M, pins, b, len, T);
+                if (OP == OP_UPDATE) update_tiny_net(T, len, nwgt[e], k, ben, pen);
+                else recalc_tiny_net(T, len, nwgt[e], gain);
+            } else if (OP == OP_UPDATE) {
+                update_small_net(M, pins, b, len, nwgt[e], k, ben, pen);
+            } else {
+                recalc_small_net(M, pins, b, len, nwgt[e], gain);
+            }
         }
     }
 }
@@ -399,8 +566,16 @@ __global__ __launch_bounds__(BLOCK) void k_gt_mover_benefit(MoveView M, const ui
         int64_t bsum = 0;
         for (uint32_t j = inc_off[u]; j < inc_off[u + 1]; ++j) {
             const uint32_t e = inc[j];
+            const uint32_t b = pin_off[e], len = pin_off[e + 1] - b;
             uint32_t c = 0;
-            for (uint32_t q = pin_off[e]; q < pin_off[e + 1] && c < 2; ++q) c += M.new_block(pins[q]) == t;
+            if (len <= TINY_NET) {
+                TinyNet T;
+                load_tiny(M, pins, b, len, T);
+#pragma unroll
+                for (uint32_t y = 0; y < TINY_NET; ++y) c += y < len && T.nb[y] == t;
+            } else {
+                for (uint32_t q = b; q < b + len && c < 2; ++q) c += M.new_block(pins[q]) == t;
+            }
             if (c == 1) bsum += nwgt[e];
         }
         ben[u] = (int32_t)bsum;
@@ -436,14 +611,6 @@ void plan_moves(Arena &A, uint32_t n, uint32_t m, uint32_t count, GtBufs &B) {
     B.scal = A.alloc<uint32_t>(64);
 }
 
-template <int KW, int V>
-void launch_rows(const hgp_hg &h, uint32_t k, const uint32_t *part, const GtBufs &B, int32_t *ben, int32_t *pen,
-                 hipStream_t st) {
-    k_gt_rows<KW, V><<<grid_for(h.n, BLOCK / V, 8 * FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, h.nwgt, part,
-                                                                                  B.lam, B.lam1, h.n, k, ben, pen);
-    HGP_LAUNCH_CHECK();
-}
-
 template <int KW>
 void table_t(const hgp_hg &h, uint32_t k, const uint32_t *part, int32_t *ben, int32_t *pen, Arena &A,
              hipStream_t st) {
@@ -461,11 +628,10 @@ void table_t(const hgp_hg &h, uint32_t k, const uint32_t *part, int32_t *ben, in
                                                               B.lam1);
         HGP_LAUNCH_CHECK();
     }
-    if (KW > 1 || k > 32) launch_rows<KW, 64>(h, k, part, B, ben, pen, st);
-    else if (k > 16) launch_rows<1, 32>(h, k, part, B, ben, pen, st);
-    else if (k > 8) launch_rows<1, 16>(h, k, part, B, ben, pen, st);
-    else if (k > 4) launch_rows<1, 8>(h, k, part, B, ben, pen, st);
-    else launch_rows<1, 4>(h, k, part, B, ben, pen, st);
+    // about eight waves per CU, each over a contiguous range of vertices
+    const unsigned blocks = (unsigned)std::min<size_t>(2 * FILL_BLOCKS, ((size_t)h.n + 63) / 64);
+    k_gt_rows<KW><<<blocks, BLOCK, 0, st>>>(h.inc_off, h.inc, h.nwgt, part, B.lam, B.lam1, h.n, k, ben, pen);
+    HGP_LAUNCH_CHECK();
     A.release(mk);
 }
 

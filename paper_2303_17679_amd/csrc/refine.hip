@@ -243,9 +243,22 @@ struct GainArgs {
     LpCtl ctl;
 };
 
-// Proposal lists: NSLOT lists by vertex chunk (see GainArgs).  A list holds
-// at most the vertices of its chunks, ceil(chunks / NSLOT) * ch.
+// Proposal lists: NSLOT lists by vertex chunk (see GainArgs).
 constexpr uint32_t NSLOT = SPREAD;
+static_assert(NSLOT == 64, "slot = XCD + 8 * (chunk mod 8)");
+
+// List of vertex chunk c (of nchunks): the XCD whose share of the chunk
+// range (xcd_slice over chunks) holds c, plus 8 (c mod 8).  Workgroup b
+// reads list b mod NSLOT, and b mod 8 is its XCD, so a chunk's candidates
+// are selected, rated, selected for moves and updated on one XCD: the net
+// records that neighbouring chunks share stay in that XCD's L2.  A list
+// holds at most chunk_slot_cap chunks.
+__host__ __device__ inline uint32_t chunk_slot(uint32_t c, uint32_t nchunks) {
+    uint32_t x = (uint32_t)((8ull * (c + 1) + nchunks - 1) / nchunks) - 1u;
+    x = x < 7u ? x : 7u;
+    return x + 8u * (c % 8u);
+}
+__host__ __device__ inline uint32_t chunk_slot_cap(uint32_t nchunks) { return ((nchunks + 7) / 8 + 7) / 8 + 1; }
 
 // Called by every lane of the wave (uniformly); `has` is set by at most one
 // lane per proposing vertex, and every proposing lane of the call belongs
@@ -460,7 +473,7 @@ __global__ __launch_bounds__(BLOCK) void k_gain_scan(GainArgs<KW> a, uint32_t ch
             else lst[cls][atomicAdd(&lcnt[cls], 1u)] = v;
         }
         __syncthreads();
-        const uint32_t slot = c % NSLOT;
+        const uint32_t slot = chunk_slot(c, nchunks);
         if (threadIdx.x < 3)
             lbase[threadIdx.x] =
                 lcnt[threadIdx.x] ? atomicAdd(&ccnt[(threadIdx.x * NSLOT + slot) * SPREAD_U32], lcnt[threadIdx.x]) : 0u;
@@ -569,7 +582,8 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
                 const uint32_t og = __shfl_xor(best_g, o, 64), ot = __shfl_xor(best_t, o, 64);
                 if (og > best_g || (og == best_g && ot < best_t)) { best_g = og; best_t = ot; }
             }
-            propose(a, u, s, best_t, best_g, __lane_id() == 0 && best_t != NONE, (u / a.ch) % NSLOT);
+            propose(a, u, s, best_t, best_g, __lane_id() == 0 && best_t != NONE,
+                    chunk_slot(u / a.ch, (a.n + a.ch - 1) / a.ch));
         }
         __syncthreads();  // the histogram is read before the next node clears it
     }
@@ -1321,13 +1335,13 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.nr = A.alloc<char>((size_t)m * netrec_bytes(KW));
     B.f = A.alloc<int64_t>((size_t)SPREAD * SPREAD_I64);
     B.pcnt = A.alloc<uint32_t>((size_t)2 * NSLOT * SPREAD_U32);
-    B.cl = A.alloc<uint32_t>(3 * ((size_t)n + (size_t)(NSLOT + 1) * GAIN_CH));
+    B.cl = A.alloc<uint32_t>(3 * ((size_t)n + (size_t)(3 * NSLOT) * GAIN_CH));
     B.ccnt = A.alloc<uint32_t>((size_t)3 * NSLOT * SPREAD_U32);
     B.bw = A.alloc<int64_t>(k);
     B.longl = A.alloc<uint32_t>(m);
     B.dlists = A.alloc<uint32_t>(n);
     B.bcnt = A.alloc<uint32_t>(n);
-    B.plist = A.alloc<uint32_t>((size_t)n + (size_t)(NSLOT + 1) * GAIN_CH);  // NSLOT lists (see GainArgs)
+    B.plist = A.alloc<uint32_t>((size_t)n + (size_t)(3 * NSLOT) * GAIN_CH);  // NSLOT lists of slot_cap (chunk_slot_cap)
     B.prop_t = A.alloc<uint32_t>(n);
     B.prop_g = A.alloc<uint32_t>(n);
     B.tstamp = A.alloc<uint32_t>(m);
@@ -1470,7 +1484,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     const uint32_t gchunks = (uint32_t)(((size_t)n + gch - 1) / gch);
     const uint32_t gain_blocks = std::min<uint32_t>(gchunks, 2048u);  // about one round of the scan
     // capacity of one proposal list: the vertices of its chunks
-    const uint32_t slot_cap = (gchunks + NSLOT - 1) / NSLOT * gch;
+    const uint32_t slot_cap = chunk_slot_cap(gchunks) * gch;
     const uint32_t hub_blocks = dc[3] ? grid_for((dc[3] + S - 1) / S, 1, 256) : 0u;
     uint32_t *nhub = B.scal + 26;  // hub candidates of the sub-round (list in dlists)
     // grids of the per-sub-round kernels, sized by what one sub-round can hold

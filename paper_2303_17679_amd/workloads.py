@@ -424,3 +424,14 @@ def workload(name: str) -> tuple[HostHypergraph, int]:
         N = int(name[len("powerlaw"):])
         return powerlaw(N, N, seed=2, max_size=min(1000, N // 10), name=name), 8
     raise KeyError(name)
+
+
+def move_sequence(n: int, k: int, part: np.ndarray, count: int, seed: int):
+    """`count` distinct nodes in a seeded random order, each with a target
+    block drawn uniformly from the k - 1 blocks other than its own: the
+    shape of one round of node moves (every node moved at most once)."""
+    keys = rng(seed, 1, np.arange(n))
+    nodes = np.argsort(keys, kind="stable")[:count].astype(np.uint32)
+    step = uniform(rng(seed, 2, np.arange(count)), k - 1).astype(np.int64) + 1
+    targets = ((part[nodes].astype(np.int64) + step) % k).astype(np.uint32)
+    return nodes, targets
