@@ -321,7 +321,10 @@ hgp_status hgp_partition_batch(const hgp_hg *hs, const hgp_params *ps, uint32_t 
 #define HGP_KID_LP_FAST 5    /* LP whole-pair approvals                       */
 #define HGP_KID_LP_FUSED 6   /* LP sorted pair walk, one workgroup            */
 #define HGP_KID_LP_UPDATE 7  /* LP connectivity update of touched nets        */
-#define HGP_KID_COUNT 8
+#define HGP_KID_HUB_INSERT 8 /* hub rating, global-table inserts               */
+#define HGP_KID_HUB_ARGMAX 9 /* hub rating, best target per table slice        */
+#define HGP_KID_HUB_LDS 10   /* hub rating in one workgroup's LDS table        */
+#define HGP_KID_COUNT 11
 
 /* Host.  Bytes of device scratch that accounting needs for levels of at most
  * n_max vertices and m_max nets. */

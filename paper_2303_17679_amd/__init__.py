@@ -31,7 +31,7 @@ EXPORTS = ["hgp_default_params", "hgp_workspace_bytes", "hgp_validate", "hgp_coa
 
 # kernel ids of the measurement calls, with the kernel symbol each one names
 KERNELS = ["k_rate_group<8, 64, 6>", "k_rate_group<16, 256, 8>", "k_rate_group<64, 1024, 10>", "k_rate_block",
-           "k_gains", "k_lp_fast", "k_lp_pairs", "k_lp_update_movers"]
+           "k_gains", "k_lp_fast", "k_lp_pairs", "k_lp_update_movers", "k_hub_insert", "k_hub_argmax", "k_hub_lds"]
 
 
 class HGPError(RuntimeError):

@@ -181,8 +181,12 @@ __global__ __launch_bounds__(NT) void k_rate_group(RateArgs a, const uint32_t *l
     // are fetched ahead (this kernel writes none of them): the ID two
     // candidates ahead, and the cluster state and incidence range of the
     // next, so those loads overlap the current candidate's gathers.
-    const uint32_t stride = gridDim.x * GPB;
-    uint32_t idx = blockIdx.x * GPB + g;
+    // XCD x takes the x-th eighth of the list (the lists hold the vertices
+    // in ascending order of classify block, i.e. about in vertex order), so
+    // candidates that share nets share an L2
+    const XcdSlice xs = xcd_slice(blockIdx.x, gridDim.x, count);
+    const uint32_t stride = xs.nw * GPB, end = xs.hi;
+    uint32_t idx = xs.lo + xs.wi * GPB + g;
     uint32_t pu = NONE, pj0 = 0, pj1 = 0;  // the next candidate's record
     int64_t pcw = 0;
     int32_t pvw = 0;
@@ -197,14 +201,14 @@ __global__ __launch_bounds__(NT) void k_rate_group(RateArgs a, const uint32_t *l
             pj1 = a.inc_off[v + 1];
         }
     };
-    fetch(idx < count ? list[idx] : NONE);
-    uint32_t nid = idx + stride < count ? list[idx + stride] : NONE;  // the ID after that
-    for (; idx < count; idx += stride) {
+    fetch(idx < end ? list[idx] : NONE);
+    uint32_t nid = idx + stride < end ? list[idx + stride] : NONE;  // the ID after that
+    for (; idx < end; idx += stride) {
         const uint32_t u = pu, j0 = pj0, j1 = pj1;
         const int64_t cu = pvw;
         const bool active = prep == u && pcw == cu;  // not joined earlier
         const uint32_t after = nid;
-        nid = idx + 2 * stride < count ? list[idx + 2 * stride] : NONE;
+        nid = idx + 2 * stride < end ? list[idx + 2 * stride] : NONE;
         fetch(after);
         if (!active) continue;  // uniform within the group
         auto insert = [&](uint32_t C, uint64_t sc) -> uint32_t {
@@ -320,7 +324,8 @@ __global__ __launch_bounds__(BLOCK) void k_rate_block(RateArgs a, const uint32_t
     __shared__ uint64_t R[LCAP];
     __shared__ uint64_t redR[BLOCK / WAVE];
     __shared__ uint32_t redC[BLOCK / WAVE];
-    for (uint32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const XcdSlice xs = xcd_slice(blockIdx.x, gridDim.x, count);
+    for (uint32_t idx = xs.lo + xs.wi; idx < xs.hi; idx += xs.nw) {
         uint32_t u = list[idx];
         if (!(a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u])) continue;  // uniform per block
         for (uint32_t s = threadIdx.x; s < LCAP; s += BLOCK) { keys[s] = NONE; stamp[s] = NONE; R[s] = 0; }
@@ -815,14 +820,23 @@ __global__ __launch_bounds__(BLOCK) void k_hub_pick(RateArgs a, const HubJob *jo
 // the cluster of every distinct pin vertex, the target info of every distinct
 // cluster, the target written).  Never runs in a timed step.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_account_rate(RateArgs a, const uint32_t *list, uint32_t count,
+struct ListVertex {
+    const uint32_t *list;
+    __device__ uint32_t operator()(uint32_t i) const { return list[i]; }
+};
+struct JobVertex {
+    const HubJob *jobs;
+    __device__ uint32_t operator()(uint32_t i) const { return jobs[i].u; }
+};
+template <class Get>
+__global__ __launch_bounds__(BLOCK) void k_account_rate(RateArgs a, Get get, uint32_t count,
                                                         uint32_t *nmark, uint32_t *vmark, uint32_t *cmark,
                                                         uint32_t stamp, unsigned long long *acc) {
     __shared__ unsigned long long red[BLOCK / WAVE];
     if (rate_skip(a)) return;
     unsigned long long bytes = 0;
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
-        const uint32_t u = list[idx];
+        const uint32_t u = get(idx);
         bytes += 4 + 4 + 8 + 4;  // list entry, rep[u], cw[u], vwgt[u]
         if (!(a.rep[u] == u && a.cw[u] == (int64_t)a.vwgt[u])) continue;
         const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
@@ -979,10 +993,15 @@ __device__ inline int classify_key(const uint32_t *bound, uint32_t n, uint64_t m
     return (int)((uint32_t)(tag_hash(mseed, 1, level, 0, u) % S) * NCLASS + c);
 }
 
+// Block b takes the contiguous vertex range [b * per, (b + 1) * per), and its
+// vertices of each key go to the list after those of blocks 0 .. b-1 (per-
+// block counts of pass 1 in bcounts[key * gridDim + b]), so every list holds
+// its vertices about in ascending order: the rating kernels give each XCD a
+// contiguous part of a list, hence of the vertex range.
 __global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *bound, uint32_t n, uint64_t mseed,
                                                     uint32_t level, uint32_t S, const int32_t *vwgt, uint32_t *rep,
                                                     int64_t *cw, int64_t *tsum, uint32_t *counts, uint32_t *cursor,
-                                                    uint32_t *lists, bool fill) {
+                                                    uint32_t *bcounts, uint32_t *lists, bool fill) {
     __shared__ uint32_t lcnt[MAX_KEYS];
     __shared__ uint32_t lbase[MAX_KEYS];
     __shared__ uint32_t lmaxd, lmaxw;
@@ -991,7 +1010,10 @@ __global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *bound, uint3
     if (threadIdx.x == 0) { lmaxd = 0; lmaxw = 0; }
     __syncthreads();
     uint32_t mw = 0;  // largest vertex weight seen by the thread
-    for (uint32_t u = blockIdx.x * BLOCK + threadIdx.x; u < n; u += gridDim.x * BLOCK) {
+    const uint32_t per = (uint32_t)(((uint64_t)n + gridDim.x - 1) / gridDim.x);
+    const uint32_t ulo = (uint32_t)min((uint64_t)blockIdx.x * per, (uint64_t)n);
+    const uint32_t uhi = (uint32_t)min((uint64_t)ulo + per, (uint64_t)n);
+    for (uint32_t u = ulo + threadIdx.x; u < uhi; u += BLOCK) {
         uint32_t D;
         const int key = classify_key(bound, n, mseed, level, S, u, &D);
         if (!fill) {
@@ -1014,19 +1036,22 @@ __global__ __launch_bounds__(BLOCK) void k_classify(const uint32_t *bound, uint3
     }
     __syncthreads();
     if (!fill) {
-        for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK)
+        for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) {
             if (lcnt[i]) atomicAdd(&counts[i], lcnt[i]);
+            bcounts[(size_t)i * gridDim.x + blockIdx.x] = lcnt[i];
+        }
         if (threadIdx.x == 0 && lmaxd) atomicMax(&counts[nkeys], lmaxd);
         if (threadIdx.x == 0 && lmaxw) atomicMax(&counts[nkeys + 2], lmaxw);
         return;
     }
     for (uint32_t i = threadIdx.x; i < nkeys; i += BLOCK) {
-        const uint32_t c = lcnt[i];
-        lbase[i] = c ? atomicAdd(&cursor[i], c) : 0u;
+        uint32_t before = cursor[i];  // the list's start
+        for (uint32_t b = 0; b < blockIdx.x; ++b) before += bcounts[(size_t)i * gridDim.x + b];
+        lbase[i] = before;
         lcnt[i] = 0;
     }
     __syncthreads();
-    for (uint32_t u = blockIdx.x * BLOCK + threadIdx.x; u < n; u += gridDim.x * BLOCK) {
+    for (uint32_t u = ulo + threadIdx.x; u < uhi; u += BLOCK) {
         uint32_t D;
         const int key = classify_key(bound, n, mseed, level, S, u, &D);
         if (key >= 0) lists[lbase[key] + atomicAdd(&lcnt[key], 1u)] = u;
@@ -1215,7 +1240,7 @@ __global__ __launch_bounds__(BLOCK) void k_apply_joins(const uint32_t *cands, ui
 struct CoarsenBufs {
     uint64_t *nscore;
     int64_t *cw, *tsum, *tinfo;
-    uint32_t *ptarget, *slow, *lists, *counts, *cursor, *scal;
+    uint32_t *ptarget, *slow, *lists, *counts, *cursor, *bcounts, *scal;
     uint8_t *ok;
     uint64_t *keys, *keys_alt, *incl;
     uint32_t *vals, *vals_alt;
@@ -1248,6 +1273,7 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, uint32_t S, Coars
     B.counts = A.alloc<uint32_t>((size_t)S * NCLASS + 3);  // + largest D, largest net, largest vertex weight
     B.bound = A.alloc<uint32_t>(n);
     B.cursor = A.alloc<uint32_t>((size_t)S * NCLASS);
+    B.bcounts = A.alloc<uint32_t>((size_t)S * NCLASS * CLASSIFY_BLOCKS);
     B.scal = A.alloc<uint32_t>(8 + 256);  // counters, then the cut decision of every sub-round
     B.ok = A.alloc<uint8_t>(n);
     B.keys = A.alloc<uint64_t>(n);
@@ -1321,7 +1347,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             h.pin_off, h.inc_off, h.inc, n, m, B.bound, B.counts + S * NCLASS + 1);
     HGP_LAUNCH_CHECK();
     k_classify<<<grid_for(n, BLOCK, CLASSIFY_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
-                                                                 B.tsum, B.counts, B.cursor, B.lists, false);
+                                                                 B.tsum, B.counts, B.cursor, B.bcounts, B.lists, false);
     HGP_LAUNCH_CHECK();
     std::vector<uint32_t> counts(S * NCLASS + 3), offs(S * NCLASS + 1);
     HGP_CHECK_HIP(hipMemcpyAsync(counts.data(), B.counts, sizeof(uint32_t) * (S * NCLASS + 3), hipMemcpyDeviceToHost,
@@ -1339,6 +1365,16 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
         HGP_CHECK_HIP(hipMemsetAsync(gR, 0, 8 * E, st));
         HGP_CHECK_HIP(hipMemsetAsync(gkeys, 0xFF, 8 * E, st));  // keys and stamps
     }
+    // Measurement only: compulsory bytes of rating the jobs' candidates.
+    auto account_jobs = [&](int kid, const RateArgs &a, const HubJob *jobs, uint32_t nj) {
+        if (!accounting(kid) || nj == 0) return;
+        Timing &T = timing();
+        ++T.stamp;
+        k_account_rate<<<grid_for(nj, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+            a, JobVertex{jobs}, nj, T.marks, T.marks + T.marks_len, T.marks + 2 * T.marks_len, T.stamp,
+            (unsigned long long *)T.acc_dev + kid);
+        HGP_LAUNCH_CHECK();
+    };
     // Hub rating of the listed candidates: jobs packed into the region in
     // batches (every table fits the region alone: E >= 16 * its capacity).
     auto global_rate = [&](const RateArgs &a, const std::vector<uint4> &info) {
@@ -1386,6 +1422,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                                      st));
         HGP_CHECK_HIP(hipMemcpyAsync(B.hub_items, items.data(), sizeof(HubItem) * items.size(),
                                      hipMemcpyHostToDevice, st));
+        account_jobs(KID_HUB_INSERT, a, B.hub_jobs, (uint32_t)jobs.size());
         for (size_t b = 0; b + 1 < bj.size(); ++b) {
             const uint32_t nj = bj[b + 1] - bj[b], ni = bi[b + 1] - bi[b], na = ba[b + 1] - ba[b];
             if (!nj) continue;
@@ -1393,15 +1430,21 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             const HubJob *jb = B.hub_jobs + bj[b];
             HGP_CHECK_HIP(hipMemcpyAsync(B.hub_aitems, aitems.data() + ba[b], sizeof(HubItem) * na,
                                          hipMemcpyHostToDevice, st));
-            k_hub_insert<<<std::min(ni, 8192u), BLOCK, 0, st>>>(a, jb, B.hub_items + bi[b], ni, gkeys, gR);
-            HGP_LAUNCH_CHECK();
+            {
+                TimedLaunch tl(KID_HUB_INSERT, st);
+                k_hub_insert<<<std::min(ni, 8192u), BLOCK, 0, st>>>(a, jb, B.hub_items + bi[b], ni, gkeys, gR);
+                HGP_LAUNCH_CHECK();
+            }
             if (huge_nets) {
                 k_hub_huge<<<std::min(nj, 8192u), BLOCK, 0, st>>>(a, jb, nj, gkeys, gstamp, gR);
                 HGP_LAUNCH_CHECK();
             }
-            k_hub_argmax<<<std::min(na, 8192u), BLOCK, 0, st>>>(a, jb, B.hub_aitems, na, gkeys, gstamp, gR,
-                                                                B.hub_partR, B.hub_partC);
-            HGP_LAUNCH_CHECK();
+            {
+                TimedLaunch tl(KID_HUB_ARGMAX, st);
+                k_hub_argmax<<<std::min(na, 8192u), BLOCK, 0, st>>>(a, jb, B.hub_aitems, na, gkeys, gstamp, gR,
+                                                                    B.hub_partR, B.hub_partC);
+                HGP_LAUNCH_CHECK();
+            }
             k_hub_pick<<<grid_for((size_t)nj * WAVE, BLOCK, 1024), BLOCK, 0, st>>>(a, jb, nj, B.hub_partR,
                                                                                   B.hub_partC, nullptr);
             HGP_LAUNCH_CHECK();
@@ -1443,6 +1486,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             la.push_back((uint32_t)litems.size());
             HGP_CHECK_HIP(hipMemcpyAsync(B.hub_jobs, ljobs.data(), sizeof(HubJob) * ljobs.size(),
                                          hipMemcpyHostToDevice, st));
+            account_jobs(KID_HUB_LDS, a, B.hub_jobs, (uint32_t)ljobs.size());
             HGP_CHECK_HIP(hipMemsetAsync(B.hub_ovf, 0, sizeof(uint32_t) * (ljobs.size() + 1), st));
             uint32_t *ovf_cnt = B.hub_ovf + n;
             HGP_CHECK_HIP(hipMemsetAsync(ovf_cnt, 0, sizeof(uint32_t), st));
@@ -1452,10 +1496,13 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                 const HubJob *jb = B.hub_jobs + lj[b];
                 HGP_CHECK_HIP(hipMemcpyAsync(B.hub_aitems, litems.data() + la[b], sizeof(HubItem) * nl,
                                              hipMemcpyHostToDevice, st));
-                k_hub_lds<<<std::min(nl, 8192u), LHUB_THREADS, 0, st>>>(a, jb, B.hub_aitems, nl, B.hub_partR,
-                                                                        B.hub_partC, B.hub_ovf + lj[b],
-                                                                        B.hub_ovf_list, ovf_cnt);
-                HGP_LAUNCH_CHECK();
+                {
+                    TimedLaunch tl(KID_HUB_LDS, st);
+                    k_hub_lds<<<std::min(nl, 8192u), LHUB_THREADS, 0, st>>>(a, jb, B.hub_aitems, nl, B.hub_partR,
+                                                                            B.hub_partC, B.hub_ovf + lj[b],
+                                                                            B.hub_ovf_list, ovf_cnt);
+                    HGP_LAUNCH_CHECK();
+                }
                 k_hub_pick<<<grid_for((size_t)nj * WAVE, BLOCK, 1024), BLOCK, 0, st>>>(a, jb, nj, B.hub_partR,
                                                                                       B.hub_partC, B.hub_ovf + lj[b]);
                 HGP_LAUNCH_CHECK();
@@ -1483,7 +1530,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     for (uint32_t i = 0; i < S * NCLASS; ++i) offs[i + 1] = offs[i] + counts[i];
     HGP_CHECK_HIP(hipMemcpyAsync(B.cursor, offs.data(), sizeof(uint32_t) * S * NCLASS, hipMemcpyHostToDevice, st));
     k_classify<<<grid_for(n, BLOCK, CLASSIFY_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
-                                                                 B.tsum, B.counts, B.cursor, B.lists, true);
+                                                                 B.tsum, B.counts, B.cursor, B.bcounts, B.lists, true);
     HGP_LAUNCH_CHECK();
 
     uint32_t cnt = n;
@@ -1516,7 +1563,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                 Timing &T = timing();
                 ++T.stamp;
                 k_account_rate<<<grid_for(cntc, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
-                    a, lst, cntc, T.marks, T.marks + T.marks_len, T.marks + 2 * T.marks_len, T.stamp,
+                    a, ListVertex{lst}, cntc, T.marks, T.marks + T.marks_len, T.marks + 2 * T.marks_len, T.stamp,
                     (unsigned long long *)T.acc_dev + kid);
                 HGP_LAUNCH_CHECK();
             }

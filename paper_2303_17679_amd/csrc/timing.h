@@ -16,6 +16,9 @@ enum KernelId : int {
     KID_LP_FAST,       // k_lp_fast: whole-pair approvals
     KID_LP_PAIRS,      // k_lp_pairs: sorted pair walk, a workgroup per over-budget block pair
     KID_LP_UPDATE,     // k_lp_update_movers: Lambda / Lambda1 / objective of touched nets
+    KID_HUB_INSERT,    // k_hub_insert: hub ratings into global tables
+    KID_HUB_ARGMAX,    // k_hub_argmax: best target of each table slice
+    KID_HUB_LDS,       // k_hub_lds: hub ratings in one workgroup's LDS table
     KID_COUNT
 };
 
