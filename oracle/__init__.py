@@ -78,6 +78,9 @@ def lib():
         L.or_gain_table_moves.restype = ctypes.c_int
         L.or_gain_table_moves.argtypes = [P, u32, P, P, P, u32, P, P]
         L.or_gain_recalc.restype = ctypes.c_int; L.or_gain_recalc.argtypes = [P, u32, P, P, P, u32, P]
+        L.or_graph_adjacency.restype = ctypes.c_int; L.or_graph_adjacency.argtypes = [P, P, P]
+        L.or_graph_gain.restype = i64; L.or_graph_gain.argtypes = [P, P, P, P, u32, u32]
+        L.or_graph_cut.restype = i64; L.or_graph_cut.argtypes = [P, P]
         _lib = L
     return _lib
 
@@ -250,6 +253,31 @@ def gain_recalc(h, k: int, part, mu, mt):
     g = np.zeros(max(mu.shape[0], 1), np.int64)
     assert lib().or_gain_recalc(v.ref, k, _ptr(part), _ptr(mu), _ptr(mt), mu.shape[0], _ptr(g)) == 0
     return g[:mu.shape[0]]
+
+
+def graph_adjacency(h):
+    """(adj, adjw) of a hypergraph whose nets all have two pins, or None."""
+    v = _View(h)
+    p = int(v.s.p)
+    adj = np.zeros(max(p, 1), np.uint32)
+    adjw = np.zeros(max(p, 1), np.int32)
+    if lib().or_graph_adjacency(v.ref, _ptr(adj), _ptr(adjw)) != 0:
+        return None
+    return adj[:p], adjw[:p]
+
+
+def graph_gain(h, adj, adjw, part, u: int, t: int) -> int:
+    v = _View(h)
+    adj = np.ascontiguousarray(adj, np.uint32)
+    adjw = np.ascontiguousarray(adjw, np.int32)
+    part = np.ascontiguousarray(part, np.uint32)
+    return int(lib().or_graph_gain(v.ref, _ptr(adj), _ptr(adjw), _ptr(part), u, t))
+
+
+def graph_cut(h, part) -> int:
+    v = _View(h)
+    part = np.ascontiguousarray(part, np.uint32)
+    return int(lib().or_graph_cut(v.ref, _ptr(part)))
 
 
 def partition(h, P: Params):

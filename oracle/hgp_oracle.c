@@ -835,3 +835,47 @@ int or_gain_recalc(const or_hg *h, uint32_t k, const uint32_t *part, const uint3
     free(phi); free(cur);
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Graphs (Sec. 10): every net has two pins.  The gain of moving u to V_t   */
+/* is w(u, V_t) - w(u, V_Pi[u]) (external minus internal edge weight), read */
+/* from one adjacency array: adj[j] is the other endpoint of the j-th edge  */
+/* of u (in the order of u's incident nets), adjw[j] its weight.            */
+/* ------------------------------------------------------------------------ */
+
+/* Builds the adjacency array of a hypergraph whose nets all have two pins;
+ * returns OR_E_INVALID if some net does not. */
+int or_graph_adjacency(const or_hg *h, uint32_t *adj, int32_t *adjw)
+{
+    for (uint32_t e = 0; e < h->m; ++e)
+        if (h->pin_off[e + 1] - h->pin_off[e] != 2) return OR_E_INVALID;
+    for (uint32_t u = 0; u < h->n; ++u)
+        for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+            uint32_t e = h->inc[j];
+            uint32_t a = h->pins[h->pin_off[e]], b = h->pins[h->pin_off[e] + 1];
+            adj[j] = (a == u) ? b : a;
+            adjw[j] = h->nwgt[e];
+        }
+    return OR_OK;
+}
+
+/* w(u, V_t) - w(u, V_Pi[u]) from the adjacency array. */
+int64_t or_graph_gain(const or_hg *h, const uint32_t *adj, const int32_t *adjw, const uint32_t *part,
+                      uint32_t u, uint32_t t)
+{
+    int64_t to_t = 0, internal = 0;
+    for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+        if (part[adj[j]] == t) to_t += adjw[j];
+        if (part[adj[j]] == part[u]) internal += adjw[j];
+    }
+    return to_t - internal;
+}
+
+/* Edge cut: the total weight of edges whose endpoints lie in different blocks. */
+int64_t or_graph_cut(const or_hg *h, const uint32_t *part)
+{
+    int64_t c = 0;
+    for (uint32_t e = 0; e < h->m; ++e)
+        if (part[h->pins[h->pin_off[e]]] != part[h->pins[h->pin_off[e] + 1]]) c += h->nwgt[e];
+    return c;
+}
