@@ -205,6 +205,119 @@ __global__ __launch_bounds__(BLOCK) void k_conn_long(const uint32_t *pin_off, co
     }
 }
 
+// Largest net size of the level (one atomic per workgroup).
+__global__ __launch_bounds__(BLOCK) void k_max_net(const uint32_t *pin_off, uint32_t m, uint32_t *out) {
+    uint32_t mx = 0;
+    for (uint32_t e = blockIdx.x * BLOCK + threadIdx.x; e < m; e += gridDim.x * BLOCK) {
+        const uint32_t sz = pin_off[e + 1] - pin_off[e];
+        mx = sz > mx ? sz : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_xor(mx, o, WAVE);
+        mx = y > mx ? y : mx;
+    }
+    __shared__ uint32_t red[BLOCK / WAVE];
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < BLOCK / WAVE; ++q) mx = red[q] > mx ? red[q] : mx;
+        if (mx) atomicMax(out, mx);
+    }
+}
+
+// Adjacency array of a graph level: for the j-th incident net e of u,
+// adj[j] = the other pin of e and adjw[j] = w(e).  A thread per vertex of up
+// to 32 nets (eight incidence loads, then eight net loads at a time), the
+// whole wave for up to ADJ_HEAVY nets; heavier vertices are listed for
+// k_graph_adj_heavy.
+constexpr uint32_t ADJ_HEAVY = 4096;
+__global__ __launch_bounds__(BLOCK) void k_graph_adj(const uint32_t *inc_off, const uint32_t *inc,
+                                                     const uint32_t *pin_off, const uint32_t *pins,
+                                                     const int32_t *nwgt, uint32_t n, uint32_t *adj, int32_t *adjw,
+                                                     uint32_t *heavy, uint32_t *nheavy) {
+    for (uint32_t u0 = blockIdx.x * BLOCK; u0 < n; u0 += gridDim.x * BLOCK) {
+        const uint32_t u = u0 + threadIdx.x;
+        uint32_t j0 = 0, j1 = 0;
+        if (u < n) { j0 = inc_off[u]; j1 = inc_off[u + 1]; }
+        const bool wide = j1 - j0 > 32;
+        if (!wide)
+            for (uint32_t j = j0; j < j1; j += 8) {
+                uint32_t e[8], b[8];
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) e[q] = j + q < j1 ? inc[j + q] : NONE;
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) b[q] = e[q] != NONE ? pin_off[e[q]] : 0u;
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) {
+                    if (e[q] == NONE) continue;
+                    const uint32_t x = pins[b[q]], y = pins[b[q] + 1];
+                    adj[j + q] = x == u ? y : x;
+                    adjw[j + q] = nwgt[e[q]];
+                }
+            }
+        uint64_t wm = __ballot(wide);
+        while (wm) {
+            const int h = __ffsll((long long)wm) - 1;
+            wm &= wm - 1;
+            const uint32_t hu = __shfl(u, h, WAVE), hj0 = __shfl(j0, h, WAVE), hj1 = __shfl(j1, h, WAVE);
+            if (hj1 - hj0 > ADJ_HEAVY) {
+                if ((int)__lane_id() == h) heavy[atomicAdd(nheavy, 1u)] = hu;
+                continue;
+            }
+            for (uint32_t j = hj0 + __lane_id(); j < hj1; j += WAVE) {
+                const uint32_t e = inc[j], b = pin_off[e], x = pins[b], y = pins[b + 1];
+                adj[j] = x == hu ? y : x;
+                adjw[j] = nwgt[e];
+            }
+        }
+    }
+}
+
+// Listed heavy vertices: their incidence ranges spread over the whole grid.
+__global__ __launch_bounds__(BLOCK) void k_graph_adj_heavy(const uint32_t *inc_off, const uint32_t *inc,
+                                                           const uint32_t *pin_off, const uint32_t *pins,
+                                                           const int32_t *nwgt, const uint32_t *heavy,
+                                                           const uint32_t *nheavy, uint32_t *adj, int32_t *adjw) {
+    const uint32_t cnt = *nheavy;
+    for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t u = heavy[i], j0 = inc_off[u], j1 = inc_off[u + 1];
+        for (uint32_t j = j0 + blockIdx.x * BLOCK + threadIdx.x; j < j1; j += gridDim.x * BLOCK) {
+            const uint32_t e = inc[j], b = pin_off[e], x = pins[b], y = pins[b + 1];
+            adj[j] = x == u ? y : x;
+            adjw[j] = nwgt[e];
+        }
+    }
+}
+
+// Objective (edge cut) and cut bits of a graph level, a thread per edge.
+__global__ __launch_bounds__(BLOCK) void k_conn_graph(const uint32_t *pin_off, const uint32_t *pins, uint32_t m,
+                                                      const int32_t *nwgt, const uint32_t *part, int64_t *f,
+                                                      uint64_t *cutbits) {
+    __shared__ int64_t red[BLOCK / WAVE];
+    int64_t acc = 0;
+    for (uint32_t e0 = blockIdx.x * blockDim.x; e0 < m; e0 += gridDim.x * blockDim.x) {
+        const uint32_t e = e0 + threadIdx.x;
+        bool cut = false;
+        if (e < m) {
+            const uint32_t b = pin_off[e];
+            cut = part[pins[b]] != part[pins[b + 1]];
+            if (cut) acc += nwgt[e];
+        }
+        const uint64_t word = __ballot(cut);
+        const uint32_t ebase = e0 + (threadIdx.x & ~(WAVE - 1));
+        if (__lane_id() == 0 && ebase < m) cutbits[ebase / WAVE] = word;
+    }
+    acc = wave_sum(acc);
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) t += red[q];
+        if (t) spread_add_i64(f, t);
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_block_weights(const uint32_t *part, const int32_t *vwgt, uint32_t n,
                                                          uint32_t k, int64_t *bw) {
     __shared__ int64_t h[256];
@@ -241,7 +354,35 @@ struct GainArgs {
     uint32_t *pc;  // [k*k] number of proposals per ordered block pair
     uint32_t k;
     LpCtl ctl;
+    // Graph levels (every net has two pins): adj[j] is the other endpoint of
+    // the j-th incident net of its vertex and adjw[j] that net's weight, so a
+    // gain reads the neighbour's block instead of a net record.  nullptr on
+    // hypergraph levels.
+    const uint32_t *adj = nullptr;
+    const int32_t *adjw = nullptr;
 };
+
+// Record of incident net j of a vertex in block s: the net record, or on a
+// graph level the one it stands for: Lambda = {s, b} and Lambda1 = Lambda if
+// the neighbour's block b differs from s, else empty.
+template <int KW>
+__device__ inline NetRec<KW> graph_rec(uint32_t s, uint32_t b, int32_t w) {
+    NetRec<KW> R;
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+        const uint64_t bits = (((uint32_t)q == (s >> 6)) ? (1ull << (s & 63)) : 0ull) |
+                              (((uint32_t)q == (b >> 6)) ? (1ull << (b & 63)) : 0ull);
+        R.lam[q] = bits;
+        R.lam1[q] = b != s ? bits : 0ull;
+    }
+    R.w = w;
+    return R;
+}
+template <int KW>
+__device__ inline NetRec<KW> inc_rec(const GainArgs<KW> &a, uint32_t j, uint32_t s) {
+    if (a.adj) return graph_rec<KW>(s, a.part[a.adj[j]], a.adjw[j]);
+    return a.nr[a.inc[j]];
+}
 
 // Proposal lists: NSLOT lists by vertex chunk (see GainArgs).
 constexpr uint32_t NSLOT = SPREAD;
@@ -315,10 +456,13 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
                 uint32_t ev[NC];
                 int32_t wv[NC];
                 uint64_t lv[NC][KW];
+                // all incidence loads, then all record (or neighbour block) loads
+                int32_t gw[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const uint32_t j = j0 + l + (uint32_t)c * G;
-                    ev[c] = j < j1 ? a.inc[j] : NONE;
+                    ev[c] = j < j1 ? (a.adj ? a.adj[j] : a.inc[j]) : NONE;
+                    gw[c] = (j < j1 && a.adj) ? a.adjw[j] : 0;
                 }
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
@@ -327,7 +471,7 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
 #pragma unroll
                     for (int q = 0; q < KW; ++q) lv[c][q] = 0;
                     if (ev[c] != NONE) {
-                        const NetRec<KW> &R = a.nr[ev[c]];
+                        const NetRec<KW> R = a.adj ? graph_rec<KW>(s, a.part[ev[c]], gw[c]) : a.nr[ev[c]];
                         wv[c] = (int32_t)R.w;
 #pragma unroll
                         for (int q = 0; q < KW; ++q) lv[c][q] = R.lam[q];
@@ -373,7 +517,7 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
                 for (int q = 0; q < KW; ++q) aff[q * 64 + l] = 0;
                 wave_sync();
                 for (uint32_t j = j0 + l; j < j1; j += G) {
-                    const NetRec<KW> &R = a.nr[a.inc[j]];
+                    const NetRec<KW> R = inc_rec<KW>(a, j, s);
                     const int64_t w = R.w;
                     wI += w;
                     if ((R.lam1[s >> 6] >> (s & 63)) & 1ull) bu += w;
@@ -527,7 +671,7 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
 #pragma unroll
         for (int q = 0; q < KW; ++q) U[q] = 0;
         for (uint32_t j = j0 + tid; j < j1; j += HUB_THREADS) {
-            const NetRec<KW> &R = a.nr[a.inc[j]];
+            const NetRec<KW> R = inc_rec<KW>(a, j, s);
             const int64_t wt = R.w;
             wI += wt;
             if ((R.lam1[s >> 6] >> (s & 63)) & 1ull) bu += wt;
@@ -1165,11 +1309,31 @@ __global__ __launch_bounds__(BLOCK) void k_account_update(const uint32_t *pin_of
 // it): Lambda / Lambda1 from the pins' blocks, boundary counts of its pins on
 // a cut flip; nets of more than 64 pins go to the long-net list.  Returns the
 // objective change w(e) (max(lambda'-1,0) - max(lambda-1,0)).
+// Graph levels keep no net records: the cut bit of every edge (the bitmap
+// the connectivity kernel leaves) is the state, and an edge's update
+// compares it with its endpoints' blocks now.  cut == nullptr on hypergraph
+// levels.
+struct GraphUpd {
+    const int32_t *nwgt;
+    uint32_t *cut;
+};
+
 template <int KW>
 __device__ inline int64_t update_net(const uint32_t *pin_off, const uint32_t *pins, uint32_t e, const uint32_t *part,
                                      NetRec<KW> *nr, uint32_t *tstamp, uint32_t stamp, uint32_t *longl,
-                                     uint32_t *nlong, uint32_t *bcnt) {
+                                     uint32_t *nlong, uint32_t *bcnt, const GraphUpd &gu) {
     if (atomicExch(&tstamp[e], stamp) == stamp) return 0;
+    if (gu.cut) {
+        const uint32_t b = pin_off[e], x = pins[b], y = pins[b + 1];
+        const bool now = part[x] != part[y];
+        const bool was = (gu.cut[e >> 5] >> (e & 31)) & 1u;
+        if (now == was) return 0;
+        atomicXor(&gu.cut[e >> 5], 1u << (e & 31));
+        const uint32_t delta = now ? 1u : 0xFFFFFFFFu;
+        atomicAdd(&bcnt[x], delta);
+        atomicAdd(&bcnt[y], delta);
+        return now ? (int64_t)gu.nwgt[e] : -(int64_t)gu.nwgt[e];
+    }
     const uint32_t b = pin_off[e], len = pin_off[e + 1] - b;
     if (len > 64) {
         longl[atomicAdd(nlong, 1u)] = e;
@@ -1200,7 +1364,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_heavy(const uint32_t *pin_o
                                                            const uint32_t *heavy, const uint32_t *nheavy,
                                                            const uint32_t *part, NetRec<KW> *nr, uint32_t *tstamp,
                                                            uint32_t stamp, int64_t *f, uint32_t *longl,
-                                                           uint32_t *nlong, uint32_t *bcnt, LpCtl ctl) {
+                                                           uint32_t *nlong, uint32_t *bcnt, LpCtl ctl, GraphUpd gu) {
     if (lp_skip(ctl)) return;
     __shared__ int64_t red[BLOCK / WAVE];
     const uint32_t cnt = *nheavy;
@@ -1209,7 +1373,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_heavy(const uint32_t *pin_o
         const uint32_t u = heavy[h];
         const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
         for (uint32_t j = j0 + blockIdx.x * BLOCK + threadIdx.x; j < j1; j += gridDim.x * BLOCK)
-            acc += update_net<KW>(pin_off, pins, inc[j], part, nr, tstamp, stamp, longl, nlong, bcnt);
+            acc += update_net<KW>(pin_off, pins, inc[j], part, nr, tstamp, stamp, longl, nlong, bcnt, gu);
     }
     acc = wave_sum(acc);
     if (__lane_id() == 0) red[threadIdx.x / WAVE] = acc;
@@ -1263,7 +1427,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
                                                             uint32_t stamp, int64_t *f, uint32_t *longl,
                                                             uint32_t *nlong, uint32_t *moves, uint32_t *bcnt,
                                                             uint32_t *heavy, uint32_t *nheavy, NextSub z,
-                                                            LpCtl ctl) {
+                                                            LpCtl ctl, GraphUpd gu) {
     if (lp_skip(ctl)) return;
     next_subround(z);
     __shared__ int64_t red[BLOCK / WAVE];
@@ -1287,7 +1451,7 @@ __global__ __launch_bounds__(BLOCK) void k_lp_update_movers(const uint32_t *pin_
             continue;
         }
         for (uint32_t j = j0 + l; j < j1; j += G)
-            acc += update_net<KW>(pin_off, pins, inc[j], part, nr, tstamp, stamp, longl, nlong, bcnt);
+            acc += update_net<KW>(pin_off, pins, inc[j], part, nr, tstamp, stamp, longl, nlong, bcnt, gu);
     }
     acc = wave_sum(acc);
     if (moved) moved_any = 1u;
@@ -1458,7 +1622,43 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         k_zero_words<<<grid_for(std::max<size_t>(m, (size_t)k * k), BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(z);
         HGP_LAUNCH_CHECK();
     }
-    build_conn<KW>(h, part, B, st, true);
+    // degree classes of the nodes (lanes per node 1 / 8 / 64) and the largest net
+    k_deg_classify<<<grid_for(n, BLOCK, REDUCE_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt);
+    HGP_LAUNCH_CHECK();
+    if (h.m) {
+        k_max_net<<<grid_for(h.m, BLOCK, REDUCE_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.m, B.scal + 4);
+        HGP_LAUNCH_CHECK();
+    }
+    uint32_t dc[NDEG], hs[16];
+    HGP_CHECK_HIP(hipMemcpyAsync(hs, B.scal, sizeof(hs), hipMemcpyDeviceToHost, st));
+    stream_sync(st);
+    for (int c = 0; c < NDEG; ++c) dc[c] = hs[5 + c];
+    const bool long_nets = hs[4] > 64;  // nets of more than 64 pins exist on this level
+    // A graph level (every net has two pins) keeps no net records: the
+    // adjacency array (built here when the workspace has room for it) and the
+    // cut bits stand in for them.
+    GraphUpd gupd{h.nwgt, nullptr};
+    const uint32_t *adj = nullptr;
+    const int32_t *adjw = nullptr;
+    if (h.m && hs[4] == 2 && (uint64_t)h.p == 2ull * h.m && A.remaining() >= 8ull * h.p + 1024) {
+        uint32_t *ad = A.alloc<uint32_t>(h.p);
+        int32_t *aw = A.alloc<int32_t>(h.p);
+        uint32_t *nheavy_adj = B.scal + 27;  // cleared with the level's scalars
+        k_graph_adj<<<grid_for(n, BLOCK, 4 * FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, h.pin_off, h.pins,
+                                                                          h.nwgt, n, ad, aw, B.heavy, nheavy_adj);
+        HGP_LAUNCH_CHECK();
+        k_graph_adj_heavy<<<FILL_BLOCKS / 2, BLOCK, 0, st>>>(h.inc_off, h.inc, h.pin_off, h.pins, h.nwgt, B.heavy,
+                                                            nheavy_adj, ad, aw);
+        HGP_LAUNCH_CHECK();
+        k_conn_graph<<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.pins, h.m, h.nwgt, part,
+                                                                          B.f, B.cut);
+        HGP_LAUNCH_CHECK();
+        adj = ad;
+        adjw = aw;
+        gupd.cut = (uint32_t *)B.cut;
+    } else {
+        build_conn<KW>(h, part, B, st, true);
+    }
     k_block_weights<<<grid_for(n, BLOCK * 8, REDUCE_BLOCKS), BLOCK, 0, st>>>(part, h.vwgt, n, k, B.bw);
     HGP_LAUNCH_CHECK();
     if ((uint64_t)h.p >= (uint64_t)16 * n)  // average degree of at least 16: a wave per node
@@ -1468,14 +1668,6 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         k_init_bcnt<KW><<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n,
                                                                            (const uint32_t *)B.cut, B.bcnt);
     HGP_LAUNCH_CHECK();
-    // degree classes of the nodes (lanes per node 1 / 8 / 64)
-    k_deg_classify<<<grid_for(n, BLOCK, REDUCE_BLOCKS), BLOCK, 0, st>>>(h.inc_off, n, dcnt);
-    HGP_LAUNCH_CHECK();
-    uint32_t dc[NDEG], hs[16];
-    HGP_CHECK_HIP(hipMemcpyAsync(hs, B.scal, sizeof(hs), hipMemcpyDeviceToHost, st));
-    stream_sync(st);
-    for (int c = 0; c < NDEG; ++c) dc[c] = hs[5 + c];
-    const bool long_nets = hs[12] > 0;  // nets of more than 64 pins exist on this level
     const uint32_t S = prm.lp_subrounds;
     // gains: chunks of `gch` vertices (a power of two in [64, GAIN_CH], about
     // n / 1024, so that even small levels spread over many workgroups)
@@ -1607,7 +1799,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             auto launch = [&](auto kern, uint32_t blocks) {
                 kern<<<blocks, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.plist, pcnt_of(stamp), slot_cap,
                                                B.prop_t, part, (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl,
-                                               nlong, moved, B.bcnt, B.heavy, nheavy, zn, ctl);
+                                               nlong, moved, B.bcnt, B.heavy, nheavy, zn, ctl, gupd);
             };
             if (upd_g == 8) launch(k_lp_update_movers<KW, 8>, upd_blocks);
             else if (upd_g == 16) launch(k_lp_update_movers<KW, 16>, upd_blocks);
@@ -1617,7 +1809,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         if (dc[3]) {  // the level has nodes of more than HUB_DEG nets
             k_lp_update_heavy<KW><<<512, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.heavy, nheavy, part,
                                                          (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl, nlong,
-                                                         B.bcnt, ctl);
+                                                         B.bcnt, ctl, gupd);
             HGP_LAUNCH_CHECK();
         }
         if (long_nets) {
@@ -1630,9 +1822,11 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     auto subround = [&](uint32_t r, uint32_t s) {
         const uint32_t stamp = 1 + r * S + s;
         const LpCtl ctl = ctl_of(stamp);
-        const GainArgs<KW> ga{h.inc_off, h.inc, h.vwgt, (const NetRec<KW> *)B.nr, part, B.bw, B.bcnt, lmax, mseed,
+        GainArgs<KW> ga{h.inc_off, h.inc, h.vwgt, (const NetRec<KW> *)B.nr, part, B.bw, B.bcnt, lmax, mseed,
                               level, r, s, S, n, B.prop_t, B.prop_g, B.plist, pcnt_of(stamp), gch, slot_cap,
                               B.pw, B.pc, k, ctl};
+        ga.adj = adj;
+        ga.adjw = adjw;
         if (accounting(KID_GAINS)) {
             Timing &T = timing();
             ++T.stamp;
@@ -1696,8 +1890,18 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             update(stamp);
             r0 = (stamp - 1) / S;
             s0 = (stamp - 1) % S + 1;
-            if (s0 == S) { ++r0; s0 = 0; }
+            rounds_run = r0 + 1;
             batch = 1;
+            if (s0 == S) {
+                // the hand-over finished its round: a round without moves
+                // ends LP here as well
+                uint32_t mv = 0;
+                HGP_CHECK_HIP(hipMemcpyAsync(&mv, B.rmoves + r0, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+                stream_sync(st);
+                if (mv == 0) break;
+                ++r0;
+                s0 = 0;
+            }
             continue;
         }
         // a round without moves ends LP (the rounds after it did nothing)

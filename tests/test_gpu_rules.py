@@ -104,3 +104,21 @@ def test_partition_workspace_too_small_for_the_hierarchy(hgp, orc):
     L = P.run()
     assert (L, int(P.f.item())) == (L_o, f_o)
     assert np.array_equal(P.part.cpu().numpy().view(np.uint32), part_o)
+
+
+@pytest.mark.parametrize("name,k,seed", [("stencil24", 8, 2), ("random120k", 2, 5), ("rmat16", 128, 4)])
+def test_trace_matches_oracle_levels(hgp, orc, name, k, seed):
+    # level sizes and LP rounds of hgp_partition_traced; random120k with
+    # k = 2 hands a block pair of more than 4096 proposals to the
+    # device-wide path in its last sub-rounds, which must not lose the count
+    import test_gpu_parity as TP
+    H = hgp
+    h = TP.make(name)
+    lv = orc.hierarchy(h, orc.params(k, seed=seed))
+    G = H.Hypergraph.from_host(h)
+    P = H.Partitioner(G, H.params(k, seed=seed))
+    tr = P.run_traced()
+    assert len(tr) == len(lv)
+    for t, L in zip(tr, lv):
+        assert (t["n"], t["m"], t["p"]) == (L["h"].n, L["h"].m, L["h"].p)
+        assert t["lp_rounds"] == L["lp_rounds"]
