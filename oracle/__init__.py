@@ -81,6 +81,8 @@ def lib():
         L.or_graph_adjacency.restype = ctypes.c_int; L.or_graph_adjacency.argtypes = [P, P, P]
         L.or_graph_gain.restype = i64; L.or_graph_gain.argtypes = [P, P, P, P, u32, u32]
         L.or_graph_cut.restype = i64; L.or_graph_cut.argtypes = [P, P]
+        L.or_graph_gain_table.restype = ctypes.c_int; L.or_graph_gain_table.argtypes = [P, u32, P, P]
+        L.or_graph_moves.restype = ctypes.c_int; L.or_graph_moves.argtypes = [P, u32, P, P, P, u32, P, P]
         _lib = L
     return _lib
 
@@ -278,6 +280,32 @@ def graph_cut(h, part) -> int:
     v = _View(h)
     part = np.ascontiguousarray(part, np.uint32)
     return int(lib().or_graph_cut(v.ref, _ptr(part)))
+
+
+def graph_gain_table(h, k: int, part):
+    """w(u, V_i) as an (n, k) int64 array, or None when a net has other than two pins."""
+    v = _View(h)
+    part = np.ascontiguousarray(part, np.uint32)
+    om = np.zeros((max(h.n, 1), k), np.int64)
+    if lib().or_graph_gain_table(v.ref, k, _ptr(part), _ptr(om)) != 0:
+        return None
+    return om[:h.n]
+
+
+def graph_moves(h, k: int, part, node, target, omega=None):
+    """Moves made in order on a graph: returns (new part, attributed gains,
+    updated omega or None).  Raises ValueError on invalid moves."""
+    v = _View(h)
+    part = np.array(part, np.uint32)
+    node = np.ascontiguousarray(node, np.uint32)
+    target = np.ascontiguousarray(target, np.uint32)
+    g = np.zeros(max(len(node), 1), np.int64)
+    om = None if omega is None else np.array(omega, np.int64).reshape(h.n, k)
+    rc = lib().or_graph_moves(v.ref, k, _ptr(part), _ptr(node), _ptr(target), len(node),
+                              None if om is None else _ptr(om), _ptr(g))
+    if rc != 0:
+        raise ValueError("invalid moves or not a graph")
+    return part, g[:len(node)], om
 
 
 def partition(h, P: Params):

@@ -879,3 +879,67 @@ int64_t or_graph_cut(const or_hg *h, const uint32_t *part)
         if (part[h->pins[h->pin_off[e]]] != part[h->pins[h->pin_off[e] + 1]]) c += h->nwgt[e];
     return c;
 }
+
+/* Graph gain table (Sec. 10): omega[u * k + i] = w(u, V_i), the total weight
+ * of u's edges whose other endpoint lies in block i, summed over the
+ * adjacency from the definition. */
+int or_graph_gain_table(const or_hg *h, uint32_t k, const uint32_t *part, int64_t *omega)
+{
+    for (uint32_t e = 0; e < h->m; ++e)
+        if (h->pin_off[e + 1] - h->pin_off[e] != 2) return OR_E_INVALID;
+    memset(omega, 0, sizeof(int64_t) * (size_t)h->n * k);
+    for (uint32_t u = 0; u < h->n; ++u)
+        for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+            const uint32_t e = h->inc[j];
+            const uint32_t a = h->pins[h->pin_off[e]], b = h->pins[h->pin_off[e] + 1];
+            const uint32_t v = (a == u) ? b : a;
+            omega[(size_t)u * k + part[v]] += h->nwgt[e];
+        }
+    return OR_OK;
+}
+
+/* A batch of moves on a graph (Sec. 10), made one after the other in the
+ * order given, every node at most once.  Moving u from V_s to V_t adds w(u, v)
+ * to w(v, V_t) and subtracts it from w(v, V_s) for every neighbour v (when
+ * omega is not NULL), then sets Pi[u] = t.  The attributed gain of the move
+ * (when gain is not NULL) sums, over the edges {u, v} of u, +w(e) for an edge
+ * that stops being cut and -w(e) for one that becomes cut, with v in the
+ * block it holds when u moves (reading R15: an edge whose state does not
+ * change is attributed nothing).  A move to the node's own block is no move
+ * (gain 0).  Invalid moves (node or block out of range, a node listed twice)
+ * are rejected before anything changes. */
+int or_graph_moves(const or_hg *h, uint32_t k, uint32_t *part, const uint32_t *mu, const uint32_t *mt,
+                   uint32_t l, int64_t *omega, int64_t *gain)
+{
+    for (uint32_t e = 0; e < h->m; ++e)
+        if (h->pin_off[e + 1] - h->pin_off[e] != 2) return OR_E_INVALID;
+    uint8_t *seen = (uint8_t *)calloc(h->n ? h->n : 1, 1);
+    if (!seen) return OR_E_NOMEM;
+    for (uint32_t i = 0; i < l; ++i) {
+        if (mu[i] >= h->n || mt[i] >= k || seen[mu[i]]) { free(seen); return OR_E_INVALID; }
+        seen[mu[i]] = 1;
+    }
+    free(seen);
+    for (uint32_t i = 0; i < l; ++i) {
+        const uint32_t u = mu[i], s = part[u], t = mt[i];
+        int64_t g = 0;
+        if (s != t) {
+            for (uint32_t j = h->inc_off[u]; j < h->inc_off[u + 1]; ++j) {
+                const uint32_t e = h->inc[j];
+                const uint32_t a = h->pins[h->pin_off[e]], b = h->pins[h->pin_off[e] + 1];
+                const uint32_t v = (a == u) ? b : a;
+                const int64_t w = h->nwgt[e];
+                const int was_cut = part[v] != s, now_cut = part[v] != t;
+                if (was_cut && !now_cut) g += w;
+                if (!was_cut && now_cut) g -= w;
+                if (omega) {
+                    omega[(size_t)v * k + t] += w;
+                    omega[(size_t)v * k + s] -= w;
+                }
+            }
+            part[u] = t;
+        }
+        if (gain) gain[i] = g;
+    }
+    return OR_OK;
+}

@@ -79,3 +79,60 @@ def test_graph_contraction_drops_self_loops_and_merges_parallel_edges(orc, seed)
         for t in range(3):
             if t != part[u]:
                 assert orc.graph_gain(H, adj, adjw, part, u, t) == bf.move_delta(H, part, u, t)
+
+
+def _moves(rs, n, k, part, count, noop=2):
+    us = rs.choice(n, size=count, replace=False).astype(np.uint32)
+    ts = np.array([(int(part[u]) + 1 + rs.randint(k - 1)) % k for u in us], np.uint32)
+    ts[:noop] = part[us[:noop]]  # moves to the node's own block
+    return us, ts
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_graph_gain_table_is_w_u_vi(orc, seed):
+    h, edges = random_graph(seed)
+    rs = np.random.RandomState(300 + seed)
+    for k in (2, 3, 6):
+        part = rs.randint(0, k, size=h.n).astype(np.uint32)
+        om = orc.graph_gain_table(h, k, part)
+        # each entry from its definition over the edge list
+        want = np.zeros((h.n, k), np.int64)
+        for (a, b), w in zip(edges, h.nwgt):
+            want[a, part[b]] += int(w)
+            want[b, part[a]] += int(w)
+        assert np.array_equal(om, want)
+        # gain = w(u, V_t) - w(u, V_Pi[u]) = the objective decrease by brute force
+        for u in range(h.n):
+            for t in range(k):
+                if t != part[u]:
+                    assert om[u, t] - om[u, part[u]] == bf.move_delta(h, part, u, t), (u, t)
+    assert orc.graph_gain_table(W.from_nets(4, [[0, 1], [1, 2, 3]]), 2, np.zeros(4, np.uint32)) is None
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_graph_table_update_and_attributed_gains(orc, seed):
+    h, edges = random_graph(seed, n=16, m=40)
+    rs = np.random.RandomState(400 + seed)
+    for k in (2, 4):
+        part = rs.randint(0, k, size=h.n).astype(np.uint32)
+        us, ts = _moves(rs, h.n, k, part, 9)
+        om0 = orc.graph_gain_table(h, k, part)
+        new, g, om = orc.graph_moves(h, k, part, us, ts, om0)
+        want_part = part.copy()
+        want_part[us] = ts
+        assert np.array_equal(new, want_part)
+        # the updated table is the table of the new partition
+        assert np.array_equal(om, orc.graph_gain_table(h, k, new))
+        # attributed gains: the objective decrease of each move made in order
+        moves = list(zip(us.tolist(), ts.tolist()))
+        assert g.tolist() == bf.sequence_gains(h, part, moves)
+        assert int(g.sum()) == bf.objective(h, part) - bf.objective(h, new)
+        assert g.tolist() == orc.gain_recalc(h, k, part, us, ts).tolist()
+
+
+def test_graph_moves_rejects_invalid(orc):
+    h, _ = random_graph(1)
+    part = np.zeros(h.n, np.uint32)
+    for us, ts in (([1, 2, 1], [1, 1, 1]), ([h.n], [1]), ([3], [2])):
+        with pytest.raises(ValueError):
+            orc.graph_moves(h, 2, part, us, ts)
