@@ -101,7 +101,7 @@ typedef struct {
 #define HGP_OP_PARTITION 4
 #define HGP_OP_VALIDATE 5
 #define HGP_OP_INITIAL 6
-#define HGP_OP_GAINS 7     /* hgp_gain_table, hgp_gain_table_update, hgp_gain_recalc */
+#define HGP_OP_GAINS 7     /* hgp_gain_table, hgp_gain_table_update, hgp_gain_recalc, hgp_graph_* */
 
 /* Host.  Fills *out with the defaults listed in hgp_params for k blocks. */
 hgp_status hgp_default_params(uint32_t k, hgp_params *out);
@@ -239,6 +239,32 @@ hgp_status hgp_gain_table_update(const hgp_hg *h, uint32_t k, uint32_t *part, co
 hgp_status hgp_gain_recalc(const hgp_hg *h, uint32_t k, const uint32_t *part, const uint32_t *node,
                            const uint32_t *target, uint32_t count, int64_t *gain, void *ws, size_t ws_bytes,
                            void *stream);
+
+/* Graph gain table (paper Sec. 10), for a hypergraph whose nets all have two
+ * pins (edges; HGP_E_INVALID otherwise): omega[u * k + i] (device int32
+ * [n * k], row u = the k values of u) = w(u, V_i), the weight of u's edges
+ * whose other endpoint lies in block i.  Moving u to t lowers the edge cut
+ * (= the connectivity objective of a graph) by omega[u*k+t] - omega[u*k+Pi[u]].
+ * part[n] holds blocks < k.  Workspace: hgp_workspace_bytes(HGP_OP_GAINS, ...).
+ * Syncs. */
+hgp_status hgp_graph_gain_table(const hgp_hg *h, uint32_t k, const uint32_t *part, int32_t *omega, void *ws,
+                                size_t ws_bytes, void *stream);
+
+/* Moves node[i] -> target[i] on a graph (paper Sec. 10; device uint32
+ * [count], every node at most once, targets < k, a move to the node's own
+ * block does nothing), taken as made one after the other in index order.
+ * part is updated.  When omega (device int32 [n * k], a graph gain table of
+ * part) is not NULL it is updated to the table of the new partition: for each
+ * move u: s -> t and each edge {u, v}, w(u, v) is added to omega[v][t] and
+ * subtracted from omega[v][s].  When gain (device int64 [count]) is not NULL,
+ * gain[i] = the attributed gain of move i: over its edges {u, v}, +w for an
+ * edge that stops being cut and -w for one that becomes cut, with v in the
+ * block it holds when move i is made (its target if v's move comes earlier in
+ * the list); the gains sum to the decrease of the edge cut.  Not a graph, a
+ * node listed twice or an index out of range returns HGP_E_INVALID with
+ * everything unchanged.  Workspace: HGP_OP_GAINS.  Syncs. */
+hgp_status hgp_graph_moves(const hgp_hg *h, uint32_t k, uint32_t *part, const uint32_t *node, const uint32_t *target,
+                           uint32_t count, int32_t *omega, int64_t *gain, void *ws, size_t ws_bytes, void *stream);
 
 /* Per-level record of one multilevel partition, in host arrays the caller
  * owns: level l = 0 is the input, l = levels the coarsest level. */

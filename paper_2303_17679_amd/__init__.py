@@ -27,7 +27,8 @@ EXPORTS = ["hgp_default_params", "hgp_workspace_bytes", "hgp_validate", "hgp_coa
            "hgp_timing_scratch_bytes", "hgp_timing_begin", "hgp_timing_end", "hgp_status_str",
            "hgp_server_create", "hgp_server_submit", "hgp_server_wait", "hgp_server_destroy",
            "hgp_batch_workspace_bytes", "hgp_partition_batch", "hgp_refine_lp_static",
-           "hgp_partition_traced", "hgp_gain_table", "hgp_gain_table_update", "hgp_gain_recalc"]
+           "hgp_partition_traced", "hgp_gain_table", "hgp_gain_table_update", "hgp_gain_recalc",
+           "hgp_graph_gain_table", "hgp_graph_moves"]
 
 # kernel ids of the measurement calls, with the kernel symbol each one names
 KERNELS = ["k_rate_group<8, 64, 6>", "k_rate_group<16, 256, 8>", "k_rate_group<64, 1024, 10>", "k_rate_block",
@@ -106,6 +107,10 @@ def lib():
         L.hgp_gain_table_update.argtypes = [P, u32, P, P, P, u32, P, P, P, ctypes.c_size_t, P]
         L.hgp_gain_recalc.restype = i32
         L.hgp_gain_recalc.argtypes = [P, u32, P, P, P, u32, P, P, ctypes.c_size_t, P]
+        L.hgp_graph_gain_table.restype = i32
+        L.hgp_graph_gain_table.argtypes = [P, u32, P, P, P, ctypes.c_size_t, P]
+        L.hgp_graph_moves.restype = i32
+        L.hgp_graph_moves.argtypes = [P, u32, P, P, P, u32, P, P, P, ctypes.c_size_t, P]
         L.hgp_partition_traced.restype = i32
         L.hgp_partition_traced.argtypes = [P, P, P, P, P, P, ctypes.c_size_t, P]
         L.hgp_status_str.restype = ctypes.c_char_p; L.hgp_status_str.argtypes = [i32]
@@ -313,6 +318,30 @@ def gain_recalc(h: Hypergraph, k: int, part, node, target, ws=None):
     _check(lib().hgp_gain_recalc(ctypes.byref(s), k, _ptr(part), _ptr(node), _ptr(target), node.numel(), _ptr(g),
                                  _ptr(ws), ws.numel(), _stream()), "hgp_gain_recalc")
     return g[:node.numel()]
+
+
+def graph_gain_table(h: Hypergraph, k: int, part, ws=None):
+    """hgp_graph_gain_table: omega int32 [n, k] = w(u, V_i) of a graph."""
+    torch = _torch()
+    om = torch.empty((h.n, k), dtype=torch.int32, device=h.device)
+    ws = _ws(OP_GAINS, h, params(k)) if ws is None else ws
+    s = h.struct()
+    _check(lib().hgp_graph_gain_table(ctypes.byref(s), k, _ptr(part), _ptr(om), _ptr(ws), ws.numel(), _stream()),
+           "hgp_graph_gain_table")
+    return om
+
+
+def graph_moves(h: Hypergraph, k: int, part, node, target, omega=None, gains=True, ws=None):
+    """hgp_graph_moves: applies the moves to part, updates omega in place
+    when given, and returns the int64 attributed gains (or None)."""
+    torch = _torch()
+    g = torch.empty(max(node.numel(), 1), dtype=torch.int64, device=h.device) if gains else None
+    ws = _ws(OP_GAINS, h, params(k)) if ws is None else ws
+    s = h.struct()
+    _check(lib().hgp_graph_moves(ctypes.byref(s), k, _ptr(part), _ptr(node), _ptr(target), node.numel(),
+                                 _ptr(omega) if omega is not None else None, _ptr(g) if g is not None else None,
+                                 _ptr(ws), ws.numel(), _stream()), "hgp_graph_moves")
+    return g[:node.numel()] if g is not None else None
 
 
 STATIC_SCRATCH_BYTES = 64 << 20  # HGP_STATIC_SCRATCH_BYTES

@@ -104,7 +104,7 @@ hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p, const
             case HGP_OP_REFINE: need = refine_workspace(n, m, k); break;
             case HGP_OP_VALIDATE: need = util_workspace(n, m); break;
             case HGP_OP_INITIAL: need = ip_workspace(n, p, k); break;
-            case HGP_OP_GAINS: need = gaintable_workspace(n, m, k, n); break;
+            case HGP_OP_GAINS: need = gaintable_workspace(n, m, k, n); break;  // also the graph tables
             case HGP_OP_PARTITION: {
                 size_t temp = std::max({coarsen_workspace(n, m, p, dp), contract_workspace(n, m, p),
                                         refine_workspace(n, m, k), ip_workspace(n, p, k), util_workspace(n, m)});
@@ -349,6 +349,32 @@ hgp_status hgp_gain_recalc(const hgp_hg *h, uint32_t k, const uint32_t *part, co
     return guarded(S(stream), [&]() {
         Arena A(ws, ws_bytes);
         return gain_recalc(*h, k, part, node, target, count, gain, A, S(stream));
+    });
+}
+
+hgp_status hgp_graph_gain_table(const hgp_hg *h, uint32_t k, const uint32_t *part, int32_t *omega, void *ws,
+                                size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h);
+    if (s != HGP_OK) return s;
+    if (k < 2) return HGP_E_INVALID;
+    if (k > 256) return HGP_E_UNSUPPORTED;
+    if (!part || !omega || !ws) return HGP_E_INVALID;
+    return guarded(S(stream), [&]() {
+        Arena A(ws, ws_bytes);
+        return graph_gain_table(*h, k, part, omega, A, S(stream));
+    });
+}
+
+hgp_status hgp_graph_moves(const hgp_hg *h, uint32_t k, uint32_t *part, const uint32_t *node, const uint32_t *target,
+                           uint32_t count, int32_t *omega, int64_t *gain, void *ws, size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h);
+    if (s != HGP_OK) return s;
+    if (k < 2) return HGP_E_INVALID;
+    if (k > 256) return HGP_E_UNSUPPORTED;
+    if (!part || !ws || (count && (!node || !target)) || count > h->n) return HGP_E_INVALID;
+    return guarded(S(stream), [&]() {
+        Arena A(ws, ws_bytes);
+        return graph_moves(*h, k, part, node, target, count, omega, gain, A, S(stream));
     });
 }
 

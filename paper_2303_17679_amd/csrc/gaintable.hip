@@ -590,6 +590,189 @@ __global__ __launch_bounds__(BLOCK) void k_gt_apply(MoveView M, const uint32_t *
     }
 }
 
+// ---------------------------------------------------------------------------
+// Graphs (paper Sec. 10): every net is an edge of two pins, so pin_off[e] =
+// 2e and the pin array is the edge list (endpoints pins[2e], pins[2e + 1]).
+// The gain table holds w(u, V_i) for every node and block (omega, int32
+// [n * k]); the gain of moving u to t is omega[u][t] - omega[u][Pi[u]].
+// ---------------------------------------------------------------------------
+
+// Number of nets of other than two pins (one atomic per workgroup).
+__global__ __launch_bounds__(BLOCK) void k_non_edges(const uint32_t *pin_off, uint32_t m, uint32_t *bad) {
+    uint32_t c = 0;
+    for (uint32_t e = blockIdx.x * BLOCK + threadIdx.x; e < m; e += gridDim.x * BLOCK)
+        c += pin_off[e + 1] - pin_off[e] != 2;
+    c = wave_sum(c);
+    __shared__ uint32_t red[BLOCK / WAVE];
+    if (__lane_id() == 0) red[threadIdx.x / WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < BLOCK / WAVE; ++q) c += red[q];
+        if (c) atomicAdd(bad, c);
+    }
+}
+
+// Rows of omega: a wave per contiguous range of vertices, batches of
+// consecutive vertices whose edges fill the 64 lanes (each lane loads one
+// edge: its other endpoint's block and its weight), then every row of the
+// batch is summed by the lanes that own its blocks (lane l owns blocks
+// q * 64 + l) from wave-uniform register reads and leaves as one coalesced
+// store.  A vertex of more than 64 edges is a batch of its own.
+template <int KW>
+__device__ inline void add_edge_to_row(uint32_t blk, int32_t w, uint32_t lane, int64_t (&acc)[KW]) {
+#pragma unroll
+    for (int q = 0; q < KW; ++q)
+        if (blk == (uint32_t)q * 64 + lane) acc[q] += w;
+}
+
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_ggt_rows(const uint32_t *inc_off, const uint32_t *inc, const uint32_t *pins,
+                                                    const int32_t *nwgt, const uint32_t *part, uint32_t n, uint32_t k,
+                                                    int32_t *omega) {
+    const uint32_t lane = __lane_id();
+    const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nwv = gridDim.x * (BLOCK / WAVE);
+    const uint32_t per = (uint32_t)(((uint64_t)n + nwv - 1) / nwv);
+    uint32_t u = (uint32_t)min((uint64_t)wid * per, (uint64_t)n);
+    const uint32_t uend = (uint32_t)min((uint64_t)u + per, (uint64_t)n);
+    // the block of the other endpoint of the edge at incidence slot j of v
+    auto far_block = [&](uint32_t j, uint32_t v, int32_t *w) {
+        const uint32_t e = inc[j];
+        const uint32_t x = pins[2 * (size_t)e], y = pins[2 * (size_t)e + 1];
+        *w = nwgt[e];
+        return part[x == v ? y : x];
+    };
+    while (u < uend) {  // uniform per wave
+        const uint32_t cand = u + lane;
+        uint32_t o = 0, d = 0;
+        if (cand < uend) {
+            o = inc_off[cand];
+            d = inc_off[cand + 1] - o;
+        }
+        uint32_t pre = d;
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const uint32_t t = __shfl_up(pre, off, WAVE);
+            if (lane >= (uint32_t)off) pre += t;
+        }
+        const uint64_t fit = __ballot(cand < uend && pre <= WAVE);  // a prefix of the lanes
+        const uint32_t nb = (uint32_t)__popcll(fit);
+        if (nb == 0) {  // one vertex of more than 64 edges
+            const uint32_t j0 = lane_i32((int32_t)o, 0), j1 = j0 + lane_i32((int32_t)d, 0);
+            int64_t acc[KW];
+#pragma unroll
+            for (int q = 0; q < KW; ++q) acc[q] = 0;
+            for (uint32_t c0 = j0; c0 < j1; c0 += WAVE) {
+                const uint32_t j = c0 + lane;
+                int32_t w = 0;
+                uint32_t b = NONE;
+                if (j < j1) b = far_block(j, u, &w);
+                const uint32_t cn = j1 - c0 < WAVE ? j1 - c0 : WAVE;
+                for (uint32_t c = 0; c < cn; ++c)
+                    add_edge_to_row<KW>((uint32_t)lane_i32((int32_t)b, c), lane_i32(w, c), lane, acc);
+            }
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                const uint32_t t = (uint32_t)q * 64 + lane;
+                if (t < k) omega[(size_t)u * k + t] = (int32_t)acc[q];
+            }
+            u += 1;
+            continue;
+        }
+        const uint32_t total = (uint32_t)lane_i32((int32_t)pre, nb - 1);
+        int32_t w = 0;
+        uint32_t b = NONE;
+        {
+            uint32_t lo = 0, hi = nb - 1;  // first i in [0, nb) with pre_i > lane
+#pragma unroll
+            for (int it = 0; it < 6; ++it) {
+                const uint32_t mid = (lo + hi) >> 1;
+                const uint32_t pm = (uint32_t)__shfl((int)pre, (int)mid, WAVE);
+                if (lo < hi) {
+                    if (pm > lane) hi = mid; else lo = mid + 1;
+                }
+            }
+            const uint32_t own = lo;
+            const uint32_t po = (uint32_t)__shfl((int)pre, (int)own, WAVE);
+            const uint32_t dd = (uint32_t)__shfl((int)d, (int)own, WAVE);
+            const uint32_t oo = (uint32_t)__shfl((int)o, (int)own, WAVE);
+            if (lane < total) b = far_block(oo + (lane - (po - dd)), u + own, &w);
+        }
+        uint32_t c = 0;
+        for (uint32_t i = 0; i < nb; ++i) {
+            const uint32_t ci = c + (uint32_t)lane_i32((int32_t)d, i);
+            int64_t acc[KW];
+#pragma unroll
+            for (int q = 0; q < KW; ++q) acc[q] = 0;
+            for (; c < ci; ++c) add_edge_to_row<KW>((uint32_t)lane_i32((int32_t)b, c), lane_i32(w, c), lane, acc);
+            const uint32_t v = u + i;
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                const uint32_t t = (uint32_t)q * 64 + lane;
+                if (t < k) omega[(size_t)v * k + t] = (int32_t)acc[q];
+            }
+        }
+        u += nb;
+    }
+}
+
+// Moves on a graph, in index order.  For move i (u: s -> t) and an edge
+// {u, v}: v stands in target[j] when its move j comes before i, else in its
+// block before the moves (M.moved and the node -> move index map decide, so
+// the caller's order settles which of an edge's two moves is first).  The
+// move is attributed +w when the edge stops being cut and -w when it starts
+// being cut; the neighbour rows change by +w at t and -w at s (integer
+// atomics: any order gives the same table).  A lane per move of up to 32
+// edges, a wave per larger move.
+__device__ inline void graph_edge(const MoveView &M, uint32_t i, uint32_t u, uint32_t s, uint32_t t, uint32_t e,
+                                  const uint32_t *pins, const int32_t *nwgt, uint32_t k, int32_t *omega,
+                                  int64_t *g) {
+    const uint32_t x = pins[2 * (size_t)e], y = pins[2 * (size_t)e + 1];
+    const uint32_t v = x == u ? y : x;
+    const int32_t w = nwgt[e];
+    uint32_t jv;
+    const uint32_t bv = (M.moved(v, &jv) && jv < i) ? M.target[jv] : M.part[v];
+    const bool was = bv != s, now = bv != t;
+    if (was && !now) *g += w;
+    if (!was && now) *g -= w;
+    if (omega) {
+        atomicAdd(&omega[(size_t)v * k + t], w);
+        atomicAdd(&omega[(size_t)v * k + s], -w);
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_graph_moves(MoveView M, const uint32_t *node, uint32_t count,
+                                                       const uint32_t *inc_off, const uint32_t *inc,
+                                                       const uint32_t *pins, const int32_t *nwgt, uint32_t k,
+                                                       int32_t *omega, int64_t *gain) {
+    const uint32_t lane = __lane_id();
+    for (uint32_t b0 = blockIdx.x * BLOCK; b0 < count; b0 += gridDim.x * BLOCK) {
+        const uint32_t i = b0 + threadIdx.x;
+        uint32_t u = 0, s = 0, t = 0, j0 = 0, j1 = 0, iu;
+        const bool act = i < count && M.from[i] != NONE && M.moved(node[i], &iu);
+        if (act) {
+            u = node[i]; s = M.from[i]; t = M.target[i];
+            j0 = inc_off[u]; j1 = inc_off[u + 1];
+        }
+        const bool wide = act && j1 - j0 > 32;
+        int64_t g = 0;
+        if (act && !wide)
+            for (uint32_t j = j0; j < j1; ++j) graph_edge(M, i, u, s, t, inc[j], pins, nwgt, k, omega, &g);
+        if (gain && i < count && !wide) gain[i] = g;
+        uint64_t wm = __ballot(wide);
+        while (wm) {  // the wave takes its wide moves one at a time
+            const int h = __ffsll((long long)wm) - 1;
+            wm &= wm - 1;
+            const uint32_t hi_ = __shfl(i, h, WAVE), hu = __shfl(u, h, WAVE), hs = __shfl(s, h, WAVE),
+                           ht = __shfl(t, h, WAVE), hj0 = __shfl(j0, h, WAVE), hj1 = __shfl(j1, h, WAVE);
+            int64_t hg = 0;
+            for (uint32_t j = hj0 + lane; j < hj1; j += WAVE)
+                graph_edge(M, hi_, hu, hs, ht, inc[j], pins, nwgt, k, omega, &hg);
+            hg = wave_sum(hg);
+            if (gain && (int)lane == h) gain[hi_] = hg;
+        }
+    }
+}
+
 struct GtBufs {
     uint64_t *lam, *lam1;
     uint32_t *idx, *from, *stamp, *longl, *scal;
@@ -715,6 +898,66 @@ hgp_status gain_recalc(const hgp_hg &h, uint32_t k, const uint32_t *part, const 
     HGP_LAUNCH_CHECK();
     k_gt_long<OP_RECALC><<<FILL_BLOCKS / 4, BLOCK, 0, st>>>(M, B.longl, nlong, h.pin_off, h.pins, h.nwgt, k,
                                                             nullptr, nullptr, (unsigned long long *)gain);
+    HGP_LAUNCH_CHECK();
+    stream_sync(st);
+    A.release(mk);
+    return HGP_OK;
+}
+
+
+// A graph: p = 2m and no net of other than two pins (one device read-back).
+static bool is_graph(const hgp_hg &h, const GtBufs &B, hipStream_t st) {
+    if ((uint64_t)h.p != 2ull * h.m) return false;
+    if (h.m == 0) return true;
+    fill<uint32_t>(B.scal + 2, 1, 0u, st);
+    k_non_edges<<<grid_for(h.m, BLOCK, REDUCE_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.m, B.scal + 2);
+    HGP_LAUNCH_CHECK();
+    uint32_t bad = 0;
+    HGP_CHECK_HIP(hipMemcpyAsync(&bad, B.scal + 2, sizeof(bad), hipMemcpyDeviceToHost, st));
+    stream_sync(st);
+    return bad == 0;
+}
+
+template <int KW>
+static void graph_rows_t(const hgp_hg &h, uint32_t k, const uint32_t *part, int32_t *omega, hipStream_t st) {
+    const unsigned blocks = (unsigned)std::min<size_t>(2 * FILL_BLOCKS, ((size_t)h.n + 63) / 64);
+    k_ggt_rows<KW><<<blocks, BLOCK, 0, st>>>(h.inc_off, h.inc, h.pins, h.nwgt, part, h.n, k, omega);
+    HGP_LAUNCH_CHECK();
+}
+
+hgp_status graph_gain_table(const hgp_hg &h, uint32_t k, const uint32_t *part, int32_t *omega, Arena &A,
+                            hipStream_t st) {
+    size_t mk = A.mark();
+    GtBufs B{};
+    plan_moves(A, h.n, h.m, 0, B);
+    if (A.measure) { A.release(mk); return HGP_OK; }
+    if (!is_graph(h, B, st)) { A.release(mk); return HGP_E_INVALID; }
+    if (h.n) {
+        switch ((k + 63) / 64) {
+            case 1: graph_rows_t<1>(h, k, part, omega, st); break;
+            case 2: graph_rows_t<2>(h, k, part, omega, st); break;
+            case 3: graph_rows_t<3>(h, k, part, omega, st); break;
+            default: graph_rows_t<4>(h, k, part, omega, st); break;
+        }
+    }
+    A.release(mk);
+    return HGP_OK;
+}
+
+hgp_status graph_moves(const hgp_hg &h, uint32_t k, uint32_t *part, const uint32_t *node, const uint32_t *target,
+                       uint32_t count, int32_t *omega, int64_t *gain, Arena &A, hipStream_t st) {
+    size_t mk = A.mark();
+    GtBufs B{};
+    plan_moves(A, h.n, h.m, count, B);
+    if (A.measure) { A.release(mk); return HGP_OK; }
+    if (!is_graph(h, B, st)) { A.release(mk); return HGP_E_INVALID; }
+    if (count == 0) { A.release(mk); return HGP_OK; }
+    if (!mark_moves(h, k, part, node, target, count, B, st)) { A.release(mk); return HGP_E_INVALID; }
+    const MoveView M{B.idx, target, B.from, part};
+    const unsigned g = grid_for(count, BLOCK, FILL_BLOCKS);
+    k_graph_moves<<<g, BLOCK, 0, st>>>(M, node, count, h.inc_off, h.inc, h.pins, h.nwgt, k, omega, gain);
+    HGP_LAUNCH_CHECK();
+    k_gt_apply<<<g, BLOCK, 0, st>>>(M, node, count, part);
     HGP_LAUNCH_CHECK();
     stream_sync(st);
     A.release(mk);

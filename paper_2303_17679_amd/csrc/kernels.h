@@ -45,5 +45,10 @@ hgp_status gain_table_update(const hgp_hg &h, uint32_t k, uint32_t *part, const 
                              hipStream_t st);
 hgp_status gain_recalc(const hgp_hg &h, uint32_t k, const uint32_t *part, const uint32_t *node,
                        const uint32_t *target, uint32_t count, int64_t *gain, Arena &A, hipStream_t st);
+// graphs (every net two pins): w(u, V_i) table and moves with attributed gains
+hgp_status graph_gain_table(const hgp_hg &h, uint32_t k, const uint32_t *part, int32_t *omega, Arena &A,
+                            hipStream_t st);
+hgp_status graph_moves(const hgp_hg &h, uint32_t k, uint32_t *part, const uint32_t *node, const uint32_t *target,
+                       uint32_t count, int32_t *omega, int64_t *gain, Arena &A, hipStream_t st);
 
 }  // namespace hgp

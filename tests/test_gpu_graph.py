@@ -66,3 +66,71 @@ def test_graph_levels_bit_exact(hgp, orc, name, k, seed):
     part, f, levels = H.partition(H.Hypergraph.from_host(h), P)
     assert (levels, f) == (L_o, f_o)
     assert np.array_equal(part.cpu().numpy().view(np.uint32), part_o)
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def moves_of(rs, n, k, part, count, noop=0):
+    us = rs.choice(n, size=min(count, n), replace=False).astype(np.uint32)
+    ts = np.array([(int(part[u]) + 1 + rs.randint(k - 1)) % k for u in us], np.uint32)
+    ts[:noop] = part[us[:noop]]  # moves to the node's own block
+    return us, ts
+
+
+TABLE_CASES = [("multigraph", 2), ("multigraph", 64), ("hubs", 8), ("hubs", 130), ("grid2d", 200), ("rmat16", 256)]
+
+
+@pytest.mark.parametrize("name,k", TABLE_CASES)
+def test_graph_gain_table_and_moves_match_oracle(hgp, orc, name, k):
+    H = hgp
+    h = graph(name)
+    G = H.Hypergraph.from_host(h)
+    rs = np.random.RandomState(k)
+    for kind in ("greedy", "random"):
+        part = orc.greedy_ip(h, k) if kind == "greedy" else rs.randint(0, k, size=h.n).astype(np.uint32)
+        print(f"[graph table] {name} k={k} {kind}", file=sys.stderr, flush=True)
+        om_o = orc.graph_gain_table(h, k, part)
+        t = dev(part)
+        om = H.graph_gain_table(G, k, t)
+        assert np.array_equal(om.cpu().numpy(), om_o)
+        for count in (1, 37, h.n // 3):
+            print(f"[graph moves] {name} k={k} {kind} moves={count}", file=sys.stderr, flush=True)
+            us, ts = moves_of(rs, h.n, k, part, count, noop=min(3, count // 4))
+            part_o, g_o, om2_o = orc.graph_moves(h, k, part, us, ts, om_o)
+            t = dev(part)
+            om = H.graph_gain_table(G, k, t)
+            g = H.graph_moves(G, k, t, dev(us), dev(ts), omega=om)
+            assert np.array_equal(t.cpu().numpy().view(np.uint32), part_o)
+            assert np.array_equal(g.cpu().numpy(), g_o)
+            assert np.array_equal(om.cpu().numpy(), om2_o)
+            # gains only, no table
+            t = dev(part)
+            g = H.graph_moves(G, k, t, dev(us), dev(ts))
+            assert np.array_equal(g.cpu().numpy(), g_o)
+
+
+def test_graph_entry_points_reject_invalid(hgp, orc):
+    H = hgp
+    h = graph("grid2d")
+    k = 4
+    G = H.Hypergraph.from_host(h)
+    part = orc.greedy_ip(h, k)
+    t = dev(part)
+    om = H.graph_gain_table(G, k, t)
+    before = om.cpu().numpy().copy()
+    for us, ts in (([5, 9, 5], [1, 2, 3]), ([5, h.n], [1, 1]), ([5, 6], [1, k])):
+        with pytest.raises(H.HGPError):
+            H.graph_moves(G, k, t, dev(us), dev(ts), omega=om)
+    assert np.array_equal(t.cpu().numpy().view(np.uint32), part)
+    assert np.array_equal(om.cpu().numpy(), before)
+    # not a graph: a net of three pins
+    hx = W.from_nets(6, [[0, 1], [1, 2, 3], [4, 5]])
+    Gx = H.Hypergraph.from_host(hx)
+    px = dev(np.zeros(6, np.uint32))
+    with pytest.raises(H.HGPError):
+        H.graph_gain_table(Gx, 2, px)
+    with pytest.raises(H.HGPError):
+        H.graph_moves(Gx, 2, px, dev([1]), dev([1]))

@@ -120,5 +120,5 @@ def test_trace_matches_oracle_levels(hgp, orc, name, k, seed):
     tr = P.run_traced()
     assert len(tr) == len(lv)
     for t, L in zip(tr, lv):
-        assert (t["n"], t["m"], t["p"]) == (L["h"].n, L["h"].m, L["h"].p)
+        assert (t["n"], t["m"], t["p"]) == (L["h"].n, L["h"].m, len(L["h"].pins))
         assert t["lp_rounds"] == L["lp_rounds"]
