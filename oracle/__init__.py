@@ -38,12 +38,13 @@ class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("eps_num", ctypes.c_uint32), ("eps_den", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("limit_factor", ctypes.c_uint32),
                 ("coarsen_subrounds", ctypes.c_uint32), ("lp_subrounds", ctypes.c_uint32),
-                ("lp_rounds", ctypes.c_uint32)]
+                ("lp_rounds", ctypes.c_uint32), ("community", ctypes.c_uint32)]
 
 
 def params(k: int, eps=(3, 100), seed: int = 0, limit_factor: int = 160,
-           coarsen_subrounds: int = 3, lp_subrounds: int = 5, lp_rounds: int = 5) -> Params:
-    return Params(k, eps[0], eps[1], seed, limit_factor, coarsen_subrounds, lp_subrounds, lp_rounds)
+           coarsen_subrounds: int = 3, lp_subrounds: int = 5, lp_rounds: int = 5, community: bool = False) -> Params:
+    return Params(k, eps[0], eps[1], seed, limit_factor, coarsen_subrounds, lp_subrounds, lp_rounds,
+                  1 if community else 0)
 
 
 _lib = None
@@ -82,6 +83,13 @@ def lib():
         L.or_graph_gain.restype = i64; L.or_graph_gain.argtypes = [P, P, P, P, u32, u32]
         L.or_graph_cut.restype = i64; L.or_graph_cut.argtypes = [P, P]
         L.or_graph_gain_table.restype = ctypes.c_int; L.or_graph_gain_table.argtypes = [P, u32, P, P]
+        L.or_rate_subround_c.restype = u32
+        L.or_rate_subround_c.argtypes = [P, P, u32, u32, P, P, P, P, P]
+        L.or_cluster_pass_c.restype = ctypes.c_int; L.or_cluster_pass_c.argtypes = [P, P, u32, P, P, P, P]
+        L.or_bipartite.restype = ctypes.c_int; L.or_bipartite.argtypes = [P, P, P, P, P, P, P]
+        L.or_louvain_subround.restype = u32; L.or_louvain_subround.argtypes = [P, u64, u32, u32, u32, P, P]
+        L.or_louvain_level.restype = u32; L.or_louvain_level.argtypes = [P, u64, u32, P, P]
+        L.or_communities.restype = ctypes.c_int; L.or_communities.argtypes = [P, u64, P, P]
         L.or_graph_moves.restype = ctypes.c_int; L.or_graph_moves.argtypes = [P, u32, P, P, P, u32, P, P]
         _lib = L
     return _lib
@@ -142,6 +150,19 @@ def rate_subround(h, P: Params, level: int, r: int, rep, cw, csize):
     return target, int(nc)
 
 
+def rate_subround_c(h, P: Params, level: int, r: int, rep, cw, csize, comm):
+    """rate_subround restricted to the communities comm (Sec. 4.3)."""
+    v = _View(h)
+    rep = np.ascontiguousarray(rep, np.uint32)
+    cw = np.ascontiguousarray(cw, np.int64)
+    csize = np.ascontiguousarray(csize, np.uint32)
+    comm = np.ascontiguousarray(comm, np.uint32)
+    target = np.empty(h.n, np.uint32)
+    nc = lib().or_rate_subround_c(v.ref, ctypes.byref(P), level, r, _ptr(rep), _ptr(cw), _ptr(csize), _ptr(comm),
+                                  _ptr(target))
+    return target, int(nc)
+
+
 def approve_apply(h, P: Params, target, rep, cw, csize) -> int:
     """Applies in place on rep (uint32), cw (int64), csize (uint32) arrays."""
     v = _View(h)
@@ -158,6 +179,62 @@ def cluster_pass(h, P: Params, level: int):
     rc = lib().or_cluster_pass(v.ref, ctypes.byref(P), level, _ptr(rep), _ptr(cnt), _ptr(run))
     assert rc == 0
     return rep, int(cnt[0]), int(run[0])
+
+
+def cluster_pass_c(h, P: Params, level: int, comm):
+    v = _View(h)
+    comm = np.ascontiguousarray(comm, np.uint32)
+    rep = np.empty(h.n, np.uint32)
+    cnt = np.zeros(1, np.uint32)
+    run = np.zeros(1, np.uint32)
+    rc = lib().or_cluster_pass_c(v.ref, ctypes.byref(P), level, _ptr(comm), _ptr(rep), _ptr(cnt), _ptr(run))
+    assert rc == 0
+    return rep, int(cnt[0]), int(run[0])
+
+
+def bipartite(h):
+    """The bipartite graph G_x of h as a two-pin hypergraph namespace (node
+    u < n: vertex u, node n + e: net e; vwgt = volumes), or None when its
+    total volume reaches 2^31."""
+    from types import SimpleNamespace
+    v = _View(h)
+    n, m, p = int(h.n), int(h.m), int(v.s.p)
+    po = np.zeros(p + 1, np.uint32); pi = np.zeros(max(2 * p, 1), np.uint32)
+    io = np.zeros(n + m + 1, np.uint32); ii = np.zeros(max(2 * p, 1), np.uint32)
+    vw = np.zeros(max(n + m, 1), np.int32); nw = np.zeros(max(p, 1), np.int32)
+    if lib().or_bipartite(v.ref, _ptr(po), _ptr(pi), _ptr(io), _ptr(ii), _ptr(vw), _ptr(nw)) != 0:
+        return None
+    return SimpleNamespace(n=n + m, m=p, pin_off=po, pins=pi[:2 * p], inc_off=io, inc=ii[:2 * p],
+                           vwgt=vw[:n + m], nwgt=nw[:p])
+
+
+def louvain_subround(g, seed: int, level: int, r: int, s: int, comm, cvol):
+    """One synchronous local-moving sub-round; returns (moves, comm, cvol)."""
+    v = _View(g)
+    comm = np.array(comm, np.uint32)
+    cvol = np.array(cvol, np.int64)
+    mv = lib().or_louvain_subround(v.ref, seed, level, r, s, _ptr(comm), _ptr(cvol))
+    return int(mv), comm, cvol
+
+
+def louvain_level(g, seed: int, level: int):
+    """Local moving of one level from singletons: (comm, moves, rounds)."""
+    v = _View(g)
+    comm = np.empty(max(g.n, 1), np.uint32)
+    rounds = np.zeros(1, np.uint32)
+    mv = lib().or_louvain_level(v.ref, seed, level, _ptr(comm), _ptr(rounds))
+    return comm[:g.n], int(mv), int(rounds[0])
+
+
+def communities(h, seed: int = 0):
+    """Community of every vertex (Sec. 4.3) and the number of Louvain levels."""
+    v = _View(h)
+    comm = np.empty(max(h.n, 1), np.uint32)
+    lv = np.zeros(1, np.uint32)
+    rc = lib().or_communities(v.ref, seed, _ptr(comm), _ptr(lv))
+    if rc != 0:
+        raise ValueError("total volume of the bipartite graph reaches 2^31")
+    return comm[:h.n], int(lv[0])
 
 
 def contract(h, rep):
@@ -323,15 +400,24 @@ def hierarchy(h, P: Params):
     partition of every level."""
     levels = [{"h": h}]
     cur = h
+    comm = communities(h, P.seed)[0] if P.community else None
     while cur.n > P.limit_factor * P.k:
         lvl = len(levels) - 1
-        rep, cnt, run = cluster_pass(cur, P, lvl)
+        if comm is not None:
+            levels[-1]["comm"] = comm
+            rep, cnt, run = cluster_pass_c(cur, P, lvl, comm)
+        else:
+            rep, cnt, run = cluster_pass(cur, P, lvl)
         levels[-1].update(rep=rep, cnt=cnt, subrounds=run)
         if 100 * (cur.n - cnt) <= cur.n:
             break
         cid, H = contract(cur, rep)
         levels[-1]["cid"] = cid
         levels.append({"h": H})
+        if comm is not None:
+            nxt = np.zeros(H.n, np.uint32)
+            nxt[cid] = comm
+            comm = nxt
         cur = H
     L = len(levels) - 1
     part = greedy_ip(cur, P.k)

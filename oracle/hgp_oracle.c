@@ -38,6 +38,7 @@ typedef struct {
     uint32_t coarsen_subrounds;       /* S_c                                   */
     uint32_t lp_subrounds;            /* S_lp                                  */
     uint32_t lp_rounds;               /* R_lp                                  */
+    uint32_t community;               /* 1: community-aware coarsening (4.3)   */
 } or_params;
 
 #define OR_NONE 0xFFFFFFFFu
@@ -152,9 +153,9 @@ static uint64_t net_score(int32_t w, uint32_t size)
  * rep/cw/csize are the snapshot at the start of the sub-round.  target[u] is
  * set for candidates (OR_NONE when no valid cluster exists) and left OR_NONE
  * for non-candidates.  Returns the number of candidates. */
-uint32_t or_rate_subround(const or_hg *h, const or_params *P, uint32_t level, uint32_t r,
-                          const uint32_t *rep, const int64_t *cw, const uint32_t *csize,
-                          uint32_t *target)
+static uint32_t rate_subround(const or_hg *h, const or_params *P, uint32_t level, uint32_t r,
+                              const uint32_t *rep, const int64_t *cw, const uint32_t *csize,
+                              const uint32_t *comm, uint32_t *target)
 {
     const uint32_t n = h->n;
     const int64_t W = or_total_weight(h);
@@ -201,7 +202,8 @@ uint32_t or_rate_subround(const or_hg *h, const or_params *P, uint32_t level, ui
             uint64_t rc = R[C];
             int valid = (C != rep[u]) &&
                         (cap_mult * ((int64_t)h->vwgt[u] + cw[C]) <= W) && /* R4 */
-                        !cand[C];                                          /* R3 */
+                        !cand[C] &&                                        /* R3 */
+                        (!comm || comm[C] == comm[u]);                     /* Sec. 4.3 */
             if (valid) {
                 uint64_t hc = or_hash(P->seed, 2, level, 0, C);
                 if (best == OR_NONE || rc > bestR ||
@@ -215,6 +217,23 @@ uint32_t or_rate_subround(const or_hg *h, const or_params *P, uint32_t level, ui
     }
     free(cand); free(R); free(seen); free(touched);
     return ncand;
+}
+
+uint32_t or_rate_subround(const or_hg *h, const or_params *P, uint32_t level, uint32_t r,
+                          const uint32_t *rep, const int64_t *cw, const uint32_t *csize,
+                          uint32_t *target)
+{
+    return rate_subround(h, P, level, r, rep, cw, csize, NULL, target);
+}
+
+/* The same with the community restriction of Sec. 4.3: u may join only a
+ * cluster whose representative lies in u's community (comm[v] for every
+ * vertex of the level). */
+uint32_t or_rate_subround_c(const or_hg *h, const or_params *P, uint32_t level, uint32_t r,
+                            const uint32_t *rep, const int64_t *cw, const uint32_t *csize,
+                            const uint32_t *comm, uint32_t *target)
+{
+    return rate_subround(h, P, level, r, rep, cw, csize, comm, target);
 }
 
 typedef struct { uint32_t C; int32_t c; uint32_t u; } or_join;
@@ -274,8 +293,8 @@ uint32_t or_approve_apply(const or_hg *h, const or_params *P, const uint32_t *ta
 /* One clustering pass of level `level` (Sec. 4.1, Sec. 11).  rep is output.
  * The pass ends early after a sub-round in which the number of clusters drops
  * below n/2.5 of the current level (R2). */
-int or_cluster_pass(const or_hg *h, const or_params *P, uint32_t level,
-                    uint32_t *rep, uint32_t *n_clusters, uint32_t *subrounds_run)
+static int cluster_pass(const or_hg *h, const or_params *P, uint32_t level, const uint32_t *comm,
+                        uint32_t *rep, uint32_t *n_clusters, uint32_t *subrounds_run)
 {
     const uint32_t n = h->n;
     int64_t *cw = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
@@ -285,7 +304,7 @@ int or_cluster_pass(const or_hg *h, const or_params *P, uint32_t level,
     for (uint32_t u = 0; u < n; ++u) { rep[u] = u; cw[u] = h->vwgt[u]; csize[u] = 1; }
     uint32_t cnt = n, run = 0;
     for (uint32_t r = 0; r < P->coarsen_subrounds; ++r) {
-        or_rate_subround(h, P, level, r, rep, cw, csize, target);
+        rate_subround(h, P, level, r, rep, cw, csize, comm, target);
         cnt -= or_approve_apply(h, P, target, rep, cw, csize);
         ++run;
         if ((uint64_t)5 * cnt < (uint64_t)2 * n) break;
@@ -294,6 +313,20 @@ int or_cluster_pass(const or_hg *h, const or_params *P, uint32_t level,
     if (subrounds_run) *subrounds_run = run;
     free(cw); free(csize); free(target);
     return OR_OK;
+}
+
+int or_cluster_pass(const or_hg *h, const or_params *P, uint32_t level,
+                    uint32_t *rep, uint32_t *n_clusters, uint32_t *subrounds_run)
+{
+    return cluster_pass(h, P, level, NULL, rep, n_clusters, subrounds_run);
+}
+
+/* A clustering pass restricted to communities (Sec. 4.3); comm[v] for every
+ * vertex of the level. */
+int or_cluster_pass_c(const or_hg *h, const or_params *P, uint32_t level, const uint32_t *comm,
+                      uint32_t *rep, uint32_t *n_clusters, uint32_t *subrounds_run)
+{
+    return cluster_pass(h, P, level, comm, rep, n_clusters, subrounds_run);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -671,6 +704,189 @@ static or_hg view(const or_level *L)
     return h;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Community detection (Sec. 4.3) by the deterministic Louvain method       */
+/* (Sec. 11) on the bipartite graph representation G_x of the hypergraph.   */
+/* Readings: R16 (edge weights), R17 (synchronous local moving and its      */
+/* integer modularity comparison), R18 (levels).                             */
+/* ------------------------------------------------------------------------ */
+#define OR_LV_ROUNDS 5      /* local moving rounds per level            */
+#define OR_LV_SUBROUNDS 5   /* sub-rounds per round                     */
+#define OR_LV_LEVELS 16     /* contraction levels at most               */
+
+/* G_x as a two-pin hypergraph: node u < n is vertex u, node n + e is net e;
+ * edge j (one per pin, in pin order) joins the pin's vertex and net node and
+ * weighs w(e) (R16).  Node weights are the volumes (sums of incident edge
+ * weights): vol(u) = sum of w(e) over the nets of u, vol(n+e) = |e| w(e).
+ * Arrays sized pin_off[p+1], pins[2p], inc_off[n+m+1], inc[2p], vwgt[n+m],
+ * nwgt[p].  The total volume must stay below 2^31 (OR_E_INVALID). */
+int or_bipartite(const or_hg *h, uint32_t *pin_off, uint32_t *pins, uint32_t *inc_off, uint32_t *inc,
+                 int32_t *vwgt, int32_t *nwgt)
+{
+    const uint32_t n = h->n, m = h->m, p = h->p;
+    int64_t total = 0;
+    for (uint32_t e = 0; e < m; ++e)
+        total += 2 * (int64_t)(h->pin_off[e + 1] - h->pin_off[e]) * h->nwgt[e];
+    if (total >= ((int64_t)1 << 31)) return OR_E_INVALID;
+    uint32_t *cursor = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!cursor) return OR_E_NOMEM;
+    for (uint32_t u = 0; u < n; ++u) { cursor[u] = h->inc_off[u]; vwgt[u] = 0; }
+    for (uint32_t j = 0; j <= p; ++j) pin_off[j] = 2 * j;
+    for (uint32_t u = 0; u <= n; ++u) inc_off[u] = h->inc_off[u];
+    for (uint32_t e = 0; e < m; ++e) {
+        inc_off[n + e + 1] = p + h->pin_off[e + 1];
+        vwgt[n + e] = (int32_t)((h->pin_off[e + 1] - h->pin_off[e]) * (int64_t)h->nwgt[e]);
+        for (uint32_t j = h->pin_off[e]; j < h->pin_off[e + 1]; ++j) {
+            const uint32_t u = h->pins[j];
+            pins[2 * j] = u;
+            pins[2 * j + 1] = n + e;
+            nwgt[j] = h->nwgt[e];
+            inc[cursor[u]++] = j;     /* nets ascending, so edges ascending per vertex */
+            inc[p + j] = j;
+            vwgt[u] += h->nwgt[e];
+        }
+    }
+    free(cursor);
+    return OR_OK;
+}
+
+/* One sub-round (r, s) of synchronous local moving (R17) on a graph g (a
+ * two-pin hypergraph; vwgt = volumes, nwgt = edge weights) at Louvain level
+ * `level`.  The nodes x with H(seed, 4, level, r, x) mod S = s decide on the
+ * state at the start of the sub-round: with m_2 = the total volume (twice the
+ * edge weight), A = comm[x], w(x, C) = the weight of x's edges into C and
+ * vol(C) = cvol[C], the move to C != A changes the modularity by
+ * [score(C) - score(A)] / (m_2^2 / 2) where score(C) = m_2 w(x, C) - vol(x)
+ * vol(C) and score(A) = m_2 w(x, A) - vol(x) (vol(A) - vol(x)).  The best C
+ * among x's neighbour communities (largest score, then smallest ID) is
+ * taken when its score exceeds score(A).  All moves of the sub-round are then
+ * applied and the volumes updated.  Returns the number of moves. */
+uint32_t or_louvain_subround(const or_hg *g, uint64_t seed, uint32_t level, uint32_t r, uint32_t s,
+                             uint32_t *comm, int64_t *cvol)
+{
+    const uint32_t N = g->n;
+    int64_t m2 = 0;
+    for (uint32_t x = 0; x < N; ++x) m2 += g->vwgt[x];
+    int64_t *acc = (int64_t *)calloc(N ? N : 1, sizeof(int64_t));
+    uint32_t *touched = (uint32_t *)malloc(sizeof(uint32_t) * (N ? N : 1));
+    uint32_t *dec = (uint32_t *)malloc(sizeof(uint32_t) * (N ? N : 1));
+    for (uint32_t x = 0; x < N; ++x) {
+        dec[x] = OR_NONE;
+        if (or_hash(seed, 4, level, r, x) % OR_LV_SUBROUNDS != s) continue;
+        const uint32_t A = comm[x];
+        const int64_t vx = g->vwgt[x];
+        uint32_t nt = 0;
+        for (uint32_t j = g->inc_off[x]; j < g->inc_off[x + 1]; ++j) {
+            const uint32_t e = g->inc[j];
+            const uint32_t a = g->pins[g->pin_off[e]], b = g->pins[g->pin_off[e] + 1];
+            const uint32_t c = comm[a == x ? b : a];
+            if (acc[c] == 0) touched[nt++] = c;   /* every edge weight is >= 1 */
+            acc[c] += g->nwgt[e];
+        }
+        const int64_t score_a = m2 * acc[A] - vx * (cvol[A] - vx);
+        uint32_t best = OR_NONE;
+        int64_t best_s = 0;
+        for (uint32_t q = 0; q < nt; ++q) {
+            const uint32_t c = touched[q];
+            if (c == A) continue;
+            const int64_t sc = m2 * acc[c] - vx * cvol[c];
+            if (best == OR_NONE || sc > best_s || (sc == best_s && c < best)) { best = c; best_s = sc; }
+        }
+        for (uint32_t q = 0; q < nt; ++q) acc[touched[q]] = 0;
+        if (best != OR_NONE && best_s > score_a) dec[x] = best;
+    }
+    uint32_t moves = 0;
+    for (uint32_t x = 0; x < N; ++x) {
+        if (dec[x] == OR_NONE) continue;
+        cvol[comm[x]] -= g->vwgt[x];
+        cvol[dec[x]] += g->vwgt[x];
+        comm[x] = dec[x];
+        ++moves;
+    }
+    free(acc); free(touched); free(dec);
+    return moves;
+}
+
+/* Local moving of one level from singleton communities: rounds of
+ * OR_LV_SUBROUNDS sub-rounds, at most OR_LV_ROUNDS, until a round moves no
+ * node (R17).  comm[x] receives a node ID per community; returns the moves. */
+uint32_t or_louvain_level(const or_hg *g, uint64_t seed, uint32_t level, uint32_t *comm, uint32_t *rounds_out)
+{
+    const uint32_t N = g->n;
+    int64_t *cvol = (int64_t *)malloc(sizeof(int64_t) * (N ? N : 1));
+    for (uint32_t x = 0; x < N; ++x) { comm[x] = x; cvol[x] = g->vwgt[x]; }
+    uint32_t total = 0, r = 0;
+    while (r < OR_LV_ROUNDS) {
+        uint32_t mv = 0;
+        for (uint32_t s = 0; s < OR_LV_SUBROUNDS; ++s) mv += or_louvain_subround(g, seed, level, r, s, comm, cvol);
+        ++r;
+        total += mv;
+        if (mv == 0) break;
+    }
+    free(cvol);
+    if (rounds_out) *rounds_out = r;
+    return total;
+}
+
+/* Communities of the vertices (Sec. 4.3, R18).  Level 0 is G_x.  After the
+ * local moving of a level, each community is contracted into one node (its
+ * representative is its smallest node ID; the contraction of Sec. 4.2 drops
+ * the self-loops and merges parallel edges, and the node weights -- the
+ * volumes -- add up), and the next level starts again from singletons.  The
+ * levels stop when a level moves no node, when a contraction does not shrink
+ * the graph, or after OR_LV_LEVELS levels.  comm[u] (u < n) is the node of
+ * the last level that holds u. */
+int or_communities(const or_hg *h, uint64_t seed, uint32_t *comm_out, uint32_t *levels_out)
+{
+    const uint32_t n = h->n, m = h->m, p = h->p, N = n + m;
+    or_level G[2];
+    for (int b = 0; b < 2; ++b) {
+        G[b].pin_off = (uint32_t *)malloc(sizeof(uint32_t) * (p + 1));
+        G[b].pins = (uint32_t *)malloc(sizeof(uint32_t) * (2 * (size_t)p + 1));
+        G[b].inc_off = (uint32_t *)malloc(sizeof(uint32_t) * (N + 1));
+        G[b].inc = (uint32_t *)malloc(sizeof(uint32_t) * (2 * (size_t)p + 1));
+        G[b].vwgt = (int32_t *)malloc(sizeof(int32_t) * (N ? N : 1));
+        G[b].nwgt = (int32_t *)malloc(sizeof(int32_t) * (p ? p : 1));
+        G[b].cid = NULL;
+    }
+    uint32_t *map = (uint32_t *)malloc(sizeof(uint32_t) * (N ? N : 1));
+    uint32_t *comm = (uint32_t *)malloc(sizeof(uint32_t) * (N ? N : 1));
+    uint32_t *minid = (uint32_t *)malloc(sizeof(uint32_t) * (N ? N : 1));
+    uint32_t *rep = (uint32_t *)malloc(sizeof(uint32_t) * (N ? N : 1));
+    uint32_t *cid = (uint32_t *)malloc(sizeof(uint32_t) * (N ? N : 1));
+    int rc = or_bipartite(h, G[0].pin_off, G[0].pins, G[0].inc_off, G[0].inc, G[0].vwgt, G[0].nwgt);
+    uint32_t levels = 0;
+    if (rc == OR_OK) {
+        G[0].n = N; G[0].m = p; G[0].p = 2 * p;
+        for (uint32_t x = 0; x < N; ++x) map[x] = x;
+        int cur = 0;
+        for (uint32_t level = 0; level < OR_LV_LEVELS; ++level) {
+            or_hg g = view(&G[cur]);
+            if (or_louvain_level(&g, seed, level, comm, NULL) == 0) break;
+            for (uint32_t x = 0; x < g.n; ++x) minid[x] = OR_NONE;
+            for (uint32_t x = 0; x < g.n; ++x)
+                if (minid[comm[x]] == OR_NONE) minid[comm[x]] = x;
+            for (uint32_t x = 0; x < g.n; ++x) rep[x] = minid[comm[x]];
+            or_level *nx = &G[1 - cur];
+            uint32_t dims[3];
+            or_contract(&g, rep, cid, dims, nx->pin_off, nx->pins, nx->inc_off, nx->inc, nx->vwgt, nx->nwgt);
+            nx->n = dims[0]; nx->m = dims[1]; nx->p = dims[2];
+            for (uint32_t x = 0; x < N; ++x) map[x] = cid[map[x]];
+            ++levels;
+            cur = 1 - cur;
+            if (nx->n == g.n) break;
+        }
+        for (uint32_t u = 0; u < n; ++u) comm_out[u] = map[u];
+    }
+    if (levels_out) *levels_out = levels;
+    for (int b = 0; b < 2; ++b) {
+        free(G[b].pin_off); free(G[b].pins); free(G[b].inc_off); free(G[b].inc); free(G[b].vwgt); free(G[b].nwgt);
+    }
+    free(map); free(comm); free(minid); free(rep); free(cid);
+    return rc;
+}
+
+
 /* Partition: coarsen while n > 160k and the pass shrinks the level by more
  * than 1% (Sec. 4.1 contraction limits), greedy initial partition on the
  * coarsest level, then project + LP per level (LP also on the coarsest level,
@@ -684,10 +900,18 @@ int or_partition(const or_hg *h0, const or_params *P, uint32_t *part, int64_t *f
     const or_hg *cur = h0;
     or_hg tmp;
     uint32_t *rep = (uint32_t *)malloc(sizeof(uint32_t) * (h0->n ? h0->n : 1));
+    /* community-aware coarsening (Sec. 4.3): the communities of the input,
+     * carried to every coarse level through the contraction map */
+    uint32_t *comm = NULL, *ccomm = NULL;
+    if (P->community) {
+        comm = (uint32_t *)malloc(sizeof(uint32_t) * (h0->n ? h0->n : 1));
+        ccomm = (uint32_t *)malloc(sizeof(uint32_t) * (h0->n ? h0->n : 1));
+        if (or_communities(h0, P->seed, comm, NULL) != OR_OK) { free(L); free(rep); free(comm); free(ccomm); return OR_E_INVALID; }
+    }
     for (;;) {
         if (!((uint64_t)cur->n > (uint64_t)P->limit_factor * P->k)) break;
         uint32_t cnt;
-        or_cluster_pass(cur, P, nl, rep, &cnt, NULL);
+        cluster_pass(cur, P, nl, comm, rep, &cnt, NULL);
         if ((uint64_t)100 * (cur->n - cnt) <= (uint64_t)cur->n) break;
         or_level *N = &L[nl];
         N->cid = (uint32_t *)malloc(sizeof(uint32_t) * (cur->n ? cur->n : 1));
@@ -700,6 +924,10 @@ int or_partition(const or_hg *h0, const or_params *P, uint32_t *part, int64_t *f
         uint32_t dims[3];
         or_contract(cur, rep, N->cid, dims, N->pin_off, N->pins, N->inc_off, N->inc, N->vwgt, N->nwgt);
         N->n = dims[0]; N->m = dims[1]; N->p = dims[2];
+        if (comm) {
+            for (uint32_t v = 0; v < cur->n; ++v) ccomm[N->cid[v]] = comm[v];
+            memcpy(comm, ccomm, sizeof(uint32_t) * N->n);
+        }
         ++nl;
         tmp = view(N);
         cur = &tmp;
@@ -726,7 +954,7 @@ int or_partition(const or_hg *h0, const or_params *P, uint32_t *part, int64_t *f
         free(L[l].cid); free(L[l].pin_off); free(L[l].pins); free(L[l].inc_off);
         free(L[l].inc); free(L[l].vwgt); free(L[l].nwgt);
     }
-    free(L); free(rep); free(cp);
+    free(L); free(rep); free(cp); free(comm); free(ccomm);
     return OR_OK;
 }
 

@@ -177,3 +177,58 @@ def alg4_gains(h, part, moves):
             if first_in.get(t) == i and i > last_out.get(t, -1) and unmoved.get(t, 0) == 0:
                 g[i] -= w
     return g
+
+
+# ---------------------------------------------------------------------------
+# Community detection (Sec. 4.3): bipartite graph and modularity
+# ---------------------------------------------------------------------------
+def bipartite_edges(h):
+    """Edges {u, n + e} of the bipartite graph, one per pin, with weight w(e)."""
+    out = []
+    for e, pins in enumerate(nets_of(h)):
+        for u in pins:
+            out.append((u, h.n + e, int(h.nwgt[e])))
+    return out
+
+
+def modularity(edges, comm):
+    """Q = sum over communities C of in(C) / M - (vol(C) / 2M)^2, exactly (Fraction);
+    edges is a list of (a, b, w) with a != b, M the total edge weight."""
+    from fractions import Fraction
+    M = sum(w for _, _, w in edges)
+    inw, vol = {}, {}
+    for a, b, w in edges:
+        vol[comm[a]] = vol.get(comm[a], 0) + w
+        vol[comm[b]] = vol.get(comm[b], 0) + w
+        if comm[a] == comm[b]:
+            inw[comm[a]] = inw.get(comm[a], 0) + w
+    return sum(Fraction(inw.get(c, 0), M) - Fraction(v, 2 * M) ** 2 for c, v in vol.items())
+
+
+def louvain_subround(edges, n_nodes, comm, seed, level, r, s, S=5):
+    """One synchronous local-moving sub-round from the definition: each node of
+    the sub-round takes the neighbour community that raises Q the most (ties:
+    smaller ID) if it raises Q at all, judged on the state at the start; then
+    all moves are made."""
+    adj = [[] for _ in range(n_nodes)]
+    for a, b, w in edges:
+        adj[a].append(b)
+        adj[b].append(a)
+    q0 = modularity(edges, comm)
+    dec = {}
+    for x in range(n_nodes):
+        if H(seed, 4, level, r, x) % S != s:
+            continue
+        best, best_d = None, None
+        for c in sorted({comm[y] for y in adj[x]} - {comm[x]}):
+            trial = list(comm)
+            trial[x] = c
+            d = modularity(edges, trial) - q0
+            if best is None or d > best_d:
+                best, best_d = c, d
+        if best is not None and best_d > 0:
+            dec[x] = best
+    out = list(comm)
+    for x, c in dec.items():
+        out[x] = c
+    return out, len(dec)
