@@ -37,6 +37,9 @@ WORKLOADS = {
     "gaintable": "gain table of the 160^3 row-net stencil (k=64) for its multilevel partition: build "
                  "benefit and penalty rows (n x k), gains of a sequence of moves of 1% of the vertices "
                  "(seeded random nodes and targets), and the table update for those moves",
+    "community": "community-aware partition of the 160^3 row-net stencil (k=64, eps=0.03): Louvain communities "
+                 "of its bipartite graph (hgp_communities), then the multilevel partition with clusters kept "
+                 "inside communities",
     "serve": "Poisson stream of partition requests, seed 5: sizes log-uniform in [1e4, 1e7] pins, family uniform "
              "over {random, power-law, stencil, R-MAT}, k uniform in {2..64}, eps=0.03, admitted by workspace "
              "footprint into a continuous-admission server; arrival rate 0.8 x the measured saturation rate",
@@ -290,6 +293,66 @@ def run_gaintable(args):
     }
 
 
+def run_community(args):
+    """Community-aware coarsening (Sec. 4.3) on stencil160: one step is one
+    hgp_partition with params.community = 1 (the Louvain communities of the
+    bipartite graph, then the restricted multilevel partition).  The
+    communities alone are timed in extra untimed-step calls."""
+    import numpy as np
+    import torch
+    import paper_2303_17679_amd as H
+    h, k = W.workload("stencil160")
+    G = H.Hypergraph.from_host(h)
+    if H.validate(G) != 0:
+        raise SystemExit("stencil160: input failed hgp_validate")
+    prm = H.params(k, seed=args.seed, trusted=True, community=True)
+    P = H.Partitioner(G, prm)
+    wsc = torch.empty(H.workspace_bytes(H.OP_COMMUNITY, G.n, G.m, G.p, H.params(k)), dtype=torch.uint8,
+                      device="cuda")
+    for _ in range(args.warmup):
+        P.run()
+        H.communities(G, args.seed, ws=wsc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        levels = P.run()
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / args.steps
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        comm, lv = H.communities(G, args.seed, ws=wsc)
+    torch.cuda.synchronize()
+    Tc = (time.perf_counter() - t1) / args.steps
+    f_gpu = int(P.f.item())
+    ncomm = int(np.unique(comm.cpu().numpy()).shape[0])
+    cpu = None
+    match = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        t2 = time.perf_counter()
+        part_o, f_o, L_o = oracle.partition(h, oracle.params(k, seed=args.seed, community=True))
+        To = time.perf_counter() - t2
+        match = bool(f_o == f_gpu and L_o == levels and
+                     np.array_equal(P.part.cpu().numpy().view(np.uint32), part_o))
+        model, ncpu = cpu_info()
+        cpu = {"value": h.p / To, "unit": "pins/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole community-aware stencil160 partition, one run, single thread, {To:.1f} s",
+               "host_cpu": model, "host_threads": ncpu}
+    return {
+        "metric": "pins/s for community detection + coarsen + LP refine",
+        "value": h.p / T, "unit": "pins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * T, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32/int64 (integer only)", "data": "synthetic",
+        "config": {"workload": "community", "description": WORKLOADS["community"], "k": k, "n": h.n, "m": h.m,
+                   "pins": h.p, "levels": levels, "objective": f_gpu, "communities": ncomm,
+                   "louvain_levels": lv, "parallelism": "single GPU"},
+        "phase_ms": {"communities": 1000.0 * Tc},
+        "roofline": None,
+        "cpu_baseline": cpu, "oracle_match": match,
+    }
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC runs
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
@@ -369,6 +432,9 @@ def main():
 
     if args.workload == "gaintable":
         print(json.dumps(run_gaintable(args)), flush=True)
+        return
+    if args.workload == "community":
+        print(json.dumps(run_community(args)), flush=True)
         return
     if args.workload in ("batch", "serve"):
         if args.count is None:

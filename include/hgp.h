@@ -86,6 +86,7 @@ typedef struct {
     uint32_t lp_subrounds;      /* S_lp, sub-rounds of an LP round [5] (Sec. 11)       */
     uint32_t lp_rounds;         /* R_lp, maximum LP rounds per level [5]               */
     uint32_t flags;             /* HGP_TRUSTED_INPUT or 0 [0]; results do not depend on it */
+    uint32_t community;         /* 1: community-aware coarsening (Sec. 4.3), 0: none [0]  */
 } hgp_params;
 
 /* hgp_params.flags: the caller vouches that the hypergraph meets every
@@ -102,6 +103,7 @@ typedef struct {
 #define HGP_OP_VALIDATE 5
 #define HGP_OP_INITIAL 6
 #define HGP_OP_GAINS 7     /* hgp_gain_table, hgp_gain_table_update, hgp_gain_recalc, hgp_graph_* */
+#define HGP_OP_COMMUNITY 8 /* hgp_communities */
 
 /* Host.  Fills *out with the defaults listed in hgp_params for k blocks. */
 hgp_status hgp_default_params(uint32_t k, hgp_params *out);
@@ -208,6 +210,23 @@ hgp_status hgp_partition(const hgp_hg *h, const hgp_params *prm, uint32_t *part,
 #define HGP_STATIC_SCRATCH_BYTES (64u << 20)
 hgp_status hgp_refine_lp_static(const hgp_hg *h, const hgp_params *prm, uint32_t level, uint32_t *part,
                                 int64_t *objective, int64_t *block_wgt, void *stream);
+
+/* Communities of the vertices for community-aware coarsening (paper
+ * Sec. 4.3): the Louvain method on the bipartite graph of h (a node per
+ * vertex and per net, an edge of weight w(e) per pin), deterministic by
+ * synchronous local moving in sub-rounds (Sec. 11): at most 5 rounds of 5
+ * sub-rounds per level, node x in sub-round H(seed, 4, level, round, x) mod 5;
+ * a node moves to the neighbour community of largest positive modularity gain
+ * (exact integer comparison; ties to the smaller community ID); at most 16
+ * levels, each community contracted into its smallest node.  comm (device
+ * uint32 [n]) receives a community ID per vertex (equal IDs = same community);
+ * levels_out (host, may be NULL) the Louvain levels contracted.  The total
+ * volume 2 * sum |e| w(e) must be below 2^31 (HGP_E_INVALID otherwise).
+ * hgp_partition runs it first when params.community is 1 and then lets a
+ * vertex join only clusters of its own community.  Workspace:
+ * hgp_workspace_bytes(HGP_OP_COMMUNITY, ...).  Syncs. */
+hgp_status hgp_communities(const hgp_hg *h, uint64_t seed, uint32_t *comm, uint32_t *levels_out, void *ws,
+                           size_t ws_bytes, void *stream);
 
 /* Gain table of a partition (paper Sec. 6.2): benefit[u] (device int32 [n])
  * = the weight of u's nets in which u is the only pin of its block, and

@@ -19,6 +19,7 @@ hgp_status check_params(const hgp_params *p) {
     if (p->coarsen_subrounds == 0 || p->lp_subrounds == 0) return HGP_E_INVALID;
     if (p->coarsen_subrounds > 256 || p->lp_subrounds > 256 || p->lp_rounds > 65535) return HGP_E_INVALID;
     if (p->flags & ~HGP_TRUSTED_INPUT) return HGP_E_INVALID;
+    if (p->community > 1) return HGP_E_INVALID;
     return HGP_OK;
 }
 
@@ -81,6 +82,7 @@ hgp_status hgp_default_params(uint32_t k, hgp_params *out) {
     out->lp_subrounds = 5;
     out->lp_rounds = 5;
     out->flags = 0;
+    out->community = 0;
     return HGP_OK;
 }
 
@@ -105,6 +107,7 @@ hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p, const
             case HGP_OP_VALIDATE: need = util_workspace(n, m); break;
             case HGP_OP_INITIAL: need = ip_workspace(n, p, k); break;
             case HGP_OP_GAINS: need = gaintable_workspace(n, m, k, n); break;  // also the graph tables
+            case HGP_OP_COMMUNITY: need = community_workspace(n, m, p); break;
             case HGP_OP_PARTITION: {
                 size_t temp = std::max({coarsen_workspace(n, m, p, dp), contract_workspace(n, m, p),
                                         refine_workspace(n, m, k), ip_workspace(n, p, k), util_workspace(n, m)});
@@ -113,6 +116,13 @@ hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p, const
                 // input and levels whose sizes sum to at most seven times it
                 // fit); on top, rep
                 size_t hier = 8 * level_bytes(n, m, p) + 4ull * n + 4096;
+                // community-aware coarsening: the detection runs first (its
+                // scratch is free again before coarsening), and every level
+                // keeps its vertices' communities
+                if (dp.community) {
+                    temp = std::max(temp, community_workspace(n, m, p));
+                    hier += 8 * (4ull * n + 256) + 4ull * n;
+                }
                 need = temp + hier;
                 break;
             }
@@ -227,6 +237,14 @@ hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
     };
     std::vector<Level> L;
     L.push_back({*h0, nullptr});
+    // community-aware coarsening (Sec. 4.3): the communities of the input,
+    // carried to every coarse level by the contraction map
+    uint32_t *comm = nullptr;
+    if (prm->community) {
+        comm = A.alloc<uint32_t>(h0->n);
+        const hgp_status cs = communities(*h0, prm->seed, comm, nullptr, A, st);
+        if (cs != HGP_OK) return cs;
+    }
     const uint64_t limit = (uint64_t)prm->limit_factor * prm->k;
     for (;;) {
         hgp_hg cur = L.back().h;
@@ -243,16 +261,21 @@ hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
         out.vwgt = A.alloc<int32_t>(cur.n);
         out.nwgt = A.alloc<int32_t>(cur.m);
         out.dims = nullptr;
+        uint32_t *ccomm = comm ? A.alloc<uint32_t>(cur.n) : nullptr;  // the coarse level's communities
         size_t mk_rep = A.mark();
         uint32_t *rep = A.alloc<uint32_t>(cur.n);
         uint32_t cnt = 0;
-        coarsen_pass(cur, *prm, (uint32_t)(L.size() - 1), rep, nullptr, &cnt, A, st, W);
+        coarsen_pass(cur, *prm, (uint32_t)(L.size() - 1), rep, nullptr, &cnt, A, st, W, comm);
         if ((uint64_t)100 * (cur.n - cnt) <= (uint64_t)cur.n) {
             A.release(mk);
             break;
         }
         uint32_t dims[3];
         contract(cur, rep, cid, out, dims, A, st);
+        if (comm) {
+            community_down(cur.n, cid, comm, ccomm, st);
+            comm = ccomm;
+        }
         A.release(mk_rep);
         // the coarse level keeps the arrays of its parent's capacities: only
         // their used prefix is read, and no copy is spent on compacting them
@@ -349,6 +372,17 @@ hgp_status hgp_gain_recalc(const hgp_hg *h, uint32_t k, const uint32_t *part, co
     return guarded(S(stream), [&]() {
         Arena A(ws, ws_bytes);
         return gain_recalc(*h, k, part, node, target, count, gain, A, S(stream));
+    });
+}
+
+hgp_status hgp_communities(const hgp_hg *h, uint64_t seed, uint32_t *comm, uint32_t *levels_out, void *ws,
+                           size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h);
+    if (s != HGP_OK) return s;
+    if (!comm || !ws) return HGP_E_INVALID;
+    return guarded(S(stream), [&]() {
+        Arena A(ws, ws_bytes);
+        return communities(*h, seed, comm, levels_out, A, S(stream));
     });
 }
 

@@ -46,6 +46,9 @@ struct RateArgs {
     const uint32_t *ncl;  // clusters after the previous sub-round
     uint32_t n_cur;       // vertices of the level
     const uint32_t *ovf;  // set: an earlier sub-round awaits the host (nullptr: none can)
+    // community of every vertex (Sec. 4.3): u may join only a cluster whose
+    // representative lies in its community; nullptr: no restriction
+    const uint32_t *comm;
 };
 
 // The pass stops once the clustering has shrunk the level below n / 2.5
@@ -110,7 +113,7 @@ __device__ inline uint32_t slot_hash(uint32_t C, int log2cap) {
 // Validity of target cluster C for candidate u on the sub-round snapshot:
 // within c_max and not a candidate singleton of the same sub-round.
 __device__ inline bool valid_target(const RateArgs &a, uint32_t u, uint32_t C) {
-    return C != u && a.cap_mult * ((int64_t)a.vwgt[u] + a.tinfo[C]) <= a.W;
+    return C != u && a.cap_mult * ((int64_t)a.vwgt[u] + a.tinfo[C]) <= a.W && (!a.comm || a.comm[C] == a.comm[u]);
 }
 
 // Called by the publishing lanes only.  The sub-round's candidate list is
@@ -292,6 +295,12 @@ __global__ __launch_bounds__(NT) void k_rate_group(RateArgs a, const uint32_t *l
             }
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) Ts[k4] = Cs[k4] != NONE ? a.tinfo[Cs[k4]] : TINFO_BAD;
+            if (a.comm) {  // a cluster of another community is no target (Sec. 4.3)
+                const uint32_t cmu = a.comm[u];
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4)
+                    if (Cs[k4] != NONE && a.comm[Cs[k4]] != cmu) Ts[k4] = TINFO_BAD;
+            }
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
                 bool ok = Cs[k4] != NONE && Cs[k4] != u && a.cap_mult * (cu + Ts[k4]) <= a.W;
@@ -1326,7 +1335,7 @@ size_t coarsen_workspace(uint32_t n, uint32_t m, uint32_t p, const hgp_params &p
 }
 
 void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *rep, uint32_t *n_clusters_dev,
-                  uint32_t *n_clusters_host, Arena &A, hipStream_t st, int64_t W_known) {
+                  uint32_t *n_clusters_host, Arena &A, hipStream_t st, int64_t W_known, const uint32_t *comm) {
     const uint32_t n = h.n, m = h.m, S = prm.coarsen_subrounds;
     size_t mk = A.mark();
     CoarsenBufs B;
@@ -1549,7 +1558,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                                                                         queued ? ovf : nullptr);
         HGP_LAUNCH_CHECK();
         RateArgs a{h.pin_off, h.pins, h.inc_off, h.inc, h.vwgt, B.nscore, rep, B.cw, B.tinfo, B.ptarget, B.tsum,
-                   mseed, level, r, S, cap_mult, W, r > 0, ncl, n, queued ? ovf : nullptr};
+                   mseed, level, r, S, cap_mult, W, r > 0, ncl, n, queued ? ovf : nullptr, comm};
         for (int c = 0; c < NCLASS; ++c) {
             uint32_t cntc = counts[r * NCLASS + c];
             if (!cntc) continue;

@@ -15,8 +15,11 @@ hgp_status validate(const hgp_hg &h, Arena &A, hipStream_t st);
 size_t coarsen_workspace(uint32_t n, uint32_t m, uint32_t p, const hgp_params &prm);
 // W_known: c(V) when the caller knows it (it is the same on every level), or
 // -1 to compute it here (one reduction and a sync).
+// comm (device, may be null): community of every vertex; u joins only
+// clusters of its own community (Sec. 4.3).
 void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *rep, uint32_t *n_clusters_dev,
-                  uint32_t *n_clusters_host, Arena &A, hipStream_t st, int64_t W_known = -1);
+                  uint32_t *n_clusters_host, Arena &A, hipStream_t st, int64_t W_known = -1,
+                  const uint32_t *comm = nullptr);
 
 // contract.hip
 size_t contract_workspace(uint32_t n, uint32_t m, uint32_t p);
@@ -35,6 +38,13 @@ void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t 
 size_t ip_workspace(uint32_t n, uint32_t p, uint32_t k);
 void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st, int64_t W_known = -1);
 void project(uint32_t n, const uint32_t *cid, const uint32_t *cpart, uint32_t *part, hipStream_t st);
+
+// community.hip
+size_t community_workspace(uint32_t n, uint32_t m, uint32_t p);
+hgp_status communities(const hgp_hg &h, uint64_t seed, uint32_t *comm, uint32_t *levels_out, Arena &A,
+                       hipStream_t st);
+// ccomm[cid[u]] = comm[u] for u < n: the communities of a contracted level
+void community_down(uint32_t n, const uint32_t *cid, const uint32_t *comm, uint32_t *ccomm, hipStream_t st);
 
 // gaintable.hip
 size_t gaintable_workspace(uint32_t n, uint32_t m, uint32_t k, uint32_t count);

@@ -274,15 +274,46 @@ __global__ __launch_bounds__(BLOCK) void k_graph_adj(const uint32_t *inc_off, co
     }
 }
 
-// Listed heavy vertices: their incidence ranges spread over the whole grid.
+// Listed heavy vertices, cut into chunks of ADJ_CHUNK incidence entries so
+// that the grid is balanced whatever the degrees: cbase[i] (one workgroup)
+// is the first chunk of listed vertex i, cbase[cnt] the number of chunks.
+constexpr uint32_t ADJ_CHUNK = 4096;
+constexpr int HEAVY_SCAN = 1024;
+__global__ __launch_bounds__(HEAVY_SCAN) void k_heavy_chunks(const uint32_t *inc_off, const uint32_t *heavy,
+                                                             const uint32_t *nheavy, uint32_t *cbase) {
+    __shared__ uint32_t red[HEAVY_SCAN / WAVE];
+    const uint32_t cnt = *nheavy;
+    uint32_t carry = 0;
+    for (uint32_t i0 = 0; i0 < cnt; i0 += HEAVY_SCAN) {
+        const uint32_t i = i0 + threadIdx.x;
+        uint32_t c = 0;
+        if (i < cnt) {
+            const uint32_t u = heavy[i];
+            c = (inc_off[u + 1] - inc_off[u] + ADJ_CHUNK - 1) / ADJ_CHUNK;
+        }
+        uint32_t tot;
+        const uint32_t incl = block_incl_scan_n<uint32_t, HEAVY_SCAN>(c, red, &tot);
+        if (i < cnt) cbase[i] = carry + incl - c;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) cbase[cnt] = carry;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_graph_adj_heavy(const uint32_t *inc_off, const uint32_t *inc,
                                                            const uint32_t *pin_off, const uint32_t *pins,
                                                            const int32_t *nwgt, const uint32_t *heavy,
-                                                           const uint32_t *nheavy, uint32_t *adj, int32_t *adjw) {
-    const uint32_t cnt = *nheavy;
-    for (uint32_t i = 0; i < cnt; ++i) {
-        const uint32_t u = heavy[i], j0 = inc_off[u], j1 = inc_off[u + 1];
-        for (uint32_t j = j0 + blockIdx.x * BLOCK + threadIdx.x; j < j1; j += gridDim.x * BLOCK) {
+                                                           const uint32_t *nheavy, const uint32_t *cbase,
+                                                           uint32_t *adj, int32_t *adjw) {
+    const uint32_t cnt = *nheavy, total = cbase[cnt];
+    for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+        uint32_t lo = 0, hi = cnt;  // the listed vertex whose chunks hold g: last i with cbase[i] <= g
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (cbase[mid] <= g) lo = mid; else hi = mid;
+        }
+        const uint32_t u = heavy[lo], j1 = inc_off[u + 1];
+        const uint32_t jb = inc_off[u] + (g - cbase[lo]) * ADJ_CHUNK, je = jb + ADJ_CHUNK < j1 ? jb + ADJ_CHUNK : j1;
+        for (uint32_t j = jb + threadIdx.x; j < je; j += BLOCK) {
             const uint32_t e = inc[j], b = pin_off[e], x = pins[b], y = pins[b + 1];
             adj[j] = x == u ? y : x;
             adjw[j] = nwgt[e];
@@ -362,26 +393,33 @@ struct GainArgs {
     const int32_t *adjw = nullptr;
 };
 
-// Record of incident net j of a vertex in block s: the net record, or on a
-// graph level the one it stands for: Lambda = {s, b} and Lambda1 = Lambda if
-// the neighbour's block b differs from s, else empty.
-template <int KW>
-__device__ inline NetRec<KW> graph_rec(uint32_t s, uint32_t b, int32_t w) {
-    NetRec<KW> R;
+// What a gain needs of incident net j of a vertex in block s: its weight,
+// its Lambda words and the Lambda1 word that holds bit s (a memory read at a
+// computed offset, never a local copy of the record: a dynamically indexed
+// local array goes to scratch memory).  On a graph level (GR, a template
+// parameter, so that neither kind of level pays for the other's loads) the
+// net is an edge to a neighbour in block b: Lambda = {s, b}, and Lambda1 =
+// Lambda when b differs from s, else empty.
+template <int KW, bool GR>
+__device__ inline void net_fields(const GainArgs<KW> &a, uint32_t j, uint32_t s, int64_t &w, uint64_t (&lam)[KW],
+                                  uint64_t &one) {
+    if constexpr (GR) {
+        const uint32_t b = a.part[a.adj[j]];
+        w = a.adjw[j];
+        one = 0;
 #pragma unroll
-    for (int q = 0; q < KW; ++q) {
-        const uint64_t bits = (((uint32_t)q == (s >> 6)) ? (1ull << (s & 63)) : 0ull) |
-                              (((uint32_t)q == (b >> 6)) ? (1ull << (b & 63)) : 0ull);
-        R.lam[q] = bits;
-        R.lam1[q] = b != s ? bits : 0ull;
+        for (int q = 0; q < KW; ++q) {
+            lam[q] = (((uint32_t)q == (s >> 6)) ? (1ull << (s & 63)) : 0ull) |
+                     (((uint32_t)q == (b >> 6)) ? (1ull << (b & 63)) : 0ull);
+            if ((uint32_t)q == (s >> 6) && b != s) one = lam[q];
+        }
+    } else {
+        const NetRec<KW> &R = a.nr[a.inc[j]];
+        w = R.w;
+#pragma unroll
+        for (int q = 0; q < KW; ++q) lam[q] = R.lam[q];
+        one = R.lam1[s >> 6];
     }
-    R.w = w;
-    return R;
-}
-template <int KW>
-__device__ inline NetRec<KW> inc_rec(const GainArgs<KW> &a, uint32_t j, uint32_t s) {
-    if (a.adj) return graph_rec<KW>(s, a.part[a.adj[j]], a.adjw[j]);
-    return a.nr[a.inc[j]];
 }
 
 // Proposal lists: NSLOT lists by vertex chunk (see GainArgs).
@@ -431,7 +469,7 @@ __device__ inline T group_sum(T v) {
 // has at most 8 nets: their weight and Lambda words stay in registers for
 // the per-target affinity sums, and all loads of a lane are issued before
 // any is used.
-template <int KW, int G>
+template <int KW, int G, bool GR>
 __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, uint32_t count, uint32_t blk,
                                   uint32_t nblk, uint32_t slot) {
     constexpr int GPB = BLOCK / G;
@@ -456,26 +494,41 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
                 uint32_t ev[NC];
                 int32_t wv[NC];
                 uint64_t lv[NC][KW];
-                // all incidence loads, then all record (or neighbour block) loads
-                int32_t gw[NC];
+                // all incidence (or adjacency) loads, then all record (or
+                // neighbour block) loads
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const uint32_t j = j0 + l + (uint32_t)c * G;
-                    ev[c] = j < j1 ? (a.adj ? a.adj[j] : a.inc[j]) : NONE;
-                    gw[c] = (j < j1 && a.adj) ? a.adjw[j] : 0;
+                    if constexpr (GR) {
+                        ev[c] = j < j1 ? a.adj[j] : NONE;
+                        wv[c] = j < j1 ? a.adjw[j] : 0;
+                    } else {
+                        ev[c] = j < j1 ? a.inc[j] : NONE;
+                    }
                 }
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     uint64_t one = 0;
-                    wv[c] = 0;
+                    if constexpr (!GR) wv[c] = 0;
 #pragma unroll
                     for (int q = 0; q < KW; ++q) lv[c][q] = 0;
                     if (ev[c] != NONE) {
-                        const NetRec<KW> R = a.adj ? graph_rec<KW>(s, a.part[ev[c]], gw[c]) : a.nr[ev[c]];
-                        wv[c] = (int32_t)R.w;
+                        if constexpr (GR) {
+                            const uint32_t b = a.part[ev[c]];
 #pragma unroll
-                        for (int q = 0; q < KW; ++q) lv[c][q] = R.lam[q];
-                        one = R.lam1[s >> 6];
+                            for (int q = 0; q < KW; ++q) {
+                                const uint64_t bits = (((uint32_t)q == (s >> 6)) ? (1ull << (s & 63)) : 0ull) |
+                                                      (((uint32_t)q == (b >> 6)) ? (1ull << (b & 63)) : 0ull);
+                                lv[c][q] = bits;
+                                if ((uint32_t)q == (s >> 6)) one = b != s ? bits : 0ull;
+                            }
+                        } else {
+                            const NetRec<KW> &R = a.nr[ev[c]];
+                            wv[c] = (int32_t)R.w;
+#pragma unroll
+                            for (int q = 0; q < KW; ++q) lv[c][q] = R.lam[q];
+                            one = R.lam1[s >> 6];
+                        }
                     }
                     wI += wv[c];
                     if ((one >> (s & 63)) & 1ull) bu += wv[c];
@@ -488,7 +541,9 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
                 for (int o = G / 2; o > 0; o >>= 1)
 #pragma unroll
                     for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
-                U[s >> 6] &= ~(1ull << (s & 63));
+#pragma unroll
+                for (int q = 0; q < KW; ++q)  // (a register array: no computed index)
+                    if ((uint32_t)q == (s >> 6)) U[q] &= ~(1ull << (s & 63));
 #pragma unroll
                 for (int q = 0; q < KW; ++q) {
                     uint64_t x = U[q];
@@ -517,13 +572,14 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
                 for (int q = 0; q < KW; ++q) aff[q * 64 + l] = 0;
                 wave_sync();
                 for (uint32_t j = j0 + l; j < j1; j += G) {
-                    const NetRec<KW> R = inc_rec<KW>(a, j, s);
-                    const int64_t w = R.w;
+                    int64_t w;
+                    uint64_t lam[KW], one;
+                    net_fields<KW, GR>(a, j, s, w, lam, one);
                     wI += w;
-                    if ((R.lam1[s >> 6] >> (s & 63)) & 1ull) bu += w;
+                    if ((one >> (s & 63)) & 1ull) bu += w;
 #pragma unroll
                     for (int q = 0; q < KW; ++q) {
-                        uint64_t x = R.lam[q];
+                        uint64_t x = lam[q];
                         U[q] |= x;
                         while (x) {
                             const int bit = __ffsll((long long)x) - 1;
@@ -538,7 +594,9 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
                 for (int o = G / 2; o > 0; o >>= 1)
 #pragma unroll
                     for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
-                U[s >> 6] &= ~(1ull << (s & 63));
+#pragma unroll
+                for (int q = 0; q < KW; ++q)  // (a register array: no computed index)
+                    if ((uint32_t)q == (s >> 6)) U[q] &= ~(1ull << (s & 63));
                 wave_sync();  // every histogram update is done
                 // lane l judges blocks q * 64 + l (ascending per lane)
 #pragma unroll
@@ -634,21 +692,28 @@ __global__ __launch_bounds__(BLOCK) void k_gain_scan(GainArgs<KW> a, uint32_t ch
 // Gains of the listed candidates: workgroup b rates part of slot b mod
 // NSLOT's class lists (the grid is a multiple of NSLOT), so every candidate
 // of the sub-round is in flight at once, not a chunk's worth per workgroup.
+// Resident workgroups per CU: six at one Lambda word (at most 80 registers);
+// more words keep more per-lane registers (8 nets x KW words), so fewer
+// workgroups rather than spills to scratch memory.
 template <int KW>
-__global__ __launch_bounds__(BLOCK, 6) void k_gains(GainArgs<KW> a, const uint32_t *cl, const uint32_t *ccnt) {
+constexpr int gains_occupancy() { return KW == 1 ? 6 : (KW == 2 ? 4 : 3); }
+
+template <int KW, bool GR>
+__global__ __launch_bounds__(BLOCK, gains_occupancy<KW>()) void k_gains(GainArgs<KW> a, const uint32_t *cl,
+                                                                        const uint32_t *ccnt) {
     if (lp_skip(a.ctl)) return;
     const uint32_t sl = blockIdx.x % NSLOT, bj = blockIdx.x / NSLOT, nbj = gridDim.x / NSLOT;
     const size_t cstride = (size_t)NSLOT * a.slot_cap;
     const size_t off = (size_t)sl * a.slot_cap;
-    gains_body<KW, 1>(a, cl + off, ccnt[(0 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
-    gains_body<KW, 8>(a, cl + cstride + off, ccnt[(1 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
-    gains_body<KW, 64>(a, cl + 2 * cstride + off, ccnt[(2 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
+    gains_body<KW, 1, GR>(a, cl + off, ccnt[(0 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
+    gains_body<KW, 8, GR>(a, cl + cstride + off, ccnt[(1 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
+    gains_body<KW, 64, GR>(a, cl + 2 * cstride + off, ccnt[(2 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
 }
 
 // Candidates of more than HUB_DEG nets: one 1024-thread workgroup each, the
 // affinity of every block summed in a shared LDS histogram.
 constexpr int HUB_THREADS = 1024;
-template <int KW>
+template <int KW, bool GR>
 __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const uint32_t *list,
                                                            const uint32_t *count_dev) {
     constexpr int NW = HUB_THREADS / WAVE;
@@ -671,13 +736,14 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
 #pragma unroll
         for (int q = 0; q < KW; ++q) U[q] = 0;
         for (uint32_t j = j0 + tid; j < j1; j += HUB_THREADS) {
-            const NetRec<KW> R = inc_rec<KW>(a, j, s);
-            const int64_t wt = R.w;
+            int64_t wt;
+            uint64_t lam[KW], one;
+            net_fields<KW, GR>(a, j, s, wt, lam, one);
             wI += wt;
-            if ((R.lam1[s >> 6] >> (s & 63)) & 1ull) bu += wt;
+            if ((one >> (s & 63)) & 1ull) bu += wt;
 #pragma unroll
             for (int q = 0; q < KW; ++q) {
-                uint64_t x = R.lam[q];
+                uint64_t x = lam[q];
                 U[q] |= x;
                 while (x) {
                     const int bit = __ffsll((long long)x) - 1;
@@ -1640,15 +1706,19 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     GraphUpd gupd{h.nwgt, nullptr};
     const uint32_t *adj = nullptr;
     const int32_t *adjw = nullptr;
-    if (h.m && hs[4] == 2 && (uint64_t)h.p == 2ull * h.m && A.remaining() >= 8ull * h.p + 1024) {
+    if (h.m && hs[4] == 2 && (uint64_t)h.p == 2ull * h.m &&
+        A.remaining() >= 8ull * h.p + 4ull * n + 2048) {
         uint32_t *ad = A.alloc<uint32_t>(h.p);
         int32_t *aw = A.alloc<int32_t>(h.p);
+        uint32_t *cbase = A.alloc<uint32_t>((size_t)n + 1);
         uint32_t *nheavy_adj = B.scal + 27;  // cleared with the level's scalars
         k_graph_adj<<<grid_for(n, BLOCK, 4 * FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, h.pin_off, h.pins,
                                                                           h.nwgt, n, ad, aw, B.heavy, nheavy_adj);
         HGP_LAUNCH_CHECK();
-        k_graph_adj_heavy<<<FILL_BLOCKS / 2, BLOCK, 0, st>>>(h.inc_off, h.inc, h.pin_off, h.pins, h.nwgt, B.heavy,
-                                                            nheavy_adj, ad, aw);
+        k_heavy_chunks<<<1, HEAVY_SCAN, 0, st>>>(h.inc_off, B.heavy, nheavy_adj, cbase);
+        HGP_LAUNCH_CHECK();
+        k_graph_adj_heavy<<<FILL_BLOCKS, BLOCK, 0, st>>>(h.inc_off, h.inc, h.pin_off, h.pins, h.nwgt, B.heavy,
+                                                        nheavy_adj, cbase, ad, aw);
         HGP_LAUNCH_CHECK();
         k_conn_graph<<<grid_for(h.m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.pins, h.m, h.nwgt, part,
                                                                           B.f, B.cut);
@@ -1838,11 +1908,13 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             k_gain_scan<KW><<<gain_blocks, BLOCK, 0, st>>>(ga, gch, gchunks, B.cl, B.ccnt, B.dlists, nhub, B.scal);
             HGP_LAUNCH_CHECK();
             TimedLaunch tl(KID_GAINS, st);
-            k_gains<KW><<<list_blocks, BLOCK, 0, st>>>(ga, B.cl, B.ccnt);
+            if (adj) k_gains<KW, true><<<list_blocks, BLOCK, 0, st>>>(ga, B.cl, B.ccnt);
+            else k_gains<KW, false><<<list_blocks, BLOCK, 0, st>>>(ga, B.cl, B.ccnt);
             HGP_LAUNCH_CHECK();
         }
         if (hub_blocks) {
-            k_gains_hub<KW><<<hub_blocks, HUB_THREADS, 0, st>>>(ga, B.dlists, nhub);
+            if (adj) k_gains_hub<KW, true><<<hub_blocks, HUB_THREADS, 0, st>>>(ga, B.dlists, nhub);
+            else k_gains_hub<KW, false><<<hub_blocks, HUB_THREADS, 0, st>>>(ga, B.dlists, nhub);
             HGP_LAUNCH_CHECK();
         }
         {  // pairs whose whole move sets are feasible: applied directly
