@@ -155,24 +155,38 @@ def run_serve(args):
     closed_loop(args.lanes, list(range(min(8, args.count))))  # warm-up
     T_sat = closed_loop(args.lanes, list(range(args.count)))
     sat = args.count / T_sat
-    rate = 0.8 * sat
-    gaps = -np.log1p(-W._unit_real(W.rng(5, 9, np.arange(args.count)))) / rate
-    arrive = np.cumsum(gaps)
-    S = H.Server(lanes=args.lanes, pool_bytes=pool)
-    tickets = []
-    t0 = time.perf_counter()
-    for j in range(args.count):
-        dt = arrive[j] - (time.perf_counter() - t0)
-        if dt > 0:
-            time.sleep(dt)
-        tickets.append(S.submit(hs[j], prms[j]))
-    lat, qms = [], []
-    for t, _, _ in tickets:
-        _, l_ms, q_ms = S.wait(t)
-        lat.append(l_ms)
-        qms.append(q_ms)
-    T_open = time.perf_counter() - t0
-    S.close()
+    unit_gaps = -np.log1p(-W._unit_real(W.rng(5, 9, np.arange(args.count))))  # Exp(1), seeded
+
+    def open_loop(factor):
+        """The whole trace with Poisson arrivals at factor x the saturation rate."""
+        rate = factor * sat
+        arrive = np.cumsum(unit_gaps / rate)
+        S = H.Server(lanes=args.lanes, pool_bytes=pool)
+        tickets = []
+        t0 = time.perf_counter()
+        for j in range(args.count):
+            dt = arrive[j] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(S.submit(hs[j], prms[j]))
+        lat, qms = [], []
+        for t, _, _ in tickets:
+            _, l_ms, q_ms = S.wait(t)
+            lat.append(l_ms)
+            qms.append(q_ms)
+        T = time.perf_counter() - t0
+        S.close()
+        print(f"[bench] open loop at {factor} x saturation: {T:.1f} s, p99 {np.percentile(lat, 99):.1f} ms",
+              file=sys.stderr, flush=True)
+        return rate, np.array(lat), np.array(qms), T
+
+    rate, lat, qms, T_open = open_loop(0.8)
+    sweep = []
+    for factor in [float(x) for x in args.rates.split(",") if x]:
+        r_f, l_f, q_f, T_f = open_loop(factor)
+        sweep.append({"rate_factor": factor, "arrival_rate_per_s": r_f, "p50_ms": float(np.percentile(l_f, 50)),
+                      "p99_ms": float(np.percentile(l_f, 99)), "queue_p99_ms": float(np.percentile(q_f, 99)),
+                      "served_pins_per_s": float(sum(pins)) / T_f})
     # plain path: one request at a time, FIFO, closed loop, on a sample
     sample = list(range(0, args.count, args.plain_stride))
     ws = torch.empty(max(need[i] for i in sample), dtype=torch.uint8, device="cuda")  # one workspace, reused
@@ -185,7 +199,6 @@ def run_serve(args):
     Tp = time.perf_counter() - t0
     del runners, ws
     plain = sum(pins[i] for i in sample) / Tp
-    lat = np.array(lat)
     return {
         "metric": "batched p99 latency (served requests, open loop at 0.8 x saturation)",
         "value": float(np.percentile(lat, 99)), "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,
@@ -200,6 +213,7 @@ def run_serve(args):
         "plain_path": {"pins_per_s": plain, "sample": f"every {args.plain_stride}th request "
                        f"({len(sample)} requests), hgp_partition one at a time"},
         "speedup_vs_plain": (float(sum(pins)) / T_sat) / plain,
+        "rate_sweep": sweep,
         "roofline": None, "cpu_baseline": None,
     }
 
@@ -421,6 +435,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=16, help="concurrent requests (batch, serve)")
     ap.add_argument("--plain-stride", type=int, default=16, help="one-at-a-time comparison on every Nth request")
     ap.add_argument("--pool-gib", type=float, default=32.0, help="server pool (serve)")
+    ap.add_argument("--rates", default="", help="serve: extra open-loop runs at these multiples of the saturation "
+                                                "rate, e.g. 0.25,0.5,1.0,1.2")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain elementwise copy of 1 GiB (read 1 GiB, write 1 GiB) three times, "
                          "the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")

@@ -922,9 +922,13 @@ __device__ inline void net_size_max(const uint32_t *pin_off, uint32_t m, uint32_
 // B(u) = sum over incident nets of at least two pins of (|e| - 1), a bound
 // on the clusters a rating of u can touch.  Thread per vertex; a vertex of
 // more than 32 incident nets is summed by its whole wave.
+// Vertices of more than VB_HUGE nets are listed (huge, count in *nhuge) and
+// summed by k_vertex_b_huge, a workgroup each, so that no wave walks a hub's
+// incidence list alone.
+constexpr uint32_t VB_HUGE = 8192;
 __global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, const uint32_t *inc_off,
                                                     const uint32_t *inc, uint32_t n, uint32_t m, uint32_t *bound,
-                                                    uint32_t *maxsz) {
+                                                    uint32_t *maxsz, uint32_t *huge, uint32_t *nhuge) {
     // largest net size of the level (decides whether the hub path needs its
     // huge-net kernel)
     net_size_max(pin_off, m, maxsz);
@@ -946,7 +950,10 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, con
                     if (sz >= 2) b += sz - 1;
                 }
             }
-        uint64_t hm = __ballot(heavy);
+        const bool is_huge = heavy && j1 - j0 > VB_HUGE;
+        const uint32_t at = warp_agg_append(nhuge, is_huge);
+        if (is_huge) huge[at] = u;
+        uint64_t hm = __ballot(heavy && !is_huge);
         while (hm) {  // the wave sums each heavy vertex together
             const int h = __ffsll((long long)hm) - 1;
             hm &= hm - 1;
@@ -960,7 +967,32 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, con
             t = wave_sum(t);
             if ((int)__lane_id() == h) b = t;
         }
-        if (u < n) bound[u] = b > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)b;
+        if (u < n && !is_huge) bound[u] = b > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)b;
+    }
+}
+
+constexpr int VB_HUGE_THREADS = 1024;
+__global__ __launch_bounds__(VB_HUGE_THREADS) void k_vertex_b_huge(const uint32_t *pin_off, const uint32_t *inc_off,
+                                                                   const uint32_t *inc, const uint32_t *huge,
+                                                                   const uint32_t *nhuge, uint32_t *bound) {
+    __shared__ uint64_t red[VB_HUGE_THREADS / WAVE];
+    const uint32_t cnt = *nhuge;
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {  // uniform per block
+        const uint32_t u = huge[i], j1 = inc_off[u + 1];
+        uint64_t t = 0;
+        for (uint32_t j = inc_off[u] + threadIdx.x; j < j1; j += VB_HUGE_THREADS) {
+            const uint32_t e = inc[j];
+            const uint32_t sz = pin_off[e + 1] - pin_off[e];
+            if (sz >= 2) t += sz - 1;
+        }
+        t = wave_sum(t);
+        if (__lane_id() == 0) red[threadIdx.x / WAVE] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int q = 1; q < VB_HUGE_THREADS / WAVE; ++q) t += red[q];
+            bound[u] = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
+        }
+        __syncthreads();
     }
 }
 
@@ -968,11 +1000,16 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_b(const uint32_t *pin_off, con
 // high (coarse levels): every vertex is summed by all 64 lanes at once.
 __global__ __launch_bounds__(BLOCK) void k_vertex_b_wave(const uint32_t *pin_off, const uint32_t *inc_off,
                                                          const uint32_t *inc, uint32_t n, uint32_t m,
-                                                         uint32_t *bound, uint32_t *maxsz) {
+                                                         uint32_t *bound, uint32_t *maxsz, uint32_t *huge,
+                                                         uint32_t *nhuge) {
     net_size_max(pin_off, m, maxsz);
     const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nw = gridDim.x * BLOCK / WAVE;
     for (uint32_t u = wid; u < n; u += nw) {
         const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
+        if (j1 - j0 > VB_HUGE) {  // uniform per wave
+            if (__lane_id() == 0) huge[atomicAdd(nhuge, 1u)] = u;
+            continue;
+        }
         uint64_t t = 0;
         for (uint32_t j = j0 + __lane_id(); j < j1; j += WAVE) {
             const uint32_t e = inc[j];
@@ -1279,7 +1316,8 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, uint32_t S, Coars
     B.ptarget = A.alloc<uint32_t>(n);
     B.slow = A.alloc<uint32_t>(n);
     B.lists = A.alloc<uint32_t>(n);
-    B.counts = A.alloc<uint32_t>((size_t)S * NCLASS + 3);  // + largest D, largest net, largest vertex weight
+    // + largest D, largest net, largest vertex weight, vertices of more than VB_HUGE nets
+    B.counts = A.alloc<uint32_t>((size_t)S * NCLASS + 4);
     B.bound = A.alloc<uint32_t>(n);
     B.cursor = A.alloc<uint32_t>((size_t)S * NCLASS);
     B.bcounts = A.alloc<uint32_t>((size_t)S * NCLASS * CLASSIFY_BLOCKS);
@@ -1347,14 +1385,19 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
 
     k_net_score<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.nwgt, m, B.nscore);
     HGP_LAUNCH_CHECK();
-    HGP_CHECK_HIP(hipMemsetAsync(B.counts, 0, sizeof(uint32_t) * (S * NCLASS + 3), st));
+    HGP_CHECK_HIP(hipMemsetAsync(B.counts, 0, sizeof(uint32_t) * (S * NCLASS + 4), st));
+    uint32_t *nhuge = B.counts + S * NCLASS + 3;
     if ((uint64_t)h.p >= (uint64_t)16 * n)  // average degree of at least 16: a wave per vertex
         k_vertex_b_wave<<<grid_for((size_t)std::max(n, m) * WAVE, BLOCK, 4 * FILL_BLOCKS), BLOCK, 0, st>>>(
-            h.pin_off, h.inc_off, h.inc, n, m, B.bound, B.counts + S * NCLASS + 1);
+            h.pin_off, h.inc_off, h.inc, n, m, B.bound, B.counts + S * NCLASS + 1, B.slow, nhuge);
     else
         k_vertex_b<<<grid_for(std::max(n, m), BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
-            h.pin_off, h.inc_off, h.inc, n, m, B.bound, B.counts + S * NCLASS + 1);
+            h.pin_off, h.inc_off, h.inc, n, m, B.bound, B.counts + S * NCLASS + 1, B.slow, nhuge);
     HGP_LAUNCH_CHECK();
+    if ((uint64_t)h.p > VB_HUGE) {  // a vertex of more than VB_HUGE nets can exist
+        k_vertex_b_huge<<<256, VB_HUGE_THREADS, 0, st>>>(h.pin_off, h.inc_off, h.inc, B.slow, nhuge, B.bound);
+        HGP_LAUNCH_CHECK();
+    }
     k_classify<<<grid_for(n, BLOCK, CLASSIFY_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
                                                                  B.tsum, B.counts, B.cursor, B.bcounts, B.lists, false);
     HGP_LAUNCH_CHECK();

@@ -104,18 +104,21 @@ struct GatherValid {
 };
 
 // Representative of every valid net: the first net, in the order the nets
-// are sorted by the upper HASH_SORT_BITS bits of their hash (stably, so by
-// net within equal bits), with an identical pin list -- the smallest net ID
+// are sorted by the upper bits of their hash (stably, so by net within equal
+// bits; see hash_sort_bits), with an identical pin list -- the smallest net ID
 // among identical nets.  The run of equal sorted bits is found by stepping
 // back over a few neighbours (runs are short), else by binary search.
 // wsum[r] receives the weights of the nets r represents besides itself.
 // repnet (NONE on entry) is written only for the nets that are merged into
 // another one, so a net with no copy costs no scattered store.
+// More nets than 2^24 (runs of about m / 2^24 nets per bucket) sort by all
+// 32 bits, so that a net is compared only with the nets of equal hash.
 constexpr int HASH_SORT_BITS = 24;
+constexpr uint32_t HASH_FULL_SORT = 1u << 24;
+__host__ __device__ inline int hash_sort_bits(uint32_t m) { return m > HASH_FULL_SORT ? 32 : HASH_SORT_BITS; }
 __global__ void k_identical(const uint32_t *keys, const uint32_t *vals, const uint32_t *nv_dev, const uint32_t *off,
                             const uint32_t *tmp, const uint32_t *usize, const int32_t *nwgt, uint32_t *repnet,
-                            int32_t *wsum) {
-    constexpr int SH = 32 - HASH_SORT_BITS;
+                            int32_t *wsum, int SH) {
     const uint32_t nv = *nv_dev;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
         const uint32_t key = keys[i], top = key >> SH;
@@ -354,13 +357,14 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
     scan_apply<uint32_t>(A, m, IsValid{B.valid}, GatherValid{B.valid, B.hkey, (uint32_t *)B.keys, B.vals}, d_nv, st);
     uint32_t *kk = (uint32_t *)B.keys;  // 32-bit hash keys in the 64-bit buffers
     uint32_t *vv = B.vals;
-    radix_sort_pairs<uint32_t>(A, &kk, &vv, (uint32_t *)B.keys_alt, B.vals_alt, m, 32 - HASH_SORT_BITS, 32, st,
+    const int sbits = hash_sort_bits(m);
+    radix_sort_pairs<uint32_t>(A, &kk, &vv, (uint32_t *)B.keys_alt, B.vals_alt, m, 32 - sbits, 32, st,
                                d_nv);
     if (m) {
         HGP_CHECK_HIP(hipMemsetAsync(B.wsum, 0, sizeof(int32_t) * m, st));
         HGP_CHECK_HIP(hipMemsetAsync(B.repnet, 0xFF, sizeof(uint32_t) * m, st));
         k_identical<<<grid_for(m, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(kk, vv, d_nv, h.pin_off, B.tmp, B.usize,
-                                                                      h.nwgt, B.repnet, B.wsum);
+                                                                      h.nwgt, B.repnet, B.wsum, 32 - sbits);
         HGP_LAUNCH_CHECK();
     }
 

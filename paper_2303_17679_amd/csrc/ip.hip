@@ -601,12 +601,16 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
         k_put_start<<<1, 64, 0, st>>>(B.order, pos, d_start, B.visited, B.bst);
         HGP_LAUNCH_CHECK();
         next = s + 1;
-        // BFS layers, BFS_BATCH at a time with the state in device memory
-        // (sizes are bounded by n and p, layers after the last do nothing);
-        // one read-back per batch tells whether the frontier has emptied
+        // BFS layers in batches with the state in device memory (sizes are
+        // bounded by n and p, layers after the last do nothing); one
+        // read-back per batch tells whether the frontier has emptied.  The
+        // batches of one BFS grow 1, 2, 4, ... up to BFS_BATCH layers, so a
+        // small component (most of them end after a layer or two) does not
+        // queue a whole batch of empty layers.
         const unsigned gT = grid_for(h.p, BLOCK, FILL_BLOCKS), gW = grid_for(n, BLOCK, FILL_BLOCKS);
-        for (uint32_t layer = 0;;) {
-            for (uint32_t b = 0; b < BFS_BATCH; ++b, ++layer) {
+        uint32_t nbatch = 1;
+        for (uint32_t layer = 0;; nbatch = std::min<uint32_t>(2 * nbatch, BFS_BATCH)) {
+            for (uint32_t b = 0; b < nbatch; ++b, ++layer) {
                 uint32_t *cur = B.bst + (layer & 1u) * BFS_WORDS, *nxt = B.bst + ((layer + 1) & 1u) * BFS_WORDS;
                 scan_apply_dn<uint32_t>(A, n, cur + BFS_F, FrontierDeg{B.order, h.inc_off, cur + BFS_FS},
                                         StoreExcl<uint32_t>{B.D}, cur + BFS_T, st);

@@ -188,32 +188,45 @@ void scan_apply(Arena &A, size_t n, In in, Out out, T *total_dev, hipStream_t st
     A.release(mk);
 }
 
-// The same scan with the element count in device memory (at most nmax):
-// the grid is sized for nmax and tiles past the count do nothing, so no host
-// round trip is needed to learn the count.
+// The same scan with the element count in device memory (at most nmax), so
+// that no host round trip is needed to learn the count.  The grids are fixed
+// (at most DN_GRID workgroups) and stride over the tiles that the count
+// reaches, so a scan costs what its count needs, not what the bound allows:
+// a bound of 10^8 elements with a count of a few hundred is three short
+// launches, not three launches of 50,000 workgroups.
+constexpr unsigned DN_GRID = 1024;
+__device__ inline size_t active_tiles(const uint32_t *n_dev) { return ((size_t)*n_dev + SCAN_TILE - 1) / SCAN_TILE; }
+
 template <class T, class In>
 __global__ __launch_bounds__(BLOCK) void k_tile_reduce_dn(const uint32_t *n_dev, In in, T *tile_sum) {
     __shared__ T lds[BLOCK / WAVE];
-    const T t = reduce_tile<T, In>((size_t)blockIdx.x * SCAN_TILE, *n_dev, in, lds);
-    if (threadIdx.x == 0) tile_sum[blockIdx.x] = t;  // zero past the count
+    const size_t n = *n_dev, nt = active_tiles(n_dev);
+    for (size_t t = blockIdx.x; t < nt; t += gridDim.x) {  // uniform per block
+        const T v = reduce_tile<T, In>(t * SCAN_TILE, n, in, lds);
+        if (threadIdx.x == 0) tile_sum[t] = v;
+        __syncthreads();  // lds is reused by the next tile
+    }
+}
+
+// Single block: exclusive scan of the active tile sums in place; *total <- sum.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles_dn(const uint32_t *n_dev, T *tile_sum, T *total) {
+    __shared__ T lds[BLOCK / WAVE];
+    const size_t nt = active_tiles(n_dev);
+    T carry = 0;
+    for (size_t base = 0; base < nt; base += SCAN_TILE)
+        carry += scan_tile<T>(base, nt, LoadArr<T>{tile_sum}, StoreExcl<T>{tile_sum}, carry, lds);
+    if (threadIdx.x == 0 && total) *total = carry;
 }
 
 template <class T, class In, class Out>
 __global__ __launch_bounds__(BLOCK) void k_tile_scan_dn(const uint32_t *n_dev, In in, Out out, const T *tile_off) {
     __shared__ T lds[BLOCK / WAVE];
-    const size_t n = *n_dev;
-    if ((size_t)blockIdx.x * SCAN_TILE >= n) return;  // uniform per block
-    scan_tile<T, In, Out>((size_t)blockIdx.x * SCAN_TILE, n, in, out, tile_off[blockIdx.x], lds);
-}
-
-template <class T, class In, class Out>
-__global__ __launch_bounds__(BLOCK) void k_tile_scan_fold_dn(const uint32_t *n_dev, In in, Out out,
-                                                             const T *tile_sum, size_t ntiles, T *total) {
-    __shared__ T lds[BLOCK / WAVE];
-    const T off = tile_offset<T>(tile_sum, ntiles, total, lds);  // block 0 writes the total
-    const size_t n = *n_dev;
-    if ((size_t)blockIdx.x * SCAN_TILE >= n) return;  // uniform per block
-    scan_tile<T, In, Out>((size_t)blockIdx.x * SCAN_TILE, n, in, out, off, lds);
+    const size_t n = *n_dev, nt = active_tiles(n_dev);
+    for (size_t t = blockIdx.x; t < nt; t += gridDim.x) {  // uniform per block
+        scan_tile<T, In, Out>(t * SCAN_TILE, n, in, out, tile_off[t], lds);
+        __syncthreads();
+    }
 }
 
 template <class T, class In, class Out>
@@ -240,18 +253,12 @@ void scan_apply_dn(Arena &A, size_t nmax, const uint32_t *n_dev, In in, Out out,
         A.release(mk);
         return;
     }
-    k_tile_reduce_dn<T, In><<<(unsigned)ntiles, BLOCK, 0, st>>>(n_dev, in, tiles);
+    const unsigned g = (unsigned)std::min<size_t>(ntiles, DN_GRID);
+    k_tile_reduce_dn<T, In><<<g, BLOCK, 0, st>>>(n_dev, in, tiles);
     HGP_LAUNCH_CHECK();
-    if (ntiles <= SCAN_FOLD_TILES) {
-        k_tile_scan_fold_dn<T, In, Out><<<(unsigned)ntiles, BLOCK, 0, st>>>(n_dev, in, out, tiles, ntiles,
-                                                                           total_dev);
-        HGP_LAUNCH_CHECK();
-        A.release(mk);
-        return;
-    }
-    k_scan_tiles<T><<<1, BLOCK, 0, st>>>(ntiles, tiles, total_dev);
+    k_scan_tiles_dn<T><<<1, BLOCK, 0, st>>>(n_dev, tiles, total_dev);
     HGP_LAUNCH_CHECK();
-    k_tile_scan_dn<T, In, Out><<<(unsigned)ntiles, BLOCK, 0, st>>>(n_dev, in, out, tiles);
+    k_tile_scan_dn<T, In, Out><<<g, BLOCK, 0, st>>>(n_dev, in, out, tiles);
     HGP_LAUNCH_CHECK();
     A.release(mk);
 }

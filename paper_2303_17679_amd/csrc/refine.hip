@@ -226,6 +226,9 @@ __global__ __launch_bounds__(BLOCK) void k_max_net(const uint32_t *pin_off, uint
     }
 }
 
+// On a graph level every net has exactly two pins, so pin_off[e] = 2e and
+// the kernels below read a net's endpoints at pins[2e] and pins[2e + 1]
+// without loading the offsets.
 // Adjacency array of a graph level: for the j-th incident net e of u,
 // adj[j] = the other pin of e and adjw[j] = w(e).  A thread per vertex of up
 // to 32 nets (eight incidence loads, then eight net loads at a time), the
@@ -243,15 +246,13 @@ __global__ __launch_bounds__(BLOCK) void k_graph_adj(const uint32_t *inc_off, co
         const bool wide = j1 - j0 > 32;
         if (!wide)
             for (uint32_t j = j0; j < j1; j += 8) {
-                uint32_t e[8], b[8];
+                uint32_t e[8];
 #pragma unroll
                 for (uint32_t q = 0; q < 8; ++q) e[q] = j + q < j1 ? inc[j + q] : NONE;
 #pragma unroll
-                for (uint32_t q = 0; q < 8; ++q) b[q] = e[q] != NONE ? pin_off[e[q]] : 0u;
-#pragma unroll
                 for (uint32_t q = 0; q < 8; ++q) {
                     if (e[q] == NONE) continue;
-                    const uint32_t x = pins[b[q]], y = pins[b[q] + 1];
+                    const uint32_t x = pins[2 * (size_t)e[q]], y = pins[2 * (size_t)e[q] + 1];
                     adj[j + q] = x == u ? y : x;
                     adjw[j + q] = nwgt[e[q]];
                 }
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(BLOCK) void k_graph_adj(const uint32_t *inc_off, co
                 continue;
             }
             for (uint32_t j = hj0 + __lane_id(); j < hj1; j += WAVE) {
-                const uint32_t e = inc[j], b = pin_off[e], x = pins[b], y = pins[b + 1];
+                const uint32_t e = inc[j], x = pins[2 * (size_t)e], y = pins[2 * (size_t)e + 1];
                 adj[j] = x == hu ? y : x;
                 adjw[j] = nwgt[e];
             }
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(BLOCK) void k_graph_adj_heavy(const uint32_t *inc_o
         const uint32_t u = heavy[lo], j1 = inc_off[u + 1];
         const uint32_t jb = inc_off[u] + (g - cbase[lo]) * ADJ_CHUNK, je = jb + ADJ_CHUNK < j1 ? jb + ADJ_CHUNK : j1;
         for (uint32_t j = jb + threadIdx.x; j < je; j += BLOCK) {
-            const uint32_t e = inc[j], b = pin_off[e], x = pins[b], y = pins[b + 1];
+            const uint32_t e = inc[j], x = pins[2 * (size_t)e], y = pins[2 * (size_t)e + 1];
             adj[j] = x == u ? y : x;
             adjw[j] = nwgt[e];
         }
@@ -331,8 +332,7 @@ __global__ __launch_bounds__(BLOCK) void k_conn_graph(const uint32_t *pin_off, c
         const uint32_t e = e0 + threadIdx.x;
         bool cut = false;
         if (e < m) {
-            const uint32_t b = pin_off[e];
-            cut = part[pins[b]] != part[pins[b + 1]];
+            cut = part[pins[2 * (size_t)e]] != part[pins[2 * (size_t)e + 1]];
             if (cut) acc += nwgt[e];
         }
         const uint64_t word = __ballot(cut);
@@ -801,12 +801,43 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
 
 // The same count with a wave per node, for levels whose average degree is
 // high (coarse levels).
+// Nodes of more than BCNT_HUGE nets are counted by a workgroup each.
+constexpr uint32_t BCNT_HUGE = 8192;
+constexpr int BCNT_HUGE_THREADS = 1024;
+__global__ __launch_bounds__(BCNT_HUGE_THREADS) void k_init_bcnt_huge(const uint32_t *inc_off, const uint32_t *inc,
+                                                                      const uint32_t *cut, const uint32_t *huge,
+                                                                      const uint32_t *nhuge, uint32_t *bcnt) {
+    __shared__ uint32_t red[BCNT_HUGE_THREADS / WAVE];
+    const uint32_t cnt = *nhuge;
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {  // uniform per block
+        const uint32_t u = huge[i], j1 = inc_off[u + 1];
+        uint32_t t = 0;
+        for (uint32_t j = inc_off[u] + threadIdx.x; j < j1; j += BCNT_HUGE_THREADS) {
+            const uint32_t e = inc[j];
+            t += (cut[e >> 5] >> (e & 31)) & 1u;
+        }
+        t = wave_sum(t);
+        if (__lane_id() == 0) red[threadIdx.x / WAVE] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int q = 1; q < BCNT_HUGE_THREADS / WAVE; ++q) t += red[q];
+            bcnt[u] = t;
+        }
+        __syncthreads();
+    }
+}
+
 template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_init_bcnt_wave(const uint32_t *inc_off, const uint32_t *inc, uint32_t n,
-                                                          const uint32_t *cut, uint32_t *bcnt) {
+                                                          const uint32_t *cut, uint32_t *bcnt, uint32_t *huge,
+                                                          uint32_t *nhuge) {
     const uint32_t wid = (blockIdx.x * BLOCK + threadIdx.x) / WAVE, nw = gridDim.x * BLOCK / WAVE;
     for (uint32_t u = wid; u < n; u += nw) {
         const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
+        if (j1 - j0 > BCNT_HUGE) {  // uniform per wave: a workgroup counts it (k_init_bcnt_huge)
+            if (__lane_id() == 0) huge[atomicAdd(nhuge, 1u)] = u;
+            continue;
+        }
         uint32_t t = 0;
         for (uint32_t j = j0 + __lane_id(); j < j1; j += WAVE) {
             const uint32_t e = inc[j];
@@ -1390,7 +1421,7 @@ __device__ inline int64_t update_net(const uint32_t *pin_off, const uint32_t *pi
                                      uint32_t *nlong, uint32_t *bcnt, const GraphUpd &gu) {
     if (atomicExch(&tstamp[e], stamp) == stamp) return 0;
     if (gu.cut) {
-        const uint32_t b = pin_off[e], x = pins[b], y = pins[b + 1];
+        const uint32_t x = pins[2 * (size_t)e], y = pins[2 * (size_t)e + 1];
         const bool now = part[x] != part[y];
         const bool was = (gu.cut[e >> 5] >> (e & 31)) & 1u;
         if (now == was) return 0;
@@ -1424,21 +1455,29 @@ __device__ inline int64_t update_net(const uint32_t *pin_off, const uint32_t *pi
 
 // Movers of more than HUB_DEG nets: their incidence lists are cut into chunks
 // of BLOCK nets spread over the whole grid (a net per thread).
+// The listed movers' incidence lists are cut into chunks of ADJ_CHUNK nets
+// (cbase from k_heavy_chunks), so the grid is balanced whatever the degrees.
 template <int KW>
 __global__ __launch_bounds__(BLOCK) void k_lp_update_heavy(const uint32_t *pin_off, const uint32_t *pins,
                                                            const uint32_t *inc_off, const uint32_t *inc,
                                                            const uint32_t *heavy, const uint32_t *nheavy,
-                                                           const uint32_t *part, NetRec<KW> *nr, uint32_t *tstamp,
-                                                           uint32_t stamp, int64_t *f, uint32_t *longl,
-                                                           uint32_t *nlong, uint32_t *bcnt, LpCtl ctl, GraphUpd gu) {
+                                                           const uint32_t *cbase, const uint32_t *part,
+                                                           NetRec<KW> *nr, uint32_t *tstamp, uint32_t stamp,
+                                                           int64_t *f, uint32_t *longl, uint32_t *nlong,
+                                                           uint32_t *bcnt, LpCtl ctl, GraphUpd gu) {
     if (lp_skip(ctl)) return;
     __shared__ int64_t red[BLOCK / WAVE];
-    const uint32_t cnt = *nheavy;
+    const uint32_t cnt = *nheavy, total = cbase[cnt];
     int64_t acc = 0;
-    for (uint32_t h = 0; h < cnt; ++h) {
-        const uint32_t u = heavy[h];
-        const uint32_t j0 = inc_off[u], j1 = inc_off[u + 1];
-        for (uint32_t j = j0 + blockIdx.x * BLOCK + threadIdx.x; j < j1; j += gridDim.x * BLOCK)
+    for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+        uint32_t lo = 0, hi = cnt;  // the listed mover whose chunks hold g
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (cbase[mid] <= g) lo = mid; else hi = mid;
+        }
+        const uint32_t u = heavy[lo], j1 = inc_off[u + 1];
+        const uint32_t jb = inc_off[u] + (g - cbase[lo]) * ADJ_CHUNK, je = jb + ADJ_CHUNK < j1 ? jb + ADJ_CHUNK : j1;
+        for (uint32_t j = jb + threadIdx.x; j < je; j += BLOCK)
             acc += update_net<KW>(pin_off, pins, inc[j], part, nr, tstamp, stamp, longl, nlong, bcnt, gu);
     }
     acc = wave_sum(acc);
@@ -1538,7 +1577,7 @@ struct RefineBufs {
     void *nr;  // NetRec<KW>[m]
     int64_t *f;     // objective, spread over SPREAD slots
     int64_t *bw;
-    uint32_t *longl, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *pw, *slow;
+    uint32_t *longl, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *hcbase, *pw, *slow;
     uint32_t *pcnt;  // [2][NSLOT * SPREAD_U32] proposal-list lengths, alternate sub-rounds
     uint32_t *cl;    // [3][NSLOT] candidate lists by degree class and slot
     uint32_t *ccnt;  // [3 * NSLOT * SPREAD_U32] their lengths
@@ -1594,6 +1633,7 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.seg = A.alloc<uint32_t>((size_t)k * (k - 1) / 2 * pair_seg_cap(n));
     B.slow = A.alloc<uint32_t>(n);
     B.heavy = A.alloc<uint32_t>(n);
+    B.hcbase = A.alloc<uint32_t>((size_t)n + 1);
     B.dbw_g = A.alloc<int64_t>(k);
     sort_reserve(A, n);
     scan_reserve<uint64_t>(A, n);
@@ -1733,11 +1773,16 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     HGP_LAUNCH_CHECK();
     if ((uint64_t)h.p >= (uint64_t)16 * n)  // average degree of at least 16: a wave per node
         k_init_bcnt_wave<KW><<<grid_for((size_t)n * WAVE, BLOCK, 4 * FILL_BLOCKS), BLOCK, 0, st>>>(
-            h.inc_off, h.inc, n, (const uint32_t *)B.cut, B.bcnt);
+            h.inc_off, h.inc, n, (const uint32_t *)B.cut, B.bcnt, B.heavy, B.scal + 28);
     else
         k_init_bcnt<KW><<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n,
                                                                            (const uint32_t *)B.cut, B.bcnt);
     HGP_LAUNCH_CHECK();
+    if ((uint64_t)h.p >= (uint64_t)16 * n && (uint64_t)h.p > BCNT_HUGE) {  // listed hubs of the wave kernel
+        k_init_bcnt_huge<<<256, BCNT_HUGE_THREADS, 0, st>>>(h.inc_off, h.inc, (const uint32_t *)B.cut, B.heavy,
+                                                            B.scal + 28, B.bcnt);
+        HGP_LAUNCH_CHECK();
+    }
     const uint32_t S = prm.lp_subrounds;
     // gains: chunks of `gch` vertices (a power of two in [64, GAIN_CH], about
     // n / 1024, so that even small levels spread over many workgroups)
@@ -1877,9 +1922,12 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             HGP_LAUNCH_CHECK();
         }
         if (dc[3]) {  // the level has nodes of more than HUB_DEG nets
-            k_lp_update_heavy<KW><<<512, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.heavy, nheavy, part,
-                                                         (NetRec<KW> *)B.nr, B.tstamp, stamp, B.f, B.longl, nlong,
-                                                         B.bcnt, ctl, gupd);
+            k_heavy_chunks<<<1, HEAVY_SCAN, 0, st>>>(h.inc_off, B.heavy, nheavy, B.hcbase);
+            HGP_LAUNCH_CHECK();
+            k_lp_update_heavy<KW><<<FILL_BLOCKS / 2, BLOCK, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, B.heavy,
+                                                                   nheavy, B.hcbase, part, (NetRec<KW> *)B.nr,
+                                                                   B.tstamp, stamp, B.f, B.longl, nlong, B.bcnt,
+                                                                   ctl, gupd);
             HGP_LAUNCH_CHECK();
         }
         if (long_nets) {
