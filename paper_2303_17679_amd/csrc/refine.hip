@@ -281,7 +281,8 @@ __global__ __launch_bounds__(BLOCK) void k_graph_adj(const uint32_t *inc_off, co
 constexpr uint32_t ADJ_CHUNK = 4096;
 constexpr int HEAVY_SCAN = 1024;
 __global__ __launch_bounds__(HEAVY_SCAN) void k_heavy_chunks(const uint32_t *inc_off, const uint32_t *heavy,
-                                                             const uint32_t *nheavy, uint32_t *cbase) {
+                                                             const uint32_t *nheavy, uint32_t *cbase,
+                                                             uint32_t chunk = ADJ_CHUNK) {
     __shared__ uint32_t red[HEAVY_SCAN / WAVE];
     const uint32_t cnt = *nheavy;
     uint32_t carry = 0;
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(HEAVY_SCAN) void k_heavy_chunks(const uint32_t *inc
         uint32_t c = 0;
         if (i < cnt) {
             const uint32_t u = heavy[i];
-            c = (inc_off[u + 1] - inc_off[u] + ADJ_CHUNK - 1) / ADJ_CHUNK;
+            c = (inc_off[u + 1] - inc_off[u] + chunk - 1) / chunk;
         }
         uint32_t tot;
         const uint32_t incl = block_incl_scan_n<uint32_t, HEAVY_SCAN>(c, red, &tot);
@@ -796,6 +797,134 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
                     chunk_slot(u / a.ch, (a.n + a.ch - 1) / a.ch));
         }
         __syncthreads();  // the histogram is read before the next node clears it
+    }
+}
+
+// Hub gains summed by the whole grid: the incidence lists of the listed
+// nodes are cut into chunks of HUB_GCH nets (cbase from k_heavy_chunks), a
+// workgroup adds a chunk's block affinities, b(u), w(I(u)) and union of
+// Lambda into the node's accumulators (integer atomics, so the sums do not
+// depend on the order), and k_gains_hub_pick judges every node's blocks from
+// them and clears them for the next sub-round.  Accumulator i: hacc[i *
+// (64 KW + 2) + t] = affinity of block t, then b(u) and w(I(u)); hU[i * KW +
+// q] = Lambda union words.
+constexpr uint32_t HUB_GCH = 8192;
+template <int KW, bool GR>
+__global__ __launch_bounds__(HUB_THREADS) void k_gains_hub_part(GainArgs<KW> a, const uint32_t *list,
+                                                                const uint32_t *count_dev, const uint32_t *cbase,
+                                                                int64_t *hacc, unsigned long long *hU) {
+    constexpr int NW = HUB_THREADS / WAVE;
+    constexpr uint32_t ROW = 64 * KW + 2;
+    __shared__ int64_t aff[64 * KW];
+    __shared__ unsigned long long Us[KW];
+    __shared__ int64_t rbu[NW], rwi[NW];
+    if (lp_skip(a.ctl)) return;
+    const uint32_t cnt = *count_dev, total = cbase[cnt], tid = threadIdx.x, w = tid / WAVE;
+    for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {  // uniform per block
+        uint32_t lo = 0, hi = cnt;  // the listed node whose chunks hold g
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (cbase[mid] <= g) lo = mid; else hi = mid;
+        }
+        const uint32_t u = list[lo], j1 = a.inc_off[u + 1];
+        const uint32_t jb = a.inc_off[u] + (g - cbase[lo]) * HUB_GCH, je = jb + HUB_GCH < j1 ? jb + HUB_GCH : j1;
+        const uint32_t s = a.part[u];
+        for (uint32_t t = tid; t < 64 * KW; t += HUB_THREADS) aff[t] = 0;
+        if (tid < KW) Us[tid] = 0;
+        __syncthreads();
+        int64_t bu = 0, wI = 0;
+        uint64_t U[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) U[q] = 0;
+        for (uint32_t j = jb + tid; j < je; j += HUB_THREADS) {
+            int64_t wt;
+            uint64_t lam[KW], one;
+            net_fields<KW, GR>(a, j, s, wt, lam, one);
+            wI += wt;
+            if ((one >> (s & 63)) & 1ull) bu += wt;
+#pragma unroll
+            for (int q = 0; q < KW; ++q) {
+                uint64_t x = lam[q];
+                U[q] |= x;
+                while (x) {
+                    const int bit = __ffsll((long long)x) - 1;
+                    x &= x - 1;
+                    atomicAdd((unsigned long long *)&aff[q * 64 + bit], (unsigned long long)wt);
+                }
+            }
+        }
+        bu = wave_sum(bu);
+        wI = wave_sum(wI);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int q = 0; q < KW; ++q) U[q] |= __shfl_xor(U[q], o, 64);
+        if (__lane_id() == 0) {
+            rbu[w] = bu;
+            rwi[w] = wI;
+#pragma unroll
+            for (int q = 0; q < KW; ++q) atomicOr(&Us[q], (unsigned long long)U[q]);
+        }
+        __syncthreads();
+        int64_t *acc = hacc + (size_t)lo * ROW;
+        for (uint32_t t = tid; t < 64 * KW; t += HUB_THREADS)
+            if (aff[t]) atomic_add_i64(&acc[t], aff[t]);
+        if (tid == 0) {
+            int64_t tb = 0, tw = 0;
+            for (int q = 0; q < NW; ++q) { tb += rbu[q]; tw += rwi[q]; }
+            if (tb) atomic_add_i64(&acc[64 * KW], tb);
+            if (tw) atomic_add_i64(&acc[64 * KW + 1], tw);
+        }
+        if (tid < KW && Us[tid]) atomicOr(&hU[(size_t)lo * KW + tid], Us[tid]);
+        __syncthreads();  // the LDS sums are read before the next chunk clears them
+    }
+}
+
+template <int KW>
+__global__ __launch_bounds__(BLOCK) void k_gains_hub_pick(GainArgs<KW> a, const uint32_t *list,
+                                                          const uint32_t *count_dev, int64_t *hacc,
+                                                          unsigned long long *hU) {
+    constexpr uint32_t ROW = 64 * KW + 2;
+    static_assert(64 * KW <= BLOCK, "a thread per block");
+    __shared__ uint32_t rg[BLOCK / WAVE], rt[BLOCK / WAVE];
+    if (lp_skip(a.ctl)) return;
+    const uint32_t cnt = *count_dev, tid = threadIdx.x, w = tid / WAVE;
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {  // uniform per block
+        const uint32_t u = list[i], s = a.part[u];
+        const int64_t cu = a.vwgt[u];
+        int64_t *acc = hacc + (size_t)i * ROW;
+        const int64_t bu = acc[64 * KW], wI = acc[64 * KW + 1];
+        uint32_t best_t = NONE, best_g = 0;
+        if (tid < 64 * KW) {  // thread t judges block t
+            const uint32_t t = tid;
+            const bool inU = (hU[(size_t)i * KW + (t >> 6)] >> (t & 63)) & 1ull;
+            if (inU && t != s && a.bw[t] + cu <= a.lmax) {
+                const int64_t gn = bu - (wI - acc[t]);
+                if (gn > 0) { best_g = (uint32_t)gn; best_t = t; }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {  // largest gain, then smallest block
+            const uint32_t og = __shfl_xor(best_g, o, 64), ot = __shfl_xor(best_t, o, 64);
+            if (og > best_g || (og == best_g && ot < best_t)) { best_g = og; best_t = ot; }
+        }
+        if (__lane_id() == 0) { rg[w] = best_g; rt[w] = best_t; }
+        __syncthreads();
+        // clear the accumulators for the next sub-round (every read is done)
+        for (uint32_t t = tid; t < ROW; t += BLOCK) acc[t] = 0;
+        if (tid < KW) hU[(size_t)i * KW + tid] = 0;
+        if (w == 0) {
+            best_g = __lane_id() < BLOCK / WAVE ? rg[__lane_id()] : 0u;
+            best_t = __lane_id() < BLOCK / WAVE ? rt[__lane_id()] : NONE;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint32_t og = __shfl_xor(best_g, o, 64), ot = __shfl_xor(best_t, o, 64);
+                if (og > best_g || (og == best_g && ot < best_t)) { best_g = og; best_t = ot; }
+            }
+            propose(a, u, s, best_t, best_g, __lane_id() == 0 && best_t != NONE,
+                    chunk_slot(u / a.ch, (a.n + a.ch - 1) / a.ch));
+        }
+        __syncthreads();
     }
 }
 
@@ -1793,6 +1922,19 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     // capacity of one proposal list: the vertices of its chunks
     const uint32_t slot_cap = chunk_slot_cap(gchunks) * gch;
     const uint32_t hub_blocks = dc[3] ? grid_for((dc[3] + S - 1) / S, 1, 256) : 0u;
+    // hub gains: accumulators for every hub of the level (a sub-round lists
+    // at most all of them), cleared once here and then by each pick
+    int64_t *hacc = nullptr;
+    unsigned long long *hU = nullptr;
+    uint32_t *hcb = nullptr;
+    const size_t hub_bytes = (size_t)dc[3] * ((64 * KW + 2) * 8 + 8 * KW + 4) + 3 * 256;
+    if (dc[3] && A.remaining() >= hub_bytes) {  // else one workgroup per hub (k_gains_hub)
+        hacc = A.alloc<int64_t>((size_t)dc[3] * (64 * KW + 2));
+        hU = A.alloc<unsigned long long>((size_t)dc[3] * KW);
+        hcb = A.alloc<uint32_t>((size_t)dc[3] + 1);
+        fill<int64_t>(hacc, (size_t)dc[3] * (64 * KW + 2), 0, st);
+        fill<unsigned long long>(hU, (size_t)dc[3] * KW, 0ull, st);
+    }
     uint32_t *nhub = B.scal + 26;  // hub candidates of the sub-round (list in dlists)
     // grids of the per-sub-round kernels, sized by what one sub-round can hold
     // (about n / S proposals and movers); every kernel strides over its count
@@ -1960,9 +2102,19 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
             else k_gains<KW, false><<<list_blocks, BLOCK, 0, st>>>(ga, B.cl, B.ccnt);
             HGP_LAUNCH_CHECK();
         }
-        if (hub_blocks) {
+        if (hub_blocks && !hacc) {
             if (adj) k_gains_hub<KW, true><<<hub_blocks, HUB_THREADS, 0, st>>>(ga, B.dlists, nhub);
             else k_gains_hub<KW, false><<<hub_blocks, HUB_THREADS, 0, st>>>(ga, B.dlists, nhub);
+            HGP_LAUNCH_CHECK();
+        } else if (hub_blocks) {
+            k_heavy_chunks<<<1, HEAVY_SCAN, 0, st>>>(h.inc_off, B.dlists, nhub, hcb, HUB_GCH);
+            HGP_LAUNCH_CHECK();
+            if (adj)
+                k_gains_hub_part<KW, true><<<FILL_BLOCKS / 2, HUB_THREADS, 0, st>>>(ga, B.dlists, nhub, hcb, hacc, hU);
+            else
+                k_gains_hub_part<KW, false><<<FILL_BLOCKS / 2, HUB_THREADS, 0, st>>>(ga, B.dlists, nhub, hcb, hacc, hU);
+            HGP_LAUNCH_CHECK();
+            k_gains_hub_pick<KW><<<hub_blocks, BLOCK, 0, st>>>(ga, B.dlists, nhub, hacc, hU);
             HGP_LAUNCH_CHECK();
         }
         {  // pairs whose whole move sets are feasible: applied directly
