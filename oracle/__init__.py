@@ -22,7 +22,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc -O2 (no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, "-o", tmp])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -38,13 +38,15 @@ class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("eps_num", ctypes.c_uint32), ("eps_den", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("limit_factor", ctypes.c_uint32),
                 ("coarsen_subrounds", ctypes.c_uint32), ("lp_subrounds", ctypes.c_uint32),
-                ("lp_rounds", ctypes.c_uint32), ("community", ctypes.c_uint32)]
+                ("lp_rounds", ctypes.c_uint32), ("community", ctypes.c_uint32), ("ip", ctypes.c_uint32)]
 
 
 def params(k: int, eps=(3, 100), seed: int = 0, limit_factor: int = 160,
-           coarsen_subrounds: int = 3, lp_subrounds: int = 5, lp_rounds: int = 5, community: bool = False) -> Params:
+           coarsen_subrounds: int = 3, lp_subrounds: int = 5, lp_rounds: int = 5, community: bool = False,
+           ip: int = 0) -> Params:
+    """ip: 0 greedy BFS fill, 1 recursive bipartitioning (Sec. 5)."""
     return Params(k, eps[0], eps[1], seed, limit_factor, coarsen_subrounds, lp_subrounds, lp_rounds,
-                  1 if community else 0)
+                  1 if community else 0, ip)
 
 
 _lib = None
@@ -83,6 +85,16 @@ def lib():
         L.or_graph_gain.restype = i64; L.or_graph_gain.argtypes = [P, P, P, P, u32, u32]
         L.or_graph_cut.restype = i64; L.or_graph_cut.argtypes = [P, P]
         L.or_graph_gain_table.restype = ctypes.c_int; L.or_graph_gain_table.argtypes = [P, u32, P, P]
+        L.or_refine_lp_limits.restype = ctypes.c_int
+        L.or_refine_lp_limits.argtypes = [P, P, u32, P, P, P, P, P, P]
+        L.or_greedy_ip_targets.restype = ctypes.c_int; L.or_greedy_ip_targets.argtypes = [P, u32, P, P]
+        L.or_lp_proposals_limits.restype = u32
+        L.or_lp_proposals_limits.argtypes = [P, P, u32, u32, u32, P, P, P, P]
+        L.or_rb_limits.restype = None; L.or_rb_limits.argtypes = [i64, u32, u32, u32, i64, u32, P, P]
+        L.or_subhypergraph.restype = ctypes.c_int
+        L.or_subhypergraph.argtypes = [P, P, u32, P, P, P, P, P, P, P, P]
+        L.or_bisect.restype = ctypes.c_int; L.or_bisect.argtypes = [P, P, P, P, P]
+        L.or_rb_ip.restype = ctypes.c_int; L.or_rb_ip.argtypes = [P, P, P]
         L.or_rate_subround_c.restype = u32
         L.or_rate_subround_c.argtypes = [P, P, u32, u32, P, P, P, P, P]
         L.or_cluster_pass_c.restype = ctypes.c_int; L.or_cluster_pass_c.argtypes = [P, P, u32, P, P, P, P]
@@ -393,6 +405,78 @@ def partition(h, P: Params):
     return part, int(f[0]), int(lv[0])
 
 
+def refine_lp_limits(h, P: Params, level: int, part, lmax):
+    """LP with per-block weight limits: (part, f, bw, rounds, moves)."""
+    v = _View(h)
+    part = np.array(part, dtype=np.uint32, copy=True)
+    lmax = np.ascontiguousarray(lmax, np.int64)
+    f = np.zeros(1, np.int64); bw = np.zeros(P.k, np.int64)
+    rounds = np.zeros(1, np.uint32); moves = np.zeros(1, np.uint64)
+    assert lib().or_refine_lp_limits(v.ref, ctypes.byref(P), level, _ptr(part), _ptr(lmax), _ptr(f), _ptr(bw),
+                                     _ptr(rounds), _ptr(moves)) == 0
+    return part, int(f[0]), bw, int(rounds[0]), int(moves[0])
+
+
+def lp_proposals_limits(h, P: Params, level: int, r: int, s: int, part, lmax):
+    v = _View(h)
+    part = np.ascontiguousarray(part, np.uint32)
+    lmax = np.ascontiguousarray(lmax, np.int64)
+    t = np.empty(h.n, np.uint32)
+    g = np.empty(h.n, np.int64)
+    lib().or_lp_proposals_limits(v.ref, ctypes.byref(P), level, r, s, _ptr(part), _ptr(lmax), _ptr(t), _ptr(g))
+    return t, g
+
+
+def greedy_ip_targets(h, k: int, targets):
+    v = _View(h)
+    t = np.ascontiguousarray(targets, np.int64)
+    part = np.empty(max(h.n, 1), np.uint32)
+    assert lib().or_greedy_ip_targets(v.ref, k, _ptr(t), _ptr(part)) == 0
+    return part[:h.n]
+
+
+def rb_limits(Wtot: int, ktot: int, eps, Wsub: int, kk: int):
+    """(L[2], T[2]) of a bisection (Eq. 1)."""
+    L = np.zeros(2, np.int64); T = np.zeros(2, np.int64)
+    lib().or_rb_limits(Wtot, ktot, eps[0], eps[1], Wsub, kk, _ptr(L), _ptr(T))
+    return L.tolist(), T.tolist()
+
+
+def subhypergraph(h, part, side: int):
+    """(H[V_side] as a namespace, vmap)."""
+    from types import SimpleNamespace
+    v = _View(h)
+    n, m, p = int(h.n), int(h.m), int(v.s.p)
+    part = np.ascontiguousarray(part, np.uint32)
+    dims = np.zeros(3, np.uint32)
+    po = np.zeros(m + 1, np.uint32); pi = np.zeros(max(p, 1), np.uint32)
+    io = np.zeros(n + 1, np.uint32); ii = np.zeros(max(p, 1), np.uint32)
+    vw = np.zeros(max(n, 1), np.int32); nw = np.zeros(max(m, 1), np.int32)
+    vm = np.zeros(max(n, 1), np.uint32)
+    assert lib().or_subhypergraph(v.ref, _ptr(part), side, _ptr(dims), _ptr(po), _ptr(pi), _ptr(io), _ptr(ii),
+                                  _ptr(vw), _ptr(nw), _ptr(vm)) == 0
+    n2, m2, p2 = (int(x) for x in dims)
+    H = SimpleNamespace(n=n2, m=m2, pin_off=po[:m2 + 1].copy(), pins=pi[:p2].copy(), inc_off=io[:n2 + 1].copy(),
+                        inc=ii[:p2].copy(), vwgt=vw[:n2].copy(), nwgt=nw[:m2].copy())
+    return H, vm[:n2].copy()
+
+
+def bisect(h, P: Params, L, T):
+    v = _View(h)
+    L = np.ascontiguousarray(L, np.int64); T = np.ascontiguousarray(T, np.int64)
+    part = np.empty(max(h.n, 1), np.uint32)
+    assert lib().or_bisect(v.ref, ctypes.byref(P), _ptr(L), _ptr(T), _ptr(part)) == 0
+    return part[:h.n]
+
+
+def rb_ip(h, P: Params):
+    """Recursive-bipartitioning initial partition (Sec. 5) of h into P.k blocks."""
+    v = _View(h)
+    part = np.empty(max(h.n, 1), np.uint32)
+    assert lib().or_rb_ip(v.ref, ctypes.byref(P), _ptr(part)) == 0
+    return part[:h.n]
+
+
 def hierarchy(h, P: Params):
     """The oracle's multilevel driver taken level by level (same steps as
     or_partition), returning every intermediate array for per-level parity:
@@ -420,7 +504,7 @@ def hierarchy(h, P: Params):
             comm = nxt
         cur = H
     L = len(levels) - 1
-    part = greedy_ip(cur, P.k)
+    part = rb_ip(cur, P) if P.ip == 1 else greedy_ip(cur, P.k)
     levels[L]["ip"] = part.copy()
     part, f, bw, rounds, moves = refine_lp(cur, P, L, part)
     levels[L].update(part=part, f=f, bw=bw, lp_rounds=rounds, lp_moves=moves)

@@ -22,6 +22,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 
 typedef struct {
     uint32_t n, m, p;
@@ -39,6 +40,8 @@ typedef struct {
     uint32_t lp_subrounds;            /* S_lp                                  */
     uint32_t lp_rounds;               /* R_lp                                  */
     uint32_t community;               /* 1: community-aware coarsening (4.3)   */
+    uint32_t ip;                      /* 0: greedy BFS fill, 1: recursive      */
+                                      /*    bipartitioning (Sec. 5, R19)       */
 } or_params;
 
 #define OR_NONE 0xFFFFFFFFu
@@ -454,7 +457,27 @@ void or_project(uint32_t n, const uint32_t *cid, const uint32_t *coarse_part, ui
 /* Greedy initial partition (a simple deterministic method, as permitted for */
 /* the coarsest level): BFS order, blocks filled to ceil(c(V)/k) in turn.     */
 /* ------------------------------------------------------------------------ */
+static int greedy_fill(const or_hg *h, uint32_t k, const int64_t *target, uint32_t *part);
+
 int or_greedy_ip(const or_hg *h, uint32_t k, uint32_t *part)
+{
+    int64_t *T = (int64_t *)malloc(sizeof(int64_t) * k);
+    const int64_t W = or_total_weight(h);
+    for (uint32_t b = 0; b < k; ++b) T[b] = (W + (int64_t)k - 1) / (int64_t)k;
+    int rc = greedy_fill(h, k, T, part);
+    free(T);
+    return rc;
+}
+
+/* The same fill with a weight target per block (block b is left once its
+ * weight reaches target[b]); the bisections of R19 fill block 0 to its share
+ * of the weight. */
+int or_greedy_ip_targets(const or_hg *h, uint32_t k, const int64_t *target, uint32_t *part)
+{
+    return greedy_fill(h, k, target, part);
+}
+
+static int greedy_fill(const or_hg *h, uint32_t k, const int64_t *target, uint32_t *part)
 {
     const uint32_t n = h->n;
     uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
@@ -475,15 +498,13 @@ int or_greedy_ip(const or_hg *h, uint32_t k, uint32_t *part)
             }
         }
     }
-    const int64_t W = or_total_weight(h);
-    const int64_t T = (W + (int64_t)k - 1) / (int64_t)k;
     uint32_t b = 0;
     int64_t cb = 0;
     for (uint32_t i = 0; i < n; ++i) {
         uint32_t v = order[i];
         part[v] = b;
         cb += h->vwgt[v];
-        if (cb >= T && b + 1 < k) { ++b; cb = 0; }
+        if (cb >= target[b] && b + 1 < k) { ++b; cb = 0; }
     }
     free(order); free(vis);
     return OR_OK;
@@ -536,7 +557,7 @@ static int cmp_move(const void *a, const void *b)
  * with the largest positive gain among those that can take u without
  * exceeding L_max; ties to the smaller block (R10).  Returns OR_NONE if none. */
 static uint32_t best_move(const or_hg *h, const uint32_t *part, const int64_t *bw,
-                          int64_t lmax, uint32_t u, int64_t *aff, uint32_t *cnt,
+                          const int64_t *lmax, uint32_t u, int64_t *aff, uint32_t *cnt,
                           uint32_t *blist, uint32_t *alist, int64_t *g_out)
 {
     const uint32_t s = part[u];
@@ -567,7 +588,7 @@ static uint32_t best_move(const or_hg *h, const uint32_t *part, const int64_t *b
         int64_t g = b_u - (w_inc - aff[t]);
         aff[t] = 0;
         if (t == s || g <= 0) continue;
-        if (bw[t] + h->vwgt[u] > lmax) continue;
+        if (bw[t] + h->vwgt[u] > lmax[t]) continue;
         if (g > bestg || (g == bestg && t < best)) { bestg = g; best = t; }
     }
     *g_out = bestg;
@@ -577,12 +598,29 @@ static uint32_t best_move(const or_hg *h, const uint32_t *part, const int64_t *b
 /* The proposals of one LP sub-round (step 1 of Sec. 11's synchronous LP) on
  * the partition `part`: prop_t[u] = best target block or OR_NONE, prop_g[u]
  * its gain, for every node of sub-round s of round r.  Exposed for tests. */
+static uint32_t lp_proposals_l(const or_hg *h, const or_params *P, uint32_t level, uint32_t r, uint32_t s,
+                               const uint32_t *part, const int64_t *lmax_in, uint32_t *prop_t, int64_t *prop_g);
+
 uint32_t or_lp_proposals(const or_hg *h, const or_params *P, uint32_t level, uint32_t r, uint32_t s,
                          const uint32_t *part, uint32_t *prop_t, int64_t *prop_g)
 {
+    return lp_proposals_l(h, P, level, r, s, part, NULL, prop_t, prop_g);
+}
+
+/* The same with per-block weight limits lmax[k]. */
+uint32_t or_lp_proposals_limits(const or_hg *h, const or_params *P, uint32_t level, uint32_t r, uint32_t s,
+                                const uint32_t *part, const int64_t *lmax, uint32_t *prop_t, int64_t *prop_g)
+{
+    return lp_proposals_l(h, P, level, r, s, part, lmax, prop_t, prop_g);
+}
+
+static uint32_t lp_proposals_l(const or_hg *h, const or_params *P, uint32_t level, uint32_t r, uint32_t s,
+                               const uint32_t *part, const int64_t *lmax_in, uint32_t *prop_t, int64_t *prop_g)
+{
     const uint32_t n = h->n, k = P->k;
     const int64_t W = or_total_weight(h);
-    const int64_t lmax = or_lmax(W, k, P->eps_num, P->eps_den);
+    int64_t *lmax = (int64_t *)malloc(sizeof(int64_t) * k);
+    for (uint32_t b = 0; b < k; ++b) lmax[b] = lmax_in ? lmax_in[b] : or_lmax(W, k, P->eps_num, P->eps_den);
     int64_t *bw = (int64_t *)malloc(sizeof(int64_t) * k);
     int64_t *aff = (int64_t *)calloc(k, sizeof(int64_t));
     uint32_t *cnt = (uint32_t *)calloc(k, sizeof(uint32_t));
@@ -601,18 +639,19 @@ uint32_t or_lp_proposals(const or_hg *h, const or_params *P, uint32_t level, uin
         prop_g[u] = g;
         ++np;
     }
-    free(bw); free(aff); free(cnt); free(blist); free(alist);
+    free(lmax); free(bw); free(aff); free(cnt); free(blist); free(alist);
     return np;
 }
 
 /* LP refinement of one level.  part is refined in place; returns the
- * objective and block weights of the result. */
-int or_refine_lp(const or_hg *h, const or_params *P, uint32_t level, uint32_t *part,
-                 int64_t *f_out, int64_t *block_w, uint32_t *rounds_out, uint64_t *moves_out)
+ * objective and block weights of the result.  lmax[b] is the weight limit of
+ * block b: L_max for every block, or the per-side limits of a bisection of
+ * the recursive bipartitioning (R19); the pair budgets of R9 take each
+ * block's own limit. */
+static int refine_lp_l(const or_hg *h, const or_params *P, uint32_t level, uint32_t *part, const int64_t *lmax,
+                       int64_t *f_out, int64_t *block_w, uint32_t *rounds_out, uint64_t *moves_out)
 {
     const uint32_t n = h->n, k = P->k;
-    const int64_t W = or_total_weight(h);
-    const int64_t lmax = or_lmax(W, k, P->eps_num, P->eps_den);
     int64_t *bw = (int64_t *)malloc(sizeof(int64_t) * k);
     int64_t *aff = (int64_t *)calloc(k, sizeof(int64_t));
     uint32_t *cnt = (uint32_t *)calloc(k, sizeof(uint32_t));
@@ -659,8 +698,8 @@ int or_refine_lp(const or_hg *h, const or_params *P, uint32_t level, uint32_t *p
                     uint32_t pa = pos_ab[(size_t)s * k + t], pb = pos_ab[(size_t)t * k + s];
                     for (uint32_t q = 0; q < la; ++q) ca[q] = h->vwgt[M[pa + q].u];
                     for (uint32_t q = 0; q < lb; ++q) cb[q] = h->vwgt[M[pb + q].u];
-                    int64_t beta_s = floor_div(lmax - bw[s], (int64_t)k - 1);
-                    int64_t beta_t = floor_div(lmax - bw[t], (int64_t)k - 1);
+                    int64_t beta_s = floor_div(lmax[s] - bw[s], (int64_t)k - 1);
+                    int64_t beta_t = floor_div(lmax[t] - bw[t], (int64_t)k - 1);
                     uint32_t ii, jj;
                     or_select_pair(ca, la, cb, lb, beta_s, beta_t, &ii, &jj);
                     for (uint32_t q = 0; q < ii; ++q) { part[M[pa + q].u] = t; }
@@ -684,6 +723,24 @@ int or_refine_lp(const or_hg *h, const or_params *P, uint32_t level, uint32_t *p
     if (moves_out) *moves_out = total_moves;
     free(bw); free(aff); free(cnt); free(blist); free(alist); free(snap); free(M); free(ca); free(cb); free(pos_ab); free(len_ab);
     return OR_OK;
+}
+
+int or_refine_lp(const or_hg *h, const or_params *P, uint32_t level, uint32_t *part,
+                 int64_t *f_out, int64_t *block_w, uint32_t *rounds_out, uint64_t *moves_out)
+{
+    int64_t *lmax = (int64_t *)malloc(sizeof(int64_t) * P->k);
+    const int64_t L = or_lmax(or_total_weight(h), P->k, P->eps_num, P->eps_den);
+    for (uint32_t b = 0; b < P->k; ++b) lmax[b] = L;
+    int rc = refine_lp_l(h, P, level, part, lmax, f_out, block_w, rounds_out, moves_out);
+    free(lmax);
+    return rc;
+}
+
+/* LP with explicit per-block weight limits (the bisections of R19). */
+int or_refine_lp_limits(const or_hg *h, const or_params *P, uint32_t level, uint32_t *part, const int64_t *lmax,
+                        int64_t *f_out, int64_t *block_w, uint32_t *rounds_out, uint64_t *moves_out)
+{
+    return refine_lp_l(h, P, level, part, lmax, f_out, block_w, rounds_out, moves_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -891,8 +948,17 @@ int or_communities(const or_hg *h, uint64_t seed, uint32_t *comm_out, uint32_t *
  * than 1% (Sec. 4.1 contraction limits), greedy initial partition on the
  * coarsest level, then project + LP per level (LP also on the coarsest level,
  * R11).  levels_out gets the number of contractions performed. */
-int or_partition(const or_hg *h0, const or_params *P, uint32_t *part, int64_t *f_out,
-                 uint32_t *levels_out)
+int or_rb_ip(const or_hg *h, const or_params *P, uint32_t *part);
+
+/* The multilevel cycle: coarsen while n > 160k and the pass shrinks the
+ * level by more than 1% (Sec. 4.1 contraction limits), initial partition of
+ * the coarsest level, then project + LP per level (LP also on the coarsest
+ * level, R11).  lmax (k entries, or NULL for L_max on every block) and
+ * target (the fill targets of the greedy initial partition, or NULL for
+ * ceil(c(V)/k)) are set by the bisections of R19.  levels_out gets the number
+ * of contractions performed. */
+static int multilevel(const or_hg *h0, const or_params *P, const int64_t *lmax_in, const int64_t *target,
+                      uint32_t *part, int64_t *f_out, uint32_t *levels_out)
 {
     const uint32_t MAXL = 4096;
     or_level *L = (or_level *)calloc(MAXL, sizeof(or_level));
@@ -934,10 +1000,19 @@ int or_partition(const or_hg *h0, const or_params *P, uint32_t *part, int64_t *f
         if (nl == MAXL) break;
     }
     /* initial partition of the coarsest level and LP on it */
+    const uint32_t k = P->k;
+    int64_t *lmax = (int64_t *)malloc(sizeof(int64_t) * k);
+    int64_t *T = (int64_t *)malloc(sizeof(int64_t) * k);
+    const int64_t W = or_total_weight(h0);
+    for (uint32_t b = 0; b < k; ++b) {
+        lmax[b] = lmax_in ? lmax_in[b] : or_lmax(W, k, P->eps_num, P->eps_den);
+        T[b] = target ? target[b] : (W + (int64_t)k - 1) / (int64_t)k;
+    }
     uint32_t *cp = (uint32_t *)malloc(sizeof(uint32_t) * (cur->n ? cur->n : 1));
-    or_greedy_ip(cur, P->k, cp);
+    if (P->ip == 1) or_rb_ip(cur, P, cp);
+    else greedy_fill(cur, k, T, cp);
     int64_t f;
-    or_refine_lp(cur, P, nl, cp, &f, NULL, NULL, NULL);
+    refine_lp_l(cur, P, nl, cp, lmax, &f, NULL, NULL, NULL);
     /* uncoarsening */
     for (int l = (int)nl - 1; l >= 0; --l) {
         or_hg fine = (l == 0) ? *h0 : view(&L[l - 1]);
@@ -945,7 +1020,7 @@ int or_partition(const or_hg *h0, const or_params *P, uint32_t *part, int64_t *f
         or_project(fine.n, L[l].cid, cp, fp);
         free(cp);
         cp = fp;
-        or_refine_lp(&fine, P, (uint32_t)l, cp, &f, NULL, NULL, NULL);
+        refine_lp_l(&fine, P, (uint32_t)l, cp, lmax, &f, NULL, NULL, NULL);
     }
     memcpy(part, cp, sizeof(uint32_t) * h0->n);
     *f_out = f;
@@ -954,7 +1029,135 @@ int or_partition(const or_hg *h0, const or_params *P, uint32_t *part, int64_t *f
         free(L[l].cid); free(L[l].pin_off); free(L[l].pins); free(L[l].inc_off);
         free(L[l].inc); free(L[l].vwgt); free(L[l].nwgt);
     }
-    free(L); free(rep); free(cp); free(comm); free(ccomm);
+    free(L); free(rep); free(cp); free(comm); free(ccomm); free(lmax); free(T);
+    return OR_OK;
+}
+
+int or_partition(const or_hg *h0, const or_params *P, uint32_t *part, int64_t *f_out, uint32_t *levels_out)
+{
+    return multilevel(h0, P, NULL, NULL, part, f_out, levels_out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Recursive bipartitioning initial partition (Sec. 5, Eq. 1; reading R19).  */
+/* ------------------------------------------------------------------------ */
+
+/* Limits and fill targets of the bisection of a subhypergraph of weight Wsub
+ * that gets kk blocks, in a partition of a hypergraph of weight Wtot into
+ * ktot blocks: side 0 gets ceil(kk/2) blocks, side 1 floor(kk/2).  The
+ * imbalance of the bisection is eps' of Eq. 1, computed in IEEE double with
+ * the C library's pow; side i's target is ceil(Wsub k_i / kk) and its limit
+ * floor((1 + eps') target_i). */
+void or_rb_limits(int64_t Wtot, uint32_t ktot, uint32_t eps_num, uint32_t eps_den, int64_t Wsub, uint32_t kk,
+                  int64_t *L, int64_t *T)
+{
+    const uint32_t ks[2] = {(kk + 1) / 2, kk / 2};
+    uint32_t lg = 0;
+    while ((1u << lg) < kk) ++lg; /* ceil(log2 kk) */
+    const double eps = (double)eps_num / (double)eps_den;
+    const double base = (1.0 + eps) * ((double)Wtot / (double)ktot) * ((double)kk / (double)Wsub);
+    const double epsp = pow(base, 1.0 / (double)lg) - 1.0;
+    for (int i = 0; i < 2; ++i) {
+        T[i] = (Wsub * (int64_t)ks[i] + (int64_t)kk - 1) / (int64_t)kk;
+        L[i] = (int64_t)floor((1.0 + epsp) * (double)T[i]);
+    }
+}
+
+/* Subhypergraph H[V'] of Sec. 2 for V' = the vertices with part[v] == side:
+ * its vertices renumbered in ascending ID, every net with a pin in V'
+ * restricted to those pins (ascending net ID, weights kept, single-pin nets
+ * included as the definition has them).  vmap[i] = the vertex of h that new
+ * vertex i stands for.  Arrays are malloc'ed into S. */
+int or_subhypergraph(const or_hg *h, const uint32_t *part, uint32_t side, uint32_t *dims, uint32_t *pin_off,
+                     uint32_t *pins, uint32_t *inc_off, uint32_t *inc, int32_t *vwgt, int32_t *nwgt, uint32_t *vmap)
+{
+    const uint32_t n = h->n, m = h->m;
+    uint32_t *nid = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t n2 = 0;
+    for (uint32_t v = 0; v < n; ++v) {
+        nid[v] = OR_NONE;
+        if (part[v] == side) { nid[v] = n2; vmap[n2] = v; vwgt[n2] = h->vwgt[v]; ++n2; }
+    }
+    uint32_t m2 = 0, p2 = 0;
+    pin_off[0] = 0;
+    for (uint32_t e = 0; e < m; ++e) {
+        const uint32_t b = p2;
+        for (uint32_t q = h->pin_off[e]; q < h->pin_off[e + 1]; ++q)
+            if (nid[h->pins[q]] != OR_NONE) pins[p2++] = nid[h->pins[q]];
+        if (p2 == b) continue;
+        nwgt[m2] = h->nwgt[e];
+        pin_off[++m2] = p2;
+    }
+    /* incidence lists: nets ascending per vertex */
+    for (uint32_t v = 0; v <= n2; ++v) inc_off[v] = 0;
+    for (uint32_t q = 0; q < p2; ++q) inc_off[pins[q] + 1]++;
+    for (uint32_t v = 0; v < n2; ++v) inc_off[v + 1] += inc_off[v];
+    uint32_t *cur = (uint32_t *)malloc(sizeof(uint32_t) * (n2 ? n2 : 1));
+    for (uint32_t v = 0; v < n2; ++v) cur[v] = inc_off[v];
+    for (uint32_t e = 0; e < m2; ++e)
+        for (uint32_t q = pin_off[e]; q < pin_off[e + 1]; ++q) inc[cur[pins[q]]++] = e;
+    dims[0] = n2; dims[1] = m2; dims[2] = p2;
+    free(nid); free(cur);
+    return OR_OK;
+}
+
+/* The bisection of one subhypergraph: the multilevel cycle with k = 2 (no
+ * community detection, greedy fill at the bottom), block i limited to L[i],
+ * block 0 filled to T[0]. */
+int or_bisect(const or_hg *h, const or_params *P, const int64_t *L, const int64_t *T, uint32_t *part)
+{
+    or_params P2 = *P;
+    P2.k = 2;
+    P2.community = 0;
+    P2.ip = 0;
+    int64_t f;
+    return multilevel(h, &P2, L, T, part, &f, NULL);
+}
+
+static void rb(const or_hg *h, const or_params *P, int64_t Wtot, uint32_t ktot, uint32_t kk, uint32_t b0,
+               const uint32_t *vmap, uint32_t *out)
+{
+    const uint32_t n = h->n;
+    if (n == 0) return;
+    if (kk == 1) {
+        for (uint32_t v = 0; v < n; ++v) out[vmap[v]] = b0;
+        return;
+    }
+    int64_t L[2], T[2];
+    or_rb_limits(Wtot, ktot, P->eps_num, P->eps_den, or_total_weight(h), kk, L, T);
+    uint32_t *bp = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    or_bisect(h, P, L, T, bp);
+    const uint32_t ks[2] = {(kk + 1) / 2, kk / 2};
+    for (uint32_t side = 0; side < 2; ++side) {
+        or_level S;
+        uint32_t dims[3];
+        S.pin_off = (uint32_t *)malloc(sizeof(uint32_t) * (h->m + 1));
+        S.pins = (uint32_t *)malloc(sizeof(uint32_t) * (h->p ? h->p : 1));
+        S.inc_off = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
+        S.inc = (uint32_t *)malloc(sizeof(uint32_t) * (h->p ? h->p : 1));
+        S.vwgt = (int32_t *)malloc(sizeof(int32_t) * n);
+        S.nwgt = (int32_t *)malloc(sizeof(int32_t) * (h->m ? h->m : 1));
+        S.cid = NULL;
+        uint32_t *smap = (uint32_t *)malloc(sizeof(uint32_t) * n);
+        or_subhypergraph(h, bp, side, dims, S.pin_off, S.pins, S.inc_off, S.inc, S.vwgt, S.nwgt, smap);
+        S.n = dims[0]; S.m = dims[1]; S.p = dims[2];
+        for (uint32_t i = 0; i < S.n; ++i) smap[i] = vmap[smap[i]];
+        or_hg sh = view(&S);
+        rb(&sh, P, Wtot, ktot, ks[side], side == 0 ? b0 : b0 + ks[0], smap, out);
+        free(S.pin_off); free(S.pins); free(S.inc_off); free(S.inc); free(S.vwgt); free(S.nwgt); free(smap);
+    }
+    free(bp);
+}
+
+/* Recursive bipartitioning (Sec. 5, R19): the k-way initial partition of h
+ * by bisections with the imbalance of Eq. 1; side 0 of a bisection into kk
+ * blocks takes blocks b0 .. b0 + ceil(kk/2) - 1, side 1 the rest. */
+int or_rb_ip(const or_hg *h, const or_params *P, uint32_t *part)
+{
+    uint32_t *vmap = (uint32_t *)malloc(sizeof(uint32_t) * (h->n ? h->n : 1));
+    for (uint32_t v = 0; v < h->n; ++v) vmap[v] = v;
+    rb(h, P, or_total_weight(h), P->k, P->k, 0, vmap, part);
+    free(vmap);
     return OR_OK;
 }
 
