@@ -40,6 +40,9 @@ WORKLOADS = {
     "community": "community-aware partition of the 160^3 row-net stencil (k=64, eps=0.03): Louvain communities "
                  "of its bipartite graph (hgp_communities), then the multilevel partition with clusters kept "
                  "inside communities",
+    "rb": "multilevel partition of the 160^3 row-net stencil (k=64, eps=0.03) with the recursive-bipartitioning "
+          "initial partition of its coarsest level (63 bisections, each a k=2 multilevel cycle with the "
+          "imbalance of Eq. 1)",
     "serve": "Poisson stream of partition requests, seed 5: sizes log-uniform in [1e4, 1e7] pins, family uniform "
              "over {random, power-law, stencil, R-MAT}, k uniform in {2..64}, eps=0.03, admitted by workspace "
              "footprint into a continuous-admission server; arrival rate 0.8 x the measured saturation rate",
@@ -57,10 +60,17 @@ def _gen_req(args):
 
 
 def _pool_map(fn, items):
+    """fn over items in worker processes, in order; a progress line on stderr
+    at every tenth of the items (long generations stay visibly alive)."""
     import multiprocessing as mp
     procs = max(1, min(16, os.cpu_count() or 1))
+    out, step = [], max(1, len(items) // 10)
     with mp.get_context("fork").Pool(procs) as pool:
-        return pool.map(fn, items, chunksize=max(1, len(items) // (procs * 8)))
+        for i, r in enumerate(pool.imap(fn, items, chunksize=max(1, len(items) // (procs * 8)))):
+            out.append(r)
+            if (i + 1) % step == 0:
+                print(f"[bench] generated {i + 1}/{len(items)}", file=sys.stderr, flush=True)
+    return out
 
 
 def run_batch(args):
@@ -169,6 +179,8 @@ def run_serve(args):
             if dt > 0:
                 time.sleep(dt)
             tickets.append(S.submit(hs[j], prms[j]))
+            if (j + 1) % max(1, args.count // 4) == 0:
+                print(f"[bench] {factor} x saturation: submitted {j + 1}/{args.count}", file=sys.stderr, flush=True)
         lat, qms = [], []
         for t, _, _ in tickets:
             _, l_ms, q_ms = S.wait(t)
@@ -193,8 +205,10 @@ def run_serve(args):
     runners = [H.Partitioner(hs[i], prms[i], ws=ws) for i in sample]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for R in runners:
+    for i, R in enumerate(runners):
         R.run()
+        if (i + 1) % max(1, len(runners) // 4) == 0:
+            print(f"[bench] one at a time: {i + 1}/{len(runners)}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     Tp = time.perf_counter() - t0
     del runners, ws
@@ -367,6 +381,65 @@ def run_community(args):
     }
 
 
+def run_rb(args):
+    """Recursive bipartitioning (Sec. 5, Eq. 1) on stencil160: one step is one
+    hgp_partition with params.ip = 1.  The same partition with the greedy
+    fill (ip = 0) is timed beside it, so the difference is the cost of the
+    recursive bipartitioning of the coarsest level."""
+    import numpy as np
+    import torch
+    import paper_2303_17679_amd as H
+    h, k = W.workload("stencil160")
+    G = H.Hypergraph.from_host(h)
+    if H.validate(G) != 0:
+        raise SystemExit("stencil160: input failed hgp_validate")
+    P = H.Partitioner(G, H.params(k, seed=args.seed, trusted=True, ip=1))
+    P0 = H.Partitioner(G, H.params(k, seed=args.seed, trusted=True), ws=P.ws)
+    for _ in range(args.warmup):
+        P.run()
+        P0.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        levels = P.run()
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / args.steps
+    f_rb = int(P.f.item())
+    part = P.part.cpu().numpy()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        P0.run()
+    torch.cuda.synchronize()
+    T0 = (time.perf_counter() - t1) / args.steps
+    f_greedy = int(P0.f.item())
+    wts = np.bincount(part, minlength=k)
+    cpu = None
+    match = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        t2 = time.perf_counter()
+        part_o, f_o, L_o = oracle.partition(h, oracle.params(k, seed=args.seed, ip=1))
+        To = time.perf_counter() - t2
+        match = bool(f_o == f_rb and L_o == levels and np.array_equal(part.view(np.uint32), part_o))
+        model, ncpu = cpu_info()
+        cpu = {"value": h.p / To, "unit": "pins/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole stencil160 partition with recursive bipartitioning, one run, single thread, "
+                         f"{To:.1f} s", "host_cpu": model, "host_threads": ncpu}
+    return {
+        "metric": "pins/s for coarsen + recursive-bipartitioning initial partition + LP refine",
+        "value": h.p / T, "unit": "pins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * T, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32/int64 (integer only)", "data": "synthetic",
+        "config": {"workload": "rb", "description": WORKLOADS["rb"], "k": k, "n": h.n, "m": h.m, "pins": h.p,
+                   "levels": levels, "objective": f_rb, "objective_greedy_ip": f_greedy,
+                   "max_block_weight": int(wts.max()), "parallelism": "single GPU"},
+        "phase_ms": {"partition_greedy_ip": 1000.0 * T0, "recursive_bipartitioning": 1000.0 * (T - T0)},
+        "roofline": None,
+        "cpu_baseline": cpu, "oracle_match": match,
+    }
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC runs
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
@@ -451,6 +524,9 @@ def main():
         return
     if args.workload == "community":
         print(json.dumps(run_community(args)), flush=True)
+        return
+    if args.workload == "rb":
+        print(json.dumps(run_rb(args)), flush=True)
         return
     if args.workload in ("batch", "serve"):
         if args.count is None:

@@ -87,6 +87,8 @@ typedef struct {
     uint32_t lp_rounds;         /* R_lp, maximum LP rounds per level [5]               */
     uint32_t flags;             /* HGP_TRUSTED_INPUT or 0 [0]; results do not depend on it */
     uint32_t community;         /* 1: community-aware coarsening (Sec. 4.3), 0: none [0]  */
+    uint32_t ip;                /* initial partition of the coarsest level: 0 greedy BFS
+                                   fill, 1 recursive bipartitioning (Sec. 5, Eq. 1) [0]   */
 } hgp_params;
 
 /* hgp_params.flags: the caller vouches that the hypergraph meets every
@@ -104,6 +106,7 @@ typedef struct {
 #define HGP_OP_INITIAL 6
 #define HGP_OP_GAINS 7     /* hgp_gain_table, hgp_gain_table_update, hgp_gain_recalc, hgp_graph_* */
 #define HGP_OP_COMMUNITY 8 /* hgp_communities */
+#define HGP_OP_RB 9        /* hgp_rb_initial_partition */
 
 /* Host.  Fills *out with the defaults listed in hgp_params for k blocks. */
 hgp_status hgp_default_params(uint32_t k, hgp_params *out);
@@ -187,9 +190,29 @@ hgp_status hgp_refine_lp(const hgp_hg *h, const hgp_params *prm, uint32_t level,
 hgp_status hgp_initial_partition(const hgp_hg *h, uint32_t k, uint32_t *part,
                                  void *ws, size_t ws_bytes, void *stream);
 
+/* Recursive-bipartitioning initial partition (Sec. 5, Eq. 1) of h into
+ * prm->k blocks.  A subhypergraph that gets kk > 1 of the blocks (at first h
+ * with all k) is bisected by the multilevel cycle of hgp_partition with k = 2
+ * and prm's other fields (community detection off, greedy fill at the
+ * bottom): side 0, which will hold ceil(kk/2) blocks, is filled to its target
+ * T_0 = ceil(c(V') ceil(kk/2) / kk), and side i may grow to
+ * floor((1 + eps') T_i), where eps' = ((1 + eps) c(V) kk / (k c(V')))^(1 /
+ * ceil(log2 kk)) - 1 (Eq. 1; IEEE double, the C library's pow).  Then both
+ * sides are extracted as the subhypergraphs of Sec. 2 (vertices renumbered
+ * in ascending ID, every net with a pin on the side kept with those pins,
+ * single-pin nets included) and partitioned in turn: side 0 into blocks b0,
+ * ..., side 1 into the blocks after them.  A subhypergraph with one block
+ * is assigned to it.  Writes part[n] (device).  Workspace:
+ * hgp_workspace_bytes(HGP_OP_RB, n, m, p, prm).  Syncs.  prm->ip and
+ * prm->community are ignored; HGP_TRUSTED_INPUT skips the input check. */
+hgp_status hgp_rb_initial_partition(const hgp_hg *h, const hgp_params *prm, uint32_t *part,
+                                    void *ws, size_t ws_bytes, void *stream);
+
 /* Whole multilevel partition (paper Alg. 1 with the deterministic components
  * above, without FM and flows): coarsen while n > limit_factor*k and a pass
- * shrinks n by more than 1 %; greedy initial partition of the coarsest level;
+ * shrinks n by more than 1 %; initial partition of the coarsest level by the
+ * greedy fill of hgp_initial_partition (prm->ip = 0) or by recursive
+ * bipartitioning as in hgp_rb_initial_partition (prm->ip = 1);
  * LP on the coarsest level, then project + LP on every finer level.
  * Writes part[n] and *objective (device int64); *levels_out (host, may be
  * NULL) gets the number of contractions.  Syncs. */

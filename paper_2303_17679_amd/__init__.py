@@ -18,8 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhgp.so")
 
-OP_COARSEN, OP_CONTRACT, OP_REFINE, OP_PARTITION, OP_VALIDATE, OP_INITIAL, OP_GAINS, OP_COMMUNITY = \
-    1, 2, 3, 4, 5, 6, 7, 8
+OP_COARSEN, OP_CONTRACT, OP_REFINE, OP_PARTITION, OP_VALIDATE, OP_INITIAL, OP_GAINS, OP_COMMUNITY, OP_RB = \
+    1, 2, 3, 4, 5, 6, 7, 8, 9
 STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_OVERFLOW", -3: "HGP_E_WORKSPACE",
           -4: "HGP_E_DEVICE", -5: "HGP_E_UNSUPPORTED"}
 
@@ -29,7 +29,7 @@ EXPORTS = ["hgp_default_params", "hgp_workspace_bytes", "hgp_validate", "hgp_coa
            "hgp_server_create", "hgp_server_submit", "hgp_server_wait", "hgp_server_destroy",
            "hgp_batch_workspace_bytes", "hgp_partition_batch", "hgp_refine_lp_static",
            "hgp_partition_traced", "hgp_gain_table", "hgp_gain_table_update", "hgp_gain_recalc",
-           "hgp_graph_gain_table", "hgp_graph_moves", "hgp_communities"]
+           "hgp_graph_gain_table", "hgp_graph_moves", "hgp_communities", "hgp_rb_initial_partition"]
 
 # kernel ids of the measurement calls, with the kernel symbol each one names
 KERNELS = ["k_rate_group<8, 64, 6>", "k_rate_group<16, 256, 8>", "k_rate_group<64, 1024, 10>", "k_rate_block",
@@ -67,16 +67,20 @@ class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("eps_num", ctypes.c_uint32), ("eps_den", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("limit_factor", ctypes.c_uint32),
                 ("coarsen_subrounds", ctypes.c_uint32), ("lp_subrounds", ctypes.c_uint32),
-                ("lp_rounds", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("community", ctypes.c_uint32)]
+                ("lp_rounds", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("community", ctypes.c_uint32),
+                ("ip", ctypes.c_uint32)]
 
 
 def params(k: int, eps=(3, 100), seed: int = 0, limit_factor: int = 160, coarsen_subrounds: int = 3,
-           lp_subrounds: int = 5, lp_rounds: int = 5, trusted: bool = False, community: bool = False) -> Params:
+           lp_subrounds: int = 5, lp_rounds: int = 5, trusted: bool = False, community: bool = False,
+           ip: int = 0) -> Params:
     """trusted: the input was validated before (hgp_validate), so
     hgp_partition skips its own input check (HGP_TRUSTED_INPUT).
-    community: community-aware coarsening (hgp_communities first)."""
+    community: community-aware coarsening (hgp_communities first).
+    ip: initial partition of the coarsest level, 0 greedy BFS fill, 1
+    recursive bipartitioning (Sec. 5, Eq. 1)."""
     return Params(k, eps[0], eps[1], seed, limit_factor, coarsen_subrounds, lp_subrounds, lp_rounds,
-                  1 if trusted else 0, 1 if community else 0)
+                  1 if trusted else 0, 1 if community else 0, ip)
 
 
 _lib = None
@@ -102,6 +106,8 @@ def lib():
         L.hgp_refine_lp_static.restype = i32; L.hgp_refine_lp_static.argtypes = [P, P, u32, P, P, P, P]
         L.hgp_initial_partition.restype = i32
         L.hgp_initial_partition.argtypes = [P, u32, P, P, ctypes.c_size_t, P]
+        L.hgp_rb_initial_partition.restype = i32
+        L.hgp_rb_initial_partition.argtypes = [P, P, P, P, ctypes.c_size_t, P]
         L.hgp_partition.restype = i32
         L.hgp_partition.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_uint32), P, ctypes.c_size_t, P]
         L.hgp_gain_table.restype = i32; L.hgp_gain_table.argtypes = [P, u32, P, P, P, P, ctypes.c_size_t, P]
@@ -382,6 +388,18 @@ def initial_partition(h: Hypergraph, k: int):
     s = h.struct()
     _check(lib().hgp_initial_partition(ctypes.byref(s), k, _ptr(part), _ptr(ws), ws.numel(), _stream()),
            "hgp_initial_partition")
+    return part
+
+
+def rb_initial_partition(h: Hypergraph, prm: Params, ws=None):
+    """hgp_rb_initial_partition: the recursive-bipartitioning initial
+    partition (Sec. 5, Eq. 1) of h into prm.k blocks (int32 tensor)."""
+    torch = _torch()
+    part = torch.empty(h.n, dtype=torch.int32, device=h.device)
+    ws = _ws(OP_RB, h, prm) if ws is None else ws
+    s = h.struct()
+    _check(lib().hgp_rb_initial_partition(ctypes.byref(s), ctypes.byref(prm), _ptr(part), _ptr(ws), ws.numel(),
+                                          _stream()), "hgp_rb_initial_partition")
     return part
 
 

@@ -2,6 +2,7 @@
 // driver (paper Alg. 1 with the deterministic components, no FM / flows).
 #include "kernels.h"
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 using namespace hgp;
@@ -19,7 +20,7 @@ hgp_status check_params(const hgp_params *p) {
     if (p->coarsen_subrounds == 0 || p->lp_subrounds == 0) return HGP_E_INVALID;
     if (p->coarsen_subrounds > 256 || p->lp_subrounds > 256 || p->lp_rounds > 65535) return HGP_E_INVALID;
     if (p->flags & ~HGP_TRUSTED_INPUT) return HGP_E_INVALID;
-    if (p->community > 1) return HGP_E_INVALID;
+    if (p->community > 1 || p->ip > 1) return HGP_E_INVALID;
     return HGP_OK;
 }
 
@@ -67,6 +68,21 @@ size_t level_bytes(uint32_t n, uint32_t m, uint32_t p) {
     return 4ull * ((size_t)m + 1 + p + (size_t)n + 1 + p + n + m + n + n) + 8 * 256;
 }
 
+// Recursive bipartitioning: a bisection's whole multilevel workspace, and
+// along the recursion path every subhypergraph with its parent's capacities,
+// its maps and its bisection.
+size_t rb_bytes(uint32_t n, uint32_t m, uint32_t p, const hgp_params &dp) {
+    hgp_params p2 = dp;
+    p2.k = 2;
+    p2.ip = 0;
+    p2.community = 0;
+    size_t bis = 0;
+    HGP_REQUIRE(hgp_workspace_bytes(HGP_OP_PARTITION, n, m, p, &p2, &bis) == HGP_OK, HGP_E_INVALID);
+    uint32_t depth = 1;
+    while ((1u << depth) < dp.k) ++depth;
+    return bis + (size_t)(depth + 1) * (level_bytes(n, m, p) + 12ull * n + 4096);
+}
+
 }  // namespace
 
 extern "C" {
@@ -83,6 +99,7 @@ hgp_status hgp_default_params(uint32_t k, hgp_params *out) {
     out->lp_rounds = 5;
     out->flags = 0;
     out->community = 0;
+    out->ip = 0;
     return HGP_OK;
 }
 
@@ -124,8 +141,10 @@ hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p, const
                     hier += 8 * (4ull * n + 256) + 4ull * n;
                 }
                 need = temp + hier;
+                if (dp.ip == 1) need += rb_bytes(n, m, p, dp);  // of the coarsest level (at most the input)
                 break;
             }
+            case HGP_OP_RB: need = rb_bytes(n, m, p, dp); break;
             default: return HGP_E_INVALID;
         }
         *out = need + 4096;
@@ -221,11 +240,35 @@ hgp_status hgp_initial_partition(const hgp_hg *h, uint32_t k, uint32_t *part, vo
 }  // extern "C"
 
 namespace {
+hgp_status rb_initial_partition(const hgp_hg &h, const hgp_params &prm, uint32_t *part, Arena &A, hipStream_t st);
+}
+
+extern "C" hgp_status hgp_rb_initial_partition(const hgp_hg *h, const hgp_params *prm, uint32_t *part, void *ws,
+                                               size_t ws_bytes, void *stream) {
+    hgp_status s = check_hg(h);
+    if (s == HGP_OK) s = check_params(prm);
+    if (s != HGP_OK) return s;
+    if (!part || !ws) return HGP_E_INVALID;
+    return guarded(S(stream), [&]() {
+        Arena A(ws, ws_bytes);
+        if (!(prm->flags & HGP_TRUSTED_INPUT)) {
+            const hgp_status v = validate(*h, A, S(stream));
+            if (v != HGP_OK) return v;
+        }
+        return rb_initial_partition(*h, *prm, part, A, S(stream));
+    });
+}
+
+namespace {
+
 // The multilevel driver (paper Alg. 1 with the deterministic components, no
 // FM / flows) on one hypergraph, scratch from A, work on st.  Syncs.  Throws
-// Error on workspace or device failures.
+// Error on workspace or device failures.  side_limits / fill_target: the
+// block limits and the fill target of a bisection of the recursive
+// bipartitioning (k = 2), or null / -1.
 hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part, int64_t *objective,
-                         uint32_t *levels_out, Arena &A, hipStream_t st, hgp_trace *trace = nullptr) {
+                         uint32_t *levels_out, Arena &A, hipStream_t st, hgp_trace *trace = nullptr,
+                         const int64_t *side_limits = nullptr, int64_t fill_target = -1) {
     if (!(prm->flags & HGP_TRUSTED_INPUT)) {
         const hgp_status v = validate(*h0, A, st);
         if (v != HGP_OK) return v;
@@ -295,13 +338,18 @@ hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
     auto rounds_of = [&](uint32_t l) -> uint32_t * {
         return (trace && trace->lp_rounds && l < trace->cap) ? trace->lp_rounds + l : nullptr;
     };
-    initial_partition(cs, prm->k, cpart, A, st, W);
-    refine_lp(cs, *prm, nl, cpart, objective, nullptr, A, st, W, rounds_of(nl));
+    if (prm->ip == 1) {
+        const hgp_status rs = rb_initial_partition(cs, *prm, cpart, A, st);
+        if (rs != HGP_OK) return rs;
+    } else {
+        initial_partition(cs, prm->k, cpart, A, st, W, fill_target);
+    }
+    refine_lp(cs, *prm, nl, cpart, objective, nullptr, A, st, W, rounds_of(nl), side_limits);
     for (int l = (int)nl - 1; l >= 0; --l) {
         hgp_hg fh = L[l].h;
         uint32_t *fpart = (l == 0) ? part : A.alloc<uint32_t>(fh.n);
         project(fh.n, L[l].cid, cpart, fpart, st);
-        refine_lp(fh, *prm, (uint32_t)l, fpart, objective, nullptr, A, st, W, rounds_of((uint32_t)l));
+        refine_lp(fh, *prm, (uint32_t)l, fpart, objective, nullptr, A, st, W, rounds_of((uint32_t)l), side_limits);
         cpart = fpart;
     }
     stream_sync(st);
@@ -315,6 +363,95 @@ hgp_status partition_one(const hgp_hg *h0, const hgp_params *prm, uint32_t *part
         }
     }
     return HGP_OK;
+}
+
+// Limits and fill targets of a bisection (Eq. 1): a subhypergraph of weight
+// Wsub that gets kk of the ktot blocks of a hypergraph of weight Wtot; side 0
+// takes ceil(kk/2) blocks.  eps' is computed in IEEE double with the C
+// library's pow; side i's target is ceil(Wsub k_i / kk), its limit
+// floor((1 + eps') target_i).
+void rb_limits(int64_t Wtot, uint32_t ktot, const hgp_params &prm, int64_t Wsub, uint32_t kk, int64_t L[2],
+               int64_t T[2]) {
+    const uint32_t ks[2] = {(kk + 1) / 2, kk / 2};
+    uint32_t lg = 0;
+    while ((1u << lg) < kk) ++lg;
+    const double eps = (double)prm.eps_num / (double)prm.eps_den;
+    const double base = (1.0 + eps) * ((double)Wtot / (double)ktot) * ((double)kk / (double)Wsub);
+    const double epsp = std::pow(base, 1.0 / (double)lg) - 1.0;
+    for (int i = 0; i < 2; ++i) {
+        T[i] = (Wsub * (int64_t)ks[i] + (int64_t)kk - 1) / (int64_t)kk;
+        L[i] = (int64_t)std::floor((1.0 + epsp) * (double)T[i]);
+    }
+}
+
+struct RbRun {
+    const hgp_params *prm;
+    int64_t Wtot;
+    uint32_t *part;
+    Arena *A;
+    hipStream_t st;
+};
+
+// Subhypergraph H (its vertex i stands for vertex vmap[i] of the level being
+// partitioned) into kk blocks from b0 on: bisect, extract both sides, recurse.
+hgp_status rb_rec(const RbRun &R, const hgp_hg &H, uint32_t kk, uint32_t b0, const uint32_t *vmap) {
+    Arena &A = *R.A;
+    if (H.n == 0) return HGP_OK;
+    if (kk == 1) {
+        assign_block(vmap, H.n, b0, R.part, R.st);
+        return HGP_OK;
+    }
+    const int64_t Wsub = total_weight(H.vwgt, H.n, A, R.st);
+    int64_t L[2], T[2];
+    rb_limits(R.Wtot, R.prm->k, *R.prm, Wsub, kk, L, T);
+    const size_t mk = A.mark();
+    uint32_t *bp = A.alloc<uint32_t>(H.n);
+    int64_t *obj = A.alloc<int64_t>(1);
+    hgp_params p2 = *R.prm;
+    p2.k = 2;
+    p2.ip = 0;
+    p2.community = 0;
+    p2.flags |= HGP_TRUSTED_INPUT;  // built here, valid by construction
+    const size_t mkb = A.mark();  // the bisection's hierarchy is free again once bp holds its result
+    hgp_status s = partition_one(&H, &p2, bp, obj, nullptr, A, R.st, nullptr, L, T[0]);
+    A.release(mkb);
+    const uint32_t ks[2] = {(kk + 1) / 2, kk / 2};
+    for (uint32_t side = 0; side < 2 && s == HGP_OK; ++side) {
+        const size_t mk2 = A.mark();
+        hgp_hg_out out;
+        out.cap_n = H.n; out.cap_m = H.m; out.cap_p = H.p;
+        out.pin_off = A.alloc<uint32_t>((size_t)H.m + 1);
+        out.pins = A.alloc<uint32_t>(H.p);
+        out.inc_off = A.alloc<uint32_t>((size_t)H.n + 1);
+        out.inc = A.alloc<uint32_t>(H.p);
+        out.vwgt = A.alloc<int32_t>(H.n);
+        out.nwgt = A.alloc<int32_t>(H.m);
+        out.dims = nullptr;
+        uint32_t *smap = A.alloc<uint32_t>(H.n);
+        uint32_t *cmap = A.alloc<uint32_t>(H.n);
+        uint32_t dims[3];
+        subhypergraph(H, bp, side, out, smap, dims, A, R.st);
+        gather_map(vmap, smap, dims[0], cmap, R.st);
+        hgp_hg S{dims[0], dims[1], dims[2], out.pin_off, out.pins, out.inc_off, out.inc, out.vwgt, out.nwgt};
+        s = rb_rec(R, S, ks[side], side == 0 ? b0 : b0 + ks[0], cmap);
+        A.release(mk2);
+    }
+    A.release(mk);
+    return s;
+}
+
+// Recursive bipartitioning (Sec. 5, Eq. 1): the k-way initial partition of h
+// by bisections, each a multilevel cycle with k = 2 and the side limits of
+// Eq. 1.
+hgp_status rb_initial_partition(const hgp_hg &h, const hgp_params &prm, uint32_t *part, Arena &A, hipStream_t st) {
+    const size_t mk = A.mark();
+    uint32_t *vmap = A.alloc<uint32_t>(h.n);
+    iota_u32(vmap, h.n, st);
+    const RbRun R{&prm, total_weight(h.vwgt, h.n, A, st), part, &A, st};
+    const hgp_status s = rb_rec(R, h, prm.k, 0, vmap);
+    stream_sync(st);
+    A.release(mk);
+    return s;
 }
 }  // namespace
 

@@ -548,13 +548,14 @@ static uint32_t read_u32(const uint32_t *d, hipStream_t st) {
     return h;
 }
 
-void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st, int64_t W_known) {
+void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st, int64_t W_known,
+                       int64_t fill_target) {
     const uint32_t n = h.n;
     size_t mk = A.mark();
     IpBufs B;
     plan(A, n, h.p, k, B);
     const int64_t W = W_known >= 0 ? W_known : total_weight(h.vwgt, n, A, st);
-    const uint64_t T = (uint64_t)((W + k - 1) / k);
+    const uint64_t T = fill_target >= 0 ? (uint64_t)fill_target : (uint64_t)((W + k - 1) / k);
     bool small = n > 0 && n <= IPS_MAX_N && h.p <= IPS_MAX_P;
     if (small) {
         unsigned long long *sq = (unsigned long long *)B.P;  // scratch until the fill

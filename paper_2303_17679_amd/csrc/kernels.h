@@ -30,13 +30,19 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
 size_t refine_workspace(uint32_t n, uint32_t m, uint32_t k);
 void objective(const hgp_hg &h, uint32_t k, const uint32_t *part, int64_t *obj, int64_t *bw, Arena &A,
                hipStream_t st);
-// rounds_out (host, may be null): LP rounds run on the level.
+// rounds_out (host, may be null): LP rounds run on the level.  side_limits
+// (host, may be null; k must be 2): the weight limits of blocks 0 and 1 of a
+// bisection of the recursive bipartitioning, in place of L_max.
 void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj, int64_t *bw,
-               Arena &A, hipStream_t st, int64_t W_known = -1, uint32_t *rounds_out = nullptr);
+               Arena &A, hipStream_t st, int64_t W_known = -1, uint32_t *rounds_out = nullptr,
+               const int64_t *side_limits = nullptr);
 
 // ip.hip
 size_t ip_workspace(uint32_t n, uint32_t p, uint32_t k);
-void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st, int64_t W_known = -1);
+// fill_target >= 0: every block is filled to it instead of ceil(c(V)/k) (a
+// bisection fills block 0 to its share; the last block takes the rest).
+void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st, int64_t W_known = -1,
+                       int64_t fill_target = -1);
 void project(uint32_t n, const uint32_t *cid, const uint32_t *cpart, uint32_t *part, hipStream_t st);
 
 // community.hip
@@ -45,6 +51,16 @@ hgp_status communities(const hgp_hg &h, uint64_t seed, uint32_t *comm, uint32_t 
                        hipStream_t st);
 // ccomm[cid[u]] = comm[u] for u < n: the communities of a contracted level
 void community_down(uint32_t n, const uint32_t *cid, const uint32_t *comm, uint32_t *ccomm, hipStream_t st);
+
+// rb.hip: the subhypergraph of the vertices with part[v] == side (Sec. 2
+// definition) into out (capacities of h suffice); vmap[i] <- the vertex of h
+// that vertex i of the subhypergraph stands for; dims_host <- n', m', p'.
+// Syncs.
+void subhypergraph(const hgp_hg &h, const uint32_t *part, uint32_t side, const hgp_hg_out &out, uint32_t *vmap,
+                   uint32_t *dims_host, Arena &A, hipStream_t st);
+void gather_map(const uint32_t *outer, const uint32_t *inner, uint32_t n, uint32_t *out, hipStream_t st);
+void assign_block(const uint32_t *vmap, uint32_t n, uint32_t b, uint32_t *part, hipStream_t st);
+void iota_u32(uint32_t *p, uint32_t n, hipStream_t st);
 
 // gaintable.hip
 size_t gaintable_workspace(uint32_t n, uint32_t m, uint32_t k, uint32_t count);

@@ -373,7 +373,7 @@ struct GainArgs {
     const uint32_t *part;
     const int64_t *bw;
     const uint32_t *bcnt;  // incident nets with lambda > 1 (boundary iff > 0)
-    int64_t lmax;
+    const int64_t *lmax;  // [k] weight limit of every block
     uint64_t mseed;
     uint32_t level, round, sub, S, n;
     uint32_t *prop_t, *prop_g;
@@ -552,7 +552,7 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
                         const int bit = __ffsll((long long)x) - 1;
                         x &= x - 1;
                         const uint32_t t = (uint32_t)(q * 64 + bit);
-                        if (a.bw[t] + cu > a.lmax) continue;
+                        if (a.bw[t] + cu > a.lmax[t]) continue;
                         int64_t aff = 0;
 #pragma unroll
                         for (int c = 0; c < NC; ++c)
@@ -603,7 +603,7 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
 #pragma unroll
                 for (int q = 0; q < KW; ++q) {
                     const uint32_t t = (uint32_t)(q * 64) + l;
-                    if (!((U[q] >> l) & 1ull) || a.bw[t] + cu > a.lmax) continue;
+                    if (!((U[q] >> l) & 1ull) || a.bw[t] + cu > a.lmax[t]) continue;
                     const int64_t gn = bu - (wI - aff[t]);
                     if (gn > (int64_t)best_g) { best_g = (uint32_t)gn; best_t = t; }
                 }
@@ -773,7 +773,7 @@ __global__ __launch_bounds__(HUB_THREADS) void k_gains_hub(GainArgs<KW> a, const
         if (tid < 64 * KW) {  // thread t judges block t
             const uint32_t t = tid;
             const bool inU = (Us[t >> 6] >> (t & 63)) & 1ull;
-            if (inU && t != s && a.bw[t] + cu <= a.lmax) {
+            if (inU && t != s && a.bw[t] + cu <= a.lmax[t]) {
                 const int64_t gn = bu - (wI - aff[t]);
                 if (gn > 0) { best_g = (uint32_t)gn; best_t = t; }
             }
@@ -898,7 +898,7 @@ __global__ __launch_bounds__(BLOCK) void k_gains_hub_pick(GainArgs<KW> a, const 
         if (tid < 64 * KW) {  // thread t judges block t
             const uint32_t t = tid;
             const bool inU = (hU[(size_t)i * KW + (t >> 6)] >> (t & 63)) & 1ull;
-            if (inU && t != s && a.bw[t] + cu <= a.lmax) {
+            if (inU && t != s && a.bw[t] + cu <= a.lmax[t]) {
                 const int64_t gn = bu - (wI - acc[t]);
                 if (gn > 0) { best_g = (uint32_t)gn; best_t = t; }
             }
@@ -1153,7 +1153,7 @@ __device__ inline int64_t floor_div_i64(int64_t a, int64_t b) {
 }
 
 __global__ void k_lp_select(const uint64_t *keys, uint32_t np, KeyLayout L, uint32_t k, const uint32_t *seg_start,
-                            const uint32_t *seg_end, const uint64_t *incl, const int64_t *bw, int64_t lmax,
+                            const uint32_t *seg_end, const uint64_t *incl, const int64_t *bw, const int64_t *lmax,
                             unsigned long long *best) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
         uint64_t key = keys[i];
@@ -1162,8 +1162,8 @@ __global__ void k_lp_select(const uint64_t *keys, uint32_t np, KeyLayout L, uint
         uint32_t x = s < t ? s : t, y = s < t ? t : s;  // unordered pair, A = moves x->y
         SegView A = seg_view(seg_start, seg_end, x * k + y, incl);
         SegView Bv = seg_view(seg_start, seg_end, y * k + x, incl);
-        int64_t beta_x = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
-        int64_t beta_y = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
+        int64_t beta_x = floor_div_i64(lmax[x] - bw[x], (int64_t)k - 1);
+        int64_t beta_y = floor_div_i64(lmax[y] - bw[y], (int64_t)k - 1);
         uint32_t ia, jb;
         if (s == x) {
             uint32_t loc = i - A.start;
@@ -1263,39 +1263,78 @@ __device__ inline size_t pair_segment(uint32_t x, uint32_t y, uint32_t k, uint32
 __global__ __launch_bounds__(BLOCK) void k_lp_fast(const uint32_t *plist, const uint32_t *pcnt, uint32_t slot_cap,
                                                    const uint32_t *prop_t, const uint32_t *pw, uint32_t k,
                                                    const int32_t *vwgt, uint32_t *part, const int64_t *bw,
-                                                   int64_t lmax, int64_t *dbw_g, uint32_t *pcur, uint32_t *seg,
+                                                   const int64_t *lmax, int64_t *dbw_g, uint32_t *pcur, uint32_t *seg,
                                                    uint32_t seg_cap, uint32_t *spairs, uint32_t *nsp, LpCtl ctl) {
     if (lp_skip(ctl)) return;
+    constexpr uint32_t HSLOTS = 2 * BLOCK;  // pair table of one step: at most BLOCK keys, half full
+    static_assert(HSLOTS == 512, "the slot hash takes 9 bits");
     __shared__ int64_t dbw[256];
+    __shared__ uint32_t hkey[HSLOTS], hcnt[HSLOTS], hbase[HSLOTS];
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK) dbw[b] = 0;
     __syncthreads();
     const uint32_t sl = blockIdx.x % NSLOT, bj = blockIdx.x / NSLOT, nbj = gridDim.x / NSLOT;
     const uint32_t np = pcnt[sl * SPREAD_U32];
     const uint32_t *pl = plist + (size_t)sl * slot_cap;
-    for (uint32_t base = bj * BLOCK; base < np; base += nbj * BLOCK) {
+    for (uint32_t base = bj * BLOCK; base < np; base += nbj * BLOCK) {  // uniform per block
         const uint32_t i = base + threadIdx.x;
+        bool slow = false;
+        uint32_t u = 0, x = 0, y = 0;
         if (i < np) {
-            const uint32_t u = pl[i];
+            u = pl[i];
             const uint32_t s = part[u], t = prop_t[u];
-            const uint32_t x = s < t ? s : t, y = s < t ? t : s;
+            x = s < t ? s : t;
+            y = s < t ? t : s;
             const int64_t xf = (int64_t)pw[x * k + y] - (int64_t)pw[y * k + x];
-            const int64_t beta_x = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
-            const int64_t beta_y = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
+            const int64_t beta_x = floor_div_i64(lmax[x] - bw[x], (int64_t)k - 1);
+            const int64_t beta_y = floor_div_i64(lmax[y] - bw[y], (int64_t)k - 1);
             if (-beta_x <= xf && xf <= beta_y) {
                 part[u] = t;
                 int64_t c = vwgt[u];
                 atomicAdd((unsigned long long *)&dbw[s], (unsigned long long)(-c));
                 atomicAdd((unsigned long long *)&dbw[t], (unsigned long long)c);
             } else {
-                const uint32_t at = atomicAdd(&pcur[x * k + y], 1u);
-                if (at < seg_cap) seg[pair_segment(x, y, k, seg_cap) + at] = u;
-                if (at == 0) spairs[atomicAdd(nsp, 1u)] = x * k + y;  // the pair's first proposal lists it
+                slow = true;
             }
+        }
+        // The step's proposals of oversized pairs take their segment positions
+        // with one global atomic per pair and step: an LDS table counts them
+        // per pair first (a pair whose proposals all hit one global counter
+        // would serialise them).  The order inside a segment does not
+        // matter: the pair kernel sorts it.
+        if (__syncthreads_or(slow)) {
+            for (uint32_t q = threadIdx.x; q < HSLOTS; q += BLOCK) { hkey[q] = NONE; hcnt[q] = 0; }
+            __syncthreads();
+            const uint32_t key = x * k + y;
+            uint32_t slot = 0, rank = 0;
+            if (slow) {
+                slot = (key * 2654435761u) >> (32 - 9);  // 9 bits: HSLOTS = 512
+                for (;;) {
+                    const uint32_t old = atomicCAS(&hkey[slot], NONE, key);
+                    if (old == NONE || old == key) break;
+                    slot = (slot + 1) & (HSLOTS - 1);
+                }
+                rank = atomicAdd(&hcnt[slot], 1u);
+            }
+            __syncthreads();
+            if (slow && rank == 0) hbase[slot] = atomicAdd(&pcur[key], hcnt[slot]);
+            __syncthreads();
+            if (slow) {
+                const uint32_t at = hbase[slot] + rank;
+                if (at < seg_cap) seg[pair_segment(x, y, k, seg_cap) + at] = u;
+                if (at == 0) spairs[atomicAdd(nsp, 1u)] = key;  // the pair's first proposal lists it
+            }
+            __syncthreads();  // the table is cleared by the next step
         }
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < k; b += BLOCK)
         if (dbw[b]) atomic_add_i64(&dbw_g[b], dbw[b]);
+}
+
+// Block weight limits: every block `uniform`, or blocks 0 and 1 `l0`, `l1`
+// (a bisection, k = 2).
+__global__ void k_set_limits(int64_t *lmax, uint32_t k, int64_t uniform, int64_t l0, int64_t l1) {
+    for (uint32_t b = threadIdx.x; b < k; b += blockDim.x) lmax[b] = k == 2 ? (b == 0 ? l0 : l1) : uniform;
 }
 
 // Clears up to ZERO_MAX word ranges in one launch.
@@ -1392,7 +1431,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *spair
                                                            const uint32_t *pc, const uint32_t *seg, uint32_t seg_cap,
                                                            uint32_t k,
                                                            const uint32_t *prop_g, const int32_t *vwgt,
-                                                           uint32_t *part, const int64_t *bw, int64_t lmax,
+                                                           uint32_t *part, const int64_t *bw, const int64_t *lmax,
                                                            int64_t *dbw_g, uint32_t *slowpair, LpCtl ctl) {
     __shared__ uint64_t skey[PAIR_MAX];
     __shared__ uint32_t sincl[PAIR_MAX];
@@ -1456,8 +1495,8 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_lp_pairs(const uint32_t *spair
         LSeg A, Bv;
         A.start = 0; A.len = nA; A.base = 0; A.incl = sincl;
         Bv.start = nA; Bv.len = L - nA; Bv.base = nA ? sincl[nA - 1] : 0u; Bv.incl = sincl;
-        const int64_t beta_x = floor_div_i64(lmax - bw[x], (int64_t)k - 1);
-        const int64_t beta_y = floor_div_i64(lmax - bw[y], (int64_t)k - 1);
+        const int64_t beta_x = floor_div_i64(lmax[x] - bw[x], (int64_t)k - 1);
+        const int64_t beta_y = floor_div_i64(lmax[y] - bw[y], (int64_t)k - 1);
         if (tid == 0 && beta_x >= 0 && beta_y >= 0) atomicMax(&sbest, 1ull << 32);  // the start state
         // every element tests the walk state right after it
         for (uint32_t i = tid; i < L; i += PAIR_THREADS) {
@@ -1707,6 +1746,7 @@ struct RefineBufs {
     int64_t *f;     // objective, spread over SPREAD slots
     int64_t *bw;
     uint32_t *longl, *plist, *prop_t, *prop_g, *tstamp, *bcnt, *scal, *heavy, *hcbase, *pw, *slow;
+    int64_t *lmaxv;  // [k] block weight limits
     uint32_t *pcnt;  // [2][NSLOT * SPREAD_U32] proposal-list lengths, alternate sub-rounds
     uint32_t *cl;    // [3][NSLOT] candidate lists by degree class and slot
     uint32_t *ccnt;  // [3 * NSLOT * SPREAD_U32] their lengths
@@ -1762,6 +1802,7 @@ static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t k, RefineBufs &B) {
     B.seg = A.alloc<uint32_t>((size_t)k * (k - 1) / 2 * pair_seg_cap(n));
     B.slow = A.alloc<uint32_t>(n);
     B.heavy = A.alloc<uint32_t>(n);
+    B.lmaxv = A.alloc<int64_t>(k);
     B.hcbase = A.alloc<uint32_t>((size_t)n + 1);
     B.dbw_g = A.alloc<int64_t>(k);
     sort_reserve(A, n);
@@ -1827,13 +1868,20 @@ void objective(const hgp_hg &h, uint32_t k, const uint32_t *part, int64_t *obj, 
 
 template <int KW>
 static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj,
-                     int64_t *bw_out, Arena &A, hipStream_t st, int64_t W_known, uint32_t *rounds_out) {
+                     int64_t *bw_out, Arena &A, hipStream_t st, int64_t W_known, uint32_t *rounds_out,
+                     const int64_t *side_limits) {
     const uint32_t n = h.n, m = h.m, k = prm.k;
     size_t mk = A.mark();
     RefineBufs B;
     plan(A, n, m, k, B);
     const int64_t W = W_known >= 0 ? W_known : total_weight(h.vwgt, n, A, st);
-    const int64_t lmax = ((int64_t)(prm.eps_den + prm.eps_num) * ((W + k - 1) / k)) / (int64_t)prm.eps_den;
+    // the weight limit of every block: L_max = (1 + eps) ceil(c(V) / k), or
+    // the two side limits of a bisection of the recursive bipartitioning
+    const int64_t Lmax = ((int64_t)(prm.eps_den + prm.eps_num) * ((W + k - 1) / k)) / (int64_t)prm.eps_den;
+    k_set_limits<<<1, 256, 0, st>>>(B.lmaxv, k, Lmax, side_limits ? side_limits[0] : Lmax,
+                                    side_limits ? side_limits[1] : Lmax);
+    HGP_LAUNCH_CHECK();
+    const int64_t *lmax = B.lmaxv;
     const uint64_t mseed = mix64(prm.seed);
     // device scalars: ntouched and nlong are adjacent so one memset clears both
     uint32_t *gmax = B.scal + 1, *ntouched = B.scal + 2, *nlong = B.scal + 3,
@@ -2200,12 +2248,12 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
 }
 
 void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t *part, int64_t *obj, int64_t *bw,
-               Arena &A, hipStream_t st, int64_t W_known, uint32_t *rounds_out) {
+               Arena &A, hipStream_t st, int64_t W_known, uint32_t *rounds_out, const int64_t *side_limits) {
     switch ((prm.k + 63) / 64) {
-        case 1: refine_t<1>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out); break;
-        case 2: refine_t<2>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out); break;
-        case 3: refine_t<3>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out); break;
-        default: refine_t<4>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out); break;
+        case 1: refine_t<1>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out, side_limits); break;
+        case 2: refine_t<2>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out, side_limits); break;
+        case 3: refine_t<3>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out, side_limits); break;
+        default: refine_t<4>(h, prm, level, part, obj, bw, A, st, W_known, rounds_out, side_limits); break;
     }
 }
 

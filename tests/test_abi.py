@@ -27,7 +27,7 @@ def H():
 
 def test_header_symbols_exported(H):
     names = declared()
-    assert len(names) == 28
+    assert len(names) == 29
     assert names == sorted(H.EXPORTS)
     L = ctypes.CDLL(H.LIB_PATH)
     for n in names:
@@ -69,9 +69,24 @@ def test_bad_parameters_rejected_on_host(H):
     assert L.hgp_workspace_bytes(H.OP_REFINE, 10, 10, 10, ctypes.byref(H.params(4, eps=(1, 0))),
                                  ctypes.byref(out)) == -1
     assert L.hgp_workspace_bytes(99, 10, 10, 10, None, ctypes.byref(out)) == -1
+    assert L.hgp_workspace_bytes(H.OP_REFINE, 10, 10, 10, ctypes.byref(H.params(4, ip=2)), ctypes.byref(out)) == -1
+    assert L.hgp_rb_initial_partition(None, ctypes.byref(H.params(4)), None, None, 0, None) == -1
     # null hypergraph / workspace pointers are refused before any device work
     assert L.hgp_partition(None, ctypes.byref(H.params(4)), None, None, None, None, 0, None) == -1
     assert L.hgp_coarsen(None, None, 0, None, None, None, 0, None) == -1
+
+
+def test_rb_workspace_covers_a_bisection_and_the_path(H):
+    # recursive bipartitioning needs a whole k = 2 multilevel workspace plus
+    # the subhypergraphs along the recursion; the partition with ip = 1 adds it
+    n, m, p = 100000, 120000, 600000
+    bis = H.workspace_bytes(H.OP_PARTITION, n, m, p, H.params(2))
+    for k in (2, 3, 8, 64, 256):
+        rb = H.workspace_bytes(H.OP_RB, n, m, p, H.params(k))
+        assert rb > bis
+        assert H.workspace_bytes(H.OP_PARTITION, n, m, p, H.params(k, ip=1)) > \
+            H.workspace_bytes(H.OP_PARTITION, n, m, p, H.params(k)) + bis
+    assert H.workspace_bytes(H.OP_RB, n, m, p, H.params(256)) > H.workspace_bytes(H.OP_RB, n, m, p, H.params(8))
 
 
 def test_static_refine_rejects_levels_beyond_its_scratch(H):

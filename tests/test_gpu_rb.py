@@ -1,0 +1,108 @@
+"""GPU parity of the recursive-bipartitioning initial partition (Sec. 5,
+Eq. 1) against the oracle, through the C ABI: the block of every vertex from
+hgp_rb_initial_partition, and the final partition, objective and level sizes
+of hgp_partition with params.ip = 1 (recursive bipartitioning of the
+coarsest level)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2303_17679_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hgp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2303_17679_amd as H
+    H.lib()
+    return H
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make(name):
+    rs = np.random.RandomState(31)
+    if name == "random2k":
+        return W.random_uniform(2000, 2000, 2, 8, seed=9, name=name)
+    if name == "hugenets":  # nets longer than a wave: the wide extraction paths
+        n = 4000
+        nets = [rs.choice(n, size=rs.randint(2, 7), replace=False) for _ in range(4000)]
+        nets += [rs.choice(n, size=sz, replace=False) for sz in (40, 90, 300, 1500)]
+        return W.from_nets(n, nets, nwgt=rs.randint(1, 4, size=len(nets)))
+    if name == "singles":  # single-pin nets and isolated vertices
+        nets = [[v] for v in range(0, 300, 7)] + [sorted(rs.choice(300, 3, replace=False).tolist())
+                                                   for _ in range(250)]
+        return W.from_nets(330, nets)
+    if name == "weighted":  # vertex weights 1..20: uneven targets and limits
+        h = W.random_uniform(3000, 2500, 2, 6, seed=4, name=name)
+        nets = [h.pins[h.pin_off[e]:h.pin_off[e + 1]] for e in range(h.m)]
+        return W.from_nets(h.n, nets, vwgt=rs.randint(1, 21, size=h.n))
+    if name == "tiny":  # fewer vertices than blocks: empty subhypergraphs
+        nets = [sorted(rs.choice(40, 3, replace=False).tolist()) for _ in range(30)]
+        return W.from_nets(40, nets)
+    return W.workload(name)[0]
+
+
+RB_CASES = [("random2k", 3, 0, (3, 100), 160), ("stencil16", 6, 1, (3, 100), 160),
+            ("powerlaw20000", 7, 2, (3, 100), 160), ("hugenets", 8, 3, (3, 100), 160),
+            ("singles", 5, 4, (3, 100), 160), ("weighted", 12, 5, (1, 10), 160),
+            ("random2k", 2, 6, (3, 100), 16), ("stencil32", 64, 7, (3, 100), 160),
+            ("rmat16", 16, 8, (3, 100), 40), ("tiny", 64, 9, (3, 100), 160)]
+
+
+@pytest.mark.parametrize("name,k,seed,eps,lf", RB_CASES)
+def test_rb_initial_partition_matches_oracle(hgp, orc, name, k, seed, eps, lf):
+    H = hgp
+    h = make(name)
+    say(f"[rb ip] {name} k={k} seed={seed} eps={eps} limit_factor={lf} n={h.n} m={h.m}")
+    part_o = orc.rb_ip(h, orc.params(k, eps=eps, seed=seed, limit_factor=lf))
+    part = H.rb_initial_partition(H.Hypergraph.from_host(h), H.params(k, eps=eps, seed=seed, limit_factor=lf))
+    assert np.array_equal(part.cpu().numpy().view(np.uint32), part_o[:h.n])
+
+
+PART_CASES = [("random2k", 3, 1), ("stencil16", 8, 2), ("powerlaw20000", 6, 3), ("hugenets", 5, 4),
+              ("stencil32", 64, 5), ("weighted", 7, 6)]
+
+
+@pytest.mark.parametrize("name,k,seed", PART_CASES)
+def test_rb_partition_matches_oracle(hgp, orc, name, k, seed):
+    H = hgp
+    h = make(name)
+    P_or = orc.params(k, seed=seed, ip=1)
+    lv = orc.hierarchy(h, P_or)
+    part_o, f_o, L_o = orc.partition(h, P_or)
+    say(f"[rb partition] {name} k={k} levels={L_o}")
+    G = H.Hypergraph.from_host(h)
+    P = H.Partitioner(G, H.params(k, seed=seed, ip=1))
+    tr = P.run_traced()
+    assert [(t["n"], t["m"], t["p"]) for t in tr] == [(L["h"].n, L["h"].m, len(L["h"].pins)) for L in lv]
+    assert int(P.f.item()) == f_o and len(tr) - 1 == L_o
+    assert np.array_equal(P.part.cpu().numpy().view(np.uint32), part_o)
+
+
+def test_rb_partition_balanced_and_repeatable(hgp):
+    # beyond the oracle's sizes: every block within L_max of the k-way
+    # partition (Sec. 2) on a unit-weight stencil, and the same blocks from a
+    # second run (the method is deterministic)
+    H = hgp
+    h = W.stencil3d(48)
+    k = 32
+    G = H.Hypergraph.from_host(h)
+    parts = []
+    for _ in range(2):
+        P = H.Partitioner(G, H.params(k, seed=3, ip=1))
+        P.run()
+        parts.append(P.part.cpu().numpy().copy())
+    part = parts[0]
+    wts = np.bincount(part, weights=np.asarray(h.vwgt, np.int64), minlength=k)
+    Wtot = int(np.sum(h.vwgt))
+    lmax = (100 + 3) * ((Wtot + k - 1) // k) // 100
+    assert part.min() >= 0 and part.max() < k
+    assert wts.max() <= lmax
+    assert np.array_equal(parts[0], parts[1])
