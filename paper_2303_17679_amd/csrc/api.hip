@@ -1,8 +1,11 @@
 // extern "C" entry points: argument checks, workspace arena, the multilevel
 // driver (paper Alg. 1 with the deterministic components, no FM / flows).
 #include "kernels.h"
+#include "timing.h"
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 using namespace hgp;
@@ -68,19 +71,32 @@ size_t level_bytes(uint32_t n, uint32_t m, uint32_t p) {
     return 4ull * ((size_t)m + 1 + p + (size_t)n + 1 + p + n + m + n + n) + 8 * 256;
 }
 
-// Recursive bipartitioning: a bisection's whole multilevel workspace, and
-// along the recursion path every subhypergraph with its parent's capacities,
-// its maps and its bisection.
-size_t rb_bytes(uint32_t n, uint32_t m, uint32_t p, const hgp_params &dp) {
+// Workspace of one lane: a bisection of an (n, m, p) hypergraph (its whole
+// multilevel workspace, then the extraction of its sides in the same room).
+size_t rb_lane_bytes(uint32_t n, uint32_t m, uint32_t p, const hgp_params &dp) {
     hgp_params p2 = dp;
     p2.k = 2;
     p2.ip = 0;
     p2.community = 0;
     size_t bis = 0;
     HGP_REQUIRE(hgp_workspace_bytes(HGP_OP_PARTITION, n, m, p, &p2, &bis) == HGP_OK, HGP_E_INVALID);
-    uint32_t depth = 1;
-    while ((1u << depth) < dp.k) ++depth;
-    return bis + (size_t)(depth + 1) * (level_bytes(n, m, p) + 12ull * n + 4096);
+    return bis + 4096;
+}
+
+// One depth's sides with their parents' sizes: per node with (n_i, m_i, p_i)
+// the result (n_i words) and per side pin_off, pins, inc_off, inc, vwgt, nwgt
+// and two maps, 36 n_i + 16 m_i + 16 p_i + 16 bytes and 17 allocations.  Over
+// a depth the n_i sum to at most n and the p_i to at most p; a side's nets
+// each have a pin, so the m_i sum to at most max(m, p); at most k nodes.
+size_t rb_region_bytes(uint32_t n, uint32_t m, uint32_t p, uint32_t k) {
+    return 4ull * (9ull * n + 4ull * std::max(m, p) + 4ull * p + 4ull * k) + 17ull * 256 * k + 4096;
+}
+
+// Recursive bipartitioning: the start map, two regions for the sides of
+// consecutive depths and one lane (more lanes run at once when the
+// workspace holds them).
+size_t rb_bytes(uint32_t n, uint32_t m, uint32_t p, const hgp_params &dp) {
+    return 4ull * n + 2 * rb_region_bytes(n, m, p, dp.k) + rb_lane_bytes(n, m, p, dp) + 8192;
 }
 
 }  // namespace
@@ -384,74 +400,170 @@ void rb_limits(int64_t Wtot, uint32_t ktot, const hgp_params &prm, int64_t Wsub,
     }
 }
 
-struct RbRun {
-    const hgp_params *prm;
-    int64_t Wtot;
-    uint32_t *part;
-    Arena *A;
-    hipStream_t st;
+// The recursion runs depth by depth.  All bisections of one depth are
+// independent (each writes only its own vertices' blocks and its own
+// subhypergraphs), so up to RB_LANES of them run at once, each on a worker
+// thread with its own stream and its own slice of the workspace; the results
+// do not depend on how many run at once or in which order.
+constexpr uint32_t RB_LANES = 8;
+
+struct RbNode {  // a subhypergraph that gets kk blocks from b0 on
+    hgp_hg H;
+    uint32_t kk, b0;
+    const uint32_t *vmap;  // its vertex i is vertex vmap[i] of the level being partitioned
+};
+struct RbSides {  // a bisected node: its result and both sides
+    uint32_t *bp = nullptr;
+    hgp_hg_out out[2];
+    uint32_t *smap[2], *cmap[2];
+    uint32_t dims[2][3];
 };
 
-// Subhypergraph H (its vertex i stands for vertex vmap[i] of the level being
-// partitioned) into kk blocks from b0 on: bisect, extract both sides, recurse.
-hgp_status rb_rec(const RbRun &R, const hgp_hg &H, uint32_t kk, uint32_t b0, const uint32_t *vmap) {
-    Arena &A = *R.A;
-    if (H.n == 0) return HGP_OK;
-    if (kk == 1) {
-        assign_block(vmap, H.n, b0, R.part, R.st);
+// Bisects node nd (kk > 1, n > 0) and extracts both sides into o, or assigns
+// its vertices to block b0 (kk == 1).  Work on ts, scratch from At; synced.
+hgp_status rb_task(const hgp_params &prm, int64_t Wtot, uint32_t *part, const RbNode &nd, RbSides &o, Arena &At,
+                   hipStream_t ts) {
+    if (nd.kk == 1) {
+        assign_block(nd.vmap, nd.H.n, nd.b0, part, ts);
+        stream_sync(ts);
         return HGP_OK;
     }
-    const int64_t Wsub = total_weight(H.vwgt, H.n, A, R.st);
+    const size_t mk = At.mark();
+    const int64_t Wsub = total_weight(nd.H.vwgt, nd.H.n, At, ts);
     int64_t L[2], T[2];
-    rb_limits(R.Wtot, R.prm->k, *R.prm, Wsub, kk, L, T);
-    const size_t mk = A.mark();
-    uint32_t *bp = A.alloc<uint32_t>(H.n);
-    int64_t *obj = A.alloc<int64_t>(1);
-    hgp_params p2 = *R.prm;
+    rb_limits(Wtot, prm.k, prm, Wsub, nd.kk, L, T);
+    int64_t *obj = At.alloc<int64_t>(1);
+    hgp_params p2 = prm;
     p2.k = 2;
     p2.ip = 0;
     p2.community = 0;
     p2.flags |= HGP_TRUSTED_INPUT;  // built here, valid by construction
-    const size_t mkb = A.mark();  // the bisection's hierarchy is free again once bp holds its result
-    hgp_status s = partition_one(&H, &p2, bp, obj, nullptr, A, R.st, nullptr, L, T[0]);
-    A.release(mkb);
-    const uint32_t ks[2] = {(kk + 1) / 2, kk / 2};
-    for (uint32_t side = 0; side < 2 && s == HGP_OK; ++side) {
-        const size_t mk2 = A.mark();
-        hgp_hg_out out;
-        out.cap_n = H.n; out.cap_m = H.m; out.cap_p = H.p;
-        out.pin_off = A.alloc<uint32_t>((size_t)H.m + 1);
-        out.pins = A.alloc<uint32_t>(H.p);
-        out.inc_off = A.alloc<uint32_t>((size_t)H.n + 1);
-        out.inc = A.alloc<uint32_t>(H.p);
-        out.vwgt = A.alloc<int32_t>(H.n);
-        out.nwgt = A.alloc<int32_t>(H.m);
-        out.dims = nullptr;
-        uint32_t *smap = A.alloc<uint32_t>(H.n);
-        uint32_t *cmap = A.alloc<uint32_t>(H.n);
-        uint32_t dims[3];
-        subhypergraph(H, bp, side, out, smap, dims, A, R.st);
-        gather_map(vmap, smap, dims[0], cmap, R.st);
-        hgp_hg S{dims[0], dims[1], dims[2], out.pin_off, out.pins, out.inc_off, out.inc, out.vwgt, out.nwgt};
-        s = rb_rec(R, S, ks[side], side == 0 ? b0 : b0 + ks[0], cmap);
-        A.release(mk2);
+    const hgp_status s = partition_one(&nd.H, &p2, o.bp, obj, nullptr, At, ts, nullptr, L, T[0]);
+    At.release(mk);
+    if (s != HGP_OK) return s;
+    for (uint32_t side = 0; side < 2; ++side) {
+        subhypergraph(nd.H, o.bp, side, o.out[side], o.smap[side], o.dims[side], At, ts);
+        gather_map(nd.vmap, o.smap[side], o.dims[side][0], o.cmap[side], ts);
     }
-    A.release(mk);
-    return s;
+    stream_sync(ts);
+    At.release(mk);
+    return HGP_OK;
 }
+
+struct LaneStreams {  // created and destroyed with the recursion
+    std::vector<hipStream_t> s;
+    ~LaneStreams() {
+        for (hipStream_t x : s) (void)hipStreamDestroy(x);
+    }
+};
 
 // Recursive bipartitioning (Sec. 5, Eq. 1): the k-way initial partition of h
 // by bisections, each a multilevel cycle with k = 2 and the side limits of
-// Eq. 1.
+// Eq. 1; side 0 of a node with kk blocks takes the first ceil(kk/2) of them.
 hgp_status rb_initial_partition(const hgp_hg &h, const hgp_params &prm, uint32_t *part, Arena &A, hipStream_t st) {
     const size_t mk = A.mark();
     uint32_t *vmap = A.alloc<uint32_t>(h.n);
     iota_u32(vmap, h.n, st);
-    const RbRun R{&prm, total_weight(h.vwgt, h.n, A, st), part, &A, st};
-    const hgp_status s = rb_rec(R, h, prm.k, 0, vmap);
-    stream_sync(st);
+    const int64_t Wtot = total_weight(h.vwgt, h.n, A, st);
+    stream_sync(st);  // the level and vmap are complete before the lanes read them
+    const size_t rbytes = rb_region_bytes(h.n, h.m, h.p, prm.k);
+    Arena R[2] = {Arena(A.alloc<char>(rbytes), rbytes), Arena(A.alloc<char>(rbytes), rbytes)};
+    // lanes: as many bisection workspaces of the largest node (the root) as
+    // the workspace holds, at least one
+    const size_t lb = rb_lane_bytes(h.n, h.m, h.p, prm);
+    // (one lane while kernels are timed: the timing state is not shared)
+    const size_t most = timing().mask ? 1 : RB_LANES;
+    const uint32_t nl = (uint32_t)std::max<size_t>(1, std::min<size_t>(most, A.remaining() / lb));
+    std::vector<Arena> lane;
+    for (uint32_t i = 0; i < nl; ++i) lane.emplace_back(A.alloc<char>(lb), lb);
+    int dev = 0;
+    HGP_CHECK_HIP(hipGetDevice(&dev));
+    LaneStreams ls;
+    for (uint32_t i = 0; i < nl; ++i) {
+        hipStream_t x;
+        HGP_CHECK_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        ls.s.push_back(x);
+    }
+    const bool bw = blocking_waits;
+    std::vector<RbNode> cur{RbNode{h, prm.k, 0, vmap}};
+    hgp_status result = HGP_OK;
+    for (uint32_t depth = 0; !cur.empty() && result == HGP_OK; ++depth) {
+        // the sides of this depth go to the region that held the previous
+        // depth's nodes (no longer read)
+        Arena &dst = R[(depth + 1) & 1];
+        dst.release(0);
+        std::vector<RbSides> sides(cur.size());
+        for (size_t i = 0; i < cur.size(); ++i) {
+            const hgp_hg &H = cur[i].H;
+            if (cur[i].kk < 2) continue;
+            RbSides &o = sides[i];
+            o.bp = dst.alloc<uint32_t>(H.n);
+            for (int sd = 0; sd < 2; ++sd) {
+                hgp_hg_out &out = o.out[sd];
+                out.cap_n = H.n; out.cap_m = H.m; out.cap_p = H.p;
+                out.pin_off = dst.alloc<uint32_t>((size_t)H.m + 1);
+                out.pins = dst.alloc<uint32_t>(H.p);
+                out.inc_off = dst.alloc<uint32_t>((size_t)H.n + 1);
+                out.inc = dst.alloc<uint32_t>(H.p);
+                out.vwgt = dst.alloc<int32_t>(H.n);
+                out.nwgt = dst.alloc<int32_t>(H.m);
+                out.dims = nullptr;
+                o.smap[sd] = dst.alloc<uint32_t>(H.n);
+                o.cmap[sd] = dst.alloc<uint32_t>(H.n);
+            }
+        }
+        std::vector<hgp_status> st_of(cur.size(), HGP_OK);
+        std::atomic<size_t> next{0};
+        std::atomic<bool> stop{false};
+        auto work = [&](uint32_t li) {
+            for (;;) {
+                const size_t i = next.fetch_add(1);
+                if (i >= cur.size() || stop.load()) return;
+                try {
+                    st_of[i] = rb_task(prm, Wtot, part, cur[i], sides[i], lane[li], ls.s[li]);
+                } catch (const Error &e) {
+                    st_of[i] = e.code;
+                } catch (...) {
+                    st_of[i] = HGP_E_DEVICE;
+                }
+                if (st_of[i] != HGP_OK) {
+                    (void)hipStreamSynchronize(ls.s[li]);  // nothing of the failed task still runs
+                    stop.store(true);
+                }
+            }
+        };
+        const uint32_t nt = (uint32_t)std::min<size_t>(nl, cur.size());
+        if (nt == 1) {
+            work(0);
+        } else {
+            std::vector<std::thread> th;
+            for (uint32_t li = 0; li < nt; ++li)
+                th.emplace_back([&, li]() {
+                    (void)hipSetDevice(dev);
+                    blocking_waits = bw;
+                    work(li);
+                });
+            for (std::thread &t : th) t.join();
+        }
+        std::vector<RbNode> nxt;
+        for (size_t i = 0; i < cur.size() && result == HGP_OK; ++i) {
+            if (st_of[i] != HGP_OK) { result = st_of[i]; break; }
+            const RbNode &nd = cur[i];
+            if (nd.kk < 2) continue;
+            const uint32_t ks[2] = {(nd.kk + 1) / 2, nd.kk / 2};
+            for (int sd = 0; sd < 2; ++sd) {
+                const RbSides &o = sides[i];
+                if (o.dims[sd][0] == 0) continue;  // an empty side gets no vertices
+                const hgp_hg_out &out = o.out[sd];
+                nxt.push_back(RbNode{hgp_hg{o.dims[sd][0], o.dims[sd][1], o.dims[sd][2], out.pin_off, out.pins,
+                                            out.inc_off, out.inc, out.vwgt, out.nwgt},
+                                     ks[sd], sd == 0 ? nd.b0 : nd.b0 + ks[0], o.cmap[sd]});
+            }
+        }
+        cur.swap(nxt);
+    }
     A.release(mk);
-    return s;
+    return result;
 }
 }  // namespace
 

@@ -106,3 +106,22 @@ def test_rb_partition_balanced_and_repeatable(hgp):
     assert part.min() >= 0 and part.max() < k
     assert wts.max() <= lmax
     assert np.array_equal(parts[0], parts[1])
+
+
+@pytest.mark.parametrize("name,k", [("stencil32", 64), ("powerlaw20000", 13)])
+def test_rb_same_result_on_one_lane_and_many(hgp, orc, name, k):
+    # The bisections of one recursion depth run on up to eight lanes at once
+    # when the workspace holds them; the minimal workspace leaves one lane.
+    # Both give the oracle's blocks.
+    import torch
+    H = hgp
+    h = make(name)
+    G = H.Hypergraph.from_host(h)
+    prm = H.params(k, seed=11)
+    need = H.workspace_bytes(H.OP_RB, G.n, G.m, G.p, prm)
+    part_o = orc.rb_ip(h, orc.params(k, seed=11))[:h.n]
+    for ws_bytes in (need, 12 * need):
+        say(f"[rb lanes] {name} k={k} workspace {ws_bytes} bytes")
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        part = H.rb_initial_partition(G, prm, ws=ws)
+        assert np.array_equal(part.cpu().numpy().view(np.uint32), part_o)
