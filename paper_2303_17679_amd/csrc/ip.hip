@@ -284,8 +284,10 @@ __global__ void k_project(uint32_t n, const uint32_t *cid, const uint32_t *cpart
 // expansion (frontier vertex, incident net, pin) is flattened to one index x
 // in lexicographic order, which is the key order of the device-wide path, so
 // a vertex joins the next layer at its smallest x and the winners are laid
-// out in x order.  Used when the whole expansion (sum over nets of |e|^2)
-// is small; it costs about one workgroup step per IPS_THREADS pins.
+// out in x order.  Only the first pair that reaches a net expands it (its
+// pins all join in that layer), so a BFS expands every net once: about one
+// workgroup step per IPS_THREADS pins and incidences.  Used when the sum over
+// nets of |e|^2 is small.
 // ---------------------------------------------------------------------------
 constexpr int IPS_THREADS = 1024;
 constexpr uint32_t IPS_MAX_N = 1u << 16;
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(IPS_THREADS) void k_ip_small(const uint32_t *pin_of
                                                           const int32_t *vwgt, uint32_t n, uint32_t k, uint64_t T,
                                                           unsigned long long *key, uint32_t *D, uint32_t *pe,
                                                           uint64_t *E, uint32_t *order, uint64_t *P, uint32_t *S,
-                                                          uint32_t *part) {
+                                                          uint32_t *part, uint32_t *netT, uint32_t m) {
     __shared__ uint32_t red[IPS_THREADS / WAVE];
     __shared__ uint64_t red64[IPS_THREADS / WAVE];
     __shared__ uint32_t vis[IPS_MAX_N / 32];  // visited bitmap
@@ -355,8 +357,10 @@ __global__ __launch_bounds__(IPS_THREADS) void k_ip_small(const uint32_t *pin_of
     auto visit = [&](uint32_t v) { atomicOr(&vis[v >> 5], 1u << (v & 31)); };
     for (uint32_t i = tid; i < (n + 31) / 32; i += IPS_THREADS) vis[i] = 0;
     for (uint32_t v = tid; v < n; v += IPS_THREADS) key[v] = ~0ull;
+    for (uint32_t e = tid; e < m; e += IPS_THREADS) netT[e] = ~0u;  // first pair of every net: none yet
     __syncthreads();
     uint32_t pos = 0, next = 0;
+    uint32_t base = 0;  // pairs of the earlier layers
     while (pos < n) {
         // smallest unvisited vertex with incident nets at or after `next`;
         // the unvisited vertices before it have no nets and join in ID order
@@ -401,30 +405,57 @@ __global__ __launch_bounds__(IPS_THREADS) void k_ip_small(const uint32_t *pin_of
                 Tn += tot;
             }
             __syncthreads();
-            // E: exclusive prefix of the pair net sizes (pins of the expansion)
-            uint64_t X = 0;
+            // A net's pins join at the first pair (frontier vertex, incident
+            // net) that reaches it, and they are all visited in that layer:
+            // so each net is expanded once, at its first pair (pair numbers
+            // grow over the layers: base + t), and a vertex's smallest
+            // expansion index over the expanded nets is its smallest over
+            // every pair of the layer.
             uint32_t cur = 0;  // frontier index owning pair c0
             for (uint32_t c0 = 0; c0 < Tn; c0 += IPS_THREADS) {
                 ips_stage<uint32_t>(D, F, cur, win32);
                 const uint32_t t = c0 + tid;
-                uint64_t sz = 0;
                 if (t < Tn) {
                     const uint32_t fi = ips_owner<uint32_t>(win32, cur, t);
                     const uint32_t e = inc[inc_off[order[fs + fi]] + (t - D[fi])];
                     pe[t] = e;
-                    sz = pin_off[e + 1] - pin_off[e];
+                    if (netT[e] >= base) atomicMin(&netT[e], base + t);
                 }
                 cur = ips_owner<uint32_t>(win32, cur, c0 + IPS_THREADS);
-                uint64_t tot;
-                const uint64_t incl = block_incl_scan_n<uint64_t, IPS_THREADS>(sz, red64, &tot);
-                if (t < Tn) E[t] = X + incl - sz;
-                X += tot;
+                __syncthreads();  // the window is restaged
             }
             __syncthreads();
+            // the layer's expanded nets in pair order (compacted in place: a
+            // chunk's reads precede its scans' barriers, its writes land
+            // below the next chunk) with E = exclusive prefix of their sizes
+            uint64_t X = 0;
+            uint32_t Tx = 0;
+            for (uint32_t c0 = 0; c0 < Tn; c0 += IPS_THREADS) {
+                const uint32_t t = c0 + tid;
+                uint32_t e = 0, first = 0;
+                uint64_t sz = 0;
+                if (t < Tn) {
+                    e = pe[t];
+                    first = netT[e] == base + t ? 1u : 0u;
+                    sz = first ? pin_off[e + 1] - pin_off[e] : 0u;
+                }
+                uint32_t totf;
+                const uint32_t incf = block_incl_scan_n<uint32_t, IPS_THREADS>(first, red, &totf);
+                uint64_t tots;
+                const uint64_t incs = block_incl_scan_n<uint64_t, IPS_THREADS>(sz, red64, &tots);
+                if (first) {
+                    pe[Tx + incf - 1] = e;
+                    E[Tx + incf - 1] = X + incs - sz;
+                }
+                Tx += totf;
+                X += tots;
+            }
+            __syncthreads();
+            base += Tn;
             // keys: smallest expansion index per unvisited vertex
             cur = 0;
             for (uint64_t c0 = 0; c0 < X; c0 += IPS_THREADS) {
-                ips_stage<uint64_t>(E, Tn, cur, win);
+                ips_stage<uint64_t>(E, Tx, cur, win);
                 const uint64_t x = c0 + tid;
                 if (x < X) {
                     const uint32_t t = ips_owner<uint64_t>(win, cur, x);
@@ -439,7 +470,7 @@ __global__ __launch_bounds__(IPS_THREADS) void k_ip_small(const uint32_t *pin_of
             uint32_t Wn = 0;
             cur = 0;
             for (uint64_t c0 = 0; c0 < X; c0 += IPS_THREADS) {
-                ips_stage<uint64_t>(E, Tn, cur, win);
+                ips_stage<uint64_t>(E, Tx, cur, win);
                 const uint64_t x = c0 + tid;
                 uint32_t w = 0, wn = 0;
                 if (x < X) {
@@ -556,7 +587,8 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
     plan(A, n, h.p, k, B);
     const int64_t W = W_known >= 0 ? W_known : total_weight(h.vwgt, n, A, st);
     const uint64_t T = fill_target >= 0 ? (uint64_t)fill_target : (uint64_t)((W + k - 1) / k);
-    bool small = n > 0 && n <= IPS_MAX_N && h.p <= IPS_MAX_P;
+    // (netT, a word per net, lives in exoff, which holds p words)
+    bool small = n > 0 && n <= IPS_MAX_N && h.p <= IPS_MAX_P && h.m <= h.p;
     if (small) {
         unsigned long long *sq = (unsigned long long *)B.P;  // scratch until the fill
         HGP_CHECK_HIP(hipMemsetAsync(sq, 0, sizeof(unsigned long long), st));
@@ -571,7 +603,7 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
     }
     if (small) {
         k_ip_small<<<1, IPS_THREADS, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, h.vwgt, n, k, T, B.key, B.D,
-                                              B.cnt, B.E, B.order, B.P, B.S, part);
+                                              B.cnt, B.E, B.order, B.P, B.S, part, B.exoff, h.m);
         HGP_LAUNCH_CHECK();
         stream_sync(st);
         A.release(mk);

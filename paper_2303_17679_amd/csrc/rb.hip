@@ -124,30 +124,15 @@ __global__ __launch_bounds__(BLOCK) void k_sub_pins(const uint32_t *pin_off, con
     }
 }
 
-// Incidence lists: vertex i's nets renumbered (a thread per vertex, a wave
-// per longer list).
+// Incidence lists: vertex i's nets renumbered, a wave per vertex (the lanes
+// stride over its list; coarse vertices have hundreds of nets).
 __global__ __launch_bounds__(BLOCK) void k_sub_inc(const uint32_t *inc_off, const uint32_t *inc, uint32_t n2,
                                                    const uint32_t *vmap, const uint32_t *nrank,
                                                    const uint32_t *inc_off_s, uint32_t *inc_s) {
-    for (uint32_t i0 = blockIdx.x * BLOCK; i0 < n2; i0 += gridDim.x * BLOCK) {
-        const uint32_t i = i0 + threadIdx.x;
-        uint32_t j0 = 0, j1 = 0, o = 0;
-        if (i < n2) {
-            const uint32_t v = vmap[i];
-            j0 = inc_off[v];
-            j1 = inc_off[v + 1];
-            o = inc_off_s[i];
-        }
-        const bool wide = j1 - j0 > SUB_WIDE;
-        if (i < n2 && !wide)
-            for (uint32_t j = j0; j < j1; ++j) inc_s[o + (j - j0)] = nrank[inc[j]];
-        uint64_t wm = __ballot(wide);
-        while (wm) {
-            const int h = __ffsll((long long)wm) - 1;
-            wm &= wm - 1;
-            const uint32_t hj0 = __shfl(j0, h, WAVE), hj1 = __shfl(j1, h, WAVE), ho = __shfl(o, h, WAVE);
-            for (uint32_t j = hj0 + __lane_id(); j < hj1; j += WAVE) inc_s[ho + (j - hj0)] = nrank[inc[j]];
-        }
+    const uint32_t wpb = BLOCK / WAVE;
+    for (uint32_t i = blockIdx.x * wpb + threadIdx.x / WAVE; i < n2; i += gridDim.x * wpb) {
+        const uint32_t v = vmap[i], j0 = inc_off[v], j1 = inc_off[v + 1], o = inc_off_s[i];
+        for (uint32_t j = j0 + __lane_id(); j < j1; j += WAVE) inc_s[o + (j - j0)] = nrank[inc[j]];
     }
 }
 
@@ -207,8 +192,8 @@ void subhypergraph(const hgp_hg &h, const uint32_t *part, uint32_t side, const h
     k_set_word<<<1, 64, 0, st>>>(out.inc_off + n2, d_n2 + 1);
     HGP_LAUNCH_CHECK();
     if (n2) {
-        k_sub_inc<<<grid_for(n2, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n2, vmap, nrank, out.inc_off,
-                                                                      out.inc);
+        k_sub_inc<<<grid_for((size_t)n2 * WAVE, BLOCK, 4 * FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, h.inc, n2, vmap,
+                                                                                       nrank, out.inc_off, out.inc);
         HGP_LAUNCH_CHECK();
     }
     dims_host[0] = n2;
