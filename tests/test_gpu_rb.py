@@ -125,3 +125,20 @@ def test_rb_same_result_on_one_lane_and_many(hgp, orc, name, k):
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         part = H.rb_initial_partition(G, prm, ws=ws)
         assert np.array_equal(part.cpu().numpy().view(np.uint32), part_o)
+
+
+@pytest.mark.parametrize("name,k,seed,eps,community", [("random2k", 4, 3, (3, 100), True),
+                                                       ("stencil16", 256, 4, (3, 100), False),
+                                                       ("weighted", 5, 5, (0, 1), False)])
+def test_rb_partition_more_settings(hgp, orc, name, k, seed, eps, community):
+    # recursive bipartitioning under community-aware coarsening (the
+    # bisections themselves detect no communities), with 256 blocks (eight
+    # recursion depths, four Lambda words) and with eps = 0
+    H = hgp
+    h = make(name)
+    P_or = orc.params(k, eps=eps, seed=seed, ip=1, community=community)
+    part_o, f_o, L_o = orc.partition(h, P_or)
+    say(f"[rb settings] {name} k={k} eps={eps} community={community} levels={L_o}")
+    part, f, L = H.partition(H.Hypergraph.from_host(h), H.params(k, eps=eps, seed=seed, ip=1, community=community))
+    assert (f, L) == (f_o, L_o)
+    assert np.array_equal(part.cpu().numpy().view(np.uint32), part_o)
