@@ -160,3 +160,31 @@ def test_server_failed_requests_leave_the_others_intact(hgp):
             assert np.array_equal(host(part), host(p_ref))
     finally:
         S.close()
+
+
+def test_batch_many_small_instances(hgp, orc):
+    # Many small instances on 16 lanes, with one to four Lambda words and
+    # several sub-round and round counts. Every result equals the oracle's
+    # and the one-at-a-time result.
+    H = hgp
+    rs = np.random.RandomState(77)
+    inst = []
+    for i in range(40):
+        n = int(rs.randint(200, 4500))
+        k = int(rs.choice([2, 3, 8, 64, 100, 200]))
+        h = W.random_uniform(n, n + int(rs.randint(0, n // 2)), 2, 8, seed=100 + i, name=f"r{i}")
+        kw = {"lp_subrounds": int(rs.choice([1, 5, 7])), "lp_rounds": int(rs.choice([1, 5, 9]))}
+        if k >= 64:
+            kw["eps"] = (1, 2)  # room to move with few vertices per block
+        inst.append((h, k, i, kw))
+    hs = [H.Hypergraph.from_host(h) for h, _, _, _ in inst]
+    prms = [H.params(k, seed=i, **kw) for (_, k, i, kw) in inst]
+    say(f"[batch small] {len(inst)} instances on 16 lanes")
+    parts, objs, levels = H.partition_batch(hs, prms, lanes=16)
+    for j, (h, k, i, kw) in enumerate(inst):
+        part_o, f_o, L_o = orc.partition(h, orc.params(k, seed=i, **kw))
+        assert (int(objs[j].item()), levels[j]) == (f_o, L_o), j
+        assert np.array_equal(host(parts[j]), part_o), j
+    for j in (0, 7, 19):
+        part, f, L = H.partition(hs[j], prms[j])
+        assert (f, L) == (int(objs[j].item()), levels[j]) and np.array_equal(host(part), host(parts[j]))
