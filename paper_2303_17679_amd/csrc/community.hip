@@ -29,6 +29,7 @@ constexpr uint32_t LV_SUBROUNDS = 5;  // sub-rounds per round
 constexpr uint32_t LV_LEVELS = 16;    // Louvain levels at most
 constexpr uint32_t LV_WIDE = 32;      // lists longer than this: a wave each
 constexpr uint32_t LV_SEG = 64;       // sorted runs longer than this: a wave each
+constexpr uint32_t LV_DIRECT = 16;    // nodes of at most this many edges decide without the sort
 
 // --- the bipartite graph ----------------------------------------------------
 
@@ -162,15 +163,18 @@ __global__ void k_lv_init(const int32_t *vw, uint32_t N, uint32_t *comm, int64_t
     }
 }
 
-// Nodes of sub-round (r, s), numbered in ID order, with their edge offsets:
-// the scan value is (1 << 32 | degree) for a node of the sub-round.
+// Nodes of sub-round (r, s), numbered in ID order, with the offsets of the
+// edges that go through the sort: the scan value is (1 << 32 | degree) for a
+// node of the sub-round with more than LV_DIRECT edges, (1 << 32) for the
+// others (they decide from their own edges, k_lv_direct).
 struct SelPack {
     const uint32_t *inc_off;
     uint64_t mseed;
     uint32_t level, r, s;
     __device__ uint64_t operator()(size_t x) const {
         if (tag_hash(mseed, 4, level, r, (uint32_t)x) % LV_SUBROUNDS != s) return 0ull;
-        return (1ull << 32) | (uint64_t)(inc_off[x + 1] - inc_off[x]);
+        const uint32_t d = inc_off[x + 1] - inc_off[x];
+        return (1ull << 32) | (uint64_t)(d > LV_DIRECT ? d : 0u);
     }
 };
 struct SelStore {
@@ -183,8 +187,20 @@ struct SelStore {
     }
 };
 
+// Decision of every node of the sub-round with at most LV_DIRECT edges, from
+// its own edges: the (community, weight) pair of each edge goes into the
+// thread's column of an LDS table in community order (insertion), and the
+// runs are walked as k_lv_decide walks a sorted run.  Same scores, same
+// ties, no keys written and no sort.
+__global__ __launch_bounds__(BLOCK) void k_lv_direct(const uint32_t *list, uint32_t count, const uint32_t *inc_off,
+                                                     const uint32_t *inc, const uint32_t *pin_off,
+                                                     const uint32_t *pins, const int32_t *nwgt,
+                                                     const uint32_t *comm, const int64_t *cvol, const int32_t *vw,
+                                                     int64_t m2, uint32_t *dec);
+
 // Keys (rank of the node in the sub-round, community of the neighbour) and
-// the edge weights, at the node's offset.
+// the edge weights, at the node's offset (nodes of more than LV_DIRECT edges
+// only).
 __global__ __launch_bounds__(BLOCK) void k_lv_emit(const uint32_t *list, const uint32_t *ioff, uint32_t count,
                                                    const uint32_t *inc_off, const uint32_t *inc,
                                                    const uint32_t *pin_off, const uint32_t *pins,
@@ -199,6 +215,7 @@ __global__ __launch_bounds__(BLOCK) void k_lv_emit(const uint32_t *list, const u
             j1 = inc_off[x + 1];
             o = ioff[i];
         }
+        if (j1 - j0 <= LV_DIRECT) j1 = j0;  // decided by k_lv_direct: nothing to emit
         const bool wide = j1 - j0 > LV_WIDE;
         auto edge = [&](uint32_t xi, uint32_t xx, uint32_t j, uint32_t at) {
             const uint32_t e = inc[j], b = pin_off[e];
@@ -229,10 +246,11 @@ __device__ inline void best_merge(Best &b, int64_t s, uint32_t c) {
     if (b.c == NONE || s > b.score || (s == b.score && c < b.c)) { b.score = s; b.c = c; }
 }
 
-// Decision of every node of the sub-round (dec[i] = the community it moves
-// to, or NONE).  A lane walks a run of up to LV_SEG entries; a wave takes a
-// longer run 64 entries at a time (segmented sum of equal communities, the
-// open group's sum carried into the next step).
+// Decision of every node of the sub-round with more than LV_DIRECT edges
+// (dec[i] = the community it moves to, or NONE; the others have an empty
+// run and are left to k_lv_direct).  A lane walks a run of up to LV_SEG
+// entries; a wave takes a longer run 64 entries at a time (segmented sum of
+// equal communities, the open group's sum carried into the next step).
 __global__ __launch_bounds__(BLOCK) void k_lv_decide(const uint32_t *list, const uint32_t *ioff, uint32_t count,
                                                      const uint64_t *keys, const uint32_t *vals,
                                                      const uint32_t *comm, const int64_t *cvol, const int32_t *vw,
@@ -250,7 +268,7 @@ __global__ __launch_bounds__(BLOCK) void k_lv_decide(const uint32_t *list, const
             vx = vw[x];
         }
         const bool wide = e - b > LV_SEG;
-        if (i < count && !wide) {
+        if (i < count && !wide && e > b) {
             Best best{0, NONE};
             int64_t wA = 0, acc = 0;
             uint32_t cur = NONE;
@@ -324,6 +342,73 @@ __global__ __launch_bounds__(BLOCK) void k_lv_decide(const uint32_t *list, const
                 dec[hi] = (best.c != NONE && best.score > sA) ? best.c : NONE;
             }
         }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_lv_direct(const uint32_t *list, uint32_t count, const uint32_t *inc_off,
+                                                     const uint32_t *inc, const uint32_t *pin_off,
+                                                     const uint32_t *pins, const int32_t *nwgt,
+                                                     const uint32_t *comm, const int64_t *cvol, const int32_t *vw,
+                                                     int64_t m2, uint32_t *dec) {
+    __shared__ uint32_t sc[LV_DIRECT][BLOCK];  // column per thread: no bank conflicts
+    __shared__ int32_t sw[LV_DIRECT][BLOCK];
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = blockIdx.x * BLOCK + t; i < count; i += gridDim.x * BLOCK) {
+        const uint32_t x = list[i], j0 = inc_off[x], deg = inc_off[x + 1] - j0;
+        if (deg > LV_DIRECT) continue;  // through the sort (k_lv_decide)
+        // eight edges at a time: every load of a stage is issued before any
+        // is used (edge, its offsets, its endpoints, the neighbour's
+        // community), then each pair is inserted in community order
+        for (uint32_t q0 = 0; q0 < deg; q0 += 8) {
+            uint32_t e[8], b[8], c[8];
+            int32_t w[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) e[k] = q0 + k < deg ? inc[j0 + q0 + k] : NONE;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                b[k] = e[k] != NONE ? pin_off[e[k]] : 0u;
+                w[k] = e[k] != NONE ? nwgt[e[k]] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (e[k] == NONE) continue;
+                const uint32_t a = pins[b[k]];
+                c[k] = a == x ? pins[b[k] + 1] : a;  // the neighbour
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) c[k] = e[k] != NONE ? comm[c[k]] : NONE;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (e[k] == NONE) continue;
+                uint32_t z = q0 + k;
+                while (z > 0 && sc[z - 1][t] > c[k]) {
+                    sc[z][t] = sc[z - 1][t];
+                    sw[z][t] = sw[z - 1][t];
+                    --z;
+                }
+                sc[z][t] = c[k];
+                sw[z][t] = w[k];
+            }
+        }
+        const uint32_t A = comm[x];
+        const int64_t vx = vw[x];
+        Best best{0, NONE};
+        int64_t wA = 0, acc = 0;
+        uint32_t cur = NONE;
+        for (uint32_t q = 0; q <= deg; ++q) {
+            const uint32_t c = q < deg ? sc[q][t] : NONE;
+            if (c != cur) {
+                if (cur != NONE) {
+                    if (cur == A) wA = acc;
+                    else best_merge(best, m2 * acc - vx * cvol[cur], cur);
+                }
+                cur = c;
+                acc = 0;
+            }
+            if (q < deg) acc += sw[q][t];
+        }
+        const int64_t sA = m2 * wA - vx * (cvol[A] - vx);
+        dec[i] = (best.c != NONE && best.score > sA) ? best.c : NONE;
     }
 }
 
@@ -505,10 +590,16 @@ hgp_status communities(const hgp_hg &h, uint64_t seed, uint32_t *comm_out, uint3
                 const uint32_t count = (uint32_t)(tot >> 32), items = (uint32_t)tot;
                 if (count == 0) continue;
                 HGP_REQUIRE(items <= items_cap, HGP_E_WORKSPACE);
-                HGP_CHECK_HIP(hipMemcpyAsync(B.ioff + count, &items, sizeof(uint32_t), hipMemcpyHostToDevice, st));
-                uint64_t *kk = keys;
-                uint32_t *vv = vals;
+                // nodes of few edges decide at once; the others sort their
+                // (node, community) keys first
+                k_lv_direct<<<grid_for(count, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+                    B.list, count, cur.inc_off, cur.inc, cur.pin_off, cur.pins, cur.nwgt, B.comm, B.cvol, cur.vwgt,
+                    m2, B.dec);
+                HGP_LAUNCH_CHECK();
                 if (items) {
+                    fill<uint32_t>(B.ioff + count, 1, items, st);
+                    uint64_t *kk = keys;
+                    uint32_t *vv = vals;
                     k_lv_emit<<<grid_for(count, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
                         B.list, B.ioff, count, cur.inc_off, cur.inc, cur.pin_off, cur.pins, cur.nwgt, B.comm, cb, kk,
                         vv);
@@ -516,10 +607,10 @@ hgp_status communities(const hgp_hg &h, uint64_t seed, uint32_t *comm_out, uint3
                     radix_sort_pairs<uint64_t>(A, &kk, &vv, kk == keys ? keys_alt : keys,
                                                vv == vals ? vals_alt : vals, items, 0,
                                                bits_for(count - 1) + cb, st);
+                    k_lv_decide<<<grid_for(count, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
+                        B.list, B.ioff, count, kk, vv, B.comm, B.cvol, cur.vwgt, m2, cmask, B.dec);
+                    HGP_LAUNCH_CHECK();
                 }
-                k_lv_decide<<<grid_for(count, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
-                    B.list, B.ioff, count, kk, vv, B.comm, B.cvol, cur.vwgt, m2, cmask, B.dec);
-                HGP_LAUNCH_CHECK();
                 k_lv_apply<<<grid_for(count, BLOCK, REDUCE_BLOCKS), BLOCK, 0, st>>>(B.list, B.dec, count, cur.vwgt,
                                                                                  B.comm, B.cvol, racc);
                 HGP_LAUNCH_CHECK();

@@ -35,7 +35,7 @@ def _csv(d: str, suffix: str):
 
 
 def short(name: str) -> str:
-    s = name.split("(")[0]
+    s = name.replace("(anonymous namespace)::", "").split("(")[0]
     return s.replace("void ", "").strip()
 
 
