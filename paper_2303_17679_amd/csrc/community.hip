@@ -218,8 +218,9 @@ __global__ __launch_bounds__(BLOCK) void k_lv_emit(const uint32_t *list, const u
         if (j1 - j0 <= LV_DIRECT) j1 = j0;  // decided by k_lv_direct: nothing to emit
         const bool wide = j1 - j0 > LV_WIDE;
         auto edge = [&](uint32_t xi, uint32_t xx, uint32_t j, uint32_t at) {
-            const uint32_t e = inc[j], b = pin_off[e];
-            const uint32_t a = pins[b], c = pins[b + 1];
+            const uint32_t e = inc[j];
+            const uint2 ab = *(const uint2 *)(pins + 2 * (size_t)e);  // two pins at 2e (see k_lv_direct)
+            const uint32_t a = ab.x, c = ab.y;
             keys[at] = ((uint64_t)xi << cb) | comm[a == xx ? c : a];
             vals[at] = (uint32_t)nwgt[e];
         };
@@ -366,15 +367,14 @@ __global__ __launch_bounds__(BLOCK) void k_lv_direct(const uint32_t *list, uint3
             for (int k = 0; k < 8; ++k) e[k] = q0 + k < deg ? inc[j0 + q0 + k] : NONE;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                b[k] = e[k] != NONE ? pin_off[e[k]] : 0u;
+                // every edge of the bipartite graph and of its contractions
+                // has two pins, at 2e and 2e + 1: one 8-byte load
+                const uint2 ab = e[k] != NONE ? *(const uint2 *)(pins + 2 * (size_t)e[k]) : make_uint2(0u, 0u);
+                b[k] = ab.x == x ? ab.y : ab.x;  // the neighbour
                 w[k] = e[k] != NONE ? nwgt[e[k]] : 0;
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (e[k] == NONE) continue;
-                const uint32_t a = pins[b[k]];
-                c[k] = a == x ? pins[b[k] + 1] : a;  // the neighbour
-            }
+            for (int k = 0; k < 8; ++k) c[k] = b[k];
 #pragma unroll
             for (int k = 0; k < 8; ++k) c[k] = e[k] != NONE ? comm[c[k]] : NONE;
 #pragma unroll
