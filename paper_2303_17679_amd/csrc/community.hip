@@ -30,6 +30,8 @@ constexpr uint32_t LV_LEVELS = 16;    // Louvain levels at most
 constexpr uint32_t LV_WIDE = 32;      // lists longer than this: a wave each
 constexpr uint32_t LV_SEG = 64;       // sorted runs longer than this: a wave each
 constexpr uint32_t LV_DIRECT = 16;    // nodes of at most this many edges decide without the sort
+constexpr uint32_t LV_WAVE = 512;     // up to this many: a wave and an LDS table per node (k_lv_wave)
+constexpr uint32_t LV_TBL = 1024;     // its slots (power of two, at least 2 LV_WAVE)
 
 // --- the bipartite graph ----------------------------------------------------
 
@@ -165,8 +167,8 @@ __global__ void k_lv_init(const int32_t *vw, uint32_t N, uint32_t *comm, int64_t
 
 // Nodes of sub-round (r, s), numbered in ID order, with the offsets of the
 // edges that go through the sort: the scan value is (1 << 32 | degree) for a
-// node of the sub-round with more than LV_DIRECT edges, (1 << 32) for the
-// others (they decide from their own edges, k_lv_direct).
+// node of the sub-round with more than LV_WAVE edges, (1 << 32) for the
+// others (they decide from their own edges, k_lv_direct and k_lv_wave).
 struct SelPack {
     const uint32_t *inc_off;
     uint64_t mseed;
@@ -174,7 +176,7 @@ struct SelPack {
     __device__ uint64_t operator()(size_t x) const {
         if (tag_hash(mseed, 4, level, r, (uint32_t)x) % LV_SUBROUNDS != s) return 0ull;
         const uint32_t d = inc_off[x + 1] - inc_off[x];
-        return (1ull << 32) | (uint64_t)(d > LV_DIRECT ? d : 0u);
+        return (1ull << 32) | (uint64_t)(d > LV_WAVE ? d : 0u);
     }
 };
 struct SelStore {
@@ -196,10 +198,10 @@ __global__ __launch_bounds__(BLOCK) void k_lv_direct(const uint32_t *list, uint3
                                                      const uint32_t *inc, const uint32_t *pin_off,
                                                      const uint32_t *pins, const int32_t *nwgt,
                                                      const uint32_t *comm, const int64_t *cvol, const int32_t *vw,
-                                                     int64_t m2, uint32_t *dec);
+                                                     int64_t m2, uint32_t *dec, uint32_t *mid, uint32_t *nmid);
 
 // Keys (rank of the node in the sub-round, community of the neighbour) and
-// the edge weights, at the node's offset (nodes of more than LV_DIRECT edges
+// the edge weights, at the node's offset (nodes of more than LV_WAVE edges
 // only).
 __global__ __launch_bounds__(BLOCK) void k_lv_emit(const uint32_t *list, const uint32_t *ioff, uint32_t count,
                                                    const uint32_t *inc_off, const uint32_t *inc,
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(BLOCK) void k_lv_emit(const uint32_t *list, const u
             j1 = inc_off[x + 1];
             o = ioff[i];
         }
-        if (j1 - j0 <= LV_DIRECT) j1 = j0;  // decided by k_lv_direct: nothing to emit
+        if (j1 - j0 <= LV_WAVE) j1 = j0;  // decided by k_lv_direct or k_lv_wave: nothing to emit
         const bool wide = j1 - j0 > LV_WIDE;
         auto edge = [&](uint32_t xi, uint32_t xx, uint32_t j, uint32_t at) {
             const uint32_t e = inc[j];
@@ -247,9 +249,9 @@ __device__ inline void best_merge(Best &b, int64_t s, uint32_t c) {
     if (b.c == NONE || s > b.score || (s == b.score && c < b.c)) { b.score = s; b.c = c; }
 }
 
-// Decision of every node of the sub-round with more than LV_DIRECT edges
+// Decision of every node of the sub-round with more than LV_WAVE edges
 // (dec[i] = the community it moves to, or NONE; the others have an empty
-// run and are left to k_lv_direct).  A lane walks a run of up to LV_SEG
+// run and are left to k_lv_direct and k_lv_wave).  A lane walks a run of up to LV_SEG
 // entries; a wave takes a longer run 64 entries at a time (segmented sum of
 // equal communities, the open group's sum carried into the next step).
 __global__ __launch_bounds__(BLOCK) void k_lv_decide(const uint32_t *list, const uint32_t *ioff, uint32_t count,
@@ -350,13 +352,22 @@ __global__ __launch_bounds__(BLOCK) void k_lv_direct(const uint32_t *list, uint3
                                                      const uint32_t *inc, const uint32_t *pin_off,
                                                      const uint32_t *pins, const int32_t *nwgt,
                                                      const uint32_t *comm, const int64_t *cvol, const int32_t *vw,
-                                                     int64_t m2, uint32_t *dec) {
+                                                     int64_t m2, uint32_t *dec, uint32_t *mid, uint32_t *nmid) {
     __shared__ uint32_t sc[LV_DIRECT][BLOCK];  // column per thread: no bank conflicts
     __shared__ int32_t sw[LV_DIRECT][BLOCK];
     const uint32_t t = threadIdx.x;
-    for (uint32_t i = blockIdx.x * BLOCK + t; i < count; i += gridDim.x * BLOCK) {
-        const uint32_t x = list[i], j0 = inc_off[x], deg = inc_off[x + 1] - j0;
-        if (deg > LV_DIRECT) continue;  // through the sort (k_lv_decide)
+    for (uint32_t i0 = blockIdx.x * BLOCK; i0 < count; i0 += gridDim.x * BLOCK) {  // uniform per block
+        const uint32_t i = i0 + t;
+        uint32_t x = 0, j0 = 0, deg = 0;
+        if (i < count) {
+            x = list[i];
+            j0 = inc_off[x];
+            deg = inc_off[x + 1] - j0;
+        }
+        // nodes of up to LV_WAVE edges are listed for k_lv_wave, longer ones go through the sort
+        const uint32_t at = warp_agg_append(nmid, i < count && deg > LV_DIRECT && deg <= LV_WAVE);
+        if (i < count && deg > LV_DIRECT && deg <= LV_WAVE) mid[at] = i;
+        if (i >= count || deg > LV_DIRECT) continue;
         // eight edges at a time: every load of a stage is issued before any
         // is used (edge, its offsets, its endpoints, the neighbour's
         // community), then each pair is inserted in community order
@@ -412,6 +423,70 @@ __global__ __launch_bounds__(BLOCK) void k_lv_direct(const uint32_t *list, uint3
     }
 }
 
+// Decision of the listed nodes of LV_DIRECT + 1 .. LV_WAVE edges: a wave per
+// node sums the weight of each neighbour community in an LDS hash table
+// (linear probing, at most LV_WAVE distinct keys in LV_TBL slots), then
+// every lane judges its slots and the wave keeps the best (largest score,
+// then the smaller community), as the sorted path does over its runs.
+constexpr int LVW_WAVES = BLOCK / WAVE;
+__global__ __launch_bounds__(BLOCK) void k_lv_wave(const uint32_t *list, const uint32_t *mid, const uint32_t *nmid,
+                                                   const uint32_t *inc_off, const uint32_t *inc,
+                                                   const uint32_t *pins, const int32_t *nwgt, const uint32_t *comm,
+                                                   const int64_t *cvol, const int32_t *vw, int64_t m2,
+                                                   uint32_t *dec) {
+    __shared__ uint32_t tk[LVW_WAVES][LV_TBL];
+    __shared__ unsigned long long tw[LVW_WAVES][LV_TBL];
+    const uint32_t w = threadIdx.x / WAVE, lane = __lane_id();
+    uint32_t *K = tk[w];
+    unsigned long long *V = tw[w];
+    const uint32_t cnt = *nmid;
+    for (uint32_t q = blockIdx.x * LVW_WAVES + w; q < cnt; q += gridDim.x * LVW_WAVES) {  // uniform per wave
+        const uint32_t i = mid[q], x = list[i], j0 = inc_off[x], j1 = inc_off[x + 1];
+        for (uint32_t z = lane; z < LV_TBL; z += WAVE) {
+            K[z] = NONE;
+            V[z] = 0ull;
+        }
+        wave_sync();
+        for (uint32_t j = j0 + lane; j < j1; j += WAVE) {
+            const uint32_t e = inc[j];
+            const uint2 ab = *(const uint2 *)(pins + 2 * (size_t)e);  // two pins at 2e
+            const uint32_t c = comm[ab.x == x ? ab.y : ab.x];
+            uint32_t z = (c * 0x9E3779B1u) >> (32 - 10);
+            static_assert(LV_TBL == 1024, "the slot hash takes 10 bits");
+            for (;;) {
+                const uint32_t old = atomicCAS(&K[z], NONE, c);
+                if (old == NONE || old == c) break;
+                z = (z + 1) & (LV_TBL - 1);
+            }
+            atomicAdd(&V[z], (unsigned long long)(int64_t)nwgt[e]);
+        }
+        wave_sync();
+        const uint32_t A = comm[x];
+        const int64_t vx = vw[x];
+        Best best{0, NONE};
+        int64_t wA = 0;
+        for (uint32_t z = lane; z < LV_TBL; z += WAVE) {
+            const uint32_t c = K[z];
+            if (c == NONE) continue;
+            const int64_t acc = (int64_t)V[z];
+            if (c == A) wA = acc;
+            else best_merge(best, m2 * acc - vx * cvol[c], c);
+        }
+        wA = wave_sum(wA);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int64_t os = __shfl_xor(best.score, o, WAVE);
+            const uint32_t oc = __shfl_xor(best.c, o, WAVE);
+            best_merge(best, os, oc);
+        }
+        if (lane == 0) {
+            const int64_t sA = m2 * wA - vx * (cvol[A] - vx);
+            dec[i] = (best.c != NONE && best.score > sA) ? best.c : NONE;
+        }
+        wave_sync();  // the table is read before the next node clears it
+    }
+}
+
 // All moves of the sub-round; the moves are counted per block into a spread
 // accumulator.
 __global__ __launch_bounds__(BLOCK) void k_lv_apply(const uint32_t *list, const uint32_t *dec, uint32_t count,
@@ -459,7 +534,7 @@ struct LvGraph {
 
 struct LvBufs {
     LvGraph G[2];
-    uint32_t *comm, *rep, *cid, *minid, *node, *list, *ioff, *dec;
+    uint32_t *comm, *rep, *cid, *minid, *node, *list, *ioff, *dec, *mid, *nmid;
     int64_t *cvol, *acc, *tot;
 };
 
@@ -481,6 +556,8 @@ void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, LvBufs &B) {
     B.list = A.alloc<uint32_t>(N);
     B.ioff = A.alloc<uint32_t>(N + 1);
     B.dec = A.alloc<uint32_t>(N);
+    B.mid = A.alloc<uint32_t>(N);
+    B.nmid = A.alloc<uint32_t>(1);
     B.cvol = A.alloc<int64_t>(N);
     B.acc = A.alloc<int64_t>((size_t)SPREAD * SPREAD_I64 * (LV_ROUNDS + 1));
     B.tot = A.alloc<int64_t>(LV_ROUNDS + 1);
@@ -592,9 +669,14 @@ hgp_status communities(const hgp_hg &h, uint64_t seed, uint32_t *comm_out, uint3
                 HGP_REQUIRE(items <= items_cap, HGP_E_WORKSPACE);
                 // nodes of few edges decide at once; the others sort their
                 // (node, community) keys first
+                fill<uint32_t>(B.nmid, 1, 0u, st);
                 k_lv_direct<<<grid_for(count, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(
                     B.list, count, cur.inc_off, cur.inc, cur.pin_off, cur.pins, cur.nwgt, B.comm, B.cvol, cur.vwgt,
-                    m2, B.dec);
+                    m2, B.dec, B.mid, B.nmid);
+                HGP_LAUNCH_CHECK();
+                k_lv_wave<<<grid_for(count, LVW_WAVES, 1024), BLOCK, 0, st>>>(B.list, B.mid, B.nmid, cur.inc_off,
+                                                                           cur.inc, cur.pins, cur.nwgt, B.comm,
+                                                                           B.cvol, cur.vwgt, m2, B.dec);
                 HGP_LAUNCH_CHECK();
                 if (items) {
                     fill<uint32_t>(B.ioff + count, 1, items, st);
