@@ -138,12 +138,12 @@ hgp_status hgp_workspace_bytes(int op, uint32_t n, uint32_t m, uint32_t p, const
             case HGP_OP_CONTRACT: need = contract_workspace(n, m, p); break;
             case HGP_OP_REFINE: need = refine_workspace(n, m, k); break;
             case HGP_OP_VALIDATE: need = util_workspace(n, m); break;
-            case HGP_OP_INITIAL: need = ip_workspace(n, p, k); break;
+            case HGP_OP_INITIAL: need = ip_workspace(n, m, p, k); break;
             case HGP_OP_GAINS: need = gaintable_workspace(n, m, k, n); break;  // also the graph tables
             case HGP_OP_COMMUNITY: need = community_workspace(n, m, p); break;
             case HGP_OP_PARTITION: {
                 size_t temp = std::max({coarsen_workspace(n, m, p, dp), contract_workspace(n, m, p),
-                                        refine_workspace(n, m, k), ip_workspace(n, p, k), util_workspace(n, m)});
+                                        refine_workspace(n, m, k), ip_workspace(n, m, p, k), util_workspace(n, m)});
                 // hierarchy: every coarse level with the capacities of its
                 // parent, and the maps, budgeted at eight input levels (the
                 // input and levels whose sizes sum to at most seven times it

@@ -131,7 +131,7 @@ __global__ void k_put_start(uint32_t *order, uint32_t pos, const uint32_t *start
 // Layer winners [pos, pos + W) become visited; the next layer's state (the
 // other copy) has them as its frontier.
 __global__ void k_bfs_mark(const uint32_t *order, const uint32_t *cur, uint32_t *nxt, uint32_t *visited,
-                           unsigned long long *key) {
+                           unsigned long long *key, uint32_t *base) {
     const uint32_t a = cur[BFS_POS], W = cur[BFS_W];
     for (uint32_t i = a + blockIdx.x * blockDim.x + threadIdx.x; i < a + W; i += gridDim.x * blockDim.x) {
         uint32_t w = order[i];
@@ -142,6 +142,7 @@ __global__ void k_bfs_mark(const uint32_t *order, const uint32_t *cur, uint32_t 
         nxt[BFS_FS] = a;
         nxt[BFS_POS] = a + W;
         nxt[BFS_F] = W;
+        if (base) *base += cur[BFS_T];  // the next layer's pairs number on from here
     }
 }
 
@@ -166,14 +167,39 @@ __device__ inline void pair_of(const uint32_t *D, uint32_t F, uint32_t t, const 
     jj = inc_off[order[fs + fi]] + (t - D[fi]);
 }
 
+// Expanding each net once (when nets are large against the pins): the
+// first pair of the layer that reaches a net is the only one to expand it,
+// because all of the net's pins join in that layer and its later pairs add
+// nothing.  netT[e] holds the first pair number (pair numbers grow over the
+// layers: *base + t), so a net expanded in an earlier layer is below *base.
+// The expansion index of a pin through its net's first pair is the smallest
+// through any pair of the net, so the keys and the order do not change.
+__global__ void k_bfs_first(const uint32_t *D, const uint32_t *bst, const uint32_t *order, const uint32_t *inc_off,
+                            const uint32_t *inc, const uint32_t *base, uint32_t *netT) {
+    const uint32_t F = bst[BFS_F], T = bst[BFS_T], fs = bst[BFS_FS], b0 = *base;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+        uint32_t fi, jj;
+        pair_of(D, F, t, order, fs, inc_off, fi, jj);
+        const uint32_t e = inc[jj];
+        if (netT[e] >= b0) atomicMin(&netT[e], b0 + t);
+    }
+}
+
+// Pair t expands its net: always, or (netT set) only as the net's first pair.
+__device__ inline bool expands(const uint32_t *netT, const uint32_t *base, uint32_t e, uint32_t t) {
+    return !netT || netT[e] == *base + t;
+}
+
 __global__ void k_bfs_keys(const uint32_t *D, const uint32_t *bst, const uint32_t *order, const uint32_t *inc_off,
                            const uint32_t *inc, const uint32_t *pin_off, const uint32_t *pins,
-                           const uint32_t *exoff, const uint32_t *visited, unsigned long long *key) {
+                           const uint32_t *exoff, const uint32_t *visited, unsigned long long *key,
+                           const uint32_t *netT, const uint32_t *base) {
     const uint32_t F = bst[BFS_F], T = bst[BFS_T], fs = bst[BFS_FS];
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
         uint32_t fi, jj;
         pair_of(D, F, t, order, fs, inc_off, fi, jj);
         uint32_t e = inc[jj];
+        if (!expands(netT, base, e, t)) continue;
         uint64_t base = ((uint64_t)fi << 32) | exoff[jj];
         const uint32_t b = pin_off[e], b1 = pin_off[e + 1];
         for (uint32_t q0 = b; q0 < b1; q0 += 8) {  // eight pins at a time: pins, then their flags
@@ -193,12 +219,17 @@ __global__ void k_bfs_keys(const uint32_t *D, const uint32_t *bst, const uint32_
 __global__ void k_bfs_winners(const uint32_t *D, const uint32_t *bst, const uint32_t *order,
                               const uint32_t *inc_off, const uint32_t *inc, const uint32_t *pin_off,
                               const uint32_t *pins, const uint32_t *exoff, const uint32_t *visited,
-                              const unsigned long long *key, uint32_t *cnt, uint32_t *order_out, bool write) {
+                              const unsigned long long *key, uint32_t *cnt, uint32_t *order_out, bool write,
+                              const uint32_t *netT, const uint32_t *base) {
     const uint32_t F = bst[BFS_F], T = bst[BFS_T], fs = bst[BFS_FS], pos = bst[BFS_POS];
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
         uint32_t fi, jj;
         pair_of(D, F, t, order, fs, inc_off, fi, jj);
         uint32_t e = inc[jj];
+        if (!expands(netT, base, e, t)) {
+            if (!write) cnt[t] = 0;
+            continue;
+        }
         uint64_t base = ((uint64_t)fi << 32) | exoff[jj];
         const uint32_t b = pin_off[e], b1 = pin_off[e + 1];
         uint32_t c = 0, wp = write ? pos + cnt[t] : 0;
@@ -540,13 +571,14 @@ __global__ __launch_bounds__(IPS_THREADS) void k_ip_small(const uint32_t *pin_of
 }
 
 struct IpBufs {
-    uint32_t *order, *visited, *J, *S, *exoff, *D, *cnt, *scal;
+    uint32_t *order, *visited, *J, *S, *exoff, *D, *cnt, *scal, *netT;
     uint32_t *bst;  // [2][BFS_WORDS] BFS layer states
     unsigned long long *key;
     uint64_t *P, *E;
 };
 
-static void plan(Arena &A, uint32_t n, uint32_t p, uint32_t k, IpBufs &B) {
+static void plan(Arena &A, uint32_t n, uint32_t m, uint32_t p, uint32_t k, IpBufs &B) {
+    B.netT = A.alloc<uint32_t>(m ? m : 1);
     B.order = A.alloc<uint32_t>(n);
     B.visited = A.alloc<uint32_t>(n);
     B.key = A.alloc<unsigned long long>(n);
@@ -563,10 +595,10 @@ static void plan(Arena &A, uint32_t n, uint32_t p, uint32_t k, IpBufs &B) {
     scan_reserve<uint32_t>(A, (size_t)p + 1);
 }
 
-size_t ip_workspace(uint32_t n, uint32_t p, uint32_t k) {
+size_t ip_workspace(uint32_t n, uint32_t m, uint32_t p, uint32_t k) {
     Arena A(nullptr, 0);
     IpBufs B;
-    plan(A, n, p, k, B);
+    plan(A, n, m, p, k, B);
     return A.peak;
 }
 
@@ -584,23 +616,21 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
     const uint32_t n = h.n;
     size_t mk = A.mark();
     IpBufs B;
-    plan(A, n, h.p, k, B);
+    plan(A, n, h.m, h.p, k, B);
     const int64_t W = W_known >= 0 ? W_known : total_weight(h.vwgt, n, A, st);
     const uint64_t T = fill_target >= 0 ? (uint64_t)fill_target : (uint64_t)((W + k - 1) / k);
-    // (netT, a word per net, lives in exoff, which holds p words)
-    bool small = n > 0 && n <= IPS_MAX_N && h.p <= IPS_MAX_P && h.m <= h.p;
-    if (small) {
+    // sum over nets of |e|^2: the work of expanding every pair's net
+    unsigned long long sqh = 0;
+    if (n && h.m) {
         unsigned long long *sq = (unsigned long long *)B.P;  // scratch until the fill
         HGP_CHECK_HIP(hipMemsetAsync(sq, 0, sizeof(unsigned long long), st));
-        if (h.m) {
-            k_sq_sizes<<<grid_for(h.m, BLOCK, 256), BLOCK, 0, st>>>(h.pin_off, h.m, sq);
-            HGP_LAUNCH_CHECK();
-        }
-        unsigned long long sqh = 0;
+        k_sq_sizes<<<grid_for(h.m, BLOCK, 256), BLOCK, 0, st>>>(h.pin_off, h.m, sq);
+        HGP_LAUNCH_CHECK();
         HGP_CHECK_HIP(hipMemcpyAsync(&sqh, sq, sizeof(sqh), hipMemcpyDeviceToHost, st));
         stream_sync(st);
-        small = sqh <= IPS_MAX_SQ;
     }
+    // (the one-workgroup path keeps its first pair per net in exoff, which holds p words)
+    const bool small = n > 0 && n <= IPS_MAX_N && h.p <= IPS_MAX_P && h.m <= h.p && sqh <= IPS_MAX_SQ;
     if (small) {
         k_ip_small<<<1, IPS_THREADS, 0, st>>>(h.pin_off, h.pins, h.inc_off, h.inc, h.vwgt, n, k, T, B.key, B.D,
                                               B.cnt, B.E, B.order, B.P, B.S, part, B.exoff, h.m);
@@ -610,6 +640,14 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
         return;
     }
     uint32_t *d_start = B.scal + 0, *d_cnt = B.scal + 1;
+    // each net expanded once per BFS when the pairs' nets are large against
+    // the pins (the extra launch per layer pays for itself)
+    const bool once = sqh > 4ull * h.p;
+    uint32_t *netT = once ? B.netT : nullptr, *base = once ? B.scal + 4 : nullptr;
+    if (once) {
+        fill<uint32_t>(B.netT, h.m, ~0u, st);
+        fill<uint32_t>(base, 1, 0u, st);
+    }
     HGP_CHECK_HIP(hipMemsetAsync(B.visited, 0, sizeof(uint32_t) * n, st));
     HGP_CHECK_HIP(hipMemsetAsync(B.key, 0xFF, sizeof(unsigned long long) * n, st));
     k_exoff<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.pin_off, h.inc_off, h.inc, n, B.exoff);
@@ -647,18 +685,22 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
                 uint32_t *cur = B.bst + (layer & 1u) * BFS_WORDS, *nxt = B.bst + ((layer + 1) & 1u) * BFS_WORDS;
                 scan_apply_dn<uint32_t>(A, n, cur + BFS_F, FrontierDeg{B.order, h.inc_off, cur + BFS_FS},
                                         StoreExcl<uint32_t>{B.D}, cur + BFS_T, st);
+                if (once) {
+                    k_bfs_first<<<gT, BLOCK, 0, st>>>(B.D, cur, B.order, h.inc_off, h.inc, base, netT);
+                    HGP_LAUNCH_CHECK();
+                }
                 k_bfs_keys<<<gT, BLOCK, 0, st>>>(B.D, cur, B.order, h.inc_off, h.inc, h.pin_off, h.pins, B.exoff,
-                                                 B.visited, B.key);
+                                                 B.visited, B.key, netT, base);
                 HGP_LAUNCH_CHECK();
                 k_bfs_winners<<<gT, BLOCK, 0, st>>>(B.D, cur, B.order, h.inc_off, h.inc, h.pin_off, h.pins,
-                                                    B.exoff, B.visited, B.key, B.cnt, B.order, false);
+                                                    B.exoff, B.visited, B.key, B.cnt, B.order, false, netT, base);
                 HGP_LAUNCH_CHECK();
                 scan_apply_dn<uint32_t>(A, h.p, cur + BFS_T, LoadArr<uint32_t>{B.cnt}, StoreExcl<uint32_t>{B.cnt},
                                         cur + BFS_W, st);
                 k_bfs_winners<<<gT, BLOCK, 0, st>>>(B.D, cur, B.order, h.inc_off, h.inc, h.pin_off, h.pins,
-                                                    B.exoff, B.visited, B.key, B.cnt, B.order, true);
+                                                    B.exoff, B.visited, B.key, B.cnt, B.order, true, netT, base);
                 HGP_LAUNCH_CHECK();
-                k_bfs_mark<<<gW, BLOCK, 0, st>>>(B.order, cur, nxt, B.visited, B.key);
+                k_bfs_mark<<<gW, BLOCK, 0, st>>>(B.order, cur, nxt, B.visited, B.key, base);
                 HGP_LAUNCH_CHECK();
             }
             uint32_t hs[BFS_WORDS];

@@ -38,7 +38,7 @@ void refine_lp(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32_t 
                const int64_t *side_limits = nullptr);
 
 // ip.hip
-size_t ip_workspace(uint32_t n, uint32_t p, uint32_t k);
+size_t ip_workspace(uint32_t n, uint32_t m, uint32_t p, uint32_t k);
 // fill_target >= 0: every block is filled to it instead of ceil(c(V)/k) (a
 // bisection fills block 0 to its share; the last block takes the rest).
 void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hipStream_t st, int64_t W_known = -1,
