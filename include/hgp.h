@@ -203,10 +203,10 @@ hgp_status hgp_initial_partition(const hgp_hg *h, uint32_t k, uint32_t *part,
  * single-pin nets included) and partitioned in turn: side 0 into blocks b0,
  * ..., side 1 into the blocks after them.  A subhypergraph with one block
  * is assigned to it.  Writes part[n] (device).  Workspace:
- * hgp_workspace_bytes(HGP_OP_RB, n, m, p, prm); the bisections of one
- * recursion depth are independent, and a larger workspace lets up to eight
- * of them run at once, each on a worker thread with a stream of its own
- * (same results).  Syncs.  prm->ip and prm->community are ignored;
+ * hgp_workspace_bytes(HGP_OP_RB, n, m, p, prm); the bisections of
+ * different subhypergraphs are independent, and a larger workspace lets up
+ * to eight of them run at once, each on a worker thread with a stream of its
+ * own (same results).  Syncs.  prm->ip and prm->community are ignored;
  * HGP_TRUSTED_INPUT skips the input check. */
 hgp_status hgp_rb_initial_partition(const hgp_hg *h, const hgp_params *prm, uint32_t *part,
                                     void *ws, size_t ws_bytes, void *stream);

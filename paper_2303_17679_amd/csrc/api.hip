@@ -5,6 +5,9 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -92,11 +95,18 @@ size_t rb_region_bytes(uint32_t n, uint32_t m, uint32_t p, uint32_t k) {
     return 4ull * (9ull * n + 4ull * std::max(m, p) + 4ull * p + 4ull * k) + 17ull * 256 * k + 4096;
 }
 
-// Recursive bipartitioning: the start map, two regions for the sides of
-// consecutive depths and one lane (more lanes run at once when the
-// workspace holds them).
+// The sides of every bisected node: a region per depth that bisects
+// (ceil(log2 k) of them).
+size_t rb_sides_bytes(uint32_t n, uint32_t m, uint32_t p, uint32_t k) {
+    uint32_t depths = 1;
+    while ((1u << depths) < k) ++depths;
+    return (size_t)depths * rb_region_bytes(n, m, p, k);
+}
+
+// Recursive bipartitioning: the start map, the sides of every bisected node
+// and one lane (more lanes run at once when the workspace holds them).
 size_t rb_bytes(uint32_t n, uint32_t m, uint32_t p, const hgp_params &dp) {
-    return 4ull * n + 2 * rb_region_bytes(n, m, p, dp.k) + rb_lane_bytes(n, m, p, dp) + 8192;
+    return 4ull * n + rb_sides_bytes(n, m, p, dp.k) + rb_lane_bytes(n, m, p, dp) + 8192;
 }
 
 }  // namespace
@@ -457,17 +467,42 @@ struct LaneStreams {  // created and destroyed with the recursion
     }
 };
 
+// Bisected node's result and both sides, with the node's sizes as
+// capacities, from the sides' arena.
+void alloc_sides(Arena &R, const hgp_hg &H, RbSides &o) {
+    o.bp = R.alloc<uint32_t>(H.n);
+    for (int sd = 0; sd < 2; ++sd) {
+        hgp_hg_out &out = o.out[sd];
+        out.cap_n = H.n; out.cap_m = H.m; out.cap_p = H.p;
+        out.pin_off = R.alloc<uint32_t>((size_t)H.m + 1);
+        out.pins = R.alloc<uint32_t>(H.p);
+        out.inc_off = R.alloc<uint32_t>((size_t)H.n + 1);
+        out.inc = R.alloc<uint32_t>(H.p);
+        out.vwgt = R.alloc<int32_t>(H.n);
+        out.nwgt = R.alloc<int32_t>(H.m);
+        out.dims = nullptr;
+        o.smap[sd] = R.alloc<uint32_t>(H.n);
+        o.cmap[sd] = R.alloc<uint32_t>(H.n);
+    }
+}
+
 // Recursive bipartitioning (Sec. 5, Eq. 1): the k-way initial partition of h
 // by bisections, each a multilevel cycle with k = 2 and the side limits of
 // Eq. 1; side 0 of a node with kk blocks takes the first ceil(kk/2) of them.
+// The nodes form a queue: a lane takes a node, bisects it and queues both
+// sides, so a side is bisected as soon as its parent is done (not when the
+// parent's whole depth is).  Each node writes only its own vertices' blocks
+// and its own sides, so the results do not depend on the order.
 hgp_status rb_initial_partition(const hgp_hg &h, const hgp_params &prm, uint32_t *part, Arena &A, hipStream_t st) {
     const size_t mk = A.mark();
     uint32_t *vmap = A.alloc<uint32_t>(h.n);
     iota_u32(vmap, h.n, st);
     const int64_t Wtot = total_weight(h.vwgt, h.n, A, st);
     stream_sync(st);  // the level and vmap are complete before the lanes read them
-    const size_t rbytes = rb_region_bytes(h.n, h.m, h.p, prm.k);
-    Arena R[2] = {Arena(A.alloc<char>(rbytes), rbytes), Arena(A.alloc<char>(rbytes), rbytes)};
+    // every bisected node's sides, kept to the end: the nodes of one depth
+    // sum to at most one region, and ceil(log2 k) depths bisect
+    const size_t sbytes = rb_sides_bytes(h.n, h.m, h.p, prm.k);
+    Arena R(A.alloc<char>(sbytes), sbytes);
     // lanes: as many bisection workspaces of the largest node (the root) as
     // the workspace holds, at least one
     const size_t lb = rb_lane_bytes(h.n, h.m, h.p, prm);
@@ -484,83 +519,66 @@ hgp_status rb_initial_partition(const hgp_hg &h, const hgp_params &prm, uint32_t
         HGP_CHECK_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
         ls.s.push_back(x);
     }
-    const bool bw = blocking_waits;
-    std::vector<RbNode> cur{RbNode{h, prm.k, 0, vmap}};
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<RbNode> q{RbNode{h, prm.k, 0, vmap}};
+    uint32_t busy = 0;
     hgp_status result = HGP_OK;
-    for (uint32_t depth = 0; !cur.empty() && result == HGP_OK; ++depth) {
-        // the sides of this depth go to the region that held the previous
-        // depth's nodes (no longer read)
-        Arena &dst = R[(depth + 1) & 1];
-        dst.release(0);
-        std::vector<RbSides> sides(cur.size());
-        for (size_t i = 0; i < cur.size(); ++i) {
-            const hgp_hg &H = cur[i].H;
-            if (cur[i].kk < 2) continue;
-            RbSides &o = sides[i];
-            o.bp = dst.alloc<uint32_t>(H.n);
-            for (int sd = 0; sd < 2; ++sd) {
-                hgp_hg_out &out = o.out[sd];
-                out.cap_n = H.n; out.cap_m = H.m; out.cap_p = H.p;
-                out.pin_off = dst.alloc<uint32_t>((size_t)H.m + 1);
-                out.pins = dst.alloc<uint32_t>(H.p);
-                out.inc_off = dst.alloc<uint32_t>((size_t)H.n + 1);
-                out.inc = dst.alloc<uint32_t>(H.p);
-                out.vwgt = dst.alloc<int32_t>(H.n);
-                out.nwgt = dst.alloc<int32_t>(H.m);
-                out.dims = nullptr;
-                o.smap[sd] = dst.alloc<uint32_t>(H.n);
-                o.cmap[sd] = dst.alloc<uint32_t>(H.n);
+    auto work = [&](uint32_t li) {
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            cv.wait(lk, [&] { return !q.empty() || busy == 0 || result != HGP_OK; });
+            if (result != HGP_OK || q.empty()) return;  // (q empty here means busy == 0: all done)
+            const RbNode nd = q.front();
+            q.pop_front();
+            ++busy;
+            RbSides o;
+            hgp_status s = HGP_OK;
+            try {
+                if (nd.kk >= 2) alloc_sides(R, nd.H, o);
+            } catch (const Error &e) {
+                s = e.code;
             }
-        }
-        std::vector<hgp_status> st_of(cur.size(), HGP_OK);
-        std::atomic<size_t> next{0};
-        std::atomic<bool> stop{false};
-        auto work = [&](uint32_t li) {
-            for (;;) {
-                const size_t i = next.fetch_add(1);
-                if (i >= cur.size() || stop.load()) return;
+            lk.unlock();
+            if (s == HGP_OK) {
                 try {
-                    st_of[i] = rb_task(prm, Wtot, part, cur[i], sides[i], lane[li], ls.s[li]);
+                    s = rb_task(prm, Wtot, part, nd, o, lane[li], ls.s[li]);
                 } catch (const Error &e) {
-                    st_of[i] = e.code;
+                    s = e.code;
                 } catch (...) {
-                    st_of[i] = HGP_E_DEVICE;
+                    s = HGP_E_DEVICE;
                 }
-                if (st_of[i] != HGP_OK) {
-                    (void)hipStreamSynchronize(ls.s[li]);  // nothing of the failed task still runs
-                    stop.store(true);
+                if (s != HGP_OK) (void)hipStreamSynchronize(ls.s[li]);  // nothing of the failed task still runs
+            }
+            lk.lock();
+            --busy;
+            if (s != HGP_OK) {
+                if (result == HGP_OK) result = s;
+            } else if (nd.kk >= 2) {
+                const uint32_t ks[2] = {(nd.kk + 1) / 2, nd.kk / 2};
+                for (int sd = 0; sd < 2; ++sd) {
+                    if (o.dims[sd][0] == 0) continue;  // an empty side gets no vertices
+                    const hgp_hg_out &out = o.out[sd];
+                    q.push_back(RbNode{hgp_hg{o.dims[sd][0], o.dims[sd][1], o.dims[sd][2], out.pin_off, out.pins,
+                                              out.inc_off, out.inc, out.vwgt, out.nwgt},
+                                       ks[sd], sd == 0 ? nd.b0 : nd.b0 + ks[0], o.cmap[sd]});
                 }
             }
-        };
-        const uint32_t nt = (uint32_t)std::min<size_t>(nl, cur.size());
-        if (nt == 1) {
-            work(0);
-        } else {
-            std::vector<std::thread> th;
-            for (uint32_t li = 0; li < nt; ++li)
-                th.emplace_back([&, li]() {
-                    (void)hipSetDevice(dev);
-                    blocking_waits = bw;
-                    work(li);
-                });
-            for (std::thread &t : th) t.join();
+            cv.notify_all();
         }
-        std::vector<RbNode> nxt;
-        for (size_t i = 0; i < cur.size() && result == HGP_OK; ++i) {
-            if (st_of[i] != HGP_OK) { result = st_of[i]; break; }
-            const RbNode &nd = cur[i];
-            if (nd.kk < 2) continue;
-            const uint32_t ks[2] = {(nd.kk + 1) / 2, nd.kk / 2};
-            for (int sd = 0; sd < 2; ++sd) {
-                const RbSides &o = sides[i];
-                if (o.dims[sd][0] == 0) continue;  // an empty side gets no vertices
-                const hgp_hg_out &out = o.out[sd];
-                nxt.push_back(RbNode{hgp_hg{o.dims[sd][0], o.dims[sd][1], o.dims[sd][2], out.pin_off, out.pins,
-                                            out.inc_off, out.inc, out.vwgt, out.nwgt},
-                                     ks[sd], sd == 0 ? nd.b0 : nd.b0 + ks[0], o.cmap[sd]});
-            }
-        }
-        cur.swap(nxt);
+    };
+    if (nl == 1) {
+        work(0);
+    } else {
+        const bool bw = blocking_waits;
+        std::vector<std::thread> th;
+        for (uint32_t li = 0; li < nl; ++li)
+            th.emplace_back([&, li]() {
+                (void)hipSetDevice(dev);
+                blocking_waits = bw;
+                work(li);
+            });
+        for (std::thread &t : th) t.join();
     }
     A.release(mk);
     return result;
