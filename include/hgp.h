@@ -412,10 +412,19 @@ hgp_status hgp_timing_scratch_bytes(uint32_t n_max, uint32_t m_max, size_t *out)
 hgp_status hgp_timing_begin(uint32_t mask, int account, void *scratch, size_t scratch_bytes,
                             uint32_t n_max, uint32_t m_max);
 
+/* Host.  Event timing of a subset of launches: from this call on, the j-th
+ * launch (j = 0, 1, ...) of each timed kernel gets its event pair only when
+ * j % every == phase.  A run repeated `every` times with phases 0 .. every-1
+ * times each launch position once, at 1/every of the event cost per run.
+ * hgp_timing_begin restores every = 1.  HGP_E_INVALID when every == 0 or
+ * phase >= every. */
+hgp_status hgp_timing_sample(uint32_t every, uint32_t phase);
+
 /* Host.  Waits for the device, then for kernel ids i < count writes
- * total_ms[i] (summed event time), launches[i] and bytes[i] (accounted
- * compulsory bytes, 0 when not accounting), and stops measuring.  Any of the
- * three pointers may be NULL. */
+ * total_ms[i] (summed event time), launches[i] (the timed launches; all
+ * launches when accounting) and bytes[i] (accounted compulsory bytes, 0 when
+ * not accounting), and stops measuring.  Any of the three pointers may be
+ * NULL. */
 hgp_status hgp_timing_end(uint32_t count, double *total_ms, uint64_t *launches, double *bytes);
 
 /* Host.  Static description of a status code. */

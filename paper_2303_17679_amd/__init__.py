@@ -25,7 +25,8 @@ STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_OVERFLOW", -3: "HGP_E_WOR
 
 EXPORTS = ["hgp_default_params", "hgp_workspace_bytes", "hgp_validate", "hgp_coarsen", "hgp_contract",
            "hgp_project", "hgp_objective", "hgp_refine_lp", "hgp_initial_partition", "hgp_partition",
-           "hgp_timing_scratch_bytes", "hgp_timing_begin", "hgp_timing_end", "hgp_status_str",
+           "hgp_timing_scratch_bytes", "hgp_timing_begin", "hgp_timing_sample", "hgp_timing_end",
+           "hgp_status_str",
            "hgp_server_create", "hgp_server_submit", "hgp_server_wait", "hgp_server_destroy",
            "hgp_batch_workspace_bytes", "hgp_partition_batch", "hgp_refine_lp_static",
            "hgp_partition_traced", "hgp_gain_table", "hgp_gain_table_update", "hgp_gain_recalc",
@@ -128,6 +129,7 @@ def lib():
         L.hgp_timing_scratch_bytes.argtypes = [u32, u32, ctypes.POINTER(ctypes.c_size_t)]
         L.hgp_timing_begin.restype = i32
         L.hgp_timing_begin.argtypes = [u32, ctypes.c_int, P, ctypes.c_size_t, u32, u32]
+        L.hgp_timing_sample.restype = i32; L.hgp_timing_sample.argtypes = [u32, u32]
         L.hgp_timing_end.restype = i32
         L.hgp_timing_end.argtypes = [u32, P, P, P]
         L.hgp_server_create.restype = i32
@@ -454,6 +456,11 @@ class KernelTimer:
     def begin(self, mask: int, account: bool = False):
         _check(lib().hgp_timing_begin(mask, int(account), _ptr(self.scratch), self.scratch.numel(), self.n_max,
                                       self.m_max), "hgp_timing_begin")
+
+    def sample(self, every: int, phase: int):
+        """Events on launch j of each timed kernel only when j % every == phase
+        (counted from this call; see hgp_timing_sample)."""
+        _check(lib().hgp_timing_sample(every, phase), "hgp_timing_sample")
 
     def end(self):
         k = len(KERNELS)

@@ -34,6 +34,8 @@ struct Timing {
     uint64_t launches[KID_COUNT] = {};
     double acc_host[KID_COUNT] = {};  // bytes counted on the host (sizes known there)
     uint64_t acc_launches[KID_COUNT] = {};
+    uint32_t every = 1, phase = 0;     // time launch j of a kernel only when j % every == phase
+    uint64_t seen[KID_COUNT] = {};     // launches of each kernel since the last sampling change
 };
 
 Timing &timing();

@@ -23,7 +23,8 @@ static hipEvent_t get_event() {
 
 TimedLaunch::TimedLaunch(int k, hipStream_t s) : kid(k), st(s) {
     if (timing().account && (timing().mask >> kid & 1u)) timing().acc_launches[kid] += 1;
-    if (!timing().account && (timing().mask >> kid & 1u)) {
+    Timing &T = timing();
+    if (!T.account && (T.mask >> kid & 1u) && T.seen[kid]++ % T.every == T.phase) {
         e0 = get_event();
         e1 = get_event();
         HGP_CHECK_HIP(hipEventRecord(e0, st));
@@ -60,7 +61,10 @@ hgp_status hgp_timing_begin(uint32_t mask, int account, void *scratch, size_t sc
         T.launches[k] = 0;
         T.acc_launches[k] = 0;
         T.acc_host[k] = 0;
+        T.seen[k] = 0;
     }
+    T.every = 1;
+    T.phase = 0;
     T.mask = mask & ((1u << KID_COUNT) - 1u);
     T.account = false;
     T.acc_dev = nullptr;
@@ -76,6 +80,15 @@ hgp_status hgp_timing_begin(uint32_t mask, int account, void *scratch, size_t sc
         T.stamp = 0;
         if (hipMemset(scratch, 0, need) != hipSuccess) return HGP_E_DEVICE;
     }
+    return HGP_OK;
+}
+
+hgp_status hgp_timing_sample(uint32_t every, uint32_t phase) {
+    if (every == 0 || phase >= every) return HGP_E_INVALID;
+    Timing &T = timing();
+    T.every = every;
+    T.phase = phase;
+    for (int k = 0; k < KID_COUNT; ++k) T.seen[k] = 0;
     return HGP_OK;
 }
 

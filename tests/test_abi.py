@@ -27,11 +27,20 @@ def H():
 
 def test_header_symbols_exported(H):
     names = declared()
-    assert len(names) == 29
+    assert len(names) == 30
     assert names == sorted(H.EXPORTS)
     L = ctypes.CDLL(H.LIB_PATH)
     for n in names:
         assert hasattr(L, n), n
+
+
+def test_timing_sample_arguments(H):
+    # host state only: the sampling period and phase are checked, nothing runs
+    L = H.lib()
+    assert L.hgp_timing_sample(0, 0) == -1
+    assert L.hgp_timing_sample(3, 3) == -1
+    assert L.hgp_timing_sample(3, 2) == 0
+    assert L.hgp_timing_sample(1, 0) == 0
 
 
 def test_status_strings(H):
