@@ -472,7 +472,7 @@ __device__ inline T group_sum(T v) {
 // any is used.
 template <int KW, int G, bool GR>
 __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, uint32_t count, uint32_t blk,
-                                  uint32_t nblk, uint32_t slot) {
+                                  uint32_t nblk, uint32_t slot, bool skip_inner = false) {
     constexpr int GPB = BLOCK / G;
     constexpr bool CACHE = G < 64;
     constexpr int NC = CACHE ? 8 : 1;
@@ -481,9 +481,12 @@ __device__ inline void gains_body(const GainArgs<KW> &a, const uint32_t *list, u
     for (uint32_t base = xs.lo + xs.wi * GPB; base < xs.hi; base += xs.nw * GPB) {
         const uint32_t idx = base + g;
         uint32_t u = 0, best_t = NONE, best_g = 0, s = 0;
-        const bool act = idx < xs.hi;
+        bool act = idx < xs.hi;
+        if (act) u = list[idx];
+        // (a vertex without a cut net has no other block in its nets: it
+        // would propose nothing)
+        if (act && skip_inner) act = a.bcnt[u] != 0;
         if (act) {  // uniform within the group
-            u = list[idx];
             const uint32_t j0 = a.inc_off[u], j1 = a.inc_off[u + 1];
             s = a.part[u];
             const int64_t cu = a.vwgt[u];
@@ -699,16 +702,103 @@ __global__ __launch_bounds__(BLOCK) void k_gain_scan(GainArgs<KW> a, uint32_t ch
 template <int KW>
 constexpr int gains_occupancy() { return KW == 1 ? 6 : (KW == 2 ? 4 : 3); }
 
+// poff == nullptr: the candidate lists of k_gain_scan (cl, ccnt).  Otherwise
+// the lists of the level built by k_lp_pre: the vertices of class c and slot
+// sl are cl[poff[c * NSLOT + sl] .. poff[c * NSLOT + sl + 1]), every vertex
+// of the sub-round whether or not it has a cut net (those without are
+// skipped), and block 0 clears the counters that k_gain_scan would.
 template <int KW, bool GR>
 __global__ __launch_bounds__(BLOCK, gains_occupancy<KW>()) void k_gains(GainArgs<KW> a, const uint32_t *cl,
-                                                                        const uint32_t *ccnt) {
+                                                                        const uint32_t *ccnt, const uint32_t *poff,
+                                                                        uint32_t *scal) {
     if (lp_skip(a.ctl)) return;
     const uint32_t sl = blockIdx.x % NSLOT, bj = blockIdx.x / NSLOT, nbj = gridDim.x / NSLOT;
+    if (poff) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[2] = 0; scal[3] = 0;
+            scal[13] = 0; scal[14] = 0;
+            scal[24] = 0;
+        }
+        const uint32_t o0 = poff[sl], o1 = poff[NSLOT + sl], o2 = poff[2 * NSLOT + sl];
+        gains_body<KW, 1, GR>(a, cl + o0, poff[sl + 1] - o0, bj, nbj, sl, true);
+        gains_body<KW, 8, GR>(a, cl + o1, poff[NSLOT + sl + 1] - o1, bj, nbj, sl, true);
+        gains_body<KW, 64, GR>(a, cl + o2, poff[2 * NSLOT + sl + 1] - o2, bj, nbj, sl, true);
+        return;
+    }
     const size_t cstride = (size_t)NSLOT * a.slot_cap;
     const size_t off = (size_t)sl * a.slot_cap;
     gains_body<KW, 1, GR>(a, cl + off, ccnt[(0 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
     gains_body<KW, 8, GR>(a, cl + cstride + off, ccnt[(1 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
     gains_body<KW, 64, GR>(a, cl + 2 * cstride + off, ccnt[(2 * NSLOT + sl) * SPREAD_U32], bj, nbj, sl);
+}
+
+// Candidate lists of every LP sub-round of a small level, built once per
+// level instead of a selection launch per sub-round (on small levels the
+// launches, not the bytes, bound a sub-round).  Key
+// ((r * S + s) * 3 + c) * NSLOT + sl: round r, its sub-round s (the
+// sub-round hash), degree class c, and the slot of the vertex's chunk (as
+// k_gain_scan assigns it).  Every vertex with an incident net is listed once
+// per round.  cur == nullptr: adds the count of every key to cnt; otherwise
+// writes the vertices at the positions reserved from cur.  A workgroup takes
+// one chunk at a time and BLOCK (vertex, round) pairs of it per step; one
+// global atomic per key and step.
+constexpr uint32_t LP_PRE_N = 1u << 17;  // levels of fewer vertices
+constexpr uint32_t LP_PRE_RS = 64;       // rounds x sub-rounds at most
+__global__ __launch_bounds__(BLOCK) void k_lp_pre(const uint32_t *inc_off, uint32_t n, uint64_t mseed,
+                                                  uint32_t level, uint32_t R, uint32_t S, uint32_t ch,
+                                                  uint32_t nchunks, uint32_t *cnt, uint32_t *cur,
+                                                  uint32_t *lists) {
+    __shared__ uint32_t lc[LP_PRE_RS * 3], lb[LP_PRE_RS * 3];
+    const uint32_t nk = R * S * 3;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t lo = c * ch, len = (lo + ch < n ? lo + ch : n) - lo;
+        const uint32_t slot = chunk_slot(c, nchunks);
+        for (uint32_t q0 = 0; q0 < len * R; q0 += BLOCK) {
+            for (uint32_t t = threadIdx.x; t < nk; t += BLOCK) lc[t] = 0;
+            __syncthreads();
+            const uint32_t q = q0 + threadIdx.x;
+            uint32_t v = 0, key = NONE, rank = 0;
+            if (q < len * R) {
+                const uint32_t r = q / len;
+                v = lo + q % len;
+                const uint32_t d = inc_off[v + 1] - inc_off[v];
+                if (d) {
+                    const uint32_t sub = (uint32_t)(tag_hash(mseed, 3, level, r, v) % S);
+                    key = (r * S + sub) * 3 + (uint32_t)deg_class(d);
+                    rank = atomicAdd(&lc[key], 1u);
+                }
+            }
+            __syncthreads();
+            for (uint32_t t = threadIdx.x; t < nk; t += BLOCK)
+                if (lc[t]) {
+                    if (cur) lb[t] = atomicAdd(&cur[t * NSLOT + slot], lc[t]);
+                    else atomicAdd(&cnt[t * NSLOT + slot], lc[t]);
+                }
+            __syncthreads();
+            if (cur && key != NONE) lists[lb[key] + rank] = v;
+            __syncthreads();
+        }
+    }
+}
+
+// Exclusive prefix of the nk counts (one workgroup): off[i] and cur[i], and
+// off[nk] = the total.
+__global__ __launch_bounds__(BLOCK) void k_lp_pre_scan(const uint32_t *cnt, uint32_t nk, uint32_t *off,
+                                                       uint32_t *cur) {
+    __shared__ uint32_t wsum[BLOCK / WAVE];
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < nk; b += BLOCK) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t v = i < nk ? cnt[i] : 0u;
+        uint32_t tot;
+        const uint32_t incl = block_incl_scan<uint32_t>(v, wsum, &tot);
+        if (i < nk) {
+            off[i] = carry + incl - v;
+            cur[i] = carry + incl - v;
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) off[nk] = carry;
 }
 
 // Candidates of more than HUB_DEG nets: one 1024-thread workgroup each, the
@@ -1994,6 +2084,33 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
     // per CU at 80 registers), so that every candidate's chain of dependent
     // gathers is in flight at once instead of in successive rounds
     const uint32_t list_blocks = slot_grid(6 * 256);
+    // Small levels without hub vertices: the candidate lists of every
+    // sub-round, built here once (k_lp_pre) in the space of k_gain_scan's
+    // lists when they fit there, else from the workspace if it has room
+    uint32_t *pre_lists = nullptr, *pre_off = nullptr;
+    const uint32_t Rlp = std::min<uint32_t>(prm.lp_rounds, LP_MAX_ROUNDS);
+    if (n && n < LP_PRE_N && !dc[3] && (uint64_t)Rlp * S <= LP_PRE_RS) {
+        const size_t nent = (size_t)Rlp * S * 3 * NSLOT;
+        auto words = [](size_t c) { return ((c * 4 + 255) & ~(size_t)255) / 4; };  // as the arena rounds
+        const size_t need = words((size_t)Rlp * n) + words(nent + 1) + 2 * words(nent);
+        uint32_t *base = nullptr;
+        if (need <= 3 * ((size_t)n + (size_t)(3 * NSLOT) * GAIN_CH)) base = B.cl;
+        else if (A.remaining() >= need * 4) base = A.alloc<uint32_t>(need);
+        if (base) {
+            pre_lists = base;
+            pre_off = base + words((size_t)Rlp * n);
+            uint32_t *cnt = pre_off + words(nent + 1), *cur = cnt + words(nent);
+            fill<uint32_t>(cnt, nent, 0u, st);
+            const uint32_t pb = std::min<uint32_t>(gchunks, FILL_BLOCKS);
+            k_lp_pre<<<pb, BLOCK, 0, st>>>(h.inc_off, n, mseed, level, Rlp, S, gch, gchunks, cnt, nullptr, nullptr);
+            HGP_LAUNCH_CHECK();
+            k_lp_pre_scan<<<1, BLOCK, 0, st>>>(cnt, (uint32_t)nent, pre_off, cur);
+            HGP_LAUNCH_CHECK();
+            k_lp_pre<<<pb, BLOCK, 0, st>>>(h.inc_off, n, mseed, level, Rlp, S, gch, gchunks, nullptr, cur,
+                                           pre_lists);
+            HGP_LAUNCH_CHECK();
+        }
+    }
     // lanes per mover by the level's average degree (a lane per incident net)
     const uint64_t avg_deg = n ? ((uint64_t)h.p + n - 1) / n : 1;
     const uint32_t upd_g = avg_deg <= 8 ? 8u : (avg_deg <= 24 ? 16u : 64u);
@@ -2142,12 +2259,18 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
                 ga, T.marks, T.stamp, (unsigned long long *)T.acc_dev + KID_GAINS);
             HGP_LAUNCH_CHECK();
         }
-        if (n) {
+        if (n && pre_lists) {
+            const uint32_t *po = pre_off + (size_t)(r * S + s) * 3 * NSLOT;
+            TimedLaunch tl(KID_GAINS, st);
+            if (adj) k_gains<KW, true><<<list_blocks, BLOCK, 0, st>>>(ga, pre_lists, nullptr, po, B.scal);
+            else k_gains<KW, false><<<list_blocks, BLOCK, 0, st>>>(ga, pre_lists, nullptr, po, B.scal);
+            HGP_LAUNCH_CHECK();
+        } else if (n) {
             k_gain_scan<KW><<<gain_blocks, BLOCK, 0, st>>>(ga, gch, gchunks, B.cl, B.ccnt, B.dlists, nhub, B.scal);
             HGP_LAUNCH_CHECK();
             TimedLaunch tl(KID_GAINS, st);
-            if (adj) k_gains<KW, true><<<list_blocks, BLOCK, 0, st>>>(ga, B.cl, B.ccnt);
-            else k_gains<KW, false><<<list_blocks, BLOCK, 0, st>>>(ga, B.cl, B.ccnt);
+            if (adj) k_gains<KW, true><<<list_blocks, BLOCK, 0, st>>>(ga, B.cl, B.ccnt, nullptr, nullptr);
+            else k_gains<KW, false><<<list_blocks, BLOCK, 0, st>>>(ga, B.cl, B.ccnt, nullptr, nullptr);
             HGP_LAUNCH_CHECK();
         }
         if (hub_blocks && !hacc) {
