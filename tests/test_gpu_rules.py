@@ -122,3 +122,26 @@ def test_trace_matches_oracle_levels(hgp, orc, name, k, seed):
     for t, L in zip(tr, lv):
         assert (t["n"], t["m"], t["p"]) == (L["h"].n, L["h"].m, len(L["h"].pins))
         assert t["lp_rounds"] == L["lp_rounds"]
+
+
+@pytest.mark.parametrize("rounds,subrounds", [(12, 5), (13, 5), (64, 1), (9, 8)])
+def test_lp_candidate_list_paths(hgp, orc, rounds, subrounds):
+    # Small levels list the candidates of every sub-round once per level when
+    # rounds x sub-rounds <= 64 and select them per sub-round otherwise; both
+    # must refine exactly as the oracle does, and so must whole partitions.
+    h = W.random_uniform(3000, 3300, 2, 9, seed=17)
+    k = 8
+    part = W.uniform(W.rng(23, 0, np.arange(h.n, dtype=np.uint64)), k).astype(np.uint32)
+    print(f"[rules] candidate lists rounds={rounds} subrounds={subrounds}", file=sys.stderr, flush=True)
+    kw = dict(eps=(1, 10), seed=3, lp_rounds=rounds, lp_subrounds=subrounds)
+    out_o, f_o, bw_o, rounds_o, moves_o = orc.refine_lp(h, orc.params(k, **kw), 0, part)
+    G = hgp.Hypergraph.from_host(h)
+    t = dev(part)
+    f, bw = hgp.refine_lp(G, hgp.params(k, **kw), 0, t)
+    assert f == f_o
+    assert np.array_equal(t.cpu().numpy().view(np.uint32), out_o)
+    assert bw.cpu().numpy().tolist() == bw_o.tolist()
+    part_o, f_o, L_o = orc.partition(h, orc.params(k, **kw))
+    p, f, L = hgp.partition(G, hgp.params(k, **kw))
+    assert (L, f) == (L_o, f_o)
+    assert np.array_equal(p.cpu().numpy().view(np.uint32), part_o)
