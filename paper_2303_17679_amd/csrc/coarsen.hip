@@ -1402,11 +1402,9 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                                                                  B.tsum, B.counts, B.cursor, B.bcounts, B.lists, false);
     HGP_LAUNCH_CHECK();
     std::vector<uint32_t> counts(S * NCLASS + 3), offs(S * NCLASS + 1);
-    HGP_CHECK_HIP(hipMemcpyAsync(counts.data(), B.counts, sizeof(uint32_t) * (S * NCLASS + 3), hipMemcpyDeviceToHost,
-                                 st));
+    read_back(counts.data(), B.counts, sizeof(uint32_t) * (S * NCLASS + 3), st);
     const bool huge_nets = counts[S * NCLASS + 1] > HUB_BIG;
     const bool small_nets = counts[S * NCLASS + 1] <= 8;  // every net fits the 8-pin lane path
-    stream_sync(st);
     // hub tables: the whole region, cleared once; every job leaves its slots clean
     const size_t E = B.greg_bytes / GENTRY_BYTES;
     uint64_t *gR = (uint64_t *)B.greg;
@@ -1510,8 +1508,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
         k_hub_info<<<grid_for(cntc, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(a, lst, cntc, B.bound, n, B.hub_info);
         HGP_LAUNCH_CHECK();
         std::vector<uint4> info(cntc), ginfo, linfo;
-        HGP_CHECK_HIP(hipMemcpyAsync(info.data(), B.hub_info, sizeof(uint4) * cntc, hipMemcpyDeviceToHost, st));
-        stream_sync(st);
+        read_back(info.data(), B.hub_info, sizeof(uint4) * cntc, st);
         for (const uint4 &f : info) {
             if (f.w == NONE) continue;  // joined by another vertex earlier in the pass
             if (!huge_nets && f.w <= LHUB_PART * LHUB_MAXP) linfo.push_back(f);
@@ -1564,8 +1561,7 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
         if (!linfo.empty()) {
             // jobs whose LDS table filled up (indices within their batch)
             uint32_t no = 0;
-            HGP_CHECK_HIP(hipMemcpyAsync(&no, B.hub_ovf + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-            stream_sync(st);
+            read_back(&no, B.hub_ovf + n, sizeof(uint32_t), st);
             if (no) {
                 std::vector<uint32_t> flags(ljobs.size());
                 HGP_CHECK_HIP(hipMemcpyAsync(flags.data(), B.hub_ovf, sizeof(uint32_t) * flags.size(),
@@ -1721,17 +1717,15 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
                 apply(r, ovf);
             }
             uint32_t hv[2];  // cluster count, handed-back sub-round
-            HGP_CHECK_HIP(hipMemcpyAsync(hv, ncl, sizeof(hv), hipMemcpyDeviceToHost, st));
-            stream_sync(st);
+            read_back(hv, ncl, sizeof(hv), st);
             cnt = hv[0];
             if (!hv[1]) break;
             // sub-round hv[1] - 1 had more slow joins than one workgroup
             // sorts: approve them on the host-driven path, apply, go on
             const uint32_t r = hv[1] - 1;
             uint32_t ns = 0;
-            HGP_CHECK_HIP(hipMemcpyAsync(&ns, nslow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            read_back(&ns, nslow, sizeof(uint32_t), st);
             HGP_CHECK_HIP(hipMemsetAsync(ovf, 0, sizeof(uint32_t), st));
-            stream_sync(st);
             host_slow(ns);
             apply(r, nullptr);
             r0 = r + 1;
@@ -1744,16 +1738,14 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
             // one read-back per sub-round: the joins that need the sorted
             // approval, and the cluster count after the previous sub-round
             uint32_t hv[3];
-            HGP_CHECK_HIP(hipMemcpyAsync(hv, B.scal, sizeof(hv), hipMemcpyDeviceToHost, st));
-            stream_sync(st);
+            read_back(hv, B.scal, sizeof(hv), st);
             const uint32_t ns = hv[1];
             cnt = hv[2];
             if ((uint64_t)5 * cnt < (uint64_t)2 * n) break;  // the pass was cut: nothing was proposed
             if (ns) host_slow(ns);
             apply(r, nullptr);
         }
-        HGP_CHECK_HIP(hipMemcpyAsync(&cnt, ncl, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        stream_sync(st);
+        read_back(&cnt, ncl, sizeof(uint32_t), st);
     }
     if (n_clusters_dev)
         HGP_CHECK_HIP(hipMemcpyAsync(n_clusters_dev, ncl, sizeof(uint32_t), hipMemcpyDeviceToDevice, st));

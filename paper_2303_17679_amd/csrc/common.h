@@ -1,6 +1,7 @@
 // Internal helpers of the gfx950 library: arena workspace, launch checking,
 // wave64 primitives and the seeded hash.  Not part of the public ABI.
 #pragma once
+#include <initializer_list>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
@@ -37,6 +38,22 @@ void stream_sync(hipStream_t st);
 // that stream, so a read-back can wait for a sync the caller needs anyway.
 constexpr int MAILBOX_WORDS = 16;
 uint32_t *host_mailbox();
+
+// Reads device memory into host memory and waits for the stream.  The copies
+// land in the calling thread's pinned staging buffer (STAGE_BYTES, allocated
+// on first use), so they queue behind one wait: a copy to pageable memory is a
+// host round trip of its own.  A read larger than what is left of the buffer
+// goes straight to its destination.  Every destination holds its bytes on
+// return.  (It allocates pinned host memory once per thread: the LP driver,
+// which the allocation-free entry point runs, does not use it.)
+struct HostRead {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+constexpr size_t STAGE_BYTES = 64 * 1024;
+void read_back(std::initializer_list<HostRead> reads, hipStream_t st);
+inline void read_back(void *dst, const void *src, size_t bytes, hipStream_t st) { read_back({{dst, src, bytes}}, st); }
 
 #define HGP_LAUNCH_CHECK() HGP_CHECK_HIP(hipGetLastError())
 

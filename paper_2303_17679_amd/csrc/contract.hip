@@ -372,8 +372,7 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
     scan_apply<uint64_t>(A, m, KeptPack{B.valid, B.repnet, B.usize},
                          StoreKept{B.newid, B.newoff, out.pin_off, out.nwgt, h.nwgt, B.wsum, out.cap_m}, d_tot, st);
     uint64_t tot = 0;
-    HGP_CHECK_HIP(hipMemcpyAsync(&tot, d_tot, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    stream_sync(st);
+    read_back(&tot, d_tot, sizeof(uint64_t), st);
     uint32_t mc = (uint32_t)(tot >> 32), pc = (uint32_t)tot;
     HGP_REQUIRE(mc <= out.cap_m && pc <= out.cap_p, HGP_E_INVALID);
     HGP_CHECK_HIP(hipMemcpyAsync(out.pin_off + mc, &pc, sizeof(uint32_t), hipMemcpyHostToDevice, st));

@@ -606,8 +606,7 @@ constexpr uint32_t BFS_BATCH = 8;  // BFS layers queued per host read-back
 
 static uint32_t read_u32(const uint32_t *d, hipStream_t st) {
     uint32_t h = 0;
-    HGP_CHECK_HIP(hipMemcpyAsync(&h, d, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    stream_sync(st);
+    read_back(&h, d, sizeof(uint32_t), st);
     return h;
 }
 
@@ -626,8 +625,7 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
         HGP_CHECK_HIP(hipMemsetAsync(sq, 0, sizeof(unsigned long long), st));
         k_sq_sizes<<<grid_for(h.m, BLOCK, 256), BLOCK, 0, st>>>(h.pin_off, h.m, sq);
         HGP_LAUNCH_CHECK();
-        HGP_CHECK_HIP(hipMemcpyAsync(&sqh, sq, sizeof(sqh), hipMemcpyDeviceToHost, st));
-        stream_sync(st);
+        read_back(&sqh, sq, sizeof(sqh), st);
     }
     // (the one-workgroup path keeps its first pair per net in exoff, which holds p words)
     const bool small = n > 0 && n <= IPS_MAX_N && h.p <= IPS_MAX_P && h.m <= h.p && sqh <= IPS_MAX_SQ;
@@ -704,9 +702,7 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
                 HGP_LAUNCH_CHECK();
             }
             uint32_t hs[BFS_WORDS];
-            HGP_CHECK_HIP(hipMemcpyAsync(hs, B.bst + (layer & 1u) * BFS_WORDS, sizeof(hs), hipMemcpyDeviceToHost,
-                                         st));
-            stream_sync(st);
+            read_back(hs, B.bst + (layer & 1u) * BFS_WORDS, sizeof(hs), st);
             if (hs[BFS_F] == 0) {
                 pos = hs[BFS_POS];
                 break;

@@ -175,9 +175,7 @@ void subhypergraph(const hgp_hg &h, const uint32_t *part, uint32_t side, const h
     scan_apply<uint64_t>(A, m, NetPack{cnt}, NetStore{h.nwgt, nrank, out.pin_off, out.nwgt, out.cap_m}, d_mp, st);
     uint32_t n2 = 0;
     uint64_t mp = 0;
-    HGP_CHECK_HIP(hipMemcpyAsync(&n2, d_n2, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HGP_CHECK_HIP(hipMemcpyAsync(&mp, d_mp, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    stream_sync(st);
+    read_back({{&n2, d_n2, sizeof(uint32_t)}, {&mp, d_mp, sizeof(uint64_t)}}, st);
     const uint32_t m2 = (uint32_t)(mp >> 32), p2 = (uint32_t)mp;
     HGP_REQUIRE(n2 <= out.cap_n && m2 <= out.cap_m && p2 <= out.cap_p, HGP_E_INVALID);
     k_set_value<<<1, 64, 0, st>>>(out.pin_off + m2, p2);

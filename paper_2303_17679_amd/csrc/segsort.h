@@ -246,8 +246,7 @@ inline void segmented_sort(Arena &A, const SegSortBufs &B, const uint32_t *off, 
                                                                      B.large, B.scal + 1, B.scal + 4);
     HGP_LAUNCH_CHECK();
     uint32_t cnt[5];
-    HGP_CHECK_HIP(hipMemcpyAsync(cnt, B.scal, sizeof(cnt), hipMemcpyDeviceToHost, st));
-    stream_sync(st);
+    read_back(cnt, B.scal, sizeof(cnt), st);
     tiers[0] = cnt[0];
     tiers[1] = cnt[1];
     if (cnt[4]) {  // some segment of the wave tier
@@ -263,8 +262,7 @@ inline void segmented_sort(Arena &A, const SegSortBufs &B, const uint32_t *off, 
         uint64_t total = 0;
         uint64_t *tot_dev = (uint64_t *)(B.scal + 2);
         scan_apply<uint64_t>(A, nl, LargeLen{off, B.large}, StoreExcl<uint64_t>{B.pos}, tot_dev, st);
-        HGP_CHECK_HIP(hipMemcpyAsync(&total, tot_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-        stream_sync(st);
+        read_back(&total, tot_dev, sizeof(uint64_t), st);
         k_seg_large_gather<<<grid_for(nl, 1, 4096), BLOCK, 0, st>>>(off, B.large, nl, data, B.pos, B.keys, B.vals);
         HGP_LAUNCH_CHECK();
         uint64_t *kk = B.keys;

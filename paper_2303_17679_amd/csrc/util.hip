@@ -1,6 +1,7 @@
 // Reductions needed on the host (total weights) and input validation.
 #include "prims.h"
 #include "kernels.h"
+#include <cstring>
 
 namespace hgp {
 
@@ -237,6 +238,33 @@ uint32_t *host_mailbox() {
     thread_local PinnedWords w;
     if (!w.p) HGP_CHECK_HIP(hipHostMalloc((void **)&w.p, sizeof(uint32_t) * MAILBOX_WORDS, hipHostMallocDefault));
     return w.p;
+}
+
+void read_back(std::initializer_list<HostRead> reads, hipStream_t st) {
+    thread_local PinnedWords stage;
+    if (!stage.p) HGP_CHECK_HIP(hipHostMalloc((void **)&stage.p, STAGE_BYTES, hipHostMallocDefault));
+    char *base = (char *)stage.p;
+    size_t used = 0;
+    for (const HostRead &r : reads) {
+        if (!r.bytes) continue;
+        const size_t at = (used + 15) & ~(size_t)15;
+        if (at + r.bytes <= STAGE_BYTES) {
+            HGP_CHECK_HIP(hipMemcpyAsync(base + at, r.src, r.bytes, hipMemcpyDeviceToHost, st));
+            used = at + r.bytes;
+        } else {
+            HGP_CHECK_HIP(hipMemcpyAsync(r.dst, r.src, r.bytes, hipMemcpyDeviceToHost, st));
+        }
+    }
+    stream_sync(st);
+    used = 0;
+    for (const HostRead &r : reads) {
+        if (!r.bytes) continue;
+        const size_t at = (used + 15) & ~(size_t)15;
+        if (at + r.bytes <= STAGE_BYTES) {
+            std::memcpy(r.dst, base + at, r.bytes);
+            used = at + r.bytes;
+        }
+    }
 }
 
 void stream_sync(hipStream_t st) {
