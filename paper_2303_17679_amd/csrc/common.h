@@ -44,16 +44,20 @@ uint32_t *host_mailbox();
 // on first use), so they queue behind one wait: a copy to pageable memory is a
 // host round trip of its own.  A read larger than what is left of the buffer
 // goes straight to its destination.  Every destination holds its bytes on
-// return.  (It allocates pinned host memory once per thread: the LP driver,
-// which the allocation-free entry point runs, does not use it.)
+// return.  It allocates the buffer on a thread's first call unless
+// may_allocate is false; then a thread without one copies straight to the
+// destinations (the LP driver, which the allocation-free entry point runs,
+// never allocates).
 struct HostRead {
     void *dst;
     const void *src;
     size_t bytes;
 };
 constexpr size_t STAGE_BYTES = 64 * 1024;
-void read_back(std::initializer_list<HostRead> reads, hipStream_t st);
-inline void read_back(void *dst, const void *src, size_t bytes, hipStream_t st) { read_back({{dst, src, bytes}}, st); }
+void read_back(std::initializer_list<HostRead> reads, hipStream_t st, bool may_allocate = true);
+inline void read_back(void *dst, const void *src, size_t bytes, hipStream_t st, bool may_allocate = true) {
+    read_back({{dst, src, bytes}}, st, may_allocate);
+}
 
 #define HGP_LAUNCH_CHECK() HGP_CHECK_HIP(hipGetLastError())
 

@@ -2003,8 +2003,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         HGP_LAUNCH_CHECK();
     }
     uint32_t dc[NDEG], hs[16];
-    HGP_CHECK_HIP(hipMemcpyAsync(hs, B.scal, sizeof(hs), hipMemcpyDeviceToHost, st));
-    stream_sync(st);
+    read_back(hs, B.scal, sizeof(hs), st, false);
     for (int c = 0; c < NDEG; ++c) dc[c] = hs[5 + c];
     const bool long_nets = hs[4] > 64;  // nets of more than 64 pins exist on this level
     // A graph level (every net has two pins) keeps no net records: the
@@ -2140,16 +2139,14 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         k_collect_slow<<<fast_blocks, BLOCK, 0, st>>>(B.plist, pcnt_of(stamp), slot_cap, part, B.prop_t, k,
                                                       B.slowpair, B.slow, nslow);
         HGP_LAUNCH_CHECK();
-        HGP_CHECK_HIP(hipMemcpyAsync(&ns, nslow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        stream_sync(st);
+        read_back(&ns, nslow, sizeof(uint32_t), st, false);
         HGP_CHECK_HIP(hipMemsetAsync(B.slowpair, 0, sizeof(uint32_t) * k * k, st));
         uint32_t G = 0;  // largest gain of the handed-over proposals
         if (ns) {
             HGP_CHECK_HIP(hipMemsetAsync(gmax, 0, sizeof(uint32_t), st));
             k_gain_max<<<grid_for(ns, BLOCK, 64), BLOCK, 0, st>>>(B.slow, ns, B.prop_g, gmax);
             HGP_LAUNCH_CHECK();
-            HGP_CHECK_HIP(hipMemcpyAsync(&G, gmax, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-            stream_sync(st);
+            read_back(&G, gmax, sizeof(uint32_t), st, false);
         }
         const int gb = bits_for(G);
         KeyLayout L;
@@ -2320,10 +2317,8 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
         for (uint32_t r = r0; r < r1; ++r)
             for (uint32_t s = (r == r0 ? s0 : 0); s < S; ++s) subround(r, s);
         uint32_t hv[1 + LP_ROUND_BATCH];
-        HGP_CHECK_HIP(hipMemcpyAsync(&hv[0], abort, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        HGP_CHECK_HIP(hipMemcpyAsync(&hv[1], B.rmoves + r0, sizeof(uint32_t) * (r1 - r0), hipMemcpyDeviceToHost,
-                                     st));
-        stream_sync(st);
+        read_back({{&hv[0], abort, sizeof(uint32_t)}, {&hv[1], B.rmoves + r0, sizeof(uint32_t) * (r1 - r0)}}, st,
+                  false);
         if (hv[0]) {
             // sub-round hv[0] handed pairs to the device-wide path: finish it
             // there, then queue the sub-rounds after it again
@@ -2339,8 +2334,7 @@ static void refine_t(const hgp_hg &h, const hgp_params &prm, uint32_t level, uin
                 // the hand-over finished its round: a round without moves
                 // ends LP here as well
                 uint32_t mv = 0;
-                HGP_CHECK_HIP(hipMemcpyAsync(&mv, B.rmoves + r0, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-                stream_sync(st);
+                read_back(&mv, B.rmoves + r0, sizeof(uint32_t), st, false);
                 if (mv == 0) break;
                 ++r0;
                 s0 = 0;

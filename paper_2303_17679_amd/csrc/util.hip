@@ -54,8 +54,7 @@ static SumMax sum_max(const int32_t *w, uint32_t n, Arena &A, hipStream_t st) {
         HGP_LAUNCH_CHECK();
     }
     char host[16];
-    HGP_CHECK_HIP(hipMemcpyAsync(host, buf, 16, hipMemcpyDeviceToHost, st));
-    stream_sync(st);
+    read_back(host, buf, 16, st, false);
     r.sum = *(int64_t *)host;
     r.max = *(int32_t *)(host + 8);
     r.nonpos = *(uint32_t *)(host + 12) != 0;
@@ -240,15 +239,17 @@ uint32_t *host_mailbox() {
     return w.p;
 }
 
-void read_back(std::initializer_list<HostRead> reads, hipStream_t st) {
+void read_back(std::initializer_list<HostRead> reads, hipStream_t st, bool may_allocate) {
     thread_local PinnedWords stage;
-    if (!stage.p) HGP_CHECK_HIP(hipHostMalloc((void **)&stage.p, STAGE_BYTES, hipHostMallocDefault));
+    if (!stage.p && may_allocate)
+        HGP_CHECK_HIP(hipHostMalloc((void **)&stage.p, STAGE_BYTES, hipHostMallocDefault));
     char *base = (char *)stage.p;
+    const size_t cap = base ? STAGE_BYTES : 0;
     size_t used = 0;
     for (const HostRead &r : reads) {
         if (!r.bytes) continue;
         const size_t at = (used + 15) & ~(size_t)15;
-        if (at + r.bytes <= STAGE_BYTES) {
+        if (at + r.bytes <= cap) {
             HGP_CHECK_HIP(hipMemcpyAsync(base + at, r.src, r.bytes, hipMemcpyDeviceToHost, st));
             used = at + r.bytes;
         } else {
@@ -260,7 +261,7 @@ void read_back(std::initializer_list<HostRead> reads, hipStream_t st) {
     for (const HostRead &r : reads) {
         if (!r.bytes) continue;
         const size_t at = (used + 15) & ~(size_t)15;
-        if (at + r.bytes <= STAGE_BYTES) {
+        if (at + r.bytes <= cap) {
             std::memcpy(r.dst, base + at, r.bytes);
             used = at + r.bytes;
         }
