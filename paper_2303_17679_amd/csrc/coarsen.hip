@@ -1021,6 +1021,28 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_b_wave(const uint32_t *pin_off
     }
 }
 
+// Fill cursors of the candidate lists: the exclusive prefix of the nk
+// (sub-round, class) counts (one workgroup), the same offsets the host forms
+// from its read-back of the counts.
+__global__ __launch_bounds__(BLOCK) void k_class_offsets(const uint32_t *counts, uint32_t nk, uint32_t *cursor) {
+    __shared__ uint32_t wsum[BLOCK / WAVE];
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < nk; b += BLOCK) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t v = i < nk ? counts[i] : 0u;
+        uint32_t tot;
+        const uint32_t incl = block_incl_scan<uint32_t>(v, wsum, &tot);
+        if (i < nk) cursor[i] = carry + incl - v;
+        carry += tot;
+    }
+}
+
+// Sets one device word from a host value (a kernel argument instead of a
+// copy from pageable host memory, which would be a host round trip).
+__global__ void k_put_word(uint32_t *p, uint32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 // pass 1 (fill=false): count per (sub-round, class); pass 2: fill lists.
 // Counters are aggregated per block in LDS: each block adds its counts with
 // one global atomic per key (and in pass 2 reserves its ranges the same way),
@@ -1576,7 +1598,8 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     };
     offs[0] = 0;
     for (uint32_t i = 0; i < S * NCLASS; ++i) offs[i + 1] = offs[i] + counts[i];
-    HGP_CHECK_HIP(hipMemcpyAsync(B.cursor, offs.data(), sizeof(uint32_t) * S * NCLASS, hipMemcpyHostToDevice, st));
+    k_class_offsets<<<1, BLOCK, 0, st>>>(B.counts, S * NCLASS, B.cursor);
+    HGP_LAUNCH_CHECK();
     k_classify<<<grid_for(n, BLOCK, CLASSIFY_BLOCKS), BLOCK, 0, st>>>(B.bound, n, mseed, level, S, h.vwgt, rep, B.cw,
                                                                  B.tsum, B.counts, B.cursor, B.bcounts, B.lists, true);
     HGP_LAUNCH_CHECK();
@@ -1589,7 +1612,8 @@ void coarsen_pass(const hgp_hg &h, const hgp_params &prm, uint32_t level, uint32
     // approval keys fit one word and no hub candidate needs host planning;
     // otherwise the host reads the slow-join count back after every sub-round.
     const bool queued = cb + wb + ub <= 64 && !any_hub;
-    HGP_CHECK_HIP(hipMemcpyAsync(ncl, &cnt, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    k_put_word<<<1, 64, 0, st>>>(ncl, cnt);
+    HGP_LAUNCH_CHECK();
     if (queued) HGP_CHECK_HIP(hipMemsetAsync(ovf, 0, sizeof(uint32_t), st));
     auto rate_subround = [&](uint32_t r) {
         k_target_info<<<grid_for(n, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(rep, B.cw, h.vwgt, n, mseed, level, S, r,

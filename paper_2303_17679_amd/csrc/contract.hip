@@ -304,6 +304,12 @@ size_t contract_workspace(uint32_t n, uint32_t m, uint32_t p) {
     return A.peak;
 }
 
+// Up to three device words from host values, as kernel arguments: a copy from
+// pageable host memory would be a host round trip of its own.
+__global__ void k_put_words3(uint32_t *p, uint32_t n, uint32_t a, uint32_t b, uint32_t c) {
+    if (blockIdx.x == 0 && threadIdx.x < n) p[threadIdx.x] = threadIdx.x == 0 ? a : (threadIdx.x == 1 ? b : c);
+}
+
 void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_out &out, uint32_t *dims_host,
               Arena &A, hipStream_t st) {
     const uint32_t n = h.n, m = h.m, p = h.p;
@@ -375,7 +381,8 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
     read_back(&tot, d_tot, sizeof(uint64_t), st);
     uint32_t mc = (uint32_t)(tot >> 32), pc = (uint32_t)tot;
     HGP_REQUIRE(mc <= out.cap_m && pc <= out.cap_p, HGP_E_INVALID);
-    HGP_CHECK_HIP(hipMemcpyAsync(out.pin_off + mc, &pc, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    k_put_words3<<<1, 64, 0, st>>>(out.pin_off + mc, 1, pc, 0, 0);
+    HGP_LAUNCH_CHECK();
     // the transpose's net ids start where the stable sort by vertex (8-bit
     // digits) leaves them: in out.inc after an even number of passes
     const int vbits = bits_for(nc ? nc - 1 : 0);
@@ -411,7 +418,10 @@ void contract(const hgp_hg &h, const uint32_t *rep, uint32_t *cid, const hgp_hg_
         HGP_CHECK_HIP(hipMemsetAsync(out.inc_off, 0, sizeof(uint32_t) * ((size_t)nc + 1), st));
     }
     uint32_t dims[3] = {nc, mc, pc};
-    if (out.dims) HGP_CHECK_HIP(hipMemcpyAsync(out.dims, dims, sizeof(dims), hipMemcpyHostToDevice, st));
+    if (out.dims) {
+        k_put_words3<<<1, 64, 0, st>>>(out.dims, 3, dims[0], dims[1], dims[2]);
+        HGP_LAUNCH_CHECK();
+    }
     stream_sync(st);
     if (dims_host) { dims_host[0] = nc; dims_host[1] = mc; dims_host[2] = pc; }
     A.release(mk);

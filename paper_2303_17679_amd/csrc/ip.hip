@@ -117,6 +117,12 @@ __global__ void k_mark_range(const uint32_t *order, uint32_t a, uint32_t b, uint
 }
 
 // The start vertex opens a BFS: order[pos] = s, the first layer state.
+// One device word from a host value (a kernel argument, not a copy from
+// pageable host memory).
+__global__ void k_put_u32(uint32_t *p, uint32_t v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+
 __global__ void k_put_start(uint32_t *order, uint32_t pos, const uint32_t *start, uint32_t *visited, uint32_t *bst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         uint32_t s = *start;
@@ -653,7 +659,8 @@ void initial_partition(const hgp_hg &h, uint32_t k, uint32_t *part, Arena &A, hi
     uint32_t pos = 0, next = 0;
     while (pos < n) {
         // next start vertex with incident nets; unreachable vertices before it join in ID order
-        HGP_CHECK_HIP(hipMemcpyAsync(d_start, &n, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        k_put_u32<<<1, 64, 0, st>>>(d_start, n);
+        HGP_LAUNCH_CHECK();
         k_find_start<<<grid_for(n - next, BLOCK, FILL_BLOCKS), BLOCK, 0, st>>>(h.inc_off, B.visited, next, n,
                                                                                d_start);
         HGP_LAUNCH_CHECK();
