@@ -124,11 +124,12 @@ def test_trace_matches_oracle_levels(hgp, orc, name, k, seed):
         assert t["lp_rounds"] == L["lp_rounds"]
 
 
-@pytest.mark.parametrize("rounds,subrounds", [(12, 5), (13, 5), (64, 1), (9, 8)])
+@pytest.mark.parametrize("rounds,subrounds", [(12, 5), (13, 5), (64, 1), (9, 8), (0, 5)])
 def test_lp_candidate_list_paths(hgp, orc, rounds, subrounds):
     # Small levels list the candidates of every sub-round once per level when
     # rounds x sub-rounds <= 64 and select them per sub-round otherwise; both
-    # must refine exactly as the oracle does, and so must whole partitions.
+    # must refine exactly as the oracle does, and so must whole partitions
+    # (zero rounds: empty lists, nothing moves).
     h = W.random_uniform(3000, 3300, 2, 9, seed=17)
     k = 8
     part = W.uniform(W.rng(23, 0, np.arange(h.n, dtype=np.uint64)), k).astype(np.uint32)
