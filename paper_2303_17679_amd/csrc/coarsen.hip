@@ -457,13 +457,17 @@ __global__ __launch_bounds__(BLOCK) void k_hub_info(RateArgs a, const uint32_t *
     }
 }
 
-// Insert cluster C of job J into its table; returns the slot.
+// Insert cluster C of job J into its table; returns the slot.  Within a
+// kernel a key only ever goes from NONE to a cluster, so the probe may read
+// it through this XCD's L2 (workgroup scope) even if another XCD has just
+// claimed the slot: a stale NONE only leads to the CAS, which is device-wide
+// and returns the key actually there, and a key once read never changes.
 __device__ inline uint32_t hub_slot(uint32_t *keys, const HubJob &J, uint32_t C) {
     const uint32_t mask = (1u << J.lg) - 1u;
     uint32_t *kt = keys + J.off;
     uint32_t slot = slot_hash(C, (int)J.lg);
     for (;;) {
-        const uint32_t k = __hip_atomic_load(&kt[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t k = __hip_atomic_load(&kt[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (k == C) return slot;
         if (k == NONE) {
             const uint32_t old = atomicCAS(&kt[slot], NONE, C);
@@ -770,9 +774,10 @@ __global__ __launch_bounds__(BLOCK) void k_hub_argmax(RateArgs a, const HubJob *
         uint32_t bC = NONE;
         for (uint32_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
             const uint64_t s = J.off + i;
-            const uint32_t C = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // (the inserts finished in an earlier kernel: plain reads)
+            const uint32_t C = keys[s];
             if (C == NONE) continue;
-            const uint64_t rc = __hip_atomic_load(&R[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t rc = R[s];
             keys[s] = NONE;
             stamp[s] = NONE;
             R[s] = 0;
