@@ -180,6 +180,18 @@ IP_CASES = ["random2k", "stencil16", "hugenets", "powerlaw20000", "random120k", 
             "edge:duplicate_nets"]
 
 
+@pytest.mark.parametrize("k", [2, 7])
+def test_initial_partition_layered_large_nets(hgp, orc, k):
+    """Nets of 40 to 120 pins (sum of squared sizes far above what one
+    workgroup takes): the layer-by-layer path with every net expanded once
+    per BFS."""
+    h = W.random_uniform(20000, 3000, 40, 120, seed=29)
+    say(f"[ip layered large nets k={k}] n={h.n} p={h.p}")
+    assert h.p > (1 << 17)
+    ip = hgp.initial_partition(hgp.Hypergraph.from_host(h), k)
+    assert np.array_equal(host(ip), orc.greedy_ip(h, k))
+
+
 @pytest.mark.parametrize("name", IP_CASES)
 @pytest.mark.parametrize("k", [2, 7])
 def test_initial_partition_paths(hgp, orc, name, k):
